@@ -1,0 +1,402 @@
+"""FP64 CPU oracle for Block CUR (Oswal, Jain, Xu, Eriksson, arXiv 1703.06065).
+
+TEST INFRASTRUCTURE ONLY.  This module is the plain, slow, obviously correct
+reference that the GPU path is checked against.  Only the tests, the smoke
+check of the package entry script and the CPU-baseline leg of the benchmark
+may import it.  It shares no code with the HIP path and imports nothing from
+the product package.
+
+Everything is float64 NumPy.  Inputs are the float32 arrays handed to the GPU,
+widened to float64.  Random numbers that the method draws (the Rademacher test
+matrix and the sampler's 64-bit words) are inputs, never drawn here.
+
+Two references are provided:
+  * exact  - top-k singular subspaces from a full LAPACK SVD (Sec. 2.1);
+  * twin   - the randomized range finder (the sketching replacement for the
+             score step that Sec. 3.1 allows) carried out in float64 with the
+             same test matrix, so that the GPU's sketch can be compared step
+             for step.
+
+Readings taken where the paper is silent or ambiguous (each is listed in the
+design notes of the repository):
+  R1  sampling probabilities are p_g = l_g / k from the top-k right singular
+      vectors of A itself (the block column-subset-selection special case
+      R = A of the Remark in Sec. 3.3, with the p_i = l_i/k form of the
+      generalized-regression lemma of App. A.1.1);
+  R2  sampling is without replacement by default (the footnote of Sec. 4.1
+      says the experiments were run that way); with replacement (Alg. 1,
+      step 2) is a flag;
+  R3  scores are quantized to integers before sampling so that selection is
+      exact and independent of summation order (see ``quantize_scores``);
+  R4  C is returned unscaled; the weights 1/sqrt(s p) of the sampling matrix S
+      (Sec. 3.1) are returned beside the indices.  The residual does not
+      depend on them because C C^+ A is a projection (Sec. 2.1);
+  R5  duplicated blocks (with replacement) are removed before the fit.
+
+Parity unpinned: the (1+eps) relative-error guarantees (Thm. 2, the Remark
+of Sec. 3.3, Lemma 3 of App. A.1.1) carry unspecified constants; they are
+reported as context only.
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+
+# ---------------------------------------------------------------------------
+# Sec. 2.1: norms and singular subspaces
+# ---------------------------------------------------------------------------
+
+def frob2(A: np.ndarray) -> float:
+    """||A||_F^2 = sum_ij A_ij^2 (Sec. 2.1, Frobenius norm)."""
+    A = np.asarray(A, dtype=np.float64)
+    return float(np.sum(A * A))
+
+
+def all_finite(A: np.ndarray) -> bool:
+    return bool(np.all(np.isfinite(A)))
+
+
+def exact_svd(A: np.ndarray):
+    """Thin SVD A = U diag(sigma) V^T with sigma descending (Sec. 2.1)."""
+    U, s, Vt = np.linalg.svd(np.asarray(A, dtype=np.float64), full_matrices=False)
+    return U, s, Vt.T
+
+
+def exact_right_subspace(A: np.ndarray, k: int) -> np.ndarray:
+    """V_{A,k}: the top-k right singular vectors of A as an n x k matrix."""
+    _, _, V = exact_svd(A)
+    return V[:, :k]
+
+
+def exact_left_subspace(A: np.ndarray, k: int) -> np.ndarray:
+    """U_{A,k}: the top-k left singular vectors of A as an m x k matrix."""
+    U, _, _ = exact_svd(A)
+    return U[:, :k]
+
+
+def best_rank_k_error(A: np.ndarray, k: int) -> float:
+    """||A - A_k||_F = sqrt(sum_{i>k} sigma_i^2) (Eckart-Young, Sec. 2.1)."""
+    s = np.linalg.svd(np.asarray(A, dtype=np.float64), compute_uv=False)
+    return float(math.sqrt(float(np.sum(s[k:] ** 2))))
+
+
+# ---------------------------------------------------------------------------
+# Def. 1, Def. 2, Def. 3, Def. 4
+# ---------------------------------------------------------------------------
+
+def column_leverage(V: np.ndarray) -> np.ndarray:
+    """l_j = ||V_k^T e_j||_2^2 for every column j (Def. 1)."""
+    V = np.asarray(V, dtype=np.float64)
+    return np.array([float(V[j, :] @ V[j, :]) for j in range(V.shape[0])])
+
+
+def block_scores(V: np.ndarray, offsets: Sequence[int]) -> np.ndarray:
+    """l_g(A, k) = ||V_k^T E_g||_F^2 for every block g (Def. 2).
+
+    ``V`` is n x k; block g holds the columns offsets[g] .. offsets[g+1]-1.
+    E_g selects those rows of V, so the score is the sum of squares of that
+    slice of V."""
+    V = np.asarray(V, dtype=np.float64)
+    off = np.asarray(offsets, dtype=np.int64)
+    out = np.empty(len(off) - 1)
+    for g in range(len(off) - 1):
+        blk = V[off[g]:off[g + 1], :]
+        out[g] = float(np.sum(blk * blk))
+    return out
+
+
+def block_stable_rank(V: np.ndarray, offsets: Sequence[int]) -> Tuple[float, np.ndarray]:
+    """alpha = min_g ||V_k^T E_g||_F^2 / ||V_k^T E_g||_2^2 (Def. 3).
+
+    Returns (alpha, per-block ratios); a block whose slice is zero has no
+    defined ratio and is skipped (NaN in the per-block array)."""
+    V = np.asarray(V, dtype=np.float64)
+    off = np.asarray(offsets, dtype=np.int64)
+    ratios = np.full(len(off) - 1, np.nan)
+    for g in range(len(off) - 1):
+        blk = V[off[g]:off[g + 1], :]
+        fro2 = float(np.sum(blk * blk))
+        if fro2 > 0.0:
+            spec = float(np.linalg.norm(blk, 2))
+            ratios[g] = fro2 / (spec * spec)
+    return float(np.nanmin(ratios)), ratios
+
+
+def incoherence(U: np.ndarray) -> float:
+    """mu = (m/k) max_i ||U_k^T e_i||_2^2 (Def. 4), U is m x k."""
+    U = np.asarray(U, dtype=np.float64)
+    m, k = U.shape
+    return float(m / k * np.max(np.sum(U * U, axis=1)))
+
+
+# ---------------------------------------------------------------------------
+# Randomized range finder (sketched scores; Sec. 3.1 allows sketching)
+# ---------------------------------------------------------------------------
+
+def range_finder(A: np.ndarray, omega: np.ndarray, q: int, k: int) -> Dict[str, np.ndarray]:
+    """Top-k right singular subspace of A from a sketch, in float64.
+
+    Q starts as the test matrix; q+1 times, Q <- orth(A^T (A Q)).  Then a
+    Rayleigh-Ritz step: Z = A Q, T = Z^T Z, T = W diag(lam) W^T with lam
+    descending, V_k = Q W[:, :k], Ritz singular values sqrt(lam), and the
+    matching left vectors U_k = Z W[:, :k] diag(1/sqrt(lam_k)).
+
+    Only span(Q) matters in exact arithmetic; orth is a Householder QR here
+    (the GPU uses Cholesky QR, which spans the same space)."""
+    A = np.asarray(A, dtype=np.float64)
+    Q = np.asarray(omega, dtype=np.float64)
+    for _ in range(q + 1):
+        Z = A @ Q
+        Y = A.T @ Z
+        Q, _ = np.linalg.qr(Y)
+    Z = A @ Q
+    T = Z.T @ Z
+    lam, W = np.linalg.eigh(T)
+    order = np.argsort(lam)[::-1]
+    lam = lam[order]
+    W = W[:, order]
+    ritz = np.sqrt(np.maximum(lam, 0.0))
+    Vk = Q @ W[:, :k]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        Uk = (Z @ W[:, :k]) / ritz[:k]
+    return {"Q": Q, "Vk": Vk, "Uk": Uk, "lam": lam, "ritz": ritz, "W": W}
+
+
+def score_condition(lam: np.ndarray, k: int) -> float:
+    """kappa = lam_1 / (lam_k - lam_{k+1}) of the Ritz values (inf without gap)."""
+    if k >= len(lam):
+        return 1.0
+    gap = lam[k - 1] - lam[k]
+    return float(lam[0] / gap) if gap > 0 else math.inf
+
+
+# ---------------------------------------------------------------------------
+# Block sampling (Alg. 1 step 2; the sampling matrix S of Sec. 3.1)
+# ---------------------------------------------------------------------------
+
+SCORE_BITS = 62
+
+
+def _ceil_log2(x: int) -> int:
+    return (x - 1).bit_length() if x > 1 else 0
+
+
+def quantize_scores(scores: Sequence[float]) -> Tuple[List[int], int]:
+    """Integer weights q_g = floor(l_g * 2^sh) with one power-of-two scale.
+
+    sh is chosen from the largest score M = f 2^E (f in [0.5, 1)) as
+    sh = 62 - ceil(log2 G) - E, so every q_g < 2^(62 - ceil(log2 G)) and the
+    total stays below 2^62.  Scaling by a power of two and taking the floor
+    are exact in float64, so q is a function of the scores alone.  Returns
+    (q, sh); all-zero scores give q = 0 and sh = 0."""
+    G = len(scores)
+    if G == 0:
+        return [], 0
+    vals = [float(x) for x in scores]
+    for x in vals:
+        if not math.isfinite(x) or x < 0.0:
+            raise ValueError("scores must be finite and non-negative")
+    M = max(vals)
+    if M == 0.0:
+        return [0] * G, 0
+    _, E = math.frexp(M)
+    sh = SCORE_BITS - _ceil_log2(G) - E
+    return [int(math.floor(math.ldexp(x, sh))) for x in vals], sh
+
+
+def draw_point(r: int, W: int) -> int:
+    """floor(r * W / 2^64): the draw r / 2^64 scaled to [0, W)."""
+    return (int(r) * int(W)) >> 64
+
+
+def sample_blocks(scores: Sequence[float], draws: Sequence[int], s: int,
+                  replace: bool = False) -> Dict[str, object]:
+    """Pick s blocks with probability proportional to their scores.
+
+    For draw t the remaining blocks (all blocks with replacement, the
+    not-yet-chosen ones without) are laid out in index order on [0, W), each
+    taking a length equal to its integer weight.  The point x = floor(r_t W /
+    2^64) falls in exactly one of them, and that block is chosen (the smallest
+    j whose running total exceeds x).  A zero-weight block is never chosen
+    while any remaining block has positive weight; when none has, the smallest
+    remaining index is taken.
+
+    The weight of a chosen block is 1/sqrt(s p_j) with p_j = q_j / sum(q)
+    (the scaling of the sampling matrix S in Sec. 3.1); +inf for q_j = 0.
+    The margin of draw t is the distance from x to the nearer edge of the
+    chosen interval, converted back to score units (2^-sh)."""
+    G = len(scores)
+    if s < 0 or (not replace and s > G):
+        raise ValueError("need 0 <= s <= G without replacement")
+    if len(draws) < s:
+        raise ValueError("need s draws")
+    q, sh = quantize_scores(scores)
+    total = sum(q)
+    chosen: List[int] = []
+    taken = [False] * G
+    margins: List[float] = []
+    for t in range(s):
+        W = sum(q[g] for g in range(G) if replace or not taken[g])
+        if W == 0:
+            j = next(g for g in range(G) if replace or not taken[g])
+            margins.append(0.0)
+        else:
+            x = draw_point(int(draws[t]), W)
+            acc = 0
+            j = -1
+            for g in range(G):
+                if not replace and taken[g]:
+                    continue
+                lo = acc
+                acc += q[g]
+                if acc > x:
+                    j = g
+                    margins.append(math.ldexp(float(min(x - lo, acc - 1 - x)), -sh))
+                    break
+            assert j >= 0
+        chosen.append(j)
+        taken[j] = True
+    weights = []
+    for j in chosen:
+        if q[j] == 0:
+            weights.append(math.inf)
+        else:
+            weights.append(math.sqrt(float(total) / (s * float(q[j]))))
+    return {"idx": np.array(chosen, dtype=np.int64), "weights": np.array(weights),
+            "margins": np.array(margins), "q": q, "shift": sh}
+
+
+def sampling_matrix(offsets: Sequence[int], idx: Sequence[int], weights: Sequence[float]) -> np.ndarray:
+    """Dense S of Sec. 3.1: n x c, the t-th slot of columns holds
+    I / sqrt(s p_{j_t}) in the rows of block j_t (blocks may have unequal widths)."""
+    off = np.asarray(offsets, dtype=np.int64)
+    n = int(off[-1])
+    widths = [int(off[j + 1] - off[j]) for j in idx]
+    S = np.zeros((n, int(sum(widths))))
+    c0 = 0
+    for j, w, bw in zip(idx, weights, widths):
+        for i in range(bw):
+            S[off[j] + i, c0 + i] = w
+        c0 += bw
+    return S
+
+
+def selected_columns(offsets: Sequence[int], idx: Sequence[int], dedupe: bool = True) -> np.ndarray:
+    """Column indices of the chosen blocks, in selection order (duplicates of a
+    block dropped when ``dedupe``)."""
+    off = np.asarray(offsets, dtype=np.int64)
+    seen = set()
+    cols: List[int] = []
+    for j in idx:
+        j = int(j)
+        if dedupe and j in seen:
+            continue
+        seen.add(j)
+        cols.extend(range(int(off[j]), int(off[j + 1])))
+    return np.array(cols, dtype=np.int64)
+
+
+def gather_columns(A: np.ndarray, offsets: Sequence[int], idx: Sequence[int], dedupe: bool = True) -> np.ndarray:
+    """C = A S without the scaling: the chosen column blocks side by side."""
+    return np.asarray(A)[:, selected_columns(offsets, idx, dedupe)]
+
+
+def gather_rows(A: np.ndarray, row_offsets: Sequence[int], idx: Sequence[int], dedupe: bool = True) -> np.ndarray:
+    """R = S_R^T A without the scaling: the chosen row blocks stacked."""
+    return np.asarray(A)[selected_columns(row_offsets, idx, dedupe), :]
+
+
+# ---------------------------------------------------------------------------
+# Fits and residuals (Sec. 2.1 pseudoinverse; Remark of Sec. 3.3)
+# ---------------------------------------------------------------------------
+
+def fit_columns(A: np.ndarray, C: np.ndarray) -> Tuple[np.ndarray, float]:
+    """U = C^+ A (minimum-norm least squares) and err = ||A - C U||_F,
+    the block column-subset-selection error C C^+ A of the Remark, Sec. 3.3."""
+    A = np.asarray(A, dtype=np.float64)
+    C = np.asarray(C, dtype=np.float64)
+    U = np.linalg.lstsq(C, A, rcond=None)[0]
+    E = A - C @ U
+    return U, float(math.sqrt(float(np.sum(E * E))))
+
+
+def fit_cur(A: np.ndarray, C: np.ndarray, R: np.ndarray) -> Tuple[np.ndarray, float]:
+    """U = C^+ A R^+ and err = ||A - C U R||_F (the CUR fit with both
+    projections, Sec. 2.1)."""
+    A = np.asarray(A, dtype=np.float64)
+    C = np.asarray(C, dtype=np.float64)
+    R = np.asarray(R, dtype=np.float64)
+    U = np.linalg.pinv(C) @ A @ np.linalg.pinv(R)
+    E = A - C @ U @ R
+    return U, float(math.sqrt(float(np.sum(E * E))))
+
+
+def fit_intersection(A: np.ndarray, C: np.ndarray, R: np.ndarray, Wmat: np.ndarray) -> Tuple[np.ndarray, float]:
+    """Alg. 1 step 3: U = W^+ with W = R S the scaled intersection, and
+    err = ||A - C U R||_F."""
+    U = np.linalg.pinv(np.asarray(Wmat, dtype=np.float64))
+    E = np.asarray(A, dtype=np.float64) - np.asarray(C, dtype=np.float64) @ U @ np.asarray(R, dtype=np.float64)
+    return U, float(math.sqrt(float(np.sum(E * E))))
+
+
+def cond2(C: np.ndarray) -> float:
+    s = np.linalg.svd(np.asarray(C, dtype=np.float64), compute_uv=False)
+    return float(s[0] / s[-1]) if s[-1] > 0 else math.inf
+
+
+# ---------------------------------------------------------------------------
+# The whole path
+# ---------------------------------------------------------------------------
+
+def decompose(A: np.ndarray, offsets: Sequence[int], k: int, s: int, omega: Optional[np.ndarray],
+              draws: Sequence[int], q: int = 2, replace: bool = False, mode: str = "twin",
+              row_offsets: Optional[Sequence[int]] = None, s_r: int = 0,
+              with_fit: bool = True) -> Dict[str, object]:
+    """Block CUR selection and fit.
+
+    mode "twin": scores from the float64 randomized range finder with the
+    given test matrix; mode "exact": scores from a full SVD.  Then s blocks
+    are sampled from the first s draws, C is gathered and U = C^+ A fitted
+    with its residual.  With ``row_offsets`` and s_r > 0 the row-block variant
+    also samples s_r row blocks from draws s .. s+s_r-1 by the row scores
+    ||U_k[rows_h, :]||_F^2 (Def. 2 applied to A^T; Corollary 1 uses the same
+    left-vector leverage), gathers R and fits U = C^+ A R^+."""
+    A64 = np.asarray(A, dtype=np.float64)
+    out: Dict[str, object] = {"frob2": frob2(A64), "finite": all_finite(A64)}
+    if mode == "twin":
+        rf = range_finder(A64, omega, q, k)
+        Vk, Uk = rf["Vk"], rf["Uk"]
+        out.update(ritz=rf["ritz"], lam=rf["lam"], kappa=score_condition(rf["lam"], k))
+    elif mode == "exact":
+        U_, sv, V_ = exact_svd(A64)
+        Vk, Uk = V_[:, :k], U_[:, :k]
+        lam = sv ** 2
+        out.update(ritz=sv, lam=lam, kappa=score_condition(lam, k))
+    else:
+        raise ValueError(mode)
+    out["Vk"] = Vk
+    scores = block_scores(Vk, offsets)
+    out["scores"] = scores
+    samp = sample_blocks(scores, draws[:s], s, replace)
+    out.update(idx=samp["idx"], weights=samp["weights"], margins=samp["margins"])
+    C = gather_columns(A64, offsets, samp["idx"])
+    out["cols"] = selected_columns(offsets, samp["idx"])
+    if row_offsets is not None and s_r > 0:
+        rscores = block_scores(Uk, row_offsets)
+        out["row_scores"] = rscores
+        rs = sample_blocks(rscores, draws[s:s + s_r], s_r, replace)
+        out.update(idx_r=rs["idx"], weights_r=rs["weights"], margins_r=rs["margins"])
+        out["rows"] = selected_columns(row_offsets, rs["idx"])
+        if with_fit:
+            R = gather_rows(A64, row_offsets, rs["idx"])
+            U, err = fit_cur(A64, C, R)
+            out.update(U=U, err=err)
+    elif with_fit:
+        U, err = fit_columns(A64, C)
+        out.update(U=U, err=err)
+    if with_fit:
+        out["rel_err"] = out["err"] / math.sqrt(out["frob2"]) if out["frob2"] > 0 else 0.0
+    return out

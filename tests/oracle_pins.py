@@ -1,0 +1,420 @@
+"""Pins that tie the FP64 oracle to facts other than itself.
+
+Each ``check_*`` takes an object exposing the oracle's functions (the real
+module, or a copy with one function replaced by a planted mistake) and raises
+AssertionError when the fact does not hold.  The facts come from the paper
+(definitions, the worked example of S, the identities in the appendix
+proofs) and from mathematics (Eckart-Young, closed forms, library routines,
+brute force), never from re-typing the oracle's own formula.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+import os
+
+import numpy as np
+
+from workloads import gen
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _rank_k(m, n, k, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((m, k)) @ rng.standard_normal((k, n))
+
+
+# --------------------------------------------------------------------------
+# Sec. 2.1: Frobenius norm = sum of squared singular values
+# --------------------------------------------------------------------------
+
+def check_frob_closed_form(O):
+    rng = np.random.default_rng(1)
+    for (m, n) in [(7, 5), (40, 90), (128, 33)]:
+        A = rng.standard_normal((m, n))
+        sv = np.linalg.svd(A, compute_uv=False)
+        want = float(np.sum(sv ** 2))
+        got = O.frob2(A)
+        assert abs(got - want) <= 1e-12 * want, (got, want)
+
+
+# --------------------------------------------------------------------------
+# Def. 1 / Def. 2: block leverage scores
+# --------------------------------------------------------------------------
+
+def check_scores_sum_to_k(O):
+    """||V_k||_F^2 = k for any orthonormal V_k (used in the proof of the
+    regression lemma, App. A.1.1), so the block scores sum to k."""
+    rng = np.random.default_rng(2)
+    for (n, k, b, ragged) in [(64, 5, 8, False), (200, 17, 7, False), (333, 30, 16, True)]:
+        V, _ = np.linalg.qr(rng.standard_normal((n, k)))
+        off = gen.ragged_blocks(n, -(-n // b), 3) if ragged else gen.contiguous_blocks(n, b)
+        sc = O.block_scores(V, off)
+        assert abs(float(np.sum(sc)) - k) <= 1e-12 * k, float(np.sum(sc))
+
+
+def check_scores_from_projector(O):
+    """For an exactly rank-k A, V_k V_k^T = A^+ A, so a block's score is the
+    trace of that projector's diagonal block (and b = 1 gives the column
+    leverage of Def. 1 as the projector's diagonal).  A^+ comes from
+    numpy.linalg.pinv, an independent route."""
+    A = _rank_k(60, 48, 6, 4)
+    P = np.linalg.pinv(A) @ A
+    V = O.exact_right_subspace(A, 6)
+    off = gen.contiguous_blocks(48, 5)
+    sc = O.block_scores(V, off)
+    want = np.array([np.trace(P[off[g]:off[g + 1], off[g]:off[g + 1]]) for g in range(len(off) - 1)])
+    assert np.allclose(sc, want, atol=1e-10), np.abs(sc - want).max()
+    lev = O.column_leverage(V)
+    assert np.allclose(lev, np.diag(P), atol=1e-10)
+    b1 = O.block_scores(V, np.arange(49))
+    assert np.allclose(b1, np.diag(P), atol=1e-10)
+
+
+def check_scores_bounds_permutation(O):
+    """0 <= l_g <= min(b_g, k); one block holds all k; permuting whole blocks
+    of A's columns permutes the scores (Def. 2)."""
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((50, 40)) @ np.diag(0.9 ** np.arange(40))
+    k = 7
+    off = gen.contiguous_blocks(40, 4)
+    V = O.exact_right_subspace(A, k)
+    sc = O.block_scores(V, off)
+    widths = np.diff(off)
+    assert np.all(sc >= -1e-15) and np.all(sc <= np.minimum(widths, k) + 1e-12)
+    one = O.block_scores(V, np.array([0, 40]))
+    assert abs(one[0] - k) <= 1e-12
+    perm = rng.permutation(len(off) - 1)
+    cols = np.concatenate([np.arange(off[g], off[g + 1]) for g in perm])
+    Vp = O.exact_right_subspace(A[:, cols], k)
+    scp = O.block_scores(Vp, off)
+    assert np.allclose(scp, sc[perm], atol=1e-9)
+
+
+def check_row_scores_transpose(O):
+    """Row-block scores from U_k equal column-block scores of A^T (Sec. 3:
+    row blocks are handled by transposing)."""
+    A = np.random.default_rng(6).standard_normal((36, 24))
+    roff = gen.contiguous_blocks(36, 6)
+    s1 = O.block_scores(O.exact_left_subspace(A, 5), roff)
+    s2 = O.block_scores(O.exact_right_subspace(A.T, 5), roff)
+    assert np.allclose(s1, s2, atol=1e-10)
+
+
+# --------------------------------------------------------------------------
+# Randomized range finder vs exact SVD
+# --------------------------------------------------------------------------
+
+def check_twin_exact_on_low_rank(O):
+    """If rank(A) = rho <= l the sketch spans A's row space exactly, so the
+    Rayleigh-Ritz vectors are the exact singular vectors (Sec. 2.1) and the
+    scores agree with the SVD's to rounding; the Ritz values are the singular
+    values."""
+    for (m, n, rho, k, l, seed) in [(300, 200, 15, 10, 20, 7), (120, 260, 8, 8, 12, 8)]:
+        A = gen.gaussian_product(m, n, rho, seed)
+        om = gen.rademacher(n, l, seed)
+        rf = O.range_finder(A, om, 1, k)
+        off = gen.contiguous_blocks(n, 10)
+        ex = O.block_scores(O.exact_right_subspace(A, k), off)
+        tw = O.block_scores(rf["Vk"], off)
+        assert np.allclose(tw, ex, atol=1e-10), np.abs(tw - ex).max()
+        sv = np.linalg.svd(A, compute_uv=False)
+        assert np.allclose(rf["ritz"][:rho], sv[:rho], rtol=1e-10)
+
+
+def check_twin_converges(O):
+    """With a clear gap after k, more power iterations move the sketched
+    scores toward the exact ones (subspace iteration converges)."""
+    w = gen.small_case(400, 300, 10, 8, 4, seed=9, sigma=np.r_[np.linspace(1, 0.5, 8), 0.05 * np.ones(4)],
+                       rank=12, noise=1e-3)
+    A = w.A.astype(np.float64)
+    ex = O.block_scores(O.exact_right_subspace(A, 8), w.offsets)
+    errs = [np.abs(O.block_scores(O.range_finder(A, w.omega, q, 8)["Vk"], w.offsets) - ex).max() for q in (0, 1, 3)]
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-8, errs
+
+
+# --------------------------------------------------------------------------
+# Sampling (Alg. 1 step 2, the sampling matrix S of Sec. 3.1)
+# --------------------------------------------------------------------------
+
+def check_sampler_inverse_cdf(O):
+    """With replacement, the chosen block is the inverse-CDF pick of the
+    integer weights: numpy.searchsorted(cumsum(q), x, side='right')."""
+    rng = np.random.default_rng(10)
+    for trial in range(40):
+        G = int(rng.integers(1, 60))
+        sc = rng.random(G) * (rng.random(G) < 0.8)
+        if sc.max() == 0:
+            sc[0] = 1.0
+        s = int(rng.integers(1, 10))
+        dr = gen.draws_u64(s, trial)
+        res = O.sample_blocks(sc, dr, s, replace=True)
+        q, _ = O.quantize_scores(sc)
+        cs = np.cumsum(np.array(q, dtype=np.int64))      # total < 2^62: exact in int64
+        W = int(cs[-1])
+        for t in range(s):
+            x = (int(dr[t]) * W) >> 64
+            want = int(np.searchsorted(cs, x, side="right"))
+            assert res["idx"][t] == want
+
+
+def check_sampler_edges(O):
+    """Draws that land exactly on interval edges, the extreme words 0 and
+    2^64-1, and zero-score blocks: block g owns [Q_{g-1}, Q_g) of the integer
+    line, so a point on an edge belongs to the block on its right, and a
+    zero-score block (an empty interval) is never hit.  Expected blocks come
+    from numpy.searchsorted(side='right') on the integer prefix sums."""
+    for sc in ([0.0, 1.0, 0.0, 1.0, 0.0], [0.25, 0.25, 0.5], [3.0], [0.0, 0.0, 2.0], [1.0, 0.0, 0.0]):
+        q, _ = O.quantize_scores(sc)
+        cs = np.cumsum(np.array(q, dtype=np.int64))
+        W = int(cs[-1])
+        words = [0, 2 ** 64 - 1]
+        for B in [0] + [int(v) for v in cs[:-1]]:
+            r = -(-(B << 64) // W)            # smallest r with floor(r W / 2^64) = B
+            if r < 2 ** 64:
+                words.append(r)
+        for r in words:
+            res = O.sample_blocks(sc, np.array([r], dtype=np.uint64), 1, replace=True)
+            x = (r * W) >> 64
+            want = int(np.searchsorted(cs, x, side="right"))
+            assert res["idx"][0] == want, (sc, r, res["idx"][0], want)
+            assert q[want] > 0
+    # all remaining scores zero: the smallest remaining index is taken
+    res = O.sample_blocks([0.0, 5.0, 0.0, 0.0], gen.draws_u64(3, 21), 3, replace=False)
+    assert list(res["idx"]) == [1, 0, 2]
+    assert math.isinf(res["weights"][1])
+
+
+def check_sampler_quantization_exact(O):
+    """Quantized weights are proportional to the scores to 2^-(62-ceil(log2 G))
+    of the largest score, and scaling all scores by a power of two leaves
+    them unchanged (the scale is a power of two chosen from the maximum)."""
+    rng = np.random.default_rng(11)
+    sc = rng.random(300)
+    q, sh = O.quantize_scores(sc)
+    qa = np.array(q, dtype=np.float64)
+    assert np.all(np.abs(qa / 2.0 ** sh - sc) <= 2.0 ** -sh)
+    q2, _ = O.quantize_scores(sc * 8.0)
+    assert q2 == q
+    assert sum(q) < 2 ** 62
+
+
+def check_sampler_without_replacement_law(O):
+    """Without replacement, P(first = a, second = b) = p_a p_b / (1 - p_a)
+    (successive sampling).  Chi-square test over all ordered pairs."""
+    sc = np.array([0.1, 0.4, 0.2, 0.3])
+    p = sc / sc.sum()
+    N = 20000
+    dr = gen.draws_u64(2 * N, 12)
+    counts = np.zeros((4, 4))
+    for i in range(N):
+        r = O.sample_blocks(sc, dr[2 * i:2 * i + 2], 2, replace=False)["idx"]
+        counts[r[0], r[1]] += 1
+    exp = np.array([[p[a] * p[b] / (1 - p[a]) if a != b else 0 for b in range(4)] for a in range(4)]) * N
+    mask = exp > 0
+    chi2 = float(np.sum((counts[mask] - exp[mask]) ** 2 / exp[mask]))
+    assert counts[~mask].sum() == 0
+    assert chi2 < 32.9, chi2   # 11 dof, p = 0.0005
+
+
+def check_sampler_frequencies(O):
+    """With replacement, block frequencies follow p_g = l_g / sum(l)."""
+    sc = np.array([0.05, 0.0, 0.5, 0.25, 0.2])
+    N = 40000
+    res = O.sample_blocks(sc, gen.draws_u64(N, 13), N, replace=True)
+    cnt = np.bincount(res["idx"], minlength=5)
+    p = sc / sc.sum()
+    mask = p > 0
+    chi2 = float(np.sum((cnt[mask] - N * p[mask]) ** 2 / (N * p[mask])))
+    assert cnt[1] == 0
+    assert chi2 < 18.5, chi2   # 3 dof, p = 0.0003
+
+
+def check_unbiased_scaling(O):
+    """E ||Q S||_F^2 = ||Q||_F^2 for the i.i.d. sampling with weights
+    1/sqrt(g p) (the expectation computed in the proof of the regression
+    lemma, App. A.1.1).  Monte Carlo against the closed form."""
+    rng = np.random.default_rng(14)
+    Qm = rng.standard_normal((5, 24))
+    off = gen.contiguous_blocks(24, 4)
+    sc = np.array([np.sum(Qm[:, off[g]:off[g + 1]] ** 2) for g in range(6)])
+    g = 3
+    T = 6000
+    dr = gen.draws_u64(g * T, 15)
+    vals = np.empty(T)
+    for t in range(T):
+        res = O.sample_blocks(sc, dr[g * t:g * t + g], g, replace=True)
+        S = O.sampling_matrix(off, res["idx"], res["weights"])
+        vals[t] = np.sum((Qm @ S) ** 2)
+    want = float(np.sum(Qm ** 2))
+    # with p proportional to ||Q^(i)||_F^2 the estimator has zero variance
+    assert np.allclose(vals, want, rtol=1e-9)
+    # and with other probabilities it is unbiased
+    sc2 = np.array([1.0, 2.0, 1.0, 0.5, 3.0, 1.5])
+    for t in range(T):
+        res = O.sample_blocks(sc2, dr[g * t:g * t + g], g, replace=True)
+        S = O.sampling_matrix(off, res["idx"], res["weights"])
+        vals[t] = np.sum((Qm @ S) ** 2)
+    se = vals.std() / math.sqrt(T)
+    assert abs(vals.mean() - want) < 4 * se, (vals.mean(), want, se)
+
+
+def check_block_product_variance(O):
+    """Block multiplication lemma (App. A.2 proof): E[C R] = A B and
+    E||AB - CR||_F^2 = sum_k ||A^(k) B_(k)||_F^2 / (g p_k) - ||AB||_F^2 / g
+    exactly, for C = A S and R = S^T B."""
+    rng = np.random.default_rng(16)
+    A = rng.standard_normal((4, 18))
+    B = rng.standard_normal((18, 3))
+    off = gen.contiguous_blocks(18, 3)
+    G = 6
+    sc = np.array([1.0, 0.5, 2.0, 1.0, 0.25, 1.25])
+    p = sc / sc.sum()
+    g = 2
+    T = 20000
+    dr = gen.draws_u64(g * T, 17)
+    AB = A @ B
+    errs = np.empty(T)
+    acc = np.zeros_like(AB)
+    for t in range(T):
+        res = O.sample_blocks(sc, dr[g * t:g * t + g], g, replace=True)
+        S = O.sampling_matrix(off, res["idx"], res["weights"])
+        CR = (A @ S) @ (S.T @ B)
+        acc += CR
+        errs[t] = np.sum((AB - CR) ** 2)
+    blk = [np.sum((A[:, off[i]:off[i + 1]] @ B[off[i]:off[i + 1], :]) ** 2) for i in range(G)]
+    want = sum(blk[i] / (g * p[i]) for i in range(G)) - np.sum(AB ** 2) / g
+    se = errs.std() / math.sqrt(T)
+    assert abs(errs.mean() - want) < 4 * se, (errs.mean(), want, se)
+    assert np.abs(acc / T - AB).max() < 0.1 * np.abs(AB).max()
+
+
+def check_sampling_matrix_example(O):
+    """The worked example of Sec. 3.1: blocks chosen in order [1, 3, 2]."""
+    pat = np.loadtxt(os.path.join(GOLDEN, "sampling_matrix_example.txt"), dtype=np.int64)
+    b = 2
+    off = gen.contiguous_blocks(4 * b, b)
+    p = np.array([0.4, 0.3, 0.2, 0.1])
+    g = 3
+    idx = np.array([0, 2, 1])
+    w = 1.0 / np.sqrt(g * p[idx])
+    S = O.sampling_matrix(off, idx, w)
+    assert S.shape == (4 * b, g * b)
+    for i in range(4):
+        for t in range(g):
+            blk = S[i * b:(i + 1) * b, t * b:(t + 1) * b]
+            j = pat[i, t]
+            want = np.zeros((b, b)) if j == 0 else np.eye(b) / math.sqrt(g * p[j - 1])
+            assert np.allclose(blk, want), (i, t, blk)
+
+
+# --------------------------------------------------------------------------
+# Fits and residuals
+# --------------------------------------------------------------------------
+
+def check_fit_projection(O):
+    """U = C^+ A satisfies the normal equations C^T (A - C U) = 0, selecting
+    every block gives C C^+ A = A, and the error is not below the best
+    rank-rank(C) error (Eckart-Young, Sec. 2.1); nested selections never
+    increase it."""
+    w = gen.tiny()
+    A = w.A.astype(np.float64)
+    off = w.offsets
+    C = O.gather_columns(A, off, [3, 7, 11])
+    U, err = O.fit_columns(A, C)
+    assert np.abs(C.T @ (A - C @ U)).max() <= 1e-10 * np.abs(A).max() * np.abs(C).max() * A.shape[0]
+    sv = np.linalg.svd(A, compute_uv=False)
+    r = np.linalg.matrix_rank(C)
+    assert err >= math.sqrt(np.sum(sv[r:] ** 2)) * (1 - 1e-12)
+    _, e_all = O.fit_columns(A, O.gather_columns(A, off, list(range(w.G))))
+    assert e_all <= 1e-10 * math.sqrt(O.frob2(A))
+    prev = math.inf
+    for s in range(1, 8):
+        _, e = O.fit_columns(A, O.gather_columns(A, off, list(range(0, 4 * s, 4))))
+        assert e <= prev * (1 + 1e-12)
+        prev = e
+
+
+def check_fit_bruteforce(O, max_subsets=None):
+    """Brute force over every s-subset of blocks of the tiny workload: the
+    sampled error lies between the best and worst subset, and equals that
+    subset's error computed by an independent formula,
+    err^2 = ||A||^2 - tr(G_JJ^-1 (G^2)_JJ) with G = A^T A (projection onto
+    span(C), Sec. 2.1)."""
+    w = gen.tiny()
+    A = w.A.astype(np.float64)
+    off = w.offsets
+    res = O.decompose(w.A, off, w.k, w.s, w.omega, w.draws, q=w.q)
+    Gm = A.T @ A
+    G2 = Gm @ Gm
+    f2 = float(np.sum(A * A))
+    subsets = list(itertools.combinations(range(w.G), w.s))
+    if max_subsets:
+        subsets = subsets[:max_subsets] + [tuple(sorted(res["idx"]))]
+    cols = np.array([np.concatenate([np.arange(off[j], off[j + 1]) for j in sub]) for sub in subsets])
+    GJ = Gm[cols[:, :, None], cols[:, None, :]]
+    G2J = G2[cols[:, :, None], cols[:, None, :]]
+    tr = np.trace(np.linalg.solve(GJ, G2J), axis1=1, axis2=2)
+    errs = np.sqrt(np.maximum(f2 - tr, 0.0))
+    mine = errs[subsets.index(tuple(sorted(res["idx"])))]
+    assert abs(mine - res["err"]) <= 1e-8 * res["err"], (mine, res["err"])
+    assert errs.min() * (1 - 1e-12) <= res["err"] <= errs.max() * (1 + 1e-12)
+    return errs
+
+
+def check_cur_reductions(O):
+    """Row-block CUR: with R = A (every row block) the CUR error equals the
+    column error; when C spans R^m it equals ||A - A R^+ R||_F; and the
+    identity A S (B S)^+ B = A S (V_k^T S)^+ V_k^T for rank-k B (App. A.1.1)."""
+    rng = np.random.default_rng(18)
+    A = rng.standard_normal((30, 50)) @ np.diag(0.9 ** np.arange(50))
+    coff = gen.contiguous_blocks(50, 5)
+    roff = gen.contiguous_blocks(30, 3)
+    C = O.gather_columns(A, coff, [1, 4, 6])
+    _, e_col = O.fit_columns(A, C)
+    _, e_cur = O.fit_cur(A, C, O.gather_rows(A, roff, list(range(10))))
+    assert abs(e_col - e_cur) <= 1e-9 * e_col
+    Cfull = O.gather_columns(A, coff, list(range(7)))   # 35 columns span R^30
+    R = O.gather_rows(A, roff, [0, 3, 5])
+    _, e = O.fit_cur(A, Cfull, R)
+    want = np.linalg.norm(A - A @ np.linalg.pinv(R) @ R)
+    assert abs(e - want) <= 1e-8 * want
+    B = rng.standard_normal((4, 6)) @ rng.standard_normal((6, 50))
+    _, _, Vt = np.linalg.svd(B, full_matrices=False)
+    Vk = Vt[:6].T
+    S = O.sampling_matrix(coff, [0, 2, 5, 7, 9], np.ones(5))
+    lhs = A @ S @ np.linalg.pinv(B @ S) @ B
+    rhs = A @ S @ np.linalg.pinv(Vk.T @ S) @ Vk.T
+    assert np.allclose(lhs, rhs, atol=1e-8)
+
+
+def check_paper_synthetic_generator(O):
+    """The paper's synthetic A = U V (Sec. 4.2) has rank k, so once the chosen
+    blocks span its column space, the error is zero to rounding."""
+    A = gen.gaussian_product(120, 120, 12, 19)
+    off = gen.contiguous_blocks(120, 10)
+    res = O.decompose(A, off, 12, 3, gen.rademacher(120, 22, 19), gen.draws_u64(3, 19))
+    assert res["err"] <= 1e-9 * math.sqrt(res["frob2"])
+
+
+ALL_CHECKS = [
+    check_frob_closed_form,
+    check_scores_sum_to_k,
+    check_scores_from_projector,
+    check_scores_bounds_permutation,
+    check_row_scores_transpose,
+    check_twin_exact_on_low_rank,
+    check_twin_converges,
+    check_sampler_inverse_cdf,
+    check_sampler_edges,
+    check_sampler_quantization_exact,
+    check_sampler_without_replacement_law,
+    check_sampler_frequencies,
+    check_unbiased_scaling,
+    check_block_product_variance,
+    check_sampling_matrix_example,
+    check_fit_projection,
+    check_cur_reductions,
+    check_paper_synthetic_generator,
+]

@@ -1,0 +1,152 @@
+"""Planted mistakes in the oracle (on the CPU) must trip at least one pin.
+
+Each mutant copies the oracle module's functions and replaces one of them
+with a plausible bug: a dropped square, a shifted block edge, a wrong sort
+order, a >= for a >, a missing factor, a transposed operand.  The test
+passes only if some pin raises for it."""
+import math
+import types
+
+import numpy as np
+import pytest
+
+from oracle import bcur_oracle as O
+
+from . import oracle_pins as P
+
+
+def _clone(**over):
+    ns = types.SimpleNamespace(**{k: getattr(O, k) for k in dir(O) if not k.startswith("__")})
+    for k, v in over.items():
+        setattr(ns, k, v)
+    # decompose calls module globals; rebind it to the clone's functions
+    return ns
+
+
+def _scores_norm_not_squared(V, offsets):
+    V = np.asarray(V, dtype=np.float64)
+    return np.array([np.sqrt(np.sum(V[offsets[g]:offsets[g + 1]] ** 2)) for g in range(len(offsets) - 1)])
+
+
+def _scores_edge_shift(V, offsets):
+    V = np.asarray(V, dtype=np.float64)
+    return np.array([np.sum(V[offsets[g]:offsets[g + 1] - 1] ** 2) for g in range(len(offsets) - 1)])
+
+
+def _frob_drops_row(A):
+    A = np.asarray(A, dtype=np.float64)
+    return float(np.sum(A[:-1] ** 2))
+
+
+def _range_finder_ascending(A, omega, q, k):
+    out = O.range_finder(A, omega, q, k)
+    W = out["W"][:, ::-1]
+    out = dict(out)
+    out["Vk"] = out["Q"] @ W[:, :k]
+    out["ritz"] = out["ritz"][::-1]
+    return out
+
+
+def _range_finder_no_transpose(A, omega, q, k):
+    # forgets A^T: iterates Q <- orth(A Q) on the row side (only valid when m == n)
+    A = np.asarray(A, dtype=np.float64)
+    Q = np.asarray(omega, dtype=np.float64)
+    for _ in range(q + 1):
+        Q, _ = np.linalg.qr(A[: Q.shape[0], : Q.shape[0]] @ Q)
+    T = Q.T @ (A.T @ A) @ Q
+    lam, W = np.linalg.eigh(T)
+    o = np.argsort(lam)[::-1]
+    return {"Q": Q, "Vk": Q @ W[:, o[:k]], "Uk": None, "lam": lam[o], "ritz": np.sqrt(np.abs(lam[o])), "W": W[:, o]}
+
+
+def _sample_ge(scores, draws, s, replace=False):
+    q, sh = O.quantize_scores(scores)
+    idx = []
+    taken = set()
+    for t in range(s):
+        W = sum(q[g] for g in range(len(q)) if replace or g not in taken)
+        x = O.draw_point(int(draws[t]), W)
+        acc = 0
+        for g in range(len(q)):
+            if not replace and g in taken:
+                continue
+            acc += q[g]
+            if acc >= x:
+                break
+        idx.append(g)
+        taken.add(g)
+    total = sum(q)
+    w = [math.sqrt(total / (s * q[j])) if q[j] else math.inf for j in idx]
+    return {"idx": np.array(idx), "weights": np.array(w), "margins": np.zeros(s), "q": q, "shift": sh}
+
+
+def _sample_weight_without_s(scores, draws, s, replace=False):
+    out = dict(O.sample_blocks(scores, draws, s, replace))
+    out["weights"] = out["weights"] * math.sqrt(s)
+    return out
+
+
+def _fit_transpose(A, C):
+    A = np.asarray(A, dtype=np.float64)
+    C = np.asarray(C, dtype=np.float64)
+    U = C.T @ A / max(1.0, float(np.sum(C * C)) / C.shape[1])
+    E = A - C @ U
+    return U, float(np.sqrt(np.sum(E * E)))
+
+
+def _gather_wrong_block(A, offsets, idx, dedupe=True):
+    return O.gather_columns(A, offsets, [min(int(j) + 1, len(offsets) - 2) for j in idx], dedupe)
+
+
+MUTANTS = {
+    "scores-not-squared": dict(block_scores=_scores_norm_not_squared),
+    "scores-edge-shift": dict(block_scores=_scores_edge_shift),
+    "frob-drops-row": dict(frob2=_frob_drops_row),
+    "ritz-ascending": dict(range_finder=_range_finder_ascending),
+    "range-finder-no-transpose": dict(range_finder=_range_finder_no_transpose),
+    "sampler-ge": dict(sample_blocks=_sample_ge),
+    "weights-without-s": dict(sample_blocks=_sample_weight_without_s),
+    "fit-transpose": dict(fit_columns=_fit_transpose),
+}
+
+
+def _pins_for(ns):
+    fails = []
+    for chk in P.ALL_CHECKS:
+        try:
+            chk(ns)
+        except Exception as e:  # AssertionError, shape errors, ...
+            fails.append((chk.__name__, type(e).__name__))
+    return fails
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name):
+    ns = _clone(**MUTANTS[name])
+    # decompose inside the clone must use the mutated pieces
+    def decompose(A, offsets, k, s, omega, draws, q=2, replace=False, mode="twin", row_offsets=None,
+                  s_r=0, with_fit=True):
+        A64 = np.asarray(A, dtype=np.float64)
+        rf = ns.range_finder(A64, omega, q, k)
+        sc = ns.block_scores(rf["Vk"], offsets)
+        smp = ns.sample_blocks(sc, draws[:s], s, replace)
+        C = ns.gather_columns(A64, offsets, smp["idx"])
+        U, err = ns.fit_columns(A64, C)
+        return {"idx": smp["idx"], "err": err, "frob2": ns.frob2(A64), "scores": sc}
+    ns.decompose = decompose
+    fails = _pins_for(ns)
+    assert fails, f"mutant {name} passed every pin"
+
+
+def test_gather_mutant_caught_by_bruteforce():
+    ns = _clone(gather_columns=_gather_wrong_block)
+
+    def decompose(A, offsets, k, s, omega, draws, q=2, **kw):
+        A64 = np.asarray(A, dtype=np.float64)
+        rf = ns.range_finder(A64, omega, q, k)
+        smp = ns.sample_blocks(ns.block_scores(rf["Vk"], offsets), draws[:s], s)
+        U, err = ns.fit_columns(A64, ns.gather_columns(A64, offsets, smp["idx"]))
+        return {"idx": smp["idx"], "err": err}
+    ns.decompose = decompose
+    with pytest.raises(AssertionError):
+        P.check_fit_bruteforce(ns, max_subsets=2000)
