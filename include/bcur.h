@@ -1,0 +1,250 @@
+/*
+ * bcur.h - C ABI of the Block CUR hot path on AMD Instinct MI355X (gfx950).
+ *
+ * Block CUR (Oswal, Jain, Xu, Eriksson, "Block CUR: Decomposing Matrices
+ * using Groups of Columns", arXiv 1703.06065) approximates A (m x n) from a
+ * few predefined blocks of its columns (and, optionally, rows) chosen by block
+ * leverage scores.  The library computes, on one GPU:
+ *
+ *   1. ||A||_F^2 and a finiteness check                       (Sec. 2.1)
+ *   2. a top-k right singular subspace V_k of A with a randomized range
+ *      finder (the sketching replacement for the score step, Sec. 3.1)
+ *   3. block leverage scores l_g = ||V_k^T E_g||_F^2            (Def. 2)
+ *   4. s blocks sampled with probability proportional to l_g  (Alg. 1, step 2)
+ *   5. C = A S, the chosen column blocks                      (Sec. 3.1)
+ *   6. U = C^+ A and the residual ||A - C C^+ A||_F           (Remark, Sec. 3.3)
+ *      or, for the row-block variant, U = C^+ A R^+ and ||A - C U R||_F.
+ *
+ * Conventions for every call:
+ *   - Matrices are row-major float32 with a leading dimension (elements
+ *     between consecutive rows) >= the number of columns.  Device matrices
+ *     handed to the library must be 16-byte aligned with a leading dimension
+ *     that is a multiple of 4.
+ *   - "device" pointers are HIP device memory on the context's device;
+ *     "host" pointers are ordinary host memory.  The library never takes
+ *     ownership of caller memory and never frees it.
+ *   - Work is issued on the context's stream.  Calls that return host values
+ *     synchronize that stream before returning; the others are stream-ordered
+ *     and return at once.
+ *   - Every call returns a bcur_status.  On an error nothing is written to
+ *     host outputs; device outputs may be partly written.  The message of the
+ *     last error of a context is available from bcur_last_error.
+ *   - A context is not thread safe: use one context per host thread.
+ */
+#ifndef BCUR_H
+#define BCUR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum bcur_status {
+    BCUR_OK = 0,
+    BCUR_E_ARG = 1,        /* invalid argument: shape, offsets, k, s, null pointer, alignment */
+    BCUR_E_NONFINITE = 2,  /* A holds a NaN or an Inf */
+    BCUR_E_NOMEM = 3,      /* a device or host allocation failed */
+    BCUR_E_HIP = 4,        /* a HIP runtime call or kernel launch failed */
+    BCUR_E_RANKDEF = 5,    /* a Cholesky factorization met a pivot below its threshold */
+    BCUR_E_ADMIT = 6,      /* serving: the request can never fit the memory budget */
+    BCUR_PENDING = 7,      /* serving: the request has not finished yet */
+    BCUR_E_STATE = 8       /* serving: unknown or already collected ticket */
+} bcur_status;
+
+/* Arithmetic used by the range finder's passes over A. */
+enum {
+    BCUR_PREC_FP32 = 0,    /* FP32 MFMA, FP32 accumulation */
+    BCUR_PREC_BF16 = 1     /* BF16 MFMA with FP32 accumulation, then one FP32 power pass */
+};
+
+/* Bits of bcur_result.flags. */
+enum {
+    BCUR_FLAG_RANKDEF_C = 1u << 0,   /* C^T C was numerically singular; U is not reliable */
+    BCUR_FLAG_ILLCOND_C = 1u << 1,   /* estimated cond(C)^2 * 2^-24 > 0.1: U is inaccurate */
+    BCUR_FLAG_ZERO_SCORE = 1u << 2,  /* a block of zero score was drawn (all remaining scores were 0) */
+    BCUR_FLAG_RANKDEF_Y = 1u << 3,   /* a Gram matrix of the range finder needed a diagonal shift */
+    BCUR_FLAG_RANKDEF_R = 1u << 4    /* R R^T was numerically singular (row-block variant) */
+};
+
+typedef struct bcur_ctx bcur_ctx;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device` that issues all work on `stream`
+ * (a hipStream_t owned by the caller; NULL means the device's null stream).
+ * The context owns a grow-only device workspace and a pinned host staging
+ * buffer. */
+bcur_status bcur_create(bcur_ctx** out, int device, void* stream);
+
+/* Destroy a context, freeing only what the library allocated. */
+bcur_status bcur_destroy(bcur_ctx* ctx);
+
+/* Wait for all work issued by the context. */
+bcur_status bcur_synchronize(bcur_ctx* ctx);
+
+/* Static text for a status code, and the message of the context's last error
+ * ("" if none).  The returned strings stay valid until the next call. */
+const char* bcur_status_str(int status);
+const char* bcur_last_error(const bcur_ctx* ctx);
+
+/* Bytes of device workspace currently held by the context. */
+size_t bcur_workspace_bytes(const bcur_ctx* ctx);
+
+/* ---- stage calls -------------------------------------------------------- */
+
+/* ||A||_F^2 = sum_ij A_ij^2 (Sec. 2.1, Frobenius norm), accumulated in float64
+ * in a fixed order (bitwise reproducible on one device).
+ * A: device, m x n, leading dimension lda.  out_frob2: host, one double.
+ * out_finite: host, set to 1 when every entry is finite, else 0.
+ * Synchronous. */
+bcur_status bcur_frob2(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda,
+                       double* out_frob2, int32_t* out_finite);
+
+/* Randomized range finder: an orthonormal basis V_k (n x k) of the top-k
+ * right singular subspace of A, the sketch that Sec. 3.1 allows in place of
+ * an SVD.  Q starts as the test matrix omega (n x l, l = k + oversampling);
+ * q+1 times Q <- orth(A^T (A Q)) (Cholesky QR with float64 Gram matrices);
+ * then Rayleigh-Ritz: Z = A Q, T = Z^T Z, T = W diag(lam) W^T (float64
+ * Jacobi), V_k = Q W[:, :k], Ritz values sqrt(lam).
+ * A: device m x n (lda).  omega: device n x l float32, row-major, dense.
+ * precision: BCUR_PREC_FP32 or BCUR_PREC_BF16.
+ * Vk: device n x k float32 (leading dimension k), written.
+ * Uk: device m x k (leading dimension k) or NULL; when given, receives
+ *     Z W[:, :k] diag(1/sqrt(lam_k)), the matching left vectors.
+ * ritz: host, l doubles, or NULL (Ritz singular values, descending).
+ * Requires 1 <= k <= l <= min(m, n, 112).  Synchronous when ritz != NULL. */
+bcur_status bcur_range_finder(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda,
+                              const float* omega, int64_t l, int64_t k, int64_t q, int32_t precision,
+                              float* Vk, float* Uk, double* ritz);
+
+/* Block leverage scores l_g = ||V^T E_g||_F^2 (Def. 2): the sum of squares of
+ * rows offsets[g] .. offsets[g+1]-1 of V, accumulated in float64.
+ * V: device n x k (ldv).  offsets: host, G+1 int64, offsets[0] = 0,
+ * strictly increasing, offsets[G] = n.  scores: host, G doubles.
+ * Synchronous. */
+bcur_status bcur_block_scores(bcur_ctx* ctx, const float* V, int64_t n, int64_t k, int64_t ldv,
+                              const int64_t* offsets, int64_t G, double* scores);
+
+/* Sample s blocks with probability proportional to their scores (Alg. 1,
+ * step 2), on the device.  Scores are quantized exactly to integers
+ * q_g = floor(l_g 2^sh) with one power-of-two scale sh = 62 - ceil(log2 G)
+ * - E, where max_g l_g = f 2^E, f in [0.5, 1).  Draw t maps the 64-bit word
+ * r_t to x = floor(r_t W / 2^64) on [0, W), W the total weight of the
+ * remaining blocks (all blocks when replace != 0, the not yet chosen ones
+ * otherwise), and picks the block whose interval, laid out in index order,
+ * holds x.  When every remaining weight is zero the smallest remaining index
+ * is taken.  weights_t = 1/sqrt(s p_j), p_j = q_j / sum(q) (the scaling of
+ * S, Sec. 3.1), +inf for a zero-weight block.
+ * scores: host, G finite non-negative doubles.  draws: host, s words.
+ * idx: host, s int64.  weights: host, s doubles or NULL.  margins: host, s
+ * doubles or NULL (distance of x to the nearer edge of its interval, in score
+ * units).  Needs s <= G when replace == 0.  Synchronous. */
+bcur_status bcur_sample_blocks(bcur_ctx* ctx, const double* scores, int64_t G, const uint64_t* draws,
+                               int64_t s, int32_t replace, int64_t* idx, double* weights, double* margins);
+
+/* C = A S without scaling (Sec. 3.1): the column blocks idx[0..s-1] of A side
+ * by side in selection order; a block listed twice is copied once.
+ * A: device m x n (lda).  offsets: host G+1.  idx: host s.
+ * C: device m x c (ldc >= c), written.  c_out: host, receives c.
+ * Stream-ordered (returns before the copy completes). */
+bcur_status bcur_gather_columns(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda,
+                                const int64_t* offsets, int64_t G, const int64_t* idx, int64_t s,
+                                float* C, int64_t ldc, int64_t* c_out);
+
+/* U = C^+ A (Sec. 2.1 pseudoinverse; the block column-subset-selection fit
+ * of the Remark in Sec. 3.3) by the normal equations: H = C^T A and
+ * C^T C on the MFMA units, a float64 Cholesky inverse of C^T C, then
+ * `refine` (0 or 1) steps of iterative refinement with the explicit residual
+ * E = A - C U.  err = ||A - C U||_F.
+ * A: device m x n (lda).  C: device m x c (ldc).  U: device c x n (ldu),
+ * written.  err: host double.  flags: host uint32 (BCUR_FLAG_*), or NULL.
+ * Synchronous. */
+bcur_status bcur_fit_columns(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda,
+                             const float* C, int64_t c, int64_t ldc, int32_t refine,
+                             float* U, int64_t ldu, double* err, uint32_t* flags);
+
+/* ---- profiling ---------------------------------------------------------- */
+
+/* Device time per stage, measured with HIP events recorded on the context's
+ * stream around each stage's kernels (the events bracket exactly the launches
+ * named below, so their elapsed time is those kernels' duration). */
+enum {
+    BCUR_STAGE_FROB = 0,      /* ||A||_F^2 */
+    BCUR_STAGE_RF_AQ = 1,     /* Z = A Q, main GEMM kernel (range finder) */
+    BCUR_STAGE_RF_ATZ = 2,    /* Y = A^T Z, main GEMM kernel (range finder) */
+    BCUR_STAGE_RF_REDUCE = 3, /* split-K sums of the range finder GEMMs */
+    BCUR_STAGE_RF_ORTH = 4,   /* Cholesky QR: Gram, factor, apply */
+    BCUR_STAGE_RF_RR = 5,     /* Rayleigh-Ritz: Gram, Jacobi, V_k */
+    BCUR_STAGE_SCORES = 6,    /* block leverage scores */
+    BCUR_STAGE_SAMPLE = 7,    /* block sampling */
+    BCUR_STAGE_GATHER = 8,    /* C = A S */
+    BCUR_STAGE_FIT_H = 9,     /* H = C^T A, main GEMM kernel */
+    BCUR_STAGE_FIT_REDUCE = 10, /* split-K sums of the fit GEMMs */
+    BCUR_STAGE_FIT_INV = 11,  /* (C^T C)^-1: blocked FP64 Cholesky inverse */
+    BCUR_STAGE_FIT_U = 12,    /* U = Ginv H */
+    BCUR_STAGE_FIT_E = 13,    /* E = A - C U with ||E||_F^2 */
+    BCUR_STAGE_FIT_F = 14,    /* F = C^T E, main GEMM kernel */
+    BCUR_STAGE_FIT_DU = 15,   /* U += Ginv F with <Ginv F, F> */
+    BCUR_NUM_STAGES = 16
+};
+
+/* Turn stage timing on (1) or off (0); turning it on clears the totals. */
+bcur_status bcur_timing_enable(bcur_ctx* ctx, int32_t on);
+
+/* Totals since timing was enabled: ms[i] milliseconds and count[i] launches
+ * of stage i, for i < BCUR_NUM_STAGES (host arrays).  Synchronizes. */
+bcur_status bcur_timing_read(bcur_ctx* ctx, double* ms, int64_t* count);
+
+/* ---- the whole path ----------------------------------------------------- */
+
+typedef struct bcur_params {
+    int64_t k;          /* target rank, 1 <= k */
+    int64_t s;          /* number of column blocks to sample */
+    int64_t l;          /* sketch width k + oversampling; l <= min(m, n, 112) */
+    int64_t q;          /* power iterations (the range finder applies A^T A q+1 times) */
+    int32_t replace;    /* 0: without replacement (default), 1: independent draws */
+    int32_t precision;  /* BCUR_PREC_FP32 or BCUR_PREC_BF16 */
+    int32_t refine;     /* refinement steps of the least-squares fit: 0 or 1 */
+    int32_t reserved;
+    int64_t s_r;        /* row blocks to sample for the row-block variant, 0 = columns only */
+} bcur_params;
+
+typedef struct bcur_result {
+    /* caller-provided buffers (capacities in parentheses) */
+    int64_t* idx;        /* host (s): chosen column blocks, selection order */
+    double* weights;     /* host (s) or NULL: 1/sqrt(s p) of each draw */
+    double* scores;      /* host (G) or NULL: block leverage scores */
+    double* ritz;        /* host (l) or NULL: Ritz singular values */
+    float* U;            /* device or NULL: U, c x n (columns only) or c x r (row variant) */
+    int64_t ldu;         /* leading dimension of U */
+    int64_t u_rows_cap;  /* rows U can hold (>= c) */
+    int64_t* idx_r;      /* host (s_r) or NULL: chosen row blocks (row variant) */
+    double* row_scores;  /* host (Gr) or NULL */
+    /* outputs */
+    int64_t c;           /* columns of C */
+    int64_t r;           /* rows of R (row variant), else 0 */
+    double frob2;        /* ||A||_F^2 */
+    double err;          /* ||A - C U||_F, or ||A - C U R||_F for the row variant */
+    double rel_err;      /* err / ||A||_F */
+    double min_margin;   /* smallest sampling margin over the column draws */
+    uint32_t flags;      /* BCUR_FLAG_* */
+    uint32_t reserved;
+} bcur_result;
+
+/* One Block CUR decomposition: stages 1-6 above.
+ * A: device m x n (lda).  col_off: host G+1 column-block offsets.
+ * row_off: host Gr+1 row-block offsets, or NULL (columns only).
+ * omega: device n x l Rademacher (or any) test matrix.  draws: host, s + s_r
+ * 64-bit words (column draws first).  Synchronous. */
+bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda,
+                           const int64_t* col_off, int64_t G, const int64_t* row_off, int64_t Gr,
+                           const bcur_params* params, const float* omega, const uint64_t* draws,
+                           bcur_result* result);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BCUR_H */

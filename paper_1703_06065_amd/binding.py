@@ -1,0 +1,287 @@
+"""ctypes binding of the Block CUR C ABI (include/bcur.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Device matrices are torch CUDA tensors (float32, row-major, 16-byte
+aligned, leading dimension a multiple of 4); small host arrays are numpy.
+Work is issued on torch's current stream.
+
+The library must have been built (``python -m paper_1703_06065_amd.build``);
+loading fails loudly otherwise -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbcur.so")
+
+OK, E_ARG, E_NONFINITE, E_NOMEM, E_HIP, E_RANKDEF, E_ADMIT, PENDING, E_STATE = range(9)
+PREC_FP32, PREC_BF16 = 0, 1
+FLAG_RANKDEF_C, FLAG_ILLCOND_C, FLAG_ZERO_SCORE, FLAG_RANKDEF_Y, FLAG_RANKDEF_R = 1, 2, 4, 8, 16
+
+# every symbol declared in include/bcur.h
+SYMBOLS = [
+    "bcur_create", "bcur_destroy", "bcur_synchronize", "bcur_status_str", "bcur_last_error",
+    "bcur_workspace_bytes", "bcur_frob2", "bcur_range_finder", "bcur_block_scores", "bcur_sample_blocks",
+    "bcur_gather_columns", "bcur_fit_columns", "bcur_decompose", "bcur_timing_enable", "bcur_timing_read",
+]
+
+STAGES = ["frob", "rf_AQ", "rf_AtZ", "rf_reduce", "rf_orth", "rf_rr", "scores", "sample", "gather", "fit_H",
+          "fit_reduce", "fit_inv", "fit_U", "fit_E", "fit_F", "fit_dU"]
+
+
+class BcurError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"bcur status {status}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int64), ("s", ctypes.c_int64), ("l", ctypes.c_int64), ("q", ctypes.c_int64),
+                ("replace", ctypes.c_int32), ("precision", ctypes.c_int32), ("refine", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("s_r", ctypes.c_int64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("idx", ctypes.POINTER(ctypes.c_int64)), ("weights", ctypes.POINTER(ctypes.c_double)),
+                ("scores", ctypes.POINTER(ctypes.c_double)), ("ritz", ctypes.POINTER(ctypes.c_double)),
+                ("U", ctypes.c_void_p), ("ldu", ctypes.c_int64), ("u_rows_cap", ctypes.c_int64),
+                ("idx_r", ctypes.POINTER(ctypes.c_int64)), ("row_scores", ctypes.POINTER(ctypes.c_double)),
+                ("c", ctypes.c_int64), ("r", ctypes.c_int64), ("frob2", ctypes.c_double), ("err", ctypes.c_double),
+                ("rel_err", ctypes.c_double), ("min_margin", ctypes.c_double), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libbcur.so and declare the signatures of every exported call."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1703_06065_amd.build`")
+    lib = ctypes.CDLL(path)
+    i64, i32, u32, dbl, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_double, ctypes.c_void_p
+    P = ctypes.POINTER
+    sig = {
+        "bcur_create": (i32, [P(vp), i32, vp]),
+        "bcur_destroy": (i32, [vp]),
+        "bcur_synchronize": (i32, [vp]),
+        "bcur_status_str": (ctypes.c_char_p, [i32]),
+        "bcur_last_error": (ctypes.c_char_p, [vp]),
+        "bcur_workspace_bytes": (ctypes.c_size_t, [vp]),
+        "bcur_frob2": (i32, [vp, vp, i64, i64, i64, P(dbl), P(i32)]),
+        "bcur_range_finder": (i32, [vp, vp, i64, i64, i64, vp, i64, i64, i64, i32, vp, vp, P(dbl)]),
+        "bcur_block_scores": (i32, [vp, vp, i64, i64, i64, P(i64), i64, P(dbl)]),
+        "bcur_sample_blocks": (i32, [vp, P(dbl), i64, P(ctypes.c_uint64), i64, i32, P(i64), P(dbl), P(dbl)]),
+        "bcur_gather_columns": (i32, [vp, vp, i64, i64, i64, P(i64), i64, P(i64), i64, vp, i64, P(i64)]),
+        "bcur_fit_columns": (i32, [vp, vp, i64, i64, i64, vp, i64, i64, i32, vp, i64, P(dbl), P(u32)]),
+        "bcur_timing_enable": (i32, [vp, i32]),
+        "bcur_timing_read": (i32, [vp, P(dbl), P(i64)]),
+        "bcur_decompose": (i32, [vp, vp, i64, i64, i64, P(i64), i64, P(i64), i64, P(Params), vp,
+                                 P(ctypes.c_uint64), P(Result)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _i64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.int64)
+
+
+def _check_dev(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name} must be a 2-D row-major tensor")
+    return t.data_ptr(), t.shape[0], t.shape[1], t.stride(0)
+
+
+def to_device(a, device="cuda"):
+    """Copy a 2-D host array to a float32 CUDA view with a padded leading dimension."""
+    import torch
+    a = np.asarray(a, dtype=np.float32)
+    t = padded_empty(a.shape[0], a.shape[1], device)
+    t.copy_(torch.from_numpy(np.ascontiguousarray(a)))
+    return t
+
+
+def padded_empty(rows: int, cols: int, device="cuda"):
+    """A rows x cols float32 CUDA view whose leading dimension is a multiple of 4."""
+    import torch
+    ld = (cols + 3) // 4 * 4
+    return torch.empty((rows, ld), dtype=torch.float32, device=device)[:, :cols]
+
+
+class Context:
+    """One library context bound to a device and to torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.lib = load_library()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self._stream = stream
+        h = ctypes.c_void_p()
+        st = self.lib.bcur_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream))
+        if st != OK:
+            raise BcurError(st, self.lib.bcur_status_str(st).decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.bcur_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, st):
+        if st != OK:
+            raise BcurError(st, f"{self.lib.bcur_status_str(st).decode()}: {self.lib.bcur_last_error(self.h).decode()}")
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(self.lib.bcur_workspace_bytes(self.h))
+
+    # -- profiling ---------------------------------------------------------
+    def timing_enable(self, on: bool = True):
+        self._chk(self.lib.bcur_timing_enable(self.h, int(on)))
+
+    def timing_read(self):
+        ms = np.zeros(len(STAGES))
+        cnt = np.zeros(len(STAGES), dtype=np.int64)
+        self._chk(self.lib.bcur_timing_read(self.h, _ptr(ms, ctypes.c_double), _ptr(cnt, ctypes.c_int64)))
+        return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(STAGES)}
+
+    # -- stages ------------------------------------------------------------
+    def frob2(self, A):
+        p, m, n, lda = _check_dev(A, "A")
+        out = ctypes.c_double()
+        fin = ctypes.c_int32()
+        self._chk(self.lib.bcur_frob2(self.h, p, m, n, lda, ctypes.byref(out), ctypes.byref(fin)))
+        return out.value, bool(fin.value)
+
+    def range_finder(self, A, omega, k: int, q: int = 2, precision: int = PREC_FP32, want_u: bool = False):
+        import torch
+        p, m, n, lda = _check_dev(A, "A")
+        po, on, l, ldo = _check_dev(omega, "omega")
+        if on != n or ldo != l:
+            raise ValueError("omega must be a dense n x l tensor")
+        V = torch.empty((n, k), dtype=torch.float32, device=A.device)
+        U = torch.empty((m, k), dtype=torch.float32, device=A.device) if want_u else None
+        ritz = np.empty(l)
+        self._chk(self.lib.bcur_range_finder(self.h, p, m, n, lda, po, l, k, q, precision, V.data_ptr(),
+                                             U.data_ptr() if U is not None else None, _ptr(ritz, ctypes.c_double)))
+        return V, U, ritz
+
+    def block_scores(self, V, offsets):
+        p, n, k, ldv = _check_dev(V, "V")
+        off = _i64(offsets)
+        G = len(off) - 1
+        out = np.empty(G)
+        self._chk(self.lib.bcur_block_scores(self.h, p, n, k, ldv, _ptr(off, ctypes.c_int64), G,
+                                             _ptr(out, ctypes.c_double)))
+        return out
+
+    def sample_blocks(self, scores, draws, s: int, replace: bool = False):
+        sc = np.ascontiguousarray(scores, dtype=np.float64)
+        dr = np.ascontiguousarray(draws, dtype=np.uint64)
+        idx = np.empty(s, dtype=np.int64)
+        w = np.empty(s)
+        mg = np.empty(s)
+        self._chk(self.lib.bcur_sample_blocks(self.h, _ptr(sc, ctypes.c_double), len(sc),
+                                              _ptr(dr, ctypes.c_uint64), s, int(replace), _ptr(idx, ctypes.c_int64),
+                                              _ptr(w, ctypes.c_double), _ptr(mg, ctypes.c_double)))
+        return idx, w, mg
+
+    def gather_columns(self, A, offsets, idx):
+        p, m, n, lda = _check_dev(A, "A")
+        off = _i64(offsets)
+        ix = _i64(idx)
+        widths = np.diff(off)
+        cap = int(sum(widths[j] for j in set(ix.tolist())))
+        C = padded_empty(m, max(cap, 1), A.device)
+        c = ctypes.c_int64()
+        self._chk(self.lib.bcur_gather_columns(self.h, p, m, n, lda, _ptr(off, ctypes.c_int64), len(off) - 1,
+                                               _ptr(ix, ctypes.c_int64), len(ix), C.data_ptr(), C.stride(0),
+                                               ctypes.byref(c)))
+        return C[:, :c.value]
+
+    def fit_columns(self, A, C, refine: int = 1):
+        p, m, n, lda = _check_dev(A, "A")
+        pc, mc, c, ldc = _check_dev(C, "C")
+        U = padded_empty(c, n, A.device)
+        err = ctypes.c_double()
+        fl = ctypes.c_uint32()
+        self._chk(self.lib.bcur_fit_columns(self.h, p, m, n, lda, pc, c, ldc, refine, U.data_ptr(), U.stride(0),
+                                            ctypes.byref(err), ctypes.byref(fl)))
+        return U, err.value, fl.value
+
+    # -- the whole path ----------------------------------------------------
+    def decompose(self, A, offsets, k: int, s: int, omega, draws, q: int = 2, replace: bool = False,
+                  refine: int = 1, precision: int = PREC_FP32, want_u: bool = True, row_offsets=None,
+                  s_r: int = 0, U_out=None):
+        p, m, n, lda = _check_dev(A, "A")
+        po, on, l, ldo = _check_dev(omega, "omega")
+        if on != n or ldo != l:
+            raise ValueError("omega must be a dense n x l tensor")
+        off = _i64(offsets)
+        G = len(off) - 1
+        dr = np.ascontiguousarray(draws, dtype=np.uint64)
+        prm = Params(k=k, s=s, l=l, q=q, replace=int(replace), precision=precision, refine=refine, reserved=0,
+                     s_r=s_r)
+        idx = np.empty(s, dtype=np.int64)
+        w = np.empty(s)
+        sc = np.empty(G)
+        ritz = np.empty(l)
+        res = Result()
+        res.idx = _ptr(idx, ctypes.c_int64)
+        res.weights = _ptr(w, ctypes.c_double)
+        res.scores = _ptr(sc, ctypes.c_double)
+        res.ritz = _ptr(ritz, ctypes.c_double)
+        U = None
+        if want_u:
+            cap = min(s * int(np.max(np.diff(off))), n)
+            U = U_out if U_out is not None else padded_empty(cap, n, A.device)
+            res.U = U.data_ptr()
+            res.ldu = U.stride(0)
+            res.u_rows_cap = U.shape[0]
+        roff_p, Gr = None, 0
+        idx_r = None
+        if row_offsets is not None:
+            roff = _i64(row_offsets)
+            Gr = len(roff) - 1
+            roff_p = _ptr(roff, ctypes.c_int64)
+            idx_r = np.empty(max(s_r, 1), dtype=np.int64)
+            res.idx_r = _ptr(idx_r, ctypes.c_int64)
+        self._chk(self.lib.bcur_decompose(self.h, p, m, n, lda, _ptr(off, ctypes.c_int64), G, roff_p, Gr,
+                                          ctypes.byref(prm), po, _ptr(dr, ctypes.c_uint64), ctypes.byref(res)))
+        out = {"idx": idx, "weights": w, "scores": sc, "ritz": ritz, "c": res.c, "r": res.r, "frob2": res.frob2,
+               "err": res.err, "rel_err": res.rel_err, "min_margin": res.min_margin, "flags": res.flags}
+        if U is not None:
+            out["U"] = U[:res.c]
+        if idx_r is not None:
+            out["idx_r"] = idx_r[:s_r]
+        return out

@@ -1,0 +1,789 @@
+// Host runtime of the Block CUR library: context, workspace, the stage
+// drivers and the C ABI declared in include/bcur.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/bcur.h"
+#include "bcur_internal.h"
+
+using namespace bcur;
+
+// Per-stage device timing: event pairs are recorded on the context's stream
+// and resolved (elapsed time added to the stage total) on the next read.
+struct StageTimer {
+    bool on = false;
+    std::vector<hipEvent_t> pool;                 // free events
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    double ms[BCUR_NUM_STAGES] = {};
+    int64_t count[BCUR_NUM_STAGES] = {};
+};
+
+struct bcur_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    char* pinned = nullptr;
+    size_t pinned_bytes = 0;
+    std::string err;
+    StageTimer timer;
+};
+
+namespace {
+
+constexpr int64_t kMaxSketch = 112;
+
+inline int64_t round4(int64_t x) { return (x + 3) & ~(int64_t)3; }
+
+bcur_status fail(bcur_ctx* ctx, bcur_status st, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+bcur_status fail(bcur_ctx* ctx, bcur_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess) return fail(ctx, BCUR_E_HIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                                          __FILE__, __LINE__);                                         \
+    } while (0)
+
+#define STCHK(expr)                           \
+    do {                                      \
+        bcur_status s_ = (expr);              \
+        if (s_ != BCUR_OK) return s_;         \
+    } while (0)
+
+// Bump allocator over the context workspace.  Layout functions run twice:
+// once with a null base to size the workspace, once to hand out pointers.
+struct Arena {
+    char* base = nullptr;
+    size_t off = 0;
+    template <class T>
+    T* take(size_t count) {
+        off = (off + 255) & ~(size_t)255;
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+bcur_status reserve(bcur_ctx* ctx, size_t bytes) {
+    if (bytes <= ctx->ws_bytes) return BCUR_OK;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (ctx->ws) HIPCHK(hipFree(ctx->ws));
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+    size_t want = bytes + bytes / 8;
+    if (hipMalloc(&ctx->ws, want) != hipSuccess) {
+        ctx->ws = nullptr;
+        return fail(ctx, BCUR_E_NOMEM, "device workspace of %zu bytes", want);
+    }
+    ctx->ws_bytes = want;
+    return BCUR_OK;
+}
+
+bcur_status reserve_pinned(bcur_ctx* ctx, size_t bytes) {
+    if (bytes <= ctx->pinned_bytes) return BCUR_OK;
+    if (ctx->pinned) HIPCHK(hipHostFree(ctx->pinned));
+    ctx->pinned = nullptr;
+    ctx->pinned_bytes = 0;
+    if (hipHostMalloc((void**)&ctx->pinned, bytes, hipHostMallocDefault) != hipSuccess) {
+        ctx->pinned = nullptr;
+        return fail(ctx, BCUR_E_NOMEM, "pinned host buffer of %zu bytes", bytes);
+    }
+    ctx->pinned_bytes = bytes;
+    return BCUR_OK;
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+hipEvent_t timer_event(bcur_ctx* ctx) {
+    StageTimer& t = ctx->timer;
+    if (!t.pool.empty()) {
+        hipEvent_t e = t.pool.back();
+        t.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records the start of a stage; the matching stage_end closes it.
+struct StageScope {
+    bcur_ctx* ctx;
+    int stage;
+    hipEvent_t a = nullptr;
+    StageScope(bcur_ctx* c, int s) : ctx(c), stage(s) {
+        if (!ctx->timer.on) return;
+        a = timer_event(ctx);
+        if (a && hipEventRecord(a, ctx->stream) != hipSuccess) a = nullptr;
+    }
+    ~StageScope() {
+        if (!a) return;
+        hipEvent_t b = timer_event(ctx);
+        if (!b || hipEventRecord(b, ctx->stream) != hipSuccess) {
+            ctx->timer.pool.push_back(a);
+            if (b) ctx->timer.pool.push_back(b);
+            return;
+        }
+        ctx->timer.pending.push_back({stage, {a, b}});
+    }
+};
+
+void timer_resolve(bcur_ctx* ctx) {
+    StageTimer& t = ctx->timer;
+    for (auto& p : t.pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.second.second) == hipSuccess &&
+            hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) {
+            t.ms[p.first] += ms;
+            t.count[p.first] += 1;
+        }
+        t.pool.push_back(p.second.first);
+        t.pool.push_back(p.second.second);
+    }
+    t.pending.clear();
+}
+
+bcur_status check_matrix(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda, const char* name) {
+    if (!A) return fail(ctx, BCUR_E_ARG, "%s is null", name);
+    if (m < 1 || n < 1) return fail(ctx, BCUR_E_ARG, "%s has shape %lld x %lld", name, (long long)m, (long long)n);
+    if (lda < n) return fail(ctx, BCUR_E_ARG, "%s: leading dimension %lld < %lld", name, (long long)lda, (long long)n);
+    if (!aligned16(A) || (lda & 3))
+        return fail(ctx, BCUR_E_ARG, "%s must be 16-byte aligned with a leading dimension that is a multiple of 4", name);
+    return BCUR_OK;
+}
+
+bcur_status check_offsets(bcur_ctx* ctx, const int64_t* off, int64_t G, int64_t n, const char* name) {
+    if (!off || G < 1) return fail(ctx, BCUR_E_ARG, "%s: need G >= 1 offsets", name);
+    if (off[0] != 0 || off[G] != n) return fail(ctx, BCUR_E_ARG, "%s must start at 0 and end at %lld", name, (long long)n);
+    for (int64_t g = 0; g < G; ++g)
+        if (off[g + 1] <= off[g]) return fail(ctx, BCUR_E_ARG, "%s must be strictly increasing (block %lld)", name, (long long)g);
+    return BCUR_OK;
+}
+
+// Column (or row) indices of the chosen blocks in selection order, each block once.
+std::vector<int64_t> expand_blocks(const int64_t* off, const int64_t* idx, int64_t s) {
+    std::vector<int64_t> out;
+    std::vector<int64_t> seen;
+    for (int64_t t = 0; t < s; ++t) {
+        const int64_t j = idx[t];
+        if (std::find(seen.begin(), seen.end(), j) != seen.end()) continue;
+        seen.push_back(j);
+        for (int64_t c = off[j]; c < off[j + 1]; ++c) out.push_back(c);
+    }
+    return out;
+}
+
+// ---- range finder ---------------------------------------------------------
+
+struct RFBufs {
+    float *Q, *Y, *Z, *part;
+    double *gpart, *T, *Rinv, *Wk, *Wks, *lam;
+    int* info;
+};
+
+size_t rf_partial_floats(int64_t m, int64_t n, int64_t l) {
+    const GemmPlan p1 = plan_sgemm(m, l, n, false, true);
+    const GemmPlan p2 = plan_sgemm(n, l, m, true, true);
+    return std::max(sgemm_partial_floats(p1, m, l), sgemm_partial_floats(p2, n, l));
+}
+
+void rf_layout(Arena& a, RFBufs& b, int64_t m, int64_t n, int64_t l, int64_t k) {
+    const int64_t lp = round4(l);
+    b.Q = a.take<float>(n * lp);
+    b.Y = a.take<float>(n * lp);
+    b.Z = a.take<float>(m * lp);
+    b.part = a.take<float>(std::max<size_t>(rf_partial_floats(m, n, l), 4));
+    const int w = std::max(gram_wgs(n), gram_wgs(m));
+    b.gpart = a.take<double>((size_t)w * l * l);
+    b.T = a.take<double>(l * l);
+    b.Rinv = a.take<double>(l * l);
+    b.Wk = a.take<double>(l * k);
+    b.Wks = a.take<double>(l * k);
+    b.lam = a.take<double>(l);
+    b.info = a.take<int>(4);
+}
+
+// A GEMM whose main kernel is timed as `stage` and its split-K sum as `rstage`.
+bcur_status gemm_timed(bcur_ctx* ctx, int stage, int rstage, const GemmPlan& p, int64_t M, int64_t N, int64_t K,
+                       bool tA, const float* A, int64_t lda, const float* B, int64_t ldb, float* D, int64_t ldd,
+                       float* part, int epi = EPI_STORE, const float* X = nullptr, int64_t ldx = 0,
+                       const float* Y = nullptr, int64_t ldy = 0, double* wsum = nullptr) {
+    {
+        StageScope ts(ctx, stage);
+        HIPCHK(launch_sgemm_main(p, M, N, K, tA, A, lda, B, ldb, D, ldd, part, epi, X, ldx, Y, ldy, wsum, ctx->stream));
+    }
+    if (p.splits > 1) {
+        StageScope ts(ctx, rstage);
+        HIPCHK(launch_splitk_reduce(p, M, N, part, D, ldd, ctx->stream));
+    }
+    return BCUR_OK;
+}
+
+bcur_status cholqr(bcur_ctx* ctx, const RFBufs& b, const float* X, int64_t rows, int64_t l, float* out) {
+    const int64_t lp = round4(l);
+    const int w = gram_wgs(rows);
+    HIPCHK(launch_gram64(X, rows, l, lp, b.gpart, w, b.T, ctx->stream));
+    HIPCHK(launch_chol_rinv_small(b.T, l, b.Rinv, b.info, ctx->stream));
+    HIPCHK(launch_apply_small(X, rows, l, lp, b.Rinv, l, l, out, lp, ctx->stream));
+    return BCUR_OK;
+}
+
+// Q <- omega; q+1 times Q <- orth(A^T (A Q)); Rayleigh-Ritz.  Vk (n x k, ld k),
+// Uk (m x k, ld k) if non-null, lam (device, l).
+bcur_status range_finder_run(bcur_ctx* ctx, const RFBufs& b, const float* A, int64_t m, int64_t n, int64_t lda,
+                             const float* omega, int64_t l, int64_t k, int64_t q, float* Vk, float* Uk) {
+    hipStream_t st = ctx->stream;
+    const int64_t lp = round4(l);
+    HIPCHK(hipMemsetAsync(b.info, 0, 4 * sizeof(int), st));
+    HIPCHK(hipMemcpy2DAsync(b.Q, lp * sizeof(float), omega, l * sizeof(float), l * sizeof(float), n,
+                            hipMemcpyDeviceToDevice, st));
+    const GemmPlan pz = plan_sgemm(m, l, n, false, true);
+    const GemmPlan py = plan_sgemm(n, l, m, true, true);
+    for (int64_t it = 0; it <= q; ++it) {
+        STCHK(gemm_timed(ctx, BCUR_STAGE_RF_AQ, BCUR_STAGE_RF_REDUCE, pz, m, l, n, false, A, lda, b.Q, lp, b.Z, lp,
+                         b.part));
+        STCHK(gemm_timed(ctx, BCUR_STAGE_RF_ATZ, BCUR_STAGE_RF_REDUCE, py, n, l, m, true, A, lda, b.Z, lp, b.Y, lp,
+                         b.part));
+        StageScope ts(ctx, BCUR_STAGE_RF_ORTH);
+        STCHK(cholqr(ctx, b, b.Y, n, l, b.Q));
+        STCHK(cholqr(ctx, b, b.Q, n, l, b.Q));
+    }
+    STCHK(gemm_timed(ctx, BCUR_STAGE_RF_AQ, BCUR_STAGE_RF_REDUCE, pz, m, l, n, false, A, lda, b.Q, lp, b.Z, lp,
+                     b.part));
+    StageScope ts(ctx, BCUR_STAGE_RF_RR);
+    HIPCHK(launch_gram64(b.Z, m, l, lp, b.gpart, gram_wgs(m), b.T, st));
+    HIPCHK(launch_jacobi_eigh(b.T, l, k, b.lam, b.Wk, b.Wks, b.info + 2, st));
+    HIPCHK(launch_apply_small(b.Q, n, l, lp, b.Wk, k, k, Vk, k, st));
+    if (Uk) HIPCHK(launch_apply_small(b.Z, m, l, lp, b.Wks, k, k, Uk, k, st));
+    return BCUR_OK;
+}
+
+// ---- fit ------------------------------------------------------------------
+
+struct FitBufs {
+    float *H, *E, *F, *Ginv32, *part, *Gtmp;
+    double *G, *Ginv, *spdws, *wsE, *wsD, *errv, *piv;
+    int64_t nwsE, nwsD;
+    int* info;
+};
+
+void fit_layout(Arena& a, FitBufs& b, int64_t m, int64_t n, int64_t c, bool need_gtmp) {
+    const int64_t np = round4(n), cp = round4(c);
+    b.H = a.take<float>(c * np);
+    b.E = a.take<float>(m * np);
+    b.F = a.take<float>(c * np);
+    b.Ginv32 = a.take<float>(c * cp);
+    const GemmPlan ph = plan_sgemm(c, n, m, true, true);
+    const GemmPlan pg = plan_sgemm(c, c, m, true, true);
+    size_t part = std::max(sgemm_partial_floats(ph, c, n), sgemm_partial_floats(pg, c, c));
+    b.part = a.take<float>(std::max<size_t>(part, 4));
+    b.Gtmp = need_gtmp ? a.take<float>(c * cp) : nullptr;
+    b.G = a.take<double>(c * c);
+    b.Ginv = a.take<double>(c * c);
+    b.spdws = a.take<double>(spd_inverse_ws_doubles(c));
+    b.nwsE = ((m + 127) / 128) * ((n + 127) / 128);
+    b.nwsD = ((c + 127) / 128) * ((n + 127) / 128);
+    b.wsE = a.take<double>(b.nwsE);
+    b.wsD = a.take<double>(b.nwsD);
+    b.errv = a.take<double>(4);
+    b.piv = a.take<double>(2 * ((c + 63) / 64));
+    b.info = a.take<int>(4);
+}
+
+// U = C^+ A through the normal equations with one optional refinement step.
+// When d_cols (device, c) gives C's columns within A (C = A[:, cols]), C^T C
+// is read off H = C^T A; otherwise (d_cols null, d_ident = 0..c-1) it is
+// formed by its own GEMM into Gtmp.  After the caller synchronizes,
+// b.errv[0] = err^2, b.info[0] bit 0 = pivot replaced, b.piv = pivot ranges.
+bcur_status fit_run(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t m, int64_t n, int64_t lda, const float* C,
+                    int64_t c, int64_t ldc, const int64_t* d_cols, const int64_t* d_ident, int refine, float* U,
+                    int64_t ldu) {
+    hipStream_t st = ctx->stream;
+    const int64_t np = round4(n), cp = round4(c);
+    HIPCHK(hipMemsetAsync(b.info, 0, 4 * sizeof(int), st));
+    const GemmPlan ph = plan_sgemm(c, n, m, true, true);
+    STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_H, BCUR_STAGE_FIT_REDUCE, ph, c, n, m, true, C, ldc, A, lda, b.H, np, b.part));
+    {
+        StageScope ts(ctx, BCUR_STAGE_FIT_INV);
+        if (d_cols) {
+            HIPCHK(launch_gram_from_cols(b.H, np, d_cols, c, b.G, st));
+        } else {
+            if (!b.Gtmp || !d_ident) return fail(ctx, BCUR_E_ARG, "internal: no Gram buffer");
+            const GemmPlan pg = plan_sgemm(c, c, m, true, true);
+            HIPCHK(launch_sgemm(pg, c, c, m, true, C, ldc, C, ldc, b.Gtmp, cp, b.part, EPI_STORE, nullptr, 0, nullptr,
+                                0, nullptr, st));
+            HIPCHK(launch_gram_from_cols(b.Gtmp, cp, d_ident, c, b.G, st));
+        }
+        HIPCHK(launch_spd_inverse(b.G, c, b.Ginv, b.spdws, b.info, b.piv, st));
+        HIPCHK(launch_f64_to_f32_2d(b.Ginv, c, c, c, b.Ginv32, cp, st));
+    }
+    const GemmPlan pu = plan_sgemm(c, n, c, false, false);
+    STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_U, BCUR_STAGE_FIT_REDUCE, pu, c, n, c, false, b.Ginv32, cp, b.H, np, U, ldu,
+                     nullptr));
+    const GemmPlan pe = plan_sgemm(m, n, c, false, false);
+    STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_E, BCUR_STAGE_FIT_REDUCE, pe, m, n, c, false, C, ldc, U, ldu, b.E, np, nullptr,
+                     EPI_RESID, A, lda, nullptr, 0, b.wsE));
+    if (refine) {
+        STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_F, BCUR_STAGE_FIT_REDUCE, ph, c, n, m, true, C, ldc, b.E, np, b.F, np,
+                         b.part));
+        STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_DU, BCUR_STAGE_FIT_REDUCE, pu, c, n, c, false, b.Ginv32, cp, b.F, np, U,
+                         ldu, nullptr, EPI_ADD_DOT, U, ldu, b.F, np, b.wsD));
+    }
+    // one partial per workgroup of the two fused-epilogue GEMMs (128 x 128 tiles)
+    const int64_t nwsE = ((m + 127) / 128) * ((n + 127) / 128);
+    const int64_t nwsD = ((c + 127) / 128) * ((n + 127) / 128);
+    HIPCHK(launch_fit_err(b.wsE, nwsE, b.wsD, refine ? nwsD : 0, b.errv, st));
+    return BCUR_OK;
+}
+
+// Reads the fit's scalars after the stream has been synchronized.
+struct FitOut {
+    double err2;
+    uint32_t flags;
+};
+
+bcur_status fit_collect(bcur_ctx* ctx, const FitBufs& b, int64_t c, FitOut* out) {
+    double hv[4];
+    int hinfo[4];
+    const int64_t nblk = (c + 63) / 64;
+    std::vector<double> piv(2 * nblk);
+    HIPCHK(hipMemcpyAsync(hv, b.errv, sizeof hv, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(hinfo, b.info, sizeof hinfo, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(piv.data(), b.piv, piv.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    uint32_t fl = 0;
+    if (hinfo[0] & 1) fl |= BCUR_FLAG_RANKDEF_C;
+    double pmin = INFINITY, pmax = 0.0;
+    for (int64_t i = 0; i < nblk; ++i) {
+        pmin = std::min(pmin, piv[2 * i]);
+        pmax = std::max(pmax, piv[2 * i + 1]);
+    }
+    // cond(C)^2 is at least the spread of the Cholesky pivots
+    if (pmin > 0.0 && pmax / pmin * ldexp(1.0, -24) > 0.1) fl |= BCUR_FLAG_ILLCOND_C;
+    out->err2 = std::max(hv[0], 0.0);
+    out->flags = fl;
+    return BCUR_OK;
+}
+
+}  // namespace
+
+// ---- C ABI ------------------------------------------------------------------
+
+extern "C" {
+
+const char* bcur_status_str(int status) {
+    switch (status) {
+        case BCUR_OK: return "ok";
+        case BCUR_E_ARG: return "invalid argument";
+        case BCUR_E_NONFINITE: return "matrix holds NaN or Inf";
+        case BCUR_E_NOMEM: return "out of memory";
+        case BCUR_E_HIP: return "HIP runtime error";
+        case BCUR_E_RANKDEF: return "numerically singular factorization";
+        case BCUR_E_ADMIT: return "request exceeds the memory budget";
+        case BCUR_PENDING: return "pending";
+        case BCUR_E_STATE: return "unknown ticket";
+        default: return "unknown status";
+    }
+}
+
+const char* bcur_last_error(const bcur_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+size_t bcur_workspace_bytes(const bcur_ctx* ctx) { return ctx ? ctx->ws_bytes : 0; }
+
+bcur_status bcur_create(bcur_ctx** out, int device, void* stream) {
+    if (!out) return BCUR_E_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return BCUR_E_ARG;
+    bcur_ctx* ctx = new (std::nothrow) bcur_ctx;
+    if (!ctx) return BCUR_E_NOMEM;
+    ctx->device = device;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete ctx;
+        return BCUR_E_HIP;
+    }
+    ctx->stream = (hipStream_t)stream;   // NULL: the device's null stream
+    *out = ctx;
+    return BCUR_OK;
+}
+
+bcur_status bcur_destroy(bcur_ctx* ctx) {
+    if (!ctx) return BCUR_E_ARG;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    timer_resolve(ctx);
+    for (hipEvent_t e : ctx->timer.pool) (void)hipEventDestroy(e);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return BCUR_OK;
+}
+
+bcur_status bcur_synchronize(bcur_ctx* ctx) {
+    if (!ctx) return BCUR_E_ARG;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return BCUR_OK;
+}
+
+bcur_status bcur_timing_enable(bcur_ctx* ctx, int32_t on) {
+    if (!ctx) return BCUR_E_ARG;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    timer_resolve(ctx);
+    ctx->timer.on = on != 0;
+    for (int i = 0; i < BCUR_NUM_STAGES; ++i) {
+        ctx->timer.ms[i] = 0.0;
+        ctx->timer.count[i] = 0;
+    }
+    return BCUR_OK;
+}
+
+bcur_status bcur_timing_read(bcur_ctx* ctx, double* ms, int64_t* count) {
+    if (!ctx || !ms || !count) return BCUR_E_ARG;
+    timer_resolve(ctx);
+    for (int i = 0; i < BCUR_NUM_STAGES; ++i) {
+        ms[i] = ctx->timer.ms[i];
+        count[i] = ctx->timer.count[i];
+    }
+    return BCUR_OK;
+}
+
+bcur_status bcur_frob2(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda, double* out_frob2,
+                       int32_t* out_finite) {
+    if (!ctx || !out_frob2) return fail(ctx, BCUR_E_ARG, "null argument");
+    STCHK(check_matrix(ctx, A, m, n, lda, "A"));
+    HIPCHK(hipSetDevice(ctx->device));
+    const int grid = frob2_grid(m, n);
+    Arena a;
+    a.take<double>(grid);
+    a.take<double>(1);
+    STCHK(reserve(ctx, a.off));
+    Arena b{ctx->ws, 0};
+    double* part = b.take<double>(grid);
+    double* out = b.take<double>(1);
+    HIPCHK(launch_frob2(A, m, n, lda, part, grid, out, ctx->stream));
+    STCHK(reserve_pinned(ctx, 64));
+    HIPCHK(hipMemcpyAsync(ctx->pinned, out, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    const double v = *reinterpret_cast<double*>(ctx->pinned);
+    *out_frob2 = v;
+    if (out_finite) *out_finite = isfinite(v) ? 1 : 0;
+    return BCUR_OK;
+}
+
+bcur_status bcur_range_finder(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda, const float* omega,
+                              int64_t l, int64_t k, int64_t q, int32_t precision, float* Vk, float* Uk, double* ritz) {
+    if (!ctx) return BCUR_E_ARG;
+    STCHK(check_matrix(ctx, A, m, n, lda, "A"));
+    if (!omega || !Vk) return fail(ctx, BCUR_E_ARG, "omega and Vk are required");
+    if (k < 1 || l < k || l > std::min(std::min(m, n), kMaxSketch))
+        return fail(ctx, BCUR_E_ARG, "need 1 <= k <= l <= min(m, n, %lld)", (long long)kMaxSketch);
+    if (q < 0 || q > 64) return fail(ctx, BCUR_E_ARG, "q out of range");
+    if (precision != BCUR_PREC_FP32) return fail(ctx, BCUR_E_ARG, "precision %d not available", precision);
+    HIPCHK(hipSetDevice(ctx->device));
+    Arena a;
+    RFBufs b;
+    rf_layout(a, b, m, n, l, k);
+    STCHK(reserve(ctx, a.off));
+    Arena r{ctx->ws, 0};
+    rf_layout(r, b, m, n, l, k);
+    STCHK(range_finder_run(ctx, b, A, m, n, lda, omega, l, k, q, Vk, Uk));
+    if (ritz) {
+        STCHK(reserve_pinned(ctx, l * sizeof(double)));
+        HIPCHK(hipMemcpyAsync(ctx->pinned, b.lam, l * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        const double* lam = reinterpret_cast<const double*>(ctx->pinned);
+        for (int64_t i = 0; i < l; ++i) ritz[i] = lam[i] > 0.0 ? sqrt(lam[i]) : 0.0;
+    }
+    return BCUR_OK;
+}
+
+bcur_status bcur_block_scores(bcur_ctx* ctx, const float* V, int64_t n, int64_t k, int64_t ldv, const int64_t* offsets,
+                              int64_t G, double* scores) {
+    if (!ctx || !V || !scores) return fail(ctx, BCUR_E_ARG, "null argument");
+    if (n < 1 || k < 1 || ldv < k) return fail(ctx, BCUR_E_ARG, "bad V shape");
+    STCHK(check_offsets(ctx, offsets, G, n, "offsets"));
+    HIPCHK(hipSetDevice(ctx->device));
+    Arena a;
+    a.take<int64_t>(G + 1);
+    a.take<double>(G);
+    STCHK(reserve(ctx, a.off));
+    Arena b{ctx->ws, 0};
+    int64_t* d_off = b.take<int64_t>(G + 1);
+    double* d_sc = b.take<double>(G);
+    HIPCHK(hipMemcpyAsync(d_off, offsets, (G + 1) * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(launch_block_scores(V, k, ldv, d_off, G, d_sc, ctx->stream));
+    HIPCHK(hipMemcpyAsync(scores, d_sc, G * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return BCUR_OK;
+}
+
+bcur_status bcur_sample_blocks(bcur_ctx* ctx, const double* scores, int64_t G, const uint64_t* draws, int64_t s,
+                               int32_t replace, int64_t* idx, double* weights, double* margins) {
+    if (!ctx || !scores || !draws || !idx) return fail(ctx, BCUR_E_ARG, "null argument");
+    if (G < 1 || s < 1 || (!replace && s > G)) return fail(ctx, BCUR_E_ARG, "need 1 <= s <= G (without replacement)");
+    HIPCHK(hipSetDevice(ctx->device));
+    Arena a;
+    a.take<double>(G);
+    a.take<uint64_t>(s);
+    a.take<uint64_t>(G);
+    a.take<uint64_t>(G);
+    a.take<int64_t>(s);
+    a.take<double>(s);
+    a.take<double>(s);
+    a.take<int>(4);
+    STCHK(reserve(ctx, a.off));
+    Arena b{ctx->ws, 0};
+    double* d_sc = b.take<double>(G);
+    uint64_t* d_dr = b.take<uint64_t>(s);
+    uint64_t* qb = b.take<uint64_t>(G);
+    uint64_t* pr = b.take<uint64_t>(G);
+    int64_t* d_idx = b.take<int64_t>(s);
+    double* d_w = b.take<double>(s);
+    double* d_mg = b.take<double>(s);
+    int* d_st = b.take<int>(4);
+    hipStream_t st = ctx->stream;
+    HIPCHK(hipMemcpyAsync(d_sc, scores, G * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_dr, draws, s * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(d_st, 0, 4 * sizeof(int), st));
+    HIPCHK(launch_sample(d_sc, G, d_dr, s, replace, qb, pr, d_idx, d_w, d_mg, d_st, st));
+    int hst[4];
+    std::vector<int64_t> hidx(s);
+    std::vector<double> hw(s), hm(s);
+    HIPCHK(hipMemcpyAsync(hst, d_st, sizeof hst, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hidx.data(), d_idx, s * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hw.data(), d_w, s * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hm.data(), d_mg, s * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hst[0] != 0) return fail(ctx, BCUR_E_ARG, "scores must be finite and non-negative");
+    memcpy(idx, hidx.data(), s * sizeof(int64_t));
+    if (weights) memcpy(weights, hw.data(), s * sizeof(double));
+    if (margins) memcpy(margins, hm.data(), s * sizeof(double));
+    return BCUR_OK;
+}
+
+bcur_status bcur_gather_columns(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda, const int64_t* offsets,
+                                int64_t G, const int64_t* idx, int64_t s, float* C, int64_t ldc, int64_t* c_out) {
+    if (!ctx || !idx || !C || !c_out) return fail(ctx, BCUR_E_ARG, "null argument");
+    STCHK(check_matrix(ctx, A, m, n, lda, "A"));
+    STCHK(check_offsets(ctx, offsets, G, n, "offsets"));
+    if (s < 1) return fail(ctx, BCUR_E_ARG, "s < 1");
+    for (int64_t t = 0; t < s; ++t)
+        if (idx[t] < 0 || idx[t] >= G) return fail(ctx, BCUR_E_ARG, "idx[%lld] out of range", (long long)t);
+    const std::vector<int64_t> cols = expand_blocks(offsets, idx, s);
+    const int64_t c = (int64_t)cols.size();
+    if (ldc < c) return fail(ctx, BCUR_E_ARG, "ldc %lld < c = %lld", (long long)ldc, (long long)c);
+    HIPCHK(hipSetDevice(ctx->device));
+    STCHK(reserve(ctx, c * sizeof(int64_t) + 256));
+    int64_t* d_cols = reinterpret_cast<int64_t*>(ctx->ws);
+    STCHK(reserve_pinned(ctx, c * sizeof(int64_t)));
+    HIPCHK(hipStreamSynchronize(ctx->stream));   // the pinned staging buffer may still be read by a copy
+    memcpy(ctx->pinned, cols.data(), c * sizeof(int64_t));
+    HIPCHK(hipMemcpyAsync(d_cols, ctx->pinned, c * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(launch_gather_cols(A, lda, m, d_cols, c, C, ldc, ctx->stream));
+    *c_out = c;
+    return BCUR_OK;
+}
+
+bcur_status bcur_fit_columns(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda, const float* C, int64_t c,
+                             int64_t ldc, int32_t refine, float* U, int64_t ldu, double* err, uint32_t* flags) {
+    if (!ctx || !U || !err) return fail(ctx, BCUR_E_ARG, "null argument");
+    STCHK(check_matrix(ctx, A, m, n, lda, "A"));
+    STCHK(check_matrix(ctx, C, m, c, ldc, "C"));
+    if (ldu < n || (ldu & 3) || !aligned16(U)) return fail(ctx, BCUR_E_ARG, "U: bad leading dimension or alignment");
+    if (refine < 0 || refine > 1) return fail(ctx, BCUR_E_ARG, "refine must be 0 or 1");
+    HIPCHK(hipSetDevice(ctx->device));
+    FitBufs b;
+    int64_t* d_id = nullptr;
+    {
+        Arena a;
+        fit_layout(a, b, m, n, c, true);
+        a.take<int64_t>(c);
+        STCHK(reserve(ctx, a.off));
+        Arena r{ctx->ws, 0};
+        fit_layout(r, b, m, n, c, true);
+        d_id = r.take<int64_t>(c);
+    }
+    STCHK(reserve_pinned(ctx, c * sizeof(int64_t)));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    int64_t* h_id = reinterpret_cast<int64_t*>(ctx->pinned);
+    for (int64_t i = 0; i < c; ++i) h_id[i] = i;
+    HIPCHK(hipMemcpyAsync(d_id, h_id, c * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+    STCHK(fit_run(ctx, b, A, m, n, lda, C, c, ldc, nullptr, d_id, refine, U, ldu));
+    FitOut fo;
+    STCHK(fit_collect(ctx, b, c, &fo));
+    *err = sqrt(fo.err2);
+    if (flags) *flags = fo.flags;
+    return BCUR_OK;
+}
+
+bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda, const int64_t* col_off,
+                           int64_t G, const int64_t* row_off, int64_t Gr, const bcur_params* p, const float* omega,
+                           const uint64_t* draws, bcur_result* res) {
+    if (!ctx) return BCUR_E_ARG;
+    if (!p || !res || !omega || !draws || !res->idx) return fail(ctx, BCUR_E_ARG, "null argument");
+    STCHK(check_matrix(ctx, A, m, n, lda, "A"));
+    STCHK(check_offsets(ctx, col_off, G, n, "col_off"));
+    const int64_t k = p->k, l = p->l, s = p->s, q = p->q;
+    if (k < 1 || l < k || l > std::min(std::min(m, n), kMaxSketch))
+        return fail(ctx, BCUR_E_ARG, "need 1 <= k <= l <= min(m, n, %lld)", (long long)kMaxSketch);
+    if (q < 0 || q > 64) return fail(ctx, BCUR_E_ARG, "q out of range");
+    if (s < 1 || (!p->replace && s > G)) return fail(ctx, BCUR_E_ARG, "need 1 <= s <= G without replacement");
+    if (p->precision != BCUR_PREC_FP32) return fail(ctx, BCUR_E_ARG, "precision %d not available", p->precision);
+    if (p->refine < 0 || p->refine > 1) return fail(ctx, BCUR_E_ARG, "refine must be 0 or 1");
+    const bool rowv = row_off != nullptr && p->s_r > 0;
+    if (rowv) {
+        STCHK(check_offsets(ctx, row_off, Gr, m, "row_off"));
+        if (!p->replace && p->s_r > Gr) return fail(ctx, BCUR_E_ARG, "s_r > Gr without replacement");
+        return fail(ctx, BCUR_E_ARG, "row-block variant not available");
+    }
+    int64_t maxw = 0;
+    for (int64_t g = 0; g < G; ++g) maxw = std::max(maxw, col_off[g + 1] - col_off[g]);
+    const int64_t cmax = std::min(s * maxw, n);
+    if (res->U && (res->ldu < n || (res->ldu & 3) || !aligned16(res->U) || res->u_rows_cap < cmax))
+        return fail(ctx, BCUR_E_ARG, "U needs ldu >= n (multiple of 4, 16-byte aligned) and %lld rows", (long long)cmax);
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+
+    // workspace: range finder | scores and sampling | fit (sized for cmax)
+    auto layout = [&](Arena& a, RFBufs& rb, FitBufs& fb, int64_t*& d_off, double*& d_sc, uint64_t*& d_dr, uint64_t*& qb,
+                      uint64_t*& pr, int64_t*& d_idx, double*& d_w, double*& d_mg, int*& d_st, double*& d_frob,
+                      double*& d_fpart, float*& Vk, float*& Cbuf, int64_t*& d_cols, float*& Ubuf) {
+        rf_layout(a, rb, m, n, l, k);
+        d_off = a.take<int64_t>(G + 1);
+        d_sc = a.take<double>(G);
+        d_dr = a.take<uint64_t>(s);
+        qb = a.take<uint64_t>(G);
+        pr = a.take<uint64_t>(G);
+        d_idx = a.take<int64_t>(s);
+        d_w = a.take<double>(s);
+        d_mg = a.take<double>(s);
+        d_st = a.take<int>(4);
+        d_frob = a.take<double>(2);
+        d_fpart = a.take<double>(frob2_grid(m, n));
+        Vk = a.take<float>(n * k);
+        Cbuf = a.take<float>(m * round4(cmax));
+        d_cols = a.take<int64_t>(cmax);
+        Ubuf = a.take<float>(cmax * round4(n));
+        fit_layout(a, fb, m, n, cmax, false);
+    };
+    RFBufs rb;
+    FitBufs fb;
+    int64_t *d_off, *d_idx, *d_cols;
+    double *d_sc, *d_w, *d_mg, *d_frob, *d_fpart;
+    uint64_t *d_dr, *qb, *pr;
+    int* d_st;
+    float *Vk, *Cbuf, *Ubuf;
+    {
+        Arena a;
+        layout(a, rb, fb, d_off, d_sc, d_dr, qb, pr, d_idx, d_w, d_mg, d_st, d_frob, d_fpart, Vk, Cbuf, d_cols, Ubuf);
+        STCHK(reserve(ctx, a.off));
+        Arena b{ctx->ws, 0};
+        layout(b, rb, fb, d_off, d_sc, d_dr, qb, pr, d_idx, d_w, d_mg, d_st, d_frob, d_fpart, Vk, Cbuf, d_cols, Ubuf);
+    }
+    // staging layout: offsets | draws | frob2 (2) | status (4 ints) | idx | weights | margins | scores | lam | cols
+    const size_t pin_need = 8 * (G + 1) + 8 * s + 16 + 16 + 24 * s + 8 * G + 8 * l + 8 * cmax + 64;
+    STCHK(reserve_pinned(ctx, pin_need));
+    HIPCHK(hipStreamSynchronize(st));
+    char* pin = ctx->pinned;
+    int64_t* h_off = reinterpret_cast<int64_t*>(pin);
+    uint64_t* h_dr = reinterpret_cast<uint64_t*>(h_off + G + 1);
+    memcpy(h_off, col_off, (G + 1) * sizeof(int64_t));
+    memcpy(h_dr, draws, s * sizeof(uint64_t));
+    HIPCHK(hipMemcpyAsync(d_off, h_off, (G + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_dr, h_dr, s * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(d_st, 0, 4 * sizeof(int), st));
+
+    // 1. ||A||_F^2
+    {
+        StageScope ts(ctx, BCUR_STAGE_FROB);
+        HIPCHK(launch_frob2(A, m, n, lda, d_fpart, frob2_grid(m, n), d_frob, st));
+    }
+    // 2. sketched top-k right subspace
+    STCHK(range_finder_run(ctx, rb, A, m, n, lda, omega, l, k, q, Vk, nullptr));
+    // 3. block scores, 4. sampling
+    {
+        StageScope ts(ctx, BCUR_STAGE_SCORES);
+        HIPCHK(launch_block_scores(Vk, k, k, d_off, G, d_sc, st));
+    }
+    {
+        StageScope ts(ctx, BCUR_STAGE_SAMPLE);
+        HIPCHK(launch_sample(d_sc, G, d_dr, s, p->replace, qb, pr, d_idx, d_w, d_mg, d_st, st));
+    }
+    // results needed on the host to lay out C
+    double* h_frob = reinterpret_cast<double*>(h_dr + s);
+    int* h_st = reinterpret_cast<int*>(h_frob + 2);
+    int64_t* h_idx = reinterpret_cast<int64_t*>(h_st + 4);
+    double* h_w = reinterpret_cast<double*>(h_idx + s);
+    double* h_mg = h_w + s;
+    double* h_sc = h_mg + s;
+    double* h_lam = h_sc + G;
+    int64_t* h_cols = reinterpret_cast<int64_t*>(h_lam + l);
+    HIPCHK(hipMemcpyAsync(h_frob, d_frob, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_st, d_st, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_idx, d_idx, s * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_w, d_w, s * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_mg, d_mg, s * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_sc, d_sc, G * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_lam, rb.lam, l * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (!isfinite(h_frob[0])) return fail(ctx, BCUR_E_NONFINITE, "A holds NaN or Inf");
+    if (h_st[0] != 0) return fail(ctx, BCUR_E_HIP, "block scores are not finite");
+    for (int64_t t = 0; t < s; ++t)
+        if (h_idx[t] < 0 || h_idx[t] >= G) return fail(ctx, BCUR_E_HIP, "sampler returned an invalid block");
+    const std::vector<int64_t> cols = expand_blocks(col_off, h_idx, s);
+    const int64_t c = (int64_t)cols.size();
+    memcpy(h_cols, cols.data(), c * sizeof(int64_t));
+    HIPCHK(hipMemcpyAsync(d_cols, h_cols, c * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    // 5. C = A S (unscaled)
+    const int64_t ldc = round4(c);
+    {
+        StageScope ts(ctx, BCUR_STAGE_GATHER);
+        HIPCHK(launch_gather_cols(A, lda, m, d_cols, c, Cbuf, ldc, st));
+    }
+    // 6. U = C^+ A and the residual
+    float* U = res->U ? res->U : Ubuf;
+    const int64_t ldu = res->U ? res->ldu : round4(n);
+    STCHK(fit_run(ctx, fb, A, m, n, lda, Cbuf, c, ldc, d_cols, nullptr, p->refine, U, ldu));
+    FitOut fo;
+    STCHK(fit_collect(ctx, fb, c, &fo));
+    int rinfo[4];
+    HIPCHK(hipMemcpy(rinfo, rb.info, sizeof rinfo, hipMemcpyDeviceToHost));
+    uint32_t fl = fo.flags;
+    if (rinfo[0] & 1) fl |= BCUR_FLAG_RANKDEF_Y;
+    if (h_st[1]) fl |= BCUR_FLAG_ZERO_SCORE;
+    memcpy(res->idx, h_idx, s * sizeof(int64_t));
+    if (res->weights) memcpy(res->weights, h_w, s * sizeof(double));
+    if (res->scores) memcpy(res->scores, h_sc, G * sizeof(double));
+    if (res->ritz)
+        for (int64_t i = 0; i < l; ++i) res->ritz[i] = h_lam[i] > 0.0 ? sqrt(h_lam[i]) : 0.0;
+    double mm = INFINITY;
+    for (int64_t t = 0; t < s; ++t) mm = std::min(mm, h_mg[t]);
+    res->c = c;
+    res->r = 0;
+    res->frob2 = h_frob[0];
+    res->err = sqrt(fo.err2);
+    res->rel_err = h_frob[0] > 0.0 ? res->err / sqrt(h_frob[0]) : 0.0;
+    res->min_margin = mm;
+    res->flags = fl;
+    return BCUR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Internal declarations shared by the Block CUR HIP sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace bcur {
+
+// Launch helpers return hipSuccess or the launch error.
+
+// ---- reductions, scores, sampling, gather (k_basic.hip) -------------------
+int frob2_grid(int64_t m, int64_t n);
+hipError_t launch_frob2(const float* A, int64_t m, int64_t n, int64_t lda, double* partial, int grid,
+                        double* out, hipStream_t st);
+hipError_t launch_block_scores(const float* V, int64_t k, int64_t ldv, const int64_t* d_off, int64_t G,
+                               double* scores, hipStream_t st);
+// status[0] = 0 ok, 1 invalid scores; status[1] = 1 when a zero-weight block was drawn
+hipError_t launch_sample(const double* scores, int64_t G, const uint64_t* draws, int64_t s, int replace,
+                         uint64_t* qbuf, uint64_t* pref, int64_t* idx, double* weights, double* margins,
+                         int* status, hipStream_t st);
+hipError_t launch_gather_cols(const float* A, int64_t lda, int64_t m, const int64_t* d_cols, int64_t c,
+                              float* C, int64_t ldc, hipStream_t st);
+hipError_t launch_gather_rows(const float* A, int64_t lda, int64_t n, const int64_t* d_rows, int64_t r,
+                              float* R, int64_t ldr, hipStream_t st);
+hipError_t launch_sum_f64(const double* x, int64_t count, double* out, hipStream_t st);
+hipError_t launch_gram_from_cols(const float* H, int64_t ldh, const int64_t* d_cols, int64_t c, double* G,
+                                 hipStream_t st);
+hipError_t launch_f64_to_f32(const double* x, int64_t count, float* y, hipStream_t st);
+// y (rows x ldy) = x (rows x cols, ldx) rounded to FP32, zero in columns cols..ldy-1
+hipError_t launch_f64_to_f32_2d(const double* x, int64_t rows, int64_t cols, int64_t ldx, float* y, int64_t ldy,
+                                hipStream_t st);
+hipError_t launch_cast_bf16(const float* A, int64_t m, int64_t n, int64_t lda, uint16_t* out, int64_t ldo,
+                            hipStream_t st);
+hipError_t launch_zero_f32(float* x, int64_t rows, int64_t cols, int64_t ld, hipStream_t st);
+hipError_t launch_fit_err(const double* parts, int64_t nparts_e, const double* dot_parts, int64_t nparts_d,
+                          double* out, hipStream_t st);
+
+// ---- FP32 MFMA GEMM (k_sgemm.hip) ------------------------------------------
+enum GemmEpi { EPI_STORE = 0, EPI_RESID = 1, EPI_ADD_DOT = 2 };
+struct GemmPlan {
+    int splits = 1;
+    int64_t kchunk = 0;
+    int64_t wgs = 0;     // workgroups of the main kernel
+    int cfg = 0;         // tile configuration index
+};
+// D = op(A) B, op(A) = A (M x K, lda) or A^T (A stored K x M, lda); B is K x N (ldb).
+GemmPlan plan_sgemm(int64_t M, int64_t N, int64_t K, bool transA, bool allow_split);
+size_t sgemm_partial_floats(const GemmPlan& p, int64_t M, int64_t N);
+// EPI_STORE: D = acc.  EPI_RESID: D = X - acc, wsum[wg] = sum (X - acc)^2.
+// EPI_ADD_DOT: D = X + acc, wsum[wg] = sum acc * Y.   Epilogues need splits == 1.
+// main kernel only (partial tiles when split) and the split-K sum
+hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K, bool transA, const float* A,
+                             int64_t lda, const float* B, int64_t ldb, float* D, int64_t ldd, float* partial,
+                             int epi, const float* X, int64_t ldx, const float* Y, int64_t ldy, double* wsum,
+                             hipStream_t st);
+hipError_t launch_splitk_reduce(const GemmPlan& p, int64_t M, int64_t N, const float* partial, float* D,
+                                int64_t ldd, hipStream_t st);
+hipError_t launch_sgemm(const GemmPlan& p, int64_t M, int64_t N, int64_t K, bool transA, const float* A,
+                        int64_t lda, const float* B, int64_t ldb, float* D, int64_t ldd, float* partial,
+                        int epi, const float* X, int64_t ldx, const float* Y, int64_t ldy, double* wsum,
+                        hipStream_t st);
+
+// ---- small dense FP64 kernels (k_small.hip) --------------------------------
+int gram_wgs(int64_t rows);
+// partial[w] (l x l) = sum over the w-th row range of X^T X, FP64 accumulation.
+hipError_t launch_gram64(const float* X, int64_t rows, int64_t l, int64_t ldx, double* partial, int wgs,
+                         double* T, hipStream_t st);
+// T (l x l, FP64) -> Rinv (l x l upper, R^T R = T + shift I), shift = l 2^-52 trace(T).
+// info[0] |= 1 when a pivot needed the shift (min pivot < 1e3 * shift).
+hipError_t launch_chol_rinv_small(const double* T, int64_t l, double* Rinv, int* info, hipStream_t st);
+// out (rows x lo, FP32, ldo) = X (rows x li, FP32, ldx) * M (li x lo, FP64, ldm)
+hipError_t launch_apply_small(const float* X, int64_t rows, int64_t li, int64_t ldx, const double* M,
+                              int64_t lo, int64_t ldm, float* out, int64_t ldo, hipStream_t st);
+// Symmetric eigensolver (one workgroup, cyclic Jacobi): lam (l, descending),
+// Wk (l x k, FP64), Wks = Wk diag(1/sqrt(lam)) (l x k) or null.
+hipError_t launch_jacobi_eigh(const double* T, int64_t l, int64_t k, double* lam, double* Wk, double* Wks,
+                              int* info, hipStream_t st);
+
+// ---- blocked FP64 Cholesky inverse (k_dense64.hip) -------------------------
+size_t spd_inverse_ws_doubles(int64_t c);
+// Ginv = G^-1 for SPD G (c x c, FP64, overwritten by its Cholesky factor).
+// info[0] |= 1 when a pivot fell below tau = c 2^-24 max diag: that column is dropped and its
+// rows and columns of Ginv are zero (the inverse of the kept columns' Gram matrix);
+// piv[0] = min pivot, piv[1] = max pivot (of the Schur complements).
+hipError_t launch_spd_inverse(double* G, int64_t c, double* Ginv, double* ws, int* info, double* piv,
+                              hipStream_t st);
+hipError_t launch_dgemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda, bool tA,
+                        const double* B, int64_t ldb, bool tB, double beta, double* D, int64_t ldd,
+                        hipStream_t st);
+
+}  // namespace bcur

@@ -1,0 +1,441 @@
+// Bandwidth-bound kernels of the Block CUR path: the Frobenius norm, block
+// leverage scores, block sampling, gathers and small utilities.
+#include <math.h>
+
+#include "bcur_internal.h"
+
+namespace bcur {
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum over the workgroup in a fixed tree order; the result is valid in thread 0.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NT / 64; ++i) r += sh[i];
+    }
+    return r;
+}
+
+__device__ __forceinline__ double sq4(float4 v) {
+    const double x = v.x, y = v.y, z = v.z, w = v.w;
+    return (x * x + y * y) + (z * z + w * w);
+}
+
+// ||A||_F^2 partial sums: one double per workgroup, fixed order per thread.
+__global__ __launch_bounds__(256) void k_frob2_partial(const float* __restrict__ A, int64_t m, int64_t n,
+                                                       int64_t lda, double* __restrict__ partial) {
+    __shared__ double sh[4];
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    const int tid = threadIdx.x;
+    if (lda == n && (n & 3) == 0) {
+        // dense rows: the matrix is one contiguous run of m*n floats
+        const float4* A4 = reinterpret_cast<const float4*>(A);
+        const int64_t total4 = m * n / 4;
+        const int64_t stride = (int64_t)gridDim.x * 256;
+        int64_t i = (int64_t)blockIdx.x * 256 + tid;
+        for (; i + 3 * stride < total4; i += 4 * stride) {
+            const float4 v0 = A4[i], v1 = A4[i + stride], v2 = A4[i + 2 * stride], v3 = A4[i + 3 * stride];
+            acc0 += sq4(v0);
+            acc1 += sq4(v1);
+            acc2 += sq4(v2);
+            acc3 += sq4(v3);
+        }
+        for (; i < total4; i += stride) acc0 += sq4(A4[i]);
+    } else {
+        for (int64_t row = blockIdx.x; row < m; row += gridDim.x) {
+            const float* a = A + row * lda;
+            if ((lda & 3) == 0) {
+                const int64_t n4 = n >> 2;
+                const float4* a4 = reinterpret_cast<const float4*>(a);
+                for (int64_t j = tid; j < n4; j += 256) acc0 += sq4(a4[j]);
+                for (int64_t j = n4 * 4 + tid; j < n; j += 256) {
+                    const double x = a[j];
+                    acc1 += x * x;
+                }
+            } else {
+                for (int64_t j = tid; j < n; j += 256) {
+                    const double x = a[j];
+                    acc1 += x * x;
+                }
+            }
+        }
+    }
+    const double r = block_sum<256>((acc0 + acc1) + (acc2 + acc3), sh);
+    if (tid == 0) partial[blockIdx.x] = r;
+}
+
+// out[0] = sum of x[0..count) in a fixed order (one workgroup).
+__global__ __launch_bounds__(256) void k_sum_f64(const double* __restrict__ x, int64_t count,
+                                                 double* __restrict__ out) {
+    __shared__ double sh[4];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < count; i += 256) acc += x[i];
+    const double r = block_sum<256>(acc, sh);
+    if (threadIdx.x == 0) out[0] = r;
+}
+
+// Def. 2: scores[g] = sum of squares of rows off[g]..off[g+1]-1 of V (n x k, ldv).
+__global__ __launch_bounds__(256) void k_block_scores(const float* __restrict__ V, int64_t k, int64_t ldv,
+                                                      const int64_t* __restrict__ off,
+                                                      double* __restrict__ scores) {
+    __shared__ double sh[4];
+    const int64_t g = blockIdx.x;
+    const int64_t r0 = off[g], r1 = off[g + 1];
+    double acc = 0.0;
+    if (ldv == k) {
+        const float* base = V + r0 * k;
+        const int64_t cnt = (r1 - r0) * k;
+        for (int64_t e = threadIdx.x; e < cnt; e += 256) {
+            const double x = base[e];
+            acc += x * x;
+        }
+    } else {
+        const int64_t cnt = (r1 - r0) * k;
+        for (int64_t e = threadIdx.x; e < cnt; e += 256) {
+            const int64_t r = e / k, c = e - r * k;
+            const double x = V[(r0 + r) * ldv + c];
+            acc += x * x;
+        }
+    }
+    const double r = block_sum<256>(acc, sh);
+    if (threadIdx.x == 0) scores[g] = r;
+}
+
+__device__ __forceinline__ int ceil_log2_i64(int64_t x) {
+    int r = 0;
+    while (((int64_t)1 << r) < x) ++r;
+    return r;
+}
+
+// Alg. 1 step 2 with exact integer weights (one workgroup of 1024 threads).
+__global__ __launch_bounds__(1024) void k_sample(const double* __restrict__ scores, int64_t G,
+                                                 const uint64_t* __restrict__ draws, int64_t s, int replace,
+                                                 uint64_t* __restrict__ qbuf, uint64_t* __restrict__ pref,
+                                                 int64_t* __restrict__ idx, double* __restrict__ weights,
+                                                 double* __restrict__ margins, int* __restrict__ status) {
+    __shared__ uint64_t scan[1024];
+    __shared__ double smax[16];
+    __shared__ int sbad[16];
+    const int tid = threadIdx.x;
+
+    // 1. largest score and validity
+    double mx = 0.0;
+    int bad = 0;
+    for (int64_t g = tid; g < G; g += 1024) {
+        const double x = scores[g];
+        if (!(x >= 0.0) || !isfinite(x)) bad = 1;
+        else mx = fmax(mx, x);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        mx = fmax(mx, __shfl_xor(mx, o, 64));
+        bad |= __shfl_xor(bad, o, 64);
+    }
+    if ((tid & 63) == 0) {
+        smax[tid >> 6] = mx;
+        sbad[tid >> 6] = bad;
+    }
+    __syncthreads();
+    mx = 0.0;
+    bad = 0;
+    for (int i = 0; i < 16; ++i) {
+        mx = fmax(mx, smax[i]);
+        bad |= sbad[i];
+    }
+    if (bad) {
+        if (tid == 0) status[0] = 1;
+        return;
+    }
+    int sh = 0;
+    if (mx > 0.0) {
+        int E;
+        frexp(mx, &E);
+        sh = 62 - ceil_log2_i64(G) - E;
+    }
+
+    // 2. q_g = floor(l_g 2^sh) and their inclusive prefix sums
+    uint64_t carry = 0;
+    for (int64_t base = 0; base < G; base += 1024) {
+        const int64_t g = base + tid;
+        uint64_t v = 0;
+        if (g < G && mx > 0.0) v = (uint64_t)floor(ldexp(scores[g], sh));
+        if (g < G) qbuf[g] = v;
+        scan[tid] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const uint64_t add = tid >= off ? scan[tid - off] : 0;
+            __syncthreads();
+            scan[tid] += add;
+            __syncthreads();
+        }
+        if (g < G) pref[g] = carry + scan[tid];
+        const uint64_t tot = scan[1023];
+        __syncthreads();
+        carry += tot;
+    }
+    __syncthreads();
+
+    // 3. the draws, one after the other
+    if (tid == 0) {
+        const uint64_t total = pref[G - 1];
+        int zero_drawn = 0;
+        for (int64_t t = 0; t < s; ++t) {
+            uint64_t removed = 0;
+            if (!replace)
+                for (int64_t u = 0; u < t; ++u) removed += qbuf[idx[u]];
+            const uint64_t W = total - removed;
+            int64_t j;
+            double margin = 0.0;
+            if (W == 0) {
+                // every remaining weight is zero: the smallest remaining index
+                j = 0;
+                for (;;) {
+                    bool taken = false;
+                    if (!replace)
+                        for (int64_t u = 0; u < t; ++u) taken |= (idx[u] == j);
+                    if (!taken) break;
+                    ++j;
+                }
+                zero_drawn = 1;
+            } else {
+                const uint64_t x = __umul64hi(draws[t], W);
+                // smallest j with f(j) = pref[j] - (chosen weight at indices <= j) > x
+                int64_t lo = 0, hi = G - 1;
+                while (lo < hi) {
+                    const int64_t mid = lo + ((hi - lo) >> 1);
+                    uint64_t f = pref[mid];
+                    if (!replace)
+                        for (int64_t u = 0; u < t; ++u)
+                            if (idx[u] <= mid) f -= qbuf[idx[u]];
+                    if (f > x) hi = mid;
+                    else lo = mid + 1;
+                }
+                j = lo;
+                uint64_t fj = pref[j];
+                if (!replace)
+                    for (int64_t u = 0; u < t; ++u)
+                        if (idx[u] <= j) fj -= qbuf[idx[u]];
+                const uint64_t lo_edge = fj - qbuf[j];
+                const uint64_t a = x - lo_edge, b = fj - 1 - x;
+                margin = ldexp((double)(a < b ? a : b), -sh);
+            }
+            idx[t] = j;
+            if (margins) margins[t] = margin;
+            if (weights) {
+                const uint64_t qj = qbuf[j];
+                weights[t] = qj == 0 ? INFINITY : sqrt((double)total / ((double)s * (double)qj));
+            }
+        }
+        status[0] = 0;
+        status[1] = zero_drawn;
+    }
+}
+
+// C[i][t] = A[i][cols[t]]
+__global__ __launch_bounds__(256) void k_gather_cols(const float* __restrict__ A, int64_t lda, int64_t m,
+                                                     const int64_t* __restrict__ cols, int64_t c,
+                                                     float* __restrict__ C, int64_t ldc) {
+    for (int64_t i = blockIdx.y; i < m; i += gridDim.y) {
+        const float* a = A + i * lda;
+        float* o = C + i * ldc;
+        for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < c; t += (int64_t)gridDim.x * 256)
+            o[t] = a[cols[t]];
+    }
+}
+
+// R[t][j] = A[rows[t]][j]
+__global__ __launch_bounds__(256) void k_gather_rows(const float* __restrict__ A, int64_t lda, int64_t n,
+                                                     const int64_t* __restrict__ rows, int64_t r,
+                                                     float* __restrict__ R, int64_t ldr) {
+    for (int64_t t = blockIdx.y; t < r; t += gridDim.y) {
+        const float* a = A + rows[t] * lda;
+        float* o = R + t * ldr;
+        for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256)
+            o[j] = a[j];
+    }
+}
+
+// G = C^T C read from H = C^T A at the chosen columns, symmetrized, FP64.
+__global__ __launch_bounds__(256) void k_gram_from_cols(const float* __restrict__ H, int64_t ldh,
+                                                        const int64_t* __restrict__ cols, int64_t c,
+                                                        double* __restrict__ G) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= c * c) return;
+    const int64_t i = e / c, j = e - i * c;
+    const double a = H[i * ldh + cols[j]], b = H[j * ldh + cols[i]];
+    G[e] = 0.5 * (a + b);
+}
+
+__global__ __launch_bounds__(256) void k_f64_to_f32(const double* __restrict__ x, int64_t count,
+                                                    float* __restrict__ y) {
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256)
+        y[e] = (float)x[e];
+}
+
+__global__ __launch_bounds__(256) void k_f64_to_f32_2d(const double* __restrict__ x, int64_t rows, int64_t cols,
+                                                       int64_t ldx, float* __restrict__ y, int64_t ldy) {
+    for (int64_t i = blockIdx.y; i < rows; i += gridDim.y)
+        for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < ldy; j += (int64_t)gridDim.x * 256)
+            y[i * ldy + j] = j < cols ? (float)x[i * ldx + j] : 0.0f;
+}
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__global__ __launch_bounds__(256) void k_cast_bf16(const float* __restrict__ A, int64_t m, int64_t n,
+                                                   int64_t lda, uint16_t* __restrict__ out, int64_t ldo) {
+    const int64_t n4 = n >> 2;
+    for (int64_t i = blockIdx.y; i < m; i += gridDim.y) {
+        const float* a = A + i * lda;
+        uint16_t* o = out + i * ldo;
+        for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n4; j += (int64_t)gridDim.x * 256) {
+            const float4 v = reinterpret_cast<const float4*>(a)[j];
+            ushort4 w;
+            w.x = f32_to_bf16_rne(v.x);
+            w.y = f32_to_bf16_rne(v.y);
+            w.z = f32_to_bf16_rne(v.z);
+            w.w = f32_to_bf16_rne(v.w);
+            reinterpret_cast<ushort4*>(o)[j] = w;
+        }
+        for (int64_t j = n4 * 4 + (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256)
+            o[j] = f32_to_bf16_rne(a[j]);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_zero_f32(float* __restrict__ x, int64_t rows, int64_t cols,
+                                                  int64_t ld) {
+    for (int64_t i = blockIdx.y; i < rows; i += gridDim.y)
+        for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < cols; j += (int64_t)gridDim.x * 256)
+            x[i * ld + j] = 0.0f;
+}
+
+// out[0] = sum(a) - sum(b), out[1] = sum(a), out[2] = sum(b), fixed order.
+__global__ __launch_bounds__(256) void k_fit_err(const double* __restrict__ a, int64_t na,
+                                                 const double* __restrict__ b, int64_t nb,
+                                                 double* __restrict__ out) {
+    __shared__ double sh[4];
+    double x = 0.0;
+    for (int64_t i = threadIdx.x; i < na; i += 256) x += a[i];
+    const double sa = block_sum<256>(x, sh);
+    __syncthreads();
+    double y = 0.0;
+    for (int64_t i = threadIdx.x; i < nb; i += 256) y += b[i];
+    const double sb = block_sum<256>(y, sh);
+    if (threadIdx.x == 0) {
+        out[0] = sa - sb;
+        out[1] = sa;
+        out[2] = sb;
+    }
+}
+
+inline dim3 grid2d(int64_t cols, int64_t rows) {
+    int64_t gx = (cols + 255) / 256;
+    if (gx > 64) gx = 64;
+    if (gx < 1) gx = 1;
+    int64_t gy = rows < 65535 ? rows : 65535;
+    if (gy < 1) gy = 1;
+    return dim3((unsigned)gx, (unsigned)gy);
+}
+
+}  // namespace
+
+int frob2_grid(int64_t m, int64_t n) {
+    int64_t g = (m * n + 16383) / 16384;
+    if (g > 2048) g = 2048;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+hipError_t launch_frob2(const float* A, int64_t m, int64_t n, int64_t lda, double* partial, int grid, double* out,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_frob2_partial, dim3(grid), dim3(256), 0, st, A, m, n, lda, partial);
+    hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(256), 0, st, (const double*)partial, (int64_t)grid, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_f64(const double* x, int64_t count, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(256), 0, st, x, count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_scores(const float* V, int64_t k, int64_t ldv, const int64_t* d_off, int64_t G,
+                               double* scores, hipStream_t st) {
+    hipLaunchKernelGGL(k_block_scores, dim3((unsigned)G), dim3(256), 0, st, V, k, ldv, d_off, scores);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample(const double* scores, int64_t G, const uint64_t* draws, int64_t s, int replace,
+                         uint64_t* qbuf, uint64_t* pref, int64_t* idx, double* weights, double* margins,
+                         int* status, hipStream_t st) {
+    hipLaunchKernelGGL(k_sample, dim3(1), dim3(1024), 0, st, scores, G, draws, s, replace, qbuf, pref, idx,
+                       weights, margins, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_cols(const float* A, int64_t lda, int64_t m, const int64_t* d_cols, int64_t c, float* C,
+                              int64_t ldc, hipStream_t st) {
+    hipLaunchKernelGGL(k_gather_cols, grid2d(c, m), dim3(256), 0, st, A, lda, m, d_cols, c, C, ldc);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(const float* A, int64_t lda, int64_t n, const int64_t* d_rows, int64_t r, float* R,
+                              int64_t ldr, hipStream_t st) {
+    hipLaunchKernelGGL(k_gather_rows, grid2d(n, r), dim3(256), 0, st, A, lda, n, d_rows, r, R, ldr);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_from_cols(const float* H, int64_t ldh, const int64_t* d_cols, int64_t c, double* G,
+                                 hipStream_t st) {
+    const int64_t blocks = (c * c + 255) / 256;
+    hipLaunchKernelGGL(k_gram_from_cols, dim3((unsigned)blocks), dim3(256), 0, st, H, ldh, d_cols, c, G);
+    return hipGetLastError();
+}
+
+hipError_t launch_f64_to_f32(const double* x, int64_t count, float* y, hipStream_t st) {
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_f64_to_f32, dim3((unsigned)blocks), dim3(256), 0, st, x, count, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_f64_to_f32_2d(const double* x, int64_t rows, int64_t cols, int64_t ldx, float* y, int64_t ldy,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(k_f64_to_f32_2d, grid2d(ldy, rows), dim3(256), 0, st, x, rows, cols, ldx, y, ldy);
+    return hipGetLastError();
+}
+
+hipError_t launch_cast_bf16(const float* A, int64_t m, int64_t n, int64_t lda, uint16_t* out, int64_t ldo,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_cast_bf16, grid2d((n + 3) / 4, m), dim3(256), 0, st, A, m, n, lda, out, ldo);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_f32(float* x, int64_t rows, int64_t cols, int64_t ld, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_f32, grid2d(cols, rows), dim3(256), 0, st, x, rows, cols, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_fit_err(const double* parts, int64_t nparts_e, const double* dot_parts, int64_t nparts_d,
+                          double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_fit_err, dim3(1), dim3(256), 0, st, parts, nparts_e, dot_parts, nparts_d, out);
+    return hipGetLastError();
+}
+
+}  // namespace bcur

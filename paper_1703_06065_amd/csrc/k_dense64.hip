@@ -1,0 +1,288 @@
+// FP64 dense kernels for the c x c normal-equation matrix G = C^T C of the
+// fit: a tiled FP64 GEMM, and G^-1 by a blocked right-looking Cholesky
+// (64-wide panels factored in LDS), a blocked triangular inverse computed by
+// anti-diagonal wavefronts, and Ginv = L^-T L^-1.
+#include <math.h>
+
+#include "bcur_internal.h"
+
+namespace bcur {
+namespace {
+
+constexpr int NB = 64;   // panel width and GEMM tile
+constexpr int KB = 16;   // GEMM k step
+
+// acc (thread's 4x4 at rows ty + 16 i, cols tx + 16 j of a 64x64 tile) +=
+// op(A)[0:M, 0:K] op(B)[0:K, 0:N]; A, B point at the tile's origin.
+template <bool TA, bool TB>
+__device__ __forceinline__ void tile_mm(double (&acc)[4][4], const double* __restrict__ A, int64_t lda,
+                                        const double* __restrict__ B, int64_t ldb, int64_t M, int64_t N, int64_t K,
+                                        double* As, double* Bs) {
+    const int tid = threadIdx.x, ty = tid / 16, tx = tid % 16;
+    for (int64_t k0 = 0; k0 < K; k0 += KB) {
+        __syncthreads();
+        for (int e = tid; e < NB * KB; e += 256) {
+            int row, kk;
+            if (!TA) {
+                row = e / KB;
+                kk = e % KB;
+            } else {
+                kk = e / NB;
+                row = e % NB;
+            }
+            const int64_t gk = k0 + kk;
+            double v = 0.0;
+            if (row < M && gk < K) v = TA ? A[gk * lda + row] : A[row * lda + gk];
+            As[kk * (NB + 1) + row] = v;
+        }
+        for (int e = tid; e < NB * KB; e += 256) {
+            int col, kk;
+            if (!TB) {
+                kk = e / NB;
+                col = e % NB;
+            } else {
+                col = e / KB;
+                kk = e % KB;
+            }
+            const int64_t gk = k0 + kk;
+            double v = 0.0;
+            if (col < N && gk < K) v = TB ? B[col * ldb + gk] : B[gk * ldb + col];
+            Bs[kk * (NB + 1) + col] = v;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < KB; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[kk * (NB + 1) + ty + 16 * i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[kk * (NB + 1) + tx + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+        }
+    }
+}
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_dgemm(int64_t M, int64_t N, int64_t K, double alpha,
+                                               const double* __restrict__ A, int64_t lda,
+                                               const double* __restrict__ B, int64_t ldb, double beta,
+                                               double* D, int64_t ldd) {
+    __shared__ double As[KB * (NB + 1)], Bs[KB * (NB + 1)];
+    const int64_t m0 = (int64_t)blockIdx.x * NB, n0 = (int64_t)blockIdx.y * NB;
+    double acc[4][4] = {};
+    const double* Ab = TA ? A + m0 : A + m0 * lda;
+    const double* Bb = TB ? B + n0 * ldb : B + n0;
+    tile_mm<TA, TB>(acc, Ab, lda, Bb, ldb, M - m0, N - n0, K, As, Bs);
+    const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t row = m0 + ty + 16 * i, col = n0 + tx + 16 * j;
+            if (row < M && col < N) {
+                const double v = alpha * acc[i][j];
+                D[row * ldd + col] = beta == 0.0 ? v : v + beta * D[row * ldd + col];
+            }
+        }
+}
+
+__global__ __launch_bounds__(256) void k_maxdiag(const double* __restrict__ G, int64_t c, double* __restrict__ out) {
+    __shared__ double sh[256];
+    double mx = 0.0;
+    for (int64_t i = threadIdx.x; i < c; i += 256) mx = fmax(mx, G[i * c + i]);
+    sh[threadIdx.x] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < 256; ++i) mx = fmax(mx, sh[i]);
+        out[0] = mx;
+    }
+}
+
+// Cholesky of the w x w diagonal block at (j0, j0) of G in LDS.  A column
+// whose Schur-complement pivot is not above tau = c 2^-24 max diag(G) is
+// numerically in the span of the columns before it: it is dropped (flagged),
+// its column of L is zeroed so it updates nothing, and its row of L^-1 is
+// zeroed so the inverse built from L^-1 is that of the kept columns, with
+// zero rows and columns for the dropped ones.  Writes L (lower, upper part of
+// the block zeroed) into G and L^-1 (NB x NB, zero padded) into Linv.
+// piv[0..1] receive the smallest and largest pivot.
+__global__ __launch_bounds__(256) void k_potrf_diag(double* __restrict__ G, int64_t c, int64_t j0, int w,
+                                                    const double* __restrict__ maxdiag, double* __restrict__ Linv,
+                                                    double* __restrict__ piv, int* __restrict__ info) {
+    __shared__ double S[NB * NB];
+    __shared__ double X[NB * NB];
+    __shared__ int drop[NB];
+    const int tid = threadIdx.x;
+    const double tau = (double)c * ldexp(1.0, -24) * maxdiag[0];
+    for (int e = tid; e < w * w; e += 256) {
+        const int i = e / w, j = e % w;
+        S[e] = G[(j0 + i) * c + (j0 + j)];
+    }
+    double pmin = INFINITY, pmax = 0.0;
+    int flag = 0;
+    for (int j = 0; j < w; ++j) {
+        __syncthreads();
+        const double d = S[j * w + j];
+        pmin = fmin(pmin, d);
+        pmax = fmax(pmax, d);
+        const bool dropped = !(d > tau);
+        if (tid == 0) drop[j] = dropped;
+        if (dropped) {
+            flag = 1;
+            continue;
+        }
+        const int ww = w - 1 - j;
+        for (int e = tid; e < ww * ww; e += 256) {
+            const int i = j + 1 + e / ww, p = j + 1 + e % ww;
+            S[i * w + p] -= S[i * w + j] * S[p * w + j] / d;
+        }
+    }
+    __syncthreads();
+    // L[i][j] = S[i][j] / sqrt(d_j), L[j][j] = sqrt(d_j); dropped columns are
+    // zero below a unit diagonal; the upper part is zeroed
+    for (int e = tid; e < w * w; e += 256) {
+        const int i = e / w, j = e % w;
+        if (drop[j]) {
+            X[e] = i == j ? 1.0 : 0.0;
+            continue;
+        }
+        const double sd = sqrt(S[j * w + j]);
+        X[e] = i > j ? S[e] / sd : (i == j ? sd : 0.0);
+    }
+    __syncthreads();
+    for (int e = tid; e < w * w; e += 256) S[e] = X[e];
+    __syncthreads();
+    // L^-1 by forward substitution, one column per thread (into X, lower);
+    // a dropped index has 1/L_jj taken as 0, which zeroes its row of L^-1
+    if (tid < w) {
+        const int cl = tid;
+        for (int i = 0; i < w; ++i) X[i * w + cl] = 0.0;
+        X[cl * w + cl] = drop[cl] ? 0.0 : 1.0 / S[cl * w + cl];
+        for (int i = cl + 1; i < w; ++i) {
+            if (drop[i]) continue;
+            double acc = 0.0;
+            for (int p = cl; p < i; ++p) acc = fma(S[i * w + p], X[p * w + cl], acc);
+            X[i * w + cl] = -acc / S[i * w + i];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < w * w; e += 256) {
+        const int i = e / w, j = e % w;
+        G[(j0 + i) * c + (j0 + j)] = S[e];
+    }
+    for (int e = tid; e < NB * NB; e += 256) {
+        const int i = e / NB, j = e % NB;
+        Linv[e] = (i < w && j < w) ? X[i * w + j] : 0.0;
+    }
+    if (tid == 0) {
+        piv[0] = pmin;
+        piv[1] = pmax;
+        if (flag) atomicOr(info, 1);
+    }
+}
+
+// One anti-diagonal of the blocked inverse X = L^-1 (lower):
+// X_ij = -Linv_ii (sum_{p=j}^{i-1} L_ip X_pj) for i = j + d, j = blockIdx.x.
+__global__ __launch_bounds__(256) void k_trtri_step(const double* __restrict__ L, double* __restrict__ X, int64_t c,
+                                                    int d, const double* __restrict__ Linv) {
+    __shared__ double As[KB * (NB + 1)], Bs[KB * (NB + 1)];
+    __shared__ double T[NB * (NB + 1)];
+    __shared__ double Li[NB * (NB + 1)];
+    const int64_t jb = blockIdx.x, ib = jb + d;
+    const int64_t j0 = jb * NB, i0 = ib * NB;
+    const int64_t wi = c - i0 < NB ? c - i0 : NB, wj = c - j0 < NB ? c - j0 : NB;
+    double acc[4][4] = {};
+    // T = L[i0:i0+wi, j0:i0] X[j0:i0, j0:j0+wj]
+    tile_mm<false, false>(acc, L + i0 * c + j0, c, X + j0 * c + j0, c, wi, wj, i0 - j0, As, Bs);
+    const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) T[(ty + 16 * i) * (NB + 1) + tx + 16 * j] = acc[i][j];
+    for (int e = threadIdx.x; e < NB * NB; e += 256) Li[(e / NB) * (NB + 1) + e % NB] = Linv[ib * NB * NB + e];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            double s = 0.0;
+            const int row = ty + 16 * i, col = tx + 16 * j;
+            for (int p = 0; p < NB; ++p) s = fma(Li[row * (NB + 1) + p], T[p * (NB + 1) + col], s);
+            if (row < wi && col < wj) X[(i0 + row) * c + j0 + col] = -s;
+        }
+}
+
+// X = 0, then the diagonal blocks of X = L^-1 from Linv.
+__global__ __launch_bounds__(256) void k_init_xinv(double* __restrict__ X, int64_t c, const double* __restrict__ Linv) {
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < c * c; e += (int64_t)gridDim.x * 256) {
+        const int64_t i = e / c, j = e - i * c;
+        const int64_t bi = i / NB, bj = j / NB;
+        X[e] = bi == bj ? Linv[bi * NB * NB + (i - bi * NB) * NB + (j - bj * NB)] : 0.0;
+    }
+}
+
+}  // namespace
+
+size_t spd_inverse_ws_doubles(int64_t c) {
+    const int64_t nblk = (c + NB - 1) / NB;
+    return (size_t)(nblk * NB * NB) + (size_t)(c * c) + (size_t)(2 * nblk) + 8;
+}
+
+hipError_t launch_dgemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda, bool tA,
+                        const double* B, int64_t ldb, bool tB, double beta, double* D, int64_t ldd, hipStream_t st) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    dim3 grid((unsigned)((M + NB - 1) / NB), (unsigned)((N + NB - 1) / NB));
+    if (!tA && !tB)
+        hipLaunchKernelGGL((k_dgemm<false, false>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, D, ldd);
+    else if (!tA && tB)
+        hipLaunchKernelGGL((k_dgemm<false, true>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, D, ldd);
+    else if (tA && !tB)
+        hipLaunchKernelGGL((k_dgemm<true, false>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, D, ldd);
+    else
+        hipLaunchKernelGGL((k_dgemm<true, true>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, D, ldd);
+    return hipGetLastError();
+}
+
+// ws: [Linv blocks nblk*NB*NB][X c*c][piv 2*nblk][maxdiag]
+hipError_t launch_spd_inverse(double* G, int64_t c, double* Ginv, double* ws, int* info, double* piv, hipStream_t st) {
+    const int64_t nblk = (c + NB - 1) / NB;
+    double* Linv = ws;
+    double* X = Linv + nblk * NB * NB;
+    double* pivb = X + c * c;
+    double* maxd = pivb + 2 * nblk;
+    hipLaunchKernelGGL(k_maxdiag, dim3(1), dim3(256), 0, st, (const double*)G, c, maxd);
+    for (int64_t jb = 0; jb < nblk; ++jb) {
+        const int64_t j0 = jb * NB;
+        const int w = (int)(c - j0 < NB ? c - j0 : NB);
+        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, st, G, c, j0, w, (const double*)maxd,
+                           Linv + jb * NB * NB, pivb + 2 * jb, info);
+        const int64_t rows = c - j0 - w;
+        if (rows > 0) {
+            double* L21 = G + (j0 + w) * c + j0;
+            hipError_t e = launch_dgemm(rows, w, w, 1.0, L21, c, false, Linv + jb * NB * NB, NB, true, 0.0, L21, c, st);
+            if (e != hipSuccess) return e;
+            e = launch_dgemm(rows, rows, w, -1.0, L21, c, false, L21, c, true, 1.0, G + (j0 + w) * c + (j0 + w), c, st);
+            if (e != hipSuccess) return e;
+        }
+    }
+    int64_t blocks = (c * c + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_init_xinv, dim3((unsigned)blocks), dim3(256), 0, st, X, c, (const double*)Linv);
+    for (int d = 1; d < nblk; ++d)
+        hipLaunchKernelGGL(k_trtri_step, dim3((unsigned)(nblk - d)), dim3(256), 0, st, (const double*)G, X, c, d,
+                           (const double*)Linv);
+    hipError_t e = launch_dgemm(c, c, c, 1.0, X, c, true, X, c, false, 0.0, Ginv, c, st);
+    if (e != hipSuccess) return e;
+    if (piv) {
+        // pivot range over the blocks: min of mins, max of maxes (host reads pivb)
+        const hipError_t e2 = hipMemcpyAsync(piv, pivb, sizeof(double) * 2 * nblk, hipMemcpyDeviceToDevice, st);
+        if (e2 != hipSuccess) return e2;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace bcur

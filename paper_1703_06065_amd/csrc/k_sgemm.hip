@@ -1,0 +1,310 @@
+// FP32 GEMMs on the CDNA4 matrix cores (v_mfma_f32_32x32x2_f32, FP32
+// accumulation) for every contraction of the Block CUR path:
+//   Z = A Q, Y = A^T Z          (range finder passes, N = sketch width)
+//   H = C^T A, F = C^T E        (fit: projection onto the chosen columns)
+//   U = Ginv H, E = A - C U     (fit: solve and residual, fused norm)
+// D = op(A) B with op(A) = A (M x K) or A^T (A stored K x M), B is K x N; all
+// operands row-major.  Tiles are staged through LDS in k-major order so each
+// MFMA operand read is 32 consecutive floats.  Split-K writes partial tiles
+// that a second kernel sums in a fixed order, so results are deterministic.
+#include "bcur_internal.h"
+
+namespace bcur {
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+struct GemmArgs {
+    int64_t M, N, K;
+    const float* A;
+    int64_t lda;
+    const float* B;
+    int64_t ldb;
+    float* D;
+    int64_t ldd;
+    int64_t kchunk;
+    int64_t split_stride;
+    const float* X;
+    int64_t ldx;
+    const float* Y;
+    int64_t ldy;
+    double* wsum;
+};
+
+// Load 4 consecutive floats p[0..3] (p 16-byte aligned), zero outside [c, cend).
+__device__ __forceinline__ float4 ld4(const float* p, bool rowok, int64_t c, int64_t cend) {
+    if (rowok && c + 3 < cend) return *reinterpret_cast<const float4*>(p);
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (rowok) {
+        if (c < cend) v.x = p[0];
+        if (c + 1 < cend) v.y = p[1];
+        if (c + 2 < cend) v.z = p[2];
+        if (c + 3 < cend) v.w = p[3];
+    }
+    return v;
+}
+
+template <int BM, int BN, int BK, int WM, int WN, bool TA, int EPI>
+__global__ __launch_bounds__(WM* WN * 64) void k_sgemm(const GemmArgs g) {
+    constexpr int NT = WM * WN * 64;
+    constexpr int WTM = BM / WM, WTN = BN / WN;
+    constexpr int TM = WTM / 32, TN = WTN / 32;
+    constexpr int LDAS = BM + 4, LDBS = BN + 4;
+    constexpr int A_F4 = BM * BK / 4 / NT;
+    constexpr int B_F4 = BK * BN / 4 / NT;
+    static_assert(TM >= 1 && TN >= 1 && A_F4 >= 1 && B_F4 >= 1, "tile shape");
+    static_assert((BM * BK / 4) % NT == 0 && (BK * BN / 4) % NT == 0, "tile shape");
+
+    __shared__ __attribute__((aligned(16))) float As[BK * LDAS];
+    __shared__ __attribute__((aligned(16))) float Bs[BK * LDBS];
+    __shared__ double red[NT / 64];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 31, h = lane >> 5;
+    const int wm = wave % WM, wn = wave / WM;
+    const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
+    const int64_t kbeg = (int64_t)blockIdx.z * g.kchunk;
+    const int64_t kend = g.K < kbeg + g.kchunk ? g.K : kbeg + g.kchunk;
+
+    f32x16 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+
+    float4 ra[A_F4], rb[B_F4];
+
+    auto load_tiles = [&](int64_t k0) {
+#pragma unroll
+        for (int u = 0; u < A_F4; ++u) {
+            const int f = tid + u * NT;
+            if (!TA) {
+                const int row = f / (BK / 4), kq = f % (BK / 4);
+                const int64_t gm = m0 + row, gk = k0 + kq * 4;
+                ra[u] = ld4(g.A + gm * g.lda + gk, gm < g.M, gk, kend);
+            } else {
+                const int kr = f / (BM / 4), mq = f % (BM / 4);
+                const int64_t gk = k0 + kr, gm = m0 + mq * 4;
+                ra[u] = ld4(g.A + gk * g.lda + gm, gk < kend, gm, g.M);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < B_F4; ++u) {
+            const int f = tid + u * NT;
+            const int kr = f / (BN / 4), nq = f % (BN / 4);
+            const int64_t gk = k0 + kr, gn = n0 + nq * 4;
+            rb[u] = ld4(g.B + gk * g.ldb + gn, gk < kend, gn, g.N);
+        }
+    };
+    auto store_tiles = [&]() {
+#pragma unroll
+        for (int u = 0; u < A_F4; ++u) {
+            const int f = tid + u * NT;
+            if (!TA) {
+                const int row = f / (BK / 4), kq = f % (BK / 4);
+                As[(kq * 4 + 0) * LDAS + row] = ra[u].x;
+                As[(kq * 4 + 1) * LDAS + row] = ra[u].y;
+                As[(kq * 4 + 2) * LDAS + row] = ra[u].z;
+                As[(kq * 4 + 3) * LDAS + row] = ra[u].w;
+            } else {
+                const int kr = f / (BM / 4), mq = f % (BM / 4);
+                *reinterpret_cast<float4*>(&As[kr * LDAS + mq * 4]) = ra[u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < B_F4; ++u) {
+            const int f = tid + u * NT;
+            const int kr = f / (BN / 4), nq = f % (BN / 4);
+            *reinterpret_cast<float4*>(&Bs[kr * LDBS + nq * 4]) = rb[u];
+        }
+    };
+
+    int64_t k0 = kbeg;
+    if (k0 < kend) load_tiles(k0);
+    for (; k0 < kend; k0 += BK) {
+        __syncthreads();
+        store_tiles();
+        __syncthreads();
+        if (k0 + BK < kend) load_tiles(k0 + BK);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 2) {
+            float a[TM], b[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) a[i] = As[(kk + h) * LDAS + wm * WTM + 32 * i + r];
+#pragma unroll
+            for (int j = 0; j < TN; ++j) b[j] = Bs[(kk + h) * LDBS + wn * WTN + 32 * j + r];
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+    }
+
+    // Output layout of a 32x32 MFMA tile: lane (r, h), register v holds
+    // row 8 (v / 4) + 4 h + (v % 4), column r.
+    float* D = g.D + (int64_t)blockIdx.z * g.split_stride;
+    double wacc = 0.0;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int64_t row = m0 + wm * WTM + 32 * i + 8 * (v >> 2) + 4 * h + (v & 3);
+                const int64_t col = n0 + wn * WTN + 32 * j + r;
+                if (row < g.M && col < g.N) {
+                    const float x = acc[i][j][v];
+                    if (EPI == EPI_STORE) {
+                        D[row * g.ldd + col] = x;
+                    } else if (EPI == EPI_RESID) {
+                        const float e = g.X[row * g.ldx + col] - x;
+                        D[row * g.ldd + col] = e;
+                        wacc += (double)e * (double)e;
+                    } else {
+                        D[row * g.ldd + col] = g.X[row * g.ldx + col] + x;
+                        wacc += (double)x * (double)g.Y[row * g.ldy + col];
+                    }
+                }
+            }
+    if (EPI != EPI_STORE) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) wacc += __shfl_xor(wacc, o, 64);
+        if (lane == 0) red[wave] = wacc;
+        __syncthreads();
+        if (tid == 0) {
+            double s = 0.0;
+#pragma unroll
+            for (int w = 0; w < NT / 64; ++w) s += red[w];
+            g.wsum[blockIdx.x + (int64_t)gridDim.x * blockIdx.y] = s;
+        }
+    }
+}
+
+// D[row][col] = sum_s P[s][row][col] in the order s = 0, 1, ...
+__global__ __launch_bounds__(256) void k_splitk_reduce(const float* __restrict__ P, int splits, int64_t stride,
+                                                       int64_t M, int64_t N, float* __restrict__ D, int64_t ldd) {
+    const int64_t total = M * N;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        float s = P[e];
+        for (int z = 1; z < splits; ++z) s += P[z * stride + e];
+        const int64_t row = e / N, col = e - row * N;
+        D[row * ldd + col] = s;
+    }
+}
+
+struct Cfg {
+    int BM, BN;
+};
+constexpr Cfg kCfg[3] = {{128, 64}, {128, 128}, {128, 128}};
+constexpr int kBK = 16;
+
+template <int CFG, bool TA, int EPI>
+hipError_t run(const GemmArgs& a, dim3 grid, hipStream_t st) {
+    if (CFG == 0)
+        hipLaunchKernelGGL((k_sgemm<128, 64, kBK, 4, 1, TA, EPI>), grid, dim3(256), 0, st, a);
+    else if (CFG == 1)
+        hipLaunchKernelGGL((k_sgemm<128, 128, kBK, 4, 1, TA, EPI>), grid, dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_sgemm<128, 128, kBK, 2, 2, TA, EPI>), grid, dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+GemmPlan plan_sgemm(int64_t M, int64_t N, int64_t K, bool transA, bool allow_split) {
+    (void)transA;
+    GemmPlan p;
+    p.cfg = N <= 64 ? 0 : (N <= 128 ? 1 : 2);
+    const int64_t tiles = ((M + kCfg[p.cfg].BM - 1) / kCfg[p.cfg].BM) * ((N + kCfg[p.cfg].BN - 1) / kCfg[p.cfg].BN);
+    int64_t splits = 1;
+    if (allow_split && tiles < 480) {
+        splits = (512 + tiles - 1) / tiles;
+        const int64_t maxs = K / (4 * kBK);
+        if (splits > maxs) splits = maxs;
+        if (splits < 1) splits = 1;
+    }
+    int64_t kchunk = (K + splits - 1) / splits;
+    kchunk = ((kchunk + kBK - 1) / kBK) * kBK;
+    if (kchunk < kBK) kchunk = kBK;
+    splits = (K + kchunk - 1) / kchunk;
+    if (splits < 1) splits = 1;
+    p.splits = (int)splits;
+    p.kchunk = kchunk;
+    p.wgs = tiles * splits;
+    return p;
+}
+
+size_t sgemm_partial_floats(const GemmPlan& p, int64_t M, int64_t N) {
+    return p.splits > 1 ? (size_t)p.splits * (size_t)M * (size_t)N : 0;
+}
+
+hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K, bool transA, const float* A,
+                             int64_t lda, const float* B, int64_t ldb, float* D, int64_t ldd, float* partial, int epi,
+                             const float* X, int64_t ldx, const float* Y, int64_t ldy, double* wsum, hipStream_t st) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    if (epi != EPI_STORE && p.splits != 1) return hipErrorInvalidValue;
+    GemmArgs a;
+    a.M = M;
+    a.N = N;
+    a.K = K;
+    a.A = A;
+    a.lda = lda;
+    a.B = B;
+    a.ldb = ldb;
+    a.kchunk = p.kchunk;
+    a.X = X;
+    a.ldx = ldx;
+    a.Y = Y;
+    a.ldy = ldy;
+    a.wsum = wsum;
+    if (p.splits > 1) {
+        a.D = partial;
+        a.ldd = N;
+        a.split_stride = M * N;
+    } else {
+        a.D = D;
+        a.ldd = ldd;
+        a.split_stride = 0;
+    }
+    // the fused epilogues exist for the square tile only
+    const int cfg = epi != EPI_STORE ? 2 : p.cfg;
+    const Cfg c = kCfg[cfg];
+    dim3 grid((unsigned)((M + c.BM - 1) / c.BM), (unsigned)((N + c.BN - 1) / c.BN), (unsigned)p.splits);
+    hipError_t e;
+    switch (cfg * 100 + (transA ? 10 : 0) + epi) {
+        case 0: e = run<0, false, EPI_STORE>(a, grid, st); break;
+        case 10: e = run<0, true, EPI_STORE>(a, grid, st); break;
+        case 100: e = run<1, false, EPI_STORE>(a, grid, st); break;
+        case 110: e = run<1, true, EPI_STORE>(a, grid, st); break;
+        case 200: e = run<2, false, EPI_STORE>(a, grid, st); break;
+        case 210: e = run<2, true, EPI_STORE>(a, grid, st); break;
+        case 201: e = run<2, false, EPI_RESID>(a, grid, st); break;
+        case 202: e = run<2, false, EPI_ADD_DOT>(a, grid, st); break;
+        default: return hipErrorInvalidValue;
+    }
+    return e;
+}
+
+hipError_t launch_splitk_reduce(const GemmPlan& p, int64_t M, int64_t N, const float* partial, float* D, int64_t ldd,
+                                hipStream_t st) {
+    if (p.splits <= 1 || M <= 0 || N <= 0) return hipSuccess;
+    int64_t blocks = (M * N + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)blocks), dim3(256), 0, st, partial, p.splits, M * N, M, N, D,
+                       ldd);
+    return hipGetLastError();
+}
+
+hipError_t launch_sgemm(const GemmPlan& p, int64_t M, int64_t N, int64_t K, bool transA, const float* A, int64_t lda,
+                        const float* B, int64_t ldb, float* D, int64_t ldd, float* partial, int epi, const float* X,
+                        int64_t ldx, const float* Y, int64_t ldy, double* wsum, hipStream_t st) {
+    const hipError_t e = launch_sgemm_main(p, M, N, K, transA, A, lda, B, ldb, D, ldd, partial, epi, X, ldx, Y, ldy,
+                                           wsum, st);
+    if (e != hipSuccess) return e;
+    return launch_splitk_reduce(p, M, N, partial, D, ldd, st);
+}
+
+}  // namespace bcur

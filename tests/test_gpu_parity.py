@@ -1,0 +1,288 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (derivations in the design notes):
+  * ||A||_F^2, block scores of a given V: FP64 accumulation of exact squares
+    of FP32 values on both sides, so only the summation order differs:
+    relative 1e-12.
+  * sampling, gather: integer / copy results, bit-exact.
+  * sketched scores: the GPU runs the range finder in FP32, the oracle twin
+    in FP64 from the same test matrix.  Rounding perturbs the top-k subspace
+    by about u32 * kappa, kappa = lam_1 / (lam_k - lam_k+1) of the Ritz
+    values, so |l_g(GPU) - l_g(twin)| <= tau * max(l_g, k/G) with
+    tau = max(1e-5, SCORE_C * 2^-24 * kappa).
+  * indices: identical whenever the oracle's smallest sampling margin exceeds
+    2 G max_g tol_g (the largest shift any interval edge can see).
+  * residual err = ||A - C C^+ A||_F: relative 1e-5 given identical indices
+    (first order insensitive to errors in U at the least-squares optimum).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import bcur_oracle as O
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+SCORE_C = 64.0
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1703_06065_amd import Context
+    return Context(0)
+
+
+def dev(a):
+    from paper_1703_06065_amd.binding import to_device
+    return to_device(a)
+
+
+def dev_dense(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def dev_ld(a, ld):
+    t = torch.zeros((a.shape[0], ld), dtype=torch.float32)
+    t[:, :a.shape[1]] = torch.from_numpy(np.asarray(a, dtype=np.float32))
+    return t.cuda()[:, :a.shape[1]]
+
+
+def note(*a):
+    print(*a, flush=True)
+
+
+def err_tol(err_ref, frob2):
+    """1e-5 relative, with a floor of 16 u32 ||A||_F for residuals that are
+    zero in exact arithmetic (the FP32 residual cannot resolve below it)."""
+    return 1e-5 * err_ref + 16 * U32 * math.sqrt(frob2)
+
+
+def score_tol(ref, k, G):
+    tau = max(1e-5, SCORE_C * U32 * min(ref["kappa"], 1e12))
+    return tau * np.maximum(ref["scores"], k / G), tau
+
+
+# ---------------------------------------------------------------------------
+# stage parity
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("m,n,pad", [(1, 1, 0), (7, 5, 3), (300, 200, 0), (513, 257, 7), (1024, 4096, 0)])
+def test_frob2(ctx, m, n, pad):
+    note(f"frob2 m={m} n={n} pad={pad}")
+    A = np.random.default_rng(m * 7 + n).standard_normal((m, n)).astype(np.float32)
+    ld = (n + pad + 3) // 4 * 4
+    got, fin = ctx.frob2(dev_ld(A, ld))
+    want = O.frob2(A.astype(np.float64))
+    assert fin
+    assert abs(got - want) <= 1e-12 * want
+
+
+def test_frob2_nonfinite(ctx):
+    note("frob2 nonfinite")
+    A = np.ones((64, 32), dtype=np.float32)
+    A[5, 7] = np.nan
+    assert ctx.frob2(dev(A))[1] is False
+    A[5, 7] = np.inf
+    assert ctx.frob2(dev(A))[1] is False
+
+
+@pytest.mark.parametrize("n,k,b,ragged", [(64, 5, 8, False), (1000, 17, 1, False), (333, 30, 16, True),
+                                          (4096, 50, 16, False), (77, 3, 77, False)])
+def test_block_scores(ctx, n, k, b, ragged):
+    note(f"block_scores n={n} k={k} b={b} ragged={ragged}")
+    V = np.random.default_rng(n + k).standard_normal((n, k)).astype(np.float32)
+    off = gen.ragged_blocks(n, -(-n // b), 5) if ragged else gen.contiguous_blocks(n, b)
+    got = ctx.block_scores(dev(V), off)
+    want = O.block_scores(V.astype(np.float64), off)
+    assert np.all(np.abs(got - want) <= 1e-12 * np.maximum(want, 1e-30))
+
+
+def _sampler_cases():
+    rng = np.random.default_rng(31)
+    cases = []
+    for t in range(30):
+        G = int(rng.integers(1, 3000)) if t % 3 else int(rng.integers(1, 40))
+        sc = rng.random(G) * (rng.random(G) < 0.7) * 10.0 ** rng.integers(-5, 5)
+        if t % 5 == 0:
+            sc[:] = 0.0
+            sc[rng.integers(0, G)] = 1.0
+        replace = bool(t % 2)
+        s = int(rng.integers(1, min(G, 40) + 1)) if not replace else int(rng.integers(1, 60))
+        dr = gen.draws_u64(s, 100 + t)
+        if t % 4 == 0:
+            dr[0] = 0
+            dr[-1] = np.uint64(2 ** 64 - 1)
+        cases.append((sc, dr, s, replace))
+    return cases
+
+
+@pytest.mark.parametrize("case", range(30))
+def test_sampler_bit_exact(ctx, case):
+    sc, dr, s, replace = _sampler_cases()[case]
+    note(f"sample case={case} G={len(sc)} s={s} replace={replace}")
+    idx, w, mg = ctx.sample_blocks(sc, dr, s, replace)
+    ref = O.sample_blocks(sc, dr, s, replace)
+    assert np.array_equal(idx, ref["idx"])
+    fin = np.isfinite(ref["weights"])
+    assert np.array_equal(np.isfinite(w), fin)
+    assert np.allclose(w[fin], ref["weights"][fin], rtol=1e-15, atol=0)
+    assert np.allclose(mg, ref["margins"], rtol=1e-15, atol=0)
+
+
+def test_sampler_rejects_bad_scores(ctx):
+    from paper_1703_06065_amd import BcurError
+    note("sample bad scores")
+    for bad in (np.array([1.0, -1.0]), np.array([1.0, np.nan]), np.array([np.inf, 1.0])):
+        with pytest.raises(BcurError):
+            ctx.sample_blocks(bad, gen.draws_u64(1, 0), 1, False)
+
+
+@pytest.mark.parametrize("m,n,b,idx", [(50, 40, 4, [3, 0, 9]), (33, 100, 7, [14, 2, 2, 5]), (8, 8, 8, [0])])
+def test_gather_bit_exact(ctx, m, n, b, idx):
+    note(f"gather m={m} n={n} b={b} idx={idx}")
+    A = np.random.default_rng(m).standard_normal((m, n)).astype(np.float32)
+    off = gen.contiguous_blocks(n, b)
+    C = ctx.gather_columns(dev(A), off, idx).cpu().numpy()
+    want = A[:, O.selected_columns(off, idx)]
+    assert np.array_equal(C, want)
+
+
+@pytest.mark.parametrize("m,n,b,blocks", [(300, 200, 10, [1, 5, 7]), (257, 515, 16, [0, 31, 12, 4]),
+                                          (1000, 129, 3, [40, 2, 11, 30, 7])])
+def test_fit_columns(ctx, m, n, b, blocks):
+    note(f"fit m={m} n={n} b={b} blocks={blocks}")
+    w = gen.small_case(m, n, b, 8, 4, seed=m + n)
+    C = w.A[:, O.selected_columns(w.offsets, blocks)]
+    U, err, flags = ctx.fit_columns(dev(w.A), dev(C), refine=1)
+    Uo, erro = O.fit_columns(w.A, C)
+    U = U.cpu().numpy().astype(np.float64)
+    cond = O.cond2(C)
+    rel_u = np.linalg.norm(U - Uo) / np.linalg.norm(Uo)
+    note(f"  err={err:.9g} oracle={erro:.9g} rel_u={rel_u:.2e} cond={cond:.3g} flags={flags}")
+    assert abs(err - erro) <= err_tol(erro, O.frob2(w.A))
+    assert rel_u <= max(1e-4, 10 * U32 * cond ** 2)
+
+
+# ---------------------------------------------------------------------------
+# the range finder
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("m,n,rho,k,l", [(300, 200, 12, 10, 20), (120, 260, 8, 8, 12), (1000, 640, 30, 25, 40)])
+def test_range_finder_exact_low_rank(ctx, m, n, rho, k, l):
+    note(f"range_finder low-rank m={m} n={n} rho={rho} k={k} l={l}")
+    A = gen.gaussian_product(m, n, rho, m + n).astype(np.float32)
+    om = gen.rademacher(n, l, m)
+    V, _, ritz = ctx.range_finder(dev(A), dev_dense(om), k, q=1)
+    off = gen.contiguous_blocks(n, 10)
+    got = ctx.block_scores(V, off)
+    ex = O.block_scores(O.exact_right_subspace(A.astype(np.float64), k), off)
+    sv = np.linalg.svd(A.astype(np.float64), compute_uv=False)
+    kappa = sv[0] ** 2 / (sv[k - 1] ** 2 - sv[k] ** 2)
+    dev_ = np.abs(got - ex).max() / (k / len(ex))
+    note(f"  max |dl|/(k/G) = {dev_:.2e} kappa={kappa:.3g}  ritz rel err={np.abs(ritz[:rho] - sv[:rho]).max() / sv[0]:.2e}")
+    assert dev_ <= max(1e-5, SCORE_C * U32 * kappa)
+    assert np.allclose(ritz[:rho], sv[:rho], rtol=1e-4, atol=1e-5 * sv[0])
+    Vh = V.cpu().numpy().astype(np.float64)
+    assert np.abs(Vh.T @ Vh - np.eye(k)).max() < 1e-5
+
+
+# ---------------------------------------------------------------------------
+# the whole path
+# ---------------------------------------------------------------------------
+
+def _check_decompose(ctx, w, replace=False, refine=1, label=""):
+    note(f"decompose {label} {w.name} m={w.m} n={w.n} G={w.G} k={w.k} s={w.s} l={w.l} replace={replace}")
+    res = ctx.decompose(dev(w.A), w.offsets, w.k, w.s, dev_dense(w.omega), w.draws, q=w.q, replace=replace, refine=refine)
+    ref = O.decompose(w.A, w.offsets, w.k, w.s, w.omega, w.draws, q=w.q, replace=replace)
+    tol, tau = score_tol(ref, w.k, w.G)
+    dl = np.abs(res["scores"] - ref["scores"])
+    note(f"  kappa={ref['kappa']:.3g} tau={tau:.2e} max|dl|/tol={np.max(dl / tol):.3f} "
+         f"max|dl|/(k/G)={dl.max() / (w.k / w.G):.2e} margin={ref['margins'].min():.3e}")
+    assert np.all(dl <= tol)
+    assert abs(res["frob2"] - ref["frob2"]) <= 1e-12 * ref["frob2"]
+    need = 2 * w.G * tol.max()
+    same = np.array_equal(res["idx"], ref["idx"])
+    note(f"  idx gpu={list(res['idx'])} oracle={list(ref['idx'])} need margin>{need:.2e}")
+    if ref["margins"].min() > need:
+        assert same
+    if same:
+        note(f"  err={res['err']:.9g} oracle={ref['err']:.9g} rel={abs(res['err'] - ref['err']) / ref['err']:.2e}")
+        assert abs(res["err"] - ref["err"]) <= err_tol(ref["err"], ref["frob2"])
+        assert res["c"] == len(ref["cols"])
+    else:
+        # a different but valid selection: distinct blocks, in range, and a
+        # residual that matches the oracle's fit of the GPU's own blocks
+        idx = res["idx"]
+        assert len(set(idx.tolist())) == len(idx) or replace
+        _, e2 = O.fit_columns(w.A, O.gather_columns(w.A, w.offsets, idx))
+        assert abs(res["err"] - e2) <= err_tol(e2, ref["frob2"])
+    return res, ref
+
+
+def test_decompose_tiny(ctx):
+    _check_decompose(ctx, gen.tiny(0), label="tiny")
+
+
+@pytest.mark.parametrize("m,n,b,k,s,ragged,seed", [
+    (300, 200, 10, 8, 4, False, 1),
+    (257, 515, 16, 12, 5, True, 2),
+    (1000, 129, 3, 5, 7, False, 3),
+    (129, 1000, 25, 20, 6, False, 4),
+    (640, 384, 32, 30, 3, False, 5),
+])
+def test_decompose_shapes(ctx, m, n, b, k, s, ragged, seed):
+    w = gen.small_case(m, n, b, k, s, seed=seed, ragged=ragged)
+    _check_decompose(ctx, w, label="shape")
+
+
+def test_decompose_with_replacement(ctx):
+    w = gen.small_case(400, 300, 10, 8, 12, seed=11, noise=1e-2)
+    _check_decompose(ctx, w, replace=True, label="replace")
+
+
+def test_decompose_all_blocks_zero_error(ctx):
+    w = gen.small_case(300, 96, 8, 6, 12, seed=12, noise=1e-2)
+    note("decompose all blocks")
+    res = ctx.decompose(dev(w.A), w.offsets, w.k, w.G, dev_dense(w.omega), w.draws[:w.G] if len(w.draws) >= w.G
+                        else gen.draws_u64(w.G, 12), q=w.q)
+    note(f"  rel_err={res['rel_err']:.3e} flags={res['flags']}")
+    assert sorted(res["idx"].tolist()) == list(range(w.G))
+    assert res["rel_err"] <= 1e-5
+
+
+def test_decompose_deterministic(ctx):
+    w = gen.small_case(500, 300, 10, 10, 5, seed=13)
+    note("decompose determinism")
+    a = ctx.decompose(dev(w.A), w.offsets, w.k, w.s, dev_dense(w.omega), w.draws)
+    b = ctx.decompose(dev(w.A), w.offsets, w.k, w.s, dev_dense(w.omega), w.draws)
+    assert a["err"] == b["err"]
+    assert np.array_equal(a["scores"], b["scores"])
+    assert torch.equal(a["U"], b["U"])
+
+
+def test_decompose_errors(ctx):
+    from paper_1703_06065_amd import BcurError, binding
+    w = gen.small_case(100, 80, 8, 5, 3, seed=14)
+    A = dev(w.A)
+    om = dev_dense(w.omega)
+    note("decompose errors")
+    bad = w.A.copy()
+    bad[3, 4] = np.nan
+    with pytest.raises(BcurError) as e:
+        ctx.decompose(dev(bad), w.offsets, w.k, w.s, om, w.draws)
+    assert e.value.status == binding.E_NONFINITE
+    with pytest.raises(BcurError) as e:
+        ctx.decompose(A, w.offsets, w.k, w.G + 1, om, gen.draws_u64(w.G + 1, 0))
+    assert e.value.status == binding.E_ARG
+    off = w.offsets.copy()
+    off[2] = off[1]
+    with pytest.raises(BcurError) as e:
+        ctx.decompose(A, off, w.k, w.s, om, w.draws)
+    assert e.value.status == binding.E_ARG
+    with pytest.raises(BcurError) as e:
+        ctx.decompose(A, w.offsets, w.l + 1, w.s, om, w.draws)
+    assert e.value.status == binding.E_ARG
