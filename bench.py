@@ -126,7 +126,7 @@ def main():
                    "l": w.l, "c": c, "refine": 1},
         "tflops_total": round((rf_flops + fit_flops) * args.steps / el / 1e12, 3),
         "stage_ms_per_step": {k: round(v[0] / args.steps, 5) for k, v in stages.items()},
-        "err": res["err"], "rel_err": res["rel_err"],
+        "err": res["err"], "rel_err": res["rel_err"], "rr_sweeps": res["rr_sweeps"],
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

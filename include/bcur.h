@@ -230,7 +230,7 @@ typedef struct bcur_result {
     double rel_err;      /* err / ||A||_F */
     double min_margin;   /* smallest sampling margin over the column draws */
     uint32_t flags;      /* BCUR_FLAG_* */
-    uint32_t reserved;
+    uint32_t rr_sweeps;  /* Jacobi sweeps of the Rayleigh-Ritz eigensolver */
 } bcur_result;
 
 /* One Block CUR decomposition: stages 1-6 above.

@@ -53,7 +53,7 @@ class Result(ctypes.Structure):
                 ("idx_r", ctypes.POINTER(ctypes.c_int64)), ("row_scores", ctypes.POINTER(ctypes.c_double)),
                 ("c", ctypes.c_int64), ("r", ctypes.c_int64), ("frob2", ctypes.c_double), ("err", ctypes.c_double),
                 ("rel_err", ctypes.c_double), ("min_margin", ctypes.c_double), ("flags", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("rr_sweeps", ctypes.c_uint32)]
 
 
 _lib = None
@@ -279,7 +279,8 @@ class Context:
         self._chk(self.lib.bcur_decompose(self.h, p, m, n, lda, _ptr(off, ctypes.c_int64), G, roff_p, Gr,
                                           ctypes.byref(prm), po, _ptr(dr, ctypes.c_uint64), ctypes.byref(res)))
         out = {"idx": idx, "weights": w, "scores": sc, "ritz": ritz, "c": res.c, "r": res.r, "frob2": res.frob2,
-               "err": res.err, "rel_err": res.rel_err, "min_margin": res.min_margin, "flags": res.flags}
+               "err": res.err, "rel_err": res.rel_err, "min_margin": res.min_margin, "flags": res.flags,
+               "rr_sweeps": res.rr_sweeps}
         if U is not None:
             out["U"] = U[:res.c]
         if idx_r is not None:

@@ -236,11 +236,14 @@ bcur_status gemm_timed(bcur_ctx* ctx, int stage, int rstage, const GemmPlan& p, 
     return BCUR_OK;
 }
 
+// One Cholesky QR pass: out = X R^-1 with R^T R = X^T X (+ a tiny shift),
+// Gram in FP64, factor and inverse in FP64, product accumulated in FP64.
 bcur_status cholqr(bcur_ctx* ctx, const RFBufs& b, const float* X, int64_t rows, int64_t l, float* out) {
     const int64_t lp = round4(l);
     const int w = gram_wgs(rows);
-    HIPCHK(launch_gram64(X, rows, l, lp, b.gpart, w, b.T, ctx->stream));
-    HIPCHK(launch_chol_rinv_small(b.T, l, b.Rinv, b.info, ctx->stream));
+    HIPCHK(launch_gram64(X, rows, l, lp, b.gpart, w, ctx->stream));
+    HIPCHK(launch_gram_reduce(b.gpart, w, l, b.T, ctx->stream));
+    HIPCHK(launch_chol_rinv_small(b.T, 1, l, b.Rinv, b.info, ctx->stream));
     HIPCHK(launch_apply_small(X, rows, l, lp, b.Rinv, l, l, out, lp, ctx->stream));
     return BCUR_OK;
 }
@@ -261,15 +264,21 @@ bcur_status range_finder_run(bcur_ctx* ctx, const RFBufs& b, const float* A, int
                          b.part));
         STCHK(gemm_timed(ctx, BCUR_STAGE_RF_ATZ, BCUR_STAGE_RF_REDUCE, py, n, l, m, true, A, lda, b.Z, lp, b.Y, lp,
                          b.part));
+        // Intermediate bases only need to be well conditioned: one Cholesky QR
+        // pass (FP64 Gram and factor) leaves an orthogonality error of about
+        // 2^-52 cond(Y)^2 + 2^-24.  The basis handed to Rayleigh-Ritz gets a
+        // second pass (Cholesky QR2), which brings it to FP32 orthonormality.
         StageScope ts(ctx, BCUR_STAGE_RF_ORTH);
         STCHK(cholqr(ctx, b, b.Y, n, l, b.Q));
-        STCHK(cholqr(ctx, b, b.Q, n, l, b.Q));
+        if (it == q) STCHK(cholqr(ctx, b, b.Q, n, l, b.Q));
     }
     STCHK(gemm_timed(ctx, BCUR_STAGE_RF_AQ, BCUR_STAGE_RF_REDUCE, pz, m, l, n, false, A, lda, b.Q, lp, b.Z, lp,
                      b.part));
     StageScope ts(ctx, BCUR_STAGE_RF_RR);
-    HIPCHK(launch_gram64(b.Z, m, l, lp, b.gpart, gram_wgs(m), b.T, st));
-    HIPCHK(launch_jacobi_eigh(b.T, l, k, b.lam, b.Wk, b.Wks, b.info + 2, st));
+    const int wz = gram_wgs(m);
+    HIPCHK(launch_gram64(b.Z, m, l, lp, b.gpart, wz, st));
+    HIPCHK(launch_gram_reduce(b.gpart, wz, l, b.T, st));
+    HIPCHK(launch_jacobi_eigh(b.T, 1, l, k, b.lam, b.Wk, b.Wks, b.info + 2, st));
     HIPCHK(launch_apply_small(b.Q, n, l, lp, b.Wk, k, k, Vk, k, st));
     if (Uk) HIPCHK(launch_apply_small(b.Z, m, l, lp, b.Wks, k, k, Uk, k, st));
     return BCUR_OK;
@@ -768,6 +777,7 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
     HIPCHK(hipMemcpy(rinfo, rb.info, sizeof rinfo, hipMemcpyDeviceToHost));
     uint32_t fl = fo.flags;
     if (rinfo[0] & 1) fl |= BCUR_FLAG_RANKDEF_Y;
+    res->rr_sweeps = (uint32_t)rinfo[2];
     if (h_st[1]) fl |= BCUR_FLAG_ZERO_SCORE;
     memcpy(res->idx, h_idx, s * sizeof(int64_t));
     if (res->weights) memcpy(res->weights, h_w, s * sizeof(double));

@@ -119,6 +119,8 @@ __device__ __forceinline__ int ceil_log2_i64(int64_t x) {
     return r;
 }
 
+constexpr int kSampleLds = 4096;   // blocks whose weights the sampler keeps in LDS
+
 // Alg. 1 step 2 with exact integer weights (one workgroup of 1024 threads).
 __global__ __launch_bounds__(1024) void k_sample(const double* __restrict__ scores, int64_t G,
                                                  const uint64_t* __restrict__ draws, int64_t s, int replace,
@@ -128,6 +130,8 @@ __global__ __launch_bounds__(1024) void k_sample(const double* __restrict__ scor
     __shared__ uint64_t scan[1024];
     __shared__ double smax[16];
     __shared__ int sbad[16];
+    __shared__ uint64_t lq[kSampleLds], lp[kSampleLds], lr[kSampleLds];
+    __shared__ int ltaken[kSampleLds];
     const int tid = threadIdx.x;
 
     // 1. largest score and validity
@@ -180,16 +184,90 @@ __global__ __launch_bounds__(1024) void k_sample(const double* __restrict__ scor
             scan[tid] += add;
             __syncthreads();
         }
-        if (g < G) pref[g] = carry + scan[tid];
+        if (g < G) {
+            pref[g] = carry + scan[tid];
+            if (G <= kSampleLds) {
+                lq[g] = v;
+                lp[g] = carry + scan[tid];
+            }
+        }
         const uint64_t tot = scan[1023];
         __syncthreads();
         carry += tot;
     }
     __syncthreads();
 
-    // 3. the draws, one after the other
+    // 3. the draws, one after the other.  When the weights fit in LDS every
+    // thread tests its blocks for the unique j with f(j-1) <= x < f(j), where
+    // f(j) = pref[j] - (weight already removed at indices <= j) is kept as an
+    // LDS prefix of removed weight; otherwise thread 0 walks global memory.
+    const uint64_t total = pref[G - 1];
+    if (G <= kSampleLds) {
+        __shared__ uint64_t s_W, s_x, s_removed;
+        __shared__ int64_t s_j;
+        __shared__ int s_zero;
+        for (int64_t g = tid; g < G; g += 1024) {
+            lr[g] = 0;
+            ltaken[g] = 0;
+        }
+        if (tid == 0) {
+            s_removed = 0;
+            s_zero = 0;
+        }
+        __syncthreads();
+        for (int64_t t = 0; t < s; ++t) {
+            if (tid == 0) {
+                const uint64_t W = total - s_removed;
+                s_W = W;
+                s_x = W ? __umul64hi(draws[t], W) : 0;
+                s_j = G;
+            }
+            __syncthreads();
+            const uint64_t W = s_W, x = s_x;
+            if (W == 0) {
+                // every remaining weight is zero: the smallest remaining index
+                for (int64_t g = tid; g < G; g += 1024)
+                    if (!ltaken[g]) atomicMin((unsigned long long*)&s_j, (unsigned long long)g);
+            } else {
+                for (int64_t g = tid; g < G; g += 1024) {
+                    const uint64_t f = lp[g] - lr[g];
+                    const uint64_t fp = g ? lp[g - 1] - lr[g - 1] : 0;
+                    if (f > x && fp <= x) s_j = g;
+                }
+            }
+            __syncthreads();
+            const int64_t j = s_j;
+            if (tid == 0) {
+                double margin = 0.0;
+                if (W != 0) {
+                    const uint64_t fj = lp[j] - lr[j];
+                    const uint64_t lo_edge = fj - lq[j];
+                    const uint64_t a = x - lo_edge, b = fj - 1 - x;
+                    margin = ldexp((double)(a < b ? a : b), -sh);
+                } else {
+                    s_zero = 1;
+                }
+                idx[t] = j;
+                if (margins) margins[t] = margin;
+                if (weights) weights[t] = lq[j] == 0 ? INFINITY : sqrt((double)total / ((double)s * (double)lq[j]));
+                if (!replace) {
+                    s_removed += lq[j];
+                    ltaken[j] = 1;
+                }
+            }
+            if (!replace) {
+                const uint64_t qj = lq[j];
+                for (int64_t g = j + tid; g < G; g += 1024) lr[g] += qj;
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            status[0] = 0;
+            status[1] = s_zero;
+        }
+        return;
+    }
     if (tid == 0) {
-        const uint64_t total = pref[G - 1];
         int zero_drawn = 0;
         for (int64_t t = 0; t < s; ++t) {
             uint64_t removed = 0;
@@ -199,7 +277,6 @@ __global__ __launch_bounds__(1024) void k_sample(const double* __restrict__ scor
             int64_t j;
             double margin = 0.0;
             if (W == 0) {
-                // every remaining weight is zero: the smallest remaining index
                 j = 0;
                 for (;;) {
                     bool taken = false;
@@ -211,7 +288,6 @@ __global__ __launch_bounds__(1024) void k_sample(const double* __restrict__ scor
                 zero_drawn = 1;
             } else {
                 const uint64_t x = __umul64hi(draws[t], W);
-                // smallest j with f(j) = pref[j] - (chosen weight at indices <= j) > x
                 int64_t lo = 0, hi = G - 1;
                 while (lo < hi) {
                     const int64_t mid = lo + ((hi - lo) >> 1);

@@ -5,6 +5,7 @@
 #include <math.h>
 
 #include "bcur_internal.h"
+#include "lds_linalg.h"
 
 namespace bcur {
 namespace {
@@ -112,74 +113,36 @@ __global__ __launch_bounds__(256) void k_maxdiag(const double* __restrict__ G, i
 __global__ __launch_bounds__(256) void k_potrf_diag(double* __restrict__ G, int64_t c, int64_t j0, int w,
                                                     const double* __restrict__ maxdiag, double* __restrict__ Linv,
                                                     double* __restrict__ piv, int* __restrict__ info) {
-    __shared__ double S[NB * NB];
-    __shared__ double X[NB * NB];
+    constexpr int LD = NB + 1;
+    __shared__ double S[NB * LD];
+    __shared__ double base[NB * 8];
+    __shared__ double sq[NB];
     __shared__ int drop[NB];
     const int tid = threadIdx.x;
     const double tau = (double)c * ldexp(1.0, -24) * maxdiag[0];
+    const int wp = pow2_at_least8(w);
     for (int e = tid; e < w * w; e += 256) {
         const int i = e / w, j = e % w;
-        S[e] = G[(j0 + i) * c + (j0 + j)];
+        S[i * LD + j] = G[(j0 + i) * c + (j0 + j)];
     }
-    double pmin = INFINITY, pmax = 0.0;
-    int flag = 0;
-    for (int j = 0; j < w; ++j) {
-        __syncthreads();
-        const double d = S[j * w + j];
-        pmin = fmin(pmin, d);
-        pmax = fmax(pmax, d);
-        const bool dropped = !(d > tau);
-        if (tid == 0) drop[j] = dropped;
-        if (dropped) {
-            flag = 1;
-            continue;
-        }
-        const int ww = w - 1 - j;
-        for (int e = tid; e < ww * ww; e += 256) {
-            const int i = j + 1 + e / ww, p = j + 1 + e % ww;
-            S[i * w + p] -= S[i * w + j] * S[p * w + j] / d;
-        }
-    }
-    __syncthreads();
-    // L[i][j] = S[i][j] / sqrt(d_j), L[j][j] = sqrt(d_j); dropped columns are
-    // zero below a unit diagonal; the upper part is zeroed
+    double pmin, pmax;
+    lds_cholesky(S, LD, w, wp, tau > 0.0 ? tau : 0.0, drop, sq, pmin, pmax);
+    // L back to G (upper part of the block zeroed)
     for (int e = tid; e < w * w; e += 256) {
         const int i = e / w, j = e % w;
-        if (drop[j]) {
-            X[e] = i == j ? 1.0 : 0.0;
-            continue;
-        }
-        const double sd = sqrt(S[j * w + j]);
-        X[e] = i > j ? S[e] / sd : (i == j ? sd : 0.0);
+        G[(j0 + i) * c + (j0 + j)] = j <= i ? S[i * LD + j] : 0.0;
     }
     __syncthreads();
-    for (int e = tid; e < w * w; e += 256) S[e] = X[e];
-    __syncthreads();
-    // L^-1 by forward substitution, one column per thread (into X, lower);
-    // a dropped index has 1/L_jj taken as 0, which zeroes its row of L^-1
-    if (tid < w) {
-        const int cl = tid;
-        for (int i = 0; i < w; ++i) X[i * w + cl] = 0.0;
-        X[cl * w + cl] = drop[cl] ? 0.0 : 1.0 / S[cl * w + cl];
-        for (int i = cl + 1; i < w; ++i) {
-            if (drop[i]) continue;
-            double acc = 0.0;
-            for (int p = cl; p < i; ++p) acc = fma(S[i * w + p], X[p * w + cl], acc);
-            X[i * w + cl] = -acc / S[i * w + i];
-        }
-    }
-    __syncthreads();
-    for (int e = tid; e < w * w; e += 256) {
-        const int i = e / w, j = e % w;
-        G[(j0 + i) * c + (j0 + j)] = S[e];
-    }
+    lds_tri_inverse(S, LD, wp, drop, base);
     for (int e = tid; e < NB * NB; e += 256) {
         const int i = e / NB, j = e % NB;
-        Linv[e] = (i < w && j < w) ? X[i * w + j] : 0.0;
+        Linv[e] = (i < w && j < w && j <= i) ? S[i * LD + j] : 0.0;
     }
     if (tid == 0) {
         piv[0] = pmin;
         piv[1] = pmax;
+        int flag = 0;
+        for (int j = 0; j < w; ++j) flag |= drop[j];
         if (flag) atomicOr(info, 1);
     }
 }
@@ -205,14 +168,24 @@ __global__ __launch_bounds__(256) void k_trtri_step(const double* __restrict__ L
         for (int j = 0; j < 4; ++j) T[(ty + 16 * i) * (NB + 1) + tx + 16 * j] = acc[i][j];
     for (int e = threadIdx.x; e < NB * NB; e += 256) Li[(e / NB) * (NB + 1) + e % NB] = Linv[ib * NB * NB + e];
     __syncthreads();
+    double x[4][4] = {};
+    for (int p = 0; p < NB; ++p) {
+        double a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = Li[(ty + 16 * i) * (NB + 1) + p];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j] = T[p * (NB + 1) + tx + 16 * j];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) x[i][j] = fma(a[i], b[j], x[i][j]);
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            double s = 0.0;
             const int row = ty + 16 * i, col = tx + 16 * j;
-            for (int p = 0; p < NB; ++p) s = fma(Li[row * (NB + 1) + p], T[p * (NB + 1) + col], s);
-            if (row < wi && col < wj) X[(i0 + row) * c + j0 + col] = -s;
+            if (row < wi && col < wj) X[(i0 + row) * c + j0 + col] = -x[i][j];
         }
 }
 
