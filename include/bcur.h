@@ -109,7 +109,8 @@ bcur_status bcur_frob2(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int6
  * then Rayleigh-Ritz: Z = A Q, T = Z^T Z, T = W diag(lam) W^T (float64
  * Jacobi), V_k = Q W[:, :k], Ritz values sqrt(lam).
  * A: device m x n (lda).  omega: device n x l float32, row-major, dense.
- * precision: BCUR_PREC_FP32 or BCUR_PREC_BF16.
+ * precision: BCUR_PREC_FP32, or BCUR_PREC_BF16 (iterations 0 .. q-1 as BF16
+ * sketch passes, iteration q and the Rayleigh-Ritz pass in FP32).
  * Vk: device n x k float32 (leading dimension k), written.
  * Uk: device m x k (leading dimension k) or NULL; when given, receives
  *     Z W[:, :k] diag(1/sqrt(lam_k)), the matching left vectors.
@@ -118,6 +119,15 @@ bcur_status bcur_frob2(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int6
 bcur_status bcur_range_finder(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda,
                               const float* omega, int64_t l, int64_t k, int64_t q, int32_t precision,
                               float* Vk, float* Uk, double* ritz);
+
+/* One sketch pass of the range finder: Y = A^T (A Q), the power step that
+ * multiplies a basis by A^T A.  BCUR_PREC_FP32: FP32 MFMA, FP32 accumulation.
+ * BCUR_PREC_BF16: A and Q rounded to BF16 (nearest even), BF16 MFMA with
+ * FP32 accumulation, A Q rounded to BF16 before the second product.
+ * A: device m x n (lda).  Q: device n x l (ldq).  Y: device n x l (ldy,
+ * multiple of 4), written.  Requires l <= 128.  Synchronous. */
+bcur_status bcur_sketch_pass(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda, const float* Q,
+                             int64_t l, int64_t ldq, int32_t precision, float* Y, int64_t ldy);
 
 /* Block leverage scores l_g = ||V^T E_g||_F^2 (Def. 2): the sum of squares of
  * rows offsets[g] .. offsets[g+1]-1 of V, accumulated in float64.
@@ -187,7 +197,8 @@ enum {
     BCUR_STAGE_FIT_E = 13,    /* E = A - C U with ||E||_F^2 */
     BCUR_STAGE_FIT_F = 14,    /* F = C^T E, main GEMM kernel */
     BCUR_STAGE_FIT_DU = 15,   /* U += Ginv F with <Ginv F, F> */
-    BCUR_NUM_STAGES = 16
+    BCUR_STAGE_RF_CAST = 16,  /* BF16 copies of A and of the sketch panels */
+    BCUR_NUM_STAGES = 17
 };
 
 /* Turn stage timing on (1) or off (0); turning it on clears the totals. */

@@ -28,10 +28,11 @@ SYMBOLS = [
     "bcur_create", "bcur_destroy", "bcur_synchronize", "bcur_status_str", "bcur_last_error",
     "bcur_workspace_bytes", "bcur_frob2", "bcur_range_finder", "bcur_block_scores", "bcur_sample_blocks",
     "bcur_gather_columns", "bcur_fit_columns", "bcur_decompose", "bcur_timing_enable", "bcur_timing_read",
+    "bcur_sketch_pass",
 ]
 
 STAGES = ["frob", "rf_AQ", "rf_AtZ", "rf_reduce", "rf_orth", "rf_rr", "scores", "sample", "gather", "fit_H",
-          "fit_reduce", "fit_inv", "fit_U", "fit_E", "fit_F", "fit_dU"]
+          "fit_reduce", "fit_inv", "fit_U", "fit_E", "fit_F", "fit_dU", "rf_cast"]
 
 
 class BcurError(RuntimeError):
@@ -82,6 +83,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "bcur_sample_blocks": (i32, [vp, P(dbl), i64, P(ctypes.c_uint64), i64, i32, P(i64), P(dbl), P(dbl)]),
         "bcur_gather_columns": (i32, [vp, vp, i64, i64, i64, P(i64), i64, P(i64), i64, vp, i64, P(i64)]),
         "bcur_fit_columns": (i32, [vp, vp, i64, i64, i64, vp, i64, i64, i32, vp, i64, P(dbl), P(u32)]),
+        "bcur_sketch_pass": (i32, [vp, vp, i64, i64, i64, vp, i64, i64, i32, vp, i64]),
         "bcur_timing_enable": (i32, [vp, i32]),
         "bcur_timing_read": (i32, [vp, P(dbl), P(i64)]),
         "bcur_decompose": (i32, [vp, vp, i64, i64, i64, P(i64), i64, P(i64), i64, P(Params), vp,
@@ -196,6 +198,15 @@ class Context:
                                              U.data_ptr() if U is not None else None, _ptr(ritz, ctypes.c_double)))
         return V, U, ritz
 
+    def sketch_pass(self, A, Q, precision: int = PREC_FP32):
+        p, m, n, lda = _check_dev(A, "A")
+        pq, qn, l, ldq = _check_dev(Q, "Q")
+        if qn != n:
+            raise ValueError("Q must have n rows")
+        Y = padded_empty(n, l, A.device)
+        self._chk(self.lib.bcur_sketch_pass(self.h, p, m, n, lda, pq, l, ldq, precision, Y.data_ptr(), Y.stride(0)))
+        return Y
+
     def block_scores(self, V, offsets):
         p, n, k, ldv = _check_dev(V, "V")
         off = _i64(offsets)
@@ -264,25 +275,31 @@ class Context:
         U = None
         if want_u:
             cap = min(s * int(np.max(np.diff(off))), n)
-            U = U_out if U_out is not None else padded_empty(cap, n, A.device)
+            ucols = n
+            if row_offsets is not None and s_r > 0:
+                ucols = min(s_r * int(np.max(np.diff(_i64(row_offsets)))), m)
+            U = U_out if U_out is not None else padded_empty(cap, ucols, A.device)
             res.U = U.data_ptr()
             res.ldu = U.stride(0)
             res.u_rows_cap = U.shape[0]
         roff_p, Gr = None, 0
-        idx_r = None
+        idx_r = rsc = None
         if row_offsets is not None:
             roff = _i64(row_offsets)
             Gr = len(roff) - 1
             roff_p = _ptr(roff, ctypes.c_int64)
             idx_r = np.empty(max(s_r, 1), dtype=np.int64)
+            rsc = np.empty(Gr)
             res.idx_r = _ptr(idx_r, ctypes.c_int64)
+            res.row_scores = _ptr(rsc, ctypes.c_double)
         self._chk(self.lib.bcur_decompose(self.h, p, m, n, lda, _ptr(off, ctypes.c_int64), G, roff_p, Gr,
                                           ctypes.byref(prm), po, _ptr(dr, ctypes.c_uint64), ctypes.byref(res)))
         out = {"idx": idx, "weights": w, "scores": sc, "ritz": ritz, "c": res.c, "r": res.r, "frob2": res.frob2,
                "err": res.err, "rel_err": res.rel_err, "min_margin": res.min_margin, "flags": res.flags,
                "rr_sweeps": res.rr_sweeps}
         if U is not None:
-            out["U"] = U[:res.c]
+            out["U"] = U[:res.c, :res.r] if res.r else U[:res.c]
         if idx_r is not None:
             out["idx_r"] = idx_r[:s_r]
+            out["row_scores"] = rsc
         return out

@@ -192,24 +192,37 @@ std::vector<int64_t> expand_blocks(const int64_t* off, const int64_t* idx, int64
 
 // ---- range finder ---------------------------------------------------------
 
+inline int64_t round8(int64_t x) { return (x + 7) & ~(int64_t)7; }
+
 struct RFBufs {
     float *Q, *Y, *Z, *part;
     double *gpart, *T, *Rinv, *Wk, *Wks, *lam;
     int* info;
+    // BF16 operands (k contiguous): A, A^T, Q^T, Z^T
+    uint16_t *Abf, *AbfT, *QT, *ZT;
 };
 
-size_t rf_partial_floats(int64_t m, int64_t n, int64_t l) {
+size_t rf_partial_floats(int64_t m, int64_t n, int64_t l, bool bf16) {
     const GemmPlan p1 = plan_sgemm(m, l, n, false, true);
     const GemmPlan p2 = plan_sgemm(n, l, m, true, true);
-    return std::max(sgemm_partial_floats(p1, m, l), sgemm_partial_floats(p2, n, l));
+    size_t s = std::max(sgemm_partial_floats(p1, m, l), sgemm_partial_floats(p2, n, l));
+    if (bf16) {
+        const GemmPlan b1 = plan_bgemm(m, l, n), b2 = plan_bgemm(n, l, m);
+        s = std::max(s, std::max(sgemm_partial_floats(b1, m, l), sgemm_partial_floats(b2, n, l)));
+    }
+    return s;
 }
 
-void rf_layout(Arena& a, RFBufs& b, int64_t m, int64_t n, int64_t l, int64_t k) {
+void rf_layout(Arena& a, RFBufs& b, int64_t m, int64_t n, int64_t l, int64_t k, bool bf16 = false) {
     const int64_t lp = round4(l);
     b.Q = a.take<float>(n * lp);
     b.Y = a.take<float>(n * lp);
     b.Z = a.take<float>(m * lp);
-    b.part = a.take<float>(std::max<size_t>(rf_partial_floats(m, n, l), 4));
+    b.part = a.take<float>(std::max<size_t>(rf_partial_floats(m, n, l, bf16), 4));
+    b.Abf = bf16 ? a.take<uint16_t>(m * round8(n)) : nullptr;
+    b.AbfT = bf16 ? a.take<uint16_t>(n * round8(m)) : nullptr;
+    b.QT = bf16 ? a.take<uint16_t>(l * round8(n)) : nullptr;
+    b.ZT = bf16 ? a.take<uint16_t>(l * round8(m)) : nullptr;
     const int w = std::max(gram_wgs(n), gram_wgs(m));
     b.gpart = a.take<double>((size_t)w * l * l);
     b.T = a.take<double>(l * l);
@@ -250,8 +263,51 @@ bcur_status cholqr(bcur_ctx* ctx, const RFBufs& b, const float* X, int64_t rows,
 
 // Q <- omega; q+1 times Q <- orth(A^T (A Q)); Rayleigh-Ritz.  Vk (n x k, ld k),
 // Uk (m x k, ld k) if non-null, lam (device, l).
+// Y = A^T (A Q) in BF16: Z = A_bf Q_bf, Y = A_bf^T Z_bf (FP32 accumulation).
+// The BF16 copies of A must already be in b.Abf / b.AbfT.
+bcur_status sketch_pass_bf16(bcur_ctx* ctx, const RFBufs& b, int64_t m, int64_t n, const float* Q, int64_t ldq,
+                             int64_t l, float* Y) {
+    hipStream_t st = ctx->stream;
+    const int64_t lp = round4(l);
+    const GemmPlan pz = plan_bgemm(m, l, n), py = plan_bgemm(n, l, m);
+    {
+        StageScope ts(ctx, BCUR_STAGE_RF_CAST);
+        HIPCHK(launch_cast_bf16_both(Q, n, l, ldq, nullptr, 0, b.QT, round8(n), st));
+    }
+    {
+        StageScope ts(ctx, BCUR_STAGE_RF_AQ);
+        HIPCHK(launch_bgemm_nt(pz, m, l, n, b.Abf, round8(n), b.QT, round8(n), b.Z, lp, b.part, st));
+    }
+    if (pz.splits > 1) {
+        StageScope ts(ctx, BCUR_STAGE_RF_REDUCE);
+        HIPCHK(launch_splitk_reduce(pz, m, l, b.part, b.Z, lp, st));
+    }
+    {
+        StageScope ts(ctx, BCUR_STAGE_RF_CAST);
+        HIPCHK(launch_cast_bf16_both(b.Z, m, l, lp, nullptr, 0, b.ZT, round8(m), st));
+    }
+    {
+        StageScope ts(ctx, BCUR_STAGE_RF_ATZ);
+        HIPCHK(launch_bgemm_nt(py, n, l, m, b.AbfT, round8(m), b.ZT, round8(m), Y, lp, b.part, st));
+    }
+    if (py.splits > 1) {
+        StageScope ts(ctx, BCUR_STAGE_RF_REDUCE);
+        HIPCHK(launch_splitk_reduce(py, n, l, b.part, Y, lp, st));
+    }
+    return BCUR_OK;
+}
+
+bcur_status cast_a_bf16(bcur_ctx* ctx, const RFBufs& b, const float* A, int64_t m, int64_t n, int64_t lda) {
+    StageScope ts(ctx, BCUR_STAGE_RF_CAST);
+    HIPCHK(launch_cast_bf16_both(A, m, n, lda, b.Abf, round8(n), b.AbfT, round8(m), ctx->stream));
+    return BCUR_OK;
+}
+
+// precision BCUR_PREC_BF16: iterations 0 .. q-1 in BF16, iteration q and the
+// Rayleigh-Ritz pass in FP32 (the final FP32 power pass).
 bcur_status range_finder_run(bcur_ctx* ctx, const RFBufs& b, const float* A, int64_t m, int64_t n, int64_t lda,
-                             const float* omega, int64_t l, int64_t k, int64_t q, float* Vk, float* Uk) {
+                             const float* omega, int64_t l, int64_t k, int64_t q, float* Vk, float* Uk,
+                             int precision = BCUR_PREC_FP32) {
     hipStream_t st = ctx->stream;
     const int64_t lp = round4(l);
     HIPCHK(hipMemsetAsync(b.info, 0, 4 * sizeof(int), st));
@@ -259,11 +315,17 @@ bcur_status range_finder_run(bcur_ctx* ctx, const RFBufs& b, const float* A, int
                             hipMemcpyDeviceToDevice, st));
     const GemmPlan pz = plan_sgemm(m, l, n, false, true);
     const GemmPlan py = plan_sgemm(n, l, m, true, true);
+    const bool bf16 = precision == BCUR_PREC_BF16 && q > 0;
+    if (bf16) STCHK(cast_a_bf16(ctx, b, A, m, n, lda));
     for (int64_t it = 0; it <= q; ++it) {
-        STCHK(gemm_timed(ctx, BCUR_STAGE_RF_AQ, BCUR_STAGE_RF_REDUCE, pz, m, l, n, false, A, lda, b.Q, lp, b.Z, lp,
-                         b.part));
-        STCHK(gemm_timed(ctx, BCUR_STAGE_RF_ATZ, BCUR_STAGE_RF_REDUCE, py, n, l, m, true, A, lda, b.Z, lp, b.Y, lp,
-                         b.part));
+        if (bf16 && it < q) {
+            STCHK(sketch_pass_bf16(ctx, b, m, n, b.Q, lp, l, b.Y));
+        } else {
+            STCHK(gemm_timed(ctx, BCUR_STAGE_RF_AQ, BCUR_STAGE_RF_REDUCE, pz, m, l, n, false, A, lda, b.Q, lp, b.Z,
+                             lp, b.part));
+            STCHK(gemm_timed(ctx, BCUR_STAGE_RF_ATZ, BCUR_STAGE_RF_REDUCE, py, n, l, m, true, A, lda, b.Z, lp, b.Y,
+                             lp, b.part));
+        }
         // Intermediate bases only need to be well conditioned: one Cholesky QR
         // pass (FP64 Gram and factor) leaves an orthogonality error of about
         // 2^-52 cond(Y)^2 + 2^-24.  The basis handed to Rayleigh-Ritz gets a
@@ -340,7 +402,7 @@ bcur_status fit_run(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t m, 
                                 0, nullptr, st));
             HIPCHK(launch_gram_from_cols(b.Gtmp, cp, d_ident, c, b.G, st));
         }
-        HIPCHK(launch_spd_inverse(b.G, c, b.Ginv, b.spdws, b.info, b.piv, st));
+        HIPCHK(launch_spd_inverse(b.G, c, b.Ginv, b.spdws, b.info, b.piv, ldexp(1.0, -24), st));
         HIPCHK(launch_f64_to_f32_2d(b.Ginv, c, c, c, b.Ginv32, cp, st));
     }
     const GemmPlan pu = plan_sgemm(c, n, c, false, false);
@@ -388,6 +450,97 @@ bcur_status fit_collect(bcur_ctx* ctx, const FitBufs& b, int64_t c, FitOut* out)
     if (pmin > 0.0 && pmax / pmin * ldexp(1.0, -24) > 0.1) fl |= BCUR_FLAG_ILLCOND_C;
     out->err2 = std::max(hv[0], 0.0);
     out->flags = fl;
+    return BCUR_OK;
+}
+
+
+// ---- row-block variant: U = C^+ A R^+ -------------------------------------
+
+struct CurBufs {
+    float *R, *W32, *E;
+    double *Gc, *Gr, *Grinv, *B, *X, *Q1, *L1, *H2, *T1, *U0, *Wd, *spc, *spr, *wsE, *errv, *pivc, *pivr;
+    int* info;
+};
+
+void cur_layout(Arena& a, CurBufs& b, int64_t m, int64_t n, int64_t c, int64_t r) {
+    b.R = a.take<float>(r * round4(n));
+    b.W32 = a.take<float>(m * round4(r));
+    b.E = a.take<float>(m * round4(n));
+    b.Gc = a.take<double>(c * c);
+    b.Gr = a.take<double>(r * r);
+    b.Grinv = a.take<double>(r * r);
+    b.B = a.take<double>(m * r);
+    b.X = a.take<double>(m * r);
+    b.Q1 = a.take<double>(m * c);
+    b.L1 = a.take<double>(c * c);
+    b.H2 = a.take<double>(c * r);
+    b.T1 = a.take<double>(c * r);
+    b.U0 = a.take<double>(c * r);
+    b.Wd = a.take<double>(m * r);
+    b.spc = a.take<double>(spd_inverse_ws_doubles(c));
+    b.spr = a.take<double>(spd_inverse_ws_doubles(r));
+    b.wsE = a.take<double>(((m + 127) / 128) * ((n + 127) / 128));
+    b.errv = a.take<double>(4);
+    b.pivc = a.take<double>(2 * ((c + 63) / 64));
+    b.pivr = a.take<double>(2 * ((r + 63) / 64));
+    b.info = a.take<int>(4);
+}
+
+// U = C^+ A R^+ and err^2 = ||A - C U R||_F^2 (in b.errv[0] after a sync).
+// FP64 arithmetic on the FP32 data (products of FP32 values are exact in
+// FP64) for the c- and r-sized pieces:
+//   R side (normal equations): G_r = R R^T, B = A R^T, X = B G_r^-1 = A R^+;
+//   C side (Cholesky QR2): C = Q R_C with R_C = (L_2^T)(L_1^T), from
+//   G_c = C^T C = L_1 L_1^T, Q_1 = C L_1^-T, Q_1^T Q_1 = L_2 L_2^T, Q = Q_1 L_2^-T,
+//   so C C^+ X = Q (Q^T X) and U = L_1^-T L_2^-T (Q^T X).
+// Cholesky QR2 keeps the projection accurate for cond(C) up to about 1e7,
+// where the normal equations of C would lose cond(C)^2 u.  The residual
+// A - (C U) R is one FP32 MFMA GEMM with the fused squared-norm epilogue.
+bcur_status fit_cur_run(bcur_ctx* ctx, const CurBufs& b, const float* A, int64_t m, int64_t n, int64_t lda,
+                        const float* C, int64_t c, int64_t ldc, int64_t r, float* U, int64_t ldu) {
+    hipStream_t st = ctx->stream;
+    const int64_t ldr = round4(n), rp = round4(r);
+    const double rel64 = ldexp(1.0, -50);
+    HIPCHK(hipMemsetAsync(b.info, 0, 4 * sizeof(int), st));
+    double *L1inv = nullptr, *L2inv = nullptr;
+    {
+        StageScope ts(ctx, BCUR_STAGE_FIT_H);
+        HIPCHK(launch_dgemm_ff(r, r, n, 1.0, b.R, ldr, false, b.R, ldr, true, 0.0, b.Gr, r, st));
+        HIPCHK(launch_dgemm_ff(m, r, n, 1.0, A, lda, false, b.R, ldr, true, 0.0, b.B, r, st));
+        HIPCHK(launch_dgemm_ff(c, c, m, 1.0, C, ldc, true, C, ldc, false, 0.0, b.Gc, c, st));
+    }
+    {
+        StageScope ts(ctx, BCUR_STAGE_FIT_INV);
+        HIPCHK(launch_spd_inverse(b.Gr, r, b.Grinv, b.spr, b.info + 1, b.pivr, rel64, st));
+        HIPCHK(launch_chol_linv(b.Gc, c, b.spc, b.info, b.pivc, rel64, &L1inv, st));
+        // L1^-1 leaves the factorization workspace, which the second pass reuses
+        HIPCHK(hipMemcpyAsync(b.L1, L1inv, c * c * sizeof(double), hipMemcpyDeviceToDevice, st));
+        L1inv = b.L1;
+        // Q1 = C L1^-T and its Gram (into G_c's storage); L2^-1 (Q = Q1 L2^-T is never formed)
+        HIPCHK(launch_dgemm_fd(m, c, c, 1.0, C, ldc, false, L1inv, c, true, 0.0, b.Q1, c, st));
+        HIPCHK(launch_dgemm(c, c, m, 1.0, b.Q1, c, true, b.Q1, c, false, 0.0, b.Gc, c, st));
+        HIPCHK(launch_chol_linv(b.Gc, c, b.spc, b.info + 2, nullptr, rel64, &L2inv, st));
+    }
+    {
+        StageScope ts(ctx, BCUR_STAGE_FIT_U);
+        // X = A R^+
+        HIPCHK(launch_dgemm(m, r, r, 1.0, b.B, r, false, b.Grinv, r, false, 0.0, b.X, r, st));
+        // T1 = Q1^T X, H2 = L2^-1 T1 = Q^T X
+        HIPCHK(launch_dgemm(c, r, m, 1.0, b.Q1, c, true, b.X, r, false, 0.0, b.T1, r, st));
+        HIPCHK(launch_dgemm(c, r, c, 1.0, L2inv, c, false, b.T1, r, false, 0.0, b.H2, r, st));
+        // U = L1^-T L2^-T H2
+        HIPCHK(launch_dgemm(c, r, c, 1.0, L2inv, c, true, b.H2, r, false, 0.0, b.T1, r, st));
+        HIPCHK(launch_dgemm(c, r, c, 1.0, L1inv, c, true, b.T1, r, false, 0.0, b.U0, r, st));
+        // W = C U = Q1 (L2^-T H2) = Q1 T1
+        HIPCHK(launch_dgemm(m, r, c, 1.0, b.Q1, c, false, b.T1, r, false, 0.0, b.Wd, r, st));
+        HIPCHK(launch_f64_to_f32_2d(b.Wd, m, r, r, b.W32, rp, st));
+        if (U) HIPCHK(launch_f64_to_f32_2d(b.U0, c, r, r, U, ldu, st));
+    }
+    const GemmPlan pe = plan_sgemm(m, n, r, false, false);
+    STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_E, BCUR_STAGE_FIT_REDUCE, pe, m, n, r, false, b.W32, rp, b.R, ldr, b.E,
+                     round4(n), nullptr, EPI_RESID, A, lda, nullptr, 0, b.wsE));
+    const int64_t nwsE = ((m + 127) / 128) * ((n + 127) / 128);
+    HIPCHK(launch_fit_err(b.wsE, nwsE, b.wsE, 0, b.errv, st));
     return BCUR_OK;
 }
 
@@ -505,15 +658,17 @@ bcur_status bcur_range_finder(bcur_ctx* ctx, const float* A, int64_t m, int64_t 
     if (k < 1 || l < k || l > std::min(std::min(m, n), kMaxSketch))
         return fail(ctx, BCUR_E_ARG, "need 1 <= k <= l <= min(m, n, %lld)", (long long)kMaxSketch);
     if (q < 0 || q > 64) return fail(ctx, BCUR_E_ARG, "q out of range");
-    if (precision != BCUR_PREC_FP32) return fail(ctx, BCUR_E_ARG, "precision %d not available", precision);
+    if (precision != BCUR_PREC_FP32 && precision != BCUR_PREC_BF16)
+        return fail(ctx, BCUR_E_ARG, "unknown precision %d", precision);
     HIPCHK(hipSetDevice(ctx->device));
+    const bool bf16 = precision == BCUR_PREC_BF16;
     Arena a;
     RFBufs b;
-    rf_layout(a, b, m, n, l, k);
+    rf_layout(a, b, m, n, l, k, bf16);
     STCHK(reserve(ctx, a.off));
     Arena r{ctx->ws, 0};
-    rf_layout(r, b, m, n, l, k);
-    STCHK(range_finder_run(ctx, b, A, m, n, lda, omega, l, k, q, Vk, Uk));
+    rf_layout(r, b, m, n, l, k, bf16);
+    STCHK(range_finder_run(ctx, b, A, m, n, lda, omega, l, k, q, Vk, Uk, precision));
     if (ritz) {
         STCHK(reserve_pinned(ctx, l * sizeof(double)));
         HIPCHK(hipMemcpyAsync(ctx->pinned, b.lam, l * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
@@ -521,6 +676,43 @@ bcur_status bcur_range_finder(bcur_ctx* ctx, const float* A, int64_t m, int64_t 
         const double* lam = reinterpret_cast<const double*>(ctx->pinned);
         for (int64_t i = 0; i < l; ++i) ritz[i] = lam[i] > 0.0 ? sqrt(lam[i]) : 0.0;
     }
+    return BCUR_OK;
+}
+
+bcur_status bcur_sketch_pass(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda, const float* Q,
+                             int64_t l, int64_t ldq, int32_t precision, float* Y, int64_t ldy) {
+    if (!ctx) return BCUR_E_ARG;
+    STCHK(check_matrix(ctx, A, m, n, lda, "A"));
+    STCHK(check_matrix(ctx, Q, n, l, ldq, "Q"));
+    if (!Y || ldy < l || (ldy & 3) || !aligned16(Y)) return fail(ctx, BCUR_E_ARG, "Y: bad pointer or leading dimension");
+    if (l > 128) return fail(ctx, BCUR_E_ARG, "l must be <= 128");
+    if (precision != BCUR_PREC_FP32 && precision != BCUR_PREC_BF16)
+        return fail(ctx, BCUR_E_ARG, "unknown precision %d", precision);
+    HIPCHK(hipSetDevice(ctx->device));
+    const bool bf16 = precision == BCUR_PREC_BF16;
+    Arena a;
+    RFBufs b;
+    rf_layout(a, b, m, n, l, l, bf16);
+    STCHK(reserve(ctx, a.off));
+    Arena r{ctx->ws, 0};
+    rf_layout(r, b, m, n, l, l, bf16);
+    const int64_t lp = round4(l);
+    HIPCHK(hipMemcpy2DAsync(b.Q, lp * sizeof(float), Q, ldq * sizeof(float), l * sizeof(float), n,
+                            hipMemcpyDeviceToDevice, ctx->stream));
+    if (bf16) {
+        STCHK(cast_a_bf16(ctx, b, A, m, n, lda));
+        STCHK(sketch_pass_bf16(ctx, b, m, n, b.Q, lp, l, b.Y));
+    } else {
+        const GemmPlan pz = plan_sgemm(m, l, n, false, true);
+        const GemmPlan py = plan_sgemm(n, l, m, true, true);
+        STCHK(gemm_timed(ctx, BCUR_STAGE_RF_AQ, BCUR_STAGE_RF_REDUCE, pz, m, l, n, false, A, lda, b.Q, lp, b.Z, lp,
+                         b.part));
+        STCHK(gemm_timed(ctx, BCUR_STAGE_RF_ATZ, BCUR_STAGE_RF_REDUCE, py, n, l, m, true, A, lda, b.Z, lp, b.Y, lp,
+                         b.part));
+    }
+    HIPCHK(hipMemcpy2DAsync(Y, ldy * sizeof(float), b.Y, lp * sizeof(float), l * sizeof(float), n,
+                            hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
     return BCUR_OK;
 }
 
@@ -643,6 +835,27 @@ bcur_status bcur_fit_columns(bcur_ctx* ctx, const float* A, int64_t m, int64_t n
     return BCUR_OK;
 }
 
+// Sampling buffers for one side (columns or rows).
+struct SampleBufs {
+    int64_t *off, *idx, *list;
+    double *sc, *w, *mg;
+    uint64_t *dr, *qb, *pr;
+    int* st;
+};
+
+void sample_layout(Arena& a, SampleBufs& b, int64_t G, int64_t s, int64_t listmax) {
+    b.off = a.take<int64_t>(G + 1);
+    b.sc = a.take<double>(G);
+    b.dr = a.take<uint64_t>(s);
+    b.qb = a.take<uint64_t>(G);
+    b.pr = a.take<uint64_t>(G);
+    b.idx = a.take<int64_t>(s);
+    b.w = a.take<double>(s);
+    b.mg = a.take<double>(s);
+    b.st = a.take<int>(4);
+    b.list = a.take<int64_t>(std::max<int64_t>(listmax, 1));
+}
+
 bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda, const int64_t* col_off,
                            int64_t G, const int64_t* row_off, int64_t Gr, const bcur_params* p, const float* omega,
                            const uint64_t* draws, bcur_result* res) {
@@ -655,144 +868,204 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
         return fail(ctx, BCUR_E_ARG, "need 1 <= k <= l <= min(m, n, %lld)", (long long)kMaxSketch);
     if (q < 0 || q > 64) return fail(ctx, BCUR_E_ARG, "q out of range");
     if (s < 1 || (!p->replace && s > G)) return fail(ctx, BCUR_E_ARG, "need 1 <= s <= G without replacement");
-    if (p->precision != BCUR_PREC_FP32) return fail(ctx, BCUR_E_ARG, "precision %d not available", p->precision);
+    if (p->precision != BCUR_PREC_FP32 && p->precision != BCUR_PREC_BF16)
+        return fail(ctx, BCUR_E_ARG, "unknown precision %d", p->precision);
+    const bool bf16 = p->precision == BCUR_PREC_BF16;
     if (p->refine < 0 || p->refine > 1) return fail(ctx, BCUR_E_ARG, "refine must be 0 or 1");
     const bool rowv = row_off != nullptr && p->s_r > 0;
+    const int64_t s_r = rowv ? p->s_r : 0;
     if (rowv) {
         STCHK(check_offsets(ctx, row_off, Gr, m, "row_off"));
-        if (!p->replace && p->s_r > Gr) return fail(ctx, BCUR_E_ARG, "s_r > Gr without replacement");
-        return fail(ctx, BCUR_E_ARG, "row-block variant not available");
+        if (!p->replace && s_r > Gr) return fail(ctx, BCUR_E_ARG, "s_r > Gr without replacement");
+        if (!res->idx_r) return fail(ctx, BCUR_E_ARG, "idx_r is required for the row-block variant");
     }
-    int64_t maxw = 0;
+    int64_t maxw = 0, maxh = 0;
     for (int64_t g = 0; g < G; ++g) maxw = std::max(maxw, col_off[g + 1] - col_off[g]);
+    if (rowv)
+        for (int64_t g = 0; g < Gr; ++g) maxh = std::max(maxh, row_off[g + 1] - row_off[g]);
     const int64_t cmax = std::min(s * maxw, n);
-    if (res->U && (res->ldu < n || (res->ldu & 3) || !aligned16(res->U) || res->u_rows_cap < cmax))
-        return fail(ctx, BCUR_E_ARG, "U needs ldu >= n (multiple of 4, 16-byte aligned) and %lld rows", (long long)cmax);
+    const int64_t rmax = rowv ? std::min(s_r * maxh, m) : 0;
+    const int64_t ucols = rowv ? rmax : n;
+    if (res->U && (res->ldu < ucols || (res->ldu & 3) || !aligned16(res->U) || res->u_rows_cap < cmax))
+        return fail(ctx, BCUR_E_ARG, "U needs ldu >= %lld (a multiple of 4, 16-byte aligned) and %lld rows",
+                    (long long)ucols, (long long)cmax);
     HIPCHK(hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
 
-    // workspace: range finder | scores and sampling | fit (sized for cmax)
-    auto layout = [&](Arena& a, RFBufs& rb, FitBufs& fb, int64_t*& d_off, double*& d_sc, uint64_t*& d_dr, uint64_t*& qb,
-                      uint64_t*& pr, int64_t*& d_idx, double*& d_w, double*& d_mg, int*& d_st, double*& d_frob,
-                      double*& d_fpart, float*& Vk, float*& Cbuf, int64_t*& d_cols, float*& Ubuf) {
-        rf_layout(a, rb, m, n, l, k);
-        d_off = a.take<int64_t>(G + 1);
-        d_sc = a.take<double>(G);
-        d_dr = a.take<uint64_t>(s);
-        qb = a.take<uint64_t>(G);
-        pr = a.take<uint64_t>(G);
-        d_idx = a.take<int64_t>(s);
-        d_w = a.take<double>(s);
-        d_mg = a.take<double>(s);
-        d_st = a.take<int>(4);
+    // workspace: range finder | sampling (columns, rows) | C, V_k, U_k | fit
+    RFBufs rb;
+    FitBufs fb;
+    CurBufs cb;
+    SampleBufs sc, sr;
+    double *d_frob, *d_fpart;
+    float *Vk, *Uk, *Cbuf, *Ubuf;
+    auto layout = [&](Arena& a) {
+        rf_layout(a, rb, m, n, l, k, bf16);
+        sample_layout(a, sc, G, s, cmax);
+        if (rowv) sample_layout(a, sr, Gr, s_r, rmax);
         d_frob = a.take<double>(2);
         d_fpart = a.take<double>(frob2_grid(m, n));
         Vk = a.take<float>(n * k);
+        Uk = rowv ? a.take<float>(m * k) : nullptr;
         Cbuf = a.take<float>(m * round4(cmax));
-        d_cols = a.take<int64_t>(cmax);
-        Ubuf = a.take<float>(cmax * round4(n));
-        fit_layout(a, fb, m, n, cmax, false);
+        Ubuf = res->U ? nullptr : a.take<float>(cmax * round4(ucols));
+        if (rowv) cur_layout(a, cb, m, n, cmax, rmax);
+        else fit_layout(a, fb, m, n, cmax, false);
     };
-    RFBufs rb;
-    FitBufs fb;
-    int64_t *d_off, *d_idx, *d_cols;
-    double *d_sc, *d_w, *d_mg, *d_frob, *d_fpart;
-    uint64_t *d_dr, *qb, *pr;
-    int* d_st;
-    float *Vk, *Cbuf, *Ubuf;
     {
         Arena a;
-        layout(a, rb, fb, d_off, d_sc, d_dr, qb, pr, d_idx, d_w, d_mg, d_st, d_frob, d_fpart, Vk, Cbuf, d_cols, Ubuf);
+        layout(a);
         STCHK(reserve(ctx, a.off));
         Arena b{ctx->ws, 0};
-        layout(b, rb, fb, d_off, d_sc, d_dr, qb, pr, d_idx, d_w, d_mg, d_st, d_frob, d_fpart, Vk, Cbuf, d_cols, Ubuf);
+        layout(b);
     }
-    // staging layout: offsets | draws | frob2 (2) | status (4 ints) | idx | weights | margins | scores | lam | cols
-    const size_t pin_need = 8 * (G + 1) + 8 * s + 16 + 16 + 24 * s + 8 * G + 8 * l + 8 * cmax + 64;
+    // pinned staging: offsets | draws | frob2 | status | idx, w, mg | scores | lam | list
+    // (for the rows the same again after the columns)
+    auto side_bytes = [](int64_t g, int64_t ss, int64_t lm) { return 8 * (g + 1) + 8 * ss + 16 + 24 * ss + 8 * g + 8 * lm; };
+    const size_t pin_need = side_bytes(G, s, cmax) + (rowv ? side_bytes(Gr, s_r, rmax) : 0) + 16 + 8 * l + 64;
     STCHK(reserve_pinned(ctx, pin_need));
     HIPCHK(hipStreamSynchronize(st));
     char* pin = ctx->pinned;
-    int64_t* h_off = reinterpret_cast<int64_t*>(pin);
-    uint64_t* h_dr = reinterpret_cast<uint64_t*>(h_off + G + 1);
+    auto ptake = [&pin](size_t bytes) {
+        char* p0 = pin;
+        pin += (bytes + 7) & ~(size_t)7;
+        return p0;
+    };
+    int64_t* h_off = reinterpret_cast<int64_t*>(ptake(8 * (G + 1)));
+    uint64_t* h_dr = reinterpret_cast<uint64_t*>(ptake(8 * s));
     memcpy(h_off, col_off, (G + 1) * sizeof(int64_t));
     memcpy(h_dr, draws, s * sizeof(uint64_t));
-    HIPCHK(hipMemcpyAsync(d_off, h_off, (G + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(d_dr, h_dr, s * sizeof(uint64_t), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemsetAsync(d_st, 0, 4 * sizeof(int), st));
+    HIPCHK(hipMemcpyAsync(sc.off, h_off, (G + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(sc.dr, h_dr, s * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(sc.st, 0, 4 * sizeof(int), st));
+    int64_t* h_roff = nullptr;
+    if (rowv) {
+        h_roff = reinterpret_cast<int64_t*>(ptake(8 * (Gr + 1)));
+        uint64_t* h_drr = reinterpret_cast<uint64_t*>(ptake(8 * s_r));
+        memcpy(h_roff, row_off, (Gr + 1) * sizeof(int64_t));
+        memcpy(h_drr, draws + s, s_r * sizeof(uint64_t));
+        HIPCHK(hipMemcpyAsync(sr.off, h_roff, (Gr + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(sr.dr, h_drr, s_r * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemsetAsync(sr.st, 0, 4 * sizeof(int), st));
+    }
 
     // 1. ||A||_F^2
     {
         StageScope ts(ctx, BCUR_STAGE_FROB);
         HIPCHK(launch_frob2(A, m, n, lda, d_fpart, frob2_grid(m, n), d_frob, st));
     }
-    // 2. sketched top-k right subspace
-    STCHK(range_finder_run(ctx, rb, A, m, n, lda, omega, l, k, q, Vk, nullptr));
+    // 2. sketched top-k right subspace (and left vectors for the row blocks)
+    STCHK(range_finder_run(ctx, rb, A, m, n, lda, omega, l, k, q, Vk, Uk, p->precision));
     // 3. block scores, 4. sampling
     {
         StageScope ts(ctx, BCUR_STAGE_SCORES);
-        HIPCHK(launch_block_scores(Vk, k, k, d_off, G, d_sc, st));
+        HIPCHK(launch_block_scores(Vk, k, k, sc.off, G, sc.sc, st));
+        if (rowv) HIPCHK(launch_block_scores(Uk, k, k, sr.off, Gr, sr.sc, st));
     }
     {
         StageScope ts(ctx, BCUR_STAGE_SAMPLE);
-        HIPCHK(launch_sample(d_sc, G, d_dr, s, p->replace, qb, pr, d_idx, d_w, d_mg, d_st, st));
+        HIPCHK(launch_sample(sc.sc, G, sc.dr, s, p->replace, sc.qb, sc.pr, sc.idx, sc.w, sc.mg, sc.st, st));
+        if (rowv)
+            HIPCHK(launch_sample(sr.sc, Gr, sr.dr, s_r, p->replace, sr.qb, sr.pr, sr.idx, sr.w, sr.mg, sr.st, st));
     }
-    // results needed on the host to lay out C
-    double* h_frob = reinterpret_cast<double*>(h_dr + s);
-    int* h_st = reinterpret_cast<int*>(h_frob + 2);
-    int64_t* h_idx = reinterpret_cast<int64_t*>(h_st + 4);
-    double* h_w = reinterpret_cast<double*>(h_idx + s);
-    double* h_mg = h_w + s;
-    double* h_sc = h_mg + s;
-    double* h_lam = h_sc + G;
-    int64_t* h_cols = reinterpret_cast<int64_t*>(h_lam + l);
+    // results needed on the host to lay out C (and R)
+    struct HostSide {
+        int* st;
+        int64_t* idx;
+        double *w, *mg, *sc;
+        int64_t* list;
+    };
+    auto stage_side = [&](const SampleBufs& b, int64_t g, int64_t ss, int64_t lm, HostSide& h) -> bcur_status {
+        h.st = reinterpret_cast<int*>(ptake(16));
+        h.idx = reinterpret_cast<int64_t*>(ptake(8 * ss));
+        h.w = reinterpret_cast<double*>(ptake(8 * ss));
+        h.mg = reinterpret_cast<double*>(ptake(8 * ss));
+        h.sc = reinterpret_cast<double*>(ptake(8 * g));
+        h.list = reinterpret_cast<int64_t*>(ptake(8 * std::max<int64_t>(lm, 1)));
+        HIPCHK(hipMemcpyAsync(h.st, b.st, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(h.idx, b.idx, ss * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(h.w, b.w, ss * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(h.mg, b.mg, ss * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(h.sc, b.sc, g * sizeof(double), hipMemcpyDeviceToHost, st));
+        return BCUR_OK;
+    };
+    double* h_frob = reinterpret_cast<double*>(ptake(16));
+    double* h_lam = reinterpret_cast<double*>(ptake(8 * l));
+    HostSide hc{}, hr{};
+    STCHK(stage_side(sc, G, s, cmax, hc));
+    if (rowv) STCHK(stage_side(sr, Gr, s_r, rmax, hr));
     HIPCHK(hipMemcpyAsync(h_frob, d_frob, sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(h_st, d_st, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(h_idx, d_idx, s * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(h_w, d_w, s * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(h_mg, d_mg, s * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(h_sc, d_sc, G * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(h_lam, rb.lam, l * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (!isfinite(h_frob[0])) return fail(ctx, BCUR_E_NONFINITE, "A holds NaN or Inf");
-    if (h_st[0] != 0) return fail(ctx, BCUR_E_HIP, "block scores are not finite");
+    if (hc.st[0] != 0 || (rowv && hr.st[0] != 0)) return fail(ctx, BCUR_E_HIP, "block scores are not finite");
     for (int64_t t = 0; t < s; ++t)
-        if (h_idx[t] < 0 || h_idx[t] >= G) return fail(ctx, BCUR_E_HIP, "sampler returned an invalid block");
-    const std::vector<int64_t> cols = expand_blocks(col_off, h_idx, s);
+        if (hc.idx[t] < 0 || hc.idx[t] >= G) return fail(ctx, BCUR_E_HIP, "sampler returned an invalid block");
+    for (int64_t t = 0; t < s_r; ++t)
+        if (hr.idx[t] < 0 || hr.idx[t] >= Gr) return fail(ctx, BCUR_E_HIP, "sampler returned an invalid row block");
+    const std::vector<int64_t> cols = expand_blocks(col_off, hc.idx, s);
     const int64_t c = (int64_t)cols.size();
-    memcpy(h_cols, cols.data(), c * sizeof(int64_t));
-    HIPCHK(hipMemcpyAsync(d_cols, h_cols, c * sizeof(int64_t), hipMemcpyHostToDevice, st));
-    // 5. C = A S (unscaled)
+    memcpy(hc.list, cols.data(), c * sizeof(int64_t));
+    HIPCHK(hipMemcpyAsync(sc.list, hc.list, c * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    int64_t r = 0;
+    if (rowv) {
+        const std::vector<int64_t> rows = expand_blocks(row_off, hr.idx, s_r);
+        r = (int64_t)rows.size();
+        memcpy(hr.list, rows.data(), r * sizeof(int64_t));
+        HIPCHK(hipMemcpyAsync(sr.list, hr.list, r * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    }
+    // 5. C = A S (unscaled) and R = S_R^T A
     const int64_t ldc = round4(c);
     {
         StageScope ts(ctx, BCUR_STAGE_GATHER);
-        HIPCHK(launch_gather_cols(A, lda, m, d_cols, c, Cbuf, ldc, st));
+        HIPCHK(launch_gather_cols(A, lda, m, sc.list, c, Cbuf, ldc, st));
+        if (rowv) HIPCHK(launch_gather_rows(A, lda, n, sr.list, r, cb.R, round4(n), st));
     }
-    // 6. U = C^+ A and the residual
+    // 6. U and the residual
     float* U = res->U ? res->U : Ubuf;
-    const int64_t ldu = res->U ? res->ldu : round4(n);
-    STCHK(fit_run(ctx, fb, A, m, n, lda, Cbuf, c, ldc, d_cols, nullptr, p->refine, U, ldu));
-    FitOut fo;
-    STCHK(fit_collect(ctx, fb, c, &fo));
+    const int64_t ldu = res->U ? res->ldu : round4(ucols);
+    double err2 = 0.0;
+    uint32_t fl = 0;
+    if (rowv) {
+        STCHK(fit_cur_run(ctx, cb, A, m, n, lda, Cbuf, c, ldc, r, U, ldu));
+        double hv[4];
+        int hinfo[4];
+        HIPCHK(hipMemcpyAsync(hv, cb.errv, sizeof hv, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(hinfo, cb.info, sizeof hinfo, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        err2 = std::max(hv[0], 0.0);
+        if ((hinfo[0] | hinfo[2]) & 1) fl |= BCUR_FLAG_RANKDEF_C;
+        if (hinfo[1] & 1) fl |= BCUR_FLAG_RANKDEF_R;
+    } else {
+        STCHK(fit_run(ctx, fb, A, m, n, lda, Cbuf, c, ldc, sc.list, nullptr, p->refine, U, ldu));
+        FitOut fo;
+        STCHK(fit_collect(ctx, fb, c, &fo));
+        err2 = fo.err2;
+        fl = fo.flags;
+    }
     int rinfo[4];
     HIPCHK(hipMemcpy(rinfo, rb.info, sizeof rinfo, hipMemcpyDeviceToHost));
-    uint32_t fl = fo.flags;
     if (rinfo[0] & 1) fl |= BCUR_FLAG_RANKDEF_Y;
-    res->rr_sweeps = (uint32_t)rinfo[2];
-    if (h_st[1]) fl |= BCUR_FLAG_ZERO_SCORE;
-    memcpy(res->idx, h_idx, s * sizeof(int64_t));
-    if (res->weights) memcpy(res->weights, h_w, s * sizeof(double));
-    if (res->scores) memcpy(res->scores, h_sc, G * sizeof(double));
+    if (hc.st[1] || (rowv && hr.st[1])) fl |= BCUR_FLAG_ZERO_SCORE;
+    memcpy(res->idx, hc.idx, s * sizeof(int64_t));
+    if (res->weights) memcpy(res->weights, hc.w, s * sizeof(double));
+    if (res->scores) memcpy(res->scores, hc.sc, G * sizeof(double));
+    if (rowv) {
+        memcpy(res->idx_r, hr.idx, s_r * sizeof(int64_t));
+        if (res->row_scores) memcpy(res->row_scores, hr.sc, Gr * sizeof(double));
+    }
     if (res->ritz)
         for (int64_t i = 0; i < l; ++i) res->ritz[i] = h_lam[i] > 0.0 ? sqrt(h_lam[i]) : 0.0;
     double mm = INFINITY;
-    for (int64_t t = 0; t < s; ++t) mm = std::min(mm, h_mg[t]);
+    for (int64_t t = 0; t < s; ++t) mm = std::min(mm, hc.mg[t]);
     res->c = c;
-    res->r = 0;
+    res->r = r;
     res->frob2 = h_frob[0];
-    res->err = sqrt(fo.err2);
+    res->err = sqrt(err2);
     res->rel_err = h_frob[0] > 0.0 ? res->err / sqrt(h_frob[0]) : 0.0;
     res->min_margin = mm;
     res->flags = fl;
+    res->rr_sweeps = (uint32_t)rinfo[2];
     return BCUR_OK;
 }
 

@@ -62,6 +62,16 @@ hipError_t launch_sgemm(const GemmPlan& p, int64_t M, int64_t N, int64_t K, bool
                         int epi, const float* X, int64_t ldx, const float* Y, int64_t ldy, double* wsum,
                         hipStream_t st);
 
+// ---- BF16 sketch passes (k_bgemm.hip) ----------------------------------------
+// out = bf16(A) (m x n, ldo) and outT = bf16(A)^T (n x m, ldt); either may be null.
+hipError_t launch_cast_bf16_both(const float* A, int64_t m, int64_t n, int64_t lda, uint16_t* out, int64_t ldo,
+                                 uint16_t* outT, int64_t ldt, hipStream_t st);
+// D (M x N, FP32) = A (M x K, bf16, lda) * B^T with B stored N x K (bf16, ldb); leading
+// dimensions multiples of 8.  Split partial tiles go to `partial` (sum with launch_splitk_reduce).
+GemmPlan plan_bgemm(int64_t M, int64_t N, int64_t K);
+hipError_t launch_bgemm_nt(const GemmPlan& p, int64_t M, int64_t N, int64_t K, const uint16_t* A, int64_t lda,
+                           const uint16_t* B, int64_t ldb, float* D, int64_t ldd, float* partial, hipStream_t st);
+
 // ---- small dense FP64 kernels (k_small.hip) --------------------------------
 int gram_wgs(int64_t rows);
 // partial[w] (l x l) = sum over the w-th row range of X^T X, FP64 accumulation (wgs partials).
@@ -70,7 +80,7 @@ hipError_t launch_gram64(const float* X, int64_t rows, int64_t l, int64_t ldx, d
 // T (l x l) = sum of the wgs partials in a fixed order, many workgroups.
 hipError_t launch_gram_reduce(const double* partial, int parts, int64_t l, double* T, hipStream_t st);
 // T = sum of the partials; T + shift I = R^T R (R upper), Rinv = R^-1 (l x l upper),
-// shift = l 2^-52 trace(T).  info[0] |= 1 when the smallest pivot was below 1e3 * shift.
+// shift = l 2^-52 trace(T).  info[0] |= 1 when the smallest pivot was below 10 * shift.
 hipError_t launch_chol_rinv_small(const double* partial, int parts, int64_t l, double* Rinv, int* info,
                                   hipStream_t st);
 // out (rows x lo, FP32, ldo) = X (rows x li, FP32, ldx) * M (li x lo, FP64, ldm)
@@ -85,13 +95,26 @@ hipError_t launch_jacobi_eigh(const double* partial, int parts, int64_t l, int64
 // ---- blocked FP64 Cholesky inverse (k_dense64.hip) -------------------------
 size_t spd_inverse_ws_doubles(int64_t c);
 // Ginv = G^-1 for SPD G (c x c, FP64, overwritten by its Cholesky factor).
-// info[0] |= 1 when a pivot fell below tau = c 2^-24 max diag: that column is dropped and its
-// rows and columns of Ginv are zero (the inverse of the kept columns' Gram matrix);
+// info[0] |= 1 when a pivot fell below tau = c rel_tau max diag (rel_tau: the relative
+// accuracy of G's entries, 2^-24 for a Gram matrix formed in FP32, 2^-50 for one formed in
+// FP64): that column is dropped and its rows and columns of Ginv are zero (the inverse of
+// the kept columns' Gram matrix);
 // piv[0] = min pivot, piv[1] = max pivot (of the Schur complements).
 hipError_t launch_spd_inverse(double* G, int64_t c, double* Ginv, double* ws, int* info, double* piv,
-                              hipStream_t st);
+                              double rel_tau, hipStream_t st);
+// The same factorization, returning *Linv = L^-1 (c x c, lower, inside ws) instead of G^-1.
+hipError_t launch_chol_linv(double* G, int64_t c, double* ws, int* info, double* piv, double rel_tau,
+                            double** Linv, hipStream_t st);
+// D = alpha op(A) op(B) + beta D in FP64 (op = transpose when the flag is set); the
+// _ff / _fd variants read FP32 operands (A and B, or A only), widened exactly.
 hipError_t launch_dgemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda, bool tA,
                         const double* B, int64_t ldb, bool tB, double beta, double* D, int64_t ldd,
                         hipStream_t st);
+hipError_t launch_dgemm_ff(int64_t M, int64_t N, int64_t K, double alpha, const float* A, int64_t lda, bool tA,
+                           const float* B, int64_t ldb, bool tB, double beta, double* D, int64_t ldd,
+                           hipStream_t st);
+hipError_t launch_dgemm_fd(int64_t M, int64_t N, int64_t K, double alpha, const float* A, int64_t lda, bool tA,
+                           const double* B, int64_t ldb, bool tB, double beta, double* D, int64_t ldd,
+                           hipStream_t st);
 
 }  // namespace bcur

@@ -1,0 +1,232 @@
+// BF16 sketch passes on the CDNA4 matrix cores (v_mfma_f32_32x32x16_bf16,
+// FP32 accumulation).  Both operands are stored with k contiguous ("NT"):
+// D (M x N, FP32) = A (M x K, bf16) * B^T, B stored N x K (bf16).  A tile
+// row of 32 k values is 64 bytes; each lane's MFMA operand is 8 consecutive
+// k values, one 16-byte LDS read.  Split-K partial tiles are summed in a
+// fixed order by the FP32 GEMM's reduction kernel.
+//
+// Also here: the casts that produce the k-contiguous operands:
+//   A (m x n, f32) -> A_bf (m x n) and A_bf^T (n x m), one tiled pass;
+//   X (rows x l, f32) -> X_bf^T (l x rows) for the sketch panels.
+#include "bcur_internal.h"
+
+namespace bcur {
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// out (m x n, ldo) = bf16(A); outT (n x m, ldt) = bf16(A)^T, through 64 x 64 LDS tiles.
+__global__ __launch_bounds__(256) void k_cast_bf16_both(const float* __restrict__ A, int64_t m, int64_t n,
+                                                        int64_t lda, uint16_t* __restrict__ out, int64_t ldo,
+                                                        uint16_t* __restrict__ outT, int64_t ldt) {
+    __shared__ uint16_t tile[64][66];
+    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int i = ty; i < 64; i += 4) {
+        const int64_t r = r0 + i, c = c0 + tx;
+        uint16_t v = 0;
+        if (r < m && c < n) {
+            v = bf16_rne(A[r * lda + c]);
+            if (out) out[r * ldo + c] = v;
+        }
+        tile[i][tx] = v;
+    }
+    __syncthreads();
+    if (!outT) return;
+    for (int i = ty; i < 64; i += 4) {
+        const int64_t c = c0 + i, r = r0 + tx;
+        if (c < n && r < m) outT[c * ldt + r] = tile[tx][i];
+    }
+}
+
+struct BArgs {
+    int64_t M, N, K;
+    const uint16_t* A;
+    int64_t lda;
+    const uint16_t* B;
+    int64_t ldb;
+    float* D;
+    int64_t ldd;
+    int64_t kchunk;
+    int64_t split_stride;
+};
+
+// 8 bf16 (16 bytes) at p[0..7] when 16-byte aligned and in range, else
+// element-wise with zeros outside [c, cend).
+__device__ __forceinline__ uint4 ld8(const uint16_t* p, bool rowok, int64_t c, int64_t cend) {
+    if (rowok && c + 7 < cend) return *reinterpret_cast<const uint4*>(p);
+    uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (rowok)
+        for (int e = 0; e < 8; ++e)
+            if (c + e < cend) v[e] = p[e];
+    uint4 r;
+    r.x = v[0] | ((uint32_t)v[1] << 16);
+    r.y = v[2] | ((uint32_t)v[3] << 16);
+    r.z = v[4] | ((uint32_t)v[5] << 16);
+    r.w = v[6] | ((uint32_t)v[7] << 16);
+    return r;
+}
+
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(WM* WN * 64) void k_bgemm_nt(const BArgs g) {
+    constexpr int BK = 32;                 // k per LDS stage
+    constexpr int NT = WM * WN * 64;
+    constexpr int WTM = BM / WM, WTN = BN / WN;
+    constexpr int TM = WTM / 32, TN = WTN / 32;
+    constexpr int LDS_ROW = BK + 8;        // bf16 per LDS row (80 bytes: spreads banks)
+    constexpr int A_V = BM * BK / 8 / NT;  // 16-byte vectors per thread
+    constexpr int B_V = BN * BK / 8 / NT;
+    static_assert(TM >= 1 && TN >= 1 && A_V >= 1 && B_V >= 1, "tile shape");
+    __shared__ __attribute__((aligned(16))) uint16_t As[BM * LDS_ROW];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[BN * LDS_ROW];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 31, h = lane >> 5;
+    const int wm = wave % WM, wn = wave / WM;
+    const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
+    const int64_t kbeg = (int64_t)blockIdx.z * g.kchunk;
+    const int64_t kend = g.K < kbeg + g.kchunk ? g.K : kbeg + g.kchunk;
+
+    f32x16 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+
+    uint4 ra[A_V], rb[B_V];
+    auto load = [&](int64_t k0) {
+#pragma unroll
+        for (int u = 0; u < A_V; ++u) {
+            const int f = tid + u * NT, row = f / (BK / 8), kq = f % (BK / 8);
+            const int64_t gm = m0 + row, gk = k0 + kq * 8;
+            ra[u] = ld8(g.A + gm * g.lda + gk, gm < g.M, gk, kend);
+        }
+#pragma unroll
+        for (int u = 0; u < B_V; ++u) {
+            const int f = tid + u * NT, row = f / (BK / 8), kq = f % (BK / 8);
+            const int64_t gn = n0 + row, gk = k0 + kq * 8;
+            rb[u] = ld8(g.B + gn * g.ldb + gk, gn < g.N, gk, kend);
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int u = 0; u < A_V; ++u) {
+            const int f = tid + u * NT, row = f / (BK / 8), kq = f % (BK / 8);
+            *reinterpret_cast<uint4*>(&As[row * LDS_ROW + kq * 8]) = ra[u];
+        }
+#pragma unroll
+        for (int u = 0; u < B_V; ++u) {
+            const int f = tid + u * NT, row = f / (BK / 8), kq = f % (BK / 8);
+            *reinterpret_cast<uint4*>(&Bs[row * LDS_ROW + kq * 8]) = rb[u];
+        }
+    };
+
+    int64_t k0 = kbeg;
+    if (k0 < kend) load(k0);
+    for (; k0 < kend; k0 += BK) {
+        __syncthreads();
+        store();
+        __syncthreads();
+        if (k0 + BK < kend) load(k0 + BK);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 16) {
+            bf16x8 a[TM], b[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+                a[i] = *reinterpret_cast<const bf16x8*>(&As[(wm * WTM + 32 * i + r) * LDS_ROW + kk + 8 * h]);
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+                b[j] = *reinterpret_cast<const bf16x8*>(&Bs[(wn * WTN + 32 * j + r) * LDS_ROW + kk + 8 * h]);
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    float* D = g.D + (int64_t)blockIdx.z * g.split_stride;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int64_t row = m0 + wm * WTM + 32 * i + 8 * (v >> 2) + 4 * h + (v & 3);
+                const int64_t col = n0 + wn * WTN + 32 * j + r;
+                if (row < g.M && col < g.N) D[row * g.ldd + col] = acc[i][j][v];
+            }
+}
+
+}  // namespace
+
+hipError_t launch_cast_bf16_both(const float* A, int64_t m, int64_t n, int64_t lda, uint16_t* out, int64_t ldo,
+                                 uint16_t* outT, int64_t ldt, hipStream_t st) {
+    dim3 grid((unsigned)((n + 63) / 64), (unsigned)((m + 63) / 64));
+    hipLaunchKernelGGL(k_cast_bf16_both, grid, dim3(256), 0, st, A, m, n, lda, out, ldo, outT, ldt);
+    return hipGetLastError();
+}
+
+GemmPlan plan_bgemm(int64_t M, int64_t N, int64_t K) {
+    GemmPlan p;
+    p.cfg = N <= 64 ? 0 : 1;
+    const int64_t BM = 128, BN = N <= 64 ? 64 : 128;
+    const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+    int64_t splits = 1;
+    if (tiles < 480) {
+        splits = (512 + tiles - 1) / tiles;
+        const int64_t maxs = K / 256;
+        if (splits > maxs) splits = maxs;
+        if (splits < 1) splits = 1;
+    }
+    int64_t kchunk = (K + splits - 1) / splits;
+    kchunk = ((kchunk + 31) / 32) * 32;
+    splits = (K + kchunk - 1) / kchunk;
+    if (splits < 1) splits = 1;
+    p.splits = (int)splits;
+    p.kchunk = kchunk;
+    p.wgs = tiles * splits;
+    return p;
+}
+
+hipError_t launch_bgemm_nt(const GemmPlan& p, int64_t M, int64_t N, int64_t K, const uint16_t* A, int64_t lda,
+                           const uint16_t* B, int64_t ldb, float* D, int64_t ldd, float* partial, hipStream_t st) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    BArgs a;
+    a.M = M;
+    a.N = N;
+    a.K = K;
+    a.A = A;
+    a.lda = lda;
+    a.B = B;
+    a.ldb = ldb;
+    a.kchunk = p.kchunk;
+    if (p.splits > 1) {
+        a.D = partial;
+        a.ldd = N;
+        a.split_stride = M * N;
+    } else {
+        a.D = D;
+        a.ldd = ldd;
+        a.split_stride = 0;
+    }
+    if (p.cfg == 0) {
+        dim3 grid((unsigned)((M + 127) / 128), (unsigned)((N + 63) / 64), (unsigned)p.splits);
+        hipLaunchKernelGGL((k_bgemm_nt<128, 64, 4, 1>), grid, dim3(256), 0, st, a);
+    } else {
+        dim3 grid((unsigned)((M + 127) / 128), (unsigned)((N + 127) / 128), (unsigned)p.splits);
+        hipLaunchKernelGGL((k_bgemm_nt<128, 128, 4, 1>), grid, dim3(256), 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace bcur

@@ -15,9 +15,9 @@ constexpr int KB = 16;   // GEMM k step
 
 // acc (thread's 4x4 at rows ty + 16 i, cols tx + 16 j of a 64x64 tile) +=
 // op(A)[0:M, 0:K] op(B)[0:K, 0:N]; A, B point at the tile's origin.
-template <bool TA, bool TB>
-__device__ __forceinline__ void tile_mm(double (&acc)[4][4], const double* __restrict__ A, int64_t lda,
-                                        const double* __restrict__ B, int64_t ldb, int64_t M, int64_t N, int64_t K,
+template <bool TA, bool TB, typename TAe = double, typename TBe = double>
+__device__ __forceinline__ void tile_mm(double (&acc)[4][4], const TAe* __restrict__ A, int64_t lda,
+                                        const TBe* __restrict__ B, int64_t ldb, int64_t M, int64_t N, int64_t K,
                                         double* As, double* Bs) {
     const int tid = threadIdx.x, ty = tid / 16, tx = tid % 16;
     for (int64_t k0 = 0; k0 < K; k0 += KB) {
@@ -33,7 +33,7 @@ __device__ __forceinline__ void tile_mm(double (&acc)[4][4], const double* __res
             }
             const int64_t gk = k0 + kk;
             double v = 0.0;
-            if (row < M && gk < K) v = TA ? A[gk * lda + row] : A[row * lda + gk];
+            if (row < M && gk < K) v = (double)(TA ? A[gk * lda + row] : A[row * lda + gk]);
             As[kk * (NB + 1) + row] = v;
         }
         for (int e = tid; e < NB * KB; e += 256) {
@@ -47,7 +47,7 @@ __device__ __forceinline__ void tile_mm(double (&acc)[4][4], const double* __res
             }
             const int64_t gk = k0 + kk;
             double v = 0.0;
-            if (col < N && gk < K) v = TB ? B[col * ldb + gk] : B[gk * ldb + col];
+            if (col < N && gk < K) v = (double)(TB ? B[col * ldb + gk] : B[gk * ldb + col]);
             Bs[kk * (NB + 1) + col] = v;
         }
         __syncthreads();
@@ -66,17 +66,19 @@ __device__ __forceinline__ void tile_mm(double (&acc)[4][4], const double* __res
     }
 }
 
-template <bool TA, bool TB>
+// D = alpha op(A) op(B) + beta D in FP64; A and B may be FP32 (products of
+// two FP32 values are exact in FP64) or FP64.
+template <bool TA, bool TB, typename TAe, typename TBe>
 __global__ __launch_bounds__(256) void k_dgemm(int64_t M, int64_t N, int64_t K, double alpha,
-                                               const double* __restrict__ A, int64_t lda,
-                                               const double* __restrict__ B, int64_t ldb, double beta,
+                                               const TAe* __restrict__ A, int64_t lda,
+                                               const TBe* __restrict__ B, int64_t ldb, double beta,
                                                double* D, int64_t ldd) {
     __shared__ double As[KB * (NB + 1)], Bs[KB * (NB + 1)];
     const int64_t m0 = (int64_t)blockIdx.x * NB, n0 = (int64_t)blockIdx.y * NB;
     double acc[4][4] = {};
-    const double* Ab = TA ? A + m0 : A + m0 * lda;
-    const double* Bb = TB ? B + n0 * ldb : B + n0;
-    tile_mm<TA, TB>(acc, Ab, lda, Bb, ldb, M - m0, N - n0, K, As, Bs);
+    const TAe* Ab = TA ? A + m0 : A + m0 * lda;
+    const TBe* Bb = TB ? B + n0 * ldb : B + n0;
+    tile_mm<TA, TB, TAe, TBe>(acc, Ab, lda, Bb, ldb, M - m0, N - n0, K, As, Bs);
     const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -103,7 +105,7 @@ __global__ __launch_bounds__(256) void k_maxdiag(const double* __restrict__ G, i
 }
 
 // Cholesky of the w x w diagonal block at (j0, j0) of G in LDS.  A column
-// whose Schur-complement pivot is not above tau = c 2^-24 max diag(G) is
+// whose Schur-complement pivot is not above tau = c rel_tau max diag(G) is
 // numerically in the span of the columns before it: it is dropped (flagged),
 // its column of L is zeroed so it updates nothing, and its row of L^-1 is
 // zeroed so the inverse built from L^-1 is that of the kept columns, with
@@ -111,15 +113,16 @@ __global__ __launch_bounds__(256) void k_maxdiag(const double* __restrict__ G, i
 // the block zeroed) into G and L^-1 (NB x NB, zero padded) into Linv.
 // piv[0..1] receive the smallest and largest pivot.
 __global__ __launch_bounds__(256) void k_potrf_diag(double* __restrict__ G, int64_t c, int64_t j0, int w,
-                                                    const double* __restrict__ maxdiag, double* __restrict__ Linv,
-                                                    double* __restrict__ piv, int* __restrict__ info) {
+                                                    const double* __restrict__ maxdiag, double rel_tau,
+                                                    double* __restrict__ Linv, double* __restrict__ piv,
+                                                    int* __restrict__ info) {
     constexpr int LD = NB + 1;
     __shared__ double S[NB * LD];
     __shared__ double base[NB * 8];
     __shared__ double sq[NB];
     __shared__ int drop[NB];
     const int tid = threadIdx.x;
-    const double tau = (double)c * ldexp(1.0, -24) * maxdiag[0];
+    const double tau = (double)c * rel_tau * maxdiag[0];
     const int wp = pow2_at_least8(w);
     for (int e = tid; e < w * w; e += 256) {
         const int i = e / w, j = e % w;
@@ -205,23 +208,43 @@ size_t spd_inverse_ws_doubles(int64_t c) {
     return (size_t)(nblk * NB * NB) + (size_t)(c * c) + (size_t)(2 * nblk) + 8;
 }
 
-hipError_t launch_dgemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda, bool tA,
-                        const double* B, int64_t ldb, bool tB, double beta, double* D, int64_t ldd, hipStream_t st) {
+template <typename TAe, typename TBe>
+hipError_t dgemm_any(int64_t M, int64_t N, int64_t K, double alpha, const TAe* A, int64_t lda, bool tA, const TBe* B,
+                     int64_t ldb, bool tB, double beta, double* D, int64_t ldd, hipStream_t st) {
     if (M <= 0 || N <= 0) return hipSuccess;
     dim3 grid((unsigned)((M + NB - 1) / NB), (unsigned)((N + NB - 1) / NB));
     if (!tA && !tB)
-        hipLaunchKernelGGL((k_dgemm<false, false>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, D, ldd);
+        hipLaunchKernelGGL((k_dgemm<false, false, TAe, TBe>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb,
+                           beta, D, ldd);
     else if (!tA && tB)
-        hipLaunchKernelGGL((k_dgemm<false, true>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, D, ldd);
+        hipLaunchKernelGGL((k_dgemm<false, true, TAe, TBe>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb,
+                           beta, D, ldd);
     else if (tA && !tB)
-        hipLaunchKernelGGL((k_dgemm<true, false>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, D, ldd);
+        hipLaunchKernelGGL((k_dgemm<true, false, TAe, TBe>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb,
+                           beta, D, ldd);
     else
-        hipLaunchKernelGGL((k_dgemm<true, true>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, D, ldd);
+        hipLaunchKernelGGL((k_dgemm<true, true, TAe, TBe>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb,
+                           beta, D, ldd);
     return hipGetLastError();
 }
 
-// ws: [Linv blocks nblk*NB*NB][X c*c][piv 2*nblk][maxdiag]
-hipError_t launch_spd_inverse(double* G, int64_t c, double* Ginv, double* ws, int* info, double* piv, hipStream_t st) {
+hipError_t launch_dgemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda, bool tA,
+                        const double* B, int64_t ldb, bool tB, double beta, double* D, int64_t ldd, hipStream_t st) {
+    return dgemm_any(M, N, K, alpha, A, lda, tA, B, ldb, tB, beta, D, ldd, st);
+}
+hipError_t launch_dgemm_ff(int64_t M, int64_t N, int64_t K, double alpha, const float* A, int64_t lda, bool tA,
+                           const float* B, int64_t ldb, bool tB, double beta, double* D, int64_t ldd, hipStream_t st) {
+    return dgemm_any(M, N, K, alpha, A, lda, tA, B, ldb, tB, beta, D, ldd, st);
+}
+hipError_t launch_dgemm_fd(int64_t M, int64_t N, int64_t K, double alpha, const float* A, int64_t lda, bool tA,
+                           const double* B, int64_t ldb, bool tB, double beta, double* D, int64_t ldd, hipStream_t st) {
+    return dgemm_any(M, N, K, alpha, A, lda, tA, B, ldb, tB, beta, D, ldd, st);
+}
+
+// ws: [Linv blocks nblk*NB*NB][X c*c][piv 2*nblk][maxdiag].  Factor G (in
+// place, lower L) and form X = L^-1 (lower) in the workspace; returns X.
+static hipError_t chol_and_inverse_factor(double* G, int64_t c, double* ws, int* info, double* piv, double rel_tau,
+                                          double** Xout, hipStream_t st) {
     const int64_t nblk = (c + NB - 1) / NB;
     double* Linv = ws;
     double* X = Linv + nblk * NB * NB;
@@ -231,7 +254,7 @@ hipError_t launch_spd_inverse(double* G, int64_t c, double* Ginv, double* ws, in
     for (int64_t jb = 0; jb < nblk; ++jb) {
         const int64_t j0 = jb * NB;
         const int w = (int)(c - j0 < NB ? c - j0 : NB);
-        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, st, G, c, j0, w, (const double*)maxd,
+        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, st, G, c, j0, w, (const double*)maxd, rel_tau,
                            Linv + jb * NB * NB, pivb + 2 * jb, info);
         const int64_t rows = c - j0 - w;
         if (rows > 0) {
@@ -248,14 +271,25 @@ hipError_t launch_spd_inverse(double* G, int64_t c, double* Ginv, double* ws, in
     for (int d = 1; d < nblk; ++d)
         hipLaunchKernelGGL(k_trtri_step, dim3((unsigned)(nblk - d)), dim3(256), 0, st, (const double*)G, X, c, d,
                            (const double*)Linv);
-    hipError_t e = launch_dgemm(c, c, c, 1.0, X, c, true, X, c, false, 0.0, Ginv, c, st);
-    if (e != hipSuccess) return e;
     if (piv) {
-        // pivot range over the blocks: min of mins, max of maxes (host reads pivb)
         const hipError_t e2 = hipMemcpyAsync(piv, pivb, sizeof(double) * 2 * nblk, hipMemcpyDeviceToDevice, st);
         if (e2 != hipSuccess) return e2;
     }
+    *Xout = X;
     return hipGetLastError();
+}
+
+hipError_t launch_spd_inverse(double* G, int64_t c, double* Ginv, double* ws, int* info, double* piv, double rel_tau,
+                              hipStream_t st) {
+    double* X = nullptr;
+    hipError_t e = chol_and_inverse_factor(G, c, ws, info, piv, rel_tau, &X, st);
+    if (e != hipSuccess) return e;
+    return launch_dgemm(c, c, c, 1.0, X, c, true, X, c, false, 0.0, Ginv, c, st);
+}
+
+hipError_t launch_chol_linv(double* G, int64_t c, double* ws, int* info, double* piv, double rel_tau, double** Linv,
+                            hipStream_t st) {
+    return chol_and_inverse_factor(G, c, ws, info, piv, rel_tau, Linv, st);
 }
 
 }  // namespace bcur

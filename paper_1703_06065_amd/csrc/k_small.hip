@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void k_chol_rinv_small(const double* __restric
         const int c = e / l, i = e % l;
         Rinv[e] = i < c ? 0.0 : S[i * ld + c];
     }
-    if (tid == 0 && info && (pmin < 1e3 * shift)) atomicOr(info, 1);
+    if (tid == 0 && info && (pmin < 10.0 * shift)) atomicOr(info, 1);
 }
 
 // out (rows x lo) = X (rows x li, FP32) * M (li x lo, FP64), FP64 accumulation.
