@@ -92,6 +92,9 @@ const char* bcur_last_error(const bcur_ctx* ctx);
 /* Bytes of device workspace currently held by the context. */
 size_t bcur_workspace_bytes(const bcur_ctx* ctx);
 
+/* Give the context's device workspace back (it is reallocated on demand). */
+bcur_status bcur_release_workspace(bcur_ctx* ctx);
+
 /* ---- stage calls -------------------------------------------------------- */
 
 /* ||A||_F^2 = sum_ij A_ij^2 (Sec. 2.1, Frobenius norm), accumulated in float64
@@ -253,6 +256,61 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
                            const int64_t* col_off, int64_t G, const int64_t* row_off, int64_t Gr,
                            const bcur_params* params, const float* omega, const uint64_t* draws,
                            bcur_result* result);
+
+/* Device workspace one bcur_decompose call needs for these shapes and
+ * parameters (bytes; library_holds_u != 0 when result->U will be NULL).
+ * Host only, no device access. */
+bcur_status bcur_footprint(int64_t m, int64_t n, const int64_t* col_off, int64_t G, const int64_t* row_off,
+                           int64_t Gr, const bcur_params* params, int32_t library_holds_u, size_t* bytes);
+
+/* ---- serving: continuous batching of decompositions ------------------------
+ *
+ * A server runs up to `max_slots` decompositions at once, each in its own
+ * slot (a context with its own HIP stream and host thread), so requests that
+ * arrive while others run are admitted as soon as a slot is free and their
+ * device-memory footprint (bcur_footprint) fits `hbm_budget`; their work
+ * overlaps on the device.  Admission is in arrival order.  Results are
+ * bitwise identical to bcur_decompose on the same inputs (the kernels and
+ * their tilings depend only on each request's shapes). */
+
+typedef struct bcur_server bcur_server;
+
+typedef struct bcur_request {
+    const float* A;          /* device, borrowed until the ticket completes */
+    int64_t m, n, lda;
+    const int64_t* col_off;  /* host, copied at submission */
+    int64_t G;
+    const int64_t* row_off;  /* host or NULL, copied */
+    int64_t Gr;
+    bcur_params params;
+    const float* omega;      /* device, borrowed */
+    const uint64_t* draws;   /* host, s + s_r words, copied */
+    float* U;                /* device output or NULL, borrowed */
+    int64_t ldu, u_rows_cap;
+    void* stream;            /* hipStream_t that produced A / omega, or NULL: the
+                                request waits for the work queued on it so far */
+} bcur_request;
+
+typedef struct bcur_stats {
+    int64_t completed, failed, queued, running;
+    double p50_ms, p99_ms, mean_ms;  /* latency from submission to completion */
+    double throughput;               /* completed per second, first submission to last completion */
+    uint64_t hbm_held, hbm_peak;     /* device workspace held now / at most */
+    int64_t peak_running;            /* most requests running at once */
+} bcur_stats;
+
+bcur_status bcur_server_create(bcur_server** out, int device, size_t hbm_budget, int32_t max_slots);
+/* Waits for queued and running requests, then frees everything. */
+bcur_status bcur_server_destroy(bcur_server* srv);
+/* BCUR_E_ADMIT when the request's footprint exceeds the whole budget. */
+bcur_status bcur_server_submit(bcur_server* srv, const bcur_request* request, uint64_t* ticket);
+/* BCUR_PENDING while running; otherwise the request's status, with the
+ * results copied into `out` (host arrays as in bcur_result) and the ticket
+ * released.  BCUR_E_STATE for an unknown or collected ticket. */
+bcur_status bcur_server_poll(bcur_server* srv, uint64_t ticket, bcur_result* out);
+/* As poll, but blocks until the request has finished. */
+bcur_status bcur_server_wait(bcur_server* srv, uint64_t ticket, bcur_result* out);
+bcur_status bcur_server_stats(bcur_server* srv, bcur_stats* out);
 
 #ifdef __cplusplus
 }

@@ -3,6 +3,6 @@
 The computation lives in the HIP library ``libbcur.so`` (sources in
 ``csrc/``, C ABI in ``include/bcur.h``); ``binding`` is its ctypes wrapper.
 """
-from .binding import BcurError, Context, load_library  # noqa: F401
+from .binding import BcurError, Context, Server, load_library  # noqa: F401
 
-__all__ = ["Context", "BcurError", "load_library"]
+__all__ = ["Context", "Server", "BcurError", "load_library"]

@@ -28,7 +28,8 @@ SYMBOLS = [
     "bcur_create", "bcur_destroy", "bcur_synchronize", "bcur_status_str", "bcur_last_error",
     "bcur_workspace_bytes", "bcur_frob2", "bcur_range_finder", "bcur_block_scores", "bcur_sample_blocks",
     "bcur_gather_columns", "bcur_fit_columns", "bcur_decompose", "bcur_timing_enable", "bcur_timing_read",
-    "bcur_sketch_pass",
+    "bcur_sketch_pass", "bcur_release_workspace", "bcur_footprint", "bcur_server_create", "bcur_server_destroy",
+    "bcur_server_submit", "bcur_server_poll", "bcur_server_wait", "bcur_server_stats",
 ]
 
 STAGES = ["frob", "rf_AQ", "rf_AtZ", "rf_reduce", "rf_orth", "rf_rr", "scores", "sample", "gather", "fit_H",
@@ -55,6 +56,21 @@ class Result(ctypes.Structure):
                 ("c", ctypes.c_int64), ("r", ctypes.c_int64), ("frob2", ctypes.c_double), ("err", ctypes.c_double),
                 ("rel_err", ctypes.c_double), ("min_margin", ctypes.c_double), ("flags", ctypes.c_uint32),
                 ("rr_sweeps", ctypes.c_uint32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("lda", ctypes.c_int64),
+                ("col_off", ctypes.POINTER(ctypes.c_int64)), ("G", ctypes.c_int64),
+                ("row_off", ctypes.POINTER(ctypes.c_int64)), ("Gr", ctypes.c_int64), ("params", Params),
+                ("omega", ctypes.c_void_p), ("draws", ctypes.POINTER(ctypes.c_uint64)), ("U", ctypes.c_void_p),
+                ("ldu", ctypes.c_int64), ("u_rows_cap", ctypes.c_int64), ("stream", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_int64), ("failed", ctypes.c_int64), ("queued", ctypes.c_int64),
+                ("running", ctypes.c_int64), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("mean_ms", ctypes.c_double), ("throughput", ctypes.c_double), ("hbm_held", ctypes.c_uint64),
+                ("hbm_peak", ctypes.c_uint64), ("peak_running", ctypes.c_int64)]
 
 
 _lib = None
@@ -84,6 +100,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "bcur_gather_columns": (i32, [vp, vp, i64, i64, i64, P(i64), i64, P(i64), i64, vp, i64, P(i64)]),
         "bcur_fit_columns": (i32, [vp, vp, i64, i64, i64, vp, i64, i64, i32, vp, i64, P(dbl), P(u32)]),
         "bcur_sketch_pass": (i32, [vp, vp, i64, i64, i64, vp, i64, i64, i32, vp, i64]),
+        "bcur_release_workspace": (i32, [vp]),
+        "bcur_footprint": (i32, [i64, i64, P(i64), i64, P(i64), i64, P(Params), i32, P(ctypes.c_size_t)]),
+        "bcur_server_create": (i32, [P(vp), i32, ctypes.c_size_t, i32]),
+        "bcur_server_destroy": (i32, [vp]),
+        "bcur_server_submit": (i32, [vp, P(Request), P(ctypes.c_uint64)]),
+        "bcur_server_poll": (i32, [vp, ctypes.c_uint64, P(Result)]),
+        "bcur_server_wait": (i32, [vp, ctypes.c_uint64, P(Result)]),
+        "bcur_server_stats": (i32, [vp, P(Stats)]),
         "bcur_timing_enable": (i32, [vp, i32]),
         "bcur_timing_read": (i32, [vp, P(dbl), P(i64)]),
         "bcur_decompose": (i32, [vp, vp, i64, i64, i64, P(i64), i64, P(i64), i64, P(Params), vp,
@@ -303,3 +327,101 @@ class Context:
             out["idx_r"] = idx_r[:s_r]
             out["row_scores"] = rsc
         return out
+
+
+class Server:
+    """Continuous-batching server (bcur_server_*): submit decompositions as
+    they arrive, poll or wait for their results."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 16 << 30, max_slots: int = 4):
+        self.lib = load_library()
+        h = ctypes.c_void_p()
+        st = self.lib.bcur_server_create(ctypes.byref(h), device, hbm_budget, max_slots)
+        if st != OK:
+            raise BcurError(st, self.lib.bcur_status_str(st).decode())
+        self.h = h
+        self._live = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.bcur_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, A, offsets, k: int, s: int, omega, draws, q: int = 2, replace: bool = False,
+               refine: int = 1, precision: int = PREC_FP32, row_offsets=None, s_r: int = 0, U_out=None):
+        import torch
+        p, m, n, lda = _check_dev(A, "A")
+        po, on, l, ldo = _check_dev(omega, "omega")
+        if on != n or ldo != l:
+            raise ValueError("omega must be a dense n x l tensor")
+        off = _i64(offsets)
+        dr = np.ascontiguousarray(draws, dtype=np.uint64)
+        rq = Request()
+        rq.A, rq.m, rq.n, rq.lda = p, m, n, lda
+        rq.col_off, rq.G = _ptr(off, ctypes.c_int64), len(off) - 1
+        roff = None
+        if row_offsets is not None and s_r > 0:
+            roff = _i64(row_offsets)
+            rq.row_off, rq.Gr = _ptr(roff, ctypes.c_int64), len(roff) - 1
+        rq.params = Params(k=k, s=s, l=l, q=q, replace=int(replace), precision=precision, refine=refine,
+                           reserved=0, s_r=s_r if roff is not None else 0)
+        rq.omega = po
+        rq.draws = _ptr(dr, ctypes.c_uint64)
+        if U_out is not None:
+            rq.U, rq.ldu, rq.u_rows_cap = U_out.data_ptr(), U_out.stride(0), U_out.shape[0]
+        rq.stream = torch.cuda.current_stream(A.device).cuda_stream
+        t = ctypes.c_uint64()
+        st = self.lib.bcur_server_submit(self.h, ctypes.byref(rq), ctypes.byref(t))
+        if st != OK:
+            raise BcurError(st, self.lib.bcur_status_str(st).decode())
+        G = len(off) - 1
+        Gr = len(roff) - 1 if roff is not None else 0
+        # keep the request's tensors alive and the result arrays ready
+        self._live[t.value] = (A, omega, U_out, np.empty(s, dtype=np.int64), np.empty(s), np.empty(G),
+                               np.empty(l), np.empty(max(s_r, 1), dtype=np.int64), np.empty(max(Gr, 1)), s_r)
+        return t.value
+
+    def _collect(self, ticket, wait):
+        A, om, U, idx, w, sc, rz, ir, rs, s_r = self._live[ticket]
+        res = Result()
+        res.idx = _ptr(idx, ctypes.c_int64)
+        res.weights = _ptr(w, ctypes.c_double)
+        res.scores = _ptr(sc, ctypes.c_double)
+        res.ritz = _ptr(rz, ctypes.c_double)
+        res.idx_r = _ptr(ir, ctypes.c_int64)
+        res.row_scores = _ptr(rs, ctypes.c_double)
+        fn = self.lib.bcur_server_wait if wait else self.lib.bcur_server_poll
+        st = fn(self.h, ticket, ctypes.byref(res))
+        if st == PENDING:
+            return None
+        del self._live[ticket]
+        if st != OK:
+            raise BcurError(st, self.lib.bcur_status_str(st).decode())
+        out = {"idx": idx, "weights": w, "scores": sc, "ritz": rz, "c": res.c, "r": res.r, "frob2": res.frob2,
+               "err": res.err, "rel_err": res.rel_err, "min_margin": res.min_margin, "flags": res.flags,
+               "rr_sweeps": res.rr_sweeps}
+        if U is not None:
+            out["U"] = U[:res.c, :res.r] if res.r else U[:res.c]
+        if s_r:
+            out["idx_r"] = ir[:s_r]
+            out["row_scores"] = rs
+        return out
+
+    def poll(self, ticket):
+        return self._collect(ticket, False)
+
+    def wait(self, ticket):
+        return self._collect(ticket, True)
+
+    def stats(self):
+        st = Stats()
+        r = self.lib.bcur_server_stats(self.h, ctypes.byref(st))
+        if r != OK:
+            raise BcurError(r, self.lib.bcur_status_str(r).decode())
+        return {f: getattr(st, f) for f, _ in Stats._fields_}

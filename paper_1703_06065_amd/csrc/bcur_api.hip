@@ -544,6 +544,57 @@ bcur_status fit_cur_run(bcur_ctx* ctx, const CurBufs& b, const float* A, int64_t
     return BCUR_OK;
 }
 
+// Sampling buffers for one side (columns or rows).
+struct SampleBufs {
+    int64_t *off, *idx, *list;
+    double *sc, *w, *mg;
+    uint64_t *dr, *qb, *pr;
+    int* st;
+};
+
+void sample_layout(Arena& a, SampleBufs& b, int64_t G, int64_t s, int64_t listmax) {
+    b.off = a.take<int64_t>(G + 1);
+    b.sc = a.take<double>(G);
+    b.dr = a.take<uint64_t>(s);
+    b.qb = a.take<uint64_t>(G);
+    b.pr = a.take<uint64_t>(G);
+    b.idx = a.take<int64_t>(s);
+    b.w = a.take<double>(s);
+    b.mg = a.take<double>(s);
+    b.st = a.take<int>(4);
+    b.list = a.take<int64_t>(std::max<int64_t>(listmax, 1));
+}
+
+// Device workspace of one decomposition, from the shapes alone (the same
+// layout bcur_decompose uses).  need_ubuf: the library holds U itself.
+size_t decompose_ws_bytes(int64_t m, int64_t n, int64_t G, int64_t maxw, int64_t Gr, int64_t maxh,
+                          const bcur_params* p, bool need_ubuf) {
+    const int64_t k = p->k, l = p->l, s = p->s;
+    const bool bf16 = p->precision == BCUR_PREC_BF16;
+    const bool rowv = Gr > 0 && p->s_r > 0;
+    const int64_t s_r = rowv ? p->s_r : 0;
+    const int64_t cmax = std::min(s * maxw, n);
+    const int64_t rmax = rowv ? std::min(s_r * maxh, m) : 0;
+    const int64_t ucols = rowv ? rmax : n;
+    Arena a;
+    RFBufs rb;
+    FitBufs fb;
+    CurBufs cb;
+    SampleBufs sc, sr;
+    rf_layout(a, rb, m, n, l, k, bf16);
+    sample_layout(a, sc, G, s, cmax);
+    if (rowv) sample_layout(a, sr, Gr, s_r, rmax);
+    a.take<double>(2);
+    a.take<double>(frob2_grid(m, n));
+    a.take<float>(n * k);
+    if (rowv) a.take<float>(m * k);
+    a.take<float>(m * round4(cmax));
+    if (need_ubuf) a.take<float>(cmax * round4(ucols));
+    if (rowv) cur_layout(a, cb, m, n, cmax, rmax);
+    else fit_layout(a, fb, m, n, cmax, false);
+    return a.off + a.off / 8;   // what reserve() allocates for this request
+}
+
 }  // namespace
 
 // ---- C ABI ------------------------------------------------------------------
@@ -568,6 +619,26 @@ const char* bcur_status_str(int status) {
 const char* bcur_last_error(const bcur_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
 
 size_t bcur_workspace_bytes(const bcur_ctx* ctx) { return ctx ? ctx->ws_bytes : 0; }
+
+bcur_status bcur_release_workspace(bcur_ctx* ctx) {
+    if (!ctx) return BCUR_E_ARG;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (ctx->ws) HIPCHK(hipFree(ctx->ws));
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+    return BCUR_OK;
+}
+
+bcur_status bcur_footprint(int64_t m, int64_t n, const int64_t* col_off, int64_t G, const int64_t* row_off, int64_t Gr,
+                           const bcur_params* p, int32_t library_holds_u, size_t* bytes) {
+    if (!p || !col_off || !bytes || G < 1 || m < 1 || n < 1) return BCUR_E_ARG;
+    int64_t maxw = 0, maxh = 0;
+    for (int64_t g = 0; g < G; ++g) maxw = std::max(maxw, col_off[g + 1] - col_off[g]);
+    if (row_off)
+        for (int64_t g = 0; g < Gr; ++g) maxh = std::max(maxh, row_off[g + 1] - row_off[g]);
+    *bytes = decompose_ws_bytes(m, n, G, maxw, row_off ? Gr : 0, maxh, p, library_holds_u != 0);
+    return BCUR_OK;
+}
 
 bcur_status bcur_create(bcur_ctx** out, int device, void* stream) {
     if (!out) return BCUR_E_ARG;
@@ -835,27 +906,6 @@ bcur_status bcur_fit_columns(bcur_ctx* ctx, const float* A, int64_t m, int64_t n
     return BCUR_OK;
 }
 
-// Sampling buffers for one side (columns or rows).
-struct SampleBufs {
-    int64_t *off, *idx, *list;
-    double *sc, *w, *mg;
-    uint64_t *dr, *qb, *pr;
-    int* st;
-};
-
-void sample_layout(Arena& a, SampleBufs& b, int64_t G, int64_t s, int64_t listmax) {
-    b.off = a.take<int64_t>(G + 1);
-    b.sc = a.take<double>(G);
-    b.dr = a.take<uint64_t>(s);
-    b.qb = a.take<uint64_t>(G);
-    b.pr = a.take<uint64_t>(G);
-    b.idx = a.take<int64_t>(s);
-    b.w = a.take<double>(s);
-    b.mg = a.take<double>(s);
-    b.st = a.take<int>(4);
-    b.list = a.take<int64_t>(std::max<int64_t>(listmax, 1));
-}
-
 bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda, const int64_t* col_off,
                            int64_t G, const int64_t* row_off, int64_t Gr, const bcur_params* p, const float* omega,
                            const uint64_t* draws, bcur_result* res) {
@@ -1044,7 +1094,8 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
         fl = fo.flags;
     }
     int rinfo[4];
-    HIPCHK(hipMemcpy(rinfo, rb.info, sizeof rinfo, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpyAsync(rinfo, rb.info, sizeof rinfo, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
     if (rinfo[0] & 1) fl |= BCUR_FLAG_RANKDEF_Y;
     if (hc.st[1] || (rowv && hr.st[1])) fl |= BCUR_FLAG_ZERO_SCORE;
     memcpy(res->idx, hc.idx, s * sizeof(int64_t));
