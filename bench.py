@@ -51,6 +51,84 @@ def cpu_baseline(w, budget_s=20.0):
                       f"(numpy/LAPACK, {el:.1f} s)"}
 
 
+def serve_bench(args):
+    """Continuous batching under Poisson arrivals (the serving workload):
+    requests of m in [256, 8192] x n in [256, 4096], rank 5..50 (k = rank),
+    block width in {8, 16, 32, 64}, s in [4, 32].  A pool of seeded request
+    matrices is generated once and reused (each request has its own test
+    matrix and draws).  Measures the saturation throughput (all requests
+    submitted at once), then p50/p99 latency at arrival rates that are
+    fractions of it, and mixed precision (BF16 range finder) against plain
+    FP32 at saturation, with the largest per-request residual gap."""
+    import numpy as np
+    import torch
+
+    from paper_1703_06065_amd import Server
+    from paper_1703_06065_amd.binding import PREC_BF16, PREC_FP32, to_device
+    from workloads import gen
+
+    pool = [gen.serving_request(i) for i in range(args.pool)]
+    dev = [(to_device(w.A), torch.from_numpy(w.omega).cuda()) for w in pool]
+    torch.cuda.synchronize()
+
+    def run(n_req, rate, precision):
+        srv = Server(0, hbm_budget=args.budget_gib << 30, max_slots=args.slots)
+        rng = np.random.default_rng(12345)
+        gaps = rng.exponential(1.0 / rate, size=n_req) if rate > 0 else np.zeros(n_req)
+        tickets = []
+        t0 = time.perf_counter()
+        next_t = t0
+        for i in range(n_req):
+            next_t += gaps[i]
+            while True:
+                now = time.perf_counter()
+                if now >= next_t:
+                    break
+                time.sleep(min(0.0005, next_t - now))
+            w = pool[i % len(pool)]
+            A, om = dev[i % len(pool)]
+            tickets.append((i % len(pool), srv.submit(A, w.offsets, w.k, w.s, om, gen.draws_u64(w.s, 7919 + i),
+                                                      q=w.q, precision=precision)))
+        errs = {}
+        for j, t in tickets:
+            r = srv.wait(t)
+            errs.setdefault(j, []).append(r["err"])
+        st = srv.stats()
+        srv.close()
+        print(f"[serve] {n_req} requests at rate {rate:.1f}/s ({'bf16' if precision == PREC_BF16 else 'fp32'}): "
+              f"{st['throughput']:.1f}/s p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms", file=sys.stderr,
+              flush=True)
+        return st, errs
+
+    # warm up every slot and shape
+    run(min(2 * len(pool), args.requests), 0, PREC_FP32)
+    sat, errs32 = run(args.requests, 0, PREC_FP32)
+    sat_mixed, errs16 = run(args.requests, 0, PREC_BF16)
+    sweep = []
+    for frac in (0.25, 0.5, 0.75, 0.9, 1.0, 1.25):
+        st, _ = run(args.requests, frac * sat["throughput"], PREC_FP32)
+        sweep.append({"rate_frac": frac, "offered_per_s": round(frac * sat["throughput"], 2),
+                      "throughput": round(st["throughput"], 2), "p50_ms": round(st["p50_ms"], 3),
+                      "p99_ms": round(st["p99_ms"], 3), "peak_running": st["peak_running"]})
+    gap = 0.0
+    for j in errs32:
+        for a, b in zip(errs32[j], errs16.get(j, [])):
+            gap = max(gap, abs(a - b) / max(a, 1e-300))
+    out = {
+        "metric": "served block-CUR decompositions/s and p50/p99 latency",
+        "value": sat["throughput"], "unit": "decompositions/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f32", "data": f"synthetic serving mix, pool of {len(pool)} seeded matrices",
+        "config": {"workload": "serving: m 256-8192, n 256-4096, rank 5-50, block 8-64, s 4-32",
+                   "requests_per_point": args.requests, "slots": args.slots, "budget_gib": args.budget_gib},
+        "saturation": {"fp32": round(sat["throughput"], 2), "mixed_bf16": round(sat_mixed["throughput"], 2),
+                       "mixed_over_fp32": round(sat_mixed["throughput"] / sat["throughput"], 3),
+                       "max_rel_residual_gap_mixed_vs_fp32": gap,
+                       "p50_ms_fp32": round(sat["p50_ms"], 3), "p99_ms_fp32": round(sat["p99_ms"], 3)},
+        "poisson_sweep": sweep,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -58,10 +136,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--mode", choices=["decompose", "serve"], default="decompose")
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--pool", type=int, default=24)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--budget-gib", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.mode == "serve":
+        serve_bench(args)
+        return
 
     import numpy as np
     import torch
