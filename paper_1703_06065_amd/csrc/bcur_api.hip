@@ -197,6 +197,7 @@ inline int64_t round8(int64_t x) { return (x + 7) & ~(int64_t)7; }
 struct RFBufs {
     float *Q, *Y, *Z, *part;
     double *gpart, *T, *Rinv, *Wk, *Wks, *lam;
+    void* jws;
     int* info;
     // BF16 operands (k contiguous): A, A^T, Q^T, Z^T
     uint16_t *Abf, *AbfT, *QT, *ZT;
@@ -230,6 +231,7 @@ void rf_layout(Arena& a, RFBufs& b, int64_t m, int64_t n, int64_t l, int64_t k, 
     b.Wk = a.take<double>(l * k);
     b.Wks = a.take<double>(l * k);
     b.lam = a.take<double>(l);
+    b.jws = a.take<double>((jacobi_ws_bytes(l) + 7) / 8);
     b.info = a.take<int>(4);
 }
 
@@ -256,7 +258,7 @@ bcur_status cholqr(bcur_ctx* ctx, const RFBufs& b, const float* X, int64_t rows,
     const int w = gram_wgs(rows);
     HIPCHK(launch_gram64(X, rows, l, lp, b.gpart, w, ctx->stream));
     HIPCHK(launch_gram_reduce(b.gpart, w, l, b.T, ctx->stream));
-    HIPCHK(launch_chol_rinv_small(b.T, 1, l, b.Rinv, b.info, ctx->stream));
+    HIPCHK(launch_chol_rinv_small(b.T, l, b.Rinv, b.info, ctx->stream));
     HIPCHK(launch_apply_small(X, rows, l, lp, b.Rinv, l, l, out, lp, ctx->stream));
     return BCUR_OK;
 }
@@ -340,7 +342,7 @@ bcur_status range_finder_run(bcur_ctx* ctx, const RFBufs& b, const float* A, int
     const int wz = gram_wgs(m);
     HIPCHK(launch_gram64(b.Z, m, l, lp, b.gpart, wz, st));
     HIPCHK(launch_gram_reduce(b.gpart, wz, l, b.T, st));
-    HIPCHK(launch_jacobi_eigh(b.T, 1, l, k, b.lam, b.Wk, b.Wks, b.info + 2, st));
+    HIPCHK(launch_jacobi_eigh(b.T, l, k, b.lam, b.Wk, b.Wks, b.jws, b.info + 2, st));
     HIPCHK(launch_apply_small(b.Q, n, l, lp, b.Wk, k, k, Vk, k, st));
     if (Uk) HIPCHK(launch_apply_small(b.Z, m, l, lp, b.Wks, k, k, Uk, k, st));
     return BCUR_OK;

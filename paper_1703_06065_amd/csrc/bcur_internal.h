@@ -81,16 +81,16 @@ hipError_t launch_gram64(const float* X, int64_t rows, int64_t l, int64_t ldx, d
 hipError_t launch_gram_reduce(const double* partial, int parts, int64_t l, double* T, hipStream_t st);
 // T = sum of the partials; T + shift I = R^T R (R upper), Rinv = R^-1 (l x l upper),
 // shift = l 2^-52 trace(T).  info[0] |= 1 when the smallest pivot was below 10 * shift.
-hipError_t launch_chol_rinv_small(const double* partial, int parts, int64_t l, double* Rinv, int* info,
-                                  hipStream_t st);
+hipError_t launch_chol_rinv_small(const double* T, int64_t l, double* Rinv, int* info, hipStream_t st);
 // out (rows x lo, FP32, ldo) = X (rows x li, FP32, ldx) * M (li x lo, FP64, ldm)
 hipError_t launch_apply_small(const float* X, int64_t rows, int64_t li, int64_t ldx, const double* M,
                               int64_t lo, int64_t ldm, float* out, int64_t ldo, hipStream_t st);
-// Symmetric eigensolver (one workgroup, cyclic Jacobi) of T = sum of the partials:
+// Symmetric eigensolver (cyclic Jacobi) of the l x l matrix T (FP64):
 // lam (l, descending), Wk (l x k, FP64), Wks = Wk diag(1/sqrt(lam)) (l x k) or null;
-// info[0] = sweeps, info[1] = 1 when converged.
-hipError_t launch_jacobi_eigh(const double* partial, int parts, int64_t l, int64_t k, double* lam, double* Wk,
-                              double* Wks, int* info, hipStream_t st);
+// info[0] = sweeps, info[1] = 1 when converged.  ws: jacobi_ws_bytes(l) bytes.
+size_t jacobi_ws_bytes(int64_t l);
+hipError_t launch_jacobi_eigh(const double* T, int64_t l, int64_t k, double* lam, double* Wk, double* Wks, void* ws,
+                              int* info, hipStream_t st);
 
 // ---- blocked FP64 Cholesky inverse (k_dense64.hip) -------------------------
 size_t spd_inverse_ws_doubles(int64_t c);

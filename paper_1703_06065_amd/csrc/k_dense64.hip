@@ -12,6 +12,7 @@ namespace {
 
 constexpr int NB = 64;   // panel width and GEMM tile
 constexpr int KB = 16;   // GEMM k step
+constexpr int kFullChol = 256;   // largest c factored by one workgroup
 
 // acc (thread's 4x4 at rows ty + 16 i, cols tx + 16 j of a 64x64 tile) +=
 // op(A)[0:M, 0:K] op(B)[0:K, 0:N]; A, B point at the tile's origin.
@@ -104,50 +105,100 @@ __global__ __launch_bounds__(256) void k_maxdiag(const double* __restrict__ G, i
     }
 }
 
-// Cholesky of the w x w diagonal block at (j0, j0) of G in LDS.  A column
-// whose Schur-complement pivot is not above tau = c rel_tau max diag(G) is
+// Cholesky of the w x w diagonal block at (j0, j0) of G (w <= 64), with the
+// inverse of its factor, in registers (reg_chol_inv).  A column whose
+// Schur-complement pivot is not above tau = c rel_tau max diag(G) is
 // numerically in the span of the columns before it: it is dropped (flagged),
-// its column of L is zeroed so it updates nothing, and its row of L^-1 is
-// zeroed so the inverse built from L^-1 is that of the kept columns, with
-// zero rows and columns for the dropped ones.  Writes L (lower, upper part of
-// the block zeroed) into G and L^-1 (NB x NB, zero padded) into Linv.
+// its column of L is zero so it updates nothing, and its row of L^-1 is zero so
+// the inverse built from L^-1 is that of the kept columns, with zero rows and
+// columns for the dropped ones.  Writes L^-1 (NB x NB, lower, zero padded) into
+// Linv; G is only read (the diagonal block of L is not needed later).
 // piv[0..1] receive the smallest and largest pivot.
-__global__ __launch_bounds__(256) void k_potrf_diag(double* __restrict__ G, int64_t c, int64_t j0, int w,
-                                                    const double* __restrict__ maxdiag, double rel_tau,
-                                                    double* __restrict__ Linv, double* __restrict__ piv,
-                                                    int* __restrict__ info) {
-    constexpr int LD = NB + 1;
-    __shared__ double S[NB * LD];
-    __shared__ double base[NB * 8];
-    __shared__ double sq[NB];
-    __shared__ int drop[NB];
-    const int tid = threadIdx.x;
+__global__ __launch_bounds__(64) void k_potrf_diag(const double* __restrict__ G, int64_t c, int64_t j0, int w,
+                                                     const double* __restrict__ maxdiag, double rel_tau,
+                                                     double* __restrict__ Linv, double* __restrict__ piv,
+                                                     int* __restrict__ info) {
+    constexpr int TG = 8, NR = 8;
+    __shared__ double P[2 * TG * NR + 1];
+    __shared__ double pv[TG * NR];
+    const int tid = threadIdx.x, tr = tid / TG, tc = tid % TG;
     const double tau = (double)c * rel_tau * maxdiag[0];
-    const int wp = pow2_at_least8(w);
-    for (int e = tid; e < w * w; e += 256) {
-        const int i = e / w, j = e % w;
-        S[i * LD + j] = G[(j0 + i) * c + (j0 + j)];
-    }
+    double m[NR * (NR + 1) / 2];
+#pragma unroll
+    for (int a = 0; a < NR; ++a)
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+            const int i = tr + TG * a, cc = tc + TG * b;
+            m[tri_slot(a, b)] = (i < w && cc <= i) ? G[(j0 + i) * c + (j0 + cc)] : 0.0;
+        }
     double pmin, pmax;
-    lds_cholesky(S, LD, w, wp, tau > 0.0 ? tau : 0.0, drop, sq, pmin, pmax);
-    // L back to G (upper part of the block zeroed)
-    for (int e = tid; e < w * w; e += 256) {
-        const int i = e / w, j = e % w;
-        G[(j0 + i) * c + (j0 + j)] = j <= i ? S[i * LD + j] : 0.0;
-    }
-    __syncthreads();
-    lds_tri_inverse(S, LD, wp, drop, base);
-    for (int e = tid; e < NB * NB; e += 256) {
-        const int i = e / NB, j = e % NB;
-        Linv[e] = (i < w && j < w && j <= i) ? S[i * LD + j] : 0.0;
-    }
+    int ndrop;
+    reg_chol_inv<TG, NR>(m, w, tau > 0.0 ? tau : 0.0, P, pv, pmin, pmax, ndrop);
+#pragma unroll
+    for (int a = 0; a < NR; ++a)
+#pragma unroll
+        for (int b = 0; b < NR; ++b) {
+            const int i = tr + TG * a, cc = tc + TG * b;
+            double v = 0.0;
+            if (b <= a && i < w && cc <= i) v = m[tri_slot(a, b < a ? b : a)];
+            Linv[i * NB + cc] = v;
+        }
     if (tid == 0) {
         piv[0] = pmin;
         piv[1] = pmax;
-        int flag = 0;
-        for (int j = 0; j < w; ++j) flag |= drop[j];
-        if (flag) atomicOr(info, 1);
+        if (ndrop) atomicOr(info, 1);
     }
+}
+
+// The whole factorization for c <= 256 in one workgroup: tau from the largest
+// diagonal entry, then reg_chol_inv on the full matrix; writes X = L^-1 (c x c,
+// zero above the diagonal) and the pivot range into every piv pair.
+__global__ __launch_bounds__(1024) void k_chol_inv_full(const double* __restrict__ G, int64_t c, double rel_tau,
+                                                        double* __restrict__ X, double* __restrict__ piv, int npiv,
+                                                        int* __restrict__ info) {
+    constexpr int TG = 32, NR = 8, NT = TG * TG;
+    __shared__ double P[2 * TG * NR + 1];
+    __shared__ double pv[TG * NR];
+    __shared__ double wmax[NT / 64];
+    const int tid = threadIdx.x, tr = tid / TG, tc = tid % TG;
+    const int w = (int)c;
+    double m[NR * (NR + 1) / 2];
+#pragma unroll
+    for (int a = 0; a < NR; ++a)
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+            const int i = tr + TG * a, cc = tc + TG * b;
+            m[tri_slot(a, b)] = (i < w && cc <= i) ? G[(int64_t)i * c + cc] : 0.0;
+        }
+    // largest diagonal entry: wave maxima, then the wave results
+    double dm = tid < w ? G[(int64_t)tid * c + tid] : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o, 64));
+    if ((tid & 63) == 0) wmax[tid >> 6] = dm;
+    __syncthreads();
+    dm = 0.0;
+#pragma unroll
+    for (int u = 0; u < NT / 64; ++u) dm = fmax(dm, wmax[u]);
+    const double tau = (double)c * rel_tau * dm;
+    double pmin, pmax;
+    int ndrop;
+    reg_chol_inv<TG, NR>(m, w, tau > 0.0 ? tau : 0.0, P, pv, pmin, pmax, ndrop);
+    // the owner of (i, c) also writes the zero at (c, i) above the diagonal
+#pragma unroll
+    for (int a = 0; a < NR; ++a)
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+            const int i = tr + TG * a, cc = tc + TG * b;
+            if (i < w && cc <= i) {
+                X[(int64_t)i * c + cc] = m[tri_slot(a, b)];
+                if (cc < i) X[(int64_t)cc * c + i] = 0.0;
+            }
+        }
+    if (tid < npiv) {
+        piv[2 * tid] = pmin;
+        piv[2 * tid + 1] = pmax;
+    }
+    if (tid == 0 && ndrop) atomicOr(info, 1);
 }
 
 // One anti-diagonal of the blocked inverse X = L^-1 (lower):
@@ -250,12 +301,18 @@ static hipError_t chol_and_inverse_factor(double* G, int64_t c, double* ws, int*
     double* X = Linv + nblk * NB * NB;
     double* pivb = X + c * c;
     double* maxd = pivb + 2 * nblk;
+    if (c <= kFullChol) {
+        hipLaunchKernelGGL(k_chol_inv_full, dim3(1), dim3(1024), 0, st, (const double*)G, c, rel_tau, X,
+                           piv ? piv : pivb, (int)nblk, info);
+        *Xout = X;
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_maxdiag, dim3(1), dim3(256), 0, st, (const double*)G, c, maxd);
     for (int64_t jb = 0; jb < nblk; ++jb) {
         const int64_t j0 = jb * NB;
         const int w = (int)(c - j0 < NB ? c - j0 : NB);
-        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, st, G, c, j0, w, (const double*)maxd, rel_tau,
-                           Linv + jb * NB * NB, pivb + 2 * jb, info);
+        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(64), 0, st, (const double*)G, c, j0, w,
+                           (const double*)maxd, rel_tau, Linv + jb * NB * NB, pivb + 2 * jb, info);
         const int64_t rows = c - j0 - w;
         if (rows > 0) {
             double* L21 = G + (j0 + w) * c + j0;

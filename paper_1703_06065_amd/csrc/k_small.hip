@@ -86,44 +86,53 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ 
     if (g == 0 && e < ll) T[e] = ((sg[0][el] + sg[1][el]) + sg[2][el]) + sg[3][el];
 }
 
-// T = sum of the `parts` l x l partial Gram matrices (fixed order); then
-// T + shift I = R^T R with shift = l 2^-52 trace(T), and Rinv = R^-1 (upper,
-// l x l).  One workgroup; LDS holds the padded matrix (row stride wp + 1).
-__global__ __launch_bounds__(256) void k_chol_rinv_small(const double* __restrict__ partial, int parts, int l,
-                                                         double* __restrict__ Rinv, int* __restrict__ info) {
-    constexpr int LD = kMaxL + 1;
-    __shared__ double S[kMaxL * LD];
-    __shared__ double base[kMaxL * 8];
-    __shared__ double dinv[kMaxL];
-    __shared__ int drop[kMaxL];
-    __shared__ double sshift;
-    const int tid = threadIdx.x;
-    const int wp = pow2_at_least8(l);
-    const int ld = wp + 1;
-    const int64_t ll = (int64_t)l * l;
-    for (int i = tid / 16; i < l; i += 16)
-        for (int j = tid & 15; j < l; j += 16) S[i * ld + j] = sum_partials(partial, parts, ll, i * l + j);
-    (void)ll;
+// T + shift I = R^T R for the l x l Gram matrix T (FP64, row-major), with
+// shift = l 2^-52 trace(T), and Rinv = R^-1 (upper, l x l, R = L^T).  One
+// workgroup of TG x TG threads; the matrix lives in registers (reg_chol_inv),
+// l <= TG * NR.  Every entry is loaded and stored by its owning thread.
+template <int TG, int NR>
+__global__ __launch_bounds__(TG* TG) void k_chol_rinv_small(const double* __restrict__ T, int l,
+                                                            double* __restrict__ Rinv, int* __restrict__ info) {
+    __shared__ double P[2 * TG * NR + 1];
+    __shared__ double pv[TG * NR];
+    const int tid = threadIdx.x, tr = tid / TG, tc = tid % TG;
+    double m[NR * (NR + 1) / 2];
+#pragma unroll
+    for (int a = 0; a < NR; ++a)
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+            const int i = tr + TG * a, c = tc + TG * b;
+            m[tri_slot(a, b)] = (i < l && c <= i) ? T[(int64_t)i * l + c] : 0.0;
+        }
+    // trace, summed in index order by every thread
+#pragma unroll
+    for (int a = 0; a < NR; ++a)
+        if (tr == tc && tr + TG * a < l) pv[tr + TG * a] = m[tri_slot(a, a)];
     __syncthreads();
-    if (tid == 0) {
-        double tr = 0.0;
-        for (int i = 0; i < l; ++i) tr += S[i * ld + i];
-        double sh = (double)l * ldexp(1.0, -52) * tr;
-        if (!(sh > 0.0)) sh = 1e-300;
-        sshift = sh;
-    }
+    double tr4[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < l; ++i) tr4[i & 3] += pv[i];
+    double shift = (double)l * ldexp(1.0, -52) * ((tr4[0] + tr4[1]) + (tr4[2] + tr4[3]));
+    if (!(shift > 0.0)) shift = 1e-300;
     __syncthreads();
-    const double shift = sshift;
-    if (tid < l) S[tid * ld + tid] += shift;
+#pragma unroll
+    for (int a = 0; a < NR; ++a)
+        if (tr == tc && tr + TG * a < l) m[tri_slot(a, a)] += shift;
     double pmin, pmax;
-    lds_cholesky(S, ld, l, wp, 0.0, drop, dinv, pmin, pmax);
-    lds_tri_inverse(S, ld, wp, drop, base);
-    // Rinv = X^T: Rinv[c][i] = X[i][c] for i >= c
-    for (int e = tid; e < l * l; e += 256) {
-        const int c = e / l, i = e % l;
-        Rinv[e] = i < c ? 0.0 : S[i * ld + c];
-    }
-    if (tid == 0 && info && (pmin < 10.0 * shift)) atomicOr(info, 1);
+    int ndrop;
+    reg_chol_inv<TG, NR>(m, l, 0.0, P, pv, pmin, pmax, ndrop);
+    // Rinv = X^T: Rinv[c][i] = X[i][c] for i >= c; the owner of (i, c) also
+    // writes the zero at (i, c) below the diagonal
+#pragma unroll
+    for (int a = 0; a < NR; ++a)
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+            const int i = tr + TG * a, c = tc + TG * b;
+            if (i < l && c <= i) {
+                Rinv[(int64_t)c * l + i] = m[tri_slot(a, b)];
+                if (c < i) Rinv[(int64_t)i * l + c] = 0.0;
+            }
+        }
+    if (tid == 0 && info && (pmin < 10.0 * shift || ndrop > 0)) atomicOr(info, 1);
 }
 
 // out (rows x lo) = X (rows x li, FP32) * M (li x lo, FP64), FP64 accumulation.
@@ -188,15 +197,9 @@ __device__ __forceinline__ int pk(int i, int j, int L) {
     return i * L - (i * (i - 1)) / 2 + (j - i);
 }
 
-// Full-precision 1/sqrt(x) and 1/x for x > 0 from the hardware estimates and
-// two Newton steps (the rotations need c^2 + s^2 = 1 to working precision,
-// not correctly rounded operations).
-__device__ __forceinline__ double rsqrt_nr(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-    y = y * fma(-0.5 * x * y, y, 1.5);
-    y = y * fma(-0.5 * x * y, y, 1.5);
-    return y;
-}
+// Full-precision 1/x for x != 0 from the hardware estimate and two Newton
+// steps (the rotations need c^2 + s^2 = 1 to working precision, not correctly
+// rounded operations; rsqrt_nr is its square-root counterpart).
 __device__ __forceinline__ double rcp_nr(double x) {
     double y = __builtin_amdgcn_rcp(x);
     y = y * fma(-x, y, 2.0);
@@ -210,12 +213,12 @@ __device__ __forceinline__ double rcp_nr(double x) {
 // every row of W is updated independently; a sweep is L-1 rounds and the
 // iteration stops after a sweep without rotations.  A pair (p, q) is rotated
 // while |a_pq| > max(2^-51 ||T||_F, 1e-15 sqrt|a_pp a_qq|).
-// The tangent t of each rotation is computed in FP32 (hardware reciprocal and
-// square root); c = 1/sqrt(1 + t^2) and s = t c are then formed in FP64 with
-// Newton-refined estimates, so every rotation is orthogonal to FP64 precision
-// while its angle is accurate to about 2^-23.  The (p, q) entry left by the
-// slightly inexact angle is kept (not forced to zero), so no backward error is
-// introduced; later rounds remove it.
+// The tangent t of each rotation is estimated in FP32 (hardware reciprocal and
+// square root) and refined by one Newton step to about 2^-46; c = 1/sqrt(1 +
+// t^2) and s = t c are then formed in FP64 with Newton-refined estimates, so
+// every rotation is orthogonal to FP64 precision.  The (p, q) entry left by
+// the slightly inexact angle is kept (not forced to zero), so no backward
+// error is introduced; later rounds remove it.
 __device__ __forceinline__ void jacobi_angle(double app, double aqq, double apq, double& c, double& s) {
     const double d = aqq - app;
     double t;
@@ -225,12 +228,19 @@ __device__ __forceinline__ void jacobi_angle(double app, double aqq, double apq,
         // scale both by one power of two so the FP32 conversion cannot overflow
         int e;
         frexp(fmax(fabs(d), fabs(apq)), &e);
-        const float df = (float)ldexp(d, -e), af = (float)ldexp(apq, -e);
+        const double ds = ldexp(d, -e), as = ldexp(apq, -e);
+        const float df = (float)ds, af = (float)as;
         const float tau = df * __builtin_amdgcn_rcpf(2.0f * af);
         const float at = fabsf(tau);
         float tf = __builtin_amdgcn_rcpf(at + __builtin_amdgcn_sqrtf(fmaf(at, at, 1.0f)));
         if (tau < 0.0f) tf = -tf;
-        t = (double)tf;
+        // t is the root of smaller magnitude of  as t^2 + ds t - as = 0; one
+        // Newton step from the FP32 estimate (residual in FP64, the small
+        // correction's quotient in FP32) brings it to about 2^-46
+        const double t0 = (double)tf;
+        const double fv = fma(as * t0, t0, fma(ds, t0, -as));
+        const double fd = fma(2.0 * as, t0, ds);
+        t = t0 - (double)((float)fv * __builtin_amdgcn_rcpf((float)fd));
     }
     c = rsqrt_nr(fma(t, t, 1.0));
     s = t * c;
@@ -400,6 +410,285 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ part
     }
 }
 
+
+// Round-robin schedule: in round rd (0 <= rd < L - 1) pair slot t rotates the
+// index pair (p, q), p < q; the L/2 pairs of a round are disjoint and every
+// pair of indices meets exactly once per sweep.  Index 0 stays put, 1 .. L-1
+// circulate.
+__device__ __forceinline__ void rr_pair(int t, int rd, int L, int& p, int& q) {
+    int xa = t - 1 + rd, xb = L - 2 - t + rd;
+    if (xa >= L - 1) xa -= L - 1;
+    if (xb >= L - 1) xb -= L - 1;
+    const int x = t == 0 ? 0 : 1 + xa, y = 1 + xb;
+    p = x < y ? x : y;
+    q = x < y ? y : x;
+}
+
+
+// The same cyclic Jacobi for L <= 64, split in two kernels.
+//
+// k_jacobi64 (one workgroup) diagonalizes T kept in slot order: pair slot t
+// of the round-robin schedule always occupies positions (2t, 2t+1), holding
+// its top and bottom index (x_t, y_t).  From one round to the next every
+// index moves to a fixed new position (slot_next), the same in every round,
+// so each 2 x 2 block (u, v) of J^T T J is read from fixed positions and
+// written to fixed permuted ones in the other copy of T (only the upper
+// triangle is stored).  Wave 0 computes the rotations, lane t for slot t, and
+// records them; after one barrier every thread applies them to its blocks.
+// k_jacobi_vectors then forms rows of W = J_1 J_2 ... J_R from the record,
+// two rows per wave across many workgroups, and writes the first k columns in
+// eigenvalue order.
+//
+// The rotation of slot (x, y) is taken from T scaled by 1 / ||T||_F: it is
+// made when |a_xy| > 2^-40 ||T||_F and |a_xy| > 1e-15 sqrt|a_xx a_yy|.  The
+// tangent t is estimated in FP32 and refined by one Newton step to about
+// 2^-46; c = 1/sqrt(1 + t^2) and s = t c are formed in FP64 with
+// Newton-refined estimates, so every rotation is orthogonal to FP64 precision.
+constexpr int kJ64 = 64, kJ64LD = 65, kJSweeps = 40;
+
+// Indices (x, y) of pair slot t in round rd: index 0 stays in slot 0, the
+// others circulate (x_t = 1 + (t - 1 + rd) mod (L - 1), y_t = 1 + (L - 2 - t +
+// rd) mod (L - 1)); advanced by one per round (period L - 1).
+struct RRSlot {
+    int xa, xb;
+    __device__ void init(int t, int L) {
+        xa = t - 1;
+        xb = L - 2 - t;
+        if (xa < 0) xa += L - 1;
+    }
+    __device__ void pair(int t, int& x, int& y) const {
+        x = t == 0 ? 0 : 1 + xa;
+        y = 1 + xb;
+    }
+    __device__ void next(int L) {
+        xa = xa + 1 == L - 1 ? 0 : xa + 1;
+        xb = xb + 1 == L - 1 ? 0 : xb + 1;
+    }
+};
+
+// Position, in the next round, of what sits at position `pos` now.
+__device__ __forceinline__ int slot_next(int pos, int H) {
+    if (H == 1 || pos == 0) return pos;
+    if (pos == 2) return 1;
+    if ((pos & 1) == 0) return pos - 2;
+    return pos == 2 * H - 1 ? 2 * H - 2 : pos + 2;
+}
+// Position of index i in the first round of a sweep.
+__device__ __forceinline__ int slot_pos0(int i, int L) { return i < L / 2 ? 2 * i : 2 * (L - 1 - i) + 1; }
+__device__ __forceinline__ int up_idx(int i, int j) { return i <= j ? i * kJ64LD + j : j * kJ64LD + i; }
+
+// Rotation from the scaled entries (|ds|, |as| <= 2, |as| > 2^-40).
+__device__ __forceinline__ void jacobi_rotation_scaled(double ds, double as, double& c, double& s) {
+    const float df = (float)ds, af = (float)as;
+    const float tau = df * __builtin_amdgcn_rcpf(2.0f * af);
+    const float at = fabsf(tau);
+    float tf = __builtin_amdgcn_rcpf(at + __builtin_amdgcn_sqrtf(fmaf(at, at, 1.0f)));
+    if (tau < 0.0f) tf = -tf;
+    // t is the root of smaller magnitude of  as t^2 + ds t - as = 0
+    const double t0 = (double)tf;
+    const double fv = fma(as * t0, t0, fma(ds, t0, -as));
+    const double fd = fma(2.0 * as, t0, ds);
+    const double t = t0 - (double)((float)fv * __builtin_amdgcn_rcpf((float)fd));
+    c = rsqrt_nr(fma(t, t, 1.0));
+    s = t * c;
+}
+
+__global__ __launch_bounds__(512) void k_jacobi64(const double* __restrict__ Tin, int l, double* __restrict__ lam_out,
+                                                  double2* __restrict__ rot, int* __restrict__ meta,
+                                                  int* __restrict__ info) {
+    __shared__ double Tb[2][kJ64 * kJ64LD];
+    __shared__ double2 cs[kJ64 / 2];
+    __shared__ double sred[8];
+    __shared__ int flag[2];
+    constexpr int NT = 512, NB = 2;  // blocks per thread: e = tid + NT r
+    const int tid = threadIdx.x;
+    const int L = l + (l & 1), H = L / 2, nblk = H * (H + 1) / 2;
+    // slot-ordered upper triangle: entry (i, j) of T at positions (pos0(i), pos0(j))
+    const int jc = tid & 63;
+    double tv[kJ64 / 8];
+#pragma unroll
+    for (int u = 0; u < kJ64 / 8; ++u) {
+        const int i = (tid >> 6) + 8 * u;
+        tv[u] = (i <= jc && jc < l) ? Tin[(int64_t)i * l + jc] : 0.0;
+    }
+    double f = 0.0;
+#pragma unroll
+    for (int u = 0; u < kJ64 / 8; ++u) {
+        const int i = (tid >> 6) + 8 * u;
+        if (i <= jc && jc < L) Tb[0][up_idx(slot_pos0(i, L), slot_pos0(jc, L))] = tv[u];
+        if (i <= jc) f += (i == jc ? 1.0 : 2.0) * tv[u] * tv[u];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) f += __shfl_xor(f, o, 64);
+    if ((tid & 63) == 0) sred[tid >> 6] = f;
+    if (tid < 2) flag[tid] = 0;
+    // this thread's blocks (u <= v) of the packed list, row u starting at u H - u (u - 1) / 2,
+    // with their fixed read and write positions
+    int buv[NB], rdx[NB][4], wrx[NB][4];
+    bool bok[NB], bdiag[NB];
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+        const int e = tid + NT * r;
+        bok[r] = e < nblk;
+        int u = 0;
+        while (bok[r] && (u + 1) * H - ((u + 1) * u) / 2 <= e) ++u;
+        const int v = bok[r] ? u + (e - (u * H - (u * (u - 1)) / 2)) : 0;
+        bdiag[r] = u == v;
+        buv[r] = u | (v << 8);
+        // entries (a0 b0, a0 b1, a1 b0, a1 b1); on the diagonal a1 b0 is a0 b1
+        const int a0 = 2 * u, a1 = 2 * u + 1, b0 = 2 * v, b1 = 2 * v + 1;
+        rdx[r][0] = up_idx(a0, b0);
+        rdx[r][1] = up_idx(a0, b1);
+        rdx[r][2] = up_idx(a1, b0);
+        rdx[r][3] = up_idx(a1, b1);
+        const int na0 = slot_next(a0, H), na1 = slot_next(a1, H), nb0 = slot_next(b0, H), nb1 = slot_next(b1, H);
+        wrx[r][0] = up_idx(na0, nb0);
+        wrx[r][1] = up_idx(na0, nb1);
+        wrx[r][2] = up_idx(na1, nb0);
+        wrx[r][3] = up_idx(na1, nb1);
+    }
+    __syncthreads();
+    const double snorm = sqrt(((sred[0] + sred[1]) + (sred[2] + sred[3])) + ((sred[4] + sred[5]) + (sred[6] + sred[7])));
+    const double inv = snorm > 0.0 ? 1.0 / snorm : 0.0;
+    const double floor_s = ldexp(1.0, -40);
+    const int t = tid;  // wave 0: lane t computes slot t
+    int cur = 0, R = 0, sweeps = 0, converged = 0;
+    for (int sw = 0; sw < kJSweeps; ++sw) {
+        if (tid == 0) flag[sw & 1] = 0;
+        for (int rd = 0; rd < L - 1; ++rd, ++R) {
+            const double* T = Tb[cur];
+            double* Tn = Tb[cur ^ 1];
+            double x[NB][4];
+#pragma unroll
+            for (int r = 0; r < NB; ++r)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) x[r][e] = T[rdx[r][e]];
+            if (tid < 64) {
+                double c = 1.0, s = 0.0;
+                if (t < H) {
+                    const double axx = T[(2 * t) * kJ64LD + 2 * t], ayy = T[(2 * t + 1) * kJ64LD + 2 * t + 1];
+                    const double axy = T[(2 * t) * kJ64LD + 2 * t + 1];
+                    const double as = axy * inv;
+                    if (fabs(as) > floor_s && axy * axy > 1e-30 * fabs(axx * ayy))
+                        jacobi_rotation_scaled((ayy - axx) * inv, as, c, s);
+                    cs[t] = make_double2(c, s);
+                    rot[(int64_t)R * H + t] = make_double2(c, s);
+                }
+                if (__ballot(s != 0.0) != 0 && tid == 0) flag[sw & 1] = 1;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < NB; ++r) {
+                if (!bok[r]) continue;
+                const double2 ru = cs[buv[r] & 0xff], rv = cs[buv[r] >> 8];
+                const double c1 = ru.x, s1 = ru.y, c2 = rv.x, s2 = rv.y;
+                if (bdiag[r]) {
+                    // x = (a_xx, a_xy, a_xy, a_yy) of one slot
+                    const double y00 = c1 * x[r][0] - s1 * x[r][1], y01 = c1 * x[r][1] - s1 * x[r][3];
+                    const double y10 = s1 * x[r][0] + c1 * x[r][1], y11 = s1 * x[r][1] + c1 * x[r][3];
+                    Tn[wrx[r][0]] = y00 * c1 - y01 * s1;
+                    Tn[wrx[r][1]] = y00 * s1 + y01 * c1;
+                    Tn[wrx[r][3]] = y10 * s1 + y11 * c1;
+                } else {
+                    const double y00 = c1 * x[r][0] - s1 * x[r][2], y01 = c1 * x[r][1] - s1 * x[r][3];
+                    const double y10 = s1 * x[r][0] + c1 * x[r][2], y11 = s1 * x[r][1] + c1 * x[r][3];
+                    Tn[wrx[r][0]] = y00 * c2 - y01 * s2;
+                    Tn[wrx[r][1]] = y00 * s2 + y01 * c2;
+                    Tn[wrx[r][2]] = y10 * c2 - y11 * s2;
+                    Tn[wrx[r][3]] = y10 * s2 + y11 * c2;
+                }
+            }
+            cur ^= 1;
+            __syncthreads();
+        }
+        ++sweeps;
+        if (!flag[sw & 1]) {
+            converged = 1;
+            break;
+        }
+    }
+    // eigenvalues descending (ties by index); after whole sweeps index i is at slot_pos0(i)
+    const double* T = Tb[cur];
+    if (tid < l) {
+        const int pi = slot_pos0(tid, L);
+        const double li = T[pi * kJ64LD + pi];
+        int rank = 0;
+        for (int j = 0; j < l; ++j) {
+            const int pj = slot_pos0(j, L);
+            const double lj = T[pj * kJ64LD + pj];
+            rank += (lj > li) || (lj == li && j < tid);
+        }
+        lam_out[rank] = li;
+        meta[1 + tid] = rank;
+    }
+    if (tid == 0) {
+        meta[0] = converged ? R - (L - 1) : R;  // a converged last sweep rotated nothing
+        if (info) {
+            info[0] = sweeps;
+            info[1] = converged;
+        }
+    }
+}
+
+// Rows 2 blockIdx.x + half of W from the recorded rotations (one wave; lane
+// t of each half applies pair t), then Wk[i][rank] = W[i][col] for the k
+// leading eigenvalues and Wks = Wk diag(1/sqrt(lam)).  Rotations are staged
+// 16 rounds at a time in registers.
+__global__ __launch_bounds__(64) void k_jacobi_vectors(const double2* __restrict__ rot, const int* __restrict__ meta,
+                                                       const double* __restrict__ lam, int l, int k,
+                                                       double* __restrict__ Wk, double* __restrict__ Wks) {
+    __shared__ double row[2][kJ64];
+    constexpr int CH = 16;
+    const int lane = threadIdx.x, t = lane & 31, half = lane >> 5;
+    const int i = 2 * blockIdx.x + half;
+    const int L = l + (l & 1), H = L / 2;
+    const int R = meta[0];
+    row[half][t] = (t == i) ? 1.0 : 0.0;
+    row[half][t + 32] = (t + 32 == i) ? 1.0 : 0.0;
+    __syncthreads();
+    const int tt = t < H ? t : 0;
+    RRSlot st;
+    st.init(tt, L);
+    double* w = row[half];
+    for (int r0 = 0; r0 < R; r0 += CH) {
+        double2 cs[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+            cs[u] = (r0 + u < R && t < H) ? rot[(int64_t)(r0 + u) * H + t] : make_double2(1.0, 0.0);
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            if (r0 + u < R) {
+                int x, y;
+                st.pair(tt, x, y);
+                if (cs[u].y != 0.0) {
+                    const double wx = w[x], wy = w[y];
+                    w[x] = cs[u].x * wx - cs[u].y * wy;
+                    w[y] = cs[u].y * wx + cs[u].x * wy;
+                }
+                st.next(L);
+            }
+            // the next round's pairs read what this round wrote (in-order LDS within the wave)
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    __syncthreads();
+    if (i < l) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int col = t + 32 * e;
+            if (col < l) {
+                const int rank = meta[1 + col];
+                if (rank < k) {
+                    const double lv = lam[rank];
+                    const double v = w[col];
+                    Wk[(int64_t)i * k + rank] = v;
+                    if (Wks) Wks[(int64_t)i * k + rank] = v * (lv > 0.0 ? 1.0 / sqrt(lv) : 0.0);
+                }
+            }
+        }
+    }
+}
+
 }  // namespace
 
 int gram_wgs(int64_t rows) {
@@ -425,10 +714,13 @@ hipError_t launch_gram_reduce(const double* partial, int parts, int64_t l, doubl
     return hipGetLastError();
 }
 
-hipError_t launch_chol_rinv_small(const double* partial, int parts, int64_t l, double* Rinv, int* info,
-                                  hipStream_t st) {
+hipError_t launch_chol_rinv_small(const double* T, int64_t l, double* Rinv, int* info, hipStream_t st) {
     if (l < 1 || l > kMaxL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_chol_rinv_small, dim3(1), dim3(256), 0, st, partial, parts, (int)l, Rinv, info);
+    // one wave up to l = 64 (a step is latency-bound: fewer waves, cheaper barrier), four above
+    if (l <= 64)
+        hipLaunchKernelGGL((k_chol_rinv_small<8, 8>), dim3(1), dim3(64), 0, st, T, (int)l, Rinv, info);
+    else
+        hipLaunchKernelGGL((k_chol_rinv_small<16, 8>), dim3(1), dim3(256), 0, st, T, (int)l, Rinv, info);
     return hipGetLastError();
 }
 
@@ -443,12 +735,25 @@ hipError_t launch_apply_small(const float* X, int64_t rows, int64_t li, int64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_jacobi_eigh(const double* partial, int parts, int64_t l, int64_t k, double* lam, double* Wk,
-                              double* Wks, int* info, hipStream_t st) {
+size_t jacobi_ws_bytes(int64_t l) {
+    const int64_t L = l + (l & 1), H = L / 2;
+    return (size_t)kJSweeps * (size_t)(L - 1) * (size_t)H * sizeof(double2) + (size_t)(l + 1) * sizeof(int) + 256;
+}
+
+hipError_t launch_jacobi_eigh(const double* T, int64_t l, int64_t k, double* lam, double* Wk, double* Wks, void* ws,
+                              int* info, hipStream_t st) {
     if (l < 1 || l > kMaxLJ || k < 1 || k > l) return hipErrorInvalidValue;
     const int L = (int)l + ((int)l & 1);
-    const int nt = L <= 32 ? 256 : 1024;
-    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(nt), 0, st, partial, parts, (int)l, (int)k, lam, Wk, Wks, info);
+    if (L <= kJ64) {
+        double2* rot = reinterpret_cast<double2*>(ws);
+        const int64_t H = L / 2;
+        int* meta = reinterpret_cast<int*>(rot + (int64_t)kJSweeps * (L - 1) * H);
+        hipLaunchKernelGGL(k_jacobi64, dim3(1), dim3(512), 0, st, T, (int)l, lam, rot, meta, info);
+        hipLaunchKernelGGL(k_jacobi_vectors, dim3((unsigned)((l + 1) / 2)), dim3(64), 0, st, (const double2*)rot,
+                           (const int*)meta, (const double*)lam, (int)l, (int)k, Wk, Wks);
+    } else {
+        hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), 0, st, T, 1, (int)l, (int)k, lam, Wk, Wks, info);
+    }
     return hipGetLastError();
 }
 

@@ -1,126 +1,154 @@
-// One-workgroup FP64 factorizations on a matrix held in LDS, shared by the
-// small-factorization kernels.  Control flow is uniform across the workgroup
-// (every loop bound depends only on the matrix size), so no wave serializes
-// on divergent lanes.
+// One-workgroup FP64 building blocks shared by the small-factorization
+// kernels: a register-resident Cholesky with the inverse of its factor, and a
+// fixed-order sum of partial results.  Control flow is uniform across the
+// workgroup (every loop bound depends only on the matrix size).
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace bcur {
 
-// Right-looking Cholesky of the w x w symmetric matrix in S (row stride ld),
-// in place: on return the lower triangle holds L with S = L L^T.  A pivot
-// (Schur complement) not above `thr` marks its column as dropped: drop[j] = 1,
-// the column of L is zero below a unit diagonal and it updates nothing.
-// Rows and columns w .. wp-1 are set to the identity.  Returns (in every
-// thread) the smallest and largest pivot seen.  One barrier per column.
-// sq (wp doubles of LDS) receives sqrt of the pivots (1 for dropped ones).
-__device__ inline void lds_cholesky(double* S, int ld, int w, int wp, double thr, int* drop, double* sq,
-                                    double& pmin, double& pmax) {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int e = tid; e < wp; e += nt) drop[e] = 0;
-    pmin = INFINITY;
-    pmax = 0.0;
-    for (int j = 0; j < w; ++j) {
-        __syncthreads();
-        const double d = S[j * ld + j];
-        pmin = fmin(pmin, d);
-        pmax = fmax(pmax, d);
-        if (!(d > thr)) {
-            if (tid == 0) drop[j] = 1;
-            continue;
-        }
-        const double rd = 1.0 / d;
-        // lower trailing triangle on a 16-wide thread grid (no integer division)
-        for (int i = j + 1 + tid / 16; i < w; i += nt / 16) {
-            const double lij = S[i * ld + j] * rd;
-            for (int p = j + 1 + (tid & 15); p <= i; p += 16) S[i * ld + p] -= lij * S[p * ld + j];
-        }
-    }
-    __syncthreads();
-    // the pivots' square roots first: the scaling below overwrites the diagonal
-    for (int j = tid; j < wp; j += nt) sq[j] = (j >= w || drop[j]) ? 1.0 : sqrt(S[j * ld + j]);
-    __syncthreads();
-    // scale the columns: L[i][j] = S[i][j] / sqrt(d_j); pad with the identity
-    for (int i = tid / 16; i < wp; i += nt / 16)
-        for (int j = tid & 15; j <= i; j += 16) {
-            double v;
-            if (i >= w || j >= w || drop[j]) v = i == j ? 1.0 : 0.0;
-            else v = i == j ? sq[j] : S[i * ld + j] / sq[j];
-            S[i * ld + j] = v;
-        }
-    __syncthreads();
+// Full-precision 1/sqrt(x) for x > 0 from the hardware estimate and two
+// Newton steps (about 1 ulp; the factorizations need scalings accurate to
+// working precision, not correctly rounded ones).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * fma(-0.5 * x * y, y, 1.5);
+    y = y * fma(-0.5 * x * y, y, 1.5);
+    return y;
 }
 
-// In-place inverse X = L^-1 of the lower-triangular wp x wp matrix in S
-// (row stride ld, wp a power of two >= 8), by recursive 2x2 blocking:
-// X21 = -X22 (L21 X11).  Diagonal 8x8 blocks are inverted first by forward
-// substitution (one column per thread, from a copy in `base`, wp*8 doubles);
-// each doubling step forms T = L21 X11 in the unused strict upper triangle
-// and then overwrites L21 with X21.  A dropped index d (drop[d] != 0) takes
-// 1/L_dd as 0, which zeroes row d and column d of X.  The strict upper
-// triangle of S is clobbered.
-__device__ inline void lds_tri_inverse(double* S, int ld, int wp, const int* drop, double* base) {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    // copy the diagonal 8x8 blocks
-    for (int e = tid; e < wp * 8; e += nt) {
-        const int o = (e >> 6) * 8, i = (e >> 3) & 7, j = e & 7;
-        base[e] = S[(o + i) * ld + o + j];
+// Register-resident Cholesky with the inverse of its factor, one workgroup of
+// TG x TG threads, for a w x w symmetric matrix, w <= TG * NR.
+//
+// Storage: one lower triangle M, entry (i, c) held by thread (i mod TG,
+// c mod TG) in slot tri_slot(i / TG, c / TG).  Step j reads the vector P (row j
+// of M left of the diagonal, column j below it; d = P_j) from LDS, then every
+// row i > j takes the rank-1 update
+//     M[i][c] -= P_i P_c / d      (c != j),      M[i][j] = -P_i / d,
+// and row j becomes final: M[j][c] = P_c / sqrt(d), M[j][j] = 1 / sqrt(d).
+// Columns right of j still hold the Schur complement, columns up to j the
+// rows of the inverse being formed (column-oriented forward substitution of
+// L X = I fused into the right-looking factorization), so after w steps M
+// holds X = L^-1 with G = L L^T.
+// A pivot d not above `thr` drops index j: 1/sqrt(d) is taken as 0, which
+// makes column j of L zero below a unit diagonal and zeroes row and column j
+// of X, so X^T X is the inverse on the kept indices (zero elsewhere).
+//
+// The steps run in chunks of TG (j = TG A + jj) with the chunk A unrolled, so
+// the slot row and column that hold index j, and the rows already final, are
+// known at compile time; what remains at run time is per-lane predication.
+// One barrier per step: P is double-buffered in `P` (2 * TG * NR doubles,
+// plus one more that takes the stores a lane does not make).  The pivots go to `piv` (w doubles of LDS);
+// pmin / pmax receive the smallest and largest pivot, ndrop the dropped count.
+__host__ __device__ constexpr int tri_slot(int a, int b) { return a * (a + 1) / 2 + b; }
+
+template <int TG, int NR, int A>
+struct CholChunk {
+    static __device__ __forceinline__ void run(double (&m)[NR * (NR + 1) / 2], int w, double thr, double* P,
+                                               double* piv, int tr, int tc) {
+        constexpr int WB = TG * NR;
+        double* trash = P + 2 * WB;  // target of the stores a lane does not make
+        if (TG * A < w) {
+            const int jend = (TG * A + TG < w ? TG * A + TG : w) - TG * A;
+            for (int jj = 0; jj < jend; ++jj) {
+                const int j = TG * A + jj;
+                const double* Pc = P + (j & 1) * WB;
+                double* Pn = P + ((j + 1) & 1) * WB;
+                const double d = Pc[j];
+                double pc[NR], pr[NR];
+#pragma unroll
+                for (int b = 0; b < NR; ++b) pc[b] = Pc[tc + TG * b];
+#pragma unroll
+                for (int a = A; a < NR; ++a) pr[a] = Pc[tr + TG * a];
+                if (threadIdx.x == 0) piv[j] = d;
+                const double r = d > thr ? rsqrt_nr(d) : 0.0;
+                const double rd = r * r;
+                const bool colj = tc == jj;  // slot column A of this lane holds index j
+#pragma unroll
+                for (int a = A; a < NR; ++a) {
+                    const double ai = (a > A || tr > jj) ? pr[a] * rd : 0.0;
+#pragma unroll
+                    for (int b = 0; b <= a; ++b) {
+                        double& x = m[tri_slot(a, b)];
+                        const double y = fma(-ai, pc[b], x);
+                        x = (b == A && colj) ? -ai : y;
+                    }
+                }
+                if (tr == jj) {  // row j becomes final
+#pragma unroll
+                    for (int b = 0; b <= A; ++b) {
+                        const double v = pc[b] * r;
+                        m[tri_slot(A, b)] = (b == A && colj) ? r : v;
+                    }
+                }
+                // publish row j+1 (c <= j+1) and column j+1 (rows below it)
+                const int jn = j + 1;
+                if (jn < w) {
+                    if (jj + 1 < TG) {
+                        if (tr == jj + 1) {
+#pragma unroll
+                            for (int b = 0; b <= A; ++b) {
+                                const bool ok = b < A || tc <= jj + 1;
+                                *(ok ? Pn + tc + TG * b : trash) = m[tri_slot(A, b)];
+                            }
+                        }
+                        if (tc == jj + 1) {
+#pragma unroll
+                            for (int a = A; a < NR; ++a) {
+                                const int i = tr + TG * a;
+                                const bool ok = (a > A || tr > jj + 1) && i < w;
+                                *(ok ? Pn + i : trash) = m[tri_slot(a, A)];
+                            }
+                        }
+                    } else if constexpr (A + 1 < NR) {
+                        if (tr == 0) {
+#pragma unroll
+                            for (int b = 0; b <= A + 1; ++b) {
+                                const bool ok = b <= A || tc == 0;
+                                *(ok ? Pn + tc + TG * b : trash) = m[tri_slot(A + 1, b)];
+                            }
+                        }
+                        if (tc == 0) {
+#pragma unroll
+                            for (int a = A + 1; a < NR; ++a) {
+                                const int i = tr + TG * a;
+                                const bool ok = (a > A + 1 || tr > 0) && i < w;
+                                *(ok ? Pn + i : trash) = m[tri_slot(a, A + 1)];
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        if constexpr (A + 1 < NR) CholChunk<TG, NR, A + 1>::run(m, w, thr, P, piv, tr, tc);
+    }
+};
+
+template <int TG, int NR>
+__device__ inline void reg_chol_inv(double (&m)[NR * (NR + 1) / 2], int w, double thr, double* P, double* piv,
+                                    double& pmin, double& pmax, int& ndrop) {
+    const int tid = threadIdx.x, tr = tid / TG, tc = tid % TG;
+    // publish row 0 / column 0
+    if (tc == 0) {
+#pragma unroll
+        for (int a = 0; a < NR; ++a) {
+            const int i = tr + TG * a;
+            if (i < w) P[i] = m[tri_slot(a, 0)];
+        }
     }
     __syncthreads();
-    for (int e = tid; e < wp; e += nt) {
-        const int blk = e >> 3, c = e & 7, o = blk * 8;
-        const double* L = base + blk * 64;
-        for (int i = 0; i < 8; ++i) {
-            double x = 0.0;
-            if (i == c) {
-                x = drop[o + c] ? 0.0 : 1.0 / L[c * 8 + c];
-            } else if (i > c && !drop[o + i]) {
-                double acc = 0.0;
-                for (int p = c; p < i; ++p) acc = fma(L[i * 8 + p], S[(o + p) * ld + o + c], acc);
-                x = -acc / L[i * 8 + i];
-            }
-            if (i >= c) S[(o + i) * ld + o + c] = x;
-        }
-    }
-    __syncthreads();
-    for (int lb = 3; (1 << lb) < wp; ++lb) {
-        const int b = 1 << lb, total = wp * b / 2;
-        // T = L21 X11 (X11 lower): T[i][j] = sum_{q=j}^{b-1} L21[i][q] X11[q][j]
-        for (int e = tid; e < total; e += nt) {
-            const int o = (e >> (2 * lb)) * 2 * b, i = (e >> lb) & (b - 1), j = e & (b - 1);
-            const double* Lr = S + (o + b + i) * ld + o;
-            const double* Xc = S + o * ld + o + j;
-            // four interleaved partial sums (fixed order) break the FMA latency chain
-            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-            int q = j;
-            for (; q + 3 < b; q += 4) {
-                a0 = fma(Lr[q], Xc[q * ld], a0);
-                a1 = fma(Lr[q + 1], Xc[(q + 1) * ld], a1);
-                a2 = fma(Lr[q + 2], Xc[(q + 2) * ld], a2);
-                a3 = fma(Lr[q + 3], Xc[(q + 3) * ld], a3);
-            }
-            for (; q < b; ++q) a0 = fma(Lr[q], Xc[q * ld], a0);
-            S[(o + i) * ld + o + b + j] = (a0 + a1) + (a2 + a3);
-        }
-        __syncthreads();
-        // X21 = -X22 T (X22 lower): X21[i][j] = -sum_{q=0}^{i} X22[i][q] T[q][j]
-        for (int e = tid; e < total; e += nt) {
-            const int o = (e >> (2 * lb)) * 2 * b, i = (e >> lb) & (b - 1), j = e & (b - 1);
-            const double* Xr = S + (o + b + i) * ld + o + b;
-            const double* Tc = S + o * ld + o + b + j;
-            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-            int q = 0;
-            for (; q + 3 <= i; q += 4) {
-                a0 = fma(Xr[q], Tc[q * ld], a0);
-                a1 = fma(Xr[q + 1], Tc[(q + 1) * ld], a1);
-                a2 = fma(Xr[q + 2], Tc[(q + 2) * ld], a2);
-                a3 = fma(Xr[q + 3], Tc[(q + 3) * ld], a3);
-            }
-            for (; q <= i; ++q) a0 = fma(Xr[q], Tc[q * ld], a0);
-            S[(o + b + i) * ld + o + j] = -((a0 + a1) + (a2 + a3));
-        }
-        __syncthreads();
+    CholChunk<TG, NR, 0>::run(m, w, thr, P, piv, tr, tc);
+    // pivot range and count of dropped pivots, in every thread
+    pmin = INFINITY;
+    pmax = 0.0;
+    ndrop = 0;
+    for (int j = 0; j < w; ++j) {
+        const double d = piv[j];
+        pmin = fmin(pmin, d);
+        pmax = fmax(pmax, d);
+        ndrop += d > thr ? 0 : 1;
     }
 }
 
@@ -141,10 +169,5 @@ __device__ inline double sum_partials(const double* __restrict__ x, int parts, i
     return acc;
 }
 
-__device__ inline int pow2_at_least8(int w) {
-    int p = 8;
-    while (p < w) p *= 2;
-    return p;
-}
 
 }  // namespace bcur
