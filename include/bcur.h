@@ -61,7 +61,7 @@ enum {
 
 /* Bits of bcur_result.flags. */
 enum {
-    BCUR_FLAG_RANKDEF_C = 1u << 0,   /* C^T C was numerically singular; U is not reliable */
+    BCUR_FLAG_RANKDEF_C = 1u << 0,   /* C^T C was numerically singular: pivots dropped */
     BCUR_FLAG_ILLCOND_C = 1u << 1,   /* estimated cond(C)^2 * 2^-24 > 0.1: U is inaccurate */
     BCUR_FLAG_ZERO_SCORE = 1u << 2,  /* a block of zero score was drawn (all remaining scores were 0) */
     BCUR_FLAG_RANKDEF_Y = 1u << 3,   /* a Gram matrix of the range finder needed a diagonal shift */
@@ -170,7 +170,12 @@ bcur_status bcur_gather_columns(bcur_ctx* ctx, const float* A, int64_t m, int64_
  * of the Remark in Sec. 3.3) by the normal equations: H = C^T A and
  * C^T C on the MFMA units, a float64 Cholesky inverse of C^T C, then
  * `refine` (0 or 1) steps of iterative refinement with the explicit residual
- * E = A - C U.  err = ||A - C U||_F.
+ * E = A - C U.  err = ||A - C U||_F.  The accuracy of U is about
+ * u32 cond(C)^2 relative.  When pivots of C^T C are dropped
+ * (BCUR_FLAG_RANKDEF_C: C numerically rank-deficient) or their spread says
+ * the FP32 normal equations are inaccurate (BCUR_FLAG_ILLCOND_C), the fit is
+ * redone by Cholesky QR2 in FP64 (a basic least-squares solution on the
+ * columns kept at 2^-50) and err is the exact residual of the returned U.
  * A: device m x n (lda).  C: device m x c (ldc).  U: device c x n (ldu),
  * written.  err: host double.  flags: host uint32 (BCUR_FLAG_*), or NULL.
  * Synchronous. */

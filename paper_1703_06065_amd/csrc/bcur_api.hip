@@ -350,9 +350,14 @@ bcur_status range_finder_run(bcur_ctx* ctx, const RFBufs& b, const float* A, int
 
 // ---- fit ------------------------------------------------------------------
 
+constexpr int64_t kFbPanel = 1024;  // columns of A per FP64 fallback panel
+
 struct FitBufs {
     float *H, *E, *F, *Ginv32, *part, *Gtmp;
     double *G, *Ginv, *spdws, *wsE, *wsD, *errv, *piv;
+    // FP64 Cholesky QR2 fallback for a numerically rank-deficient or
+    // ill-conditioned C: its Gram matrix, L1^-1, Q1 = C L1^-T, two c x kFbPanel panels
+    double *Gc64, *L1, *Q1, *T1, *T2;
     int64_t nwsE, nwsD;
     int* info;
 };
@@ -375,16 +380,22 @@ void fit_layout(Arena& a, FitBufs& b, int64_t m, int64_t n, int64_t c, bool need
     b.nwsD = ((c + 127) / 128) * ((n + 127) / 128);
     b.wsE = a.take<double>(b.nwsE);
     b.wsD = a.take<double>(b.nwsD);
-    b.errv = a.take<double>(4);
+    b.errv = a.take<double>(8);
     b.piv = a.take<double>(2 * ((c + 63) / 64));
     b.info = a.take<int>(4);
+    b.Gc64 = a.take<double>(c * c);
+    b.L1 = a.take<double>(c * c);
+    b.Q1 = a.take<double>(m * c);
+    b.T1 = a.take<double>(c * std::min<int64_t>(n, kFbPanel));
+    b.T2 = a.take<double>(c * std::min<int64_t>(n, kFbPanel));
 }
 
 // U = C^+ A through the normal equations with one optional refinement step.
 // When d_cols (device, c) gives C's columns within A (C = A[:, cols]), C^T C
 // is read off H = C^T A; otherwise (d_cols null, d_ident = 0..c-1) it is
 // formed by its own GEMM into Gtmp.  After the caller synchronizes,
-// b.errv[0] = err^2, b.info[0] bit 0 = pivot replaced, b.piv = pivot ranges.
+// b.errv[0] = ||E||^2 - <F, dU> (err^2 after the refinement), b.errv[1] =
+// ||E||^2 (before it), b.info[0] bit 0 = pivots dropped, b.piv = pivot ranges.
 bcur_status fit_run(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t m, int64_t n, int64_t lda, const float* C,
                     int64_t c, int64_t ldc, const int64_t* d_cols, const int64_t* d_ident, int refine, float* U,
                     int64_t ldu) {
@@ -419,7 +430,7 @@ bcur_status fit_run(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t m, 
         STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_DU, BCUR_STAGE_FIT_REDUCE, pu, c, n, c, false, b.Ginv32, cp, b.F, np, U,
                          ldu, nullptr, EPI_ADD_DOT, U, ldu, b.F, np, b.wsD));
     }
-    // one partial per workgroup of the two fused-epilogue GEMMs (128 x 128 tiles)
+    // one partial per workgroup of the fused-epilogue GEMMs (128 x 128 tiles)
     const int64_t nwsE = ((m + 127) / 128) * ((n + 127) / 128);
     const int64_t nwsD = ((c + 127) / 128) * ((n + 127) / 128);
     HIPCHK(launch_fit_err(b.wsE, nwsE, b.wsD, refine ? nwsD : 0, b.errv, st));
@@ -432,8 +443,50 @@ struct FitOut {
     uint32_t flags;
 };
 
-bcur_status fit_collect(bcur_ctx* ctx, const FitBufs& b, int64_t c, FitOut* out) {
-    double hv[4];
+// U = C^+ A by Cholesky QR2 in FP64 (the scheme of the row-block variant):
+// L1 L1^T = C^T C from FP32 C with FP64 sums, Q1 = C L1^-T, L2 L2^T = Q1^T Q1,
+// U = L1^-T L2^-T L2^-1 Q1^T A, with pivots below 2^-50 of the largest dropped
+// (a basic least-squares solution on the kept columns).  Then E = A - C U for
+// the returned FP32 U with its fused norm: err2 is that U's exact residual.
+bcur_status fit_fallback64(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t m, int64_t n, int64_t lda,
+                           const float* C, int64_t c, int64_t ldc, float* U, int64_t ldu, double* err2) {
+    hipStream_t st = ctx->stream;
+    const double rel64 = ldexp(1.0, -50);
+    double *L1inv = nullptr, *L2inv = nullptr;
+    {
+        StageScope ts(ctx, BCUR_STAGE_FIT_INV);
+        HIPCHK(launch_dgemm_ff(c, c, m, 1.0, C, ldc, true, C, ldc, false, 0.0, b.Gc64, c, st));
+        HIPCHK(launch_chol_linv(b.Gc64, c, b.spdws, b.info + 1, nullptr, rel64, &L1inv, st));
+        HIPCHK(hipMemcpyAsync(b.L1, L1inv, c * c * sizeof(double), hipMemcpyDeviceToDevice, st));
+        HIPCHK(launch_dgemm_fd(m, c, c, 1.0, C, ldc, false, b.L1, c, true, 0.0, b.Q1, c, st));
+        HIPCHK(launch_dgemm(c, c, m, 1.0, b.Q1, c, true, b.Q1, c, false, 0.0, b.Gc64, c, st));
+        HIPCHK(launch_chol_linv(b.Gc64, c, b.spdws, b.info + 2, nullptr, rel64, &L2inv, st));
+    }
+    {
+        StageScope ts(ctx, BCUR_STAGE_FIT_U);
+        for (int64_t j0 = 0; j0 < n; j0 += kFbPanel) {
+            const int64_t w = std::min(kFbPanel, n - j0);
+            HIPCHK(launch_dgemm_df(c, w, m, 1.0, b.Q1, c, true, A + j0, lda, false, 0.0, b.T1, w, st));  // Q1^T A
+            HIPCHK(launch_dgemm(c, w, c, 1.0, L2inv, c, false, b.T1, w, false, 0.0, b.T2, w, st));       // L2^-1 .
+            HIPCHK(launch_dgemm(c, w, c, 1.0, L2inv, c, true, b.T2, w, false, 0.0, b.T1, w, st));        // L2^-T .
+            HIPCHK(launch_dgemm(c, w, c, 1.0, b.L1, c, true, b.T1, w, false, 0.0, b.T2, w, st));         // L1^-T .
+            HIPCHK(launch_f64_to_f32_2d(b.T2, c, w, w, U + j0, ldu, st));
+        }
+    }
+    const GemmPlan pe = plan_sgemm(m, n, c, false, false);
+    STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_E, BCUR_STAGE_FIT_REDUCE, pe, m, n, c, false, C, ldc, U, ldu, b.E, round4(n),
+                     nullptr, EPI_RESID, A, lda, nullptr, 0, b.wsE));
+    HIPCHK(launch_fit_err(b.wsE, b.nwsE, b.wsD, 0, b.errv, st));
+    double hv[3];
+    HIPCHK(hipMemcpyAsync(hv, b.errv, sizeof hv, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *err2 = hv[0];
+    return BCUR_OK;
+}
+
+bcur_status fit_collect(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t m, int64_t n, int64_t lda,
+                        const float* C, int64_t c, int64_t ldc, float* U, int64_t ldu, FitOut* out) {
+    double hv[8];
     int hinfo[4];
     const int64_t nblk = (c + 63) / 64;
     std::vector<double> piv(2 * nblk);
@@ -450,7 +503,12 @@ bcur_status fit_collect(bcur_ctx* ctx, const FitBufs& b, int64_t c, FitOut* out)
     }
     // cond(C)^2 is at least the spread of the Cholesky pivots
     if (pmin > 0.0 && pmax / pmin * ldexp(1.0, -24) > 0.1) fl |= BCUR_FLAG_ILLCOND_C;
-    out->err2 = std::max(hv[0], 0.0);
+    double err2 = hv[0];
+    if (fl & (BCUR_FLAG_RANKDEF_C | BCUR_FLAG_ILLCOND_C)) {
+        // the FP32 normal equations lose about u32 cond(C)^2: redo the fit in FP64
+        STCHK(fit_fallback64(ctx, b, A, m, n, lda, C, c, ldc, U, ldu, &err2));
+    }
+    out->err2 = std::max(err2, 0.0);
     out->flags = fl;
     return BCUR_OK;
 }
@@ -902,7 +960,7 @@ bcur_status bcur_fit_columns(bcur_ctx* ctx, const float* A, int64_t m, int64_t n
     HIPCHK(hipMemcpyAsync(d_id, h_id, c * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
     STCHK(fit_run(ctx, b, A, m, n, lda, C, c, ldc, nullptr, d_id, refine, U, ldu));
     FitOut fo;
-    STCHK(fit_collect(ctx, b, c, &fo));
+    STCHK(fit_collect(ctx, b, A, m, n, lda, C, c, ldc, U, ldu, &fo));
     *err = sqrt(fo.err2);
     if (flags) *flags = fo.flags;
     return BCUR_OK;
@@ -1091,7 +1149,7 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
     } else {
         STCHK(fit_run(ctx, fb, A, m, n, lda, Cbuf, c, ldc, sc.list, nullptr, p->refine, U, ldu));
         FitOut fo;
-        STCHK(fit_collect(ctx, fb, c, &fo));
+        STCHK(fit_collect(ctx, fb, A, m, n, lda, Cbuf, c, ldc, U, ldu, &fo));
         err2 = fo.err2;
         fl = fo.flags;
     }

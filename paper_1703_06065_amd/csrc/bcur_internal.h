@@ -116,5 +116,7 @@ hipError_t launch_dgemm_ff(int64_t M, int64_t N, int64_t K, double alpha, const 
 hipError_t launch_dgemm_fd(int64_t M, int64_t N, int64_t K, double alpha, const float* A, int64_t lda, bool tA,
                            const double* B, int64_t ldb, bool tB, double beta, double* D, int64_t ldd,
                            hipStream_t st);
+hipError_t launch_dgemm_df(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda, bool tA,
+                           const float* B, int64_t ldb, bool tB, double beta, double* D, int64_t ldd, hipStream_t st);
 
 }  // namespace bcur

@@ -291,6 +291,10 @@ hipError_t launch_dgemm_fd(int64_t M, int64_t N, int64_t K, double alpha, const 
                            const double* B, int64_t ldb, bool tB, double beta, double* D, int64_t ldd, hipStream_t st) {
     return dgemm_any(M, N, K, alpha, A, lda, tA, B, ldb, tB, beta, D, ldd, st);
 }
+hipError_t launch_dgemm_df(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda, bool tA,
+                           const float* B, int64_t ldb, bool tB, double beta, double* D, int64_t ldd, hipStream_t st) {
+    return dgemm_any(M, N, K, alpha, A, lda, tA, B, ldb, tB, beta, D, ldd, st);
+}
 
 // ws: [Linv blocks nblk*NB*NB][X c*c][piv 2*nblk][maxdiag].  Factor G (in
 // place, lower L) and form X = L^-1 (lower) in the workspace; returns X.

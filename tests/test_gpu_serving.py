@@ -76,6 +76,14 @@ def test_budget_and_refusal():
         fps.append(b.value)
     budget = int(max(fps) * 1.2)
     note(f"footprints {fps} budget {budget}")
+    # a request whose own footprint exceeds the budget must be refused
+    big = gen.serving_request(99, (4096, 4096), (2048, 2048))
+    prm = binding.Params(k=big.k, s=big.s, l=big.l, q=big.q, replace=0, precision=0, refine=1, reserved=0, s_r=0)
+    b = ctypes.c_size_t()
+    off = np.ascontiguousarray(big.offsets, dtype=np.int64)
+    assert lib.bcur_footprint(big.m, big.n, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), big.G, None, 0,
+                              ctypes.byref(prm), 1, ctypes.byref(b)) == 0
+    assert b.value > budget
     srv = Server(0, hbm_budget=budget, max_slots=3)
     tickets = [srv.submit(A, w.offsets, w.k, w.s, om, w.draws, q=w.q) for w, (A, om) in zip(ws, inputs)]
     res = [srv.wait(t) for t in tickets]
@@ -84,7 +92,6 @@ def test_budget_and_refusal():
     assert st["completed"] == len(ws)
     assert st["hbm_peak"] <= budget
     assert all(np.isfinite(r["err"]) for r in res)
-    big = gen.serving_request(99, (2048, 2048), (1024, 1024))
     with pytest.raises(BcurError) as e:
         srv.submit(dev(big.A), big.offsets, big.k, big.s, dense(big.omega), big.draws)
     assert e.value.status == binding.E_ADMIT
