@@ -181,7 +181,8 @@ def main():
     for _ in range(args.warmup):
         res = ctx.decompose(A, w.offsets, w.k, w.s, om, w.draws, q=w.q, U_out=Ubuf)
     torch.cuda.synchronize()
-    ctx.timing_enable(True)
+    # timed region: only the dominant kernel's two launches record HIP events
+    ctx.timing_enable(("fit_H", "fit_F"))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -189,6 +190,13 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     stages = ctx.timing_read()
+    # per-stage breakdown from a separate, untimed pass (its events slow the host side)
+    ctx.timing_enable(True)
+    nb = min(args.steps, 10)
+    for _ in range(nb):
+        ctx.decompose(A, w.offsets, w.k, w.s, om, w.draws, q=w.q, U_out=Ubuf)
+    torch.cuda.synchronize()
+    breakdown = ctx.timing_read()
     ctx.timing_enable(False)
     el = t1 - t0
     c = int(res["c"])
@@ -226,7 +234,7 @@ def main():
                                f"q={w.q}, l={w.l}", "m": w.m, "n": w.n, "G": w.G, "k": w.k, "s": w.s, "q": w.q,
                    "l": w.l, "c": c, "refine": 1},
         "tflops_total": round((rf_flops + fit_flops) * args.steps / el / 1e12, 3),
-        "stage_ms_per_step": {k: round(v[0] / args.steps, 5) for k, v in stages.items()},
+        "stage_ms_per_step": {k: round(v[0] / nb, 5) for k, v in breakdown.items()},
         "err": res["err"], "rel_err": res["rel_err"], "rr_sweeps": res["rr_sweeps"],
         "roofline": roof,
     }

@@ -209,7 +209,10 @@ enum {
     BCUR_NUM_STAGES = 17
 };
 
-/* Turn stage timing on (1) or off (0); turning it on clears the totals. */
+/* Stage timing: `on` = 0 turns it off; otherwise bit i of `on` times stage
+ * i (-1 times every stage).  Each timed stage records two events per
+ * launch on the context's stream, so time only the stages needed.
+ * Changing the setting clears the totals. */
 bcur_status bcur_timing_enable(bcur_ctx* ctx, int32_t on);
 
 /* Totals since timing was enabled: ms[i] milliseconds and count[i] launches

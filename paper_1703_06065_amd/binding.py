@@ -192,8 +192,17 @@ class Context:
         return int(self.lib.bcur_workspace_bytes(self.h))
 
     # -- profiling ---------------------------------------------------------
-    def timing_enable(self, on: bool = True):
-        self._chk(self.lib.bcur_timing_enable(self.h, int(on)))
+    def timing_enable(self, on=True):
+        """on: False (off), True (every stage), or an iterable of stage names."""
+        if on is True:
+            mask = -1
+        elif not on:
+            mask = 0
+        else:
+            mask = 0
+            for name in on:
+                mask |= 1 << STAGES.index(name)
+        self._chk(self.lib.bcur_timing_enable(self.h, mask))
 
     def timing_read(self):
         ms = np.zeros(len(STAGES))

@@ -19,6 +19,7 @@ using namespace bcur;
 // and resolved (elapsed time added to the stage total) on the next read.
 struct StageTimer {
     bool on = false;
+    uint32_t mask = 0;                            // stages that record events
     std::vector<hipEvent_t> pool;                 // free events
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
     double ms[BCUR_NUM_STAGES] = {};
@@ -33,6 +34,7 @@ struct bcur_ctx {
     size_t ws_bytes = 0;
     char* pinned = nullptr;
     size_t pinned_bytes = 0;
+    bool pinned_busy = false;  // a call left copies into `pinned` without synchronizing
     std::string err;
     StageTimer timer;
 };
@@ -129,7 +131,7 @@ struct StageScope {
     int stage;
     hipEvent_t a = nullptr;
     StageScope(bcur_ctx* c, int s) : ctx(c), stage(s) {
-        if (!ctx->timer.on) return;
+        if (!ctx->timer.on || !((ctx->timer.mask >> s) & 1u)) return;
         a = timer_event(ctx);
         if (a && hipEventRecord(a, ctx->stream) != hipSuccess) a = nullptr;
     }
@@ -612,17 +614,20 @@ struct SampleBufs {
     int* st;
 };
 
+// The sampler's results (idx, w, mg, st, sc) are laid out last and in one
+// stretch so the host fetches them with a single copy; `tail` (bytes, may
+// be 0) extends the stretch for the caller's own results.
 void sample_layout(Arena& a, SampleBufs& b, int64_t G, int64_t s, int64_t listmax) {
     b.off = a.take<int64_t>(G + 1);
-    b.sc = a.take<double>(G);
     b.dr = a.take<uint64_t>(s);
     b.qb = a.take<uint64_t>(G);
     b.pr = a.take<uint64_t>(G);
+    b.list = a.take<int64_t>(std::max<int64_t>(listmax, 1));
     b.idx = a.take<int64_t>(s);
     b.w = a.take<double>(s);
     b.mg = a.take<double>(s);
     b.st = a.take<int>(4);
-    b.list = a.take<int64_t>(std::max<int64_t>(listmax, 1));
+    b.sc = a.take<double>(G);
 }
 
 // Device workspace of one decomposition, from the shapes alone (the same
@@ -741,6 +746,7 @@ bcur_status bcur_timing_enable(bcur_ctx* ctx, int32_t on) {
     HIPCHK(hipStreamSynchronize(ctx->stream));
     timer_resolve(ctx);
     ctx->timer.on = on != 0;
+    ctx->timer.mask = (uint32_t)on;
     for (int i = 0; i < BCUR_NUM_STAGES; ++i) {
         ctx->timer.ms[i] = 0.0;
         ctx->timer.count[i] = 0;
@@ -929,6 +935,7 @@ bcur_status bcur_gather_columns(bcur_ctx* ctx, const float* A, int64_t m, int64_
     HIPCHK(hipStreamSynchronize(ctx->stream));   // the pinned staging buffer may still be read by a copy
     memcpy(ctx->pinned, cols.data(), c * sizeof(int64_t));
     HIPCHK(hipMemcpyAsync(d_cols, ctx->pinned, c * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+    ctx->pinned_busy = true;  // the copy may still read the staging buffer when this returns
     HIPCHK(launch_gather_cols(A, lda, m, d_cols, c, C, ldc, ctx->stream));
     *c_out = c;
     return BCUR_OK;
@@ -1012,8 +1019,8 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
     auto layout = [&](Arena& a) {
         rf_layout(a, rb, m, n, l, k, bf16);
         sample_layout(a, sc, G, s, cmax);
-        if (rowv) sample_layout(a, sr, Gr, s_r, rmax);
         d_frob = a.take<double>(2);
+        if (rowv) sample_layout(a, sr, Gr, s_r, rmax);
         d_fpart = a.take<double>(frob2_grid(m, n));
         Vk = a.take<float>(n * k);
         Uk = rowv ? a.take<float>(m * k) : nullptr;
@@ -1031,10 +1038,13 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
     }
     // pinned staging: offsets | draws | frob2 | status | idx, w, mg | scores | lam | list
     // (for the rows the same again after the columns)
-    auto side_bytes = [](int64_t g, int64_t ss, int64_t lm) { return 8 * (g + 1) + 8 * ss + 16 + 24 * ss + 8 * g + 8 * lm; };
+    auto side_bytes = [](int64_t g, int64_t ss, int64_t lm) {
+        return 8 * (g + 1) + 8 * ss + (24 * ss + 16 + 8 * g + 16 + 5 * 256) + 8 * lm + 16;
+    };
     const size_t pin_need = side_bytes(G, s, cmax) + (rowv ? side_bytes(Gr, s_r, rmax) : 0) + 16 + 8 * l + 64;
     STCHK(reserve_pinned(ctx, pin_need));
-    HIPCHK(hipStreamSynchronize(st));
+    if (ctx->pinned_busy) HIPCHK(hipStreamSynchronize(st));
+    ctx->pinned_busy = true;
     char* pin = ctx->pinned;
     auto ptake = [&pin](size_t bytes) {
         char* p0 = pin;
@@ -1085,27 +1095,30 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
         double *w, *mg, *sc;
         int64_t* list;
     };
-    auto stage_side = [&](const SampleBufs& b, int64_t g, int64_t ss, int64_t lm, HostSide& h) -> bcur_status {
-        h.st = reinterpret_cast<int*>(ptake(16));
-        h.idx = reinterpret_cast<int64_t*>(ptake(8 * ss));
-        h.w = reinterpret_cast<double*>(ptake(8 * ss));
-        h.mg = reinterpret_cast<double*>(ptake(8 * ss));
-        h.sc = reinterpret_cast<double*>(ptake(8 * g));
+    // one copy per side: the device results from idx to the end of sc (for
+    // the columns also d_frob, laid out right after), mirrored on the host
+    auto stage_side = [&](const SampleBufs& b, int64_t lm, const char* dev_end, HostSide& h) -> bcur_status {
+        const char* d0 = reinterpret_cast<const char*>(b.idx);
+        const size_t span = (size_t)(dev_end - d0);
+        char* h0 = ptake(span);
+        auto mirror = [&](const void* dp) { return h0 + (reinterpret_cast<const char*>(dp) - d0); };
+        h.idx = reinterpret_cast<int64_t*>(mirror(b.idx));
+        h.w = reinterpret_cast<double*>(mirror(b.w));
+        h.mg = reinterpret_cast<double*>(mirror(b.mg));
+        h.st = reinterpret_cast<int*>(mirror(b.st));
+        h.sc = reinterpret_cast<double*>(mirror(b.sc));
         h.list = reinterpret_cast<int64_t*>(ptake(8 * std::max<int64_t>(lm, 1)));
-        HIPCHK(hipMemcpyAsync(h.st, b.st, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(h.idx, b.idx, ss * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(h.w, b.w, ss * sizeof(double), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(h.mg, b.mg, ss * sizeof(double), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(h.sc, b.sc, g * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(h0, d0, span, hipMemcpyDeviceToHost, st));
         return BCUR_OK;
     };
-    double* h_frob = reinterpret_cast<double*>(ptake(16));
-    double* h_lam = reinterpret_cast<double*>(ptake(8 * l));
     HostSide hc{}, hr{};
-    STCHK(stage_side(sc, G, s, cmax, hc));
-    if (rowv) STCHK(stage_side(sr, Gr, s_r, rmax, hr));
-    HIPCHK(hipMemcpyAsync(h_frob, d_frob, sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(h_lam, rb.lam, l * sizeof(double), hipMemcpyDeviceToHost, st));
+    STCHK(stage_side(sc, cmax, reinterpret_cast<const char*>(d_frob + 1), hc));
+    const double* h_frob = reinterpret_cast<const double*>(reinterpret_cast<const char*>(hc.idx) +
+                                                           (reinterpret_cast<const char*>(d_frob) -
+                                                            reinterpret_cast<const char*>(sc.idx)));
+    if (rowv) STCHK(stage_side(sr, rmax, reinterpret_cast<const char*>(sr.sc + Gr), hr));
+    double* h_lam = reinterpret_cast<double*>(ptake(8 * l));
+    int* rinfo = reinterpret_cast<int*>(ptake(16));
     HIPCHK(hipStreamSynchronize(st));
     if (!isfinite(h_frob[0])) return fail(ctx, BCUR_E_NONFINITE, "A holds NaN or Inf");
     if (hc.st[0] != 0 || (rowv && hr.st[0] != 0)) return fail(ctx, BCUR_E_HIP, "block scores are not finite");
@@ -1131,6 +1144,9 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
         HIPCHK(launch_gather_cols(A, lda, m, sc.list, c, Cbuf, ldc, st));
         if (rowv) HIPCHK(launch_gather_rows(A, lda, n, sr.list, r, cb.R, round4(n), st));
     }
+    // results the host reads after the fit's synchronization
+    HIPCHK(hipMemcpyAsync(h_lam, rb.lam, l * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(rinfo, rb.info, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
     // 6. U and the residual
     float* U = res->U ? res->U : Ubuf;
     const int64_t ldu = res->U ? res->ldu : round4(ucols);
@@ -1153,9 +1169,7 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
         err2 = fo.err2;
         fl = fo.flags;
     }
-    int rinfo[4];
-    HIPCHK(hipMemcpyAsync(rinfo, rb.info, sizeof rinfo, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    ctx->pinned_busy = false;  // the fit's synchronization completed every copy
     if (rinfo[0] & 1) fl |= BCUR_FLAG_RANKDEF_Y;
     if (hc.st[1] || (rowv && hr.st[1])) fl |= BCUR_FLAG_ZERO_SCORE;
     memcpy(res->idx, hc.idx, s * sizeof(int64_t));
