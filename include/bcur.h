@@ -118,7 +118,7 @@ bcur_status bcur_frob2(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int6
  * Uk: device m x k (leading dimension k) or NULL; when given, receives
  *     Z W[:, :k] diag(1/sqrt(lam_k)), the matching left vectors.
  * ritz: host, l doubles, or NULL (Ritz singular values, descending).
- * Requires 1 <= k <= l <= min(m, n, 112).  Synchronous when ritz != NULL. */
+ * Requires 1 <= k <= l <= min(m, n, 128).  Synchronous when ritz != NULL. */
 bcur_status bcur_range_finder(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda,
                               const float* omega, int64_t l, int64_t k, int64_t q, int32_t precision,
                               float* Vk, float* Uk, double* ritz);
@@ -224,7 +224,7 @@ bcur_status bcur_timing_read(bcur_ctx* ctx, double* ms, int64_t* count);
 typedef struct bcur_params {
     int64_t k;          /* target rank, 1 <= k */
     int64_t s;          /* number of column blocks to sample */
-    int64_t l;          /* sketch width k + oversampling; l <= min(m, n, 112) */
+    int64_t l;          /* sketch width k + oversampling; l <= min(m, n, 128) */
     int64_t q;          /* power iterations (the range finder applies A^T A q+1 times) */
     int32_t replace;    /* 0: without replacement (default), 1: independent draws */
     int32_t precision;  /* BCUR_PREC_FP32 or BCUR_PREC_BF16 */

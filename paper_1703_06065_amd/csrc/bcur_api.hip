@@ -41,7 +41,7 @@ struct bcur_ctx {
 
 namespace {
 
-constexpr int64_t kMaxSketch = 112;
+constexpr int64_t kMaxSketch = 128;
 
 inline int64_t round4(int64_t x) { return (x + 3) & ~(int64_t)3; }
 

@@ -11,7 +11,6 @@ namespace bcur {
 namespace {
 
 constexpr int kMaxL = 128;     // sketch width limit of the Gram / Cholesky / apply kernels
-constexpr int kMaxLJ = 112;    // sketch width limit of the Jacobi kernel (LDS)
 constexpr int kRC = 32;        // rows per LDS chunk
 
 // partial[w] = X[rows of w]^T X[rows of w]; thread (ti, tj) owns the 4x4 block
@@ -188,272 +187,45 @@ __global__ __launch_bounds__(256) void k_apply_small(const float* __restrict__ X
     }
 }
 
-__device__ __forceinline__ int pk(int i, int j, int L) {
-    if (i > j) {
-        const int t = i;
-        i = j;
-        j = t;
-    }
-    return i * L - (i * (i - 1)) / 2 + (j - i);
-}
-
-// Full-precision 1/x for x != 0 from the hardware estimate and two Newton
-// steps (the rotations need c^2 + s^2 = 1 to working precision, not correctly
-// rounded operations; rsqrt_nr is its square-root counterpart).
-__device__ __forceinline__ double rcp_nr(double x) {
-    double y = __builtin_amdgcn_rcp(x);
-    y = y * fma(-x, y, 2.0);
-    y = y * fma(-x, y, 2.0);
-    return y;
-}
-
-// Cyclic Jacobi on the symmetric l x l matrix T (FP64), one workgroup.
-// T is the sum of `parts` partial Gram matrices.  Each round rotates L/2
-// disjoint index pairs (round-robin schedule), so every 2x2 block of T and
-// every row of W is updated independently; a sweep is L-1 rounds and the
-// iteration stops after a sweep without rotations.  A pair (p, q) is rotated
-// while |a_pq| > max(2^-51 ||T||_F, 1e-15 sqrt|a_pp a_qq|).
-// The tangent t of each rotation is estimated in FP32 (hardware reciprocal and
-// square root) and refined by one Newton step to about 2^-46; c = 1/sqrt(1 +
-// t^2) and s = t c are then formed in FP64 with Newton-refined estimates, so
-// every rotation is orthogonal to FP64 precision.  The (p, q) entry left by
-// the slightly inexact angle is kept (not forced to zero), so no backward
-// error is introduced; later rounds remove it.
-__device__ __forceinline__ void jacobi_angle(double app, double aqq, double apq, double& c, double& s) {
-    const double d = aqq - app;
-    double t;
-    if (fabs(apq) < 1e-30 * fabs(d)) {
-        t = apq * rcp_nr(d);                       // |tau| > 1e30: t = 1 / (2 tau)
-    } else {
-        // scale both by one power of two so the FP32 conversion cannot overflow
-        int e;
-        frexp(fmax(fabs(d), fabs(apq)), &e);
-        const double ds = ldexp(d, -e), as = ldexp(apq, -e);
-        const float df = (float)ds, af = (float)as;
-        const float tau = df * __builtin_amdgcn_rcpf(2.0f * af);
-        const float at = fabsf(tau);
-        float tf = __builtin_amdgcn_rcpf(at + __builtin_amdgcn_sqrtf(fmaf(at, at, 1.0f)));
-        if (tau < 0.0f) tf = -tf;
-        // t is the root of smaller magnitude of  as t^2 + ds t - as = 0; one
-        // Newton step from the FP32 estimate (residual in FP64, the small
-        // correction's quotient in FP32) brings it to about 2^-46
-        const double t0 = (double)tf;
-        const double fv = fma(as * t0, t0, fma(ds, t0, -as));
-        const double fd = fma(2.0 * as, t0, ds);
-        t = t0 - (double)((float)fv * __builtin_amdgcn_rcpf((float)fd));
-    }
-    c = rsqrt_nr(fma(t, t, 1.0));
-    s = t * c;
-}
-
-__global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ partial, int parts, int l, int k,
-                                                 double* __restrict__ lam_out, double* __restrict__ Wk,
-                                                 double* __restrict__ Wks, int* __restrict__ info) {
-    __shared__ double P[kMaxLJ * (kMaxLJ + 1) / 2];
-    __shared__ double W[kMaxLJ * kMaxLJ];
-    __shared__ double cc[kMaxLJ / 2], ss[kMaxLJ / 2];
-    __shared__ int cp[kMaxLJ / 2], cq[kMaxLJ / 2];
-    __shared__ int blk[(kMaxLJ / 2) * (kMaxLJ / 2 + 1) / 2];
-    __shared__ int rotflag;
-    __shared__ double snorm, sred[16];
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int L = l + (l & 1), H = L / 2;
-    const int nblk = H * (H + 1) / 2;
-    const int64_t ll = (int64_t)l * l;
-    const int TX = 32, TY = nt / 32, tx = tid % 32, ty = tid / 32;
-    for (int i = ty; i < L; i += TY)
-        for (int j = tx; j < L; j += TX) {
-            if (i <= j) P[pk(i, j, L)] = (i < l && j < l) ? sum_partials(partial, parts, ll, i * l + j) : 0.0;
-            W[i * L + j] = i == j ? 1.0 : 0.0;
-        }
-    // block table: (a, b) with a <= b, packed as a | b << 16; row a starts at a H - a (a - 1) / 2
-    if (tid < H) {
-        const int a = tid, o = a * H - (a * (a - 1)) / 2;
-        for (int b = a; b < H; ++b) blk[o + b - a] = a | (b << 16);
-    }
-    __syncthreads();
-    {
-        double f = 0.0;
-        for (int i = ty; i < l; i += TY)
-            for (int j = i + tx; j < l; j += TX) {
-                const double v = P[pk(i, j, L)];
-                f += (i == j ? 1.0 : 2.0) * v * v;
-            }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) f += __shfl_xor(f, o, 64);
-        if ((tid & 63) == 0) sred[tid >> 6] = f;
-        __syncthreads();
-        if (tid == 0) {
-            double t = 0.0;
-            for (int w = 0; w < nt / 64; ++w) t += sred[w];
-            snorm = sqrt(t);
-        }
-        __syncthreads();
-    }
-    // rounding in the rotations leaves off-diagonal noise of about 2^-53 ||T||_F,
-    // so the relative test alone cannot terminate when eigenvalues span decades
-    const double abs_floor = ldexp(1.0, -51) * snorm;
-    int sweeps = 0, converged = 0;
-    for (int sw = 0; sw < 40; ++sw) {
-        if (tid == 0) rotflag = 0;
-        __syncthreads();
-        for (int rd = 0; rd < L - 1; ++rd) {
-            if (tid < H) {
-                // round-robin: players 1..L-1 rotate by rd, player 0 stays
-                int xa = tid - 1 + rd, xb = L - 2 - tid + rd;
-                if (xa >= L - 1) xa -= L - 1;
-                if (xb >= L - 1) xb -= L - 1;
-                const int a = tid == 0 ? 0 : 1 + xa;
-                const int b = 1 + xb;
-                const int p = a < b ? a : b, q = a < b ? b : a;
-                double c = 1.0, s = 0.0;
-                if (q < l) {
-                    const double apq = P[pk(p, q, L)];
-                    const double app = P[pk(p, p, L)], aqq = P[pk(q, q, L)];
-                    if (fabs(apq) > abs_floor && apq * apq > 1e-30 * fabs(app * aqq)) {
-                        jacobi_angle(app, aqq, apq, c, s);
-                        rotflag = 1;
-                    }
-                }
-                cp[tid] = p;
-                cq[tid] = q;
-                cc[tid] = c;
-                ss[tid] = s;
-            }
-            __syncthreads();
-            // T <- J^T T J, one 2x2 block per (pair a, pair b), a <= b
-            for (int e = tid; e < nblk; e += nt) {
-                const int ab = blk[e], a = ab & 0xffff, b = ab >> 16;
-                const double s1 = ss[a], s2 = ss[b];
-                if (s1 == 0.0 && s2 == 0.0) continue;
-                const double c1 = cc[a], c2 = cc[b];
-                const int p1 = cp[a], q1 = cq[a], p2 = cp[b], q2 = cq[b];
-                if (a == b) {
-                    const int i00 = pk(p1, p1, L), i01 = pk(p1, q1, L), i11 = pk(q1, q1, L);
-                    const double x00 = P[i00], x01 = P[i01], x11 = P[i11];
-                    const double y00 = c1 * x00 - s1 * x01, y01 = c1 * x01 - s1 * x11;
-                    const double y10 = s1 * x00 + c1 * x01, y11 = s1 * x01 + c1 * x11;
-                    P[i00] = y00 * c1 - y01 * s1;
-                    P[i01] = y00 * s1 + y01 * c1;
-                    P[i11] = y10 * s1 + y11 * c1;
-                } else {
-                    const int i00 = pk(p1, p2, L), i01 = pk(p1, q2, L), i10 = pk(q1, p2, L), i11 = pk(q1, q2, L);
-                    const double x00 = P[i00], x01 = P[i01], x10 = P[i10], x11 = P[i11];
-                    const double y00 = c1 * x00 - s1 * x10, y01 = c1 * x01 - s1 * x11;
-                    const double y10 = s1 * x00 + c1 * x10, y11 = s1 * x01 + c1 * x11;
-                    P[i00] = y00 * c2 - y01 * s2;
-                    P[i01] = y00 * s2 + y01 * c2;
-                    P[i10] = y10 * c2 - y11 * s2;
-                    P[i11] = y10 * s2 + y11 * c2;
-                }
-            }
-            // W <- W J: each thread loads all of its entries before updating them
-            {
-                constexpr int MI = (kMaxLJ + 31) / 32, MA = (kMaxLJ / 2 + 31) / 32;
-                double wpv[MI][MA], wqv[MI][MA];
-#pragma unroll
-                for (int u = 0; u < MI; ++u)
-#pragma unroll
-                    for (int v = 0; v < MA; ++v) {
-                        const int i = ty + u * TY, a = tx + v * TX;
-                        if (i < L && a < H && ss[a] != 0.0) {
-                            wpv[u][v] = W[i * L + cp[a]];
-                            wqv[u][v] = W[i * L + cq[a]];
-                        }
-                    }
-#pragma unroll
-                for (int u = 0; u < MI; ++u)
-#pragma unroll
-                    for (int v = 0; v < MA; ++v) {
-                        const int i = ty + u * TY, a = tx + v * TX;
-                        if (i < L && a < H) {
-                            const double s = ss[a];
-                            if (s != 0.0) {
-                                const double c = cc[a];
-                                W[i * L + cp[a]] = c * wpv[u][v] - s * wqv[u][v];
-                                W[i * L + cq[a]] = s * wpv[u][v] + c * wqv[u][v];
-                            }
-                        }
-                    }
-            }
-            __syncthreads();
-        }
-        const int rf = rotflag;
-        __syncthreads();
-        ++sweeps;
-        if (!rf) {
-            converged = 1;
-            break;
-        }
-    }
-    // eigenvalues descending (ties by index) and the first k eigenvectors
-    if (tid < l) {
-        const double li = P[pk(tid, tid, L)];
-        int rank = 0;
-        for (int j = 0; j < l; ++j) {
-            const double lj = P[pk(j, j, L)];
-            rank += (lj > li) || (lj == li && j < tid);
-        }
-        lam_out[rank] = li;
-        if (rank < k) {
-            const double inv = li > 0.0 ? 1.0 / sqrt(li) : 0.0;
-            for (int row = 0; row < l; ++row) {
-                const double w = W[row * L + tid];
-                Wk[row * k + rank] = w;
-                if (Wks) Wks[row * k + rank] = w * inv;
-            }
-        }
-    }
-    if (tid == 0 && info) {
-        info[0] = sweeps;
-        info[1] = converged;
-    }
-}
-
-
-// Round-robin schedule: in round rd (0 <= rd < L - 1) pair slot t rotates the
-// index pair (p, q), p < q; the L/2 pairs of a round are disjoint and every
-// pair of indices meets exactly once per sweep.  Index 0 stays put, 1 .. L-1
-// circulate.
-__device__ __forceinline__ void rr_pair(int t, int rd, int L, int& p, int& q) {
-    int xa = t - 1 + rd, xb = L - 2 - t + rd;
-    if (xa >= L - 1) xa -= L - 1;
-    if (xb >= L - 1) xb -= L - 1;
-    const int x = t == 0 ? 0 : 1 + xa, y = 1 + xb;
-    p = x < y ? x : y;
-    q = x < y ? y : x;
-}
-
-
-// The same cyclic Jacobi for L <= 64, split in two kernels.
+// Cyclic Jacobi eigensolver of the small symmetric Rayleigh-Ritz matrix T,
+// in two kernels.
 //
-// k_jacobi64 (one workgroup) diagonalizes T kept in slot order: pair slot t
-// of the round-robin schedule always occupies positions (2t, 2t+1), holding
-// its top and bottom index (x_t, y_t).  From one round to the next every
-// index moves to a fixed new position (slot_next), the same in every round,
-// so each 2 x 2 block (u, v) of J^T T J is read from fixed positions and
-// written to fixed permuted ones in the other copy of T (only the upper
-// triangle is stored).  Wave 0 computes the rotations, lane t for slot t, and
-// records them; after one barrier every thread applies them to its blocks.
-// k_jacobi_vectors then forms rows of W = J_1 J_2 ... J_R from the record,
-// two rows per wave across many workgroups, and writes the first k columns in
-// eigenvalue order.
+// Round-robin schedule: in round rd (0 <= rd < L - 1, L = l rounded up to even)
+// pair slot t rotates the index pair (x_t, y_t); the L/2 pairs of a round are
+// disjoint and every pair of indices meets exactly once in any L - 1
+// consecutive rounds (index 0 stays in slot 0, the others circulate).
 //
-// The rotation of slot (x, y) is taken from T scaled by 1 / ||T||_F: it is
-// made when |a_xy| > 2^-40 ||T||_F and |a_xy| > 1e-15 sqrt|a_xx a_yy|.  The
-// tangent t is estimated in FP32 and refined by one Newton step to about
-// 2^-46; c = 1/sqrt(1 + t^2) and s = t c are formed in FP64 with
-// Newton-refined estimates, so every rotation is orthogonal to FP64 precision.
-constexpr int kJ64 = 64, kJ64LD = 65, kJSweeps = 40;
+// k_jacobi_rr (one workgroup) keeps T in slot order: slot t always occupies
+// positions (2t, 2t+1).  From one round to the next every index moves to a
+// fixed new position (slot_next), so each 2 x 2 block (u, v) of J^T T J is
+// read from fixed positions and written to fixed permuted ones in the other
+// copy of T (upper triangle only).  Wave 0 owns the diagonal blocks (t, t) and
+// one off-diagonal block per slot, which together hold every entry that the
+// next round's rotations are computed from: after updating its blocks it
+// forms the next round's rotations (lane t for slot t, neighbours' entries by
+// lane shuffles) and publishes them while the other waves still update the
+// remaining blocks, so a round costs one barrier.  The rotations are recorded
+// for k_jacobi_vectors, which forms rows of W = J_1 J_2 ... J_R from the record
+// across many workgroups and writes the first k columns in eigenvalue order.
+//
+// A pair (x, y) is rotated when |a_xy| > 2^-40 ||T||_F and |a_xy| > 1e-15
+// sqrt|a_xx a_yy|, from T scaled by 1 / ||T||_F.  The iteration stops once L - 1
+// consecutive rounds rotate nothing: then T did not change during them and
+// every pair was found below the threshold.  The tangent t is estimated in FP32
+// and refined by one Newton step to about 2^-46; c = 1/sqrt(1 + t^2) and s = t c
+// are formed in FP64 with a Newton-refined estimate, so every rotation is
+// orthogonal to FP64 precision.  The entry left by the slightly inexact angle
+// is kept, not forced to zero, so no backward error is introduced.
+constexpr int kJSweeps = 40;  // at most kJSweeps (L - 1) rounds
 
-// Indices (x, y) of pair slot t in round rd: index 0 stays in slot 0, the
-// others circulate (x_t = 1 + (t - 1 + rd) mod (L - 1), y_t = 1 + (L - 2 - t +
-// rd) mod (L - 1)); advanced by one per round (period L - 1).
+// Indices (x, y) of pair slot t in round rd: x_0 = 0, x_t = 1 + (t - 1 + rd)
+// mod (L - 1), y_t = 1 + (L - 2 - t + rd) mod (L - 1); advanced by one round
+// at a time (period L - 1).
 struct RRSlot {
     int xa, xb;
-    __device__ void init(int t, int L) {
-        xa = t - 1;
-        xb = L - 2 - t;
+    __device__ void init(int t, int L, int rd) {
+        xa = (t - 1 + rd) % (L - 1);
+        xb = (L - 2 - t + rd) % (L - 1);
         if (xa < 0) xa += L - 1;
     }
     __device__ void pair(int t, int& x, int& y) const {
@@ -473,12 +245,34 @@ __device__ __forceinline__ int slot_next(int pos, int H) {
     if ((pos & 1) == 0) return pos - 2;
     return pos == 2 * H - 1 ? 2 * H - 2 : pos + 2;
 }
-// Position of index i in the first round of a sweep.
+// Position of index i in the first round.
 __device__ __forceinline__ int slot_pos0(int i, int L) { return i < L / 2 ? 2 * i : 2 * (L - 1 - i) + 1; }
-__device__ __forceinline__ int up_idx(int i, int j) { return i <= j ? i * kJ64LD + j : j * kJ64LD + i; }
 
-// Rotation from the scaled entries (|ds|, |as| <= 2, |as| > 2^-40).
-__device__ __forceinline__ void jacobi_rotation_scaled(double ds, double as, double& c, double& s) {
+// Slot-ordered symmetric L x L matrix (L <= KL) stored as its upper 2 x 2
+// blocks (u <= v), four doubles each (x00, x01, x10, x11), packed row by row,
+// so a block is read with two 16-byte loads; a diagonal block leaves x10 unused.
+// Four more doubles (kTrash) take the stores of lanes without a block.
+template <int KL>
+struct JStore {
+    static constexpr int HB = KL / 2, kTrash = 4 * (HB * (HB + 1) / 2), kSize = kTrash + 4;
+    __device__ static int blk(int u, int v) { return u * HB - (u * (u - 1)) / 2 + (v - u); }  // u <= v
+    __device__ static int idx(int i, int j) {
+        if ((i >> 1) > (j >> 1) || ((i >> 1) == (j >> 1) && i > j)) {
+            const int x = i;
+            i = j;
+            j = x;
+        }
+        return 4 * blk(i >> 1, j >> 1) + 2 * (i & 1) + (j & 1);
+    }
+};
+
+// Rotation (c, s) of a slot from its entries; (1, 0) below the threshold.
+// Branch-free: below the threshold it runs on stand-in values and is discarded.
+__device__ __forceinline__ double2 jacobi_rotation(double xx, double yy, double xy, double inv, double floor_s) {
+    const double as0 = xy * inv;
+    const bool rotate = fabs(as0) > floor_s && xy * xy > 1e-30 * fabs(xx * yy);
+    // scaled entries: |ds|, |as| <= 2 and |as| > 2^-40, so the FP32 estimate cannot overflow
+    const double as = rotate ? as0 : 1.0, ds = rotate ? (yy - xx) * inv : 0.0;
     const float df = (float)ds, af = (float)as;
     const float tau = df * __builtin_amdgcn_rcpf(2.0f * af);
     const float at = fabsf(tau);
@@ -489,181 +283,307 @@ __device__ __forceinline__ void jacobi_rotation_scaled(double ds, double as, dou
     const double fv = fma(as * t0, t0, fma(ds, t0, -as));
     const double fd = fma(2.0 * as, t0, ds);
     const double t = t0 - (double)((float)fv * __builtin_amdgcn_rcpf((float)fd));
-    c = rsqrt_nr(fma(t, t, 1.0));
-    s = t * c;
+    const double c = rsqrt_nr(fma(t, t, 1.0));
+    return rotate ? make_double2(c, t * c) : make_double2(1.0, 0.0);
 }
 
-__global__ __launch_bounds__(512) void k_jacobi64(const double* __restrict__ Tin, int l, double* __restrict__ lam_out,
-                                                  double2* __restrict__ rot, int* __restrict__ meta,
-                                                  int* __restrict__ info) {
-    __shared__ double Tb[2][kJ64 * kJ64LD];
-    __shared__ double2 cs[kJ64 / 2];
-    __shared__ double sred[8];
-    __shared__ int flag[2];
-    constexpr int NT = 512, NB = 2;  // blocks per thread: e = tid + NT r
+// J_u^T X J_v of an off-diagonal block x = (x00, x01, x10, x11).
+__device__ __forceinline__ void rot_block(const double (&x)[4], double c1, double s1, double c2, double s2,
+                                          double (&o)[4]) {
+    const double y00 = c1 * x[0] - s1 * x[2], y01 = c1 * x[1] - s1 * x[3];
+    const double y10 = s1 * x[0] + c1 * x[2], y11 = s1 * x[1] + c1 * x[3];
+    o[0] = y00 * c2 - y01 * s2;
+    o[1] = y00 * s2 + y01 * c2;
+    o[2] = y10 * c2 - y11 * s2;
+    o[3] = y10 * s2 + y11 * c2;
+}
+
+// The e-th block (u < v) of those not owned by wave 0: (u, u+1) for 1 <= u <=
+// H-3, then (u, v) with v - u >= 3, row by row.  Returns false past the end.
+__device__ __forceinline__ bool other_block(int e, int H, int& u, int& v) {
+    const int nA = H > 3 ? H - 3 : 0;
+    if (e < nA) {
+        u = e + 1;
+        v = e + 2;
+        return true;
+    }
+    e -= nA;
+    if (e >= nA * (nA + 1) / 2) return false;
+    // row u holds H - 3 - u blocks and starts at u (H - 3) - u (u - 1) / 2
+    u = 0;
+    while ((u + 1) * nA - ((u + 1) * u) / 2 <= e) ++u;
+    v = u + 3 + (e - (u * nA - (u * (u - 1)) / 2));
+    return true;
+}
+
+template <int KL, int NT, int NB>
+__global__ __launch_bounds__(NT) void k_jacobi_rr(const double* __restrict__ Tin, int l,
+                                                  double* __restrict__ lam_out, double2* __restrict__ rot,
+                                                  int* __restrict__ meta, int* __restrict__ info) {
+    using St = JStore<KL>;
+    static_assert((KL / 2) * (KL / 2 - 3) / 2 <= (NT - 64) * NB, "too few block slots");
+    __shared__ __attribute__((aligned(16))) double Tb[2][St::kSize];
+    __shared__ double2 cs[2][64];  // one entry per lane of wave 0; slots >= H are never read
+    __shared__ double sred[NT / 64];
+    __shared__ int stop[2];
+    __shared__ int posof[KL];
     const int tid = threadIdx.x;
-    const int L = l + (l & 1), H = L / 2, nblk = H * (H + 1) / 2;
+    const int L = l + (l & 1), H = L / 2;
+    const int Rmax = kJSweeps * (L - 1);
     // slot-ordered upper triangle: entry (i, j) of T at positions (pos0(i), pos0(j))
-    const int jc = tid & 63;
-    double tv[kJ64 / 8];
+    {
+        constexpr int RS = NT / KL, NU = KL / RS;
+        const int jc = tid % KL;
+        double tv[NU];
 #pragma unroll
-    for (int u = 0; u < kJ64 / 8; ++u) {
-        const int i = (tid >> 6) + 8 * u;
-        tv[u] = (i <= jc && jc < l) ? Tin[(int64_t)i * l + jc] : 0.0;
-    }
-    double f = 0.0;
+        for (int u = 0; u < NU; ++u) {
+            const int i = tid / KL + RS * u;
+            tv[u] = (i <= jc && jc < l) ? Tin[(int64_t)i * l + jc] : 0.0;
+        }
+        double f = 0.0;
 #pragma unroll
-    for (int u = 0; u < kJ64 / 8; ++u) {
-        const int i = (tid >> 6) + 8 * u;
-        if (i <= jc && jc < L) Tb[0][up_idx(slot_pos0(i, L), slot_pos0(jc, L))] = tv[u];
-        if (i <= jc) f += (i == jc ? 1.0 : 2.0) * tv[u] * tv[u];
-    }
+        for (int u = 0; u < NU; ++u) {
+            const int i = tid / KL + RS * u;
+            if (i <= jc && jc < L) Tb[0][St::idx(slot_pos0(i, L), slot_pos0(jc, L))] = tv[u];
+            if (i <= jc) f += (i == jc ? 1.0 : 2.0) * tv[u] * tv[u];
+        }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) f += __shfl_xor(f, o, 64);
-    if ((tid & 63) == 0) sred[tid >> 6] = f;
-    if (tid < 2) flag[tid] = 0;
-    // this thread's blocks (u <= v) of the packed list, row u starting at u H - u (u - 1) / 2,
-    // with their fixed read and write positions
-    int buv[NB], rdx[NB][4], wrx[NB][4];
-    bool bok[NB], bdiag[NB];
-#pragma unroll
-    for (int r = 0; r < NB; ++r) {
-        const int e = tid + NT * r;
-        bok[r] = e < nblk;
-        int u = 0;
-        while (bok[r] && (u + 1) * H - ((u + 1) * u) / 2 <= e) ++u;
-        const int v = bok[r] ? u + (e - (u * H - (u * (u - 1)) / 2)) : 0;
-        bdiag[r] = u == v;
-        buv[r] = u | (v << 8);
-        // entries (a0 b0, a0 b1, a1 b0, a1 b1); on the diagonal a1 b0 is a0 b1
-        const int a0 = 2 * u, a1 = 2 * u + 1, b0 = 2 * v, b1 = 2 * v + 1;
-        rdx[r][0] = up_idx(a0, b0);
-        rdx[r][1] = up_idx(a0, b1);
-        rdx[r][2] = up_idx(a1, b0);
-        rdx[r][3] = up_idx(a1, b1);
-        const int na0 = slot_next(a0, H), na1 = slot_next(a1, H), nb0 = slot_next(b0, H), nb1 = slot_next(b1, H);
-        wrx[r][0] = up_idx(na0, nb0);
-        wrx[r][1] = up_idx(na0, nb1);
-        wrx[r][2] = up_idx(na1, nb0);
-        wrx[r][3] = up_idx(na1, nb1);
+        for (int o = 32; o > 0; o >>= 1) f += __shfl_xor(f, o, 64);
+        if ((tid & 63) == 0) sred[tid >> 6] = f;
     }
     __syncthreads();
-    const double snorm = sqrt(((sred[0] + sred[1]) + (sred[2] + sred[3])) + ((sred[4] + sred[5]) + (sred[6] + sred[7])));
+    double nrm2 = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) nrm2 += sred[w];
+    const double snorm = sqrt(nrm2);
     const double inv = snorm > 0.0 ? 1.0 / snorm : 0.0;
     const double floor_s = ldexp(1.0, -40);
-    const int t = tid;  // wave 0: lane t computes slot t
-    int cur = 0, R = 0, sweeps = 0, converged = 0;
-    for (int sw = 0; sw < kJSweeps; ++sw) {
-        if (tid == 0) flag[sw & 1] = 0;
-        for (int rd = 0; rd < L - 1; ++rd, ++R) {
-            const double* T = Tb[cur];
+    int cur = 0, r = 0;
+    if (tid < 64) {
+        // ---- wave 0: diagonal block t and one off-diagonal block per slot ----
+        // Lane t also recomputes, from LDS, the entries of its neighbours'
+        // diagonal blocks that slot t's next rotation needs (bitwise the same
+        // as the owner's values: same operations, explicit FMAs), so no lane
+        // exchange sits on the round's critical path.
+        const int t = tid, tt = t < H ? t : 0;
+        const bool act_t = t < H;
+        const bool has_up = act_t && t + 1 < H, has_dn = act_t && t >= 1;
+        // off block feeding slot t's next a_xy: (0, 1) for slot 0, (t-1, t+1)
+        // inside, (H-2, H-1) for the last slot; written by its owner only
+        // (for H = 2 lane 1 reads the block lane 0 writes)
+        const bool has_src = act_t && H >= 2;
+        const bool has_off = has_src && (H >= 3 || t == 0);
+        const int ou = !has_src || t == 0 ? 0 : (t == H - 1 ? H - 2 : t - 1);
+        const int ov = !has_src ? 0 : (t == 0 ? 1 : (t == H - 1 ? H - 1 : t + 1));
+        const int a0 = 2 * tt, a1 = 2 * tt + 1;
+        const int na0 = slot_next(a0, H), na1 = slot_next(a1, H);
+        // lanes without a block store to the spare entries
+        const int dw0 = act_t ? St::idx(na0, na0) : St::kTrash, dw1 = act_t ? St::idx(na0, na1) : St::kTrash + 1,
+                  dw3 = act_t ? St::idx(na1, na1) : St::kTrash + 2;
+        const int tu = has_up ? t + 1 : tt, td = has_dn ? t - 1 : tt;
+        // blocks read: own diagonal, the diagonal above and below, the off block
+        const int dbk = St::blk(tt, tt), ubk = St::blk(tu, tu), xbk = St::blk(td, td), obk = St::blk(ou, ov);
+        int owx[4];
+        {
+            const int u0 = 2 * ou, u1 = u0 + 1, v0 = 2 * ov, v1 = v0 + 1;
+            const int nu0 = slot_next(u0, H), nu1 = slot_next(u1, H), nv0 = slot_next(v0, H),
+                      nv1 = slot_next(v1, H);
+            owx[0] = has_off ? St::idx(nu0, nv0) : St::kTrash;
+            owx[1] = has_off ? St::idx(nu0, nv1) : St::kTrash + 1;
+            owx[2] = has_off ? St::idx(nu1, nv0) : St::kTrash + 2;
+            owx[3] = has_off ? St::idx(nu1, nv1) : St::kTrash + 3;
+        }
+        // rotations of round 0
+        const double* T = Tb[0];
+        double2 cst = act_t ? jacobi_rotation(T[4 * dbk], T[4 * dbk + 3], T[4 * dbk + 1], inv, floor_s)
+                            : make_double2(1.0, 0.0);
+        cs[0][t] = cst;
+        if (act_t) rot[t] = cst;
+        bool any = __ballot(cst.y != 0.0) != 0;
+        int quiet = any ? 0 : 1, last_active = any ? 1 : 0;
+        if (t == 0) stop[0] = quiet >= L - 1;
+        __syncthreads();
+        for (; r < Rmax && quiet < L - 1; ++r) {
+            const int p = r & 1, q = p ^ 1;
+            T = Tb[cur];
+            const double2* T2 = reinterpret_cast<const double2*>(T);
             double* Tn = Tb[cur ^ 1];
-            double x[NB][4];
-#pragma unroll
-            for (int r = 0; r < NB; ++r)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) x[r][e] = T[rdx[r][e]];
-            if (tid < 64) {
-                double c = 1.0, s = 0.0;
-                if (t < H) {
-                    const double axx = T[(2 * t) * kJ64LD + 2 * t], ayy = T[(2 * t + 1) * kJ64LD + 2 * t + 1];
-                    const double axy = T[(2 * t) * kJ64LD + 2 * t + 1];
-                    const double as = axy * inv;
-                    if (fabs(as) > floor_s && axy * axy > 1e-30 * fabs(axx * ayy))
-                        jacobi_rotation_scaled((ayy - axx) * inv, as, c, s);
-                    cs[t] = make_double2(c, s);
-                    rot[(int64_t)R * H + t] = make_double2(c, s);
-                }
-                if (__ballot(s != 0.0) != 0 && tid == 0) flag[sw & 1] = 1;
+            const double2 d01 = T2[2 * dbk], u01 = T2[2 * ubk], w01 = T2[2 * xbk];
+            const double x3 = T[4 * dbk + 3], u3 = T[4 * ubk + 3], w3 = T[4 * xbk + 3];
+            const double2 olo = T2[2 * obk], ohi = T2[2 * obk + 1];
+            const double2 csu = cs[p][tu], csd = cs[p][td];
+            const double x0 = d01.x, x1 = d01.y, u0 = u01.x, u1 = u01.y, w0 = w01.x, w1 = w01.y;
+            const double xo[4] = {olo.x, olo.y, ohi.x, ohi.y};
+            // own diagonal block J^T X J, X = (a_xx, a_xy; a_xy, a_yy)
+            const double c = cst.x, s = cst.y;
+            const double y00 = fma(c, x0, -s * x1), y01 = fma(c, x1, -s * x3);
+            const double y10 = fma(s, x0, c * x1), y11 = fma(s, x1, c * x3);
+            const double r00 = fma(y00, c, -y01 * s), r01 = fma(y00, s, y01 * c), r11 = fma(y10, s, y11 * c);
+            // r00 of the block above, r11 of the block below (the owners' operations)
+            const double uy00 = fma(csu.x, u0, -csu.y * u1), uy01 = fma(csu.x, u1, -csu.y * u3);
+            const double up00 = fma(uy00, csu.x, -uy01 * csu.y);
+            const double wy10 = fma(csd.y, w0, csd.x * w1), wy11 = fma(csd.y, w1, csd.x * w3);
+            const double dn11 = fma(wy10, csd.y, wy11 * csd.x);
+            double o[4];
+            {
+                const double2 cu = t == 0 ? cst : csd, cv = t == H - 1 ? cst : csu;
+                rot_block(xo, cu.x, cu.y, cv.x, cv.y, o);
             }
-            __syncthreads();
+            Tn[dw0] = r00;
+            Tn[dw1] = r01;
+            Tn[dw3] = r11;
 #pragma unroll
-            for (int r = 0; r < NB; ++r) {
-                if (!bok[r]) continue;
-                const double2 ru = cs[buv[r] & 0xff], rv = cs[buv[r] >> 8];
-                const double c1 = ru.x, s1 = ru.y, c2 = rv.x, s2 = rv.y;
-                if (bdiag[r]) {
-                    // x = (a_xx, a_xy, a_xy, a_yy) of one slot
-                    const double y00 = c1 * x[r][0] - s1 * x[r][1], y01 = c1 * x[r][1] - s1 * x[r][3];
-                    const double y10 = s1 * x[r][0] + c1 * x[r][1], y11 = s1 * x[r][1] + c1 * x[r][3];
-                    Tn[wrx[r][0]] = y00 * c1 - y01 * s1;
-                    Tn[wrx[r][1]] = y00 * s1 + y01 * c1;
-                    Tn[wrx[r][3]] = y10 * s1 + y11 * c1;
-                } else {
-                    const double y00 = c1 * x[r][0] - s1 * x[r][2], y01 = c1 * x[r][1] - s1 * x[r][3];
-                    const double y10 = s1 * x[r][0] + c1 * x[r][2], y11 = s1 * x[r][1] + c1 * x[r][3];
-                    Tn[wrx[r][0]] = y00 * c2 - y01 * s2;
-                    Tn[wrx[r][1]] = y00 * s2 + y01 * c2;
-                    Tn[wrx[r][2]] = y10 * c2 - y11 * s2;
-                    Tn[wrx[r][3]] = y10 * s2 + y11 * c2;
-                }
+            for (int e = 0; e < 4; ++e) Tn[owx[e]] = o[e];
+            // entries of slot t in the next round
+            double xx, yy, xy;
+            if (H == 1) {
+                xx = r00;
+                yy = r11;
+                xy = r01;
+            } else if (t == 0) {
+                xx = r00;
+                yy = up00;
+                xy = o[0];
+            } else if (t == H - 1) {
+                xx = r11;
+                yy = dn11;
+                xy = o[3];
+            } else {
+                xx = up00;
+                yy = dn11;
+                xy = o[2];
+            }
+            cst = act_t ? jacobi_rotation(xx, yy, xy, inv, floor_s) : make_double2(1.0, 0.0);
+            cs[q][t] = cst;
+            any = __ballot(cst.y != 0.0) != 0;
+            quiet = any ? 0 : quiet + 1;
+            if (r + 1 < Rmax) {
+                if (act_t) rot[(int64_t)(r + 1) * H + t] = cst;
+                if (any) last_active = r + 2;
+            }
+            if (t == 0) stop[q] = quiet >= L - 1;
+            cur ^= 1;
+            __syncthreads();
+        }
+        if (t == 0) {
+            meta[0] = last_active;
+            if (info) {
+                info[0] = (r + L - 2) / (L - 1);
+                info[1] = r < Rmax;
+            }
+        }
+        // positions of the indices in round r
+        if (act_t) {
+            RRSlot sl;
+            sl.init(t, L, r % (L - 1));
+            int x, y;
+            sl.pair(t, x, y);
+            posof[x] = 2 * t;
+            posof[y] = 2 * t + 1;
+        }
+    } else {
+        // ---- waves 1..: the remaining off-diagonal blocks ----
+        int buv[NB], rbk[NB], wrx[NB][4];
+        bool bok[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            int u = 0, v = 1;
+            bok[b] = other_block(tid - 64 + (NT - 64) * b, H, u, v);
+            buv[b] = u | (v << 8);
+            const int a0 = 2 * u, a1 = 2 * u + 1, b0 = 2 * v, b1 = 2 * v + 1;
+            rbk[b] = St::blk(u, v);
+            const int na0 = slot_next(a0, H), na1 = slot_next(a1, H), nb0 = slot_next(b0, H),
+                      nb1 = slot_next(b1, H);
+            wrx[b][0] = St::idx(na0, nb0);
+            wrx[b][1] = St::idx(na0, nb1);
+            wrx[b][2] = St::idx(na1, nb0);
+            wrx[b][3] = St::idx(na1, nb1);
+        }
+        __syncthreads();
+        for (; r < Rmax; ++r) {
+            const int p = r & 1;
+            const double2* T2 = reinterpret_cast<const double2*>(Tb[cur]);
+            double* Tn = Tb[cur ^ 1];
+            // the loads are issued before the stop test (all indices are in range)
+            const int halt = stop[p];
+            double x[NB][4];
+            double2 ru[NB], rv[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                if (!bok[b]) continue;
+                const double2 lo = T2[2 * rbk[b]], hi = T2[2 * rbk[b] + 1];
+                x[b][0] = lo.x;
+                x[b][1] = lo.y;
+                x[b][2] = hi.x;
+                x[b][3] = hi.y;
+                ru[b] = cs[p][buv[b] & 0xff];
+                rv[b] = cs[p][buv[b] >> 8];
+            }
+            if (halt) break;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                if (!bok[b]) continue;
+                double o[4];
+                rot_block(x[b], ru[b].x, ru[b].y, rv[b].x, rv[b].y, o);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) Tn[wrx[b][e]] = o[e];
             }
             cur ^= 1;
             __syncthreads();
         }
-        ++sweeps;
-        if (!flag[sw & 1]) {
-            converged = 1;
-            break;
-        }
     }
-    // eigenvalues descending (ties by index); after whole sweeps index i is at slot_pos0(i)
+    __syncthreads();
+    // eigenvalues descending (ties by index)
     const double* T = Tb[cur];
     if (tid < l) {
-        const int pi = slot_pos0(tid, L);
-        const double li = T[pi * kJ64LD + pi];
+        const int pi = posof[tid];
+        const double li = T[St::idx(pi, pi)];
         int rank = 0;
         for (int j = 0; j < l; ++j) {
-            const int pj = slot_pos0(j, L);
-            const double lj = T[pj * kJ64LD + pj];
+            const int pj = posof[j];
+            const double lj = T[St::idx(pj, pj)];
             rank += (lj > li) || (lj == li && j < tid);
         }
         lam_out[rank] = li;
         meta[1 + tid] = rank;
     }
-    if (tid == 0) {
-        meta[0] = converged ? R - (L - 1) : R;  // a converged last sweep rotated nothing
-        if (info) {
-            info[0] = sweeps;
-            info[1] = converged;
-        }
-    }
 }
 
-// Rows 2 blockIdx.x + half of W from the recorded rotations (one wave; lane
-// t of each half applies pair t), then Wk[i][rank] = W[i][col] for the k
-// leading eigenvalues and Wks = Wk diag(1/sqrt(lam)).  Rotations are staged
-// 16 rounds at a time in registers.
+// Rows of W from the recorded rotations: one wave applies them to RPW rows at
+// once (lane t of each row applies slot t), then Wk[i][rank] = W[i][col] for
+// the k leading eigenvalues and Wks = Wk diag(1/sqrt(lam)).  Rotations are
+// staged 16 rounds at a time in registers.
+template <int KL>
 __global__ __launch_bounds__(64) void k_jacobi_vectors(const double2* __restrict__ rot, const int* __restrict__ meta,
                                                        const double* __restrict__ lam, int l, int k,
                                                        double* __restrict__ Wk, double* __restrict__ Wks) {
-    __shared__ double row[2][kJ64];
-    constexpr int CH = 16;
-    const int lane = threadIdx.x, t = lane & 31, half = lane >> 5;
-    const int i = 2 * blockIdx.x + half;
+    constexpr int HW = KL / 2, RPW = 64 / HW, CH = 16;
+    __shared__ double row[RPW][KL];
+    const int lane = threadIdx.x, t = lane % HW, half = lane / HW;
+    const int i = RPW * blockIdx.x + half;
     const int L = l + (l & 1), H = L / 2;
     const int R = meta[0];
     row[half][t] = (t == i) ? 1.0 : 0.0;
-    row[half][t + 32] = (t + 32 == i) ? 1.0 : 0.0;
+    row[half][t + HW] = (t + HW == i) ? 1.0 : 0.0;
     __syncthreads();
     const int tt = t < H ? t : 0;
     RRSlot st;
-    st.init(tt, L);
+    st.init(tt, L, 0);
     double* w = row[half];
     for (int r0 = 0; r0 < R; r0 += CH) {
-        double2 cs[CH];
+        double2 c[CH];
 #pragma unroll
         for (int u = 0; u < CH; ++u)
-            cs[u] = (r0 + u < R && t < H) ? rot[(int64_t)(r0 + u) * H + t] : make_double2(1.0, 0.0);
+            c[u] = (r0 + u < R && t < H) ? rot[(int64_t)(r0 + u) * H + t] : make_double2(1.0, 0.0);
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
             if (r0 + u < R) {
                 int x, y;
                 st.pair(tt, x, y);
-                if (cs[u].y != 0.0) {
+                if (c[u].y != 0.0) {
                     const double wx = w[x], wy = w[y];
-                    w[x] = cs[u].x * wx - cs[u].y * wy;
-                    w[y] = cs[u].y * wx + cs[u].x * wy;
+                    w[x] = c[u].x * wx - c[u].y * wy;
+                    w[y] = c[u].y * wx + c[u].x * wy;
                 }
                 st.next(L);
             }
@@ -675,7 +595,7 @@ __global__ __launch_bounds__(64) void k_jacobi_vectors(const double2* __restrict
     if (i < l) {
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
-            const int col = t + 32 * e;
+            const int col = t + HW * e;
             if (col < l) {
                 const int rank = meta[1 + col];
                 if (rank < k) {
@@ -742,17 +662,19 @@ size_t jacobi_ws_bytes(int64_t l) {
 
 hipError_t launch_jacobi_eigh(const double* T, int64_t l, int64_t k, double* lam, double* Wk, double* Wks, void* ws,
                               int* info, hipStream_t st) {
-    if (l < 1 || l > kMaxLJ || k < 1 || k > l) return hipErrorInvalidValue;
+    if (l < 1 || l > kMaxL || k < 1 || k > l) return hipErrorInvalidValue;
     const int L = (int)l + ((int)l & 1);
-    if (L <= kJ64) {
-        double2* rot = reinterpret_cast<double2*>(ws);
-        const int64_t H = L / 2;
-        int* meta = reinterpret_cast<int*>(rot + (int64_t)kJSweeps * (L - 1) * H);
-        hipLaunchKernelGGL(k_jacobi64, dim3(1), dim3(512), 0, st, T, (int)l, lam, rot, meta, info);
-        hipLaunchKernelGGL(k_jacobi_vectors, dim3((unsigned)((l + 1) / 2)), dim3(64), 0, st, (const double2*)rot,
-                           (const int*)meta, (const double*)lam, (int)l, (int)k, Wk, Wks);
+    const int64_t H = L / 2;
+    double2* rot = reinterpret_cast<double2*>(ws);
+    int* meta = reinterpret_cast<int*>(rot + (int64_t)kJSweeps * (L - 1) * H);
+    if (L <= 64) {
+        hipLaunchKernelGGL((k_jacobi_rr<64, 512, 2>), dim3(1), dim3(512), 0, st, T, (int)l, lam, rot, meta, info);
+        hipLaunchKernelGGL(k_jacobi_vectors<64>, dim3((unsigned)((l + 1) / 2)), dim3(64), 0, st,
+                           (const double2*)rot, (const int*)meta, (const double*)lam, (int)l, (int)k, Wk, Wks);
     } else {
-        hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), 0, st, T, 1, (int)l, (int)k, lam, Wk, Wks, info);
+        hipLaunchKernelGGL((k_jacobi_rr<128, 1024, 3>), dim3(1), dim3(1024), 0, st, T, (int)l, lam, rot, meta, info);
+        hipLaunchKernelGGL(k_jacobi_vectors<128>, dim3((unsigned)l), dim3(64), 0, st, (const double2*)rot,
+                           (const int*)meta, (const double*)lam, (int)l, (int)k, Wk, Wks);
     }
     return hipGetLastError();
 }

@@ -300,15 +300,20 @@ def test_decompose_errors(ctx):
     with pytest.raises(BcurError) as e:
         ctx.decompose(A, w.offsets, w.l + 1, w.s, om, w.draws)
     assert e.value.status == binding.E_ARG
+    # sketch width above the eigensolver's limit of 128
+    Aw = dev(gen.gaussian_product(200, 200, 8, 15).astype(np.float32))
+    with pytest.raises(BcurError) as e:
+        ctx.range_finder(Aw, dev_dense(gen.rademacher(200, 129, 16)), 8, q=1)
+    assert e.value.status == binding.E_ARG
 
 
 # ---------------------------------------------------------------------------
-# kernel-selection boundaries: sketch widths around the one-workgroup Jacobi
-# limit (L <= 64) and the smallest widths, C widths around the single-kernel
+# kernel-selection boundaries: sketch widths around the two Jacobi variants
+# (L <= 64 and L <= 128), the limit 128 and the smallest widths, C widths around the single-kernel
 # Cholesky limit (c <= 256) and the 64-wide panels of the blocked path
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("l", [1, 2, 3, 4, 5, 63, 64, 65, 66, 100])
+@pytest.mark.parametrize("l", [1, 2, 3, 4, 5, 6, 7, 63, 64, 65, 66, 100, 127, 128])
 def test_range_finder_sketch_widths(ctx, l):
     k = max(1, l - 3)
     m, n = 400, 300
