@@ -372,14 +372,16 @@ void fit_layout(Arena& a, FitBufs& b, int64_t m, int64_t n, int64_t c, bool need
     b.Ginv32 = a.take<float>(c * cp);
     const GemmPlan ph = plan_sgemm(c, n, m, true, true);
     const GemmPlan pg = plan_sgemm(c, c, m, true, true);
-    size_t part = std::max(sgemm_partial_floats(ph, c, n), sgemm_partial_floats(pg, c, c));
+    const GemmPlan pu = plan_sgemm(c, n, c, false, true);
+    size_t part = std::max(std::max(sgemm_partial_floats(ph, c, n), sgemm_partial_floats(pg, c, c)),
+                           sgemm_partial_floats(pu, c, n));
     b.part = a.take<float>(std::max<size_t>(part, 4));
     b.Gtmp = need_gtmp ? a.take<float>(c * cp) : nullptr;
     b.G = a.take<double>(c * c);
     b.Ginv = a.take<double>(c * c);
     b.spdws = a.take<double>(spd_inverse_ws_doubles(c));
     b.nwsE = ((m + 127) / 128) * ((n + 127) / 128);
-    b.nwsD = ((c + 127) / 128) * ((n + 127) / 128);
+    b.nwsD = add_dot_parts(pu, c, n);
     b.wsE = a.take<double>(b.nwsE);
     b.wsD = a.take<double>(b.nwsD);
     b.errv = a.take<double>(8);
@@ -420,22 +422,21 @@ bcur_status fit_run(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t m, 
         HIPCHK(launch_spd_inverse(b.G, c, b.Ginv, b.spdws, b.info, b.piv, ldexp(1.0, -24), st));
         HIPCHK(launch_f64_to_f32_2d(b.Ginv, c, c, c, b.Ginv32, cp, st));
     }
-    const GemmPlan pu = plan_sgemm(c, n, c, false, false);
+    const GemmPlan pu = plan_sgemm(c, n, c, false, true);
     STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_U, BCUR_STAGE_FIT_REDUCE, pu, c, n, c, false, b.Ginv32, cp, b.H, np, U, ldu,
-                     nullptr));
+                     b.part));
     const GemmPlan pe = plan_sgemm(m, n, c, false, false);
     STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_E, BCUR_STAGE_FIT_REDUCE, pe, m, n, c, false, C, ldc, U, ldu, b.E, np, nullptr,
                      EPI_RESID, A, lda, nullptr, 0, b.wsE));
     if (refine) {
         STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_F, BCUR_STAGE_FIT_REDUCE, ph, c, n, m, true, C, ldc, b.E, np, b.F, np,
                          b.part));
-        STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_DU, BCUR_STAGE_FIT_REDUCE, pu, c, n, c, false, b.Ginv32, cp, b.F, np, U,
-                         ldu, nullptr, EPI_ADD_DOT, U, ldu, b.F, np, b.wsD));
+        StageScope ts(ctx, BCUR_STAGE_FIT_DU);
+        HIPCHK(launch_sgemm_add_dot(pu, c, n, c, b.Ginv32, cp, b.F, np, U, ldu, b.part, U, ldu, b.F, np, b.wsD, st));
     }
-    // one partial per workgroup of the fused-epilogue GEMMs (128 x 128 tiles)
+    // one partial per workgroup of the residual GEMM (128 x 128 tiles), and of the dU sum
     const int64_t nwsE = ((m + 127) / 128) * ((n + 127) / 128);
-    const int64_t nwsD = ((c + 127) / 128) * ((n + 127) / 128);
-    HIPCHK(launch_fit_err(b.wsE, nwsE, b.wsD, refine ? nwsD : 0, b.errv, st));
+    HIPCHK(launch_fit_err(b.wsE, nwsE, b.wsD, refine ? add_dot_parts(pu, c, n) : 0, b.errv, st));
     return BCUR_OK;
 }
 

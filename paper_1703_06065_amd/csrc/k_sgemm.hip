@@ -76,6 +76,29 @@ __global__ __launch_bounds__(WM* WN * 64) void k_sgemm(const GemmArgs g) {
 
     float4 ra[A_F4], rb[B_F4];
 
+    // EPI_RESID: the residual input X of this thread's outputs is read before the
+    // main loop (a wave-uniform base plus one lane offset per load), so its HBM
+    // latency is hidden behind the MFMA work instead of following it.
+    constexpr int XM = EPI == EPI_RESID ? TM : 1, XN = EPI == EPI_RESID ? TN : 1;
+    float xv[XM][XN][16];
+    if constexpr (EPI == EPI_RESID) {
+        const int wmu = __builtin_amdgcn_readfirstlane(wm), wnu = __builtin_amdgcn_readfirstlane(wn);
+        const int64_t rb0 = m0 + wmu * WTM, cb0 = n0 + wnu * WTN;
+        const float* xbase = g.X + rb0 * g.ldx + cb0;
+        const int64_t lane_off = 4 * h * g.ldx + r;
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int rr = 32 * i + 8 * (v >> 2) + (v & 3);
+                    const int64_t row = rb0 + rr + 4 * h, col = cb0 + 32 * j + r;
+                    const float* px = xbase + (int64_t)rr * g.ldx + 32 * j;
+                    xv[i][j][v] = (row < g.M && col < g.N) ? px[lane_off] : 0.f;
+                }
+    }
+
     auto load_tiles = [&](int64_t k0) {
 #pragma unroll
         for (int u = 0; u < A_F4; ++u) {
@@ -160,7 +183,7 @@ __global__ __launch_bounds__(WM* WN * 64) void k_sgemm(const GemmArgs g) {
                     if (EPI == EPI_STORE) {
                         D[row * g.ldd + col] = x;
                     } else if (EPI == EPI_RESID) {
-                        const float e = g.X[row * g.ldx + col] - x;
+                        const float e = xv[i][j][v] - x;
                         D[row * g.ldd + col] = e;
                         wacc += (double)e * (double)e;
                     } else {
@@ -193,6 +216,38 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const float* __restrict__
         const int64_t row = e / N, col = e - row * N;
         D[row * ldd + col] = s;
     }
+}
+
+// The split-K sum with the EPI_ADD_DOT epilogue: D = X + S, S = sum_s P[s] in
+// the order s = 0, 1, ..., and wsum[block] = sum of S * Y over the block's
+// elements (each thread's in order, then the threads in a fixed tree).
+constexpr int kAddDotBlocks = 512;
+__global__ __launch_bounds__(256) void k_splitk_reduce_add_dot(const float* __restrict__ P, int splits, int64_t stride,
+                                                               int64_t M, int64_t N, float* D, int64_t ldd,
+                                                               const float* X, int64_t ldx,
+                                                               const float* __restrict__ Y, int64_t ldy,
+                                                               double* __restrict__ wsum) {
+    __shared__ double red[4];
+    const int64_t total = M * N;
+    double acc = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        float s = P[e];
+        for (int z = 1; z < splits; ++z) s += P[z * stride + e];
+        const int64_t row = e / N, col = e - row * N;
+        D[row * ldd + col] = X[row * ldx + col] + s;
+        acc += (double)s * (double)Y[row * ldy + col];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) wsum[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+int64_t add_dot_blocks(int64_t M, int64_t N) {
+    int64_t b = (M * N + 255) / 256;
+    if (b > kAddDotBlocks) b = kAddDotBlocks;
+    return b < 1 ? 1 : b;
 }
 
 struct Cfg {
@@ -295,6 +350,26 @@ hipError_t launch_splitk_reduce(const GemmPlan& p, int64_t M, int64_t N, const f
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)blocks), dim3(256), 0, st, partial, p.splits, M * N, M, N, D,
                        ldd);
+    return hipGetLastError();
+}
+
+int64_t add_dot_parts(const GemmPlan& p, int64_t M, int64_t N) {
+    if (p.splits > 1) return add_dot_blocks(M, N);
+    return ((M + kCfg[2].BM - 1) / kCfg[2].BM) * ((N + kCfg[2].BN - 1) / kCfg[2].BN);
+}
+
+hipError_t launch_sgemm_add_dot(const GemmPlan& p, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
+                                const float* B, int64_t ldb, float* D, int64_t ldd, float* partial, const float* X,
+                                int64_t ldx, const float* Y, int64_t ldy, double* wsum, hipStream_t st) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    if (p.splits <= 1)
+        return launch_sgemm_main(p, M, N, K, false, A, lda, B, ldb, D, ldd, partial, EPI_ADD_DOT, X, ldx, Y, ldy, wsum,
+                                 st);
+    const hipError_t e = launch_sgemm_main(p, M, N, K, false, A, lda, B, ldb, D, ldd, partial, EPI_STORE, nullptr, 0,
+                                           nullptr, 0, nullptr, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_splitk_reduce_add_dot, dim3((unsigned)add_dot_blocks(M, N)), dim3(256), 0, st, partial,
+                       p.splits, M * N, M, N, D, ldd, X, ldx, Y, ldy, wsum);
     return hipGetLastError();
 }
 
