@@ -355,8 +355,8 @@ bcur_status range_finder_run(bcur_ctx* ctx, const RFBufs& b, const float* A, int
 constexpr int64_t kFbPanel = 1024;  // columns of A per FP64 fallback panel
 
 struct FitBufs {
-    float *H, *E, *F, *Ginv32, *part, *Gtmp;
-    double *G, *Ginv, *spdws, *wsE, *wsD, *errv, *piv;
+    float *H, *E, *F, *X32, *part, *Gtmp;
+    double *G, *spdws, *wsE, *wsD, *errv, *piv;
     // FP64 Cholesky QR2 fallback for a numerically rank-deficient or
     // ill-conditioned C: its Gram matrix, L1^-1, Q1 = C L1^-T, two c x kFbPanel panels
     double *Gc64, *L1, *Q1, *T1, *T2;
@@ -369,16 +369,15 @@ void fit_layout(Arena& a, FitBufs& b, int64_t m, int64_t n, int64_t c, bool need
     b.H = a.take<float>(c * np);
     b.E = a.take<float>(m * np);
     b.F = a.take<float>(c * np);
-    b.Ginv32 = a.take<float>(c * cp);
+    b.X32 = a.take<float>(c * cp);
     const GemmPlan ph = plan_sgemm(c, n, m, true, true);
     const GemmPlan pg = plan_sgemm(c, c, m, true, true);
-    const GemmPlan pu = plan_sgemm(c, n, c, false, true);
+    const GemmPlan pu = plan_sgemm(c, n, c, true, true);
     size_t part = std::max(std::max(sgemm_partial_floats(ph, c, n), sgemm_partial_floats(pg, c, c)),
                            sgemm_partial_floats(pu, c, n));
     b.part = a.take<float>(std::max<size_t>(part, 4));
     b.Gtmp = need_gtmp ? a.take<float>(c * cp) : nullptr;
     b.G = a.take<double>(c * c);
-    b.Ginv = a.take<double>(c * c);
     b.spdws = a.take<double>(spd_inverse_ws_doubles(c));
     b.nwsE = ((m + 127) / 128) * ((n + 127) / 128);
     b.nwsD = add_dot_parts(pu, c, n);
@@ -394,7 +393,9 @@ void fit_layout(Arena& a, FitBufs& b, int64_t m, int64_t n, int64_t c, bool need
     b.T2 = a.take<double>(c * std::min<int64_t>(n, kFbPanel));
 }
 
-// U = C^+ A through the normal equations with one optional refinement step.
+// U = C^+ A through the normal equations with one optional refinement step:
+// G = C^T C = L L^T (FP64), X = L^-1 rounded to FP32 (G^-1 = X^T X), U = X^T (X H)
+// and dU = X^T (X F), each as two FP32 GEMMs.
 // When d_cols (device, c) gives C's columns within A (C = A[:, cols]), C^T C
 // is read off H = C^T A; otherwise (d_cols null, d_ident = 0..c-1) it is
 // formed by its own GEMM into Gtmp.  After the caller synchronizes,
@@ -419,11 +420,15 @@ bcur_status fit_run(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t m, 
                                 0, nullptr, st));
             HIPCHK(launch_gram_from_cols(b.Gtmp, cp, d_ident, c, b.G, st));
         }
-        HIPCHK(launch_spd_inverse(b.G, c, b.Ginv, b.spdws, b.info, b.piv, ldexp(1.0, -24), st));
-        HIPCHK(launch_f64_to_f32_2d(b.Ginv, c, c, c, b.Ginv32, cp, st));
+        double* Linv = nullptr;
+        HIPCHK(launch_chol_linv(b.G, c, b.spdws, b.info, b.piv, ldexp(1.0, -24), &Linv, st));
+        HIPCHK(launch_f64_to_f32_2d(Linv, c, c, c, b.X32, cp, st));
     }
-    const GemmPlan pu = plan_sgemm(c, n, c, false, true);
-    STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_U, BCUR_STAGE_FIT_REDUCE, pu, c, n, c, false, b.Ginv32, cp, b.H, np, U, ldu,
+    // W = X H (in F, not yet needed), U = X^T W
+    const GemmPlan pw = plan_sgemm(c, n, c, false, true), pt = plan_sgemm(c, n, c, true, true);
+    STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_U, BCUR_STAGE_FIT_REDUCE, pw, c, n, c, false, b.X32, cp, b.H, np, b.F, np,
+                     b.part));
+    STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_U, BCUR_STAGE_FIT_REDUCE, pt, c, n, c, true, b.X32, cp, b.F, np, U, ldu,
                      b.part));
     const GemmPlan pe = plan_sgemm(m, n, c, false, false);
     STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_E, BCUR_STAGE_FIT_REDUCE, pe, m, n, c, false, C, ldc, U, ldu, b.E, np, nullptr,
@@ -431,12 +436,16 @@ bcur_status fit_run(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t m, 
     if (refine) {
         STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_F, BCUR_STAGE_FIT_REDUCE, ph, c, n, m, true, C, ldc, b.E, np, b.F, np,
                          b.part));
+        // W = X F (in H, no longer needed), U += X^T W with <X^T W, F>
         StageScope ts(ctx, BCUR_STAGE_FIT_DU);
-        HIPCHK(launch_sgemm_add_dot(pu, c, n, c, b.Ginv32, cp, b.F, np, U, ldu, b.part, U, ldu, b.F, np, b.wsD, st));
+        HIPCHK(launch_sgemm(pw, c, n, c, false, b.X32, cp, b.F, np, b.H, np, b.part, EPI_STORE, nullptr, 0, nullptr, 0,
+                            nullptr, st));
+        HIPCHK(launch_sgemm_add_dot(pt, c, n, c, true, b.X32, cp, b.H, np, U, ldu, b.part, U, ldu, b.F, np, b.wsD,
+                                    st));
     }
     // one partial per workgroup of the residual GEMM (128 x 128 tiles), and of the dU sum
     const int64_t nwsE = ((m + 127) / 128) * ((n + 127) / 128);
-    HIPCHK(launch_fit_err(b.wsE, nwsE, b.wsD, refine ? add_dot_parts(pu, c, n) : 0, b.errv, st));
+    HIPCHK(launch_fit_err(b.wsE, nwsE, b.wsD, refine ? add_dot_parts(pt, c, n) : 0, b.errv, st));
     return BCUR_OK;
 }
 

@@ -57,13 +57,13 @@ hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K,
                              hipStream_t st);
 hipError_t launch_splitk_reduce(const GemmPlan& p, int64_t M, int64_t N, const float* partial, float* D,
                                 int64_t ldd, hipStream_t st);
-// D = X + A B (A: M x K, not transposed) and wsum[w] = partial sums of (A B) * Y,
+// D = X + op(A) B and wsum[w] = partial sums of (op(A) B) * Y,
 // with split-K when the plan has it (the sum and the epilogue then run in a
 // second kernel).  add_dot_parts gives the number of wsum partials written.
 int64_t add_dot_parts(const GemmPlan& p, int64_t M, int64_t N);
-hipError_t launch_sgemm_add_dot(const GemmPlan& p, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
-                                const float* B, int64_t ldb, float* D, int64_t ldd, float* partial, const float* X,
-                                int64_t ldx, const float* Y, int64_t ldy, double* wsum, hipStream_t st);
+hipError_t launch_sgemm_add_dot(const GemmPlan& p, int64_t M, int64_t N, int64_t K, bool transA, const float* A,
+                                int64_t lda, const float* B, int64_t ldb, float* D, int64_t ldd, float* partial,
+                                const float* X, int64_t ldx, const float* Y, int64_t ldy, double* wsum, hipStream_t st);
 hipError_t launch_sgemm(const GemmPlan& p, int64_t M, int64_t N, int64_t K, bool transA, const float* A,
                         int64_t lda, const float* B, int64_t ldb, float* D, int64_t ldd, float* partial,
                         int epi, const float* X, int64_t ldx, const float* Y, int64_t ldy, double* wsum,

@@ -338,6 +338,7 @@ hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K,
         case 210: e = run<2, true, EPI_STORE>(a, grid, st); break;
         case 201: e = run<2, false, EPI_RESID>(a, grid, st); break;
         case 202: e = run<2, false, EPI_ADD_DOT>(a, grid, st); break;
+        case 212: e = run<2, true, EPI_ADD_DOT>(a, grid, st); break;
         default: return hipErrorInvalidValue;
     }
     return e;
@@ -358,14 +359,14 @@ int64_t add_dot_parts(const GemmPlan& p, int64_t M, int64_t N) {
     return ((M + kCfg[2].BM - 1) / kCfg[2].BM) * ((N + kCfg[2].BN - 1) / kCfg[2].BN);
 }
 
-hipError_t launch_sgemm_add_dot(const GemmPlan& p, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
-                                const float* B, int64_t ldb, float* D, int64_t ldd, float* partial, const float* X,
-                                int64_t ldx, const float* Y, int64_t ldy, double* wsum, hipStream_t st) {
+hipError_t launch_sgemm_add_dot(const GemmPlan& p, int64_t M, int64_t N, int64_t K, bool transA, const float* A,
+                                int64_t lda, const float* B, int64_t ldb, float* D, int64_t ldd, float* partial,
+                                const float* X, int64_t ldx, const float* Y, int64_t ldy, double* wsum, hipStream_t st) {
     if (M <= 0 || N <= 0) return hipSuccess;
     if (p.splits <= 1)
-        return launch_sgemm_main(p, M, N, K, false, A, lda, B, ldb, D, ldd, partial, EPI_ADD_DOT, X, ldx, Y, ldy, wsum,
-                                 st);
-    const hipError_t e = launch_sgemm_main(p, M, N, K, false, A, lda, B, ldb, D, ldd, partial, EPI_STORE, nullptr, 0,
+        return launch_sgemm_main(p, M, N, K, transA, A, lda, B, ldb, D, ldd, partial, EPI_ADD_DOT, X, ldx, Y, ldy,
+                                 wsum, st);
+    const hipError_t e = launch_sgemm_main(p, M, N, K, transA, A, lda, B, ldb, D, ldd, partial, EPI_STORE, nullptr, 0,
                                            nullptr, 0, nullptr, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_splitk_reduce_add_dot, dim3((unsigned)add_dot_blocks(M, N)), dim3(256), 0, st, partial,

@@ -636,9 +636,10 @@ hipError_t launch_gram_reduce(const double* partial, int parts, int64_t l, doubl
 
 hipError_t launch_chol_rinv_small(const double* T, int64_t l, double* Rinv, int* info, hipStream_t st) {
     if (l < 1 || l > kMaxL) return hipErrorInvalidValue;
-    // one wave up to l = 64 (a step is latency-bound: fewer waves, cheaper barrier), four above
+    // a step is latency-bound: up to l = 64 a 16 x 16 grid with 4 x 4 slots per
+    // thread measured fastest (vs one wave with 8 x 8 slots), 16 x 16 with 8 x 8 above
     if (l <= 64)
-        hipLaunchKernelGGL((k_chol_rinv_small<8, 8>), dim3(1), dim3(64), 0, st, T, (int)l, Rinv, info);
+        hipLaunchKernelGGL((k_chol_rinv_small<16, 4>), dim3(1), dim3(256), 0, st, T, (int)l, Rinv, info);
     else
         hipLaunchKernelGGL((k_chol_rinv_small<16, 8>), dim3(1), dim3(256), 0, st, T, (int)l, Rinv, info);
     return hipGetLastError();
