@@ -201,10 +201,10 @@ enum {
     BCUR_STAGE_FIT_H = 9,     /* H = C^T A, main GEMM kernel */
     BCUR_STAGE_FIT_REDUCE = 10, /* split-K sums of the fit GEMMs */
     BCUR_STAGE_FIT_INV = 11,  /* (C^T C)^-1: blocked FP64 Cholesky inverse */
-    BCUR_STAGE_FIT_U = 12,    /* U = Ginv H */
+    BCUR_STAGE_FIT_U = 12,    /* U = X^T (X H), X = L^-1, G = L L^T */
     BCUR_STAGE_FIT_E = 13,    /* E = A - C U with ||E||_F^2 */
     BCUR_STAGE_FIT_F = 14,    /* F = C^T E, main GEMM kernel */
-    BCUR_STAGE_FIT_DU = 15,   /* U += Ginv F with <Ginv F, F> */
+    BCUR_STAGE_FIT_DU = 15,   /* U += X^T (X F) with <X^T X F, F> */
     BCUR_STAGE_RF_CAST = 16,  /* BF16 copies of A and of the sketch panels */
     BCUR_NUM_STAGES = 17
 };
