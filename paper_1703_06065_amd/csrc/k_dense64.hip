@@ -150,55 +150,211 @@ __global__ __launch_bounds__(64) void k_potrf_diag(const double* __restrict__ G,
     }
 }
 
-// The whole factorization for c <= 256 in one workgroup: tau from the largest
-// diagonal entry, then reg_chol_inv on the full matrix; writes X = L^-1 (c x c,
-// zero above the diagonal) and the pivot range into every piv pair.
-__global__ __launch_bounds__(1024) void k_chol_inv_full(const double* __restrict__ G, int64_t c, double rel_tau,
+// The whole factorization for c <= 256 in one workgroup (tau from the largest
+// diagonal entry; writes X = L^-1, zero above the diagonal, and the pivot
+// range into every piv pair), blocked by 16-wide panels with the bulk on the
+// FP64 matrix cores (v_mfma_f64_16x16x4f64: lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16]; register v of the result is D[4 v + l / 16][l % 16]).
+// The lower triangle is held as 16 x 16 tiles in the result layout, tile
+// e = I (I + 1) / 2 + C (I >= C) in slot e / 8 of wave e mod 8 (eight waves: a
+// lane's 256 registers hold the 17 tiles of its wave).  Panel J applies the 16
+// rank-1 steps of reg_chol_inv as one block:
+//   A  the diagonal tile S11 is factored in one wave by the rank-1 steps,
+//      giving X11 = L11^-1 (pivots not above tau dropped, as there);
+//   B  row J becomes final: X_J = X11 W_J for the tiles left of the diagonal;
+//      column J gives L21 = S21 X11^T, and its tiles become -L21 X11;
+//   C  every other tile below row J takes the rank-16 update
+//      -= L21_I [X_J | L21^T]_C.
+// Padding beyond c is the identity, so it never couples to the matrix.
+typedef double d4v __attribute__((ext_vector_type(4)));
+constexpr int kMT = 16;      // tiles per side
+constexpr int kMW = 8;       // waves
+constexpr int kMSlots = 17;  // lower tiles per wave: ceil(136 / 8)
+constexpr int kMLd = 17;     // padded row length of the LDS tiles
+
+__global__ __launch_bounds__(kMW * 64) void k_chol_inv_mfma(const double* __restrict__ G, int64_t c, double rel_tau,
                                                         double* __restrict__ X, double* __restrict__ piv, int npiv,
                                                         int* __restrict__ info) {
-    constexpr int TG = 32, NR = 8, NT = TG * TG;
-    __shared__ double P[2 * TG * NR + 1];
-    __shared__ double pv[TG * NR];
-    __shared__ double wmax[NT / 64];
-    const int tid = threadIdx.x, tr = tid / TG, tc = tid % TG;
-    const int w = (int)c;
-    double m[NR * (NR + 1) / 2];
+    __shared__ double L21s[kMT * 16 * kMLd];       // L21, row i at i * kMLd
+    __shared__ double Vs[16 * (kMT * 16 + 1)];     // X_J (columns < 16 J), row k at k * 257
+    __shared__ double X11s[16 * kMLd];
+    __shared__ double scr[kMW][16 * kMLd];         // one tile per wave
+    __shared__ double pivs[kMT * 16];
+    __shared__ double wmax[kMW];
+    constexpr int LDV = kMT * 16 + 1;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: slot data in scalar registers
+    const int g = lane >> 4, cc = lane & 15;
+    const int w = (int)c, nt = (w + 15) / 16, ntiles = nt * (nt + 1) / 2;
+    // zeros above the diagonal of X
+    for (int64_t e = tid; e < c * c; e += kMW * 64) {
+        const int64_t i = e / c, j = e - i * c;
+        if (j > i) X[e] = 0.0;
+    }
+    // this wave's tiles: tm[s] = I | C << 8 (scalar), -1 past the last tile
+    int tm[kMSlots];
 #pragma unroll
-    for (int a = 0; a < NR; ++a)
+    for (int s = 0; s < kMSlots; ++s) {
+        const int e = wave + kMW * s;
+        int I = 0;
+        while ((I + 1) * (I + 2) / 2 <= e) ++I;
+        tm[s] = e < ntiles ? (I | ((e - I * (I + 1) / 2) << 8)) : -1;
+    }
+    d4v acc[kMSlots];
 #pragma unroll
-        for (int b = 0; b <= a; ++b) {
-            const int i = tr + TG * a, cc = tc + TG * b;
-            m[tri_slot(a, b)] = (i < w && cc <= i) ? G[(int64_t)i * c + cc] : 0.0;
+    for (int s = 0; s < kMSlots; ++s)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = 16 * (tm[s] & 0xff) + 4 * v + g, j = 16 * (tm[s] >> 8) + cc;
+            double x = 0.0;
+            if (tm[s] >= 0 && j <= i) x = (i < w && j < w) ? G[(int64_t)i * c + j] : (i == j ? 1.0 : 0.0);
+            acc[s][v] = x;
         }
-    // largest diagonal entry: wave maxima, then the wave results
-    double dm = tid < w ? G[(int64_t)tid * c + tid] : 0.0;
+    double dm = 0.0;
+    for (int i = tid; i < w; i += kMW * 64) dm = fmax(dm, G[(int64_t)i * c + i]);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o, 64));
-    if ((tid & 63) == 0) wmax[tid >> 6] = dm;
+    if (lane == 0) wmax[wave] = dm;
     __syncthreads();
     dm = 0.0;
 #pragma unroll
-    for (int u = 0; u < NT / 64; ++u) dm = fmax(dm, wmax[u]);
-    const double tau = (double)c * rel_tau * dm;
-    double pmin, pmax;
-    int ndrop;
-    reg_chol_inv<TG, NR>(m, w, tau > 0.0 ? tau : 0.0, P, pv, pmin, pmax, ndrop);
-    // the owner of (i, c) also writes the zero at (c, i) above the diagonal
+    for (int u = 0; u < kMW; ++u) dm = fmax(dm, wmax[u]);
+    const double tau = fmax((double)c * rel_tau * dm, 0.0);
+    double* S = scr[wave];
+
+    for (int J = 0; J < nt; ++J) {
+        // the tile coordinates are re-read every panel, so the LDS addresses
+        // derived from them are not all kept live across the loop
 #pragma unroll
-    for (int a = 0; a < NR; ++a)
+        for (int s = 0; s < kMSlots; ++s) asm volatile("" : "+s"(tm[s]));
+        // ---- A: factor the diagonal tile (its owner wave) ----
+        const int ed = J * (J + 1) / 2 + J;
+        if (wave == ed % kMW) {
+            const int sd = ed / kMW;
 #pragma unroll
-        for (int b = 0; b <= a; ++b) {
-            const int i = tr + TG * a, cc = tc + TG * b;
-            if (i < w && cc <= i) {
-                X[(int64_t)i * c + cc] = m[tri_slot(a, b)];
-                if (cc < i) X[(int64_t)cc * c + i] = 0.0;
+            for (int s = 0; s < kMSlots; ++s)
+                if (s == sd)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) S[(4 * v + g) * kMLd + cc] = acc[s][v];
+            d4v a;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) a[v] = S[(4 * v + g) * kMLd + cc];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const double d = S[j * kMLd + j];
+                double pr[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) pr[v] = S[(4 * v + g) * kMLd + j];
+                const double pc = cc <= j ? S[j * kMLd + cc] : S[cc * kMLd + j];
+                if (lane == 0) pivs[16 * J + j] = d;
+                const double r = d > tau ? rsqrt_nr(d) : 0.0, rd = r * r;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = 4 * v + g;
+                    if (i > j) {
+                        if (cc == j)
+                            a[v] = -pr[v] * rd;
+                        else if (cc <= i)
+                            a[v] = fma(-pr[v] * rd, pc, a[v]);
+                    } else if (i == j) {
+                        if (cc < j)
+                            a[v] = pc * r;
+                        else if (cc == j)
+                            a[v] = r;
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int v = 0; v < 4; ++v) S[(4 * v + g) * kMLd + cc] = a[v];
+                __builtin_amdgcn_wave_barrier();
+            }
+            // X11 (zero above the diagonal): to LDS, to X, and kept as the final tile
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 4 * v + g;
+                const double x = cc <= i ? a[v] : 0.0;
+                a[v] = x;
+                X11s[i * kMLd + cc] = x;
+                const int gi = 16 * J + i, gj = 16 * J + cc;
+                if (cc <= i && gi < w && gj < w) X[(int64_t)gi * c + gj] = x;
+            }
+#pragma unroll
+            for (int s = 0; s < kMSlots; ++s)
+                if (s == sd) acc[s] = a;
+        }
+        __syncthreads();
+        // ---- B: row J final, column J to L21 ----
+#pragma unroll
+        for (int s = 0; s < kMSlots; ++s) {
+            if (tm[s] < 0) continue;
+            const int I = tm[s] & 0xff, C = tm[s] >> 8;
+            if (I == J && C < J) {
+                // X_J,C = X11 W (W: this tile; its register v is B's k-block v)
+                d4v xt = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int kb = 0; kb < 4; ++kb)
+                    xt = __builtin_amdgcn_mfma_f64_16x16x4f64(X11s[cc * kMLd + 4 * kb + g], acc[s][kb], xt, 0, 0, 0);
+                acc[s] = xt;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = 4 * v + g, gi = 16 * J + i, gj = 16 * C + cc;
+                    Vs[i * LDV + gj] = xt[v];
+                    if (gi < w) X[(int64_t)gi * c + gj] = xt[v];
+                }
+            } else if (I > J && C == J) {
+                // L21 = S21 X11^T: S21 goes through this wave's scratch for the A layout
+#pragma unroll
+                for (int v = 0; v < 4; ++v) S[(4 * v + g) * kMLd + cc] = acc[s][v];
+                __builtin_amdgcn_wave_barrier();
+                d4v l21 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int kb = 0; kb < 4; ++kb)
+                    l21 = __builtin_amdgcn_mfma_f64_16x16x4f64(S[cc * kMLd + 4 * kb + g], X11s[cc * kMLd + 4 * kb + g],
+                                                               l21, 0, 0, 0);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) L21s[(16 * I + 4 * v + g) * kMLd + cc] = l21[v];
+                __builtin_amdgcn_wave_barrier();
+                // this tile becomes -L21 X11
+                d4v t = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int kb = 0; kb < 4; ++kb)
+                    t = __builtin_amdgcn_mfma_f64_16x16x4f64(-L21s[(16 * I + cc) * kMLd + 4 * kb + g],
+                                                             X11s[(4 * kb + g) * kMLd + cc], t, 0, 0, 0);
+                acc[s] = t;
+                __builtin_amdgcn_wave_barrier();
             }
         }
-    if (tid < npiv) {
-        piv[2 * tid] = pmin;
-        piv[2 * tid + 1] = pmax;
+        __syncthreads();
+        // ---- C: rank-16 update of the tiles below row J ----
+#pragma unroll
+        for (int s = 0; s < kMSlots; ++s) {
+            if (tm[s] < 0) continue;
+            const int I = tm[s] & 0xff, C = tm[s] >> 8;
+            if (I <= J || C == J) continue;
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) {
+                const double av = -L21s[(16 * I + cc) * kMLd + 4 * kb + g];
+                const double bv = C < J ? Vs[(4 * kb + g) * LDV + 16 * C + cc] : L21s[(16 * C + cc) * kMLd + 4 * kb + g];
+                acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[s], 0, 0, 0);
+            }
+        }
     }
-    if (tid == 0 && ndrop) atomicOr(info, 1);
+    __syncthreads();
+    if (tid == 0) {
+        double pmin = INFINITY, pmax = 0.0;
+        int ndrop = 0;
+        for (int j = 0; j < w; ++j) {
+            const double d = pivs[j];
+            pmin = fmin(pmin, d);
+            pmax = fmax(pmax, d);
+            ndrop += d > tau ? 0 : 1;
+        }
+        for (int q = 0; q < npiv; ++q) {
+            piv[2 * q] = pmin;
+            piv[2 * q + 1] = pmax;
+        }
+        if (ndrop) atomicOr(info, 1);
+    }
 }
 
 // One anti-diagonal of the blocked inverse X = L^-1 (lower):
@@ -306,7 +462,7 @@ static hipError_t chol_and_inverse_factor(double* G, int64_t c, double* ws, int*
     double* pivb = X + c * c;
     double* maxd = pivb + 2 * nblk;
     if (c <= kFullChol) {
-        hipLaunchKernelGGL(k_chol_inv_full, dim3(1), dim3(1024), 0, st, (const double*)G, c, rel_tau, X,
+        hipLaunchKernelGGL(k_chol_inv_mfma, dim3(1), dim3(kMW * 64), 0, st, (const double*)G, c, rel_tau, X,
                            piv ? piv : pivb, (int)nblk, info);
         *Xout = X;
         return hipGetLastError();
