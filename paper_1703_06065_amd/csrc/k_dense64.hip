@@ -247,21 +247,16 @@ __global__ __launch_bounds__(kMW * 64) void k_chol_inv_mfma(const double* __rest
                 for (int v = 0; v < 4; ++v) pr[v] = S[(4 * v + g) * kMLd + j];
                 const double pc = cc <= j ? S[j * kMLd + cc] : S[cc * kMLd + j];
                 if (lane == 0) pivs[16 * J + j] = d;
-                const double r = d > tau ? rsqrt_nr(d) : 0.0, rd = r * r;
+                // branch-free (divergent branches cost more than the selects):
+                // the root is taken of a positive stand-in and masked
+                const double r = d > tau ? rsqrt_nr(d > tau ? d : 1.0) : 0.0, rd = r * r;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int i = 4 * v + g;
-                    if (i > j) {
-                        if (cc == j)
-                            a[v] = -pr[v] * rd;
-                        else if (cc <= i)
-                            a[v] = fma(-pr[v] * rd, pc, a[v]);
-                    } else if (i == j) {
-                        if (cc < j)
-                            a[v] = pc * r;
-                        else if (cc == j)
-                            a[v] = r;
-                    }
+                    const double q = -pr[v] * rd;
+                    const double below = cc == j ? q : (cc <= i ? fma(q, pc, a[v]) : a[v]);
+                    const double onrow = cc < j ? pc * r : (cc == j ? r : a[v]);
+                    a[v] = i > j ? below : (i == j ? onrow : a[v]);
                 }
                 __builtin_amdgcn_wave_barrier();
 #pragma unroll
