@@ -26,12 +26,13 @@ PEAK_HBM_GBS = 8000.0
 def algorithmic_flops(m, n, k, l, q, c):
     """FLOPs the method needs per decomposition (sketch width l, no padding)."""
     rf = (2 * q + 3) * 2.0 * m * n * l              # (q+1) x (A Q, A^T Z) + the Rayleigh-Ritz A Q
-    fit = 3 * 2.0 * m * c * n + 2 * 2.0 * c * c * n  # C^T A, A - C U, C^T E; Ginv H, Ginv F
+    fit = 3 * 2.0 * m * c * n + 4 * 2.0 * c * c * n  # C^T A, A - C U, C^T E; X^T (X H), X^T (X F)
     return rf, fit
 
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 counter runs of
-# this command (FETCH_SIZE and WRITE_SIZE, KiB per dispatch), each scaled by
+# this command (FETCH_SIZE and WRITE_SIZE, KiB per H / F dispatch: grid of
+# 512 x 32 x 8 workgroups), each scaled by
 # the same counter's reading for a plain copy of known size; null when the
 # kernel has changed since the counters were taken.
 TRAFFIC = {"m": 8192, "n": 4096, "c": 256, "fetch_kib": 147538.0, "write_kib": 32768.0,
