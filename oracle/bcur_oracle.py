@@ -33,6 +33,17 @@ design notes of the repository):
       depend on them because C C^+ A is a projection (Sec. 2.1);
   R5  duplicated blocks (with replacement) are removed before the fit.
 
+  R11 (Alg. 1) step 1 draws r distinct rows uniformly: the sampler below
+      with unit weights on m one-row blocks; R is scaled by 1/sqrt(r p_i) =
+      sqrt(m / r) (the sampling matrix S_R of Sec. 3.1);
+  R12 (Alg. 1) the scores use the top-kr right singular vectors of R; the
+      listing says r, the text says k, so kr is a parameter (r by default);
+  R13 (Alg. 1) U = W^+ treats singular values of W at or below
+      max(r, c) 2^-24 sigma_1 as zero (W holds FP32 data);
+  R14 (Sec. 4.1) U_k is read as (W_k)^+, the pseudoinverse of the best
+      rank-k approximation of W: it keeps the k largest singular values of W
+      (the best rank-k approximation of W^+ itself would keep the smallest).
+
 Parity unpinned: the (1+eps) relative-error guarantees (Thm. 2, the Remark
 of Sec. 3.3, Lemma 3 of App. A.1.1) carry unspecified constants; they are
 reported as context only.
@@ -342,6 +353,22 @@ def fit_intersection(A: np.ndarray, C: np.ndarray, R: np.ndarray, Wmat: np.ndarr
     return U, float(math.sqrt(float(np.sum(E * E))))
 
 
+def pinv_cut(Wmat: np.ndarray, rank_k: int = 0) -> Tuple[np.ndarray, int]:
+    """W^+ from the SVD with the cutoff of R13; rank_k > 0 keeps at most the
+    rank_k largest singular values, giving (W_k)^+ (R14).  Returns the
+    pseudoinverse and the number of singular values kept."""
+    W = np.asarray(Wmat, dtype=np.float64)
+    Uw, sw, Vtw = np.linalg.svd(W, full_matrices=False)
+    if sw.size == 0 or sw[0] == 0.0:
+        return np.zeros((W.shape[1], W.shape[0])), 0
+    keep = int(np.sum(sw > max(W.shape) * 2.0 ** -24 * sw[0]))
+    if rank_k > 0:
+        keep = min(keep, rank_k)
+    inv = np.zeros_like(sw)
+    inv[:keep] = 1.0 / sw[:keep]
+    return (Vtw.T * inv) @ Uw.T, keep
+
+
 def cond2(C: np.ndarray) -> float:
     s = np.linalg.svd(np.asarray(C, dtype=np.float64), compute_uv=False)
     return float(s[0] / s[-1]) if s[-1] > 0 else math.inf
@@ -399,4 +426,56 @@ def decompose(A: np.ndarray, offsets: Sequence[int], k: int, s: int, omega: Opti
         out.update(U=U, err=err)
     if with_fit:
         out["rel_err"] = out["err"] / math.sqrt(out["frob2"]) if out["frob2"] > 0 else 0.0
+    return out
+
+
+def alg1_rows(m: int, r: int, draws: Sequence[int]) -> np.ndarray:
+    """Alg. 1 step 1: r distinct rows, each remaining row equally likely
+    (p_i = 1/m; R11): the sampler with unit weights on m one-row blocks."""
+    return sample_blocks(np.ones(m), draws, r, replace=False)["idx"]
+
+
+def alg1(A: np.ndarray, offsets: Sequence[int], r: int, s: int, omega: Optional[np.ndarray],
+         draws: Sequence[int], kr: Optional[int] = None, q: int = 1, replace: bool = False,
+         rank_k: int = 0, mode: str = "twin") -> Dict[str, object]:
+    """Algorithm 1 of Sec. 3.1 (Block CUR with uniform rows), steps in order.
+
+    1. r rows drawn uniformly (draws[:r]; R11): R = S_R^T A = sqrt(m/r) A[rows].
+    2. scores l_g(R, kr) = ||V_{R,kr}^T E_g||_F^2 (Def. 2 on R; R12) from the
+       float64 range finder on R with the test matrix omega (n x r, "twin") or
+       an exact SVD of R ("exact"); s blocks drawn from draws[r:r+s] with
+       p_g = l_g / kr; C = A S with S scaled by 1/sqrt(s p) (Sec. 3.1).
+    3. W = R S, U = W^+ (R13) or U_k = (W_k)^+ (R14), err = ||A - C U R||_F."""
+    A64 = np.asarray(A, dtype=np.float64)
+    m, n = A64.shape
+    kr = r if kr is None else kr
+    out: Dict[str, object] = {"frob2": frob2(A64), "finite": all_finite(A64)}
+    rows = alg1_rows(m, r, draws[:r])
+    R = math.sqrt(m / r) * A64[rows, :]
+    if mode == "twin":
+        Vr = range_finder(R, omega, q, kr)["Vk"]
+    elif mode == "exact":
+        Vr = exact_right_subspace(R, kr)
+    else:
+        raise ValueError(mode)
+    scores = block_scores(Vr, offsets)
+    samp = sample_blocks(scores, draws[r:r + s], s, replace)
+    idx, weights = samp["idx"], samp["weights"]
+    # duplicated blocks (with replacement) are kept once, with the first draw's weight (R5)
+    seen, keep_idx, keep_w = set(), [], []
+    for j, wgt in zip(idx, weights):
+        if int(j) not in seen:
+            seen.add(int(j))
+            keep_idx.append(int(j))
+            keep_w.append(float(wgt))
+    S = sampling_matrix(offsets, keep_idx, keep_w)
+    C = A64 @ S
+    Wmat = R @ S
+    U, rank_w = pinv_cut(Wmat, rank_k)
+    E = A64 - C @ U @ R
+    err = float(math.sqrt(float(np.sum(E * E))))
+    out.update(rows=rows, R=R, scores=scores, idx=idx, weights=weights, margins=samp["margins"],
+               kept=keep_idx, kept_weights=keep_w,
+               cols=selected_columns(offsets, keep_idx), C=C, W=Wmat, U=U, rank_w=rank_w, err=err,
+               rel_err=err / math.sqrt(out["frob2"]) if out["frob2"] > 0 else 0.0)
     return out

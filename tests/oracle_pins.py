@@ -398,6 +398,93 @@ def check_paper_synthetic_generator(O):
     assert res["err"] <= 1e-9 * math.sqrt(res["frob2"])
 
 
+# --------------------------------------------------------------------------
+# Algorithm 1 (Sec. 3.1): uniform rows, U = W^+ of the scaled intersection
+# --------------------------------------------------------------------------
+
+def check_alg1_rows_uniform_distinct(O):
+    """Step 1: r distinct rows; with unit weights the draw x = floor(r_t W /
+    2^64) picks the x-th remaining row, so the draw 0 takes the first
+    remaining row and the draw 2^64 - 1 the last."""
+    m = 11
+    rows = O.alg1_rows(m, 4, [0, 2 ** 64 - 1, 0, 2 ** 64 - 1])
+    assert list(rows) == [0, 10, 1, 9], rows
+    rows = O.alg1_rows(m, m, gen.draws_u64(m, 20))
+    assert sorted(int(i) for i in rows) == list(range(m))
+    # a draw just below (j + 1) / W of the range lands in remaining row j
+    W = m
+    for j in (0, 3, 10):
+        d = ((j + 1) << 64) // W - 1
+        assert int(O.alg1_rows(m, 1, [d])[0]) == j
+
+
+def check_alg1_penrose(O):
+    """U = W^+ satisfies the four Penrose conditions (Sec. 2.1), for a full
+    rank W and for one with a repeated column."""
+    rng = np.random.default_rng(21)
+    for W in (rng.standard_normal((7, 5)), rng.standard_normal((5, 9))):
+        Wd = np.concatenate([W, W[:, :1]], axis=1)
+        for M in (W, Wd):
+            U, _ = O.pinv_cut(M)
+            assert np.allclose(M @ U @ M, M, atol=1e-10)
+            assert np.allclose(U @ M @ U, U, atol=1e-10)
+            assert np.allclose((M @ U).T, M @ U, atol=1e-10)
+            assert np.allclose((U @ M).T, U @ M, atol=1e-10)
+
+
+def check_alg1_rank_k(O):
+    """U_k = (W_k)^+: W U_k W is the best rank-k approximation of W, so
+    ||W - W U_k W||_F^2 is the sum of the squared singular values past k
+    (Eckart-Young); U_k equals U once k reaches rank(W); C U_k R has rank k."""
+    rng = np.random.default_rng(22)
+    W = rng.standard_normal((9, 6)) @ np.diag([5.0, 3.0, 2.0, 1.0, 0.5, 0.1])
+    sv = np.linalg.svd(W, compute_uv=False)
+    for k in (1, 2, 4):
+        Uk, kept = O.pinv_cut(W, k)
+        assert kept == k
+        got = np.linalg.norm(W - W @ Uk @ W)
+        want = math.sqrt(float(np.sum(sv[k:] ** 2)))
+        assert abs(got - want) <= 1e-10 * sv[0], (k, got, want)
+    U, kept = O.pinv_cut(W)
+    U6, _ = O.pinv_cut(W, 6)
+    assert kept == 6 and np.allclose(U, U6, atol=1e-12)
+    A = gen.gaussian_product(40, 48, 8, 23)
+    off = gen.contiguous_blocks(48, 6)
+    res = O.alg1(A, off, 12, 3, gen.rademacher(48, 12, 23), gen.draws_u64(15, 23), rank_k=3)
+    assert res["rank_w"] == 3
+    assert np.linalg.matrix_rank(res["C"] @ res["U"] @ res["R"]) == 3
+
+
+def check_alg1_all_rows_is_column_fit(O):
+    """With every row sampled (r = m) R is A with its rows permuted, so
+    C W^+ R = A S (A S)^+ A = C C^+ A whenever C has full column rank: the
+    error is the column-selection error of the least-squares fit, and the
+    scaling of S drops out (Sec. 2.1, the Remark of Sec. 3.3)."""
+    rng = np.random.default_rng(24)
+    A = rng.standard_normal((24, 60)) @ np.diag(0.95 ** np.arange(60))
+    off = gen.contiguous_blocks(60, 5)
+    res = O.alg1(A, off, 24, 3, None, gen.draws_u64(27, 24), kr=6, mode="exact")
+    Cun = O.gather_columns(A, off, res["idx"])
+    _, want = O.fit_columns(A, Cun)
+    assert abs(res["err"] - want) <= 1e-9 * want, (res["err"], want)
+    # unscaled C and R through the library pseudoinverse give the same error
+    Run = A[res["rows"], :]
+    Wun = Run[:, O.selected_columns(off, res["idx"])]
+    _, e2 = O.fit_intersection(A, Cun, Run, Wun)
+    assert abs(e2 - want) <= 1e-9 * want
+
+
+def check_alg1_exact_low_rank(O):
+    """When the sampled rows and columns capture the rank of A, C W^+ R
+    reconstructs A exactly (the intersection carries its whole rank)."""
+    A = gen.gaussian_product(50, 64, 6, 25)
+    off = gen.contiguous_blocks(64, 8)
+    for mode in ("exact", "twin"):
+        res = O.alg1(A, off, 10, 2, gen.rademacher(64, 10, 25), gen.draws_u64(12, 25), kr=6, mode=mode)
+        assert res["rank_w"] == 6
+        assert res["err"] <= 1e-9 * math.sqrt(res["frob2"]), res["err"]
+
+
 ALL_CHECKS = [
     check_frob_closed_form,
     check_scores_sum_to_k,
@@ -417,4 +504,9 @@ ALL_CHECKS = [
     check_fit_projection,
     check_cur_reductions,
     check_paper_synthetic_generator,
+    check_alg1_rows_uniform_distinct,
+    check_alg1_penrose,
+    check_alg1_rank_k,
+    check_alg1_all_rows_is_column_fit,
+    check_alg1_exact_low_rank,
 ]

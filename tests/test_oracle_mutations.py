@@ -98,7 +98,30 @@ def _gather_wrong_block(A, offsets, idx, dedupe=True):
     return O.gather_columns(A, offsets, [min(int(j) + 1, len(offsets) - 2) for j in idx], dedupe)
 
 
+def _pinv_smallest(Wmat, rank_k=0):
+    # the literal best rank-k approximation of W^+: keeps the smallest singular values of W
+    W = np.asarray(Wmat, dtype=np.float64)
+    Uw, sw, Vtw = np.linalg.svd(W, full_matrices=False)
+    keep = int(np.sum(sw > max(W.shape) * 2.0 ** -24 * sw[0]))
+    inv = np.zeros_like(sw)
+    lo = keep - rank_k if 0 < rank_k < keep else 0
+    inv[lo:keep] = 1.0 / sw[lo:keep]
+    return (Vtw.T * inv) @ Uw.T, keep - lo
+
+
+def _pinv_transpose(Wmat, rank_k=0):
+    W = np.asarray(Wmat, dtype=np.float64)
+    return W.T / max(1.0, float(np.sum(W * W))), min(W.shape)
+
+
+def _rows_with_replacement(m, r, draws):
+    return O.sample_blocks(np.ones(m), draws, r, replace=True)["idx"]
+
+
 MUTANTS = {
+    "pinv-keeps-smallest": dict(pinv_cut=_pinv_smallest),
+    "pinv-transpose": dict(pinv_cut=_pinv_transpose),
+    "rows-with-replacement": dict(alg1_rows=_rows_with_replacement),
     "scores-not-squared": dict(block_scores=_scores_norm_not_squared),
     "scores-edge-shift": dict(block_scores=_scores_edge_shift),
     "frob-drops-row": dict(frob2=_frob_drops_row),
