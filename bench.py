@@ -145,6 +145,105 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def alg1_flops(m, n, r, kr, c):
+    """FLOPs of Algorithm 1 per decomposition: R R^T and V = R^T U_kr S^-1,
+    the Gram matrix of W and W^+, C U (m x c x r) and the residual
+    A - (C U) R (m x r x n)."""
+    t = min(r, c)
+    return (2.0 * r * r * n + 2.0 * n * r * kr + 2.0 * t * t * max(r, c) + 2.0 * c * r * t
+            + 2.0 * m * c * r + 2.0 * m * r * n)
+
+
+def alg1_bench(args):
+    """Algorithm 1 (uniform rows, U = W^+) on the same 8192 x 4096 workload:
+    r = 128 rows, scores from the top-r right singular vectors of R (the
+    listing's choice; --kr picks fewer), s = 16 column blocks."""
+    import numpy as np
+    import torch
+
+    from paper_1703_06065_amd import Context
+    from paper_1703_06065_amd.binding import padded_empty, to_device
+    from workloads import gen
+
+    w = gen.plain_fp32(args.seed)
+    r = args.rows
+    kr = args.kr if args.kr > 0 else r
+    draws = gen.draws_u64(r + w.s, args.seed + 1)
+    A = to_device(w.A)
+    ctx = Context(0)
+    Ubuf = padded_empty(w.s * int(np.max(np.diff(w.offsets))), r)
+    for _ in range(args.warmup):
+        res = ctx.decompose_alg1(A, w.offsets, r, w.s, draws, kr=kr, U_out=Ubuf)
+    torch.cuda.synchronize()
+    # timed region: only the residual GEMM (stage fit_E) records HIP events
+    ctx.timing_enable(("fit_E",))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = ctx.decompose_alg1(A, w.offsets, r, w.s, draws, kr=kr, U_out=Ubuf)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = ctx.timing_read()
+    ctx.timing_enable(True)
+    nb = min(args.steps, 10)
+    for _ in range(nb):
+        ctx.decompose_alg1(A, w.offsets, r, w.s, draws, kr=kr, U_out=Ubuf)
+    torch.cuda.synchronize()
+    breakdown = ctx.timing_read()
+    ctx.timing_enable(False)
+    el = t1 - t0
+    c = int(res["c"])
+    # the residual GEMM A - (C U) R: 2 m r n FLOP per launch, one launch per step
+    per_launch_flop = 2.0 * w.m * r * w.n
+    avg_ms = stages["fit_E"][0] / max(stages["fit_E"][1], 1)
+    ach = per_launch_flop / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(ach / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
+            "kernel": "k_sgemm<128,128,16,2,2> residual epilogue (E = A - (C U) R)", "launches_per_step": 1,
+            "avg_ms": round(avg_ms, 5), "flop_per_launch": per_launch_flop,
+            "algorithmic_bytes_per_launch": 4.0 * (w.m * r + r * w.n + 2.0 * w.m * w.n)}
+    out = {
+        "metric": "block-CUR decompositions/s (Algorithm 1: uniform rows, U = W^+)",
+        "value": args.steps / el,
+        "unit": "decompositions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded numpy: rank-50 Haar signal sigma_i = 1/i + 1e-3 Gaussian noise)",
+        "config": {"workload": f"plain-fp32 {w.m}x{w.n}, {w.G} column blocks of 16, Algorithm 1 with r={r} "
+                               f"uniform rows, kr={kr}, s={w.s}", "m": w.m, "n": w.n, "G": w.G, "r": r, "kr": kr,
+                   "s": w.s, "c": c},
+        "tflops_total": round(alg1_flops(w.m, w.n, r, kr, c) * args.steps / el / 1e12, 3),
+        "stage_ms_per_step": {k: round(v[0] / nb, 5) for k, v in breakdown.items() if v[1]},
+        "err": res["err"], "rel_err": res["rel_err"], "rank_w": res["rank_w"], "sweeps": res["sweeps"],
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        from oracle import bcur_oracle as O
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+        except Exception:  # pragma: no cover
+            threads = os.cpu_count()
+        done, c0 = 0, time.perf_counter()
+        while True:
+            O.alg1(w.A, w.offsets, r, w.s, None, draws, kr=kr)
+            done += 1
+            ce = time.perf_counter() - c0
+            if ce > 20.0 or done >= 5:
+                break
+        out["cpu_baseline"] = {"value": done / ce, "unit": "decompositions/s", "cores": int(threads),
+                               "kind": "oracle",
+                               "sample": f"{done} whole Algorithm 1 decomposition(s) of the same workload by the "
+                                         f"FP64 oracle (numpy/LAPACK, {ce:.1f} s)"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,7 +251,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--mode", choices=["decompose", "serve"], default="decompose")
+    ap.add_argument("--mode", choices=["decompose", "serve", "alg1"], default="decompose")
+    ap.add_argument("--rows", type=int, default=128, help="Algorithm 1: rows drawn (r)")
+    ap.add_argument("--kr", type=int, default=0,
+                    help="Algorithm 1: right singular vectors of R behind the scores (0: r, as in the listing)")
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--pool", type=int, default=24)
     ap.add_argument("--slots", type=int, default=4)
@@ -163,6 +265,9 @@ def main():
         sys.exit(2)
     if args.mode == "serve":
         serve_bench(args)
+        return
+    if args.mode == "alg1":
+        alg1_bench(args)
         return
 
     import numpy as np

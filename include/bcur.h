@@ -65,7 +65,11 @@ enum {
     BCUR_FLAG_ILLCOND_C = 1u << 1,   /* estimated cond(C)^2 * 2^-24 > 0.1: U is inaccurate */
     BCUR_FLAG_ZERO_SCORE = 1u << 2,  /* a block of zero score was drawn (all remaining scores were 0) */
     BCUR_FLAG_RANKDEF_Y = 1u << 3,   /* a Gram matrix of the range finder needed a diagonal shift */
-    BCUR_FLAG_RANKDEF_R = 1u << 4    /* R R^T was numerically singular (row-block variant) */
+    BCUR_FLAG_RANKDEF_R = 1u << 4,   /* R R^T was numerically singular (row-block variant; Algorithm 1:
+                                        fewer than kr singular values of R above the cutoff) */
+    BCUR_FLAG_RANKDEF_W = 1u << 5,   /* Algorithm 1: singular values of W at or below the cutoff were dropped */
+    BCUR_FLAG_PINV_EIG = 1u << 6     /* Algorithm 1 (informational): W^+ came from the eigensystem of W's Gram
+                                        matrix, not from its certified Cholesky factor */
 };
 
 typedef struct bcur_ctx bcur_ctx;
@@ -206,7 +210,11 @@ enum {
     BCUR_STAGE_FIT_F = 14,    /* F = C^T E, main GEMM kernel */
     BCUR_STAGE_FIT_DU = 15,   /* U += X^T (X F) with <X^T X F, F> */
     BCUR_STAGE_RF_CAST = 16,  /* BF16 copies of A and of the sketch panels */
-    BCUR_NUM_STAGES = 17
+    BCUR_STAGE_A1_ROWS = 17,  /* Algorithm 1: uniform row draws, R = A[rows, :] and its transpose */
+    BCUR_STAGE_A1_SVDR = 18,  /* Algorithm 1: R R^T, its eigensolver, V_kr = R^T U_kr Sigma^-1 */
+    BCUR_STAGE_A1_PINV = 19,  /* Algorithm 1: W, its Gram matrix, eigensolver, W^+, scaled U */
+    BCUR_STAGE_A1_CU = 20,    /* Algorithm 1: P = C U (FP64 accumulation, rounded to FP32) */
+    BCUR_NUM_STAGES = 21
 };
 
 /* Stage timing: `on` = 0 turns it off; otherwise bit i of `on` times stage
@@ -270,6 +278,69 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
  * Host only, no device access. */
 bcur_status bcur_footprint(int64_t m, int64_t n, const int64_t* col_off, int64_t G, const int64_t* row_off,
                            int64_t Gr, const bcur_params* params, int32_t library_holds_u, size_t* bytes);
+
+/* ---- Algorithm 1: uniform rows, U = W^+ ------------------------------------
+ *
+ * The method as listed in Algorithm 1 of Sec. 3.1:
+ *   1. r rows of A drawn uniformly without replacement, R = S_R^T A with the
+ *      scaling sqrt(m / r) of the sampling matrix S_R;
+ *   2. block scores l_g(R, kr) = ||V_{R,kr}^T E_g||_F^2 (Def. 2 applied to R)
+ *      from the exact top-kr right singular vectors of R (for kr = r any
+ *      orthonormal basis of the row space of R: Cholesky QR of R^T in FP64;
+ *      for kr < r the eigensystem of R R^T in FP64); s column blocks drawn
+ *      with p_g = l_g / sum(l), C = A S with S scaled by 1/sqrt(s p_g) per
+ *      block;
+ *   3. W = R S (r x c), U = W^+ (Sec. 2.1), or U_k = (W_k)^+, the pseudoinverse
+ *      of the best rank-k approximation of W (the rank-k variant of Sec. 4.1),
+ *      and err = ||A - C U R||_F.
+ * Row draw t takes the x-th remaining row in ascending order with
+ * x = floor(draws[t] (m - t) / 2^64).  Column draws follow bcur_sample_blocks.
+ * W^+ treats singular values of W at or below max(r, c) 2^-24 sigma_1(W) as
+ * zero (W holds FP32 data).  It is formed from the Cholesky factor of W's
+ * smaller Gram matrix when the factor's inverse certifies that no singular
+ * value is near that cutoff, else from the Gram matrix's eigensystem.  A block drawn with zero weight (possible only
+ * when every remaining score is zero) enters S with scale 1.  Repeated
+ * column blocks (with replacement) are kept once, with their first weight. */
+
+typedef struct bcur_alg1_params {
+    int64_t r;          /* rows drawn, 1 <= r <= min(m, 128) */
+    int64_t kr;         /* right singular vectors of R behind the scores, 1 <= kr <= min(r, n) */
+    int64_t s;          /* column blocks to draw */
+    int64_t rank_k;     /* 0: U = W^+;  k >= 1: U_k = (W_k)^+ */
+    int32_t replace;    /* column draws: 0 without replacement, 1 independent */
+    int32_t pinv_eig;   /* 0: Cholesky route when certified (default); 1: always the eigensystem */
+} bcur_alg1_params;
+
+typedef struct bcur_alg1_result {
+    /* caller-provided buffers (capacities in parentheses) */
+    int64_t* rows;       /* host (r): sampled rows of A, draw order */
+    int64_t* idx;        /* host (s): chosen column blocks, selection order */
+    double* weights;     /* host (s) or NULL: 1/sqrt(s p) of each column draw */
+    double* scores;      /* host (G) or NULL: block scores l_g(R, kr) */
+    float* U;            /* device or NULL: c x r (ldu >= r, a multiple of 4, 16-byte aligned), the
+                            core for the UNSCALED factors: A ~ A[:, cols] U A[rows, :], i.e.
+                            sqrt(m / r) D W^+ with D the per-column scales of S */
+    int64_t ldu;
+    int64_t u_rows_cap;  /* rows U can hold (>= c) */
+    /* outputs */
+    int64_t c;           /* columns of C */
+    int64_t rank_w;      /* singular values of W kept in U */
+    double frob2;        /* ||A||_F^2 */
+    double err;          /* ||A - C U R||_F for the returned FP32 U */
+    double rel_err;      /* err / ||A||_F */
+    double min_margin;   /* smallest sampling margin over the column draws */
+    uint32_t flags;      /* BCUR_FLAG_* */
+    uint32_t sweeps;     /* Jacobi sweeps of the eigensolver of W's Gram matrix (0 on the Cholesky route) */
+} bcur_alg1_result;
+
+/* Algorithm 1 of Sec. 3.1 (with its rank-k variant of Sec. 4.1).
+ * A: device m x n (lda).  col_off: host G+1 column-block offsets.
+ * draws: host, r + s 64-bit words (row draws first).  Synchronous.
+ * BCUR_E_ARG for r, kr, s or rank_k out of range; BCUR_E_NONFINITE when A
+ * holds a NaN or an Inf. */
+bcur_status bcur_decompose_alg1(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda,
+                                const int64_t* col_off, int64_t G, const bcur_alg1_params* params,
+                                const uint64_t* draws, bcur_alg1_result* result);
 
 /* ---- serving: continuous batching of decompositions ------------------------
  *

@@ -42,7 +42,9 @@ design notes of the repository):
       max(r, c) 2^-24 sigma_1 as zero (W holds FP32 data);
   R14 (Sec. 4.1) U_k is read as (W_k)^+, the pseudoinverse of the best
       rank-k approximation of W: it keeps the k largest singular values of W
-      (the best rank-k approximation of W^+ itself would keep the smallest).
+      (the best rank-k approximation of W^+ itself would keep the smallest);
+  R15 (Alg. 1) a block drawn with zero weight (only when every remaining
+      score is zero) enters S with scale 1, since 1/sqrt(s p) is undefined.
 
 Parity unpinned: the (1+eps) relative-error guarantees (Thm. 2, the Remark
 of Sec. 3.3, Lemma 3 of App. A.1.1) carry unspecified constants; they are
@@ -435,17 +437,42 @@ def alg1_rows(m: int, r: int, draws: Sequence[int]) -> np.ndarray:
     return sample_blocks(np.ones(m), draws, r, replace=False)["idx"]
 
 
+def alg1_fit(A: np.ndarray, offsets: Sequence[int], rows: Sequence[int], idx: Sequence[int],
+             weights: Sequence[float], rank_k: int = 0) -> Dict[str, object]:
+    """Alg. 1 step 3 for given row and column draws: R = sqrt(m/r) A[rows],
+    C = A S with the first weight of each distinct block (R5, R15), W = R S,
+    U = W^+ (R13) or U_k = (W_k)^+ (R14), err = ||A - C U R||_F."""
+    A64 = np.asarray(A, dtype=np.float64)
+    m = A64.shape[0]
+    r = len(rows)
+    R = math.sqrt(m / r) * A64[np.asarray(rows, dtype=np.int64), :]
+    seen, keep_idx, keep_w = set(), [], []
+    for j, wgt in zip(idx, weights):
+        if int(j) not in seen:
+            seen.add(int(j))
+            keep_idx.append(int(j))
+            keep_w.append(float(wgt) if math.isfinite(wgt) else 1.0)
+    S = sampling_matrix(offsets, keep_idx, keep_w)
+    C = A64 @ S
+    Wmat = R @ S
+    U, rank_w = pinv_cut(Wmat, rank_k)
+    E = A64 - C @ U @ R
+    return dict(R=R, kept=keep_idx, kept_weights=keep_w, cols=selected_columns(offsets, keep_idx), C=C, W=Wmat,
+                U=U, rank_w=rank_w, err=float(math.sqrt(float(np.sum(E * E)))))
+
+
 def alg1(A: np.ndarray, offsets: Sequence[int], r: int, s: int, omega: Optional[np.ndarray],
          draws: Sequence[int], kr: Optional[int] = None, q: int = 1, replace: bool = False,
-         rank_k: int = 0, mode: str = "twin") -> Dict[str, object]:
+         rank_k: int = 0, mode: str = "exact") -> Dict[str, object]:
     """Algorithm 1 of Sec. 3.1 (Block CUR with uniform rows), steps in order.
 
     1. r rows drawn uniformly (draws[:r]; R11): R = S_R^T A = sqrt(m/r) A[rows].
     2. scores l_g(R, kr) = ||V_{R,kr}^T E_g||_F^2 (Def. 2 on R; R12) from the
-       float64 range finder on R with the test matrix omega (n x r, "twin") or
-       an exact SVD of R ("exact"); s blocks drawn from draws[r:r+s] with
-       p_g = l_g / kr; C = A S with S scaled by 1/sqrt(s p) (Sec. 3.1).
-    3. W = R S, U = W^+ (R13) or U_k = (W_k)^+ (R14), err = ||A - C U R||_F."""
+       SVD of the small matrix R ("exact", the step as the algorithm states it)
+       or from the float64 range finder on R with the test matrix omega
+       ("twin"); s blocks drawn from draws[r:r+s] with p_g = l_g / kr.
+    3. C = A S with S scaled by 1/sqrt(s p) (Sec. 3.1), W = R S, U = W^+ or
+       U_k = (W_k)^+, err = ||A - C U R||_F (alg1_fit)."""
     A64 = np.asarray(A, dtype=np.float64)
     m, n = A64.shape
     kr = r if kr is None else kr
@@ -460,22 +487,9 @@ def alg1(A: np.ndarray, offsets: Sequence[int], r: int, s: int, omega: Optional[
         raise ValueError(mode)
     scores = block_scores(Vr, offsets)
     samp = sample_blocks(scores, draws[r:r + s], s, replace)
-    idx, weights = samp["idx"], samp["weights"]
-    # duplicated blocks (with replacement) are kept once, with the first draw's weight (R5)
-    seen, keep_idx, keep_w = set(), [], []
-    for j, wgt in zip(idx, weights):
-        if int(j) not in seen:
-            seen.add(int(j))
-            keep_idx.append(int(j))
-            keep_w.append(float(wgt))
-    S = sampling_matrix(offsets, keep_idx, keep_w)
-    C = A64 @ S
-    Wmat = R @ S
-    U, rank_w = pinv_cut(Wmat, rank_k)
-    E = A64 - C @ U @ R
-    err = float(math.sqrt(float(np.sum(E * E))))
-    out.update(rows=rows, R=R, scores=scores, idx=idx, weights=weights, margins=samp["margins"],
-               kept=keep_idx, kept_weights=keep_w,
-               cols=selected_columns(offsets, keep_idx), C=C, W=Wmat, U=U, rank_w=rank_w, err=err,
-               rel_err=err / math.sqrt(out["frob2"]) if out["frob2"] > 0 else 0.0)
+    fit = alg1_fit(A64, offsets, rows, samp["idx"], samp["weights"], rank_k)
+    out.update(fit)
+    out.update(rows=rows, scores=scores, idx=samp["idx"], weights=samp["weights"], margins=samp["margins"],
+               sv_r=np.linalg.svd(A64[rows, :], compute_uv=False),
+               rel_err=fit["err"] / math.sqrt(out["frob2"]) if out["frob2"] > 0 else 0.0)
     return out

@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(HERE, "libbcur.so")
 
 OK, E_ARG, E_NONFINITE, E_NOMEM, E_HIP, E_RANKDEF, E_ADMIT, PENDING, E_STATE = range(9)
 PREC_FP32, PREC_BF16 = 0, 1
-FLAG_RANKDEF_C, FLAG_ILLCOND_C, FLAG_ZERO_SCORE, FLAG_RANKDEF_Y, FLAG_RANKDEF_R = 1, 2, 4, 8, 16
+FLAG_RANKDEF_C, FLAG_ILLCOND_C, FLAG_ZERO_SCORE, FLAG_RANKDEF_Y, FLAG_RANKDEF_R, FLAG_RANKDEF_W = 1, 2, 4, 8, 16, 32
+FLAG_PINV_EIG = 64
 
 # every symbol declared in include/bcur.h
 SYMBOLS = [
@@ -29,11 +30,12 @@ SYMBOLS = [
     "bcur_workspace_bytes", "bcur_frob2", "bcur_range_finder", "bcur_block_scores", "bcur_sample_blocks",
     "bcur_gather_columns", "bcur_fit_columns", "bcur_decompose", "bcur_timing_enable", "bcur_timing_read",
     "bcur_sketch_pass", "bcur_release_workspace", "bcur_footprint", "bcur_server_create", "bcur_server_destroy",
-    "bcur_server_submit", "bcur_server_poll", "bcur_server_wait", "bcur_server_stats",
+    "bcur_server_submit", "bcur_server_poll", "bcur_server_wait", "bcur_server_stats", "bcur_decompose_alg1",
 ]
 
 STAGES = ["frob", "rf_AQ", "rf_AtZ", "rf_reduce", "rf_orth", "rf_rr", "scores", "sample", "gather", "fit_H",
-          "fit_reduce", "fit_inv", "fit_U", "fit_E", "fit_F", "fit_dU", "rf_cast"]
+          "fit_reduce", "fit_inv", "fit_U", "fit_E", "fit_F", "fit_dU", "rf_cast", "a1_rows", "a1_svdr", "a1_pinv",
+          "a1_cu"]
 
 
 class BcurError(RuntimeError):
@@ -56,6 +58,20 @@ class Result(ctypes.Structure):
                 ("c", ctypes.c_int64), ("r", ctypes.c_int64), ("frob2", ctypes.c_double), ("err", ctypes.c_double),
                 ("rel_err", ctypes.c_double), ("min_margin", ctypes.c_double), ("flags", ctypes.c_uint32),
                 ("rr_sweeps", ctypes.c_uint32)]
+
+
+class Alg1Params(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_int64), ("kr", ctypes.c_int64), ("s", ctypes.c_int64), ("rank_k", ctypes.c_int64),
+                ("replace", ctypes.c_int32), ("pinv_eig", ctypes.c_int32)]
+
+
+class Alg1Result(ctypes.Structure):
+    _fields_ = [("rows", ctypes.POINTER(ctypes.c_int64)), ("idx", ctypes.POINTER(ctypes.c_int64)),
+                ("weights", ctypes.POINTER(ctypes.c_double)), ("scores", ctypes.POINTER(ctypes.c_double)),
+                ("U", ctypes.c_void_p), ("ldu", ctypes.c_int64),
+                ("u_rows_cap", ctypes.c_int64), ("c", ctypes.c_int64), ("rank_w", ctypes.c_int64),
+                ("frob2", ctypes.c_double), ("err", ctypes.c_double), ("rel_err", ctypes.c_double),
+                ("min_margin", ctypes.c_double), ("flags", ctypes.c_uint32), ("sweeps", ctypes.c_uint32)]
 
 
 class Request(ctypes.Structure):
@@ -112,6 +128,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "bcur_timing_read": (i32, [vp, P(dbl), P(i64)]),
         "bcur_decompose": (i32, [vp, vp, i64, i64, i64, P(i64), i64, P(i64), i64, P(Params), vp,
                                  P(ctypes.c_uint64), P(Result)]),
+        "bcur_decompose_alg1": (i32, [vp, vp, i64, i64, i64, P(i64), i64, P(Alg1Params), P(ctypes.c_uint64),
+                                      P(Alg1Result)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -335,6 +353,45 @@ class Context:
         if idx_r is not None:
             out["idx_r"] = idx_r[:s_r]
             out["row_scores"] = rsc
+        return out
+
+
+    def decompose_alg1(self, A, offsets, r: int, s: int, draws, kr: Optional[int] = None, rank_k: int = 0,
+                       replace: bool = False, want_u: bool = True, U_out=None, pinv_eig: bool = False):
+        """Algorithm 1 (uniform rows, U = W^+ or U_k = (W_k)^+).  draws: r row
+        words then s column words.  U is the c x r core for the unscaled
+        factors: A ~ A[:, cols] U A[rows, :]."""
+        p, m, n, lda = _check_dev(A, "A")
+        off = _i64(offsets)
+        G = len(off) - 1
+        kr = r if kr is None else kr
+        dr = np.ascontiguousarray(draws, dtype=np.uint64)
+        if dr.size < r + s:
+            raise ValueError("need r + s draws")
+        prm = Alg1Params(r=r, kr=kr, s=s, rank_k=rank_k, replace=int(replace), pinv_eig=int(pinv_eig))
+        rows = np.empty(r, dtype=np.int64)
+        idx = np.empty(s, dtype=np.int64)
+        w = np.empty(s)
+        sc = np.empty(G)
+        res = Alg1Result()
+        res.rows = _ptr(rows, ctypes.c_int64)
+        res.idx = _ptr(idx, ctypes.c_int64)
+        res.weights = _ptr(w, ctypes.c_double)
+        res.scores = _ptr(sc, ctypes.c_double)
+        U = None
+        if want_u:
+            cap = min(s * int(np.max(np.diff(off))), n)
+            U = U_out if U_out is not None else padded_empty(cap, r, A.device)
+            res.U = U.data_ptr()
+            res.ldu = U.stride(0)
+            res.u_rows_cap = U.shape[0]
+        self._chk(self.lib.bcur_decompose_alg1(self.h, p, m, n, lda, _ptr(off, ctypes.c_int64), G,
+                                               ctypes.byref(prm), _ptr(dr, ctypes.c_uint64), ctypes.byref(res)))
+        out = {"rows": rows, "idx": idx, "weights": w, "scores": sc, "c": res.c, "rank_w": res.rank_w,
+               "frob2": res.frob2, "err": res.err, "rel_err": res.rel_err, "min_margin": res.min_margin,
+               "flags": res.flags, "sweeps": res.sweeps}
+        if U is not None:
+            out["U"] = U[:res.c]
         return out
 
 

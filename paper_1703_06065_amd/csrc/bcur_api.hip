@@ -1204,4 +1204,271 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
     return BCUR_OK;
 }
 
+bcur_status bcur_decompose_alg1(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda,
+                                const int64_t* col_off, int64_t G, const bcur_alg1_params* p, const uint64_t* draws,
+                                bcur_alg1_result* res) {
+    if (!ctx) return BCUR_E_ARG;
+    if (!p || !res || !draws || !res->rows || !res->idx) return fail(ctx, BCUR_E_ARG, "null argument");
+    STCHK(check_matrix(ctx, A, m, n, lda, "A"));
+    STCHK(check_offsets(ctx, col_off, G, n, "col_off"));
+    const int64_t r = p->r, kr = p->kr, s = p->s, rank_k = p->rank_k;
+    if (r < 1 || r > std::min(m, kMaxSketch))
+        return fail(ctx, BCUR_E_ARG, "need 1 <= r <= min(m, %lld)", (long long)kMaxSketch);
+    if (kr < 1 || kr > std::min(r, n)) return fail(ctx, BCUR_E_ARG, "need 1 <= kr <= min(r, n)");
+    if (s < 1 || (!p->replace && s > G)) return fail(ctx, BCUR_E_ARG, "need 1 <= s <= G without replacement");
+    if (rank_k < 0) return fail(ctx, BCUR_E_ARG, "rank_k < 0");
+    if (p->replace < 0 || p->replace > 1 || p->pinv_eig < 0 || p->pinv_eig > 1)
+        return fail(ctx, BCUR_E_ARG, "replace and pinv_eig must be 0 or 1");
+    int64_t maxw = 0;
+    for (int64_t g = 0; g < G; ++g) maxw = std::max(maxw, col_off[g + 1] - col_off[g]);
+    const int64_t cmax = std::min(s * maxw, n);
+    if (res->U && (res->ldu < r || (res->ldu & 3) || !aligned16(res->U) || res->u_rows_cap < cmax))
+        return fail(ctx, BCUR_E_ARG, "U needs ldu >= %lld (a multiple of 4, 16-byte aligned) and %lld rows",
+                    (long long)r, (long long)cmax);
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    const int64_t rp = round4(r), np = round4(n), tmax = std::min(r, cmax);
+
+    // workspace: columns' sampler | first-sync results | R, R^T, its eigensystem | C, W, W^+ | residual
+    SampleBufs sc;
+    double *d_frob, *d_fpart, *lamR, *gpart, *TR, *WkR, *WksR, *dscale, *Wt, *Gw, *Rw, *lamW, *Vw, *Mw, *U64, *P64,
+        *wsE, *errv;
+    int64_t* d_rows;
+    uint64_t* d_rdr;
+    int *infoR, *infoW;
+    float *R0, *RT, *Q1, *Vk, *Cbuf, *Ubuf, *P32, *E;
+    const bool cholqr_scores = kr == r;
+    void *jwsR, *jwsW;
+    const int gw = gram_wgs(n);
+    const int64_t nwsE = ((m + 127) / 128) * ((n + 127) / 128);
+    auto layout = [&](Arena& a) {
+        d_rdr = a.take<uint64_t>(r);
+        sample_layout(a, sc, G, s, cmax);
+        // read back in one copy, from sc.idx to the end of infoR
+        d_frob = a.take<double>(2);
+        lamR = a.take<double>(r);
+        d_rows = a.take<int64_t>(r);
+        infoR = a.take<int>(4);
+        d_fpart = a.take<double>(frob2_grid(m, n));
+        R0 = a.take<float>(r * np);
+        RT = a.take<float>(n * rp);
+        gpart = a.take<double>((size_t)gw * r * r);
+        TR = a.take<double>(r * r);
+        WkR = a.take<double>(r * kr);
+        WksR = a.take<double>(r * kr);
+        jwsR = a.take<double>((jacobi_ws_bytes(r) + 7) / 8);
+        Q1 = cholqr_scores ? a.take<float>(n * rp) : nullptr;
+        Vk = a.take<float>(n * kr);
+        Cbuf = a.take<float>(m * round4(cmax));
+        dscale = a.take<double>(cmax);
+        Wt = a.take<double>(cmax * r);
+        Gw = a.take<double>(tmax * tmax);
+        Rw = a.take<double>(tmax * tmax);
+        Vw = a.take<double>(tmax * tmax);
+        Mw = a.take<double>(tmax * tmax);
+        jwsW = a.take<double>((jacobi_ws_bytes(tmax) + 7) / 8);
+        U64 = a.take<double>(cmax * r);
+        Ubuf = res->U ? nullptr : a.take<float>(cmax * rp);
+        P64 = a.take<double>(m * r);
+        P32 = a.take<float>(m * rp);
+        E = a.take<float>(m * np);
+        wsE = a.take<double>(nwsE);
+        // read back in one copy at the end
+        errv = a.take<double>(8);
+        lamW = a.take<double>(tmax);
+        infoW = a.take<int>(8);
+    };
+    {
+        Arena a;
+        layout(a);
+        STCHK(reserve(ctx, a.off));
+        Arena b{ctx->ws, 0};
+        layout(b);
+    }
+    const char* span1_0 = reinterpret_cast<const char*>(sc.idx);
+    const size_t span1 = (size_t)(reinterpret_cast<const char*>(infoR + 4) - span1_0);
+    const char* span2_0 = reinterpret_cast<const char*>(errv);
+    const size_t span2 = (size_t)(reinterpret_cast<const char*>(infoW + 8) - span2_0);
+    // pinned staging: offsets | draws | columns and their scales | the two read-back spans
+    const size_t pin_need = 8 * (G + 1) + 8 * (r + s) + 16 * cmax + span1 + span2 + 64;
+    STCHK(reserve_pinned(ctx, pin_need));
+    if (ctx->pinned_busy) HIPCHK(hipStreamSynchronize(st));
+    ctx->pinned_busy = true;
+    char* pin = ctx->pinned;
+    auto ptake = [&pin](size_t bytes) {
+        char* p0 = pin;
+        pin += (bytes + 7) & ~(size_t)7;
+        return p0;
+    };
+    int64_t* h_off = reinterpret_cast<int64_t*>(ptake(8 * (G + 1)));
+    uint64_t* h_dr = reinterpret_cast<uint64_t*>(ptake(8 * (r + s)));
+    int64_t* h_cols = reinterpret_cast<int64_t*>(ptake(8 * cmax));
+    double* h_scale = reinterpret_cast<double*>(ptake(8 * cmax));
+    char* h1 = ptake(span1);
+    char* h2 = ptake(span2);
+    auto mirror1 = [&](const void* dp) { return h1 + (reinterpret_cast<const char*>(dp) - span1_0); };
+    auto mirror2 = [&](const void* dp) { return h2 + (reinterpret_cast<const char*>(dp) - span2_0); };
+    memcpy(h_off, col_off, (G + 1) * sizeof(int64_t));
+    memcpy(h_dr, draws, (r + s) * sizeof(uint64_t));
+    HIPCHK(hipMemcpyAsync(sc.off, h_off, (G + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_rdr, h_dr, r * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(sc.dr, h_dr + r, s * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(sc.st, 0, 4 * sizeof(int), st));
+    HIPCHK(hipMemsetAsync(infoR, 0, 4 * sizeof(int), st));
+    HIPCHK(hipMemsetAsync(infoW, 0, 8 * sizeof(int), st));
+
+    // ||A||_F^2
+    {
+        StageScope ts(ctx, BCUR_STAGE_FROB);
+        HIPCHK(launch_frob2(A, m, n, lda, d_fpart, frob2_grid(m, n), d_frob, st));
+    }
+    // step 1: r uniform rows, R = A[rows, :] (the scaling sqrt(m/r) is applied in W and U)
+    {
+        StageScope ts(ctx, BCUR_STAGE_A1_ROWS);
+        HIPCHK(launch_uniform_rows(m, d_rdr, r, d_rows, st));
+        HIPCHK(launch_gather_rows(A, lda, n, d_rows, r, R0, np, st));
+        HIPCHK(launch_gather_rows_t(A, lda, n, d_rows, r, RT, rp, st));
+    }
+    // step 2: top-kr right singular vectors of R (a uniform row scale changes
+    // neither V nor the scores).  With kr = r they span the row space of R and
+    // any orthonormal basis of it gives the same scores: V = R^T L^-T from
+    // R R^T = L L^T, by Cholesky QR twice.  Otherwise from the eigensystem
+    // R R^T = U_R Lambda U_R^T: V_kr = R^T U_kr Lambda_kr^-1/2.
+    {
+        StageScope ts(ctx, BCUR_STAGE_A1_SVDR);
+        if (cholqr_scores) {
+            HIPCHK(launch_gram64(RT, n, r, rp, gpart, gw, st));
+            HIPCHK(launch_gram_reduce(gpart, gw, r, TR, st));
+            HIPCHK(launch_chol_rinv_small(TR, r, WkR, infoR + 2, st));
+            HIPCHK(launch_apply_small(RT, n, r, rp, WkR, r, r, Q1, rp, st));
+            HIPCHK(launch_gram64(Q1, n, r, rp, gpart, gw, st));
+            HIPCHK(launch_gram_reduce(gpart, gw, r, TR, st));
+            HIPCHK(launch_chol_rinv_small(TR, r, WksR, infoR + 3, st));
+            HIPCHK(launch_apply_small(Q1, n, r, rp, WksR, r, r, Vk, kr, st));
+        } else {
+            HIPCHK(launch_gram64(RT, n, r, rp, gpart, gw, st));
+            HIPCHK(launch_gram_reduce(gpart, gw, r, TR, st));
+            HIPCHK(launch_jacobi_eigh(TR, r, kr, lamR, WkR, WksR, jwsR, infoR, st));
+            HIPCHK(launch_apply_small(RT, n, r, rp, WksR, kr, kr, Vk, kr, st));
+        }
+    }
+    {
+        StageScope ts(ctx, BCUR_STAGE_SCORES);
+        HIPCHK(launch_block_scores(Vk, kr, kr, sc.off, G, sc.sc, st));
+    }
+    {
+        StageScope ts(ctx, BCUR_STAGE_SAMPLE);
+        HIPCHK(launch_sample(sc.sc, G, sc.dr, s, p->replace, sc.qb, sc.pr, sc.idx, sc.w, sc.mg, sc.st, st));
+    }
+    HIPCHK(hipMemcpyAsync(h1, span1_0, span1, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const int64_t* hidx = reinterpret_cast<const int64_t*>(mirror1(sc.idx));
+    const double* hw = reinterpret_cast<const double*>(mirror1(sc.w));
+    const double* hmg = reinterpret_cast<const double*>(mirror1(sc.mg));
+    const int* hst = reinterpret_cast<const int*>(mirror1(sc.st));
+    const double* hsc = reinterpret_cast<const double*>(mirror1(sc.sc));
+    const double* hfrob = reinterpret_cast<const double*>(mirror1(d_frob));
+    const double* hlamR = reinterpret_cast<const double*>(mirror1(lamR));
+    const int64_t* hrows = reinterpret_cast<const int64_t*>(mirror1(d_rows));
+    if (!isfinite(hfrob[0])) return fail(ctx, BCUR_E_NONFINITE, "A holds NaN or Inf");
+    if (hst[0] != 0) return fail(ctx, BCUR_E_HIP, "block scores are not finite");
+    for (int64_t t = 0; t < s; ++t)
+        if (hidx[t] < 0 || hidx[t] >= G) return fail(ctx, BCUR_E_HIP, "sampler returned an invalid block");
+    // columns of C and the scale of each (the first draw's weight of its block;
+    // scale 1 for a block drawn at zero weight)
+    int64_t c = 0;
+    for (int64_t t = 0; t < s; ++t) {
+        const int64_t j = hidx[t];
+        bool dup = false;
+        for (int64_t u = 0; u < t; ++u) dup |= hidx[u] == j;
+        if (dup) continue;
+        const double wj = isfinite(hw[t]) ? hw[t] : 1.0;
+        for (int64_t col = col_off[j]; col < col_off[j + 1]; ++col) {
+            h_cols[c] = col;
+            h_scale[c] = wj;
+            ++c;
+        }
+    }
+    HIPCHK(hipMemcpyAsync(sc.list, h_cols, c * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(dscale, h_scale, c * sizeof(double), hipMemcpyHostToDevice, st));
+    const int64_t ldc = round4(c), t_w = std::min(r, c);
+    const double alpha = sqrt((double)m / (double)r);
+    // C = A S unscaled
+    {
+        StageScope ts(ctx, BCUR_STAGE_GATHER);
+        HIPCHK(launch_gather_cols(A, lda, m, sc.list, c, Cbuf, ldc, st));
+    }
+    // step 3: W = alpha R S (held transposed, c x r), U = W^+ through the
+    // pseudoinverse M of the smaller Gram matrix G, then the core for the
+    // unscaled factors alpha D U.  M = G^-1 from a Cholesky factor when its
+    // inverse certifies that no singular value of W is near the cutoff and no
+    // truncation is asked for; otherwise (decided on the device) M from the
+    // eigensystem of G with the cutoff and the rank-k truncation.
+    // infoW: [0..1] eigensolver, [2] Cholesky, [3] 1 = eigensystem used, [4..5] kept counts
+    float* U = res->U ? res->U : Ubuf;
+    const int64_t ldu = res->U ? res->ldu : rp;
+    {
+        StageScope ts(ctx, BCUR_STAGE_A1_PINV);
+        HIPCHK(launch_alg1_w(RT, rp, r, sc.list, dscale, c, alpha, Wt, st));
+        if (c <= r)   // W^T W = Wt Wt^T,  W^+ = (W^T W)^+ W^T
+            HIPCHK(launch_dgemm(c, c, r, 1.0, Wt, r, false, Wt, r, true, 0.0, Gw, t_w, st));
+        else          // W W^T = Wt^T Wt,  W^+ = W^T (W W^T)^+
+            HIPCHK(launch_dgemm(r, r, c, 1.0, Wt, r, true, Wt, r, false, 0.0, Gw, t_w, st));
+        const double cut = ldexp((double)std::max(r, c), -24);
+        const int force_eig = p->pinv_eig || (rank_k > 0 && rank_k < t_w);
+        HIPCHK(launch_chol_rinv_small(Gw, t_w, Rw, infoW + 2, st));
+        HIPCHK(launch_pinv_certify(Gw, Rw, t_w, infoW + 2, cut * cut, force_eig, infoW + 3, infoW + 4, st));
+        HIPCHK(launch_gram_inv_rinv(Rw, t_w, Mw, infoW + 3, st));
+        HIPCHK(launch_jacobi_eigh(Gw, t_w, t_w, lamW, Vw, nullptr, jwsW, infoW, st, infoW + 3));
+        HIPCHK(launch_pinv_eig(lamW, Vw, t_w, cut * cut, rank_k, Mw, infoW + 4, infoW + 3, st));
+        if (c <= r)
+            HIPCHK(launch_dgemm(c, r, c, 1.0, Mw, t_w, false, Wt, r, false, 0.0, U64, r, st));
+        else
+            HIPCHK(launch_dgemm(c, r, r, 1.0, Wt, r, false, Mw, t_w, false, 0.0, U64, r, st));
+        HIPCHK(launch_scale_rows_f32(U64, c, r, dscale, alpha, U, ldu, st));
+    }
+    // err = ||A - (C U) R||_F for the FP32 U: C U with FP64 accumulation, rounded
+    // to FP32, then the residual GEMM with its fused squared norm
+    {
+        StageScope ts(ctx, BCUR_STAGE_A1_CU);
+        HIPCHK(launch_dgemm_ff(m, r, c, 1.0, Cbuf, ldc, false, U, ldu, false, 0.0, P64, r, st));
+        HIPCHK(launch_f64_to_f32_2d(P64, m, r, r, P32, rp, st));
+    }
+    const GemmPlan pe = plan_sgemm(m, n, r, false, false);
+    STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_E, BCUR_STAGE_FIT_REDUCE, pe, m, n, r, false, P32, rp, R0, np, E, np, nullptr,
+                     EPI_RESID, A, lda, nullptr, 0, wsE));
+    HIPCHK(launch_fit_err(wsE, nwsE, wsE, 0, errv, st));
+    HIPCHK(hipMemcpyAsync(h2, span2_0, span2, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    ctx->pinned_busy = false;
+    const double* herr = reinterpret_cast<const double*>(mirror2(errv));
+    const int* hinfoW = reinterpret_cast<const int*>(mirror2(infoW));
+    uint32_t fl = 0;
+    if (hst[1]) fl |= BCUR_FLAG_ZERO_SCORE;
+    if (hinfoW[4] < t_w) fl |= BCUR_FLAG_RANKDEF_W;
+    if (hinfoW[3]) fl |= BCUR_FLAG_PINV_EIG;
+    const int* hinfoR = reinterpret_cast<const int*>(mirror1(infoR));
+    if (cholqr_scores) {
+        if ((hinfoR[2] | hinfoR[3]) & 1) fl |= BCUR_FLAG_RANKDEF_R;
+    } else {
+        const double cutR = ldexp((double)std::max(r, n), -24);
+        if (!(hlamR[kr - 1] > cutR * cutR * hlamR[0])) fl |= BCUR_FLAG_RANKDEF_R;
+    }
+    memcpy(res->rows, hrows, r * sizeof(int64_t));
+    memcpy(res->idx, hidx, s * sizeof(int64_t));
+    if (res->weights) memcpy(res->weights, hw, s * sizeof(double));
+    if (res->scores) memcpy(res->scores, hsc, G * sizeof(double));
+    double mm = INFINITY;
+    for (int64_t t = 0; t < s; ++t) mm = std::min(mm, hmg[t]);
+    res->c = c;
+    res->rank_w = hinfoW[5];
+    res->frob2 = hfrob[0];
+    res->err = sqrt(std::max(herr[0], 0.0));
+    res->rel_err = hfrob[0] > 0.0 ? res->err / sqrt(hfrob[0]) : 0.0;
+    res->min_margin = mm;
+    res->flags = fl;
+    res->sweeps = (uint32_t)hinfoW[0];
+    return BCUR_OK;
+}
+
 }  // extern "C"

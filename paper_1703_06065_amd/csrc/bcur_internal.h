@@ -96,8 +96,9 @@ hipError_t launch_apply_small(const float* X, int64_t rows, int64_t li, int64_t 
 // lam (l, descending), Wk (l x k, FP64), Wks = Wk diag(1/sqrt(lam)) (l x k) or null;
 // info[0] = sweeps, info[1] = 1 when converged.  ws: jacobi_ws_bytes(l) bytes.
 size_t jacobi_ws_bytes(int64_t l);
+// With gate non-null both kernels return at once when *gate == 0 (nothing is written).
 hipError_t launch_jacobi_eigh(const double* T, int64_t l, int64_t k, double* lam, double* Wk, double* Wks, void* ws,
-                              int* info, hipStream_t st);
+                              int* info, hipStream_t st, const int* gate = nullptr);
 
 // ---- blocked FP64 Cholesky inverse (k_dense64.hip) -------------------------
 size_t spd_inverse_ws_doubles(int64_t c);
@@ -125,5 +126,29 @@ hipError_t launch_dgemm_fd(int64_t M, int64_t N, int64_t K, double alpha, const 
                            hipStream_t st);
 hipError_t launch_dgemm_df(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda, bool tA,
                            const float* B, int64_t ldb, bool tB, double beta, double* D, int64_t ldd, hipStream_t st);
+
+// ---- Algorithm 1 (k_alg1.hip) ------------------------------------------------
+// rows[t] (t < r <= min(m, 128)): the x-th row not yet taken, x = floor(draws[t] (m - t) / 2^64)
+hipError_t launch_uniform_rows(int64_t m, const uint64_t* draws, int64_t r, int64_t* rows, hipStream_t st);
+// RT (n x ldrt) = A[rows, :]^T, columns r .. ldrt-1 zero
+hipError_t launch_gather_rows_t(const float* A, int64_t lda, int64_t n, const int64_t* d_rows, int64_t r, float* RT,
+                                int64_t ldrt, hipStream_t st);
+// Wt (c x r, FP64, ld r): Wt[t][i] = alpha d_scale[t] RT[d_cols[t]][i]
+hipError_t launch_alg1_w(const float* RT, int64_t ldrt, int64_t r, const int64_t* d_cols, const double* d_scale,
+                         int64_t c, double alpha, double* Wt, hipStream_t st);
+// M (t x t) = V diag(1/lam over the kept prefix) V^T (lam descending, V t x t with eigenvectors in
+// columns); kept = #{lam_j > cut lam_0}, capped at rank_k when rank_k > 0; cnt = {above cut, kept}.
+// Skipped when gate is non-null and *gate == 0.
+hipError_t launch_pinv_eig(const double* lam, const double* V, int64_t t, double cut, int64_t rank_k, double* M,
+                           int* cnt, const int* gate, hipStream_t st);
+// *use_eig = 0 (and cnt = {t, t}) when G's Cholesky inverse factor Rinv certifies that no eigenvalue
+// of G is at or below cut2 lam_max and force_eig is 0; else *use_eig = 1
+hipError_t launch_pinv_certify(const double* G, const double* Rinv, int64_t t, const int* chol_info, double cut2,
+                               int force_eig, int* use_eig, int* cnt, hipStream_t st);
+// M = Rinv Rinv^T (t x t), skipped when *use_eig != 0
+hipError_t launch_gram_inv_rinv(const double* Rinv, int64_t t, double* M, const int* use_eig, hipStream_t st);
+// U (c x r, FP32, ldu) = alpha diag(d_scale) U64 (c x r, FP64, ld r)
+hipError_t launch_scale_rows_f32(const double* U64, int64_t c, int64_t r, const double* d_scale, double alpha,
+                                 float* U, int64_t ldu, hipStream_t st);
 
 }  // namespace bcur

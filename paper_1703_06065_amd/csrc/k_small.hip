@@ -319,7 +319,8 @@ __device__ __forceinline__ bool other_block(int e, int H, int& u, int& v) {
 template <int KL, int NT, int NB>
 __global__ __launch_bounds__(NT) void k_jacobi_rr(const double* __restrict__ Tin, int l,
                                                   double* __restrict__ lam_out, double2* __restrict__ rot,
-                                                  int* __restrict__ meta, int* __restrict__ info) {
+                                                  int* __restrict__ meta, int* __restrict__ info,
+                                                  const int* __restrict__ gate) {
     using St = JStore<KL>;
     static_assert((KL / 2) * (KL / 2 - 3) / 2 <= (NT - 64) * NB, "too few block slots");
     __shared__ __attribute__((aligned(16))) double Tb[2][St::kSize];
@@ -327,6 +328,7 @@ __global__ __launch_bounds__(NT) void k_jacobi_rr(const double* __restrict__ Tin
     __shared__ double sred[NT / 64];
     __shared__ int stop[2];
     __shared__ int posof[KL];
+    if (gate && *gate == 0) return;
     const int tid = threadIdx.x;
     const int L = l + (l & 1), H = L / 2;
     const int Rmax = kJSweeps * (L - 1);
@@ -556,9 +558,11 @@ __global__ __launch_bounds__(NT) void k_jacobi_rr(const double* __restrict__ Tin
 template <int KL>
 __global__ __launch_bounds__(64) void k_jacobi_vectors(const double2* __restrict__ rot, const int* __restrict__ meta,
                                                        const double* __restrict__ lam, int l, int k,
-                                                       double* __restrict__ Wk, double* __restrict__ Wks) {
+                                                       double* __restrict__ Wk, double* __restrict__ Wks,
+                                                       const int* __restrict__ gate) {
     constexpr int HW = KL / 2, RPW = 64 / HW, CH = 16;
     __shared__ double row[RPW][KL];
+    if (gate && *gate == 0) return;
     const int lane = threadIdx.x, t = lane % HW, half = lane / HW;
     const int i = RPW * blockIdx.x + half;
     const int L = l + (l & 1), H = L / 2;
@@ -662,20 +666,22 @@ size_t jacobi_ws_bytes(int64_t l) {
 }
 
 hipError_t launch_jacobi_eigh(const double* T, int64_t l, int64_t k, double* lam, double* Wk, double* Wks, void* ws,
-                              int* info, hipStream_t st) {
+                              int* info, hipStream_t st, const int* gate) {
     if (l < 1 || l > kMaxL || k < 1 || k > l) return hipErrorInvalidValue;
     const int L = (int)l + ((int)l & 1);
     const int64_t H = L / 2;
     double2* rot = reinterpret_cast<double2*>(ws);
     int* meta = reinterpret_cast<int*>(rot + (int64_t)kJSweeps * (L - 1) * H);
     if (L <= 64) {
-        hipLaunchKernelGGL((k_jacobi_rr<64, 512, 2>), dim3(1), dim3(512), 0, st, T, (int)l, lam, rot, meta, info);
+        hipLaunchKernelGGL((k_jacobi_rr<64, 512, 2>), dim3(1), dim3(512), 0, st, T, (int)l, lam, rot, meta, info,
+                           gate);
         hipLaunchKernelGGL(k_jacobi_vectors<64>, dim3((unsigned)((l + 1) / 2)), dim3(64), 0, st,
-                           (const double2*)rot, (const int*)meta, (const double*)lam, (int)l, (int)k, Wk, Wks);
+                           (const double2*)rot, (const int*)meta, (const double*)lam, (int)l, (int)k, Wk, Wks, gate);
     } else {
-        hipLaunchKernelGGL((k_jacobi_rr<128, 1024, 3>), dim3(1), dim3(1024), 0, st, T, (int)l, lam, rot, meta, info);
+        hipLaunchKernelGGL((k_jacobi_rr<128, 1024, 3>), dim3(1), dim3(1024), 0, st, T, (int)l, lam, rot, meta, info,
+                           gate);
         hipLaunchKernelGGL(k_jacobi_vectors<128>, dim3((unsigned)l), dim3(64), 0, st, (const double2*)rot,
-                           (const int*)meta, (const double*)lam, (int)l, (int)k, Wk, Wks);
+                           (const int*)meta, (const double*)lam, (int)l, (int)k, Wk, Wks, gate);
     }
     return hipGetLastError();
 }

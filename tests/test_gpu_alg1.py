@@ -1,0 +1,234 @@
+"""Parity of Algorithm 1 (Sec. 3.1; rank-k variant of Sec. 4.1) on the GPU,
+through the C ABI, with the FP64 oracle.
+
+Tolerances:
+  * row draws, column blocks: integer results, bit-exact (the column draws
+    whenever the oracle's smallest margin exceeds 2 G max_g tol_g).
+  * scores: for kr < r the GPU takes the SVD of R from the FP64 eigensystem
+    of R R^T (FP32 data, exact products), for kr = r an orthonormal basis of
+    the row space of R by Cholesky QR twice; V is rounded to FP32, so
+    |l_g(GPU) - l_g| <= tau max(l_g, kr/G), tau = max(1e-5, 64 u64 kappa_R),
+    kappa_R = sigma_1^2 / (sigma_kr^2 - sigma_kr+1^2).
+  * U: W^+ through the inverse of W's Gram matrix in FP64 (its Cholesky
+    factor when certified, else its eigensystem) loses about u64 cond(W)^2,
+    then U is stored in FP32:
+    ||U - U_oracle||_F <= (4 u32 + 1e3 u64 cond_kept(W)^2) ||U_oracle||_F.
+    The route taken is checked through the PINV_EIG flag.
+  * err is the residual of the returned FP32 U: it is compared with the
+    oracle's residual of that same U (FP64 products), 1e-5 relative with a
+    floor of 16 u32 ||A||_F, and the oracle's own err is reported beside it.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import bcur_oracle as O
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+U64 = 2.0 ** -52
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1703_06065_amd import Context
+    return Context(0)
+
+
+def dev(a):
+    from paper_1703_06065_amd.binding import to_device
+    return to_device(a)
+
+
+def note(*a):
+    print(*a, flush=True)
+
+
+def err_tol(err_ref, frob2):
+    return 1e-5 * err_ref + 16 * U32 * math.sqrt(frob2)
+
+
+def unscaled_core(A, ref):
+    """The oracle's U for the unscaled factors A[:, cols] and A[rows, :]:
+    sqrt(m / r) D W^+ with D the per-column scales of S."""
+    m = A.shape[0]
+    r = len(ref["rows"])
+    scales = []
+    off = ref["offsets"]
+    for j, w_ in zip(ref["kept"], ref["kept_weights"]):
+        scales.extend([w_] * int(off[j + 1] - off[j]))
+    return math.sqrt(m / r) * np.asarray(scales)[:, None] * ref["U"]
+
+
+def own_err(A, cols, rows, U):
+    A64 = A.astype(np.float64)
+    E = A64 - A64[:, cols] @ U.astype(np.float64) @ A64[rows, :]
+    return float(math.sqrt(np.sum(E * E)))
+
+
+def check_alg1(ctx, A, off, r, s, draws, kr=None, rank_k=0, replace=False, label="", route=None, pinv_eig=False):
+    m, n = A.shape
+    G = len(off) - 1
+    kr = r if kr is None else kr
+    note(f"alg1 {label} m={m} n={n} G={G} r={r} kr={kr} s={s} rank_k={rank_k} replace={replace}")
+    res = ctx.decompose_alg1(dev(A), off, r, s, draws, kr=kr, rank_k=rank_k, replace=replace, pinv_eig=pinv_eig)
+    ref = O.alg1(A, off, r, s, None, draws, kr=kr, rank_k=rank_k, replace=replace)
+    ref["offsets"] = off
+    # 1. row draws: bit-exact
+    assert np.array_equal(res["rows"], ref["rows"]), (res["rows"], ref["rows"])
+    assert abs(res["frob2"] - ref["frob2"]) <= 1e-12 * ref["frob2"]
+    sv = ref["sv_r"]
+    # 2. scores
+    lam = np.concatenate([sv ** 2, [0.0]])
+    gap = lam[kr - 1] - lam[kr]
+    kappa = lam[0] / gap if gap > 0 else math.inf
+    tau = max(1e-5, 64 * U64 * min(kappa, 1e30))
+    tol = tau * np.maximum(ref["scores"], kr / G)
+    dl = np.abs(res["scores"] - ref["scores"])
+    note(f"  kappa_R={kappa:.3g} tau={tau:.2e} max|dl|/tol={np.max(dl / tol):.3f} margin={ref['margins'].min():.3e}")
+    assert np.all(dl <= tol)
+    need = 2 * G * tol.max()
+    same = np.array_equal(res["idx"], ref["idx"])
+    note(f"  idx gpu={list(res['idx'])} oracle={list(ref['idx'])} need margin>{need:.2e}")
+    if ref["margins"].min() > need:
+        assert same
+    if not same:
+        # a different but valid selection: the oracle's fit of the GPU's draws
+        ref.update(O.alg1_fit(A, off, res["rows"], res["idx"], res["weights"], rank_k))
+    cols = ref["cols"]
+    assert res["c"] == len(cols)
+    # 3. U and the rank kept
+    assert res["rank_w"] == ref["rank_w"]
+    Ug = res["U"][: res["c"], :r].cpu().numpy().astype(np.float64)
+    Uo = unscaled_core(A, ref)
+    svw = np.linalg.svd(ref["W"], compute_uv=False)
+    kk = ref["rank_w"]
+    cond = svw[0] / svw[kk - 1] if kk > 0 else 1.0
+    rel_u = np.linalg.norm(Ug - Uo) / max(np.linalg.norm(Uo), 1e-300)
+    tol_u = 4 * U32 + 1e3 * U64 * cond ** 2
+    e_own = own_err(A, cols, res["rows"], Ug)
+    note(f"  c={res['c']} rank_w={res['rank_w']} cond_kept(W)={cond:.3g} rel_u={rel_u:.2e} tol_u={tol_u:.2e} "
+         f"err={res['err']:.9g} own={e_own:.9g} oracle={ref['err']:.9g} flags={res['flags']} sweeps={res['sweeps']}")
+    assert rel_u <= tol_u
+    from paper_1703_06065_amd import binding
+    if route is not None:
+        assert bool(res["flags"] & binding.FLAG_PINV_EIG) == (route == "eig"), res["flags"]
+    assert abs(res["err"] - e_own) <= err_tol(e_own, ref["frob2"])
+    # the FP32 core moves the residual by at most u32 ||C||_F ||U||_F ||R||_F
+    C = A.astype(np.float64)[:, cols]
+    R = A.astype(np.float64)[res["rows"], :]
+    quant = 4 * U32 * np.linalg.norm(C) * np.linalg.norm(Uo) * np.linalg.norm(R)
+    assert abs(res["err"] - ref["err"]) <= err_tol(ref["err"], ref["frob2"]) + quant
+    from paper_1703_06065_amd import binding
+    assert bool(res["flags"] & binding.FLAG_RANKDEF_W) == (ref["rank_w"] < min(r, len(cols)) and
+                                                           (rank_k == 0 or ref["rank_w"] < min(rank_k, r, len(cols))))
+    return res, ref
+
+
+def lowrank(m, n, rank, noise, seed):
+    return gen.lowrank_haar(m, n, 1.0 / np.arange(1, rank + 1), noise, seed)
+
+
+@pytest.mark.parametrize("m,n,b,r,kr,s,ragged,seed", [
+    (512, 256, 8, 40, 10, 4, False, 0),     # c = 32 <= r: Gram W^T W
+    (300, 200, 10, 20, 20, 5, False, 1),    # c = 50 > r: Gram W W^T
+    (1000, 700, 7, 128, 50, 30, True, 2),   # r at its maximum, ragged blocks
+    (97, 61, 3, 1, 1, 2, False, 3),         # one row
+    (100, 90, 9, 100, 30, 4, False, 4),     # every row drawn
+    (640, 333, 16, 64, 64, 9, True, 5),     # kr = r, c > r
+    (257, 129, 1, 33, 12, 33, False, 6),    # one-column blocks, c = r
+])
+def test_alg1_shapes(ctx, m, n, b, r, kr, s, ragged, seed):
+    A = lowrank(m, n, min(40, m, n), 1e-3, seed)
+    off = gen.ragged_blocks(n, -(-n // b), seed) if ragged else gen.contiguous_blocks(n, b)
+    dr = gen.draws_u64(r + s, seed)
+    a, _ = check_alg1(ctx, A, off, r, s, dr, kr=kr, label="shape", route="chol")
+    # the same draws with W^+ from the eigensystem: the same selection and core
+    b_, _ = check_alg1(ctx, A, off, r, s, dr, kr=kr, label="shape (eigensystem)", route="eig", pinv_eig=True)
+    assert np.array_equal(a["idx"], b_["idx"]) and a["rank_w"] == b_["rank_w"]
+
+
+@pytest.mark.parametrize("pinv_eig", [False, True])
+def test_alg1_illconditioned_w_full_rank(ctx, pinv_eig):
+    # sigma_i = 10^(-i/8) without noise: W (40 x 32) is full rank with
+    # cond(W) ~ 8e4, well above the cutoff, so both routes keep all of it
+    sig = 10.0 ** (-np.arange(40) / 8.0)
+    A = gen.lowrank_haar(500, 320, sig, 0.0, 17)
+    off = gen.contiguous_blocks(320, 8)
+    res, ref = check_alg1(ctx, A, off, 40, 4, gen.draws_u64(44, 17), kr=40, label="ill-conditioned W",
+                          route="eig" if pinv_eig else "chol", pinv_eig=pinv_eig)
+    assert res["rank_w"] == 32
+
+
+@pytest.mark.parametrize("rank_k", [1, 5, 17])
+def test_alg1_rank_k(ctx, rank_k):
+    A = lowrank(600, 320, 30, 1e-3, 11)
+    off = gen.contiguous_blocks(320, 8)
+    res, ref = check_alg1(ctx, A, off, 48, 6, gen.draws_u64(54, 11), kr=20, rank_k=rank_k, label="U_k",
+                          route="eig")
+    Ug = res["U"][: res["c"]].cpu().numpy().astype(np.float64)
+    assert np.linalg.matrix_rank(Ug, tol=1e-4 * np.linalg.norm(Ug, 2)) == rank_k
+
+
+def test_alg1_rank_deficient_w(ctx):
+    # rank-6 data: W (20 x 40) has 6 singular values above the cutoff
+    A = gen.gaussian_product(400, 240, 6, 12, dtype=np.float32)
+    off = gen.contiguous_blocks(240, 8)
+    res, ref = check_alg1(ctx, A, off, 20, 5, gen.draws_u64(25, 12), kr=6, label="rank-deficient W",
+                          route="eig")
+    from paper_1703_06065_amd import binding
+    assert res["rank_w"] == 6 and res["flags"] & binding.FLAG_RANKDEF_W
+    assert res["rel_err"] <= 1e-5
+
+
+def test_alg1_with_replacement(ctx):
+    A = lowrank(400, 96, 20, 1e-3, 13)
+    off = gen.contiguous_blocks(96, 8)   # 12 blocks, 20 draws: repeats are certain
+    res, ref = check_alg1(ctx, A, off, 32, 20, gen.draws_u64(52, 13), kr=10, replace=True, label="replace")
+    assert len(set(res["idx"].tolist())) < 20
+
+
+def test_alg1_row_draw_edges(ctx):
+    # draw 0 takes the first free row, 2^64 - 1 the last
+    A = lowrank(130, 64, 10, 1e-3, 14)
+    off = gen.contiguous_blocks(64, 8)
+    dr = np.array([0, 2 ** 64 - 1] * 64 + list(gen.draws_u64(3, 14)), dtype=np.uint64)
+    res, ref = check_alg1(ctx, A, off, 128, 3, dr, kr=10, label="row edges")
+    assert list(res["rows"][:4]) == [0, 129, 1, 128]
+
+
+def test_alg1_deterministic(ctx):
+    A = lowrank(512, 256, 20, 1e-3, 15)
+    off = gen.contiguous_blocks(256, 8)
+    dr = gen.draws_u64(44, 15)
+    a = ctx.decompose_alg1(dev(A), off, 40, 4, dr, kr=10)
+    b = ctx.decompose_alg1(dev(A), off, 40, 4, dr, kr=10)
+    assert a["err"] == b["err"] and np.array_equal(a["idx"], b["idx"])
+    assert torch.equal(a["U"], b["U"])
+
+
+def test_alg1_errors(ctx):
+    from paper_1703_06065_amd import binding
+    A = lowrank(200, 100, 10, 1e-3, 16)
+    off = gen.contiguous_blocks(100, 10)
+    dA = dev(A)
+    dr = gen.draws_u64(300, 16)
+    for kw in [dict(r=129, s=2), dict(r=0, s=2), dict(r=10, s=2, kr=11), dict(r=10, s=11), dict(r=10, s=2, rank_k=-1)]:
+        with pytest.raises(binding.BcurError) as e:
+            ctx.decompose_alg1(dA, off, kw.pop("r"), kw.pop("s"), dr, **kw)
+        assert e.value.status == binding.E_ARG
+    Abad = A.copy()
+    Abad[3, 4] = np.nan
+    with pytest.raises(binding.BcurError) as e:
+        ctx.decompose_alg1(dev(Abad), off, 10, 2, dr)
+    assert e.value.status == binding.E_NONFINITE
+
+
+def test_alg1_plain_fp32_full_size(ctx):
+    """The 8192 x 4096 workload (256 blocks of 16), r = 128 rows, kr = 50, s = 16."""
+    w = gen.plain_fp32(0)
+    check_alg1(ctx, w.A, w.offsets, 128, w.s, gen.draws_u64(128 + w.s, 1), kr=w.k, label="plain-fp32 full size")
