@@ -1231,13 +1231,14 @@ bcur_status bcur_decompose_alg1(bcur_ctx* ctx, const float* A, int64_t m, int64_
 
     // workspace: columns' sampler | first-sync results | R, R^T, its eigensystem | C, W, W^+ | residual
     SampleBufs sc;
-    double *d_frob, *d_fpart, *lamR, *gpart, *TR, *WkR, *WksR, *dscale, *Wt, *Gw, *Rw, *lamW, *Vw, *Mw, *U64, *P64,
+    double *d_frob, *d_fpart, *lamR, *gpart, *TR, *WkR, *WksR, *dscale, *Wx, *gpartW, *Gw, *Rw, *lamW, *Vw, *Mw, *P64,
         *wsE, *errv;
     int64_t* d_rows;
     uint64_t* d_rdr;
     int *infoR, *infoW;
-    float *R0, *RT, *Q1, *Vk, *Cbuf, *Ubuf, *P32, *E;
-    const bool cholqr_scores = kr == r;
+    float *R0, *RT, *Vk, *Cbuf, *Ubuf, *P32;
+    const bool chol_scores = kr == r;
+    const int gwW = gram_wgs(std::max(r, cmax));
     void *jwsR, *jwsW;
     const int gw = gram_wgs(n);
     const int64_t nwsE = ((m + 127) / 128) * ((n + 127) / 128);
@@ -1257,21 +1258,19 @@ bcur_status bcur_decompose_alg1(bcur_ctx* ctx, const float* A, int64_t m, int64_
         WkR = a.take<double>(r * kr);
         WksR = a.take<double>(r * kr);
         jwsR = a.take<double>((jacobi_ws_bytes(r) + 7) / 8);
-        Q1 = cholqr_scores ? a.take<float>(n * rp) : nullptr;
         Vk = a.take<float>(n * kr);
         Cbuf = a.take<float>(m * round4(cmax));
         dscale = a.take<double>(cmax);
-        Wt = a.take<double>(cmax * r);
+        Wx = a.take<double>(cmax * r);
+        gpartW = a.take<double>((size_t)gwW * tmax * tmax);
         Gw = a.take<double>(tmax * tmax);
         Rw = a.take<double>(tmax * tmax);
         Vw = a.take<double>(tmax * tmax);
         Mw = a.take<double>(tmax * tmax);
         jwsW = a.take<double>((jacobi_ws_bytes(tmax) + 7) / 8);
-        U64 = a.take<double>(cmax * r);
         Ubuf = res->U ? nullptr : a.take<float>(cmax * rp);
         P64 = a.take<double>(m * r);
         P32 = a.take<float>(m * rp);
-        E = a.take<float>(m * np);
         wsE = a.take<double>(nwsE);
         // read back in one copy at the end
         errv = a.take<double>(8);
@@ -1331,20 +1330,17 @@ bcur_status bcur_decompose_alg1(bcur_ctx* ctx, const float* A, int64_t m, int64_
     }
     // step 2: top-kr right singular vectors of R (a uniform row scale changes
     // neither V nor the scores).  With kr = r they span the row space of R and
-    // any orthonormal basis of it gives the same scores: V = R^T L^-T from
-    // R R^T = L L^T, by Cholesky QR twice.  Otherwise from the eigensystem
+    // any orthonormal basis of it gives the same scores: V = R^T L^-T from the
+    // FP64 factor R R^T = L L^T (orthonormal up to about u64 cond(R)^2, the
+    // accuracy of the scores themselves).  Otherwise from the eigensystem
     // R R^T = U_R Lambda U_R^T: V_kr = R^T U_kr Lambda_kr^-1/2.
     {
         StageScope ts(ctx, BCUR_STAGE_A1_SVDR);
-        if (cholqr_scores) {
+        if (chol_scores) {
             HIPCHK(launch_gram64(RT, n, r, rp, gpart, gw, st));
             HIPCHK(launch_gram_reduce(gpart, gw, r, TR, st));
             HIPCHK(launch_chol_rinv_small(TR, r, WkR, infoR + 2, st));
-            HIPCHK(launch_apply_small(RT, n, r, rp, WkR, r, r, Q1, rp, st));
-            HIPCHK(launch_gram64(Q1, n, r, rp, gpart, gw, st));
-            HIPCHK(launch_gram_reduce(gpart, gw, r, TR, st));
-            HIPCHK(launch_chol_rinv_small(TR, r, WksR, infoR + 3, st));
-            HIPCHK(launch_apply_small(Q1, n, r, rp, WksR, r, r, Vk, kr, st));
+            HIPCHK(launch_apply_small(RT, n, r, rp, WkR, r, r, Vk, kr, st));
         } else {
             HIPCHK(launch_gram64(RT, n, r, rp, gpart, gw, st));
             HIPCHK(launch_gram_reduce(gpart, gw, r, TR, st));
@@ -1398,9 +1394,10 @@ bcur_status bcur_decompose_alg1(bcur_ctx* ctx, const float* A, int64_t m, int64_
         StageScope ts(ctx, BCUR_STAGE_GATHER);
         HIPCHK(launch_gather_cols(A, lda, m, sc.list, c, Cbuf, ldc, st));
     }
-    // step 3: W = alpha R S (held transposed, c x r), U = W^+ through the
-    // pseudoinverse M of the smaller Gram matrix G, then the core for the
-    // unscaled factors alpha D U.  M = G^-1 from a Cholesky factor when its
+    // step 3: W = alpha R S, U = W^+ through the pseudoinverse M of the smaller
+    // Gram matrix G = X^T X, where X = W (r x c) when c <= r and X = W^T (c x r)
+    // otherwise: W^+ = M W^T = (X M)^T, or W^+ = W^T M = X M.  The core for the
+    // unscaled factors is alpha D W^+.  M = G^-1 from a Cholesky factor when its
     // inverse certifies that no singular value of W is near the cutoff and no
     // truncation is asked for; otherwise (decided on the device) M from the
     // eigensystem of G with the cutoff and the rank-k truncation.
@@ -1409,11 +1406,12 @@ bcur_status bcur_decompose_alg1(bcur_ctx* ctx, const float* A, int64_t m, int64_
     const int64_t ldu = res->U ? res->ldu : rp;
     {
         StageScope ts(ctx, BCUR_STAGE_A1_PINV);
-        HIPCHK(launch_alg1_w(RT, rp, r, sc.list, dscale, c, alpha, Wt, st));
-        if (c <= r)   // W^T W = Wt Wt^T,  W^+ = (W^T W)^+ W^T
-            HIPCHK(launch_dgemm(c, c, r, 1.0, Wt, r, false, Wt, r, true, 0.0, Gw, t_w, st));
-        else          // W W^T = Wt^T Wt,  W^+ = W^T (W W^T)^+
-            HIPCHK(launch_dgemm(r, r, c, 1.0, Wt, r, true, Wt, r, false, 0.0, Gw, t_w, st));
+        const bool wide = c > r;   // X = W^T
+        const int64_t K = wide ? c : r;
+        HIPCHK(launch_alg1_w(RT, rp, r, sc.list, dscale, c, alpha, wide ? 1 : 0, Wx, st));
+        const int gk = gram_wgs(K);
+        HIPCHK(launch_gram64(Wx, K, t_w, t_w, gpartW, gk, st));
+        HIPCHK(launch_gram_reduce(gpartW, gk, t_w, Gw, st));
         const double cut = ldexp((double)std::max(r, c), -24);
         const int force_eig = p->pinv_eig || (rank_k > 0 && rank_k < t_w);
         HIPCHK(launch_chol_rinv_small(Gw, t_w, Rw, infoW + 2, st));
@@ -1421,11 +1419,7 @@ bcur_status bcur_decompose_alg1(bcur_ctx* ctx, const float* A, int64_t m, int64_
         HIPCHK(launch_gram_inv_rinv(Rw, t_w, Mw, infoW + 3, st));
         HIPCHK(launch_jacobi_eigh(Gw, t_w, t_w, lamW, Vw, nullptr, jwsW, infoW, st, infoW + 3));
         HIPCHK(launch_pinv_eig(lamW, Vw, t_w, cut * cut, rank_k, Mw, infoW + 4, infoW + 3, st));
-        if (c <= r)
-            HIPCHK(launch_dgemm(c, r, c, 1.0, Mw, t_w, false, Wt, r, false, 0.0, U64, r, st));
-        else
-            HIPCHK(launch_dgemm(c, r, r, 1.0, Wt, r, false, Mw, t_w, false, 0.0, U64, r, st));
-        HIPCHK(launch_scale_rows_f32(U64, c, r, dscale, alpha, U, ldu, st));
+        HIPCHK(launch_pinv_apply(Wx, K, t_w, Mw, dscale, alpha, wide ? 0 : 1, U, ldu, st));
     }
     // err = ||A - (C U) R||_F for the FP32 U: C U with FP64 accumulation, rounded
     // to FP32, then the residual GEMM with its fused squared norm
@@ -1435,8 +1429,8 @@ bcur_status bcur_decompose_alg1(bcur_ctx* ctx, const float* A, int64_t m, int64_
         HIPCHK(launch_f64_to_f32_2d(P64, m, r, r, P32, rp, st));
     }
     const GemmPlan pe = plan_sgemm(m, n, r, false, false);
-    STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_E, BCUR_STAGE_FIT_REDUCE, pe, m, n, r, false, P32, rp, R0, np, E, np, nullptr,
-                     EPI_RESID, A, lda, nullptr, 0, wsE));
+    STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_E, BCUR_STAGE_FIT_REDUCE, pe, m, n, r, false, P32, rp, R0, np, nullptr, 0,
+                     nullptr, EPI_RESID_NORM, A, lda, nullptr, 0, wsE));
     HIPCHK(launch_fit_err(wsE, nwsE, wsE, 0, errv, st));
     HIPCHK(hipMemcpyAsync(h2, span2_0, span2, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -1448,8 +1442,8 @@ bcur_status bcur_decompose_alg1(bcur_ctx* ctx, const float* A, int64_t m, int64_
     if (hinfoW[4] < t_w) fl |= BCUR_FLAG_RANKDEF_W;
     if (hinfoW[3]) fl |= BCUR_FLAG_PINV_EIG;
     const int* hinfoR = reinterpret_cast<const int*>(mirror1(infoR));
-    if (cholqr_scores) {
-        if ((hinfoR[2] | hinfoR[3]) & 1) fl |= BCUR_FLAG_RANKDEF_R;
+    if (chol_scores) {
+        if (hinfoR[2] & 1) fl |= BCUR_FLAG_RANKDEF_R;
     } else {
         const double cutR = ldexp((double)std::max(r, n), -24);
         if (!(hlamR[kr - 1] > cutR * cutR * hlamR[0])) fl |= BCUR_FLAG_RANKDEF_R;

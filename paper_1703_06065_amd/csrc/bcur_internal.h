@@ -38,7 +38,7 @@ hipError_t launch_fit_err(const double* parts, int64_t nparts_e, const double* d
                           double* out, hipStream_t st);
 
 // ---- FP32 MFMA GEMM (k_sgemm.hip) ------------------------------------------
-enum GemmEpi { EPI_STORE = 0, EPI_RESID = 1, EPI_ADD_DOT = 2 };
+enum GemmEpi { EPI_STORE = 0, EPI_RESID = 1, EPI_ADD_DOT = 2, EPI_RESID_NORM = 3 };
 struct GemmPlan {
     int splits = 1;
     int64_t kchunk = 0;
@@ -49,6 +49,7 @@ struct GemmPlan {
 GemmPlan plan_sgemm(int64_t M, int64_t N, int64_t K, bool transA, bool allow_split);
 size_t sgemm_partial_floats(const GemmPlan& p, int64_t M, int64_t N);
 // EPI_STORE: D = acc.  EPI_RESID: D = X - acc, wsum[wg] = sum (X - acc)^2.
+// EPI_RESID_NORM: wsum only, D is not written (may be null).
 // EPI_ADD_DOT: D = X + acc, wsum[wg] = sum acc * Y.   Epilogues need splits == 1.
 // main kernel only (partial tiles when split) and the split-K sum
 hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K, bool transA, const float* A,
@@ -83,6 +84,9 @@ hipError_t launch_bgemm_nt(const GemmPlan& p, int64_t M, int64_t N, int64_t K, c
 int gram_wgs(int64_t rows);
 // partial[w] (l x l) = sum over the w-th row range of X^T X, FP64 accumulation (wgs partials).
 hipError_t launch_gram64(const float* X, int64_t rows, int64_t l, int64_t ldx, double* partial, int wgs,
+                         hipStream_t st);
+// the same for an FP64 X
+hipError_t launch_gram64(const double* X, int64_t rows, int64_t l, int64_t ldx, double* partial, int wgs,
                          hipStream_t st);
 // T (l x l) = sum of the wgs partials in a fixed order, many workgroups.
 hipError_t launch_gram_reduce(const double* partial, int parts, int64_t l, double* T, hipStream_t st);
@@ -133,9 +137,10 @@ hipError_t launch_uniform_rows(int64_t m, const uint64_t* draws, int64_t r, int6
 // RT (n x ldrt) = A[rows, :]^T, columns r .. ldrt-1 zero
 hipError_t launch_gather_rows_t(const float* A, int64_t lda, int64_t n, const int64_t* d_rows, int64_t r, float* RT,
                                 int64_t ldrt, hipStream_t st);
-// Wt (c x r, FP64, ld r): Wt[t][i] = alpha d_scale[t] RT[d_cols[t]][i]
+// W = alpha R S in FP64 with W[i][t] = alpha d_scale[t] RT[d_cols[t]][i]: stored as Wt (c x r, ld r)
+// when transposed = 1, else as W (r x c, ld c)
 hipError_t launch_alg1_w(const float* RT, int64_t ldrt, int64_t r, const int64_t* d_cols, const double* d_scale,
-                         int64_t c, double alpha, double* Wt, hipStream_t st);
+                         int64_t c, double alpha, int transposed, double* W, hipStream_t st);
 // M (t x t) = V diag(1/lam over the kept prefix) V^T (lam descending, V t x t with eigenvectors in
 // columns); kept = #{lam_j > cut lam_0}, capped at rank_k when rank_k > 0; cnt = {above cut, kept}.
 // Skipped when gate is non-null and *gate == 0.
@@ -147,8 +152,10 @@ hipError_t launch_pinv_certify(const double* G, const double* Rinv, int64_t t, c
                                int force_eig, int* use_eig, int* cnt, hipStream_t st);
 // M = Rinv Rinv^T (t x t), skipped when *use_eig != 0
 hipError_t launch_gram_inv_rinv(const double* Rinv, int64_t t, double* M, const int* use_eig, hipStream_t st);
-// U (c x r, FP32, ldu) = alpha diag(d_scale) U64 (c x r, FP64, ld r)
-hipError_t launch_scale_rows_f32(const double* U64, int64_t c, int64_t r, const double* d_scale, double alpha,
-                                 float* U, int64_t ldu, hipStream_t st);
+// Y = X M for X (K x t, FP64, ld t) and M (t x t, FP64, symmetric); with row scales s_i = alpha
+// d_scale[i]: transposed = 0 stores U[i][j] = s_i Y[i][j] (K x t), transposed = 1 stores
+// U[j][i] = s_j Y[i][j] (t x K), rounded to FP32 (ldu)
+hipError_t launch_pinv_apply(const double* X, int64_t K, int64_t t, const double* M, const double* d_scale,
+                             double alpha, int transposed, float* U, int64_t ldu, hipStream_t st);
 
 }  // namespace bcur

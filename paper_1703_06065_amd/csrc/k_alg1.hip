@@ -17,14 +17,15 @@ namespace {
 __global__ __launch_bounds__(64) void k_uniform_rows(int64_t m, const uint64_t* __restrict__ draws, int r,
                                                     int64_t* __restrict__ rows) {
     const int lane = threadIdx.x;
-    const uint64_t d0 = lane < r ? draws[lane] : 0, d1 = lane + 64 < r ? draws[lane + 64] : 0;
+    // x of draws lane and lane + 64, computed up front
+    const long long x0 = lane < r ? (long long)__umul64hi(draws[lane], (uint64_t)(m - lane)) : 0;
+    const long long x1 = lane + 64 < r ? (long long)__umul64hi(draws[lane + 64], (uint64_t)(m - lane - 64)) : 0;
     long long a0 = LLONG_MAX, a1 = LLONG_MAX;
     for (int t = 0; t < r; ++t) {
-        const uint64_t dt = t < 64 ? d0 : d1;
+        const long long xt = t < 64 ? x0 : x1;
         const int src = t & 63;
-        const uint64_t d = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(dt >> 32), src) << 32) |
-                           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)dt, src);
-        const long long x = (long long)__umul64hi(d, (uint64_t)(m - t));
+        const long long x = (long long)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(xt >> 32), src) << 32) |
+                                        (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)xt, src));
         long long j = x;
         for (;;) {
             const long long jn = x + __popcll(__ballot(a0 <= j)) + __popcll(__ballot(a1 <= j));
@@ -61,14 +62,19 @@ __global__ __launch_bounds__(256) void k_gather_rows_t(const float* __restrict__
     }
 }
 
-// Wt (c x r, FP64) = (alpha R S)^T: Wt[t][i] = alpha d[t] RT[cols[t]][i].
+// W = alpha R S in FP64, W[i][t] = alpha d[t] RT[cols[t]][i] (i < r, t < c), stored
+// transposed (Wt, c x r) or not (W, r x c).  One workgroup per column t of W.
 __global__ __launch_bounds__(128) void k_alg1_w(const float* __restrict__ RT, int64_t ldrt, int r,
                                                const int64_t* __restrict__ cols, const double* __restrict__ d,
-                                               double alpha, double* __restrict__ Wt) {
+                                               int64_t c, double alpha, int transposed, double* __restrict__ W) {
     const int64_t t = blockIdx.x;
     const double sc = alpha * d[t];
     const float* src = RT + cols[t] * ldrt;
-    for (int i = threadIdx.x; i < r; i += 128) Wt[t * r + i] = sc * (double)src[i];
+    for (int i = threadIdx.x; i < r; i += 128) {
+        const double v = sc * (double)src[i];
+        if (transposed) W[t * r + i] = v;
+        else W[(int64_t)i * c + t] = v;
+    }
 }
 
 // M (t x t) = sum over the kept j of v_j v_j^T / lam_j, with lam descending and
@@ -111,14 +117,15 @@ __global__ __launch_bounds__(256) void k_pinv_certify(const double* __restrict__
                                                      int force_eig, int* __restrict__ use_eig,
                                                      int* __restrict__ cnt) {
     __shared__ double s_tr[4], s_fr[4];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     double tr = 0.0, fr = 0.0;
     for (int i = tid; i < t; i += 256) tr += G[(int64_t)i * t + i];
-    for (int64_t e = tid; e < (int64_t)t * t; e += 256) {
-        const int i = (int)(e / t), j = (int)(e - (int64_t)i * t);
-        const double v = j >= i ? Rinv[e] : 0.0;
-        fr = fma(v, v, fr);
-    }
+    // the upper triangle of Rinv: rows by wave, columns by lane
+    for (int i = wave; i < t; i += 4)
+        for (int j = i + lane; j < t; j += 64) {
+            const double v = Rinv[(int64_t)i * t + j];
+            fr = fma(v, v, fr);
+        }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         tr += __shfl_xor(tr, o, 64);
@@ -159,13 +166,45 @@ __global__ __launch_bounds__(128) void k_gram_inv_rinv(const double* __restrict_
     }
 }
 
-// U (c x r, FP32, ldu) = alpha diag(d) U64 (c x r, FP64, ld r).
-__global__ __launch_bounds__(128) void k_scale_rows_f32(const double* __restrict__ U64, int r,
-                                                       const double* __restrict__ d, double alpha,
-                                                       float* __restrict__ U, int64_t ldu) {
-    const int64_t t = blockIdx.x;
-    const double sc = alpha * d[t];
-    for (int i = threadIdx.x; i < r; i += 128) U[t * ldu + i] = (float)(sc * U64[t * r + i]);
+// Y = X M (X: K x t, M: t x t symmetric, FP64), scaled by s_i = alpha d[i] per
+// row of the core and rounded to FP32: U[i][j] = s_i Y[i][j], or, transposed,
+// U[j][i] = s_j Y[i][j].  A workgroup takes 16 rows of X (staged in LDS) and
+// all t columns; thread (j, q) accumulates rows 4q .. 4q+3 of column j.
+constexpr int kPaRows = 16;
+__global__ __launch_bounds__(256) void k_pinv_apply(const double* __restrict__ X, int64_t K, int t,
+                                                   const double* __restrict__ M, const double* __restrict__ d,
+                                                   double alpha, int transposed, float* __restrict__ U,
+                                                   int64_t ldu) {
+    __shared__ double xs[kPaRows][129];
+    const int tid = threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.x * kPaRows;
+    const int nrow = (int)(K - i0 < kPaRows ? K - i0 : kPaRows);
+    for (int e = tid; e < kPaRows * t; e += 256) {
+        const int rr = e / t, k = e - rr * t;
+        xs[rr][k] = rr < nrow ? X[(i0 + rr) * t + k] : 0.0;
+    }
+    __syncthreads();
+    // columns j = tid % 64 + 64 h (h = 0, 1), row quarter q = tid / 64
+    const int jl = tid & 63, q = tid >> 6;
+    for (int h = 0; h < 2; ++h) {
+        const int j = jl + 64 * h;
+        if (j >= t) break;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int k = 0; k < t; ++k) {
+            const double mk = M[(int64_t)k * t + j];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u] = fma(xs[4 * q + u][k], mk, acc[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int rr = 4 * q + u;
+            if (rr < nrow) {
+                const int64_t i = i0 + rr;
+                if (transposed) U[(int64_t)j * ldu + i] = (float)(alpha * d[j] * acc[u]);
+                else U[i * ldu + j] = (float)(alpha * d[i] * acc[u]);
+            }
+        }
+    }
 }
 
 }  // namespace
@@ -185,9 +224,10 @@ hipError_t launch_gather_rows_t(const float* A, int64_t lda, int64_t n, const in
 }
 
 hipError_t launch_alg1_w(const float* RT, int64_t ldrt, int64_t r, const int64_t* d_cols, const double* d_scale,
-                         int64_t c, double alpha, double* Wt, hipStream_t st) {
+                         int64_t c, double alpha, int transposed, double* W, hipStream_t st) {
     if (c < 1 || r < 1 || ldrt < r) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_alg1_w, dim3((unsigned)c), dim3(128), 0, st, RT, ldrt, (int)r, d_cols, d_scale, alpha, Wt);
+    hipLaunchKernelGGL(k_alg1_w, dim3((unsigned)c), dim3(128), 0, st, RT, ldrt, (int)r, d_cols, d_scale, c, alpha,
+                       transposed, W);
     return hipGetLastError();
 }
 
@@ -213,10 +253,11 @@ hipError_t launch_gram_inv_rinv(const double* Rinv, int64_t t, double* M, const 
     return hipGetLastError();
 }
 
-hipError_t launch_scale_rows_f32(const double* U64, int64_t c, int64_t r, const double* d_scale, double alpha,
-                                 float* U, int64_t ldu, hipStream_t st) {
-    if (c < 1 || r < 1 || ldu < r) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_scale_rows_f32, dim3((unsigned)c), dim3(128), 0, st, U64, (int)r, d_scale, alpha, U, ldu);
+hipError_t launch_pinv_apply(const double* X, int64_t K, int64_t t, const double* M, const double* d_scale,
+                             double alpha, int transposed, float* U, int64_t ldu, hipStream_t st) {
+    if (K < 1 || t < 1 || t > 128 || ldu < (transposed ? K : t)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_pinv_apply, dim3((unsigned)((K + kPaRows - 1) / kPaRows)), dim3(256), 0, st, X, K, (int)t, M,
+                       d_scale, alpha, transposed, U, ldu);
     return hipGetLastError();
 }
 

@@ -79,9 +79,10 @@ __global__ __launch_bounds__(WM* WN * 64) void k_sgemm(const GemmArgs g) {
     // EPI_RESID: the residual input X of this thread's outputs is read before the
     // main loop (a wave-uniform base plus one lane offset per load), so its HBM
     // latency is hidden behind the MFMA work instead of following it.
-    constexpr int XM = EPI == EPI_RESID ? TM : 1, XN = EPI == EPI_RESID ? TN : 1;
+    constexpr bool kResid = EPI == EPI_RESID || EPI == EPI_RESID_NORM;
+    constexpr int XM = kResid ? TM : 1, XN = kResid ? TN : 1;
     float xv[XM][XN][16];
-    if constexpr (EPI == EPI_RESID) {
+    if constexpr (kResid) {
         const int wmu = __builtin_amdgcn_readfirstlane(wm), wnu = __builtin_amdgcn_readfirstlane(wn);
         const int64_t rb0 = m0 + wmu * WTM, cb0 = n0 + wnu * WTN;
         const float* xbase = g.X + rb0 * g.ldx + cb0;
@@ -182,9 +183,9 @@ __global__ __launch_bounds__(WM* WN * 64) void k_sgemm(const GemmArgs g) {
                     const float x = acc[i][j][v];
                     if (EPI == EPI_STORE) {
                         D[row * g.ldd + col] = x;
-                    } else if (EPI == EPI_RESID) {
+                    } else if (kResid) {
                         const float e = xv[i][j][v] - x;
-                        D[row * g.ldd + col] = e;
+                        if (EPI == EPI_RESID) D[row * g.ldd + col] = e;
                         wacc += (double)e * (double)e;
                     } else {
                         D[row * g.ldd + col] = g.X[row * g.ldx + col] + x;
@@ -337,6 +338,7 @@ hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K,
         case 200: e = run<2, false, EPI_STORE>(a, grid, st); break;
         case 210: e = run<2, true, EPI_STORE>(a, grid, st); break;
         case 201: e = run<2, false, EPI_RESID>(a, grid, st); break;
+        case 203: e = run<2, false, EPI_RESID_NORM>(a, grid, st); break;
         case 202: e = run<2, false, EPI_ADD_DOT>(a, grid, st); break;
         case 212: e = run<2, true, EPI_ADD_DOT>(a, grid, st); break;
         default: return hipErrorInvalidValue;

@@ -16,9 +16,10 @@ constexpr int kRC = 32;        // rows per LDS chunk
 // partial[w] = X[rows of w]^T X[rows of w]; thread (ti, tj) owns the 4x4 block
 // of entries (4 ti .. 4 ti + 3, 4 tj .. 4 tj + 3).  Products of two floats are
 // exact in FP64 and every entry sums its rows in order, so T is symmetric bitwise.
-__global__ __launch_bounds__(1024) void k_gram64(const float* __restrict__ X, int64_t rows, int l, int64_t ldx,
+template <typename T>
+__global__ __launch_bounds__(1024) void k_gram64(const T* __restrict__ X, int64_t rows, int l, int64_t ldx,
                                                  int64_t rows_per_wg, double* __restrict__ partial) {
-    __shared__ __attribute__((aligned(16))) float xs[kRC * kMaxL];
+    __shared__ __attribute__((aligned(16))) T xs[kRC * kMaxL];
     const int lp = (l + 3) & ~3, TT = lp / 4;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int ti = tid / TT, tj = tid % TT;
@@ -34,14 +35,23 @@ __global__ __launch_bounds__(1024) void k_gram64(const float* __restrict__ X, in
         __syncthreads();
         for (int e = tid; e < kRC * lp; e += nt) {
             const int rr = e / lp, cc = e % lp;
-            xs[e] = (rr < nr && cc < l) ? X[(rb + rr) * ldx + cc] : 0.0f;
+            xs[e] = (rr < nr && cc < l) ? X[(rb + rr) * ldx + cc] : (T)0;
         }
         __syncthreads();
         for (int rr = 0; rr < nr; ++rr) {
-            const float4 xi = *reinterpret_cast<const float4*>(&xs[rr * lp + 4 * ti]);
-            const float4 xj = *reinterpret_cast<const float4*>(&xs[rr * lp + 4 * tj]);
-            const double vi[4] = {xi.x, xi.y, xi.z, xi.w};
-            const double vj[4] = {xj.x, xj.y, xj.z, xj.w};
+            double vi[4], vj[4];
+            if constexpr (sizeof(T) == 4) {
+                const float4 xi = *reinterpret_cast<const float4*>(&xs[rr * lp + 4 * ti]);
+                const float4 xj = *reinterpret_cast<const float4*>(&xs[rr * lp + 4 * tj]);
+                vi[0] = xi.x; vi[1] = xi.y; vi[2] = xi.z; vi[3] = xi.w;
+                vj[0] = xj.x; vj[1] = xj.y; vj[2] = xj.z; vj[3] = xj.w;
+            } else {
+                const double2* pi = reinterpret_cast<const double2*>(&xs[rr * lp + 4 * ti]);
+                const double2* pj = reinterpret_cast<const double2*>(&xs[rr * lp + 4 * tj]);
+                const double2 i0 = pi[0], i1 = pi[1], j0 = pj[0], j1 = pj[1];
+                vi[0] = i0.x; vi[1] = i0.y; vi[2] = i1.x; vi[3] = i1.y;
+                vj[0] = j0.x; vj[1] = j0.y; vj[2] = j1.x; vj[3] = j1.y;
+            }
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -622,14 +632,25 @@ int gram_wgs(int64_t rows) {
     return (int)w;
 }
 
-hipError_t launch_gram64(const float* X, int64_t rows, int64_t l, int64_t ldx, double* partial, int wgs,
-                         hipStream_t st) {
+template <typename T>
+static hipError_t gram64_impl(const T* X, int64_t rows, int64_t l, int64_t ldx, double* partial, int wgs,
+                              hipStream_t st) {
     if (l < 1 || l > kMaxL) return hipErrorInvalidValue;
     const int lp = ((int)l + 3) & ~3;
     const int nt = (lp / 4) * (lp / 4);
     const int64_t rpw = (rows + wgs - 1) / wgs;
-    hipLaunchKernelGGL(k_gram64, dim3(wgs), dim3(nt < 64 ? 64 : nt), 0, st, X, rows, (int)l, ldx, rpw, partial);
+    hipLaunchKernelGGL(k_gram64<T>, dim3(wgs), dim3(nt < 64 ? 64 : nt), 0, st, X, rows, (int)l, ldx, rpw, partial);
     return hipGetLastError();
+}
+
+hipError_t launch_gram64(const float* X, int64_t rows, int64_t l, int64_t ldx, double* partial, int wgs,
+                         hipStream_t st) {
+    return gram64_impl(X, rows, l, ldx, partial, wgs, st);
+}
+
+hipError_t launch_gram64(const double* X, int64_t rows, int64_t l, int64_t ldx, double* partial, int wgs,
+                         hipStream_t st) {
+    return gram64_impl(X, rows, l, ldx, partial, wgs, st);
 }
 
 hipError_t launch_gram_reduce(const double* partial, int parts, int64_t l, double* T, hipStream_t st) {
@@ -641,7 +662,8 @@ hipError_t launch_gram_reduce(const double* partial, int parts, int64_t l, doubl
 hipError_t launch_chol_rinv_small(const double* T, int64_t l, double* Rinv, int* info, hipStream_t st) {
     if (l < 1 || l > kMaxL) return hipErrorInvalidValue;
     // a step is latency-bound: up to l = 64 a 16 x 16 grid with 4 x 4 slots per
-    // thread measured fastest (vs one wave with 8 x 8 slots), 16 x 16 with 8 x 8 above
+    // thread measured fastest (vs one wave with 8 x 8 slots); above, 16 x 16 with
+    // 8 x 8 (74 us at l = 128, against 93 us for 32 x 32 with 4 x 4)
     if (l <= 64)
         hipLaunchKernelGGL((k_chol_rinv_small<16, 4>), dim3(1), dim3(256), 0, st, T, (int)l, Rinv, info);
     else

@@ -5,8 +5,9 @@ Tolerances:
   * row draws, column blocks: integer results, bit-exact (the column draws
     whenever the oracle's smallest margin exceeds 2 G max_g tol_g).
   * scores: for kr < r the GPU takes the SVD of R from the FP64 eigensystem
-    of R R^T (FP32 data, exact products), for kr = r an orthonormal basis of
-    the row space of R by Cholesky QR twice; V is rounded to FP32, so
+    of R R^T (FP32 data, exact products), for kr = r the basis R^T L^-T of
+    the row space of R from the FP64 factor R R^T = L L^T, orthonormal up to
+    about u64 cond(R)^2; V is rounded to FP32, so
     |l_g(GPU) - l_g| <= tau max(l_g, kr/G), tau = max(1e-5, 64 u64 kappa_R),
     kappa_R = sigma_1^2 / (sigma_kr^2 - sigma_kr+1^2).
   * U: W^+ through the inverse of W's Gram matrix in FP64 (its Cholesky
