@@ -493,3 +493,49 @@ def alg1(A: np.ndarray, offsets: Sequence[int], r: int, s: int, omega: Optional[
                sv_r=np.linalg.svd(A64[rows, :], compute_uv=False),
                rel_err=fit["err"] / math.sqrt(out["frob2"]) if out["frob2"] > 0 else 0.0)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Boosting (Sec. 3.3: Thm. 2 from Lemma 3 by keeping the best of t runs)
+# ---------------------------------------------------------------------------
+
+def trial_draws(draws: Sequence[int], i: int, s: int) -> Sequence[int]:
+    """The s draws of trial i: words i*s .. i*s+s-1 (independent across trials)."""
+    return draws[i * s:(i + 1) * s]
+
+
+def boost_pick(errs: Sequence[float]) -> int:
+    """The kept trial: the smallest error, the first one on ties."""
+    best = 0
+    for i, e in enumerate(errs):
+        if e < errs[best]:
+            best = i
+    return best
+
+
+def boost(A: np.ndarray, offsets: Sequence[int], k: int, s: int, omega: Optional[np.ndarray],
+          draws: Sequence[int], t: int, q: int = 2, replace: bool = False,
+          mode: str = "twin") -> Dict[str, object]:
+    """Boosting over t independent samplings (Sec. 3.3): the scores come from
+    one top-k subspace V_k (shared by the trials); trial i samples s blocks
+    with its own draws, fits U_i = C_i^+ A and err_i = ||A - C_i C_i^+ A||_F;
+    the trial with the smallest error is returned (t = ln(1/delta) turns a
+    per-run failure probability below 1/e into delta)."""
+    base = decompose(A, offsets, k, s, omega, draws[:s], q=q, replace=replace, mode=mode, with_fit=False)
+    trials = []
+    for i in range(t):
+        samp = sample_blocks(base["scores"], trial_draws(draws, i, s), s, replace)
+        C = gather_columns(A, offsets, samp["idx"])
+        U, err = fit_columns(A, C)
+        trials.append({"idx": samp["idx"], "weights": samp["weights"], "margins": samp["margins"], "U": U,
+                       "err": err, "cols": selected_columns(offsets, samp["idx"])})
+    errs = [tr["err"] for tr in trials]
+    b = boost_pick(errs)
+    out = {key: base[key] for key in ("frob2", "finite", "scores", "Vk") if key in base}
+    for key in ("kappa", "ritz", "lam"):
+        if key in base:
+            out[key] = base[key]
+    out.update(trials=trials, errs=np.array(errs), best=b, idx=trials[b]["idx"], weights=trials[b]["weights"],
+               U=trials[b]["U"], err=trials[b]["err"], cols=trials[b]["cols"],
+               rel_err=trials[b]["err"] / math.sqrt(out["frob2"]) if out["frob2"] > 0 else 0.0)
+    return out

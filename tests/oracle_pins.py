@@ -485,6 +485,64 @@ def check_alg1_exact_low_rank(O):
         assert res["err"] <= 1e-9 * math.sqrt(res["frob2"]), res["err"]
 
 
+# --------------------------------------------------------------------------
+# Boosting (Sec. 3.3)
+# --------------------------------------------------------------------------
+
+def check_boost_law(O):
+    """Independent trials: P(min_i err_i > q) = P(err > q)^t for every level
+    q.  Single runs (their own draws) give P(err > q) at q = their median;
+    boosted runs with t = 3 must match its cube within five standard errors
+    (reusing one draw set for every trial would give P(err > q) itself,
+    keeping the largest error 1 - (1 - P)^3)."""
+    w = gen.tiny(0)
+    base = O.decompose(w.A, w.offsets, w.k, w.s, w.omega, w.draws, q=w.q, with_fit=False)
+    sc = base["scores"]
+    cache = {}
+    A64 = w.A.astype(np.float64)
+    fro2 = float(np.sum(A64 * A64))
+
+    def err_of(idx):
+        # ||A - C C^+ A||_F^2 = ||A||_F^2 - ||Q^T A||_F^2 for C = Q R (full column rank here)
+        key = tuple(sorted(int(j) for j in idx))
+        if key not in cache:
+            cols = np.concatenate([np.arange(w.offsets[j], w.offsets[j + 1]) for j in key])
+            Q = np.linalg.qr(A64[:, cols])[0]
+            cache[key] = math.sqrt(max(fro2 - float(np.sum((Q.T @ A64) ** 2)), 0.0))
+        return cache[key]
+
+    n1, t, nb = 600, 3, 600
+    d1 = gen.draws_u64(n1 * w.s, 101)
+    singles = np.array([err_of(O.sample_blocks(sc, d1[i * w.s:(i + 1) * w.s], w.s)["idx"]) for i in range(n1)])
+    q = float(np.median(singles))
+    p1 = float(np.mean(singles > q))
+    db = gen.draws_u64(nb * t * w.s, 202)
+    # the boosted runs call the oracle's own boost with precomputed scores
+    mins = []
+    for i in range(nb):
+        dr = db[i * t * w.s:(i + 1) * t * w.s]
+        errs = [err_of(O.sample_blocks(sc, O.trial_draws(dr, j, w.s), w.s)["idx"]) for j in range(t)]
+        mins.append(errs[O.boost_pick(errs)])
+    pt = float(np.mean(np.array(mins) > q))
+    sd = math.sqrt(pt * (1 - pt) / nb + (3 * p1 * p1) ** 2 * p1 * (1 - p1) / n1) + 1e-3
+    assert abs(pt - p1 ** t) <= 5 * sd, (pt, p1, p1 ** t, sd)
+
+
+def check_boost_keeps_first_minimum(O):
+    """The kept trial is the first one of smallest error, and the whole
+    boosted result is that trial's single decomposition."""
+    assert O.boost_pick([3.0, 1.0, 2.0, 1.0]) == 1
+    assert O.boost_pick([0.5]) == 0
+    w = gen.tiny(1)
+    t = 4
+    dr = gen.draws_u64(t * w.s, 303)
+    res = O.boost(w.A, w.offsets, w.k, w.s, w.omega, dr, t, q=w.q)
+    single = [O.decompose(w.A, w.offsets, w.k, w.s, w.omega, dr[i * w.s:(i + 1) * w.s], q=w.q)["err"]
+              for i in range(t)]
+    assert np.allclose(res["errs"], single, rtol=1e-12)
+    assert res["err"] == min(res["errs"]) and res["best"] == int(np.argmin(single))
+
+
 ALL_CHECKS = [
     check_frob_closed_form,
     check_scores_sum_to_k,
@@ -509,4 +567,6 @@ ALL_CHECKS = [
     check_alg1_rank_k,
     check_alg1_all_rows_is_column_fit,
     check_alg1_exact_low_rank,
+    check_boost_law,
+    check_boost_keeps_first_minimum,
 ]

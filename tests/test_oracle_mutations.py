@@ -118,7 +118,13 @@ def _rows_with_replacement(m, r, draws):
     return O.sample_blocks(np.ones(m), draws, r, replace=True)["idx"]
 
 
+def _pick_largest(errs):
+    return int(np.argmax(errs))
+
+
 MUTANTS = {
+    "boost-reuses-draws": dict(trial_draws=lambda draws, i, s: draws[:s]),
+    "boost-keeps-largest": dict(boost_pick=_pick_largest),
     "pinv-keeps-smallest": dict(pinv_cut=_pinv_smallest),
     "pinv-transpose": dict(pinv_cut=_pinv_transpose),
     "rows-with-replacement": dict(alg1_rows=_rows_with_replacement),
@@ -134,12 +140,14 @@ MUTANTS = {
 
 
 def _pins_for(ns):
+    """The first pin that fails on the clone (the pins run cheapest first)."""
     fails = []
     for chk in P.ALL_CHECKS:
         try:
             chk(ns)
         except Exception as e:  # AssertionError, shape errors, ...
             fails.append((chk.__name__, type(e).__name__))
+            break
     return fails
 
 
