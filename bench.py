@@ -244,6 +244,99 @@ def alg1_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def boost_bench(args):
+    """Boosting on the 8192 x 4096 workload: one range finder and one set of
+    scores, t samplings of s = 16 blocks, each fitted with one refinement
+    step; the best trial kept.  One step = one boosted decomposition."""
+    import numpy as np
+    import torch
+
+    from paper_1703_06065_amd import Context
+    from paper_1703_06065_amd.binding import padded_empty, to_device
+    from workloads import gen
+
+    w = gen.plain_fp32(args.seed)
+    t = args.trials
+    draws = gen.draws_u64(t * w.s, args.seed + 2)
+    A = to_device(w.A)
+    om = torch.from_numpy(w.omega).cuda()
+    ctx = Context(0)
+    Ubuf = padded_empty(w.s * int(np.max(np.diff(w.offsets))), w.n)
+    for _ in range(args.warmup):
+        res = ctx.decompose_boost(A, w.offsets, w.k, w.s, om, draws, t, q=w.q, U_out=Ubuf)
+    torch.cuda.synchronize()
+    # timed region: only the all-trials H = C^T A GEMM (stage fit_H) records HIP events
+    ctx.timing_enable(("fit_H",))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = ctx.decompose_boost(A, w.offsets, w.k, w.s, om, draws, t, q=w.q, U_out=Ubuf)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = ctx.timing_read()
+    ctx.timing_enable(True)
+    nb = min(args.steps, 10)
+    for _ in range(nb):
+        ctx.decompose_boost(A, w.offsets, w.k, w.s, om, draws, t, q=w.q, U_out=Ubuf)
+    torch.cuda.synchronize()
+    breakdown = ctx.timing_read()
+    ctx.timing_enable(False)
+    el = t1 - t0
+    # every trial here has c = 256 columns (16 distinct blocks of 16): ctot = t c
+    c = int(res["c"])
+    ctot = t * c
+    per_launch_flop = 2.0 * w.m * ctot * w.n
+    avg_ms = stages["fit_H"][0] / max(stages["fit_H"][1], 1)
+    ach = per_launch_flop / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(ach / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
+            "kernel": "k_sgemm<128,128,16,2,2,TA> (H = C^T A over the t trials' concatenated columns)",
+            "launches_per_step": 1, "avg_ms": round(avg_ms, 5), "flop_per_launch": per_launch_flop,
+            "algorithmic_bytes_per_launch": 4.0 * (w.m * ctot + w.m * w.n + ctot * w.n)}
+    rf_flops, fit_flops = algorithmic_flops(w.m, w.n, w.k, w.l, w.q, c)
+    out = {
+        "metric": f"block-CUR boosted decompositions/s (t = {t} trials)",
+        "value": args.steps / el,
+        "unit": "decompositions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded numpy: rank-50 Haar signal sigma_i = 1/i + 1e-3 Gaussian noise)",
+        "config": {"workload": f"plain-fp32 {w.m}x{w.n}, {w.G} column blocks of 16, k={w.k}, s={w.s}, q={w.q}, "
+                               f"l={w.l}, boosting over t={t} samplings", "m": w.m, "n": w.n, "G": w.G, "k": w.k,
+                   "s": w.s, "q": w.q, "l": w.l, "t": t, "c": c, "refine": 1},
+        "tflops_total": round((rf_flops + t * fit_flops) * args.steps / el / 1e12, 3),
+        "stage_ms_per_step": {k: round(v[0] / nb, 5) for k, v in breakdown.items() if v[1]},
+        "errs": [float(e) for e in res["errs"]], "best": res["best"], "err": res["err"],
+        "rel_err": res["rel_err"],
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        from oracle import bcur_oracle as O
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+        except Exception:  # pragma: no cover
+            threads = os.cpu_count()
+        done, c0 = 0, time.perf_counter()
+        while True:
+            O.boost(w.A, w.offsets, w.k, w.s, w.omega, draws, t, q=w.q)
+            done += 1
+            ce = time.perf_counter() - c0
+            if ce > 20.0 or done >= 3:
+                break
+        out["cpu_baseline"] = {"value": done / ce, "unit": "decompositions/s", "cores": int(threads),
+                               "kind": "oracle",
+                               "sample": f"{done} whole boosted decomposition(s) (t = {t}) of the same workload by "
+                                         f"the FP64 oracle twin (numpy/LAPACK, {ce:.1f} s)"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -251,7 +344,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--mode", choices=["decompose", "serve", "alg1"], default="decompose")
+    ap.add_argument("--mode", choices=["decompose", "serve", "alg1", "boost"], default="decompose")
+    ap.add_argument("--trials", type=int, default=3, help="boosting: t = ln(1/delta) trials (3 for delta = 0.05)")
     ap.add_argument("--rows", type=int, default=128, help="Algorithm 1: rows drawn (r)")
     ap.add_argument("--kr", type=int, default=0,
                     help="Algorithm 1: right singular vectors of R behind the scores (0: r, as in the listing)")
@@ -268,6 +362,9 @@ def main():
         return
     if args.mode == "alg1":
         alg1_bench(args)
+        return
+    if args.mode == "boost":
+        boost_bench(args)
         return
 
     import numpy as np

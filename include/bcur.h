@@ -279,6 +279,23 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
 bcur_status bcur_footprint(int64_t m, int64_t n, const int64_t* col_off, int64_t G, const int64_t* row_off,
                            int64_t Gr, const bcur_params* params, int32_t library_holds_u, size_t* bytes);
 
+/* ---- boosting -------------------------------------------------------------
+ *
+ * Sec. 3.3 turns the constant-probability guarantee of one run into
+ * probability 1 - delta by running t = ln(1/delta) independent samplings and
+ * keeping the one of smallest error.  Here: one range finder and one set of
+ * block scores (stages 1-3 of bcur_decompose) shared by t trials; trial i
+ * draws s blocks with draws[i*s .. i*s+s-1], gathers C_i and fits U_i = C_i^+ A
+ * with its residual exactly as bcur_decompose does (columns only, params->s_r
+ * = 0); the H_i = C_i^T A products of all trials run as one GEMM over their
+ * concatenated columns.  result describes the kept trial (smallest err, the
+ * first on ties) and receives its U; errs (host, t) receives every trial's
+ * err; *best (may be NULL) its index.  1 <= t <= 64.  Synchronous. */
+bcur_status bcur_decompose_boost(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda,
+                                 const int64_t* col_off, int64_t G, const bcur_params* params,
+                                 const float* omega, int64_t t, const uint64_t* draws, bcur_result* result,
+                                 double* errs, int64_t* best);
+
 /* ---- Algorithm 1: uniform rows, U = W^+ ------------------------------------
  *
  * The method as listed in Algorithm 1 of Sec. 3.1:

@@ -31,6 +31,7 @@ SYMBOLS = [
     "bcur_gather_columns", "bcur_fit_columns", "bcur_decompose", "bcur_timing_enable", "bcur_timing_read",
     "bcur_sketch_pass", "bcur_release_workspace", "bcur_footprint", "bcur_server_create", "bcur_server_destroy",
     "bcur_server_submit", "bcur_server_poll", "bcur_server_wait", "bcur_server_stats", "bcur_decompose_alg1",
+    "bcur_decompose_boost",
 ]
 
 STAGES = ["frob", "rf_AQ", "rf_AtZ", "rf_reduce", "rf_orth", "rf_rr", "scores", "sample", "gather", "fit_H",
@@ -128,6 +129,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "bcur_timing_read": (i32, [vp, P(dbl), P(i64)]),
         "bcur_decompose": (i32, [vp, vp, i64, i64, i64, P(i64), i64, P(i64), i64, P(Params), vp,
                                  P(ctypes.c_uint64), P(Result)]),
+        "bcur_decompose_boost": (i32, [vp, vp, i64, i64, i64, P(i64), i64, P(Params), vp, i64, P(ctypes.c_uint64),
+                                       P(Result), P(dbl), P(i64)]),
         "bcur_decompose_alg1": (i32, [vp, vp, i64, i64, i64, P(i64), i64, P(Alg1Params), P(ctypes.c_uint64),
                                       P(Alg1Result)]),
     }
@@ -355,6 +358,48 @@ class Context:
             out["row_scores"] = rsc
         return out
 
+
+    def decompose_boost(self, A, offsets, k: int, s: int, omega, draws, t: int, q: int = 2, replace: bool = False,
+                        refine: int = 1, precision: int = PREC_FP32, want_u: bool = True, U_out=None):
+        """Boosting: t samplings (draws[i*s:(i+1)*s] for trial i) from one set of
+        scores; returns the kept trial's result with every trial's err."""
+        p, m, n, lda = _check_dev(A, "A")
+        po, on, l, ldo = _check_dev(omega, "omega")
+        if on != n or ldo != l:
+            raise ValueError("omega must be a dense n x l tensor")
+        off = _i64(offsets)
+        G = len(off) - 1
+        dr = np.ascontiguousarray(draws, dtype=np.uint64)
+        if dr.size < t * s:
+            raise ValueError("need t * s draws")
+        prm = Params(k=k, s=s, l=l, q=q, replace=int(replace), precision=precision, refine=refine, reserved=0, s_r=0)
+        idx = np.empty(s, dtype=np.int64)
+        w = np.empty(s)
+        sc = np.empty(G)
+        ritz = np.empty(l)
+        errs = np.empty(t)
+        best = ctypes.c_int64()
+        res = Result()
+        res.idx = _ptr(idx, ctypes.c_int64)
+        res.weights = _ptr(w, ctypes.c_double)
+        res.scores = _ptr(sc, ctypes.c_double)
+        res.ritz = _ptr(ritz, ctypes.c_double)
+        U = None
+        if want_u:
+            cap = min(s * int(np.max(np.diff(off))), n)
+            U = U_out if U_out is not None else padded_empty(cap, n, A.device)
+            res.U = U.data_ptr()
+            res.ldu = U.stride(0)
+            res.u_rows_cap = U.shape[0]
+        self._chk(self.lib.bcur_decompose_boost(self.h, p, m, n, lda, _ptr(off, ctypes.c_int64), G, ctypes.byref(prm),
+                                                po, t, _ptr(dr, ctypes.c_uint64), ctypes.byref(res),
+                                                _ptr(errs, ctypes.c_double), ctypes.byref(best)))
+        out = {"idx": idx, "weights": w, "scores": sc, "ritz": ritz, "c": res.c, "frob2": res.frob2, "err": res.err,
+               "rel_err": res.rel_err, "min_margin": res.min_margin, "flags": res.flags, "rr_sweeps": res.rr_sweeps,
+               "errs": errs, "best": best.value}
+        if U is not None:
+            out["U"] = U[:res.c]
+        return out
 
     def decompose_alg1(self, A, offsets, r: int, s: int, draws, kr: Optional[int] = None, rank_k: int = 0,
                        replace: bool = False, want_u: bool = True, U_out=None, pinv_eig: bool = False):

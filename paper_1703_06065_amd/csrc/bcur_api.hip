@@ -42,6 +42,7 @@ struct bcur_ctx {
 namespace {
 
 constexpr int64_t kMaxSketch = 128;
+constexpr int64_t kMaxTrials = 64;   // boosting trials per call
 
 inline int64_t round4(int64_t x) { return (x + 3) & ~(int64_t)3; }
 
@@ -401,18 +402,24 @@ void fit_layout(Arena& a, FitBufs& b, int64_t m, int64_t n, int64_t c, bool need
 // formed by its own GEMM into Gtmp.  After the caller synchronizes,
 // b.errv[0] = ||E||^2 - <F, dU> (err^2 after the refinement), b.errv[1] =
 // ||E||^2 (before it), b.info[0] bit 0 = pivots dropped, b.piv = pivot ranges.
+// Hpre: H = C^T A already computed by the caller (c x n, ld round4(n)); b.H is
+// then only scratch.
 bcur_status fit_run(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t m, int64_t n, int64_t lda, const float* C,
                     int64_t c, int64_t ldc, const int64_t* d_cols, const int64_t* d_ident, int refine, float* U,
-                    int64_t ldu) {
+                    int64_t ldu, const float* Hpre = nullptr) {
     hipStream_t st = ctx->stream;
     const int64_t np = round4(n), cp = round4(c);
     HIPCHK(hipMemsetAsync(b.info, 0, 4 * sizeof(int), st));
     const GemmPlan ph = plan_sgemm(c, n, m, true, true);
-    STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_H, BCUR_STAGE_FIT_REDUCE, ph, c, n, m, true, C, ldc, A, lda, b.H, np, b.part));
+    // H = C^T A, or the caller's precomputed rows of it (ld np)
+    const float* H = Hpre ? Hpre : b.H;
+    if (!Hpre)
+        STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_H, BCUR_STAGE_FIT_REDUCE, ph, c, n, m, true, C, ldc, A, lda, b.H, np,
+                         b.part));
     {
         StageScope ts(ctx, BCUR_STAGE_FIT_INV);
         if (d_cols) {
-            HIPCHK(launch_gram_from_cols(b.H, np, d_cols, c, b.G, st));
+            HIPCHK(launch_gram_from_cols(H, np, d_cols, c, b.G, st));
         } else {
             if (!b.Gtmp || !d_ident) return fail(ctx, BCUR_E_ARG, "internal: no Gram buffer");
             const GemmPlan pg = plan_sgemm(c, c, m, true, true);
@@ -426,7 +433,7 @@ bcur_status fit_run(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t m, 
     }
     // W = X H (in F, not yet needed), U = X^T W
     const GemmPlan pw = plan_sgemm(c, n, c, false, true), pt = plan_sgemm(c, n, c, true, true);
-    STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_U, BCUR_STAGE_FIT_REDUCE, pw, c, n, c, false, b.X32, cp, b.H, np, b.F, np,
+    STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_U, BCUR_STAGE_FIT_REDUCE, pw, c, n, c, false, b.X32, cp, H, np, b.F, np,
                      b.part));
     STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_U, BCUR_STAGE_FIT_REDUCE, pt, c, n, c, true, b.X32, cp, b.F, np, U, ldu,
                      b.part));
@@ -1201,6 +1208,203 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
     res->min_margin = mm;
     res->flags = fl;
     res->rr_sweeps = (uint32_t)rinfo[2];
+    return BCUR_OK;
+}
+
+bcur_status bcur_decompose_boost(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda,
+                                 const int64_t* col_off, int64_t G, const bcur_params* p, const float* omega,
+                                 int64_t t, const uint64_t* draws, bcur_result* res, double* errs, int64_t* best_out) {
+    if (!ctx) return BCUR_E_ARG;
+    if (!p || !res || !omega || !draws || !res->idx || !errs) return fail(ctx, BCUR_E_ARG, "null argument");
+    STCHK(check_matrix(ctx, A, m, n, lda, "A"));
+    STCHK(check_offsets(ctx, col_off, G, n, "col_off"));
+    const int64_t k = p->k, l = p->l, s = p->s, q = p->q;
+    if (t < 1 || t > kMaxTrials) return fail(ctx, BCUR_E_ARG, "need 1 <= t <= %lld", (long long)kMaxTrials);
+    if (k < 1 || l < k || l > std::min(std::min(m, n), kMaxSketch))
+        return fail(ctx, BCUR_E_ARG, "need 1 <= k <= l <= min(m, n, %lld)", (long long)kMaxSketch);
+    if (q < 0 || q > 64) return fail(ctx, BCUR_E_ARG, "q out of range");
+    if (s < 1 || (!p->replace && s > G)) return fail(ctx, BCUR_E_ARG, "need 1 <= s <= G without replacement");
+    if (p->precision != BCUR_PREC_FP32 && p->precision != BCUR_PREC_BF16)
+        return fail(ctx, BCUR_E_ARG, "unknown precision %d", p->precision);
+    if (p->refine < 0 || p->refine > 1) return fail(ctx, BCUR_E_ARG, "refine must be 0 or 1");
+    if (p->s_r != 0) return fail(ctx, BCUR_E_ARG, "boosting covers the column-block path only (s_r = 0)");
+    const bool bf16 = p->precision == BCUR_PREC_BF16;
+    int64_t maxw = 0;
+    for (int64_t g = 0; g < G; ++g) maxw = std::max(maxw, col_off[g + 1] - col_off[g]);
+    const int64_t cmax = std::min(s * maxw, n), cseg = round4(cmax), ctot_max = t * cseg;
+    if (res->U && (res->ldu < n || (res->ldu & 3) || !aligned16(res->U) || res->u_rows_cap < cmax))
+        return fail(ctx, BCUR_E_ARG, "U needs ldu >= %lld (a multiple of 4, 16-byte aligned) and %lld rows",
+                    (long long)n, (long long)cmax);
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    const int64_t np = round4(n);
+
+    // workspace: range finder | scores and the trials' draws and results | C of all trials, H of all
+    // trials | one fit's buffers | two U buffers
+    RFBufs rb;
+    FitBufs fb;
+    double *d_frob, *d_fpart, *d_sc, *d_w, *d_mg;
+    int64_t *d_off, *d_idx, *d_list;
+    uint64_t *d_dr, *d_qb, *d_pr;
+    int* d_st;
+    float *Vk, *Call, *Hall, *hpart, *Ua, *Ub;
+    // split-K partials of the all-trials H GEMM: the largest over the column
+    // counts it can have (multiples of 4 up to ctot_max)
+    size_t hpart_floats = 4;
+    for (int64_t cc = 4; cc <= ctot_max; cc += 4)
+        hpart_floats = std::max(hpart_floats, sgemm_partial_floats(plan_sgemm(cc, n, m, true, true), cc, n));
+    auto layout = [&](Arena& a) {
+        rf_layout(a, rb, m, n, l, k, bf16);
+        d_off = a.take<int64_t>(G + 1);
+        d_dr = a.take<uint64_t>(t * s);
+        d_qb = a.take<uint64_t>(G);
+        d_pr = a.take<uint64_t>(G);
+        d_list = a.take<int64_t>(ctot_max);
+        // read back in one copy: idx .. frob
+        d_idx = a.take<int64_t>(t * s);
+        d_w = a.take<double>(t * s);
+        d_mg = a.take<double>(t * s);
+        d_st = a.take<int>(4 * t);
+        d_sc = a.take<double>(G);
+        d_frob = a.take<double>(2);
+        d_fpart = a.take<double>(frob2_grid(m, n));
+        Vk = a.take<float>(n * k);
+        Call = a.take<float>(m * ctot_max);
+        Hall = a.take<float>(ctot_max * np);
+        hpart = a.take<float>(hpart_floats);
+        fit_layout(a, fb, m, n, cmax, false);
+        Ua = a.take<float>(cmax * np);
+        Ub = res->U ? nullptr : a.take<float>(cmax * np);
+    };
+    {
+        Arena a;
+        layout(a);
+        STCHK(reserve(ctx, a.off));
+        Arena b{ctx->ws, 0};
+        layout(b);
+    }
+    const char* span0 = reinterpret_cast<const char*>(d_idx);
+    const size_t span = (size_t)(reinterpret_cast<const char*>(d_frob + 1) - span0);
+    const size_t pin_need = 8 * (G + 1) + 8 * t * s + 8 * ctot_max + span + 8 * l + 64;
+    STCHK(reserve_pinned(ctx, pin_need));
+    if (ctx->pinned_busy) HIPCHK(hipStreamSynchronize(st));
+    ctx->pinned_busy = true;
+    char* pin = ctx->pinned;
+    auto ptake = [&pin](size_t bytes) {
+        char* p0 = pin;
+        pin += (bytes + 7) & ~(size_t)7;
+        return p0;
+    };
+    int64_t* h_off = reinterpret_cast<int64_t*>(ptake(8 * (G + 1)));
+    uint64_t* h_dr = reinterpret_cast<uint64_t*>(ptake(8 * t * s));
+    int64_t* h_list = reinterpret_cast<int64_t*>(ptake(8 * ctot_max));
+    char* h0 = ptake(span);
+    double* h_lam = reinterpret_cast<double*>(ptake(8 * l));
+    int* rinfo = reinterpret_cast<int*>(ptake(16));
+    auto mirror = [&](const void* dp) { return h0 + (reinterpret_cast<const char*>(dp) - span0); };
+    memcpy(h_off, col_off, (G + 1) * sizeof(int64_t));
+    memcpy(h_dr, draws, t * s * sizeof(uint64_t));
+    HIPCHK(hipMemcpyAsync(d_off, h_off, (G + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_dr, h_dr, t * s * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(d_st, 0, 4 * t * sizeof(int), st));
+    {
+        StageScope ts(ctx, BCUR_STAGE_FROB);
+        HIPCHK(launch_frob2(A, m, n, lda, d_fpart, frob2_grid(m, n), d_frob, st));
+    }
+    // one top-k subspace and one set of scores for every trial
+    STCHK(range_finder_run(ctx, rb, A, m, n, lda, omega, l, k, q, Vk, nullptr, p->precision));
+    {
+        StageScope ts(ctx, BCUR_STAGE_SCORES);
+        HIPCHK(launch_block_scores(Vk, k, k, d_off, G, d_sc, st));
+    }
+    {
+        StageScope ts(ctx, BCUR_STAGE_SAMPLE);
+        for (int64_t i = 0; i < t; ++i)
+            HIPCHK(launch_sample(d_sc, G, d_dr + i * s, s, p->replace, d_qb, d_pr, d_idx + i * s, d_w + i * s,
+                                 d_mg + i * s, d_st + 4 * i, st));
+    }
+    HIPCHK(hipMemcpyAsync(h0, span0, span, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_lam, rb.lam, l * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(rinfo, rb.info, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const int64_t* hidx = reinterpret_cast<const int64_t*>(mirror(d_idx));
+    const double* hw = reinterpret_cast<const double*>(mirror(d_w));
+    const double* hmg = reinterpret_cast<const double*>(mirror(d_mg));
+    const int* hst = reinterpret_cast<const int*>(mirror(d_st));
+    const double* hsc = reinterpret_cast<const double*>(mirror(d_sc));
+    const double* hfrob = reinterpret_cast<const double*>(mirror(d_frob));
+    if (!isfinite(hfrob[0])) return fail(ctx, BCUR_E_NONFINITE, "A holds NaN or Inf");
+    uint32_t zero_drawn = 0;
+    for (int64_t i = 0; i < t; ++i) {
+        if (hst[4 * i] != 0) return fail(ctx, BCUR_E_HIP, "block scores are not finite");
+        zero_drawn |= hst[4 * i + 1] ? 1u : 0u;
+    }
+    for (int64_t e = 0; e < t * s; ++e)
+        if (hidx[e] < 0 || hidx[e] >= G) return fail(ctx, BCUR_E_HIP, "sampler returned an invalid block");
+    // the trials' columns side by side, each segment starting at a multiple of 4
+    // (padded with copies of its first column)
+    std::vector<int64_t> seg_off(t), seg_c(t);
+    int64_t ctot = 0;
+    for (int64_t i = 0; i < t; ++i) {
+        const std::vector<int64_t> cols = expand_blocks(col_off, hidx + i * s, s);
+        const int64_t ci = (int64_t)cols.size();
+        seg_off[i] = ctot;
+        seg_c[i] = ci;
+        for (int64_t j = 0; j < round4(ci); ++j) h_list[ctot + j] = cols[j < ci ? j : 0];
+        ctot += round4(ci);
+    }
+    HIPCHK(hipMemcpyAsync(d_list, h_list, ctot * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    {
+        StageScope ts(ctx, BCUR_STAGE_GATHER);
+        HIPCHK(launch_gather_cols(A, lda, m, d_list, ctot, Call, ctot, st));
+    }
+    // H = C^T A for every trial at once: one GEMM over the concatenated columns
+    const GemmPlan ph = plan_sgemm(ctot, n, m, true, true);
+    STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_H, BCUR_STAGE_FIT_REDUCE, ph, ctot, n, m, true, Call, ctot, A, lda, Hall, np,
+                     hpart));
+    float* Ubest = res->U ? res->U : Ub;
+    const int64_t ldb = res->U ? res->ldu : np;
+    float* Ucur = Ua;
+    int64_t best = -1;
+    double best_err2 = INFINITY;
+    uint32_t best_flags = 0;
+    for (int64_t i = 0; i < t; ++i) {
+        const float* Ci = Call + seg_off[i];
+        STCHK(fit_run(ctx, fb, A, m, n, lda, Ci, seg_c[i], ctot, d_list + seg_off[i], nullptr, p->refine, Ucur, np,
+                      Hall + seg_off[i] * np));
+        FitOut fo;
+        STCHK(fit_collect(ctx, fb, A, m, n, lda, Ci, seg_c[i], ctot, Ucur, np, &fo));
+        errs[i] = sqrt(fo.err2);
+        if (fo.err2 < best_err2) {
+            best_err2 = fo.err2;
+            best = i;
+            best_flags = fo.flags;
+            HIPCHK(hipMemcpy2DAsync(Ubest, ldb * sizeof(float), Ucur, np * sizeof(float), n * sizeof(float),
+                                    seg_c[i], hipMemcpyDeviceToDevice, st));
+        }
+    }
+    if (best < 0) best = 0;   // every error was NaN: report the first trial
+    HIPCHK(hipStreamSynchronize(st));
+    ctx->pinned_busy = false;
+    uint32_t fl = best_flags;
+    if (rinfo[0] & 1) fl |= BCUR_FLAG_RANKDEF_Y;
+    if (zero_drawn) fl |= BCUR_FLAG_ZERO_SCORE;
+    memcpy(res->idx, hidx + best * s, s * sizeof(int64_t));
+    if (res->weights) memcpy(res->weights, hw + best * s, s * sizeof(double));
+    if (res->scores) memcpy(res->scores, hsc, G * sizeof(double));
+    if (res->ritz)
+        for (int64_t i = 0; i < l; ++i) res->ritz[i] = h_lam[i] > 0.0 ? sqrt(h_lam[i]) : 0.0;
+    double mm = INFINITY;
+    for (int64_t u = 0; u < s; ++u) mm = std::min(mm, hmg[best * s + u]);
+    res->c = seg_c[best];
+    res->r = 0;
+    res->frob2 = hfrob[0];
+    res->err = errs[best];
+    res->rel_err = hfrob[0] > 0.0 ? res->err / sqrt(hfrob[0]) : 0.0;
+    res->min_margin = mm;
+    res->flags = fl;
+    res->rr_sweeps = (uint32_t)rinfo[2];
+    if (best_out) *best_out = best;
     return BCUR_OK;
 }
 
