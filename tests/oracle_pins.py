@@ -543,7 +543,67 @@ def check_boost_keeps_first_minimum(O):
     assert res["err"] == min(res["errs"]) and res["best"] == int(np.argmin(single))
 
 
+# --------------------------------------------------------------------------
+# Diagnostics (Defs. 3 and 4)
+# --------------------------------------------------------------------------
+
+def check_block_stable_rank_closed_forms(O):
+    """Stable rank ||X||_F^2 / ||X||_2^2 of each block slice of V: 1 for a
+    rank-1 slice (one-column blocks, or a block whose rows are multiples of one
+    vector), exactly the rank for a slice with equal nonzero singular values,
+    and 1 <= ratio <= rank(slice) <= min(b_g, k) in general (Def. 3 and the
+    bounds stated with it)."""
+    rng = np.random.default_rng(61)
+    n, k = 48, 6
+    V = np.linalg.qr(rng.standard_normal((n, k)))[0]
+    # one-column blocks: every ratio is 1
+    alpha, ratios = O.block_stable_rank(V, np.arange(n + 1))
+    assert np.allclose(ratios, 1.0, rtol=1e-12) and abs(alpha - 1.0) <= 1e-12
+    # planted slices: rows 0..3 multiples of one vector (rank 1); rows 4..9
+    # = 3 orthogonal rows of equal norm, each repeated twice (singular values equal)
+    W = rng.standard_normal((n, k))
+    u = rng.standard_normal(k)
+    W[0:4] = np.outer([1.0, -2.0, 0.5, 3.0], u)
+    Q = np.linalg.qr(rng.standard_normal((k, 3)))[0].T   # 3 orthonormal rows
+    W[4:10] = np.repeat(Q, 2, axis=0)
+    off = [0, 4, 10, 17, 30, n]
+    alpha, ratios = O.block_stable_rank(W, off)
+    assert abs(ratios[0] - 1.0) <= 1e-12
+    assert abs(ratios[1] - 3.0) <= 1e-12
+    for g in range(len(off) - 1):
+        blk = W[off[g]:off[g + 1]]
+        rk = np.linalg.matrix_rank(blk)
+        assert 1.0 - 1e-12 <= ratios[g] <= rk + 1e-12 <= min(off[g + 1] - off[g], k) + 1e-12
+    assert alpha == np.nanmin(ratios)
+    # a zero slice has no ratio
+    W[30:n] = 0.0
+    _, ratios = O.block_stable_rank(W, off)
+    assert np.isnan(ratios[-1])
+
+
+def check_incoherence_extremes(O):
+    """mu = (m/k) max_i ||U_k^T e_i||^2 lies in [1, m/k] (Def. 4): 1 when every
+    row of the orthonormal U_k has the same norm (columns of a normalized
+    Hadamard matrix), m/k when a column of U_k is a coordinate vector."""
+    m, k = 64, 8
+    H = np.array([[1.0]])
+    while H.shape[0] < m:
+        H = np.block([[H, H], [H, -H]])
+    U = H[:, :k] / math.sqrt(m)
+    assert abs(O.incoherence(U) - 1.0) <= 1e-12
+    rng = np.random.default_rng(62)
+    Q = np.linalg.qr(rng.standard_normal((m - 1, k - 1)))[0]
+    U = np.zeros((m, k))
+    U[0, 0] = 1.0
+    U[1:, 1:] = Q
+    assert abs(O.incoherence(U) - m / k) <= 1e-12
+    U = np.linalg.qr(rng.standard_normal((m, k)))[0]
+    assert 1.0 - 1e-12 <= O.incoherence(U) <= m / k + 1e-12
+
+
 ALL_CHECKS = [
+    check_block_stable_rank_closed_forms,
+    check_incoherence_extremes,
     check_frob_closed_form,
     check_scores_sum_to_k,
     check_scores_from_projector,

@@ -122,7 +122,26 @@ def _pick_largest(errs):
     return int(np.argmax(errs))
 
 
+def _stable_rank_spectral_unsquared(V, offsets):
+    V = np.asarray(V, dtype=np.float64)
+    off = np.asarray(offsets, dtype=np.int64)
+    ratios = np.full(len(off) - 1, np.nan)
+    for g in range(len(off) - 1):
+        blk = V[off[g]:off[g + 1], :]
+        fro2 = float(np.sum(blk * blk))
+        if fro2 > 0.0:
+            ratios[g] = fro2 / float(np.linalg.norm(blk, 2))
+    return float(np.nanmin(ratios)), ratios
+
+
+def _incoherence_without_m_over_k(U):
+    U = np.asarray(U, dtype=np.float64)
+    return float(np.max(np.sum(U * U, axis=1)))
+
+
 MUTANTS = {
+    "stable-rank-spectral-unsquared": dict(block_stable_rank=_stable_rank_spectral_unsquared),
+    "incoherence-without-m-over-k": dict(incoherence=_incoherence_without_m_over_k),
     "boost-reuses-draws": dict(trial_draws=lambda draws, i, s: draws[:s]),
     "boost-keeps-largest": dict(boost_pick=_pick_largest),
     "pinv-keeps-smallest": dict(pinv_cut=_pinv_smallest),
