@@ -337,6 +337,90 @@ def boost_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def diag_bench(args):
+    """The diagnostics of Defs. 3 and 4 on the 8192 x 4096 workload's sketched
+    V_k (4096 x 50, 256 blocks of 16) and U_k (8192 x 50).  One step = the
+    block stable rank of every block plus the incoherence."""
+    import numpy as np
+    import torch
+
+    from paper_1703_06065_amd import Context
+    from paper_1703_06065_amd.binding import to_device
+    from workloads import gen
+
+    w = gen.plain_fp32(args.seed)
+    ctx = Context(0)
+    Vk, Uk, _ = ctx.range_finder(to_device(w.A), torch.from_numpy(w.omega).cuda(), w.k, q=w.q, want_u=True)
+    for _ in range(args.warmup):
+        alpha, ratios, steps = ctx.block_stable_rank(Vk, w.offsets, want_steps=True)
+        mu = ctx.incoherence(Uk)
+    torch.cuda.synchronize()
+    ctx.timing_enable(("diag_alpha", "diag_mu"))
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        alpha, ratios, steps = ctx.block_stable_rank(Vk, w.offsets, want_steps=True)
+        mu = ctx.incoherence(Uk)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = ctx.timing_read()
+    ctx.timing_enable(False)
+    el = t1 - t0
+    # FP64 work of the stable-rank kernel as executed: per block the d x d Gram
+    # over the other side, the squaring steps, and the Rayleigh quotient
+    widths = np.diff(w.offsets)
+    flop = 0.0
+    for b, st in zip(widths, steps):
+        d, other = min(int(b), w.k), max(int(b), w.k)
+        flop += 2.0 * d * d * other + st * (2.0 * d ** 3 + 3.0 * d * d) + 2.0 * d * d
+    avg_ms = stages["diag_alpha"][0] / max(stages["diag_alpha"][1], 1)
+    ach = flop / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    peak64 = 78.6
+    roof = {"bound": "alu", "achieved": round(ach, 4), "peak": peak64, "unit": "TFLOP/s",
+            "frac": round(ach / peak64, 5), "traffic": None,
+            "kernel": "k_block_stable_rank (one workgroup per block, FP64 vector)", "launches_per_step": 1,
+            "avg_ms": round(avg_ms, 5), "flop_per_launch": flop,
+            "mu_kernel_ms": round(stages["diag_mu"][0] / max(stages["diag_mu"][1], 1), 5)}
+    out = {
+        "metric": "block-CUR diagnostics evaluations/s (block stable rank + incoherence)",
+        "value": args.steps / el,
+        "unit": "evaluations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (the sketched V_k and U_k of the plain-fp32 workload)",
+        "config": {"workload": f"sketched V_k {w.n}x{w.k} in {w.G} blocks of 16, U_k {w.m}x{w.k}",
+                   "n": w.n, "m": w.m, "k": w.k, "G": w.G},
+        "alpha": alpha, "mu": mu, "max_steps": int(np.max(steps)),
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        from oracle import bcur_oracle as O
+        V64 = Vk.cpu().numpy().astype(np.float64)
+        U64 = Uk.cpu().numpy().astype(np.float64)
+        done, c0 = 0, time.perf_counter()
+        while True:
+            O.block_stable_rank(V64, w.offsets)
+            O.incoherence(U64)
+            done += 1
+            ce = time.perf_counter() - c0
+            if ce > 10.0 or done >= 50:
+                break
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+        except Exception:  # pragma: no cover
+            threads = os.cpu_count()
+        out["cpu_baseline"] = {"value": done / ce, "unit": "evaluations/s", "cores": int(threads), "kind": "oracle",
+                               "sample": f"{done} evaluations of both diagnostics by the FP64 oracle on the same "
+                                         f"V_k and U_k ({ce:.1f} s)"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -344,7 +428,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--mode", choices=["decompose", "serve", "alg1", "boost"], default="decompose")
+    ap.add_argument("--mode", choices=["decompose", "serve", "alg1", "boost", "diag"], default="decompose")
     ap.add_argument("--trials", type=int, default=3, help="boosting: t = ln(1/delta) trials (3 for delta = 0.05)")
     ap.add_argument("--rows", type=int, default=128, help="Algorithm 1: rows drawn (r)")
     ap.add_argument("--kr", type=int, default=0,
@@ -365,6 +449,9 @@ def main():
         return
     if args.mode == "boost":
         boost_bench(args)
+        return
+    if args.mode == "diag":
+        diag_bench(args)
         return
 
     import numpy as np

@@ -187,6 +187,25 @@ bcur_status bcur_fit_columns(bcur_ctx* ctx, const float* A, int64_t m, int64_t n
                              const float* C, int64_t c, int64_t ldc, int32_t refine,
                              float* U, int64_t ldu, double* err, uint32_t* flags);
 
+/* ---- diagnostics (Sec. 3.2) ------------------------------------------------ */
+
+/* Block stable rank (Def. 3) of the slices of V (device n x k, ldv; the
+ * top-k right singular vectors, e.g. from bcur_range_finder): ratios[g] =
+ * ||V^T E_g||_F^2 / ||V^T E_g||_2^2 (host G, or NULL; NaN for a zero slice) and
+ * *alpha = their minimum over the nonzero slices.  FP64 from the exact squares
+ * of the FP32 entries; the spectral norm of each slice comes from the Gram
+ * matrix of its smaller side by repeated squaring to the top eigenspace
+ * (steps: host G, or NULL, receives the squaring steps each block took, at
+ * most 64).  BCUR_E_ARG when min(block width, k) > 64 for some block.
+ * Synchronous. */
+bcur_status bcur_block_stable_rank(bcur_ctx* ctx, const float* V, int64_t n, int64_t k, int64_t ldv,
+                                   const int64_t* offsets, int64_t G, double* ratios, int32_t* steps,
+                                   double* alpha);
+
+/* Column-space incoherence (Def. 4) of U (device m x k, ldu; the top-k left
+ * singular vectors): *mu = (m / k) max_i ||U^T e_i||_2^2, FP64.  Synchronous. */
+bcur_status bcur_incoherence(bcur_ctx* ctx, const float* U, int64_t m, int64_t k, int64_t ldu, double* mu);
+
 /* ---- profiling ---------------------------------------------------------- */
 
 /* Device time per stage, measured with HIP events recorded on the context's
@@ -214,7 +233,9 @@ enum {
     BCUR_STAGE_A1_SVDR = 18,  /* Algorithm 1: R R^T, its eigensolver, V_kr = R^T U_kr Sigma^-1 */
     BCUR_STAGE_A1_PINV = 19,  /* Algorithm 1: W, its Gram matrix, eigensolver, W^+, scaled U */
     BCUR_STAGE_A1_CU = 20,    /* Algorithm 1: P = C U (FP64 accumulation, rounded to FP32) */
-    BCUR_NUM_STAGES = 21
+    BCUR_STAGE_DIAG_ALPHA = 21, /* block stable rank */
+    BCUR_STAGE_DIAG_MU = 22,  /* incoherence */
+    BCUR_NUM_STAGES = 23
 };
 
 /* Stage timing: `on` = 0 turns it off; otherwise bit i of `on` times stage

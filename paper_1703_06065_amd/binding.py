@@ -31,12 +31,12 @@ SYMBOLS = [
     "bcur_gather_columns", "bcur_fit_columns", "bcur_decompose", "bcur_timing_enable", "bcur_timing_read",
     "bcur_sketch_pass", "bcur_release_workspace", "bcur_footprint", "bcur_server_create", "bcur_server_destroy",
     "bcur_server_submit", "bcur_server_poll", "bcur_server_wait", "bcur_server_stats", "bcur_decompose_alg1",
-    "bcur_decompose_boost",
+    "bcur_decompose_boost", "bcur_block_stable_rank", "bcur_incoherence",
 ]
 
 STAGES = ["frob", "rf_AQ", "rf_AtZ", "rf_reduce", "rf_orth", "rf_rr", "scores", "sample", "gather", "fit_H",
           "fit_reduce", "fit_inv", "fit_U", "fit_E", "fit_F", "fit_dU", "rf_cast", "a1_rows", "a1_svdr", "a1_pinv",
-          "a1_cu"]
+          "a1_cu", "diag_alpha", "diag_mu"]
 
 
 class BcurError(RuntimeError):
@@ -129,6 +129,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "bcur_timing_read": (i32, [vp, P(dbl), P(i64)]),
         "bcur_decompose": (i32, [vp, vp, i64, i64, i64, P(i64), i64, P(i64), i64, P(Params), vp,
                                  P(ctypes.c_uint64), P(Result)]),
+        "bcur_block_stable_rank": (i32, [vp, vp, i64, i64, i64, P(i64), i64, P(dbl), P(i32), P(dbl)]),
+        "bcur_incoherence": (i32, [vp, vp, i64, i64, i64, P(dbl)]),
         "bcur_decompose_boost": (i32, [vp, vp, i64, i64, i64, P(i64), i64, P(Params), vp, i64, P(ctypes.c_uint64),
                                        P(Result), P(dbl), P(i64)]),
         "bcur_decompose_alg1": (i32, [vp, vp, i64, i64, i64, P(i64), i64, P(Alg1Params), P(ctypes.c_uint64),
@@ -269,6 +271,27 @@ class Context:
         self._chk(self.lib.bcur_block_scores(self.h, p, n, k, ldv, _ptr(off, ctypes.c_int64), G,
                                              _ptr(out, ctypes.c_double)))
         return out
+
+    def block_stable_rank(self, V, offsets, want_steps: bool = False):
+        """(alpha, per-block ratios) of Def. 3 for the slices of V (n x k), and
+        the squaring steps per block when want_steps."""
+        p, n, k, ldv = _check_dev(V, "V")
+        off = _i64(offsets)
+        G = len(off) - 1
+        ratios = np.empty(G)
+        steps = np.empty(G, dtype=np.int32)
+        alpha = ctypes.c_double()
+        self._chk(self.lib.bcur_block_stable_rank(self.h, p, n, k, ldv, _ptr(off, ctypes.c_int64), G,
+                                                  _ptr(ratios, ctypes.c_double), _ptr(steps, ctypes.c_int32),
+                                                  ctypes.byref(alpha)))
+        return (alpha.value, ratios, steps) if want_steps else (alpha.value, ratios)
+
+    def incoherence(self, U):
+        """mu of Def. 4 for U (m x k)."""
+        p, m, k, ldu = _check_dev(U, "U")
+        mu = ctypes.c_double()
+        self._chk(self.lib.bcur_incoherence(self.h, p, m, k, ldu, ctypes.byref(mu)))
+        return mu.value
 
     def sample_blocks(self, scores, draws, s: int, replace: bool = False):
         sc = np.ascontiguousarray(scores, dtype=np.float64)

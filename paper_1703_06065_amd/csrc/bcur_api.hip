@@ -890,6 +890,67 @@ bcur_status bcur_block_scores(bcur_ctx* ctx, const float* V, int64_t n, int64_t 
     return BCUR_OK;
 }
 
+bcur_status bcur_block_stable_rank(bcur_ctx* ctx, const float* V, int64_t n, int64_t k, int64_t ldv,
+                                   const int64_t* offsets, int64_t G, double* ratios, int32_t* steps,
+                                   double* alpha) {
+    if (!ctx || !V || !alpha) return fail(ctx, BCUR_E_ARG, "null argument");
+    if (n < 1 || k < 1 || ldv < k) return fail(ctx, BCUR_E_ARG, "bad V shape");
+    STCHK(check_offsets(ctx, offsets, G, n, "offsets"));
+    for (int64_t g = 0; g < G; ++g)
+        if (std::min(offsets[g + 1] - offsets[g], k) > kDiagMaxD)
+            return fail(ctx, BCUR_E_ARG, "block %lld: min(width, k) exceeds %d", (long long)g, kDiagMaxD);
+    HIPCHK(hipSetDevice(ctx->device));
+    Arena a;
+    a.take<int64_t>(G + 1);
+    a.take<double>(G);
+    a.take<int>(G);
+    STCHK(reserve(ctx, a.off));
+    Arena b{ctx->ws, 0};
+    int64_t* d_off = b.take<int64_t>(G + 1);
+    double* d_r = b.take<double>(G);
+    int* d_steps = b.take<int>(G);
+    std::vector<double> hr(G);
+    std::vector<int> hs(G);
+    HIPCHK(hipMemcpyAsync(d_off, offsets, (G + 1) * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+    {
+        StageScope ts(ctx, BCUR_STAGE_DIAG_ALPHA);
+        HIPCHK(launch_block_stable_rank(V, k, ldv, d_off, G, d_r, d_steps, ctx->stream));
+    }
+    HIPCHK(hipMemcpyAsync(hr.data(), d_r, G * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(hs.data(), d_steps, G * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (steps)
+        for (int64_t g = 0; g < G; ++g) steps[g] = hs[g];
+    double mn = NAN;
+    for (int64_t g = 0; g < G; ++g)
+        if (!isnan(hr[g]) && !(hr[g] >= mn)) mn = hr[g];
+    if (ratios) memcpy(ratios, hr.data(), G * sizeof(double));
+    *alpha = mn;
+    return BCUR_OK;
+}
+
+bcur_status bcur_incoherence(bcur_ctx* ctx, const float* U, int64_t m, int64_t k, int64_t ldu, double* mu) {
+    if (!ctx || !U || !mu) return fail(ctx, BCUR_E_ARG, "null argument");
+    if (m < 1 || k < 1 || ldu < k) return fail(ctx, BCUR_E_ARG, "bad U shape");
+    HIPCHK(hipSetDevice(ctx->device));
+    Arena a;
+    a.take<double>(row_norm_grid(m));
+    a.take<double>(1);
+    STCHK(reserve(ctx, a.off));
+    Arena b{ctx->ws, 0};
+    double* part = b.take<double>(row_norm_grid(m));
+    double* d_mu = b.take<double>(1);
+    double h = 0.0;
+    {
+        StageScope ts(ctx, BCUR_STAGE_DIAG_MU);
+        HIPCHK(launch_incoherence(U, m, k, ldu, part, d_mu, ctx->stream));
+    }
+    HIPCHK(hipMemcpyAsync(&h, d_mu, sizeof h, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    *mu = h;
+    return BCUR_OK;
+}
+
 bcur_status bcur_sample_blocks(bcur_ctx* ctx, const double* scores, int64_t G, const uint64_t* draws, int64_t s,
                                int32_t replace, int64_t* idx, double* weights, double* margins) {
     if (!ctx || !scores || !draws || !idx) return fail(ctx, BCUR_E_ARG, "null argument");

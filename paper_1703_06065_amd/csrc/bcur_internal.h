@@ -131,6 +131,17 @@ hipError_t launch_dgemm_fd(int64_t M, int64_t N, int64_t K, double alpha, const 
 hipError_t launch_dgemm_df(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda, bool tA,
                            const float* B, int64_t ldb, bool tB, double beta, double* D, int64_t ldd, hipStream_t st);
 
+// ---- diagnostics (k_diag.hip) --------------------------------------------------
+constexpr int kDiagMaxD = 64;   // largest min(block width, k) of the stable-rank kernel
+// ratios[g] = ||X_g||_F^2 / ||X_g||_2^2 for the slice X_g of V (rows d_off[g] .. d_off[g+1]-1),
+// NaN for a zero slice; steps[g] = squaring steps taken; needs min(width, k) <= kDiagMaxD for every block
+hipError_t launch_block_stable_rank(const float* V, int64_t k, int64_t ldv, const int64_t* d_off, int64_t G,
+                                    double* ratios, int* steps, hipStream_t st);
+int row_norm_grid(int64_t m);
+// out[0] = (m / k) max_i sum_c U[i][c]^2; partial: row_norm_grid(m) doubles
+hipError_t launch_incoherence(const float* U, int64_t m, int64_t k, int64_t ldu, double* partial, double* out,
+                              hipStream_t st);
+
 // ---- Algorithm 1 (k_alg1.hip) ------------------------------------------------
 // rows[t] (t < r <= min(m, 128)): the x-th row not yet taken, x = floor(draws[t] (m - t) / 2^64)
 hipError_t launch_uniform_rows(int64_t m, const uint64_t* draws, int64_t r, int64_t* rows, hipStream_t st);

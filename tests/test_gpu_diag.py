@@ -1,0 +1,126 @@
+"""Parity of the diagnostics of Sec. 3.2 on the GPU (through the C ABI) with
+the FP64 oracle: the block stable rank of Def. 3 and the incoherence of
+Def. 4, on the same FP32 inputs.
+
+Tolerances: both sides form exact FP64 squares of FP32 entries; the oracle
+takes the spectral norm of each slice from LAPACK's SVD, the GPU from the
+Gram matrix of the slice's smaller side (FP64, the eigenvalue carries about
+d u64 of relative error) by repeated squaring to the top eigenspace and a
+Rayleigh quotient, so ratios agree to 1e-9 relative; the incoherence is a
+maximum of FP64 row sums: 1e-12 relative.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import bcur_oracle as O
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1703_06065_amd import Context
+    return Context(0)
+
+
+def dev(a):
+    from paper_1703_06065_amd.binding import to_device
+    return to_device(a)
+
+
+def note(*a):
+    print(*a, flush=True)
+
+
+def orthonormal(rows, cols, seed):
+    return np.linalg.qr(np.random.default_rng(seed).standard_normal((rows, cols)))[0].astype(np.float32)
+
+
+def check_stable_rank(ctx, V, off, label=""):
+    alpha, ratios = ctx.block_stable_rank(dev(V), off)
+    a_ref, r_ref = O.block_stable_rank(V.astype(np.float64), off)
+    ok = ~np.isnan(r_ref)
+    assert np.array_equal(np.isnan(ratios), ~ok)
+    rel = np.max(np.abs(ratios[ok] - r_ref[ok]) / r_ref[ok]) if ok.any() else 0.0
+    note(f"stable rank {label}: n={V.shape[0]} k={V.shape[1]} G={len(off) - 1} alpha={alpha:.9g} "
+         f"oracle={a_ref:.9g} max rel={rel:.2e}")
+    assert rel <= 1e-9
+    assert abs(alpha - a_ref) <= 1e-9 * a_ref
+    return alpha, ratios
+
+
+@pytest.mark.parametrize("n,k,b,ragged,seed", [
+    (256, 10, 8, False, 1),      # d = b < k
+    (4096, 50, 16, False, 2),    # the plain-fp32 shape
+    (1000, 20, 100, False, 3),   # d = k < b (Gram of the k side)
+    (777, 33, 9, True, 4),       # ragged widths
+    (300, 64, 64, False, 5),     # d = 64, the largest
+    (50, 7, 1, False, 6),        # one-column blocks: every ratio 1
+])
+def test_stable_rank_shapes(ctx, n, k, b, ragged, seed):
+    V = orthonormal(n, k, seed)
+    off = gen.ragged_blocks(n, -(-n // b), seed) if ragged else gen.contiguous_blocks(n, b)
+    alpha, ratios = check_stable_rank(ctx, V, off, label=f"b={b}")
+    if b == 1:
+        assert np.allclose(ratios, 1.0, rtol=1e-12)
+
+
+def test_stable_rank_planted(ctx):
+    # rank-1 slice (ratio 1), a slice with three equal singular values (ratio 3), a zero slice (NaN)
+    rng = np.random.default_rng(7)
+    n, k = 48, 6
+    W = rng.standard_normal((n, k)).astype(np.float32)
+    W[0:4] = np.outer([1.0, -2.0, 0.5, 4.0], rng.standard_normal(k)).astype(np.float32)
+    P = np.eye(k, dtype=np.float32)[:3]
+    W[4:10] = np.repeat(P, 2, axis=0)
+    W[30:48] = 0.0
+    off = [0, 4, 10, 17, 30, 48]
+    alpha, ratios = check_stable_rank(ctx, W, off, label="planted")
+    assert abs(ratios[0] - 1.0) <= 1e-12 and abs(ratios[1] - 3.0) <= 1e-12 and np.isnan(ratios[4])
+
+
+def test_stable_rank_rejects_wide_blocks(ctx):
+    from paper_1703_06065_amd import binding
+    V = orthonormal(200, 70, 8)
+    with pytest.raises(binding.BcurError) as e:
+        ctx.block_stable_rank(dev(V), [0, 100, 200])
+    assert e.value.status == binding.E_ARG
+
+
+@pytest.mark.parametrize("m,k,seed", [(64, 8, 1), (8192, 50, 2), (1000, 1, 3), (333, 77, 4)])
+def test_incoherence(ctx, m, k, seed):
+    U = orthonormal(m, k, seed)
+    mu = ctx.incoherence(dev(U))
+    ref = O.incoherence(U.astype(np.float64))
+    note(f"incoherence m={m} k={k}: {mu:.12g} oracle {ref:.12g}")
+    assert abs(mu - ref) <= 1e-12 * ref
+
+
+def test_incoherence_extremes(ctx):
+    m, k = 64, 8
+    H = np.array([[1.0]])
+    while H.shape[0] < m:
+        H = np.block([[H, H], [H, -H]])
+    U = (H[:, :k] / math.sqrt(m)).astype(np.float32)   # entries +-1/8: exact in FP32
+    assert abs(ctx.incoherence(dev(U)) - 1.0) <= 1e-12
+    U = np.zeros((m, k), dtype=np.float32)
+    U[0, 0] = 1.0
+    U[1:, 1:] = orthonormal(m - 1, k - 1, 9)
+    assert abs(ctx.incoherence(dev(U)) - m / k) <= 1e-12 * m / k
+
+
+def test_diagnostics_of_the_sketched_subspaces(ctx):
+    """alpha and mu of the plain-fp32 workload's sketched V_k and U_k."""
+    w = gen.plain_fp32(0)
+    Vk, Uk, ritz = ctx.range_finder(dev(w.A), torch.from_numpy(w.omega).cuda(), w.k, q=w.q, want_u=True)
+    V = Vk.cpu().numpy()
+    check_stable_rank(ctx, V, w.offsets, label="sketched V_k")
+    U = Uk.cpu().numpy()
+    mu = ctx.incoherence(Uk)
+    ref = O.incoherence(U.astype(np.float64))
+    note(f"incoherence of the sketched U_k: {mu:.9g} oracle {ref:.9g} (bound [1, m/k = {w.m / w.k:.0f}])")
+    assert abs(mu - ref) <= 1e-12 * ref
