@@ -539,3 +539,36 @@ def boost(A: np.ndarray, offsets: Sequence[int], k: int, s: int, omega: Optional
                U=trials[b]["U"], err=trials[b]["err"], cols=trials[b]["cols"],
                rel_err=trials[b]["err"] / math.sqrt(out["frob2"]) if out["frob2"] > 0 else 0.0)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Blocks of arbitrary column (row) sets
+# ---------------------------------------------------------------------------
+
+def decompose_mapped(A: np.ndarray, offsets: Sequence[int], k: int, s: int, omega: Optional[np.ndarray],
+                     draws: Sequence[int], col_map: Optional[Sequence[int]] = None,
+                     row_map: Optional[Sequence[int]] = None, **kw) -> Dict[str, object]:
+    """Block g holds the columns col_map[offsets[g] .. offsets[g+1]-1] (the E_g
+    of Def. 2 may pick any set of columns; the blocks partition the columns),
+    and likewise row block h the rows row_map[...].  This is the contiguous
+    case on A with its columns (rows) listed in map order: the test matrix
+    rows follow the columns, the chosen positions map back through the maps,
+    U = C^+ A gets its columns back in A's order; errors are unchanged by the
+    reordering (Frobenius norms)."""
+    A64 = np.asarray(A, dtype=np.float64)
+    m, n = A64.shape
+    cm = np.arange(n) if col_map is None else np.asarray(col_map, dtype=np.int64)
+    rm = np.arange(m) if row_map is None else np.asarray(row_map, dtype=np.int64)
+    if sorted(cm.tolist()) != list(range(n)) or sorted(rm.tolist()) != list(range(m)):
+        raise ValueError("the maps must be permutations")
+    Ap = A64[np.ix_(rm, cm)]
+    om = None if omega is None else np.asarray(omega)[cm]
+    out = decompose(Ap, offsets, k, s, om, draws, **kw)
+    out["cols"] = cm[np.asarray(out["cols"], dtype=np.int64)]
+    if "rows" in out:
+        out["rows"] = rm[np.asarray(out["rows"], dtype=np.int64)]
+    inv = np.argsort(cm)
+    out["Vk"] = np.asarray(out["Vk"])[inv]
+    if "U" in out and "rows" not in out:
+        out["U"] = np.asarray(out["U"])[:, inv]
+    return out

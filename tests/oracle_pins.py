@@ -601,6 +601,37 @@ def check_incoherence_extremes(O):
     assert 1.0 - 1e-12 <= O.incoherence(U) <= m / k + 1e-12
 
 
+# --------------------------------------------------------------------------
+# Blocks of arbitrary column sets
+# --------------------------------------------------------------------------
+
+def check_mapped_blocks_follow_def2(O):
+    """With blocks of scattered columns, each score is Def. 2 with E_g picking
+    that block's columns: the sum of the per-column leverages (Def. 1) of the
+    exact V_k over the block's set; choosing every block leaves no error; the
+    identity map reproduces the contiguous case."""
+    w = gen.tiny(4)
+    n = w.n
+    rng = np.random.default_rng(71)
+    cmap = rng.permutation(n)
+    res = O.decompose_mapped(w.A, w.offsets, w.k, w.s, None, w.draws, col_map=cmap, mode="exact")
+    lev = O.column_leverage(O.exact_right_subspace(w.A.astype(np.float64), w.k))
+    want = np.array([lev[cmap[w.offsets[g]:w.offsets[g + 1]]].sum() for g in range(w.G)])
+    assert np.allclose(res["scores"], want, rtol=1e-9, atol=1e-12)
+    cols = res["cols"]
+    sets = [set(cmap[w.offsets[j]:w.offsets[j + 1]].tolist()) for j in res["idx"]]
+    assert set(cols.tolist()) == set().union(*sets) and len(cols) == sum(len(x) for x in sets)
+    # the returned U reproduces A's columns in A's order
+    C = w.A.astype(np.float64)[:, cols]
+    E = w.A.astype(np.float64) - C @ res["U"]
+    assert abs(math.sqrt(float(np.sum(E * E))) - res["err"]) <= 1e-9 * max(res["err"], 1.0)
+    allb = O.decompose_mapped(w.A, w.offsets, w.k, w.G, None, gen.draws_u64(w.G, 72), col_map=cmap, mode="exact")
+    assert allb["err"] <= 1e-9 * math.sqrt(allb["frob2"])
+    ident = O.decompose_mapped(w.A, w.offsets, w.k, w.s, w.omega, w.draws, col_map=np.arange(n), q=w.q)
+    plain = O.decompose(w.A, w.offsets, w.k, w.s, w.omega, w.draws, q=w.q)
+    assert np.array_equal(ident["idx"], plain["idx"]) and abs(ident["err"] - plain["err"]) <= 1e-12 * plain["err"]
+
+
 ALL_CHECKS = [
     check_block_stable_rank_closed_forms,
     check_incoherence_extremes,
@@ -627,6 +658,7 @@ ALL_CHECKS = [
     check_alg1_rank_k,
     check_alg1_all_rows_is_column_fit,
     check_alg1_exact_low_rank,
+    check_mapped_blocks_follow_def2,
     check_boost_law,
     check_boost_keeps_first_minimum,
 ]
