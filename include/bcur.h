@@ -260,6 +260,14 @@ typedef struct bcur_params {
     int32_t refine;     /* refinement steps of the least-squares fit: 0 or 1 */
     int32_t reserved;
     int64_t s_r;        /* row blocks to sample for the row-block variant, 0 = columns only */
+    /* Blocks of arbitrary column (row) sets: host, n (m) entries forming a
+     * permutation, or NULL.  Column block g is then the set of columns
+     * col_map[col_off[g] .. col_off[g+1]-1] (row block h: row_map[row_off[h]
+     * .. row_off[h+1]-1]); the E_g of Def. 2 may pick any columns.  NULL means
+     * the identity (contiguous blocks).  C and R hold the chosen columns and
+     * rows in selection order, each block's in map order. */
+    const int64_t* col_map;
+    const int64_t* row_map;
 } bcur_params;
 
 typedef struct bcur_result {

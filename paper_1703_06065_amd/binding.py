@@ -48,7 +48,8 @@ class BcurError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int64), ("s", ctypes.c_int64), ("l", ctypes.c_int64), ("q", ctypes.c_int64),
                 ("replace", ctypes.c_int32), ("precision", ctypes.c_int32), ("refine", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("s_r", ctypes.c_int64)]
+                ("reserved", ctypes.c_int32), ("s_r", ctypes.c_int64), ("col_map", ctypes.POINTER(ctypes.c_int64)),
+                ("row_map", ctypes.POINTER(ctypes.c_int64))]
 
 
 class Result(ctypes.Structure):
@@ -330,7 +331,7 @@ class Context:
     # -- the whole path ----------------------------------------------------
     def decompose(self, A, offsets, k: int, s: int, omega, draws, q: int = 2, replace: bool = False,
                   refine: int = 1, precision: int = PREC_FP32, want_u: bool = True, row_offsets=None,
-                  s_r: int = 0, U_out=None):
+                  s_r: int = 0, U_out=None, col_map=None, row_map=None):
         p, m, n, lda = _check_dev(A, "A")
         po, on, l, ldo = _check_dev(omega, "omega")
         if on != n or ldo != l:
@@ -340,6 +341,13 @@ class Context:
         dr = np.ascontiguousarray(draws, dtype=np.uint64)
         prm = Params(k=k, s=s, l=l, q=q, replace=int(replace), precision=precision, refine=refine, reserved=0,
                      s_r=s_r)
+        cmap = rmap = None
+        if col_map is not None:
+            cmap = _i64(col_map)
+            prm.col_map = _ptr(cmap, ctypes.c_int64)
+        if row_map is not None:
+            rmap = _i64(row_map)
+            prm.row_map = _ptr(rmap, ctypes.c_int64)
         idx = np.empty(s, dtype=np.int64)
         w = np.empty(s)
         sc = np.empty(G)
@@ -383,7 +391,7 @@ class Context:
 
 
     def decompose_boost(self, A, offsets, k: int, s: int, omega, draws, t: int, q: int = 2, replace: bool = False,
-                        refine: int = 1, precision: int = PREC_FP32, want_u: bool = True, U_out=None):
+                        refine: int = 1, precision: int = PREC_FP32, want_u: bool = True, U_out=None, col_map=None):
         """Boosting: t samplings (draws[i*s:(i+1)*s] for trial i) from one set of
         scores; returns the kept trial's result with every trial's err."""
         p, m, n, lda = _check_dev(A, "A")
@@ -396,6 +404,10 @@ class Context:
         if dr.size < t * s:
             raise ValueError("need t * s draws")
         prm = Params(k=k, s=s, l=l, q=q, replace=int(replace), precision=precision, refine=refine, reserved=0, s_r=0)
+        cmap = None
+        if col_map is not None:
+            cmap = _i64(col_map)
+            prm.col_map = _ptr(cmap, ctypes.c_int64)
         idx = np.empty(s, dtype=np.int64)
         w = np.empty(s)
         sc = np.empty(G)
@@ -488,7 +500,8 @@ class Server:
             pass
 
     def submit(self, A, offsets, k: int, s: int, omega, draws, q: int = 2, replace: bool = False,
-               refine: int = 1, precision: int = PREC_FP32, row_offsets=None, s_r: int = 0, U_out=None):
+               refine: int = 1, precision: int = PREC_FP32, row_offsets=None, s_r: int = 0, U_out=None,
+               col_map=None):
         import torch
         p, m, n, lda = _check_dev(A, "A")
         po, on, l, ldo = _check_dev(omega, "omega")
@@ -505,6 +518,10 @@ class Server:
             rq.row_off, rq.Gr = _ptr(roff, ctypes.c_int64), len(roff) - 1
         rq.params = Params(k=k, s=s, l=l, q=q, replace=int(replace), precision=precision, refine=refine,
                            reserved=0, s_r=s_r if roff is not None else 0)
+        cmap = None   # copied by the server at submission
+        if col_map is not None:
+            cmap = _i64(col_map)
+            rq.params.col_map = _ptr(cmap, ctypes.c_int64)
         rq.omega = po
         rq.draws = _ptr(dr, ctypes.c_uint64)
         if U_out is not None:

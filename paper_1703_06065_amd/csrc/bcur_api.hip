@@ -180,17 +180,31 @@ bcur_status check_offsets(bcur_ctx* ctx, const int64_t* off, int64_t G, int64_t 
     return BCUR_OK;
 }
 
-// Column (or row) indices of the chosen blocks in selection order, each block once.
-std::vector<int64_t> expand_blocks(const int64_t* off, const int64_t* idx, int64_t s) {
+// Column (or row) indices of the chosen blocks in selection order, each block
+// once; with a map, block j holds map[off[j] .. off[j+1]-1].
+std::vector<int64_t> expand_blocks(const int64_t* off, const int64_t* idx, int64_t s, const int64_t* map = nullptr) {
     std::vector<int64_t> out;
     std::vector<int64_t> seen;
     for (int64_t t = 0; t < s; ++t) {
         const int64_t j = idx[t];
         if (std::find(seen.begin(), seen.end(), j) != seen.end()) continue;
         seen.push_back(j);
-        for (int64_t c = off[j]; c < off[j + 1]; ++c) out.push_back(c);
+        for (int64_t c = off[j]; c < off[j + 1]; ++c) out.push_back(map ? map[c] : c);
     }
     return out;
+}
+
+// A block map must be a permutation of 0 .. count-1 (or null).
+bcur_status check_map(bcur_ctx* ctx, const int64_t* map, int64_t count, const char* name) {
+    if (!map) return BCUR_OK;
+    std::vector<char> seen(count, 0);
+    for (int64_t i = 0; i < count; ++i) {
+        if (map[i] < 0 || map[i] >= count || seen[map[i]])
+            return fail(ctx, BCUR_E_ARG, "%s is not a permutation of 0 .. %lld (entry %lld)", name,
+                        (long long)(count - 1), (long long)i);
+        seen[map[i]] = 1;
+    }
+    return BCUR_OK;
 }
 
 // ---- range finder ---------------------------------------------------------
@@ -670,6 +684,14 @@ size_t decompose_ws_bytes(int64_t m, int64_t n, int64_t G, int64_t maxw, int64_t
     a.take<double>(frob2_grid(m, n));
     a.take<float>(n * k);
     if (rowv) a.take<float>(m * k);
+    if (p->col_map) {
+        a.take<int64_t>(n);
+        a.take<float>(n * k);
+    }
+    if (rowv && p->row_map) {
+        a.take<int64_t>(m);
+        a.take<float>(m * k);
+    }
     a.take<float>(m * round4(cmax));
     if (need_ubuf) a.take<float>(cmax * round4(ucols));
     if (rowv) cur_layout(a, cb, m, n, cmax, rmax);
@@ -1074,6 +1096,9 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
         if (!p->replace && s_r > Gr) return fail(ctx, BCUR_E_ARG, "s_r > Gr without replacement");
         if (!res->idx_r) return fail(ctx, BCUR_E_ARG, "idx_r is required for the row-block variant");
     }
+    STCHK(check_map(ctx, p->col_map, n, "col_map"));
+    const int64_t* rmap_h = rowv ? p->row_map : nullptr;
+    STCHK(check_map(ctx, rmap_h, m, "row_map"));
     int64_t maxw = 0, maxh = 0;
     for (int64_t g = 0; g < G; ++g) maxw = std::max(maxw, col_off[g + 1] - col_off[g]);
     if (rowv)
@@ -1093,7 +1118,8 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
     CurBufs cb;
     SampleBufs sc, sr;
     double *d_frob, *d_fpart;
-    float *Vk, *Uk, *Cbuf, *Ubuf;
+    float *Vk, *Uk, *Cbuf, *Ubuf, *Vp = nullptr, *Up = nullptr;
+    int64_t *d_cmap = nullptr, *d_rmap = nullptr;
     auto layout = [&](Arena& a) {
         rf_layout(a, rb, m, n, l, k, bf16);
         sample_layout(a, sc, G, s, cmax);
@@ -1102,6 +1128,14 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
         d_fpart = a.take<double>(frob2_grid(m, n));
         Vk = a.take<float>(n * k);
         Uk = rowv ? a.take<float>(m * k) : nullptr;
+        if (p->col_map) {
+            d_cmap = a.take<int64_t>(n);
+            Vp = a.take<float>(n * k);
+        }
+        if (rmap_h) {
+            d_rmap = a.take<int64_t>(m);
+            Up = a.take<float>(m * k);
+        }
         Cbuf = a.take<float>(m * round4(cmax));
         Ubuf = res->U ? nullptr : a.take<float>(cmax * round4(ucols));
         if (rowv) cur_layout(a, cb, m, n, cmax, rmax);
@@ -1119,7 +1153,8 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
     auto side_bytes = [](int64_t g, int64_t ss, int64_t lm) {
         return 8 * (g + 1) + 8 * ss + (24 * ss + 16 + 8 * g + 16 + 5 * 256) + 8 * lm + 16;
     };
-    const size_t pin_need = side_bytes(G, s, cmax) + (rowv ? side_bytes(Gr, s_r, rmax) : 0) + 16 + 8 * l + 64;
+    const size_t pin_need = side_bytes(G, s, cmax) + (rowv ? side_bytes(Gr, s_r, rmax) : 0) + 16 + 8 * l + 64 +
+                            (p->col_map ? 8 * n + 8 : 0) + (rmap_h ? 8 * m + 8 : 0);
     STCHK(reserve_pinned(ctx, pin_need));
     if (ctx->pinned_busy) HIPCHK(hipStreamSynchronize(st));
     ctx->pinned_busy = true;
@@ -1146,6 +1181,16 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
         HIPCHK(hipMemcpyAsync(sr.dr, h_drr, s_r * sizeof(uint64_t), hipMemcpyHostToDevice, st));
         HIPCHK(hipMemsetAsync(sr.st, 0, 4 * sizeof(int), st));
     }
+    if (p->col_map) {
+        int64_t* h_cm = reinterpret_cast<int64_t*>(ptake(8 * n));
+        memcpy(h_cm, p->col_map, n * sizeof(int64_t));
+        HIPCHK(hipMemcpyAsync(d_cmap, h_cm, n * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    }
+    if (rmap_h) {
+        int64_t* h_rm = reinterpret_cast<int64_t*>(ptake(8 * m));
+        memcpy(h_rm, rmap_h, m * sizeof(int64_t));
+        HIPCHK(hipMemcpyAsync(d_rmap, h_rm, m * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    }
 
     // 1. ||A||_F^2
     {
@@ -1154,11 +1199,14 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
     }
     // 2. sketched top-k right subspace (and left vectors for the row blocks)
     STCHK(range_finder_run(ctx, rb, A, m, n, lda, omega, l, k, q, Vk, Uk, p->precision));
-    // 3. block scores, 4. sampling
+    // 3. block scores (with a map, over the rows of V_k (U_k) listed in map
+    // order, so each block's rows are contiguous), 4. sampling
     {
         StageScope ts(ctx, BCUR_STAGE_SCORES);
-        HIPCHK(launch_block_scores(Vk, k, k, sc.off, G, sc.sc, st));
-        if (rowv) HIPCHK(launch_block_scores(Uk, k, k, sr.off, Gr, sr.sc, st));
+        if (d_cmap) HIPCHK(launch_gather_rows(Vk, k, k, d_cmap, n, Vp, k, st));
+        if (d_rmap) HIPCHK(launch_gather_rows(Uk, k, k, d_rmap, m, Up, k, st));
+        HIPCHK(launch_block_scores(d_cmap ? Vp : Vk, k, k, sc.off, G, sc.sc, st));
+        if (rowv) HIPCHK(launch_block_scores(d_rmap ? Up : Uk, k, k, sr.off, Gr, sr.sc, st));
     }
     {
         StageScope ts(ctx, BCUR_STAGE_SAMPLE);
@@ -1204,13 +1252,13 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
         if (hc.idx[t] < 0 || hc.idx[t] >= G) return fail(ctx, BCUR_E_HIP, "sampler returned an invalid block");
     for (int64_t t = 0; t < s_r; ++t)
         if (hr.idx[t] < 0 || hr.idx[t] >= Gr) return fail(ctx, BCUR_E_HIP, "sampler returned an invalid row block");
-    const std::vector<int64_t> cols = expand_blocks(col_off, hc.idx, s);
+    const std::vector<int64_t> cols = expand_blocks(col_off, hc.idx, s, p->col_map);
     const int64_t c = (int64_t)cols.size();
     memcpy(hc.list, cols.data(), c * sizeof(int64_t));
     HIPCHK(hipMemcpyAsync(sc.list, hc.list, c * sizeof(int64_t), hipMemcpyHostToDevice, st));
     int64_t r = 0;
     if (rowv) {
-        const std::vector<int64_t> rows = expand_blocks(row_off, hr.idx, s_r);
+        const std::vector<int64_t> rows = expand_blocks(row_off, hr.idx, s_r, rmap_h);
         r = (int64_t)rows.size();
         memcpy(hr.list, rows.data(), r * sizeof(int64_t));
         HIPCHK(hipMemcpyAsync(sr.list, hr.list, r * sizeof(int64_t), hipMemcpyHostToDevice, st));
@@ -1289,6 +1337,7 @@ bcur_status bcur_decompose_boost(bcur_ctx* ctx, const float* A, int64_t m, int64
         return fail(ctx, BCUR_E_ARG, "unknown precision %d", p->precision);
     if (p->refine < 0 || p->refine > 1) return fail(ctx, BCUR_E_ARG, "refine must be 0 or 1");
     if (p->s_r != 0) return fail(ctx, BCUR_E_ARG, "boosting covers the column-block path only (s_r = 0)");
+    STCHK(check_map(ctx, p->col_map, n, "col_map"));
     const bool bf16 = p->precision == BCUR_PREC_BF16;
     int64_t maxw = 0;
     for (int64_t g = 0; g < G; ++g) maxw = std::max(maxw, col_off[g + 1] - col_off[g]);
@@ -1308,7 +1357,8 @@ bcur_status bcur_decompose_boost(bcur_ctx* ctx, const float* A, int64_t m, int64
     int64_t *d_off, *d_idx, *d_list;
     uint64_t *d_dr, *d_qb, *d_pr;
     int* d_st;
-    float *Vk, *Call, *Hall, *hpart, *Ua, *Ub;
+    float *Vk, *Call, *Hall, *hpart, *Ua, *Ub, *Vp = nullptr;
+    int64_t* d_cmap = nullptr;
     // split-K partials of the all-trials H GEMM: the largest over the column
     // counts it can have (multiples of 4 up to ctot_max)
     size_t hpart_floats = 4;
@@ -1330,6 +1380,10 @@ bcur_status bcur_decompose_boost(bcur_ctx* ctx, const float* A, int64_t m, int64
         d_frob = a.take<double>(2);
         d_fpart = a.take<double>(frob2_grid(m, n));
         Vk = a.take<float>(n * k);
+        if (p->col_map) {
+            d_cmap = a.take<int64_t>(n);
+            Vp = a.take<float>(n * k);
+        }
         Call = a.take<float>(m * ctot_max);
         Hall = a.take<float>(ctot_max * np);
         hpart = a.take<float>(hpart_floats);
@@ -1346,7 +1400,7 @@ bcur_status bcur_decompose_boost(bcur_ctx* ctx, const float* A, int64_t m, int64
     }
     const char* span0 = reinterpret_cast<const char*>(d_idx);
     const size_t span = (size_t)(reinterpret_cast<const char*>(d_frob + 1) - span0);
-    const size_t pin_need = 8 * (G + 1) + 8 * t * s + 8 * ctot_max + span + 8 * l + 64;
+    const size_t pin_need = 8 * (G + 1) + 8 * t * s + 8 * ctot_max + span + 8 * l + 64 + (p->col_map ? 8 * n : 0);
     STCHK(reserve_pinned(ctx, pin_need));
     if (ctx->pinned_busy) HIPCHK(hipStreamSynchronize(st));
     ctx->pinned_busy = true;
@@ -1368,6 +1422,11 @@ bcur_status bcur_decompose_boost(bcur_ctx* ctx, const float* A, int64_t m, int64
     HIPCHK(hipMemcpyAsync(d_off, h_off, (G + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(d_dr, h_dr, t * s * sizeof(uint64_t), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemsetAsync(d_st, 0, 4 * t * sizeof(int), st));
+    if (p->col_map) {
+        int64_t* h_cm = reinterpret_cast<int64_t*>(ptake(8 * n));
+        memcpy(h_cm, p->col_map, n * sizeof(int64_t));
+        HIPCHK(hipMemcpyAsync(d_cmap, h_cm, n * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    }
     {
         StageScope ts(ctx, BCUR_STAGE_FROB);
         HIPCHK(launch_frob2(A, m, n, lda, d_fpart, frob2_grid(m, n), d_frob, st));
@@ -1376,7 +1435,8 @@ bcur_status bcur_decompose_boost(bcur_ctx* ctx, const float* A, int64_t m, int64
     STCHK(range_finder_run(ctx, rb, A, m, n, lda, omega, l, k, q, Vk, nullptr, p->precision));
     {
         StageScope ts(ctx, BCUR_STAGE_SCORES);
-        HIPCHK(launch_block_scores(Vk, k, k, d_off, G, d_sc, st));
+        if (d_cmap) HIPCHK(launch_gather_rows(Vk, k, k, d_cmap, n, Vp, k, st));
+        HIPCHK(launch_block_scores(d_cmap ? Vp : Vk, k, k, d_off, G, d_sc, st));
     }
     {
         StageScope ts(ctx, BCUR_STAGE_SAMPLE);
@@ -1407,7 +1467,7 @@ bcur_status bcur_decompose_boost(bcur_ctx* ctx, const float* A, int64_t m, int64
     std::vector<int64_t> seg_off(t), seg_c(t);
     int64_t ctot = 0;
     for (int64_t i = 0; i < t; ++i) {
-        const std::vector<int64_t> cols = expand_blocks(col_off, hidx + i * s, s);
+        const std::vector<int64_t> cols = expand_blocks(col_off, hidx + i * s, s, p->col_map);
         const int64_t ci = (int64_t)cols.size();
         seg_off[i] = ctot;
         seg_c[i] = ci;

@@ -38,8 +38,8 @@ struct Ticket {
     // request (host arrays copied, device pointers borrowed)
     const float* A = nullptr;
     int64_t m = 0, n = 0, lda = 0;
-    std::vector<int64_t> col_off, row_off;
-    bcur_params params{};
+    std::vector<int64_t> col_off, row_off, col_map, row_map;
+    bcur_params params{};   // its map pointers point into col_map / row_map
     const float* omega = nullptr;
     std::vector<uint64_t> draws;
     float* U = nullptr;
@@ -272,6 +272,10 @@ bcur_status bcur_server_submit(bcur_server* srv, const bcur_request* rq, uint64_
     t->col_off.assign(rq->col_off, rq->col_off + rq->G + 1);
     if (rowv) t->row_off.assign(rq->row_off, rq->row_off + rq->Gr + 1);
     t->params = p;
+    if (p.col_map) t->col_map.assign(p.col_map, p.col_map + rq->n);
+    if (rowv && p.row_map) t->row_map.assign(p.row_map, p.row_map + rq->m);
+    t->params.col_map = p.col_map ? t->col_map.data() : nullptr;
+    t->params.row_map = rowv && p.row_map ? t->row_map.data() : nullptr;
     t->omega = rq->omega;
     t->draws.assign(rq->draws, rq->draws + p.s + (rowv ? p.s_r : 0));
     t->U = rq->U;
