@@ -524,7 +524,7 @@ def main():
                                f"q={w.q}, l={w.l}", "m": w.m, "n": w.n, "G": w.G, "k": w.k, "s": w.s, "q": w.q,
                    "l": w.l, "c": c, "refine": 1},
         "tflops_total": round((rf_flops + fit_flops) * args.steps / el / 1e12, 3),
-        "stage_ms_per_step": {k: round(v[0] / nb, 5) for k, v in breakdown.items()},
+        "stage_ms_per_step": {k: round(v[0] / nb, 5) for k, v in breakdown.items() if v[1]},
         "err": res["err"], "rel_err": res["rel_err"], "rr_sweeps": res["rr_sweeps"],
         "roofline": roof,
     }

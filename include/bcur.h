@@ -388,6 +388,17 @@ bcur_status bcur_decompose_alg1(bcur_ctx* ctx, const float* A, int64_t m, int64_
                                 const int64_t* col_off, int64_t G, const bcur_alg1_params* params,
                                 const uint64_t* draws, bcur_alg1_result* result);
 
+/* Boosting as Thm. 2 states it (Sec. 3.3): Algorithm 1 run t times with
+ * independent draws, trial i taking words i(r+s) .. i(r+s)+r+s-1 of draws
+ * (host, t(r+s) words: its r row draws, then its s column draws); result
+ * describes the run of smallest err (the first on ties) and receives its
+ * core; errs (host, t) every run's err; *best (may be NULL) its index.
+ * 1 <= t <= 64.  Synchronous. */
+bcur_status bcur_decompose_alg1_boost(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda,
+                                      const int64_t* col_off, int64_t G, const bcur_alg1_params* params,
+                                      int64_t t, const uint64_t* draws, bcur_alg1_result* result, double* errs,
+                                      int64_t* best);
+
 /* ---- serving: continuous batching of decompositions ------------------------
  *
  * A server runs up to `max_slots` decompositions at once, each in its own

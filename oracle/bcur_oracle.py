@@ -572,3 +572,18 @@ def decompose_mapped(A: np.ndarray, offsets: Sequence[int], k: int, s: int, omeg
     if "U" in out and "rows" not in out:
         out["U"] = np.asarray(out["U"])[:, inv]
     return out
+
+
+def alg1_boost(A: np.ndarray, offsets: Sequence[int], r: int, s: int, draws: Sequence[int], t: int,
+               kr: Optional[int] = None, rank_k: int = 0, replace: bool = False) -> Dict[str, object]:
+    """Boosting as Thm. 2 states it (Sec. 3.3): Algorithm 1 run t times with
+    independent draws (trial i takes words i(r+s) .. i(r+s)+r+s-1: its r row
+    draws, then its s column draws), the run of smallest error kept (the first
+    on ties)."""
+    runs = [alg1(A, offsets, r, s, None, trial_draws(draws, i, r + s), kr=kr, rank_k=rank_k, replace=replace)
+            for i in range(t)]
+    errs = [run["err"] for run in runs]
+    b = boost_pick(errs)
+    out = dict(runs[b])
+    out.update(trials=runs, errs=np.array(errs), best=b)
+    return out

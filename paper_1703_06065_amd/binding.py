@@ -31,7 +31,7 @@ SYMBOLS = [
     "bcur_gather_columns", "bcur_fit_columns", "bcur_decompose", "bcur_timing_enable", "bcur_timing_read",
     "bcur_sketch_pass", "bcur_release_workspace", "bcur_footprint", "bcur_server_create", "bcur_server_destroy",
     "bcur_server_submit", "bcur_server_poll", "bcur_server_wait", "bcur_server_stats", "bcur_decompose_alg1",
-    "bcur_decompose_boost", "bcur_block_stable_rank", "bcur_incoherence",
+    "bcur_decompose_boost", "bcur_block_stable_rank", "bcur_incoherence", "bcur_decompose_alg1_boost",
 ]
 
 STAGES = ["frob", "rf_AQ", "rf_AtZ", "rf_reduce", "rf_orth", "rf_rr", "scores", "sample", "gather", "fit_H",
@@ -134,6 +134,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "bcur_incoherence": (i32, [vp, vp, i64, i64, i64, P(dbl)]),
         "bcur_decompose_boost": (i32, [vp, vp, i64, i64, i64, P(i64), i64, P(Params), vp, i64, P(ctypes.c_uint64),
                                        P(Result), P(dbl), P(i64)]),
+        "bcur_decompose_alg1_boost": (i32, [vp, vp, i64, i64, i64, P(i64), i64, P(Alg1Params), i64,
+                                            P(ctypes.c_uint64), P(Alg1Result), P(dbl), P(i64)]),
         "bcur_decompose_alg1": (i32, [vp, vp, i64, i64, i64, P(i64), i64, P(Alg1Params), P(ctypes.c_uint64),
                                       P(Alg1Result)]),
     }
@@ -437,10 +439,12 @@ class Context:
         return out
 
     def decompose_alg1(self, A, offsets, r: int, s: int, draws, kr: Optional[int] = None, rank_k: int = 0,
-                       replace: bool = False, want_u: bool = True, U_out=None, pinv_eig: bool = False):
+                       replace: bool = False, want_u: bool = True, U_out=None, pinv_eig: bool = False,
+                       trials: Optional[int] = None):
         """Algorithm 1 (uniform rows, U = W^+ or U_k = (W_k)^+).  draws: r row
-        words then s column words.  U is the c x r core for the unscaled
-        factors: A ~ A[:, cols] U A[rows, :]."""
+        words then s column words (per trial when `trials` boosts over that many
+        runs, keeping the smallest error).  U is the c x r core for the
+        unscaled factors: A ~ A[:, cols] U A[rows, :]."""
         p, m, n, lda = _check_dev(A, "A")
         off = _i64(offsets)
         G = len(off) - 1
@@ -448,6 +452,7 @@ class Context:
         dr = np.ascontiguousarray(draws, dtype=np.uint64)
         if dr.size < r + s:
             raise ValueError("need r + s draws")
+        errs = best = None
         prm = Alg1Params(r=r, kr=kr, s=s, rank_k=rank_k, replace=int(replace), pinv_eig=int(pinv_eig))
         rows = np.empty(r, dtype=np.int64)
         idx = np.empty(s, dtype=np.int64)
@@ -465,11 +470,24 @@ class Context:
             res.U = U.data_ptr()
             res.ldu = U.stride(0)
             res.u_rows_cap = U.shape[0]
-        self._chk(self.lib.bcur_decompose_alg1(self.h, p, m, n, lda, _ptr(off, ctypes.c_int64), G,
-                                               ctypes.byref(prm), _ptr(dr, ctypes.c_uint64), ctypes.byref(res)))
+        if trials is None:
+            self._chk(self.lib.bcur_decompose_alg1(self.h, p, m, n, lda, _ptr(off, ctypes.c_int64), G,
+                                                   ctypes.byref(prm), _ptr(dr, ctypes.c_uint64), ctypes.byref(res)))
+        else:
+            if dr.size < trials * (r + s):
+                raise ValueError("need trials * (r + s) draws")
+            errs = np.empty(trials)
+            best = ctypes.c_int64()
+            self._chk(self.lib.bcur_decompose_alg1_boost(self.h, p, m, n, lda, _ptr(off, ctypes.c_int64), G,
+                                                         ctypes.byref(prm), trials, _ptr(dr, ctypes.c_uint64),
+                                                         ctypes.byref(res), _ptr(errs, ctypes.c_double),
+                                                         ctypes.byref(best)))
         out = {"rows": rows, "idx": idx, "weights": w, "scores": sc, "c": res.c, "rank_w": res.rank_w,
                "frob2": res.frob2, "err": res.err, "rel_err": res.rel_err, "min_margin": res.min_margin,
                "flags": res.flags, "sweeps": res.sweeps}
+        if trials is not None:
+            out["errs"] = errs
+            out["best"] = best.value
         if U is not None:
             out["U"] = U[:res.c]
         return out

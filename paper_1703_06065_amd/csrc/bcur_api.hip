@@ -1529,9 +1529,12 @@ bcur_status bcur_decompose_boost(bcur_ctx* ctx, const float* A, int64_t m, int64
     return BCUR_OK;
 }
 
-bcur_status bcur_decompose_alg1(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda,
-                                const int64_t* col_off, int64_t G, const bcur_alg1_params* p, const uint64_t* draws,
-                                bcur_alg1_result* res) {
+// One run of Algorithm 1.  The workspace layout ends with ntail buffers of
+// cmax x round4(r) floats; with tail_slot >= 0 the core goes to that buffer
+// (ld round4(r)) instead of res->U, and *tail returns the first buffer.
+static bcur_status alg1_impl(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda,
+                             const int64_t* col_off, int64_t G, const bcur_alg1_params* p, const uint64_t* draws,
+                             bcur_alg1_result* res, int ntail, int tail_slot, float** tail) {
     if (!ctx) return BCUR_E_ARG;
     if (!p || !res || !draws || !res->rows || !res->idx) return fail(ctx, BCUR_E_ARG, "null argument");
     STCHK(check_matrix(ctx, A, m, n, lda, "A"));
@@ -1593,7 +1596,7 @@ bcur_status bcur_decompose_alg1(bcur_ctx* ctx, const float* A, int64_t m, int64_
         Vw = a.take<double>(tmax * tmax);
         Mw = a.take<double>(tmax * tmax);
         jwsW = a.take<double>((jacobi_ws_bytes(tmax) + 7) / 8);
-        Ubuf = res->U ? nullptr : a.take<float>(cmax * rp);
+        Ubuf = ntail > 0 ? a.take<float>((size_t)ntail * cmax * rp) : nullptr;
         P64 = a.take<double>(m * r);
         P32 = a.take<float>(m * rp);
         wsE = a.take<double>(nwsE);
@@ -1727,8 +1730,9 @@ bcur_status bcur_decompose_alg1(bcur_ctx* ctx, const float* A, int64_t m, int64_
     // truncation is asked for; otherwise (decided on the device) M from the
     // eigensystem of G with the cutoff and the rank-k truncation.
     // infoW: [0..1] eigensolver, [2] Cholesky, [3] 1 = eigensystem used, [4..5] kept counts
-    float* U = res->U ? res->U : Ubuf;
-    const int64_t ldu = res->U ? res->ldu : rp;
+    if (tail) *tail = Ubuf;
+    float* U = tail_slot >= 0 ? Ubuf + (size_t)tail_slot * cmax * rp : res->U;
+    const int64_t ldu = tail_slot >= 0 ? rp : res->ldu;
     {
         StageScope ts(ctx, BCUR_STAGE_A1_PINV);
         const bool wide = c > r;   // X = W^T
@@ -1787,6 +1791,75 @@ bcur_status bcur_decompose_alg1(bcur_ctx* ctx, const float* A, int64_t m, int64_
     res->min_margin = mm;
     res->flags = fl;
     res->sweeps = (uint32_t)hinfoW[0];
+    return BCUR_OK;
+}
+
+
+bcur_status bcur_decompose_alg1(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda,
+                                const int64_t* col_off, int64_t G, const bcur_alg1_params* p, const uint64_t* draws,
+                                bcur_alg1_result* res) {
+    if (!ctx) return BCUR_E_ARG;
+    if (!res) return fail(ctx, BCUR_E_ARG, "null argument");
+    return alg1_impl(ctx, A, m, n, lda, col_off, G, p, draws, res, res->U ? 0 : 1, res->U ? -1 : 0, nullptr);
+}
+
+bcur_status bcur_decompose_alg1_boost(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda,
+                                      const int64_t* col_off, int64_t G, const bcur_alg1_params* p, int64_t t,
+                                      const uint64_t* draws, bcur_alg1_result* res, double* errs,
+                                      int64_t* best_out) {
+    if (!ctx) return BCUR_E_ARG;
+    if (!p || !res || !draws || !res->rows || !res->idx || !errs) return fail(ctx, BCUR_E_ARG, "null argument");
+    if (t < 1 || t > kMaxTrials) return fail(ctx, BCUR_E_ARG, "need 1 <= t <= %lld", (long long)kMaxTrials);
+    STCHK(check_offsets(ctx, col_off, G, n, "col_off"));
+    const int64_t r = p->r, s = p->s;
+    if (r < 1 || s < 1) return fail(ctx, BCUR_E_ARG, "need r >= 1 and s >= 1");
+    int64_t maxw = 0;
+    for (int64_t g = 0; g < G; ++g) maxw = std::max(maxw, col_off[g + 1] - col_off[g]);
+    const int64_t cmax = std::min(s * maxw, n), rp = round4(r);
+    if (res->U && (res->ldu < r || (res->ldu & 3) || !aligned16(res->U) || res->u_rows_cap < cmax))
+        return fail(ctx, BCUR_E_ARG, "U needs ldu >= %lld (a multiple of 4, 16-byte aligned) and %lld rows",
+                    (long long)r, (long long)cmax);
+    // every trial keeps its host results; the cores alternate between two
+    // workspace buffers so the best one so far is never overwritten
+    std::vector<int64_t> rows((size_t)t * r), idx((size_t)t * s);
+    std::vector<double> w((size_t)t * s), sc((size_t)t * G);
+    std::vector<bcur_alg1_result> runs(t);
+    int64_t best = -1;
+    int best_slot = 1;
+    float* tail = nullptr;
+    for (int64_t i = 0; i < t; ++i) {
+        bcur_alg1_result& ri = runs[i];
+        ri = bcur_alg1_result{};
+        ri.rows = rows.data() + i * r;
+        ri.idx = idx.data() + i * s;
+        ri.weights = w.data() + i * s;
+        ri.scores = sc.data() + i * G;
+        const int slot = best_slot ^ 1;
+        STCHK(alg1_impl(ctx, A, m, n, lda, col_off, G, p, draws + i * (r + s), &ri, 2, slot, &tail));
+        errs[i] = ri.err;
+        if (best < 0 || ri.err < runs[best].err) {
+            best = i;
+            best_slot = slot;
+        }
+    }
+    const bcur_alg1_result& rb = runs[best];
+    if (res->U)
+        HIPCHK(hipMemcpy2DAsync(res->U, res->ldu * sizeof(float), tail + (size_t)best_slot * cmax * rp,
+                                rp * sizeof(float), r * sizeof(float), rb.c, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    memcpy(res->rows, rb.rows, r * sizeof(int64_t));
+    memcpy(res->idx, rb.idx, s * sizeof(int64_t));
+    if (res->weights) memcpy(res->weights, rb.weights, s * sizeof(double));
+    if (res->scores) memcpy(res->scores, rb.scores, G * sizeof(double));
+    res->c = rb.c;
+    res->rank_w = rb.rank_w;
+    res->frob2 = rb.frob2;
+    res->err = rb.err;
+    res->rel_err = rb.rel_err;
+    res->min_margin = rb.min_margin;
+    res->flags = rb.flags;
+    res->sweeps = rb.sweeps;
+    if (best_out) *best_out = best;
     return BCUR_OK;
 }
 

@@ -632,6 +632,19 @@ def check_mapped_blocks_follow_def2(O):
     assert np.array_equal(ident["idx"], plain["idx"]) and abs(ident["err"] - plain["err"]) <= 1e-12 * plain["err"]
 
 
+def check_alg1_boost_keeps_first_minimum(O):
+    """Boosted Algorithm 1: every trial is the single run with its own r + s
+    draws, and the kept one is the first of smallest error."""
+    A = gen.lowrank_haar(200, 96, 1.0 / np.arange(1, 13), 1e-2, 81)
+    off = gen.contiguous_blocks(96, 8)
+    r, s, t = 24, 3, 4
+    dr = gen.draws_u64(t * (r + s), 81)
+    res = O.alg1_boost(A, off, r, s, dr, t, kr=8)
+    single = [O.alg1(A, off, r, s, None, dr[i * (r + s):(i + 1) * (r + s)], kr=8)["err"] for i in range(t)]
+    assert np.allclose(res["errs"], single, rtol=1e-12)
+    assert res["best"] == int(np.argmin(single)) and res["err"] == min(single)
+
+
 ALL_CHECKS = [
     check_block_stable_rank_closed_forms,
     check_incoherence_extremes,
@@ -661,4 +674,5 @@ ALL_CHECKS = [
     check_mapped_blocks_follow_def2,
     check_boost_law,
     check_boost_keeps_first_minimum,
+    check_alg1_boost_keeps_first_minimum,
 ]

@@ -233,3 +233,31 @@ def test_alg1_plain_fp32_full_size(ctx):
     """The 8192 x 4096 workload (256 blocks of 16), r = 128 rows, kr = 50, s = 16."""
     w = gen.plain_fp32(0)
     check_alg1(ctx, w.A, w.offsets, 128, w.s, gen.draws_u64(128 + w.s, 1), kr=w.k, label="plain-fp32 full size")
+
+
+@pytest.mark.parametrize("t", [1, 3])
+def test_alg1_boost(ctx, t):
+    """Boosted Algorithm 1: every run's err and the kept run against the
+    oracle's, the kept core's own residual."""
+    A = lowrank(600, 320, 30, 1e-2, 18)
+    off = gen.contiguous_blocks(320, 8)
+    r, s, kr = 48, 6, 20
+    dr = gen.draws_u64(t * (r + s), 18)
+    res = ctx.decompose_alg1(dev(A), off, r, s, dr, kr=kr, trials=t)
+    ref = O.alg1_boost(A, off, r, s, dr, t, kr=kr)
+    frob2 = ref["frob2"]
+    note(f"alg1 boost t={t}: errs gpu={res['errs']} oracle={ref['errs']} best gpu={res['best']} oracle={ref['best']}")
+    for i, run in enumerate(ref["trials"]):
+        # every run's draws are identical on both sides; its blocks agree when the margins allow
+        if run["margins"].min() > 1e-3:
+            assert abs(res["errs"][i] - run["err"]) <= 1e-5 * run["err"] + 16 * U32 * math.sqrt(frob2)
+    errs = np.asarray(ref["errs"])
+    others = np.delete(errs, ref["best"])
+    if others.size == 0 or np.min(others) - errs[ref["best"]] > 1e-4 * errs.max():
+        assert res["best"] == ref["best"]
+        assert np.array_equal(res["rows"], ref["rows"]) and np.array_equal(res["idx"], ref["idx"])
+    assert res["err"] == res["errs"][res["best"]] == np.min(res["errs"])
+    cols = O.selected_columns(off, res["idx"])
+    Ug = res["U"][: res["c"], :r].cpu().numpy().astype(np.float64)
+    e_own = own_err(A, cols, res["rows"], Ug)
+    assert abs(res["err"] - e_own) <= err_tol(e_own, frob2)
