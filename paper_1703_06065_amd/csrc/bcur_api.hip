@@ -270,13 +270,16 @@ bcur_status gemm_timed(bcur_ctx* ctx, int stage, int rstage, const GemmPlan& p, 
 
 // One Cholesky QR pass: out = X R^-1 with R^T R = X^T X (+ a tiny shift),
 // Gram in FP64, factor and inverse in FP64, product accumulated in FP64.
-bcur_status cholqr(bcur_ctx* ctx, const RFBufs& b, const float* X, int64_t rows, int64_t l, float* out) {
+// gate (device, or null): the pass runs only when *gate != 0; need2 (device,
+// or null) receives whether a second pass would still improve orthogonality.
+bcur_status cholqr(bcur_ctx* ctx, const RFBufs& b, const float* X, int64_t rows, int64_t l, float* out,
+                   const int* gate = nullptr, int* need2 = nullptr) {
     const int64_t lp = round4(l);
     const int w = gram_wgs(rows);
-    HIPCHK(launch_gram64(X, rows, l, lp, b.gpart, w, ctx->stream));
-    HIPCHK(launch_gram_reduce(b.gpart, w, l, b.T, ctx->stream));
-    HIPCHK(launch_chol_rinv_small(b.T, l, b.Rinv, b.info, ctx->stream));
-    HIPCHK(launch_apply_small(X, rows, l, lp, b.Rinv, l, l, out, lp, ctx->stream));
+    HIPCHK(launch_gram64(X, rows, l, lp, b.gpart, w, ctx->stream, gate));
+    HIPCHK(launch_gram_reduce(b.gpart, w, l, b.T, ctx->stream, gate));
+    HIPCHK(launch_chol_rinv_small(b.T, l, b.Rinv, b.info, ctx->stream, gate, need2));
+    HIPCHK(launch_apply_small(X, rows, l, lp, b.Rinv, l, l, out, lp, ctx->stream, gate));
     return BCUR_OK;
 }
 
@@ -348,10 +351,12 @@ bcur_status range_finder_run(bcur_ctx* ctx, const RFBufs& b, const float* A, int
         // Intermediate bases only need to be well conditioned: one Cholesky QR
         // pass (FP64 Gram and factor) leaves an orthogonality error of about
         // 2^-52 cond(Y)^2 + 2^-24.  The basis handed to Rayleigh-Ritz gets a
-        // second pass (Cholesky QR2), which brings it to FP32 orthonormality.
+        // second pass (Cholesky QR2) unless the first factor certifies that
+        // its error is already below 2^-26 (decided on the device: the second
+        // pass's kernels return at once).
         StageScope ts(ctx, BCUR_STAGE_RF_ORTH);
-        STCHK(cholqr(ctx, b, b.Y, n, l, b.Q));
-        if (it == q) STCHK(cholqr(ctx, b, b.Q, n, l, b.Q));
+        STCHK(cholqr(ctx, b, b.Y, n, l, b.Q, nullptr, it == q ? b.info + 1 : nullptr));
+        if (it == q) STCHK(cholqr(ctx, b, b.Q, n, l, b.Q, b.info + 1));
     }
     STCHK(gemm_timed(ctx, BCUR_STAGE_RF_AQ, BCUR_STAGE_RF_REDUCE, pz, m, l, n, false, A, lda, b.Q, lp, b.Z, lp,
                      b.part));

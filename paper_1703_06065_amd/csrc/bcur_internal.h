@@ -83,19 +83,25 @@ hipError_t launch_bgemm_nt(const GemmPlan& p, int64_t M, int64_t N, int64_t K, c
 // ---- small dense FP64 kernels (k_small.hip) --------------------------------
 int gram_wgs(int64_t rows);
 // partial[w] (l x l) = sum over the w-th row range of X^T X, FP64 accumulation (wgs partials).
+// With gate non-null the Gram, reduce, factor and apply kernels return at once when *gate == 0.
 hipError_t launch_gram64(const float* X, int64_t rows, int64_t l, int64_t ldx, double* partial, int wgs,
-                         hipStream_t st);
+                         hipStream_t st, const int* gate = nullptr);
 // the same for an FP64 X
 hipError_t launch_gram64(const double* X, int64_t rows, int64_t l, int64_t ldx, double* partial, int wgs,
                          hipStream_t st);
 // T (l x l) = sum of the wgs partials in a fixed order, many workgroups.
-hipError_t launch_gram_reduce(const double* partial, int parts, int64_t l, double* T, hipStream_t st);
+hipError_t launch_gram_reduce(const double* partial, int parts, int64_t l, double* T, hipStream_t st,
+                              const int* gate = nullptr);
 // T = sum of the partials; T + shift I = R^T R (R upper), Rinv = R^-1 (l x l upper),
 // shift = l 2^-52 trace(T).  info[0] |= 1 when the smallest pivot was below 10 * shift.
-hipError_t launch_chol_rinv_small(const double* T, int64_t l, double* Rinv, int* info, hipStream_t st);
+// need2 (or null): 0 when ||T||_F ||Rinv||_F^2 < 2^26 and no pivot was small (one Cholesky QR
+// pass then leaves an orthogonality error below 2^-26), else 1.
+hipError_t launch_chol_rinv_small(const double* T, int64_t l, double* Rinv, int* info, hipStream_t st,
+                                  const int* gate = nullptr, int* need2 = nullptr);
 // out (rows x lo, FP32, ldo) = X (rows x li, FP32, ldx) * M (li x lo, FP64, ldm)
 hipError_t launch_apply_small(const float* X, int64_t rows, int64_t li, int64_t ldx, const double* M,
-                              int64_t lo, int64_t ldm, float* out, int64_t ldo, hipStream_t st);
+                              int64_t lo, int64_t ldm, float* out, int64_t ldo, hipStream_t st,
+                              const int* gate = nullptr);
 // Symmetric eigensolver (cyclic Jacobi) of the l x l matrix T (FP64):
 // lam (l, descending), Wk (l x k, FP64), Wks = Wk diag(1/sqrt(lam)) (l x k) or null;
 // info[0] = sweeps, info[1] = 1 when converged.  ws: jacobi_ws_bytes(l) bytes.

@@ -18,8 +18,10 @@ constexpr int kRC = 32;        // rows per LDS chunk
 // exact in FP64 and every entry sums its rows in order, so T is symmetric bitwise.
 template <typename T>
 __global__ __launch_bounds__(1024) void k_gram64(const T* __restrict__ X, int64_t rows, int l, int64_t ldx,
-                                                 int64_t rows_per_wg, double* __restrict__ partial) {
+                                                 int64_t rows_per_wg, double* __restrict__ partial,
+                                                 const int* __restrict__ gate) {
     __shared__ __attribute__((aligned(16))) T xs[kRC * kMaxL];
+    if (gate && *gate == 0) return;
     const int lp = (l + 3) & ~3, TT = lp / 4;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int ti = tid / TT, tj = tid % TT;
@@ -73,8 +75,9 @@ __global__ __launch_bounds__(1024) void k_gram64(const T* __restrict__ X, int64_
 // for one entry with up to 16 loads in flight, and the 4 group sums are added
 // in group order.
 __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ partial, int parts, int64_t ll,
-                                                     double* __restrict__ T) {
+                                                     double* __restrict__ T, const int* __restrict__ gate) {
     __shared__ double sg[4][64];
+    if (gate && *gate == 0) return;
     const int tid = threadIdx.x, g = tid >> 6, el = tid & 63;
     const int64_t e = (int64_t)blockIdx.x * 64 + el;
     double acc = 0.0;
@@ -99,19 +102,33 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ 
 // shift = l 2^-52 trace(T), and Rinv = R^-1 (upper, l x l, R = L^T).  One
 // workgroup of TG x TG threads; the matrix lives in registers (reg_chol_inv),
 // l <= TG * NR.  Every entry is loaded and stored by its owning thread.
+//
+// With `gate` non-null the kernel returns at once when *gate == 0.  With
+// `need2` non-null it writes 0 there when one Cholesky QR pass with this
+// factor already leaves a basis orthonormal far below FP32 rounding: the
+// orthogonality error of a pass is about u64 cond(T), and cond(T) <=
+// ||T||_F ||Rinv||_F^2 (lambda_max <= ||T||_F, 1/lambda_min <= ||R^-1||_2^2), so
+// a bound below 2^26 (error below 2^-26) suffices; otherwise it writes 1.
 template <int TG, int NR>
 __global__ __launch_bounds__(TG* TG) void k_chol_rinv_small(const double* __restrict__ T, int l,
-                                                            double* __restrict__ Rinv, int* __restrict__ info) {
+                                                            double* __restrict__ Rinv, int* __restrict__ info,
+                                                            const int* __restrict__ gate, int* __restrict__ need2) {
+    constexpr int NW = TG * TG / 64;
     __shared__ double P[2 * TG * NR + 1];
     __shared__ double pv[TG * NR];
+    __shared__ double sred[2][NW];
+    if (gate && *gate == 0) return;
     const int tid = threadIdx.x, tr = tid / TG, tc = tid % TG;
     double m[NR * (NR + 1) / 2];
+    double gf = 0.0;   // this thread's share of ||T||_F^2
 #pragma unroll
     for (int a = 0; a < NR; ++a)
 #pragma unroll
         for (int b = 0; b <= a; ++b) {
             const int i = tr + TG * a, c = tc + TG * b;
-            m[tri_slot(a, b)] = (i < l && c <= i) ? T[(int64_t)i * l + c] : 0.0;
+            const double v = (i < l && c <= i) ? T[(int64_t)i * l + c] : 0.0;
+            m[tri_slot(a, b)] = v;
+            gf = fma(i == c ? v : 2.0 * v, v, gf);
         }
     // trace, summed in index order by every thread
 #pragma unroll
@@ -141,15 +158,48 @@ __global__ __launch_bounds__(TG* TG) void k_chol_rinv_small(const double* __rest
                 if (c < i) Rinv[(int64_t)i * l + c] = 0.0;
             }
         }
-    if (tid == 0 && info && (pmin < 10.0 * shift || ndrop > 0)) atomicOr(info, 1);
+    const bool small_pivot = pmin < 10.0 * shift || ndrop > 0;
+    if (tid == 0 && info && small_pivot) atomicOr(info, 1);
+    if (need2) {
+        double xf = 0.0;
+#pragma unroll
+        for (int a = 0; a < NR; ++a)
+#pragma unroll
+            for (int b = 0; b <= a; ++b) {
+                const int i = tr + TG * a, c = tc + TG * b;
+                const double v = (i < l && c <= i) ? m[tri_slot(a, b)] : 0.0;
+                xf = fma(v, v, xf);
+            }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            gf += __shfl_xor(gf, o, 64);
+            xf += __shfl_xor(xf, o, 64);
+        }
+        if ((tid & 63) == 0) {
+            sred[0][tid >> 6] = gf;
+            sred[1][tid >> 6] = xf;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double g2 = 0.0, x2 = 0.0;
+            for (int w = 0; w < NW; ++w) {
+                g2 += sred[0][w];
+                x2 += sred[1][w];
+            }
+            const double bound = sqrt(g2) * x2;
+            need2[0] = (small_pivot || !(bound < ldexp(1.0, 26))) ? 1 : 0;
+        }
+    }
 }
 
 // out (rows x lo) = X (rows x li, FP32) * M (li x lo, FP64), FP64 accumulation.
 __global__ __launch_bounds__(256) void k_apply_small(const float* __restrict__ X, int64_t rows, int li, int64_t ldx,
                                                      const double* __restrict__ M, int lo, int64_t ldm,
-                                                     float* __restrict__ out, int64_t ldo) {
+                                                     float* __restrict__ out, int64_t ldo,
+                                                     const int* __restrict__ gate) {
     __shared__ double Ms[kMaxL * kMaxL];
     __shared__ float Xs[kRC * (kMaxL + 1)];
+    if (gate && *gate == 0) return;
     const int lop = (lo + 3) & ~3;
     const int lis = li + 1;
     const int tid = threadIdx.x;
@@ -634,51 +684,57 @@ int gram_wgs(int64_t rows) {
 
 template <typename T>
 static hipError_t gram64_impl(const T* X, int64_t rows, int64_t l, int64_t ldx, double* partial, int wgs,
-                              hipStream_t st) {
+                              hipStream_t st, const int* gate) {
     if (l < 1 || l > kMaxL) return hipErrorInvalidValue;
     const int lp = ((int)l + 3) & ~3;
     const int nt = (lp / 4) * (lp / 4);
     const int64_t rpw = (rows + wgs - 1) / wgs;
-    hipLaunchKernelGGL(k_gram64<T>, dim3(wgs), dim3(nt < 64 ? 64 : nt), 0, st, X, rows, (int)l, ldx, rpw, partial);
+    hipLaunchKernelGGL(k_gram64<T>, dim3(wgs), dim3(nt < 64 ? 64 : nt), 0, st, X, rows, (int)l, ldx, rpw, partial,
+                       gate);
     return hipGetLastError();
 }
 
 hipError_t launch_gram64(const float* X, int64_t rows, int64_t l, int64_t ldx, double* partial, int wgs,
-                         hipStream_t st) {
-    return gram64_impl(X, rows, l, ldx, partial, wgs, st);
+                         hipStream_t st, const int* gate) {
+    return gram64_impl(X, rows, l, ldx, partial, wgs, st, gate);
 }
 
 hipError_t launch_gram64(const double* X, int64_t rows, int64_t l, int64_t ldx, double* partial, int wgs,
                          hipStream_t st) {
-    return gram64_impl(X, rows, l, ldx, partial, wgs, st);
+    return gram64_impl(X, rows, l, ldx, partial, wgs, st, nullptr);
 }
 
-hipError_t launch_gram_reduce(const double* partial, int parts, int64_t l, double* T, hipStream_t st) {
+hipError_t launch_gram_reduce(const double* partial, int parts, int64_t l, double* T, hipStream_t st,
+                              const int* gate) {
     const int64_t ll = l * l;
-    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((ll + 63) / 64)), dim3(256), 0, st, partial, parts, ll, T);
+    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((ll + 63) / 64)), dim3(256), 0, st, partial, parts, ll, T,
+                       gate);
     return hipGetLastError();
 }
 
-hipError_t launch_chol_rinv_small(const double* T, int64_t l, double* Rinv, int* info, hipStream_t st) {
+hipError_t launch_chol_rinv_small(const double* T, int64_t l, double* Rinv, int* info, hipStream_t st,
+                                  const int* gate, int* need2) {
     if (l < 1 || l > kMaxL) return hipErrorInvalidValue;
     // a step is latency-bound: up to l = 64 a 16 x 16 grid with 4 x 4 slots per
     // thread measured fastest (vs one wave with 8 x 8 slots); above, 16 x 16 with
     // 8 x 8 (74 us at l = 128, against 93 us for 32 x 32 with 4 x 4)
     if (l <= 64)
-        hipLaunchKernelGGL((k_chol_rinv_small<16, 4>), dim3(1), dim3(256), 0, st, T, (int)l, Rinv, info);
+        hipLaunchKernelGGL((k_chol_rinv_small<16, 4>), dim3(1), dim3(256), 0, st, T, (int)l, Rinv, info, gate,
+                           need2);
     else
-        hipLaunchKernelGGL((k_chol_rinv_small<16, 8>), dim3(1), dim3(256), 0, st, T, (int)l, Rinv, info);
+        hipLaunchKernelGGL((k_chol_rinv_small<16, 8>), dim3(1), dim3(256), 0, st, T, (int)l, Rinv, info, gate,
+                           need2);
     return hipGetLastError();
 }
 
 hipError_t launch_apply_small(const float* X, int64_t rows, int64_t li, int64_t ldx, const double* M, int64_t lo,
-                              int64_t ldm, float* out, int64_t ldo, hipStream_t st) {
+                              int64_t ldm, float* out, int64_t ldo, hipStream_t st, const int* gate) {
     if (li < 1 || li > kMaxL || lo < 1 || lo > kMaxL) return hipErrorInvalidValue;
     int64_t blocks = (rows + kRC - 1) / kRC;
     if (blocks > 1024) blocks = 1024;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_apply_small, dim3((unsigned)blocks), dim3(256), 0, st, X, rows, (int)li, ldx, M, (int)lo,
-                       ldm, out, ldo);
+                       ldm, out, ldo, gate);
     return hipGetLastError();
 }
 
