@@ -194,6 +194,14 @@ std::vector<int64_t> expand_blocks(const int64_t* off, const int64_t* idx, int64
     return out;
 }
 
+// The common width of all blocks, or 0 when they differ.
+int64_t uniform_width(const int64_t* off, int64_t G) {
+    const int64_t b = off[1] - off[0];
+    for (int64_t g = 1; g < G; ++g)
+        if (off[g + 1] - off[g] != b) return 0;
+    return b;
+}
+
 // A block map must be a permutation of 0 .. count-1 (or null).
 bcur_status check_map(bcur_ctx* ctx, const int64_t* map, int64_t count, const char* name) {
     if (!map) return BCUR_OK;
@@ -1250,23 +1258,45 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
     if (rowv) STCHK(stage_side(sr, rmax, reinterpret_cast<const char*>(sr.sc + Gr), hr));
     double* h_lam = reinterpret_cast<double*>(ptake(8 * l));
     int* rinfo = reinterpret_cast<int*>(ptake(16));
-    HIPCHK(hipStreamSynchronize(st));
-    if (!isfinite(h_frob[0])) return fail(ctx, BCUR_E_NONFINITE, "A holds NaN or Inf");
-    if (hc.st[0] != 0 || (rowv && hr.st[0] != 0)) return fail(ctx, BCUR_E_HIP, "block scores are not finite");
-    for (int64_t t = 0; t < s; ++t)
-        if (hc.idx[t] < 0 || hc.idx[t] >= G) return fail(ctx, BCUR_E_HIP, "sampler returned an invalid block");
-    for (int64_t t = 0; t < s_r; ++t)
-        if (hr.idx[t] < 0 || hr.idx[t] >= Gr) return fail(ctx, BCUR_E_HIP, "sampler returned an invalid row block");
-    const std::vector<int64_t> cols = expand_blocks(col_off, hc.idx, s, p->col_map);
-    const int64_t c = (int64_t)cols.size();
-    memcpy(hc.list, cols.data(), c * sizeof(int64_t));
-    HIPCHK(hipMemcpyAsync(sc.list, hc.list, c * sizeof(int64_t), hipMemcpyHostToDevice, st));
-    int64_t r = 0;
-    if (rowv) {
-        const std::vector<int64_t> rows = expand_blocks(row_off, hr.idx, s_r, rmap_h);
-        r = (int64_t)rows.size();
-        memcpy(hr.list, rows.data(), r * sizeof(int64_t));
-        HIPCHK(hipMemcpyAsync(sr.list, hr.list, r * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    // The checks of the draws, once their results are on the host.
+    auto check_draws = [&]() -> bcur_status {
+        if (!isfinite(h_frob[0])) return fail(ctx, BCUR_E_NONFINITE, "A holds NaN or Inf");
+        if (hc.st[0] != 0 || (rowv && hr.st[0] != 0)) return fail(ctx, BCUR_E_HIP, "block scores are not finite");
+        for (int64_t t = 0; t < s; ++t)
+            if (hc.idx[t] < 0 || hc.idx[t] >= G) return fail(ctx, BCUR_E_HIP, "sampler returned an invalid block");
+        for (int64_t t = 0; t < s_r; ++t)
+            if (hr.idx[t] < 0 || hr.idx[t] >= Gr)
+                return fail(ctx, BCUR_E_HIP, "sampler returned an invalid row block");
+        return BCUR_OK;
+    };
+    // Blocks of one width drawn without replacement: c = s b (and r = s_r h) is
+    // known, so the lists are expanded on the device and the path runs to its
+    // end without a host round trip; the draws are checked after the fit's
+    // synchronization.  Otherwise the host expands the chosen blocks (dropping
+    // repeats) before the gather.
+    const int64_t bw = uniform_width(col_off, G), bh = rowv ? uniform_width(row_off, Gr) : 0;
+    const bool on_device = !p->replace && bw > 0 && (!rowv || bh > 0);
+    int64_t c = 0, r = 0;
+    if (on_device) {
+        c = s * bw;
+        HIPCHK(launch_expand_blocks(sc.idx, s, sc.off, G, d_cmap, bw, sc.list, st));
+        if (rowv) {
+            r = s_r * bh;
+            HIPCHK(launch_expand_blocks(sr.idx, s_r, sr.off, Gr, d_rmap, bh, sr.list, st));
+        }
+    } else {
+        HIPCHK(hipStreamSynchronize(st));
+        STCHK(check_draws());
+        const std::vector<int64_t> cols = expand_blocks(col_off, hc.idx, s, p->col_map);
+        c = (int64_t)cols.size();
+        memcpy(hc.list, cols.data(), c * sizeof(int64_t));
+        HIPCHK(hipMemcpyAsync(sc.list, hc.list, c * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        if (rowv) {
+            const std::vector<int64_t> rows = expand_blocks(row_off, hr.idx, s_r, rmap_h);
+            r = (int64_t)rows.size();
+            memcpy(hr.list, rows.data(), r * sizeof(int64_t));
+            HIPCHK(hipMemcpyAsync(sr.list, hr.list, r * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        }
     }
     // 5. C = A S (unscaled) and R = S_R^T A
     const int64_t ldc = round4(c);
@@ -1301,6 +1331,7 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
         fl = fo.flags;
     }
     ctx->pinned_busy = false;  // the fit's synchronization completed every copy
+    if (on_device) STCHK(check_draws());
     if (rinfo[0] & 1) fl |= BCUR_FLAG_RANKDEF_Y;
     if (hc.st[1] || (rowv && hr.st[1])) fl |= BCUR_FLAG_ZERO_SCORE;
     memcpy(res->idx, hc.idx, s * sizeof(int64_t));

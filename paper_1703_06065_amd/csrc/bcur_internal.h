@@ -22,6 +22,10 @@ hipError_t launch_sample(const double* scores, int64_t G, const uint64_t* draws,
                          int* status, hipStream_t st);
 hipError_t launch_gather_cols(const float* A, int64_t lda, int64_t m, const int64_t* d_cols, int64_t c,
                               float* C, int64_t ldc, hipStream_t st);
+// out[t b + i] = map[off[idx[t]] + i] (identity when map is null) for s blocks of width b; an index
+// outside [0, G) is read as 0
+hipError_t launch_expand_blocks(const int64_t* idx, int64_t s, const int64_t* off, int64_t G, const int64_t* map,
+                                int64_t b, int64_t* out, hipStream_t st);
 hipError_t launch_gather_rows(const float* A, int64_t lda, int64_t n, const int64_t* d_rows, int64_t r,
                               float* R, int64_t ldr, hipStream_t st);
 hipError_t launch_sum_f64(const double* x, int64_t count, double* out, hipStream_t st);

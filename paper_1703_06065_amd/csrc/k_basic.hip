@@ -319,6 +319,25 @@ __global__ __launch_bounds__(1024) void k_sample(const double* __restrict__ scor
     }
 }
 
+// The column (row) list of s chosen blocks of equal width b drawn without
+// replacement: out[t b + i] = map[off[idx[t]] + i] (map null: the identity).
+// A block index outside [0, G) (the sampler did not run on valid scores) is
+// read as block 0, so every later access stays in bounds; the host rejects
+// such a result after its synchronization.
+__global__ __launch_bounds__(256) void k_expand_blocks(const int64_t* __restrict__ idx, int64_t s,
+                                                      const int64_t* __restrict__ off, int64_t G,
+                                                      const int64_t* __restrict__ map, int64_t b,
+                                                      int64_t* __restrict__ out) {
+    const int64_t total = s * b;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const int64_t t = e / b, i = e - t * b;
+        int64_t j = idx[t];
+        if (j < 0 || j >= G) j = 0;
+        const int64_t pos = off[j] + i;
+        out[e] = map ? map[pos] : pos;
+    }
+}
+
 // C[i][t] = A[i][cols[t]]
 __global__ __launch_bounds__(256) void k_gather_cols(const float* __restrict__ A, int64_t lda, int64_t m,
                                                      const int64_t* __restrict__ cols, int64_t c,
@@ -467,6 +486,15 @@ hipError_t launch_sample(const double* scores, int64_t G, const uint64_t* draws,
 hipError_t launch_gather_cols(const float* A, int64_t lda, int64_t m, const int64_t* d_cols, int64_t c, float* C,
                               int64_t ldc, hipStream_t st) {
     hipLaunchKernelGGL(k_gather_cols, grid2d(c, m), dim3(256), 0, st, A, lda, m, d_cols, c, C, ldc);
+    return hipGetLastError();
+}
+
+hipError_t launch_expand_blocks(const int64_t* idx, int64_t s, const int64_t* off, int64_t G, const int64_t* map,
+                                int64_t b, int64_t* out, hipStream_t st) {
+    if (s < 1 || b < 1 || G < 1) return hipErrorInvalidValue;
+    int64_t blocks = (s * b + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_expand_blocks, dim3((unsigned)blocks), dim3(256), 0, st, idx, s, off, G, map, b, out);
     return hipGetLastError();
 }
 
