@@ -221,7 +221,7 @@ inline int64_t round8(int64_t x) { return (x + 7) & ~(int64_t)7; }
 
 struct RFBufs {
     float *Q, *Y, *Z, *part;
-    double *gpart, *T, *Rinv, *Wk, *Wks, *lam;
+    double *gpart, *T, *Rinv, *Wk, *Wks, *lam, *sqpart;
     void* jws;
     int* info;
     // BF16 operands (k contiguous): A, A^T, Q^T, Z^T
@@ -256,6 +256,7 @@ void rf_layout(Arena& a, RFBufs& b, int64_t m, int64_t n, int64_t l, int64_t k, 
     b.Wk = a.take<double>(l * k);
     b.Wks = a.take<double>(l * k);
     b.lam = a.take<double>(l);
+    b.sqpart = a.take<double>(plan_sgemm(m, l, n, false, true).wgs);
     b.jws = a.take<double>((jacobi_ws_bytes(l) + 7) / 8);
     b.info = a.take<int>(4);
 }
@@ -335,9 +336,15 @@ bcur_status cast_a_bf16(bcur_ctx* ctx, const RFBufs& b, const float* A, int64_t 
 
 // precision BCUR_PREC_BF16: iterations 0 .. q-1 in BF16, iteration q and the
 // Rayleigh-Ritz pass in FP32 (the final FP32 power pass).
+//
+// frob2 (device, or null): with an FP32 first pass, ||A||_F^2 is summed from
+// that pass's loads of A (each element is loaded once) into frob2[0]; the
+// caller computes it separately on the BF16 path (range_finder_fuses_frob).
+bool range_finder_fuses_frob(int64_t q, int precision) { return !(precision == BCUR_PREC_BF16 && q > 0); }
+
 bcur_status range_finder_run(bcur_ctx* ctx, const RFBufs& b, const float* A, int64_t m, int64_t n, int64_t lda,
                              const float* omega, int64_t l, int64_t k, int64_t q, float* Vk, float* Uk,
-                             int precision = BCUR_PREC_FP32) {
+                             int precision = BCUR_PREC_FP32, double* frob2 = nullptr) {
     hipStream_t st = ctx->stream;
     const int64_t lp = round4(l);
     HIPCHK(hipMemsetAsync(b.info, 0, 4 * sizeof(int), st));
@@ -351,8 +358,11 @@ bcur_status range_finder_run(bcur_ctx* ctx, const RFBufs& b, const float* A, int
         if (bf16 && it < q) {
             STCHK(sketch_pass_bf16(ctx, b, m, n, b.Q, lp, l, b.Y));
         } else {
+            const bool sqa = frob2 && it == 0;
             STCHK(gemm_timed(ctx, BCUR_STAGE_RF_AQ, BCUR_STAGE_RF_REDUCE, pz, m, l, n, false, A, lda, b.Q, lp, b.Z,
-                             lp, b.part));
+                             lp, b.part, sqa ? EPI_STORE_SQA : EPI_STORE, nullptr, 0, nullptr, 0,
+                             sqa ? b.sqpart : nullptr));
+            if (sqa) HIPCHK(launch_sum_f64(b.sqpart, pz.wgs, frob2, st));
             STCHK(gemm_timed(ctx, BCUR_STAGE_RF_ATZ, BCUR_STAGE_RF_REDUCE, py, n, l, m, true, A, lda, b.Z, lp, b.Y,
                              lp, b.part));
         }
@@ -1205,13 +1215,15 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
         HIPCHK(hipMemcpyAsync(d_rmap, h_rm, m * sizeof(int64_t), hipMemcpyHostToDevice, st));
     }
 
-    // 1. ||A||_F^2
-    {
+    // 1. ||A||_F^2 (summed by the range finder's first FP32 pass over A when it has one)
+    const bool fused_frob = range_finder_fuses_frob(q, p->precision);
+    if (!fused_frob) {
         StageScope ts(ctx, BCUR_STAGE_FROB);
         HIPCHK(launch_frob2(A, m, n, lda, d_fpart, frob2_grid(m, n), d_frob, st));
     }
     // 2. sketched top-k right subspace (and left vectors for the row blocks)
-    STCHK(range_finder_run(ctx, rb, A, m, n, lda, omega, l, k, q, Vk, Uk, p->precision));
+    STCHK(range_finder_run(ctx, rb, A, m, n, lda, omega, l, k, q, Vk, Uk, p->precision,
+                           fused_frob ? d_frob : nullptr));
     // 3. block scores (with a map, over the rows of V_k (U_k) listed in map
     // order, so each block's rows are contiguous), 4. sampling
     {
@@ -1463,12 +1475,14 @@ bcur_status bcur_decompose_boost(bcur_ctx* ctx, const float* A, int64_t m, int64
         memcpy(h_cm, p->col_map, n * sizeof(int64_t));
         HIPCHK(hipMemcpyAsync(d_cmap, h_cm, n * sizeof(int64_t), hipMemcpyHostToDevice, st));
     }
-    {
+    const bool fused_frob = range_finder_fuses_frob(q, p->precision);
+    if (!fused_frob) {
         StageScope ts(ctx, BCUR_STAGE_FROB);
         HIPCHK(launch_frob2(A, m, n, lda, d_fpart, frob2_grid(m, n), d_frob, st));
     }
     // one top-k subspace and one set of scores for every trial
-    STCHK(range_finder_run(ctx, rb, A, m, n, lda, omega, l, k, q, Vk, nullptr, p->precision));
+    STCHK(range_finder_run(ctx, rb, A, m, n, lda, omega, l, k, q, Vk, nullptr, p->precision,
+                           fused_frob ? d_frob : nullptr));
     {
         StageScope ts(ctx, BCUR_STAGE_SCORES);
         if (d_cmap) HIPCHK(launch_gather_rows(Vk, k, k, d_cmap, n, Vp, k, st));

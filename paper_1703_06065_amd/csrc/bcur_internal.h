@@ -42,7 +42,7 @@ hipError_t launch_fit_err(const double* parts, int64_t nparts_e, const double* d
                           double* out, hipStream_t st);
 
 // ---- FP32 MFMA GEMM (k_sgemm.hip) ------------------------------------------
-enum GemmEpi { EPI_STORE = 0, EPI_RESID = 1, EPI_ADD_DOT = 2, EPI_RESID_NORM = 3 };
+enum GemmEpi { EPI_STORE = 0, EPI_RESID = 1, EPI_ADD_DOT = 2, EPI_RESID_NORM = 3, EPI_STORE_SQA = 4 };
 struct GemmPlan {
     int splits = 1;
     int64_t kchunk = 0;
@@ -54,6 +54,9 @@ GemmPlan plan_sgemm(int64_t M, int64_t N, int64_t K, bool transA, bool allow_spl
 size_t sgemm_partial_floats(const GemmPlan& p, int64_t M, int64_t N);
 // EPI_STORE: D = acc.  EPI_RESID: D = X - acc, wsum[wg] = sum (X - acc)^2.
 // EPI_RESID_NORM: wsum only, D is not written (may be null).
+// EPI_STORE_SQA (A not transposed): as EPI_STORE, and wsum[wg] (one per workgroup of the grid,
+// p.wgs in all, split-K included) = the FP64 sum of squares of the A elements that workgroup
+// loaded, so that the sum over all of them is ||A||_F^2.
 // EPI_ADD_DOT: D = X + acc, wsum[wg] = sum acc * Y.   Epilogues need splits == 1.
 // main kernel only (partial tiles when split) and the split-K sum
 hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K, bool transA, const float* A,

@@ -122,10 +122,23 @@ __global__ __launch_bounds__(WM* WN * 64) void k_sgemm(const GemmArgs g) {
             rb[u] = ld4(g.B + gk * g.ldb + gn, gk < kend, gn, g.N);
         }
     };
+    // EPI_STORE_SQA: the sum of squares of the A operand as it passes through
+    // (each element of A is loaded by exactly one workgroup of the first column
+    // of tiles; the others do not count)
+    constexpr bool kSqa = EPI == EPI_STORE_SQA && !TA;
+    const bool count_sq = kSqa && blockIdx.y == 0;
+    double sqa = 0.0;
     auto store_tiles = [&]() {
 #pragma unroll
         for (int u = 0; u < A_F4; ++u) {
             const int f = tid + u * NT;
+            if (kSqa && count_sq) {
+                const double x0 = ra[u].x, x1 = ra[u].y, x2 = ra[u].z, x3 = ra[u].w;
+                sqa = fma(x0, x0, sqa);
+                sqa = fma(x1, x1, sqa);
+                sqa = fma(x2, x2, sqa);
+                sqa = fma(x3, x3, sqa);
+            }
             if (!TA) {
                 const int row = f / (BK / 4), kq = f % (BK / 4);
                 As[(kq * 4 + 0) * LDAS + row] = ra[u].x;
@@ -181,7 +194,7 @@ __global__ __launch_bounds__(WM* WN * 64) void k_sgemm(const GemmArgs g) {
                 const int64_t col = n0 + wn * WTN + 32 * j + r;
                 if (row < g.M && col < g.N) {
                     const float x = acc[i][j][v];
-                    if (EPI == EPI_STORE) {
+                    if (EPI == EPI_STORE || EPI == EPI_STORE_SQA) {
                         D[row * g.ldd + col] = x;
                     } else if (kResid) {
                         const float e = xv[i][j][v] - x;
@@ -193,7 +206,18 @@ __global__ __launch_bounds__(WM* WN * 64) void k_sgemm(const GemmArgs g) {
                     }
                 }
             }
-    if (EPI != EPI_STORE) {
+    if constexpr (EPI == EPI_STORE_SQA) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) sqa += __shfl_xor(sqa, o, 64);
+        if (lane == 0) red[wave] = sqa;
+        __syncthreads();
+        if (tid == 0) {
+            double s2 = 0.0;
+#pragma unroll
+            for (int w = 0; w < NT / 64; ++w) s2 += red[w];
+            g.wsum[blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z)] = s2;
+        }
+    } else if (EPI != EPI_STORE) {
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) wacc += __shfl_xor(wacc, o, 64);
         if (lane == 0) red[wave] = wacc;
@@ -301,7 +325,9 @@ hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K,
                              int64_t lda, const float* B, int64_t ldb, float* D, int64_t ldd, float* partial, int epi,
                              const float* X, int64_t ldx, const float* Y, int64_t ldy, double* wsum, hipStream_t st) {
     if (M <= 0 || N <= 0) return hipSuccess;
-    if (epi != EPI_STORE && p.splits != 1) return hipErrorInvalidValue;
+    const bool store_like = epi == EPI_STORE || epi == EPI_STORE_SQA;
+    if (!store_like && p.splits != 1) return hipErrorInvalidValue;
+    if (epi == EPI_STORE_SQA && transA) return hipErrorInvalidValue;
     GemmArgs a;
     a.M = M;
     a.N = N;
@@ -326,7 +352,7 @@ hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K,
         a.split_stride = 0;
     }
     // the fused epilogues exist for the square tile only
-    const int cfg = epi != EPI_STORE ? 2 : p.cfg;
+    const int cfg = store_like ? p.cfg : 2;
     const Cfg c = kCfg[cfg];
     dim3 grid((unsigned)((M + c.BM - 1) / c.BM), (unsigned)((N + c.BN - 1) / c.BN), (unsigned)p.splits);
     hipError_t e;
@@ -337,6 +363,9 @@ hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K,
         case 110: e = run<1, true, EPI_STORE>(a, grid, st); break;
         case 200: e = run<2, false, EPI_STORE>(a, grid, st); break;
         case 210: e = run<2, true, EPI_STORE>(a, grid, st); break;
+        case 4: e = run<0, false, EPI_STORE_SQA>(a, grid, st); break;
+        case 104: e = run<1, false, EPI_STORE_SQA>(a, grid, st); break;
+        case 204: e = run<2, false, EPI_STORE_SQA>(a, grid, st); break;
         case 201: e = run<2, false, EPI_RESID>(a, grid, st); break;
         case 203: e = run<2, false, EPI_RESID_NORM>(a, grid, st); break;
         case 202: e = run<2, false, EPI_ADD_DOT>(a, grid, st); break;
