@@ -31,11 +31,10 @@ def algorithmic_flops(m, n, k, l, q, c):
 
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 counter runs of
-# this command (FETCH_SIZE and WRITE_SIZE, KiB per H / F dispatch: grid of
-# 512 x 32 x 8 workgroups), each scaled by
-# the same counter's reading for a plain copy of known size; null when the
+# this command (FETCH_SIZE and WRITE_SIZE, KiB per H / F dispatch), each scaled
+# by the same counter's reading for a plain copy of known size; None when the
 # kernel has changed since the counters were taken.
-TRAFFIC = {"m": 8192, "n": 4096, "c": 256, "fetch_kib": 147538.0, "write_kib": 32768.0,
+TRAFFIC = {"m": 8192, "n": 4096, "c": 256, "fetch_kib": None, "write_kib": None,
            "fetch_scale": 262144.0 / 131092.8125, "write_scale": 262144.0 / 262144.0}
 
 
@@ -290,7 +289,7 @@ def boost_bench(args):
     ach = per_launch_flop / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
     roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
             "frac": round(ach / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
-            "kernel": "k_sgemm<128,128,16,2,2,TA> (H = C^T A over the t trials' concatenated columns)",
+            "kernel": "k_sgemm<256,128,16,4,2,TA> (H = C^T A over the t trials' concatenated columns)",
             "launches_per_step": 1, "avg_ms": round(avg_ms, 5), "flop_per_launch": per_launch_flop,
             "algorithmic_bytes_per_launch": 4.0 * (w.m * ctot + w.m * w.n + ctot * w.n)}
     rf_flops, fit_flops = algorithmic_flops(w.m, w.n, w.k, w.l, w.q, c)
@@ -493,7 +492,7 @@ def main():
     rf_flops, fit_flops = algorithmic_flops(w.m, w.n, w.k, w.l, w.q, c)
 
     # Roofline of the dominant kernel.  Per decomposition the FP32 MFMA GEMM
-    # k_sgemm<128,128> with A transposed runs twice, for H = C^T A (stage fit_H)
+    # k_sgemm<256,128> with A transposed runs twice, for H = C^T A (stage fit_H)
     # and F = C^T E (stage fit_F); its total device time is the largest of all
     # kernels (see the kernel statistics under profiles/).  Each stage brackets
     # exactly one launch of it (its split-K sum is timed as fit_reduce), so the
@@ -504,7 +503,7 @@ def main():
     ach = per_launch_flop / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
     roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
             "frac": round(ach / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": traffic_bytes(w.m, w.n, c),
-            "kernel": "k_sgemm<128,128,16,2,2,TA> (H = C^T A, F = C^T E)", "launches_per_step": 2,
+            "kernel": "k_sgemm<256,128,16,4,2,TA> (H = C^T A, F = C^T E)", "launches_per_step": 2,
             "avg_ms": round(avg_ms, 5), "flop_per_launch": per_launch_flop,
             "algorithmic_bytes_per_launch": 4.0 * (w.m * c + w.m * w.n + c * w.n)}
     out = {

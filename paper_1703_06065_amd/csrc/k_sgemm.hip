@@ -278,7 +278,7 @@ int64_t add_dot_blocks(int64_t M, int64_t N) {
 struct Cfg {
     int BM, BN;
 };
-constexpr Cfg kCfg[3] = {{128, 64}, {128, 128}, {128, 128}};
+constexpr Cfg kCfg[4] = {{128, 64}, {128, 128}, {128, 128}, {256, 128}};
 constexpr int kBK = 16;
 
 template <int CFG, bool TA, int EPI>
@@ -287,21 +287,27 @@ hipError_t run(const GemmArgs& a, dim3 grid, hipStream_t st) {
         hipLaunchKernelGGL((k_sgemm<128, 64, kBK, 4, 1, TA, EPI>), grid, dim3(256), 0, st, a);
     else if (CFG == 1)
         hipLaunchKernelGGL((k_sgemm<128, 128, kBK, 4, 1, TA, EPI>), grid, dim3(256), 0, st, a);
-    else
+    else if (CFG == 2)
         hipLaunchKernelGGL((k_sgemm<128, 128, kBK, 2, 2, TA, EPI>), grid, dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_sgemm<256, 128, kBK, 4, 2, TA, EPI>), grid, dim3(512), 0, st, a);
     return hipGetLastError();
 }
 
 }  // namespace
 
 GemmPlan plan_sgemm(int64_t M, int64_t N, int64_t K, bool transA, bool allow_split) {
-    (void)transA;
     GemmPlan p;
     p.cfg = N <= 64 ? 0 : (N <= 128 ? 1 : 2);
+    // wide products with A transposed, more than 128 rows and a long K (H = C^T A,
+    // F = C^T E): 256 x 128 tiles of eight waves, so the long operand is streamed
+    // half as often; the split-K target counts workgroups of eight waves
+    if (transA && M > 128 && N > 128 && K >= 2048) p.cfg = 3;
     const int64_t tiles = ((M + kCfg[p.cfg].BM - 1) / kCfg[p.cfg].BM) * ((N + kCfg[p.cfg].BN - 1) / kCfg[p.cfg].BN);
+    const int64_t target = p.cfg == 3 ? 256 : 512;
     int64_t splits = 1;
-    if (allow_split && tiles < 480) {
-        splits = (512 + tiles - 1) / tiles;
+    if (allow_split && tiles < target - 32) {
+        splits = (target + tiles - 1) / tiles;
         const int64_t maxs = K / (4 * kBK);
         if (splits > maxs) splits = maxs;
         if (splits < 1) splits = 1;
@@ -363,6 +369,7 @@ hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K,
         case 110: e = run<1, true, EPI_STORE>(a, grid, st); break;
         case 200: e = run<2, false, EPI_STORE>(a, grid, st); break;
         case 210: e = run<2, true, EPI_STORE>(a, grid, st); break;
+        case 310: e = run<3, true, EPI_STORE>(a, grid, st); break;
         case 4: e = run<0, false, EPI_STORE_SQA>(a, grid, st); break;
         case 104: e = run<1, false, EPI_STORE_SQA>(a, grid, st); break;
         case 204: e = run<2, false, EPI_STORE_SQA>(a, grid, st); break;
