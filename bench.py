@@ -31,10 +31,11 @@ def algorithmic_flops(m, n, k, l, q, c):
 
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 counter runs of
-# this command (FETCH_SIZE and WRITE_SIZE, KiB per H / F dispatch), each scaled
-# by the same counter's reading for a plain copy of known size; None when the
-# kernel has changed since the counters were taken.
-TRAFFIC = {"m": 8192, "n": 4096, "c": 256, "fetch_kib": None, "write_kib": None,
+# this command (FETCH_SIZE and WRITE_SIZE, KiB per H / F dispatch: 256
+# workgroups of 512 threads), each scaled by the same counter's reading for a
+# plain copy of known size; None when the kernel has changed since the
+# counters were taken.
+TRAFFIC = {"m": 8192, "n": 4096, "c": 256, "fetch_kib": 98381.5, "write_kib": 32768.0,
            "fetch_scale": 262144.0 / 131092.8125, "write_scale": 262144.0 / 262144.0}
 
 
