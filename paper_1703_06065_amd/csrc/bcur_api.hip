@@ -417,7 +417,7 @@ void fit_layout(Arena& a, FitBufs& b, int64_t m, int64_t n, int64_t c, bool need
     b.Gtmp = need_gtmp ? a.take<float>(c * cp) : nullptr;
     b.G = a.take<double>(c * c);
     b.spdws = a.take<double>(spd_inverse_ws_doubles(c));
-    b.nwsE = ((m + 127) / 128) * ((n + 127) / 128);
+    b.nwsE = resid_parts(m, n, c);
     b.nwsD = add_dot_parts(pu, c, n);
     b.wsE = a.take<double>(b.nwsE);
     b.wsD = a.take<double>(b.nwsD);
@@ -487,9 +487,8 @@ bcur_status fit_run(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t m, 
         HIPCHK(launch_sgemm_add_dot(pt, c, n, c, true, b.X32, cp, b.H, np, U, ldu, b.part, U, ldu, b.F, np, b.wsD,
                                     st));
     }
-    // one partial per workgroup of the residual GEMM (128 x 128 tiles), and of the dU sum
-    const int64_t nwsE = ((m + 127) / 128) * ((n + 127) / 128);
-    HIPCHK(launch_fit_err(b.wsE, nwsE, b.wsD, refine ? add_dot_parts(pt, c, n) : 0, b.errv, st));
+    // one partial per workgroup of the residual GEMM, and of the dU sum
+    HIPCHK(launch_fit_err(b.wsE, resid_parts(m, n, c), b.wsD, refine ? add_dot_parts(pt, c, n) : 0, b.errv, st));
     return BCUR_OK;
 }
 
@@ -595,7 +594,7 @@ void cur_layout(Arena& a, CurBufs& b, int64_t m, int64_t n, int64_t c, int64_t r
     b.Wd = a.take<double>(m * r);
     b.spc = a.take<double>(spd_inverse_ws_doubles(c));
     b.spr = a.take<double>(spd_inverse_ws_doubles(r));
-    b.wsE = a.take<double>(((m + 127) / 128) * ((n + 127) / 128));
+    b.wsE = a.take<double>(resid_parts(m, n, r));
     b.errv = a.take<double>(4);
     b.pivc = a.take<double>(2 * ((c + 63) / 64));
     b.pivr = a.take<double>(2 * ((r + 63) / 64));
@@ -655,8 +654,7 @@ bcur_status fit_cur_run(bcur_ctx* ctx, const CurBufs& b, const float* A, int64_t
     const GemmPlan pe = plan_sgemm(m, n, r, false, false);
     STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_E, BCUR_STAGE_FIT_REDUCE, pe, m, n, r, false, b.W32, rp, b.R, ldr, b.E,
                      round4(n), nullptr, EPI_RESID, A, lda, nullptr, 0, b.wsE));
-    const int64_t nwsE = ((m + 127) / 128) * ((n + 127) / 128);
-    HIPCHK(launch_fit_err(b.wsE, nwsE, b.wsE, 0, b.errv, st));
+    HIPCHK(launch_fit_err(b.wsE, resid_parts(m, n, r), b.wsE, 0, b.errv, st));
     return BCUR_OK;
 }
 
@@ -1619,7 +1617,7 @@ static bcur_status alg1_impl(bcur_ctx* ctx, const float* A, int64_t m, int64_t n
     const int gwW = gram_wgs(std::max(r, cmax));
     void *jwsR, *jwsW;
     const int gw = gram_wgs(n);
-    const int64_t nwsE = ((m + 127) / 128) * ((n + 127) / 128);
+    const int64_t nwsE = resid_parts(m, n, r);
     auto layout = [&](Arena& a) {
         d_rdr = a.take<uint64_t>(r);
         sample_layout(a, sc, G, s, cmax);

@@ -358,6 +358,8 @@ hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K,
         a.split_stride = 0;
     }
     // the fused epilogues exist for the square tile only
+    // the fused epilogues exist for the square tile only (a 256 x 128 residual
+    // tile measured slower: 202 us against 192 us for E = A - C U at 8192 x 4096 x 256)
     const int cfg = store_like ? p.cfg : 2;
     const Cfg c = kCfg[cfg];
     dim3 grid((unsigned)((M + c.BM - 1) / c.BM), (unsigned)((N + c.BN - 1) / c.BN), (unsigned)p.splits);
@@ -390,6 +392,11 @@ hipError_t launch_splitk_reduce(const GemmPlan& p, int64_t M, int64_t N, const f
     hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)blocks), dim3(256), 0, st, partial, p.splits, M * N, M, N, D,
                        ldd);
     return hipGetLastError();
+}
+
+int64_t resid_parts(int64_t M, int64_t N, int64_t K) {
+    (void)K;   // the residual epilogues always run on the square tile
+    return ((M + kCfg[2].BM - 1) / kCfg[2].BM) * ((N + kCfg[2].BN - 1) / kCfg[2].BN);
 }
 
 int64_t add_dot_parts(const GemmPlan& p, int64_t M, int64_t N) {
