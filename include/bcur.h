@@ -196,11 +196,12 @@ bcur_status bcur_fit_columns(bcur_ctx* ctx, const float* A, int64_t m, int64_t n
  * of the FP32 entries; the spectral norm of each slice comes from the Gram
  * matrix of its smaller side by repeated squaring to the top eigenspace
  * (steps: host G, or NULL, receives the squaring steps each block took, at
- * most 64).  BCUR_E_ARG when min(block width, k) > 64 for some block.
+ * most 64).  col_map (host n, or NULL): blocks of arbitrary row sets of V,
+ * as in bcur_params.  BCUR_E_ARG when min(block width, k) > 64 for some block.
  * Synchronous. */
 bcur_status bcur_block_stable_rank(bcur_ctx* ctx, const float* V, int64_t n, int64_t k, int64_t ldv,
-                                   const int64_t* offsets, int64_t G, double* ratios, int32_t* steps,
-                                   double* alpha);
+                                   const int64_t* offsets, int64_t G, const int64_t* col_map, double* ratios,
+                                   int32_t* steps, double* alpha);
 
 /* Column-space incoherence (Def. 4) of U (device m x k, ldu; the top-k left
  * singular vectors): *mu = (m / k) max_i ||U^T e_i||_2^2, FP64.  Synchronous. */
@@ -355,6 +356,8 @@ typedef struct bcur_alg1_params {
     int64_t rank_k;     /* 0: U = W^+;  k >= 1: U_k = (W_k)^+ */
     int32_t replace;    /* column draws: 0 without replacement, 1 independent */
     int32_t pinv_eig;   /* 0: Cholesky route when certified (default); 1: always the eigensystem */
+    const int64_t* col_map;  /* host (n) permutation or NULL: blocks of arbitrary column sets, as in
+                                bcur_params */
 } bcur_alg1_params;
 
 typedef struct bcur_alg1_result {

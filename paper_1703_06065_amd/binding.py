@@ -64,7 +64,8 @@ class Result(ctypes.Structure):
 
 class Alg1Params(ctypes.Structure):
     _fields_ = [("r", ctypes.c_int64), ("kr", ctypes.c_int64), ("s", ctypes.c_int64), ("rank_k", ctypes.c_int64),
-                ("replace", ctypes.c_int32), ("pinv_eig", ctypes.c_int32)]
+                ("replace", ctypes.c_int32), ("pinv_eig", ctypes.c_int32),
+                ("col_map", ctypes.POINTER(ctypes.c_int64))]
 
 
 class Alg1Result(ctypes.Structure):
@@ -130,7 +131,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "bcur_timing_read": (i32, [vp, P(dbl), P(i64)]),
         "bcur_decompose": (i32, [vp, vp, i64, i64, i64, P(i64), i64, P(i64), i64, P(Params), vp,
                                  P(ctypes.c_uint64), P(Result)]),
-        "bcur_block_stable_rank": (i32, [vp, vp, i64, i64, i64, P(i64), i64, P(dbl), P(i32), P(dbl)]),
+        "bcur_block_stable_rank": (i32, [vp, vp, i64, i64, i64, P(i64), i64, P(i64), P(dbl), P(i32), P(dbl)]),
         "bcur_incoherence": (i32, [vp, vp, i64, i64, i64, P(dbl)]),
         "bcur_decompose_boost": (i32, [vp, vp, i64, i64, i64, P(i64), i64, P(Params), vp, i64, P(ctypes.c_uint64),
                                        P(Result), P(dbl), P(i64)]),
@@ -275,7 +276,7 @@ class Context:
                                              _ptr(out, ctypes.c_double)))
         return out
 
-    def block_stable_rank(self, V, offsets, want_steps: bool = False):
+    def block_stable_rank(self, V, offsets, want_steps: bool = False, col_map=None):
         """(alpha, per-block ratios) of Def. 3 for the slices of V (n x k), and
         the squaring steps per block when want_steps."""
         p, n, k, ldv = _check_dev(V, "V")
@@ -284,7 +285,9 @@ class Context:
         ratios = np.empty(G)
         steps = np.empty(G, dtype=np.int32)
         alpha = ctypes.c_double()
+        cmap = None if col_map is None else _i64(col_map)
         self._chk(self.lib.bcur_block_stable_rank(self.h, p, n, k, ldv, _ptr(off, ctypes.c_int64), G,
+                                                  None if cmap is None else _ptr(cmap, ctypes.c_int64),
                                                   _ptr(ratios, ctypes.c_double), _ptr(steps, ctypes.c_int32),
                                                   ctypes.byref(alpha)))
         return (alpha.value, ratios, steps) if want_steps else (alpha.value, ratios)
@@ -440,7 +443,7 @@ class Context:
 
     def decompose_alg1(self, A, offsets, r: int, s: int, draws, kr: Optional[int] = None, rank_k: int = 0,
                        replace: bool = False, want_u: bool = True, U_out=None, pinv_eig: bool = False,
-                       trials: Optional[int] = None):
+                       trials: Optional[int] = None, col_map=None):
         """Algorithm 1 (uniform rows, U = W^+ or U_k = (W_k)^+).  draws: r row
         words then s column words (per trial when `trials` boosts over that many
         runs, keeping the smallest error).  U is the c x r core for the
@@ -454,6 +457,10 @@ class Context:
             raise ValueError("need r + s draws")
         errs = best = None
         prm = Alg1Params(r=r, kr=kr, s=s, rank_k=rank_k, replace=int(replace), pinv_eig=int(pinv_eig))
+        cmap = None
+        if col_map is not None:
+            cmap = _i64(col_map)
+            prm.col_map = _ptr(cmap, ctypes.c_int64)
         rows = np.empty(r, dtype=np.int64)
         idx = np.empty(s, dtype=np.int64)
         w = np.empty(s)

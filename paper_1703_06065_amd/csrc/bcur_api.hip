@@ -934,11 +934,12 @@ bcur_status bcur_block_scores(bcur_ctx* ctx, const float* V, int64_t n, int64_t 
 }
 
 bcur_status bcur_block_stable_rank(bcur_ctx* ctx, const float* V, int64_t n, int64_t k, int64_t ldv,
-                                   const int64_t* offsets, int64_t G, double* ratios, int32_t* steps,
-                                   double* alpha) {
+                                   const int64_t* offsets, int64_t G, const int64_t* col_map, double* ratios,
+                                   int32_t* steps, double* alpha) {
     if (!ctx || !V || !alpha) return fail(ctx, BCUR_E_ARG, "null argument");
     if (n < 1 || k < 1 || ldv < k) return fail(ctx, BCUR_E_ARG, "bad V shape");
     STCHK(check_offsets(ctx, offsets, G, n, "offsets"));
+    STCHK(check_map(ctx, col_map, n, "col_map"));
     for (int64_t g = 0; g < G; ++g)
         if (std::min(offsets[g + 1] - offsets[g], k) > kDiagMaxD)
             return fail(ctx, BCUR_E_ARG, "block %lld: min(width, k) exceeds %d", (long long)g, kDiagMaxD);
@@ -947,17 +948,29 @@ bcur_status bcur_block_stable_rank(bcur_ctx* ctx, const float* V, int64_t n, int
     a.take<int64_t>(G + 1);
     a.take<double>(G);
     a.take<int>(G);
+    if (col_map) {
+        a.take<int64_t>(n);
+        a.take<float>(n * k);
+    }
     STCHK(reserve(ctx, a.off));
     Arena b{ctx->ws, 0};
     int64_t* d_off = b.take<int64_t>(G + 1);
     double* d_r = b.take<double>(G);
     int* d_steps = b.take<int>(G);
+    int64_t* d_map = col_map ? b.take<int64_t>(n) : nullptr;
+    float* Vp = col_map ? b.take<float>(n * k) : nullptr;
     std::vector<double> hr(G);
     std::vector<int> hs(G);
     HIPCHK(hipMemcpyAsync(d_off, offsets, (G + 1) * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+    if (col_map) {
+        // the rows of V in map order, so every block is a contiguous slice
+        HIPCHK(hipMemcpyAsync(d_map, col_map, n * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(launch_gather_rows(V, ldv, k, d_map, n, Vp, k, ctx->stream));
+    }
     {
         StageScope ts(ctx, BCUR_STAGE_DIAG_ALPHA);
-        HIPCHK(launch_block_stable_rank(V, k, ldv, d_off, G, d_r, d_steps, ctx->stream));
+        HIPCHK(launch_block_stable_rank(col_map ? Vp : V, k, col_map ? k : ldv, d_off, G, d_r, d_steps,
+                                        ctx->stream));
     }
     HIPCHK(hipMemcpyAsync(hr.data(), d_r, G * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipMemcpyAsync(hs.data(), d_steps, G * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
@@ -1595,6 +1608,7 @@ static bcur_status alg1_impl(bcur_ctx* ctx, const float* A, int64_t m, int64_t n
     if (rank_k < 0) return fail(ctx, BCUR_E_ARG, "rank_k < 0");
     if (p->replace < 0 || p->replace > 1 || p->pinv_eig < 0 || p->pinv_eig > 1)
         return fail(ctx, BCUR_E_ARG, "replace and pinv_eig must be 0 or 1");
+    STCHK(check_map(ctx, p->col_map, n, "col_map"));
     int64_t maxw = 0;
     for (int64_t g = 0; g < G; ++g) maxw = std::max(maxw, col_off[g + 1] - col_off[g]);
     const int64_t cmax = std::min(s * maxw, n);
@@ -1612,7 +1626,8 @@ static bcur_status alg1_impl(bcur_ctx* ctx, const float* A, int64_t m, int64_t n
     int64_t* d_rows;
     uint64_t* d_rdr;
     int *infoR, *infoW;
-    float *R0, *RT, *Vk, *Cbuf, *Ubuf, *P32;
+    float *R0, *RT, *Vk, *Cbuf, *Ubuf, *P32, *Vp = nullptr;
+    int64_t* d_cmap = nullptr;
     const bool chol_scores = kr == r;
     const int gwW = gram_wgs(std::max(r, cmax));
     void *jwsR, *jwsW;
@@ -1635,6 +1650,10 @@ static bcur_status alg1_impl(bcur_ctx* ctx, const float* A, int64_t m, int64_t n
         WksR = a.take<double>(r * kr);
         jwsR = a.take<double>((jacobi_ws_bytes(r) + 7) / 8);
         Vk = a.take<float>(n * kr);
+        if (p->col_map) {
+            d_cmap = a.take<int64_t>(n);
+            Vp = a.take<float>(n * kr);
+        }
         Cbuf = a.take<float>(m * round4(cmax));
         dscale = a.take<double>(cmax);
         Wx = a.take<double>(cmax * r);
@@ -1665,7 +1684,7 @@ static bcur_status alg1_impl(bcur_ctx* ctx, const float* A, int64_t m, int64_t n
     const char* span2_0 = reinterpret_cast<const char*>(errv);
     const size_t span2 = (size_t)(reinterpret_cast<const char*>(infoW + 8) - span2_0);
     // pinned staging: offsets | draws | columns and their scales | the two read-back spans
-    const size_t pin_need = 8 * (G + 1) + 8 * (r + s) + 16 * cmax + span1 + span2 + 64;
+    const size_t pin_need = 8 * (G + 1) + 8 * (r + s) + 16 * cmax + span1 + span2 + 64 + (p->col_map ? 8 * n : 0);
     STCHK(reserve_pinned(ctx, pin_need));
     if (ctx->pinned_busy) HIPCHK(hipStreamSynchronize(st));
     ctx->pinned_busy = true;
@@ -1691,6 +1710,11 @@ static bcur_status alg1_impl(bcur_ctx* ctx, const float* A, int64_t m, int64_t n
     HIPCHK(hipMemsetAsync(sc.st, 0, 4 * sizeof(int), st));
     HIPCHK(hipMemsetAsync(infoR, 0, 4 * sizeof(int), st));
     HIPCHK(hipMemsetAsync(infoW, 0, 8 * sizeof(int), st));
+    if (p->col_map) {
+        int64_t* h_cm = reinterpret_cast<int64_t*>(ptake(8 * n));
+        memcpy(h_cm, p->col_map, n * sizeof(int64_t));
+        HIPCHK(hipMemcpyAsync(d_cmap, h_cm, n * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    }
 
     // ||A||_F^2
     {
@@ -1726,7 +1750,8 @@ static bcur_status alg1_impl(bcur_ctx* ctx, const float* A, int64_t m, int64_t n
     }
     {
         StageScope ts(ctx, BCUR_STAGE_SCORES);
-        HIPCHK(launch_block_scores(Vk, kr, kr, sc.off, G, sc.sc, st));
+        if (d_cmap) HIPCHK(launch_gather_rows(Vk, kr, kr, d_cmap, n, Vp, kr, st));
+        HIPCHK(launch_block_scores(d_cmap ? Vp : Vk, kr, kr, sc.off, G, sc.sc, st));
     }
     {
         StageScope ts(ctx, BCUR_STAGE_SAMPLE);
@@ -1756,7 +1781,7 @@ static bcur_status alg1_impl(bcur_ctx* ctx, const float* A, int64_t m, int64_t n
         if (dup) continue;
         const double wj = isfinite(hw[t]) ? hw[t] : 1.0;
         for (int64_t col = col_off[j]; col < col_off[j + 1]; ++col) {
-            h_cols[c] = col;
+            h_cols[c] = p->col_map ? p->col_map[col] : col;
             h_scale[c] = wj;
             ++c;
         }

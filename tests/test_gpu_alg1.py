@@ -261,3 +261,24 @@ def test_alg1_boost(ctx, t):
     Ug = res["U"][: res["c"], :r].cpu().numpy().astype(np.float64)
     e_own = own_err(A, cols, res["rows"], Ug)
     assert abs(res["err"] - e_own) <= err_tol(e_own, frob2)
+
+
+def test_alg1_with_column_map(ctx):
+    """Blocks of scattered columns: the result equals the oracle's on A with
+    its columns listed in map order (the chosen columns map back to A)."""
+    A = lowrank(500, 240, 20, 1e-3, 19)
+    off = gen.contiguous_blocks(240, 8)
+    cmap = np.random.default_rng(119).permutation(240)
+    r, s, kr = 40, 4, 12
+    dr = gen.draws_u64(r + s, 19)
+    res = ctx.decompose_alg1(dev(A), off, r, s, dr, kr=kr, col_map=cmap)
+    ref = O.alg1(A[:, cmap], off, r, s, None, dr, kr=kr)
+    assert np.array_equal(res["rows"], ref["rows"])
+    note(f"alg1 mapped: idx gpu={list(res['idx'])} oracle={list(ref['idx'])} margin={ref['margins'].min():.2e}")
+    if ref["margins"].min() > 1e-3:
+        assert np.array_equal(res["idx"], ref["idx"])
+        cols = cmap[ref["cols"]]
+        Ug = res["U"][: res["c"], :r].cpu().numpy().astype(np.float64)
+        e_own = own_err(A, cols, res["rows"], Ug)
+        assert abs(res["err"] - e_own) <= err_tol(e_own, ref["frob2"])
+        assert abs(res["err"] - ref["err"]) <= err_tol(ref["err"], ref["frob2"]) + 1e-6 * ref["err"]

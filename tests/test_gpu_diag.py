@@ -124,3 +124,12 @@ def test_diagnostics_of_the_sketched_subspaces(ctx):
     ref = O.incoherence(U.astype(np.float64))
     note(f"incoherence of the sketched U_k: {mu:.9g} oracle {ref:.9g} (bound [1, m/k = {w.m / w.k:.0f}])")
     assert abs(mu - ref) <= 1e-12 * ref
+
+
+def test_stable_rank_with_column_map(ctx):
+    V = orthonormal(512, 20, 10)
+    off = gen.contiguous_blocks(512, 16)
+    cmap = np.random.default_rng(110).permutation(512)
+    alpha, ratios = ctx.block_stable_rank(dev(V), off, col_map=cmap)
+    a_ref, r_ref = O.block_stable_rank(V.astype(np.float64)[cmap], off)
+    assert np.max(np.abs(ratios - r_ref) / r_ref) <= 1e-9 and abs(alpha - a_ref) <= 1e-9 * a_ref
