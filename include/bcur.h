@@ -173,8 +173,8 @@ bcur_status bcur_gather_columns(bcur_ctx* ctx, const float* A, int64_t m, int64_
 /* U = C^+ A (Sec. 2.1 pseudoinverse; the block column-subset-selection fit
  * of the Remark in Sec. 3.3) by the normal equations: H = C^T A and
  * C^T C on the MFMA units, a float64 Cholesky inverse of C^T C, then
- * `refine` (0 or 1) steps of iterative refinement with the explicit residual
- * E = A - C U.  err = ||A - C U||_F.  The accuracy of U is about
+ * `refine` (0 or 1) steps of iterative refinement whose right-hand side
+ * C^T (A - C U) is formed as H - (C^T C) U.  err = ||A - C U||_F.  The accuracy of U is about
  * u32 cond(C)^2 relative.  When pivots of C^T C are dropped
  * (BCUR_FLAG_RANKDEF_C: C numerically rank-deficient) or their spread says
  * the FP32 normal equations are inaccurate (BCUR_FLAG_ILLCOND_C), the fit is
@@ -226,8 +226,8 @@ enum {
     BCUR_STAGE_FIT_REDUCE = 10, /* split-K sums of the fit GEMMs */
     BCUR_STAGE_FIT_INV = 11,  /* (C^T C)^-1: blocked FP64 Cholesky inverse */
     BCUR_STAGE_FIT_U = 12,    /* U = X^T (X H), X = L^-1, G = L L^T */
-    BCUR_STAGE_FIT_E = 13,    /* E = A - C U with ||E||_F^2 */
-    BCUR_STAGE_FIT_F = 14,    /* F = C^T E, main GEMM kernel */
+    BCUR_STAGE_FIT_E = 13,    /* ||A - C U||_F^2 (the residual is not stored) */
+    BCUR_STAGE_FIT_F = 14,    /* F = C^T (A - C U), formed as H - (C^T C) U */
     BCUR_STAGE_FIT_DU = 15,   /* U += X^T (X F) with <X^T X F, F> */
     BCUR_STAGE_RF_CAST = 16,  /* BF16 copies of A and of the sketch panels */
     BCUR_STAGE_A1_ROWS = 17,  /* Algorithm 1: uniform row draws, R = A[rows, :] and its transpose */

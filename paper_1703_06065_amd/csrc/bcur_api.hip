@@ -393,8 +393,8 @@ bcur_status range_finder_run(bcur_ctx* ctx, const RFBufs& b, const float* A, int
 constexpr int64_t kFbPanel = 1024;  // columns of A per FP64 fallback panel
 
 struct FitBufs {
-    float *H, *E, *F, *X32, *part, *Gtmp;
-    double *G, *spdws, *wsE, *wsD, *errv, *piv;
+    float *H, *F, *X32, *G32, *part, *Gtmp;
+    double *G, *spdws, *wsE, *wsD, *wsF, *errv, *piv;
     // FP64 Cholesky QR2 fallback for a numerically rank-deficient or
     // ill-conditioned C: its Gram matrix, L1^-1, Q1 = C L1^-T, two c x kFbPanel panels
     double *Gc64, *L1, *Q1, *T1, *T2;
@@ -405,9 +405,9 @@ struct FitBufs {
 void fit_layout(Arena& a, FitBufs& b, int64_t m, int64_t n, int64_t c, bool need_gtmp) {
     const int64_t np = round4(n), cp = round4(c);
     b.H = a.take<float>(c * np);
-    b.E = a.take<float>(m * np);
     b.F = a.take<float>(c * np);
     b.X32 = a.take<float>(c * cp);
+    b.G32 = a.take<float>(c * cp);
     const GemmPlan ph = plan_sgemm(c, n, m, true, true);
     const GemmPlan pg = plan_sgemm(c, c, m, true, true);
     const GemmPlan pu = plan_sgemm(c, n, c, true, true);
@@ -421,6 +421,7 @@ void fit_layout(Arena& a, FitBufs& b, int64_t m, int64_t n, int64_t c, bool need
     b.nwsD = add_dot_parts(pu, c, n);
     b.wsE = a.take<double>(b.nwsE);
     b.wsD = a.take<double>(b.nwsD);
+    b.wsF = a.take<double>(resid_parts(c, n, c));
     b.errv = a.take<double>(8);
     b.piv = a.take<double>(2 * ((c + 63) / 64));
     b.info = a.take<int>(4);
@@ -433,7 +434,8 @@ void fit_layout(Arena& a, FitBufs& b, int64_t m, int64_t n, int64_t c, bool need
 
 // U = C^+ A through the normal equations with one optional refinement step:
 // G = C^T C = L L^T (FP64), X = L^-1 rounded to FP32 (G^-1 = X^T X), U = X^T (X H)
-// and dU = X^T (X F), each as two FP32 GEMMs.
+// and dU = X^T (X F), each as two FP32 GEMMs, with the refinement's right-hand
+// side F = C^T (A - C U) formed as H - G U (G as factored, in FP32).
 // When d_cols (device, c) gives C's columns within A (C = A[:, cols]), C^T C
 // is read off H = C^T A; otherwise (d_cols null, d_ident = 0..c-1) it is
 // formed by its own GEMM into Gtmp.  After the caller synchronizes,
@@ -464,6 +466,9 @@ bcur_status fit_run(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t m, 
                                 0, nullptr, st));
             HIPCHK(launch_gram_from_cols(b.Gtmp, cp, d_ident, c, b.G, st));
         }
+        // G as factored, in FP32, for the refinement's F = H - G U (its entries are
+        // FP32 values: read off H or formed by an FP32 GEMM)
+        if (refine) HIPCHK(launch_f64_to_f32_2d(b.G, c, c, c, b.G32, cp, st));
         double* Linv = nullptr;
         HIPCHK(launch_chol_linv(b.G, c, b.spdws, b.info, b.piv, ldexp(1.0, -24), &Linv, st));
         HIPCHK(launch_f64_to_f32_2d(Linv, c, c, c, b.X32, cp, st));
@@ -474,13 +479,20 @@ bcur_status fit_run(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t m, 
                      b.part));
     STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_U, BCUR_STAGE_FIT_REDUCE, pt, c, n, c, true, b.X32, cp, b.F, np, U, ldu,
                      b.part));
+    // ||A - C U||_F^2 (the residual itself is never stored)
     const GemmPlan pe = plan_sgemm(m, n, c, false, false);
-    STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_E, BCUR_STAGE_FIT_REDUCE, pe, m, n, c, false, C, ldc, U, ldu, b.E, np, nullptr,
-                     EPI_RESID, A, lda, nullptr, 0, b.wsE));
+    STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_E, BCUR_STAGE_FIT_REDUCE, pe, m, n, c, false, C, ldc, U, ldu, nullptr, 0,
+                     nullptr, EPI_RESID_NORM, A, lda, nullptr, 0, b.wsE));
     if (refine) {
-        STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_F, BCUR_STAGE_FIT_REDUCE, ph, c, n, m, true, C, ldc, b.E, np, b.F, np,
-                         b.part));
-        // W = X F (in H, no longer needed), U += X^T W with <X^T W, F>
+        // F = C^T (A - C U) = H - G U from the products already formed: a c x n x c
+        // GEMM in place of a second 2 m c n pass over the m x n residual
+        {
+            StageScope ts(ctx, BCUR_STAGE_FIT_F);
+            const GemmPlan pf = plan_sgemm(c, n, c, false, false);
+            HIPCHK(launch_sgemm(pf, c, n, c, false, b.G32, cp, U, ldu, b.F, np, nullptr, EPI_RESID, H, np, nullptr, 0,
+                                b.wsF, st));
+        }
+        // W = X F (in H's buffer, or b.H when H was the caller's), U += X^T W with <X^T W, F>
         StageScope ts(ctx, BCUR_STAGE_FIT_DU);
         HIPCHK(launch_sgemm(pw, c, n, c, false, b.X32, cp, b.F, np, b.H, np, b.part, EPI_STORE, nullptr, 0, nullptr, 0,
                             nullptr, st));
@@ -529,8 +541,8 @@ bcur_status fit_fallback64(bcur_ctx* ctx, const FitBufs& b, const float* A, int6
         }
     }
     const GemmPlan pe = plan_sgemm(m, n, c, false, false);
-    STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_E, BCUR_STAGE_FIT_REDUCE, pe, m, n, c, false, C, ldc, U, ldu, b.E, round4(n),
-                     nullptr, EPI_RESID, A, lda, nullptr, 0, b.wsE));
+    STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_E, BCUR_STAGE_FIT_REDUCE, pe, m, n, c, false, C, ldc, U, ldu, nullptr, 0,
+                     nullptr, EPI_RESID_NORM, A, lda, nullptr, 0, b.wsE));
     HIPCHK(launch_fit_err(b.wsE, b.nwsE, b.wsD, 0, b.errv, st));
     double hv[3];
     HIPCHK(hipMemcpyAsync(hv, b.errv, sizeof hv, hipMemcpyDeviceToHost, st));
@@ -572,7 +584,7 @@ bcur_status fit_collect(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t
 // ---- row-block variant: U = C^+ A R^+ -------------------------------------
 
 struct CurBufs {
-    float *R, *W32, *E;
+    float *R, *W32;
     double *Gc, *Gr, *Grinv, *B, *X, *Q1, *L1, *H2, *T1, *U0, *Wd, *spc, *spr, *wsE, *errv, *pivc, *pivr;
     int* info;
 };
@@ -580,7 +592,6 @@ struct CurBufs {
 void cur_layout(Arena& a, CurBufs& b, int64_t m, int64_t n, int64_t c, int64_t r) {
     b.R = a.take<float>(r * round4(n));
     b.W32 = a.take<float>(m * round4(r));
-    b.E = a.take<float>(m * round4(n));
     b.Gc = a.take<double>(c * c);
     b.Gr = a.take<double>(r * r);
     b.Grinv = a.take<double>(r * r);
@@ -652,8 +663,8 @@ bcur_status fit_cur_run(bcur_ctx* ctx, const CurBufs& b, const float* A, int64_t
         if (U) HIPCHK(launch_f64_to_f32_2d(b.U0, c, r, r, U, ldu, st));
     }
     const GemmPlan pe = plan_sgemm(m, n, r, false, false);
-    STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_E, BCUR_STAGE_FIT_REDUCE, pe, m, n, r, false, b.W32, rp, b.R, ldr, b.E,
-                     round4(n), nullptr, EPI_RESID, A, lda, nullptr, 0, b.wsE));
+    STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_E, BCUR_STAGE_FIT_REDUCE, pe, m, n, r, false, b.W32, rp, b.R, ldr, nullptr,
+                     0, nullptr, EPI_RESID_NORM, A, lda, nullptr, 0, b.wsE));
     HIPCHK(launch_fit_err(b.wsE, resid_parts(m, n, r), b.wsE, 0, b.errv, st));
     return BCUR_OK;
 }

@@ -1,8 +1,9 @@
 // FP32 GEMMs on the CDNA4 matrix cores (v_mfma_f32_32x32x2_f32, FP32
 // accumulation) for every contraction of the Block CUR path:
 //   Z = A Q, Y = A^T Z          (range finder passes, N = sketch width)
-//   H = C^T A, F = C^T E        (fit: projection onto the chosen columns)
-//   U = Ginv H, E = A - C U     (fit: solve and residual, fused norm)
+//   H = C^T A                   (fit: projection onto the chosen columns)
+//   U = X^T (X H), ||A - C U||  (fit: solve and residual norm)
+//   F = H - G U                 (fit: the refinement's right-hand side)
 // D = op(A) B with op(A) = A (M x K) or A^T (A stored K x M), B is K x N; all
 // operands row-major.  Tiles are staged through LDS in k-major order so each
 // MFMA operand read is 32 consecutive floats.  Split-K writes partial tiles
@@ -299,8 +300,8 @@ hipError_t run(const GemmArgs& a, dim3 grid, hipStream_t st) {
 GemmPlan plan_sgemm(int64_t M, int64_t N, int64_t K, bool transA, bool allow_split) {
     GemmPlan p;
     p.cfg = N <= 64 ? 0 : (N <= 128 ? 1 : 2);
-    // wide products with A transposed, more than 128 rows and a long K (H = C^T A,
-    // F = C^T E): 256 x 128 tiles of eight waves, so the long operand is streamed
+    // wide products with A transposed, more than 128 rows and a long K
+    // (H = C^T A): 256 x 128 tiles of eight waves, so the long operand is streamed
     // half as often; the split-K target counts workgroups of eight waves
     if (transA && M > 128 && N > 128 && K >= 2048) p.cfg = 3;
     const int64_t tiles = ((M + kCfg[p.cfg].BM - 1) / kCfg[p.cfg].BM) * ((N + kCfg[p.cfg].BN - 1) / kCfg[p.cfg].BN);

@@ -77,7 +77,7 @@ def test_budget_and_refusal():
     budget = int(max(fps) * 1.2)
     note(f"footprints {fps} budget {budget}")
     # a request whose own footprint exceeds the budget must be refused
-    big = gen.serving_request(99, (4096, 4096), (2048, 2048))
+    big = gen.serving_request(99, (8192, 8192), (4096, 4096))
     prm = binding.Params(k=big.k, s=big.s, l=big.l, q=big.q, replace=0, precision=0, refine=1, reserved=0, s_r=0)
     b = ctypes.c_size_t()
     off = np.ascontiguousarray(big.offsets, dtype=np.int64)
