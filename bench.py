@@ -30,12 +30,11 @@ def algorithmic_flops(m, n, k, l, q, c):
     return rf, fit
 
 
-# HBM bytes per launch of the dominant kernel from rocprofv3 counter runs of
-# this command (FETCH_SIZE and WRITE_SIZE, KiB per H / F dispatch: 256
-# workgroups of 512 threads), each scaled by the same counter's reading for a
-# plain copy of known size; None when the kernel has changed since the
-# counters were taken.
-TRAFFIC = {"m": 8192, "n": 4096, "c": 256, "fetch_kib": 98381.5, "write_kib": 32768.0,
+# HBM bytes per launch of the dominant kernel (the residual GEMM) from
+# rocprofv3 counter runs of this command (FETCH_SIZE and WRITE_SIZE, KiB per
+# dispatch), each scaled by the same counter's reading for a plain copy of
+# known size; None when the kernel has changed since the counters were taken.
+TRAFFIC = {"m": 8192, "n": 4096, "c": 256, "fetch_kib": 92456.1, "write_kib": 64.3,
            "fetch_scale": 262144.0 / 131092.8125, "write_scale": 262144.0 / 262144.0}
 
 
@@ -472,7 +471,7 @@ def main():
         res = ctx.decompose(A, w.offsets, w.k, w.s, om, w.draws, q=w.q, U_out=Ubuf)
     torch.cuda.synchronize()
     # timed region: only the dominant kernel's launch records HIP events
-    ctx.timing_enable(("fit_H",))
+    ctx.timing_enable(("fit_E",))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -492,19 +491,23 @@ def main():
     c = int(res["c"])
     rf_flops, fit_flops = algorithmic_flops(w.m, w.n, w.k, w.l, w.q, c)
 
-    # Roofline of the dominant kernel.  Per decomposition the FP32 MFMA GEMM
-    # k_sgemm<256,128> with A transposed runs once, for H = C^T A (stage
-    # fit_H); the stage brackets exactly that launch (its split-K sum is timed
-    # as fit_reduce), so its HIP events give the average launch time.
+    # Roofline of the dominant kernel: of the kernels that a throughput roofline
+    # bounds (MFMA or HBM), the one with the largest device time per
+    # decomposition is the residual GEMM ||A - C U||_F^2 (k_sgemm<128,128>, NN,
+    # norm-only epilogue: A is read, nothing m x n is written), one launch per
+    # decomposition in stage fit_E.  The one-workgroup FP64 solvers (the l x l
+    # Jacobi of the Rayleigh-Ritz step and the c x c Cholesky inverse) take
+    # longer but are latency-bound: their times are in stage_ms_per_step
+    # (rf_rr, fit_inv).
     per_launch_flop = 2.0 * w.m * c * w.n
-    n_launch = stages["fit_H"][1]
-    avg_ms = stages["fit_H"][0] / max(n_launch, 1)
+    n_launch = stages["fit_E"][1]
+    avg_ms = stages["fit_E"][0] / max(n_launch, 1)
     ach = per_launch_flop / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
     roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
             "frac": round(ach / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": traffic_bytes(w.m, w.n, c),
-            "kernel": "k_sgemm<256,128,16,4,2,TA> (H = C^T A)", "launches_per_step": 1,
-            "avg_ms": round(avg_ms, 5), "flop_per_launch": per_launch_flop,
-            "algorithmic_bytes_per_launch": 4.0 * (w.m * c + w.m * w.n + c * w.n)}
+            "kernel": "k_sgemm<128,128,16,2,2> norm-only residual epilogue (||A - C U||_F^2)",
+            "launches_per_step": 1, "avg_ms": round(avg_ms, 5), "flop_per_launch": per_launch_flop,
+            "algorithmic_bytes_per_launch": 4.0 * (w.m * w.n + w.m * c + c * w.n)}
     out = {
         "metric": "block-CUR decompositions/s",
         "value": args.steps / el,

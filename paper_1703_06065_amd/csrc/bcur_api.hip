@@ -393,7 +393,7 @@ bcur_status range_finder_run(bcur_ctx* ctx, const RFBufs& b, const float* A, int
 constexpr int64_t kFbPanel = 1024;  // columns of A per FP64 fallback panel
 
 struct FitBufs {
-    float *H, *F, *X32, *G32, *part, *Gtmp;
+    float *H, *F, *X32, *G32, *Gi32, *part, *Gtmp;
     double *G, *spdws, *wsE, *wsD, *wsF, *errv, *piv;
     // FP64 Cholesky QR2 fallback for a numerically rank-deficient or
     // ill-conditioned C: its Gram matrix, L1^-1, Q1 = C L1^-T, two c x kFbPanel panels
@@ -408,11 +408,13 @@ void fit_layout(Arena& a, FitBufs& b, int64_t m, int64_t n, int64_t c, bool need
     b.F = a.take<float>(c * np);
     b.X32 = a.take<float>(c * cp);
     b.G32 = a.take<float>(c * cp);
+    b.Gi32 = a.take<float>(c * cp);
     const GemmPlan ph = plan_sgemm(c, n, m, true, true);
     const GemmPlan pg = plan_sgemm(c, c, m, true, true);
-    const GemmPlan pu = plan_sgemm(c, n, c, true, true);
+    const GemmPlan pi = plan_sgemm(c, c, c, true, true);
+    const GemmPlan pu = plan_sgemm(c, n, c, false, true);
     size_t part = std::max(std::max(sgemm_partial_floats(ph, c, n), sgemm_partial_floats(pg, c, c)),
-                           sgemm_partial_floats(pu, c, n));
+                           std::max(sgemm_partial_floats(pu, c, n), sgemm_partial_floats(pi, c, c)));
     b.part = a.take<float>(std::max<size_t>(part, 4));
     b.Gtmp = need_gtmp ? a.take<float>(c * cp) : nullptr;
     b.G = a.take<double>(c * c);
@@ -433,16 +435,17 @@ void fit_layout(Arena& a, FitBufs& b, int64_t m, int64_t n, int64_t c, bool need
 }
 
 // U = C^+ A through the normal equations with one optional refinement step:
-// G = C^T C = L L^T (FP64), X = L^-1 rounded to FP32 (G^-1 = X^T X), U = X^T (X H)
-// and dU = X^T (X F), each as two FP32 GEMMs, with the refinement's right-hand
-// side F = C^T (A - C U) formed as H - G U (G as factored, in FP32).
+// G = C^T C = L L^T (FP64), X = L^-1 rounded to FP32, G^-1 = X^T X formed in
+// FP32 (one c x c x c product), U = G^-1 H and dU = G^-1 F, with the
+// refinement's right-hand side F = C^T (A - C U) formed as H - G U (G as
+// factored, in FP32).
 // When d_cols (device, c) gives C's columns within A (C = A[:, cols]), C^T C
 // is read off H = C^T A; otherwise (d_cols null, d_ident = 0..c-1) it is
 // formed by its own GEMM into Gtmp.  After the caller synchronizes,
 // b.errv[0] = ||E||^2 - <F, dU> (err^2 after the refinement), b.errv[1] =
 // ||E||^2 (before it), b.info[0] bit 0 = pivots dropped, b.piv = pivot ranges.
 // Hpre: H = C^T A already computed by the caller (c x n, ld round4(n)); b.H is
-// then only scratch.
+// then unused.
 bcur_status fit_run(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t m, int64_t n, int64_t lda, const float* C,
                     int64_t c, int64_t ldc, const int64_t* d_cols, const int64_t* d_ident, int refine, float* U,
                     int64_t ldu, const float* Hpre = nullptr) {
@@ -472,12 +475,14 @@ bcur_status fit_run(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t m, 
         double* Linv = nullptr;
         HIPCHK(launch_chol_linv(b.G, c, b.spdws, b.info, b.piv, ldexp(1.0, -24), &Linv, st));
         HIPCHK(launch_f64_to_f32_2d(Linv, c, c, c, b.X32, cp, st));
+        // G^-1 = X^T X (X is zero above its diagonal)
+        const GemmPlan pi = plan_sgemm(c, c, c, true, true);
+        HIPCHK(launch_sgemm(pi, c, c, c, true, b.X32, cp, b.X32, cp, b.Gi32, cp, b.part, EPI_STORE, nullptr, 0,
+                            nullptr, 0, nullptr, st));
     }
-    // W = X H (in F, not yet needed), U = X^T W
-    const GemmPlan pw = plan_sgemm(c, n, c, false, true), pt = plan_sgemm(c, n, c, true, true);
-    STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_U, BCUR_STAGE_FIT_REDUCE, pw, c, n, c, false, b.X32, cp, H, np, b.F, np,
-                     b.part));
-    STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_U, BCUR_STAGE_FIT_REDUCE, pt, c, n, c, true, b.X32, cp, b.F, np, U, ldu,
+    // U = G^-1 H
+    const GemmPlan pu = plan_sgemm(c, n, c, false, true);
+    STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_U, BCUR_STAGE_FIT_REDUCE, pu, c, n, c, false, b.Gi32, cp, H, np, U, ldu,
                      b.part));
     // ||A - C U||_F^2 (the residual itself is never stored)
     const GemmPlan pe = plan_sgemm(m, n, c, false, false);
@@ -488,19 +493,17 @@ bcur_status fit_run(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t m, 
         // GEMM in place of a second 2 m c n pass over the m x n residual
         {
             StageScope ts(ctx, BCUR_STAGE_FIT_F);
-            const GemmPlan pf = plan_sgemm(c, n, c, false, false);
-            HIPCHK(launch_sgemm(pf, c, n, c, false, b.G32, cp, U, ldu, b.F, np, nullptr, EPI_RESID, H, np, nullptr, 0,
+            const GemmPlan pf = plan_sgemm(c, n, c, false, true);
+            HIPCHK(launch_sgemm(pf, c, n, c, false, b.G32, cp, U, ldu, b.F, np, b.part, EPI_RESID, H, np, nullptr, 0,
                                 b.wsF, st));
         }
-        // W = X F (in H's buffer, or b.H when H was the caller's), U += X^T W with <X^T W, F>
+        // U += G^-1 F with <G^-1 F, F>
         StageScope ts(ctx, BCUR_STAGE_FIT_DU);
-        HIPCHK(launch_sgemm(pw, c, n, c, false, b.X32, cp, b.F, np, b.H, np, b.part, EPI_STORE, nullptr, 0, nullptr, 0,
-                            nullptr, st));
-        HIPCHK(launch_sgemm_add_dot(pt, c, n, c, true, b.X32, cp, b.H, np, U, ldu, b.part, U, ldu, b.F, np, b.wsD,
+        HIPCHK(launch_sgemm_add_dot(pu, c, n, c, false, b.Gi32, cp, b.F, np, U, ldu, b.part, U, ldu, b.F, np, b.wsD,
                                     st));
     }
     // one partial per workgroup of the residual GEMM, and of the dU sum
-    HIPCHK(launch_fit_err(b.wsE, resid_parts(m, n, c), b.wsD, refine ? add_dot_parts(pt, c, n) : 0, b.errv, st));
+    HIPCHK(launch_fit_err(b.wsE, resid_parts(m, n, c), b.wsD, refine ? add_dot_parts(pu, c, n) : 0, b.errv, st));
     return BCUR_OK;
 }
 

@@ -57,7 +57,8 @@ size_t sgemm_partial_floats(const GemmPlan& p, int64_t M, int64_t N);
 // EPI_STORE_SQA (A not transposed): as EPI_STORE, and wsum[wg] (one per workgroup of the grid,
 // p.wgs in all, split-K included) = the FP64 sum of squares of the A elements that workgroup
 // loaded, so that the sum over all of them is ||A||_F^2.
-// EPI_ADD_DOT: D = X + acc, wsum[wg] = sum acc * Y.   Epilogues need splits == 1.
+// EPI_ADD_DOT: D = X + acc, wsum[wg] = sum acc * Y.   Epilogues need splits == 1 here;
+// launch_sgemm also takes EPI_RESID with split-K (D = X - the split sum, no wsum written).
 // main kernel only (partial tiles when split) and the split-K sum
 hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K, bool transA, const float* A,
                              int64_t lda, const float* B, int64_t ldb, float* D, int64_t ldd, float* partial,

@@ -244,6 +244,20 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const float* __restrict__
     }
 }
 
+// The split-K sum with the EPI_RESID epilogue: D = X - sum_s P[s] in the order
+// s = 0, 1, ...
+__global__ __launch_bounds__(256) void k_splitk_reduce_sub(const float* __restrict__ P, int splits, int64_t stride,
+                                                           int64_t M, int64_t N, float* __restrict__ D, int64_t ldd,
+                                                           const float* __restrict__ X, int64_t ldx) {
+    const int64_t total = M * N;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        float s = P[e];
+        for (int z = 1; z < splits; ++z) s += P[z * stride + e];
+        const int64_t row = e / N, col = e - row * N;
+        D[row * ldd + col] = X[row * ldx + col] - s;
+    }
+}
+
 // The split-K sum with the EPI_ADD_DOT epilogue: D = X + S, S = sum_s P[s] in
 // the order s = 0, 1, ..., and wsum[block] = sum of S * Y over the block's
 // elements (each thread's in order, then the threads in a fixed tree).
@@ -307,7 +321,21 @@ GemmPlan plan_sgemm(int64_t M, int64_t N, int64_t K, bool transA, bool allow_spl
     const int64_t tiles = ((M + kCfg[p.cfg].BM - 1) / kCfg[p.cfg].BM) * ((N + kCfg[p.cfg].BN - 1) / kCfg[p.cfg].BN);
     const int64_t target = p.cfg == 3 ? 256 : 512;
     int64_t splits = 1;
-    if (allow_split && tiles < target - 32) {
+    if (p.cfg == 3 && allow_split) {
+        // one workgroup of eight waves fills a compute unit: pick the split
+        // count that minimises (rounds of 256 workgroups) x (K per workgroup +
+        // a fixed cost of about 64 K steps), so no round runs mostly empty
+        const int64_t maxs = std::max<int64_t>(1, K / (4 * kBK));
+        int64_t best = -1;
+        for (int64_t s = 1; s <= maxs; ++s) {
+            const int64_t kc = ((K + s - 1) / s + kBK - 1) / kBK * kBK;
+            const int64_t cost = ((tiles * s + 255) / 256) * (kc + 64);
+            if (best < 0 || cost < best) {
+                best = cost;
+                splits = s;
+            }
+        }
+    } else if (allow_split && tiles < target - 32) {
         splits = (target + tiles - 1) / tiles;
         const int64_t maxs = K / (4 * kBK);
         if (splits > maxs) splits = maxs;
@@ -358,7 +386,6 @@ hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K,
         a.ldd = ldd;
         a.split_stride = 0;
     }
-    // the fused epilogues exist for the square tile only
     // the fused epilogues exist for the square tile only (a 256 x 128 residual
     // tile measured slower: 202 us against 192 us for E = A - C U at 8192 x 4096 x 256)
     const int cfg = store_like ? p.cfg : 2;
@@ -423,6 +450,19 @@ hipError_t launch_sgemm_add_dot(const GemmPlan& p, int64_t M, int64_t N, int64_t
 hipError_t launch_sgemm(const GemmPlan& p, int64_t M, int64_t N, int64_t K, bool transA, const float* A, int64_t lda,
                         const float* B, int64_t ldb, float* D, int64_t ldd, float* partial, int epi, const float* X,
                         int64_t ldx, const float* Y, int64_t ldy, double* wsum, hipStream_t st) {
+    if (epi == EPI_RESID && p.splits > 1) {
+        // D = X - A B split over K: partial products, then the subtracting sum
+        // (no sum of squares: wsum is not written on this path)
+        if (M <= 0 || N <= 0) return hipSuccess;
+        const hipError_t e = launch_sgemm_main(p, M, N, K, transA, A, lda, B, ldb, D, ldd, partial, EPI_STORE,
+                                               nullptr, 0, nullptr, 0, nullptr, st);
+        if (e != hipSuccess) return e;
+        int64_t blocks = (M * N + 255) / 256;
+        if (blocks > 8192) blocks = 8192;
+        hipLaunchKernelGGL(k_splitk_reduce_sub, dim3((unsigned)blocks), dim3(256), 0, st, partial, p.splits, M * N, M,
+                           N, D, ldd, X, ldx);
+        return hipGetLastError();
+    }
     const hipError_t e = launch_sgemm_main(p, M, N, K, transA, A, lda, B, ldb, D, ldd, partial, epi, X, ldx, Y, ldy,
                                            wsum, st);
     if (e != hipSuccess) return e;
