@@ -271,12 +271,16 @@ __global__ __launch_bounds__(256) void k_apply_small(const float* __restrict__ X
 // A pair (x, y) is rotated when |a_xy| > 2^-40 ||T||_F and |a_xy| > 1e-15
 // sqrt|a_xx a_yy|, from T scaled by 1 / ||T||_F.  The iteration stops once L - 1
 // consecutive rounds rotate nothing: then T did not change during them and
-// every pair was found below the threshold.  The tangent t is estimated in FP32
+// every pair was found below the threshold.  It also stops as soon as every
+// off-diagonal entry is at most 2^-40 ||T||_F, which every wave checks on the
+// blocks it writes every kJCheck rounds: then no pair can rotate again, so the
+// rounds that would follow are identities and the result is the same.  The tangent t is estimated in FP32
 // and refined by one Newton step to about 2^-46; c = 1/sqrt(1 + t^2) and s = t c
 // are formed in FP64 with a Newton-refined estimate, so every rotation is
 // orthogonal to FP64 precision.  The entry left by the slightly inexact angle
 // is kept, not forced to zero, so no backward error is introduced.
 constexpr int kJSweeps = 40;  // at most kJSweeps (L - 1) rounds
+constexpr int kJCheck = 8;    // rounds between the all-entries convergence checks
 
 // Indices (x, y) of pair slot t in round rd: x_0 = 0, x_t = 1 + (t - 1 + rd)
 // mod (L - 1), y_t = 1 + (L - 2 - t + rd) mod (L - 1); advanced by one round
@@ -387,6 +391,7 @@ __global__ __launch_bounds__(NT) void k_jacobi_rr(const double* __restrict__ Tin
     __shared__ double2 cs[2][64];  // one entry per lane of wave 0; slots >= H are never read
     __shared__ double sred[NT / 64];
     __shared__ int stop[2];
+    __shared__ int cflag[2][NT / 64];  // per wave: an entry it wrote is above the floor
     __shared__ int posof[KL];
     if (gate && *gate == 0) return;
     const int tid = threadIdx.x;
@@ -464,9 +469,17 @@ __global__ __launch_bounds__(NT) void k_jacobi_rr(const double* __restrict__ Tin
         bool any = __ballot(cst.y != 0.0) != 0;
         int quiet = any ? 0 : 1, last_active = any ? 1 : 0;
         if (t == 0) stop[0] = quiet >= L - 1;
+        bool conv = false;
         __syncthreads();
-        for (; r < Rmax && quiet < L - 1; ++r) {
+        for (; r < Rmax && quiet < L - 1 && !conv; ++r) {
             const int p = r & 1, q = p ^ 1;
+            // the flags of the round before, when it was a check round
+            const bool chk = r > 0 && r % kJCheck == 0;
+            int cf = 0;
+            if (chk) {
+#pragma unroll
+                for (int w = 0; w < NT / 64; ++w) cf |= cflag[q][w];
+            }
             T = Tb[cur];
             const double2* T2 = reinterpret_cast<const double2*>(T);
             double* Tn = Tb[cur ^ 1];
@@ -496,6 +509,13 @@ __global__ __launch_bounds__(NT) void k_jacobi_rr(const double* __restrict__ Tin
             Tn[dw3] = r11;
 #pragma unroll
             for (int e = 0; e < 4; ++e) Tn[owx[e]] = o[e];
+            if (r % kJCheck == kJCheck - 1) {
+                bool big = act_t && fabs(r01) * inv > floor_s;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) big = big || (has_off && fabs(o[e]) * inv > floor_s);
+                const int f = __ballot(big) != 0;
+                if (t == 0) cflag[p][0] = f;
+            }
             // entries of slot t in the next round
             double xx, yy, xy;
             if (H == 1) {
@@ -523,7 +543,8 @@ __global__ __launch_bounds__(NT) void k_jacobi_rr(const double* __restrict__ Tin
                 if (act_t) rot[(int64_t)(r + 1) * H + t] = cst;
                 if (any) last_active = r + 2;
             }
-            if (t == 0) stop[q] = quiet >= L - 1;
+            conv = chk && cf == 0;
+            if (t == 0) stop[q] = quiet >= L - 1 || conv;
             cur ^= 1;
             __syncthreads();
         }
@@ -582,13 +603,21 @@ __global__ __launch_bounds__(NT) void k_jacobi_rr(const double* __restrict__ Tin
                 rv[b] = cs[p][buv[b] >> 8];
             }
             if (halt) break;
+            bool big = false;
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 if (!bok[b]) continue;
                 double o[4];
                 rot_block(x[b], ru[b].x, ru[b].y, rv[b].x, rv[b].y, o);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) Tn[wrx[b][e]] = o[e];
+                for (int e = 0; e < 4; ++e) {
+                    Tn[wrx[b][e]] = o[e];
+                    big = big || fabs(o[e]) * inv > floor_s;
+                }
+            }
+            if (r % kJCheck == kJCheck - 1) {
+                const int f = __ballot(big) != 0;
+                if ((tid & 63) == 0) cflag[p][tid >> 6] = f;
             }
             cur ^= 1;
             __syncthreads();
