@@ -244,6 +244,24 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const float* __restrict__
     }
 }
 
+// The same sum for a contiguous D (ldd = N), four elements per thread: P and D
+// are 16-byte aligned and M N is a multiple of 4, so element e4 covers
+// 4 e4 .. 4 e4 + 3 of every split with one vector load (same order of addition).
+__global__ __launch_bounds__(256) void k_splitk_reduce_v4(const float4* __restrict__ P, int splits, int64_t stride4,
+                                                          int64_t total4, float4* __restrict__ D) {
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total4; e += (int64_t)gridDim.x * 256) {
+        float4 s = P[e];
+        for (int z = 1; z < splits; ++z) {
+            const float4 v = P[z * stride4 + e];
+            s.x += v.x;
+            s.y += v.y;
+            s.z += v.z;
+            s.w += v.w;
+        }
+        D[e] = s;
+    }
+}
+
 // The split-K sum with the EPI_RESID epilogue: D = X - sum_s P[s] in the order
 // s = 0, 1, ...
 __global__ __launch_bounds__(256) void k_splitk_reduce_sub(const float* __restrict__ P, int splits, int64_t stride,
@@ -282,6 +300,62 @@ __global__ __launch_bounds__(256) void k_splitk_reduce_add_dot(const float* __re
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
     if (threadIdx.x == 0) wsum[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// k_splitk_reduce_sub and k_splitk_reduce_add_dot for contiguous D, X and Y
+// (leading dimension N), four elements per thread with vector loads: sub
+// writes D = X - S; add_dot writes D = X + S and wsum[block] = sum of S * Y
+// (each thread's elements in order, then the threads in a fixed tree).
+__global__ __launch_bounds__(256) void k_splitk_reduce_sub_v4(const float4* __restrict__ P, int splits,
+                                                              int64_t stride4, int64_t total4,
+                                                              float4* __restrict__ D, const float4* __restrict__ X) {
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total4; e += (int64_t)gridDim.x * 256) {
+        float4 s = P[e];
+        for (int z = 1; z < splits; ++z) {
+            const float4 v = P[z * stride4 + e];
+            s.x += v.x;
+            s.y += v.y;
+            s.z += v.z;
+            s.w += v.w;
+        }
+        const float4 x = X[e];
+        D[e] = make_float4(x.x - s.x, x.y - s.y, x.z - s.z, x.w - s.w);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_splitk_reduce_add_dot_v4(const float4* __restrict__ P, int splits,
+                                                                  int64_t stride4, int64_t total4, float4* D,
+                                                                  const float4* X, const float4* __restrict__ Y,
+                                                                  double* __restrict__ wsum) {
+    __shared__ double red[4];
+    double acc = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total4; e += (int64_t)gridDim.x * 256) {
+        float4 s = P[e];
+        for (int z = 1; z < splits; ++z) {
+            const float4 v = P[z * stride4 + e];
+            s.x += v.x;
+            s.y += v.y;
+            s.z += v.z;
+            s.w += v.w;
+        }
+        const float4 x = X[e], y = Y[e];
+        D[e] = make_float4(x.x + s.x, x.y + s.y, x.z + s.z, x.w + s.w);
+        acc += (double)s.x * (double)y.x;
+        acc += (double)s.y * (double)y.y;
+        acc += (double)s.z * (double)y.z;
+        acc += (double)s.w * (double)y.w;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) wsum[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+bool contiguous_v4(int64_t M, int64_t N, const void* a, int64_t lda, const void* b, int64_t ldb, const void* c,
+                   int64_t ldc, const void* d) {
+    const auto al = [](const void* q) { return q == nullptr || ((uintptr_t)q & 15) == 0; };
+    return (M * N) % 4 == 0 && lda == N && ldb == N && ldc == N && al(a) && al(b) && al(c) && al(d);
 }
 
 int64_t add_dot_blocks(int64_t M, int64_t N) {
@@ -415,6 +489,15 @@ hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K,
 hipError_t launch_splitk_reduce(const GemmPlan& p, int64_t M, int64_t N, const float* partial, float* D, int64_t ldd,
                                 hipStream_t st) {
     if (p.splits <= 1 || M <= 0 || N <= 0) return hipSuccess;
+    if (ldd == N && (M * N) % 4 == 0 && ((uintptr_t)partial & 15) == 0 && ((uintptr_t)D & 15) == 0) {
+        const int64_t total4 = M * N / 4;
+        int64_t blocks = (total4 + 255) / 256;
+        if (blocks > 8192) blocks = 8192;
+        hipLaunchKernelGGL(k_splitk_reduce_v4, dim3((unsigned)blocks), dim3(256), 0, st,
+                           reinterpret_cast<const float4*>(partial), p.splits, total4, total4,
+                           reinterpret_cast<float4*>(D));
+        return hipGetLastError();
+    }
     int64_t blocks = (M * N + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)blocks), dim3(256), 0, st, partial, p.splits, M * N, M, N, D,
@@ -442,6 +525,14 @@ hipError_t launch_sgemm_add_dot(const GemmPlan& p, int64_t M, int64_t N, int64_t
     const hipError_t e = launch_sgemm_main(p, M, N, K, transA, A, lda, B, ldb, D, ldd, partial, EPI_STORE, nullptr, 0,
                                            nullptr, 0, nullptr, st);
     if (e != hipSuccess) return e;
+    if (contiguous_v4(M, N, D, ldd, X, ldx, Y, ldy, partial)) {
+        const int64_t total4 = M * N / 4;
+        hipLaunchKernelGGL(k_splitk_reduce_add_dot_v4, dim3((unsigned)add_dot_blocks(M, N)), dim3(256), 0, st,
+                           reinterpret_cast<const float4*>(partial), p.splits, total4, total4,
+                           reinterpret_cast<float4*>(D), reinterpret_cast<const float4*>(X),
+                           reinterpret_cast<const float4*>(Y), wsum);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_splitk_reduce_add_dot, dim3((unsigned)add_dot_blocks(M, N)), dim3(256), 0, st, partial,
                        p.splits, M * N, M, N, D, ldd, X, ldx, Y, ldy, wsum);
     return hipGetLastError();
@@ -457,6 +548,15 @@ hipError_t launch_sgemm(const GemmPlan& p, int64_t M, int64_t N, int64_t K, bool
         const hipError_t e = launch_sgemm_main(p, M, N, K, transA, A, lda, B, ldb, D, ldd, partial, EPI_STORE,
                                                nullptr, 0, nullptr, 0, nullptr, st);
         if (e != hipSuccess) return e;
+        if (contiguous_v4(M, N, D, ldd, X, ldx, partial, N, nullptr)) {
+            const int64_t total4 = M * N / 4;
+            int64_t blocks = (total4 + 255) / 256;
+            if (blocks > 8192) blocks = 8192;
+            hipLaunchKernelGGL(k_splitk_reduce_sub_v4, dim3((unsigned)blocks), dim3(256), 0, st,
+                               reinterpret_cast<const float4*>(partial), p.splits, total4, total4,
+                               reinterpret_cast<float4*>(D), reinterpret_cast<const float4*>(X));
+            return hipGetLastError();
+        }
         int64_t blocks = (M * N + 255) / 256;
         if (blocks > 8192) blocks = 8192;
         hipLaunchKernelGGL(k_splitk_reduce_sub, dim3((unsigned)blocks), dim3(256), 0, st, partial, p.splits, M * N, M,
