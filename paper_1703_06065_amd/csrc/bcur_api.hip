@@ -256,9 +256,9 @@ void rf_layout(Arena& a, RFBufs& b, int64_t m, int64_t n, int64_t l, int64_t k, 
     b.Wk = a.take<double>(l * k);
     b.Wks = a.take<double>(l * k);
     b.lam = a.take<double>(l);
+    b.info = a.take<int>(4);  // right after lam: the host fetches both with one copy
     b.sqpart = a.take<double>(plan_sgemm(m, l, n, false, true).wgs);
     b.jws = a.take<double>((jacobi_ws_bytes(l) + 7) / 8);
-    b.info = a.take<int>(4);
 }
 
 // A GEMM whose main kernel is timed as `stage` and its split-K sum as `rstage`.
@@ -556,14 +556,15 @@ bcur_status fit_fallback64(bcur_ctx* ctx, const FitBufs& b, const float* A, int6
 
 bcur_status fit_collect(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t m, int64_t n, int64_t lda,
                         const float* C, int64_t c, int64_t ldc, float* U, int64_t ldu, FitOut* out) {
-    double hv[8];
-    int hinfo[4];
     const int64_t nblk = (c + 63) / 64;
-    std::vector<double> piv(2 * nblk);
-    HIPCHK(hipMemcpyAsync(hv, b.errv, sizeof hv, hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipMemcpyAsync(hinfo, b.info, sizeof hinfo, hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipMemcpyAsync(piv.data(), b.piv, piv.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    // errv, piv and info are consecutive in the workspace: one copy
+    const char* d0 = reinterpret_cast<const char*>(b.errv);
+    std::vector<char> hb((size_t)(reinterpret_cast<const char*>(b.info + 4) - d0));
+    HIPCHK(hipMemcpyAsync(hb.data(), d0, hb.size(), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    const double* hv = reinterpret_cast<const double*>(hb.data());
+    const double* piv = reinterpret_cast<const double*>(hb.data() + (reinterpret_cast<const char*>(b.piv) - d0));
+    const int* hinfo = reinterpret_cast<const int*>(hb.data() + (reinterpret_cast<const char*>(b.info) - d0));
     uint32_t fl = 0;
     if (hinfo[0] & 1) fl |= BCUR_FLAG_RANKDEF_C;
     double pmin = INFINITY, pmax = 0.0;
@@ -1201,8 +1202,9 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
     auto side_bytes = [](int64_t g, int64_t ss, int64_t lm) {
         return 8 * (g + 1) + 8 * ss + (24 * ss + 16 + 8 * g + 16 + 5 * 256) + 8 * lm + 16;
     };
+    // (+256 per merged span: offsets | draws, lam | info keep their workspace padding)
     const size_t pin_need = side_bytes(G, s, cmax) + (rowv ? side_bytes(Gr, s_r, rmax) : 0) + 16 + 8 * l + 64 +
-                            (p->col_map ? 8 * n + 8 : 0) + (rmap_h ? 8 * m + 8 : 0);
+                            (p->col_map ? 8 * n + 8 : 0) + (rmap_h ? 8 * m + 8 : 0) + 3 * 256;
     STCHK(reserve_pinned(ctx, pin_need));
     if (ctx->pinned_busy) HIPCHK(hipStreamSynchronize(st));
     ctx->pinned_busy = true;
@@ -1212,21 +1214,23 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
         pin += (bytes + 7) & ~(size_t)7;
         return p0;
     };
-    int64_t* h_off = reinterpret_cast<int64_t*>(ptake(8 * (G + 1)));
-    uint64_t* h_dr = reinterpret_cast<uint64_t*>(ptake(8 * s));
-    memcpy(h_off, col_off, (G + 1) * sizeof(int64_t));
-    memcpy(h_dr, draws, s * sizeof(uint64_t));
-    HIPCHK(hipMemcpyAsync(sc.off, h_off, (G + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(sc.dr, h_dr, s * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+    // offsets and draws (consecutive in the workspace) go up in one copy per side
+    auto upload_side = [&](const SampleBufs& b, const int64_t* off_src, int64_t g, const uint64_t* dr_src,
+                           int64_t ss) -> int64_t* {
+        const char* d0 = reinterpret_cast<const char*>(b.off);
+        const size_t span = (size_t)(reinterpret_cast<const char*>(b.dr + ss) - d0);
+        char* h0 = ptake(span);
+        int64_t* h_off = reinterpret_cast<int64_t*>(h0);
+        memcpy(h_off, off_src, (g + 1) * sizeof(int64_t));
+        memcpy(h0 + (reinterpret_cast<const char*>(b.dr) - d0), dr_src, ss * sizeof(uint64_t));
+        return hipMemcpyAsync(b.off, h0, span, hipMemcpyHostToDevice, st) == hipSuccess ? h_off : nullptr;
+    };
+    if (!upload_side(sc, col_off, G, draws, s)) return fail(ctx, BCUR_E_HIP, "upload of the offsets failed");
     HIPCHK(hipMemsetAsync(sc.st, 0, 4 * sizeof(int), st));
     int64_t* h_roff = nullptr;
     if (rowv) {
-        h_roff = reinterpret_cast<int64_t*>(ptake(8 * (Gr + 1)));
-        uint64_t* h_drr = reinterpret_cast<uint64_t*>(ptake(8 * s_r));
-        memcpy(h_roff, row_off, (Gr + 1) * sizeof(int64_t));
-        memcpy(h_drr, draws + s, s_r * sizeof(uint64_t));
-        HIPCHK(hipMemcpyAsync(sr.off, h_roff, (Gr + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
-        HIPCHK(hipMemcpyAsync(sr.dr, h_drr, s_r * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+        h_roff = upload_side(sr, row_off, Gr, draws + s, s_r);
+        if (!h_roff) return fail(ctx, BCUR_E_HIP, "upload of the row offsets failed");
         HIPCHK(hipMemsetAsync(sr.st, 0, 4 * sizeof(int), st));
     }
     if (p->col_map) {
@@ -1293,8 +1297,12 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
                                                            (reinterpret_cast<const char*>(d_frob) -
                                                             reinterpret_cast<const char*>(sc.idx)));
     if (rowv) STCHK(stage_side(sr, rmax, reinterpret_cast<const char*>(sr.sc + Gr), hr));
-    double* h_lam = reinterpret_cast<double*>(ptake(8 * l));
-    int* rinfo = reinterpret_cast<int*>(ptake(16));
+    // lam and info (consecutive in the workspace) come back in one copy
+    const char* rf0 = reinterpret_cast<const char*>(rb.lam);
+    const size_t rf_span = (size_t)(reinterpret_cast<const char*>(rb.info + 4) - rf0);
+    char* h_rf = ptake(rf_span);
+    double* h_lam = reinterpret_cast<double*>(h_rf);
+    int* rinfo = reinterpret_cast<int*>(h_rf + (reinterpret_cast<const char*>(rb.info) - rf0));
     // The checks of the draws, once their results are on the host.
     auto check_draws = [&]() -> bcur_status {
         if (!isfinite(h_frob[0])) return fail(ctx, BCUR_E_NONFINITE, "A holds NaN or Inf");
@@ -1343,8 +1351,7 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
         if (rowv) HIPCHK(launch_gather_rows(A, lda, n, sr.list, r, cb.R, round4(n), st));
     }
     // results the host reads after the fit's synchronization
-    HIPCHK(hipMemcpyAsync(h_lam, rb.lam, l * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(rinfo, rb.info, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_rf, rf0, rf_span, hipMemcpyDeviceToHost, st));
     // 6. U and the residual
     float* U = res->U ? res->U : Ubuf;
     const int64_t ldu = res->U ? res->ldu : round4(ucols);
@@ -1473,7 +1480,8 @@ bcur_status bcur_decompose_boost(bcur_ctx* ctx, const float* A, int64_t m, int64
     }
     const char* span0 = reinterpret_cast<const char*>(d_idx);
     const size_t span = (size_t)(reinterpret_cast<const char*>(d_frob + 1) - span0);
-    const size_t pin_need = 8 * (G + 1) + 8 * t * s + 8 * ctot_max + span + 8 * l + 64 + (p->col_map ? 8 * n : 0);
+    const size_t pin_need =
+        8 * (G + 1) + 8 * t * s + 8 * ctot_max + span + 8 * l + 64 + (p->col_map ? 8 * n : 0) + 2 * 256;
     STCHK(reserve_pinned(ctx, pin_need));
     if (ctx->pinned_busy) HIPCHK(hipStreamSynchronize(st));
     ctx->pinned_busy = true;
@@ -1483,17 +1491,24 @@ bcur_status bcur_decompose_boost(bcur_ctx* ctx, const float* A, int64_t m, int64
         pin += (bytes + 7) & ~(size_t)7;
         return p0;
     };
-    int64_t* h_off = reinterpret_cast<int64_t*>(ptake(8 * (G + 1)));
-    uint64_t* h_dr = reinterpret_cast<uint64_t*>(ptake(8 * t * s));
+    // offsets and draws (consecutive in the workspace) go up in one copy
+    const char* in0 = reinterpret_cast<const char*>(d_off);
+    const size_t in_span = (size_t)(reinterpret_cast<const char*>(d_dr + t * s) - in0);
+    char* h_in = ptake(in_span);
+    int64_t* h_off = reinterpret_cast<int64_t*>(h_in);
+    uint64_t* h_dr = reinterpret_cast<uint64_t*>(h_in + (reinterpret_cast<const char*>(d_dr) - in0));
     int64_t* h_list = reinterpret_cast<int64_t*>(ptake(8 * ctot_max));
     char* h0 = ptake(span);
-    double* h_lam = reinterpret_cast<double*>(ptake(8 * l));
-    int* rinfo = reinterpret_cast<int*>(ptake(16));
+    // lam and info (consecutive in the workspace) come back in one copy
+    const char* rf0 = reinterpret_cast<const char*>(rb.lam);
+    const size_t rf_span = (size_t)(reinterpret_cast<const char*>(rb.info + 4) - rf0);
+    char* h_rf = ptake(rf_span);
+    double* h_lam = reinterpret_cast<double*>(h_rf);
+    int* rinfo = reinterpret_cast<int*>(h_rf + (reinterpret_cast<const char*>(rb.info) - rf0));
     auto mirror = [&](const void* dp) { return h0 + (reinterpret_cast<const char*>(dp) - span0); };
     memcpy(h_off, col_off, (G + 1) * sizeof(int64_t));
     memcpy(h_dr, draws, t * s * sizeof(uint64_t));
-    HIPCHK(hipMemcpyAsync(d_off, h_off, (G + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(d_dr, h_dr, t * s * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_off, h_in, in_span, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemsetAsync(d_st, 0, 4 * t * sizeof(int), st));
     if (p->col_map) {
         int64_t* h_cm = reinterpret_cast<int64_t*>(ptake(8 * n));
@@ -1520,8 +1535,7 @@ bcur_status bcur_decompose_boost(bcur_ctx* ctx, const float* A, int64_t m, int64
                                  d_mg + i * s, d_st + 4 * i, st));
     }
     HIPCHK(hipMemcpyAsync(h0, span0, span, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(h_lam, rb.lam, l * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(rinfo, rb.info, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_rf, rf0, rf_span, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     const int64_t* hidx = reinterpret_cast<const int64_t*>(mirror(d_idx));
     const double* hw = reinterpret_cast<const double*>(mirror(d_w));
