@@ -193,56 +193,70 @@ __global__ __launch_bounds__(TG* TG) void k_chol_rinv_small(const double* __rest
 }
 
 // out (rows x lo) = X (rows x li, FP32) * M (li x lo, FP64), FP64 accumulation.
+// Thread t owns row t / cg of a chunk of rg = 256 / cg rows and the four
+// columns 4 (t % cg) .. + 3, cg = lop / 4 (lop = lo rounded up to 4), so every
+// thread has work at any lo; M (li x lop) and the chunk of X sit in LDS sized
+// to li (dynamic), which leaves room for several workgroups per compute unit.
+// Each output sums its li products in order with FMAs.
 __global__ __launch_bounds__(256) void k_apply_small(const float* __restrict__ X, int64_t rows, int li, int64_t ldx,
                                                      const double* __restrict__ M, int lo, int64_t ldm,
                                                      float* __restrict__ out, int64_t ldo,
                                                      const int* __restrict__ gate) {
-    __shared__ double Ms[kMaxL * kMaxL];
-    __shared__ float Xs[kRC * (kMaxL + 1)];
+    extern __shared__ __attribute__((aligned(16))) double apply_lds[];
     if (gate && *gate == 0) return;
-    const int lop = (lo + 3) & ~3;
-    const int lis = li + 1;
+    const int lop = (lo + 3) & ~3, cg = lop / 4, rg = 256 / cg;
+    double* Ms = apply_lds;
+    float* Xs = reinterpret_cast<float*>(apply_lds + li * lop);
     const int tid = threadIdx.x;
     for (int e = tid; e < li * lop; e += 256) {
-        const int i = e / lop, o = e % lop;
+        const int i = e / lop, o = e - i * lop;
         Ms[e] = o < lo ? M[(int64_t)i * ldm + o] : 0.0;
     }
-    const int tr = tid / 32, tc = tid % 32;   // 8 x 32 threads -> 32 rows x 128 columns
-    for (int64_t rb = (int64_t)blockIdx.x * kRC; rb < rows; rb += (int64_t)gridDim.x * kRC) {
-        const int nr = (int)(rows - rb < kRC ? rows - rb : kRC);
+    const int tr = tid / cg, tc = tid - tr * cg;
+    const bool act = tr < rg;
+    for (int64_t rb = (int64_t)blockIdx.x * rg; rb < rows; rb += (int64_t)gridDim.x * rg) {
+        const int nr = (int)(rows - rb < rg ? rows - rb : rg);
         __syncthreads();
-        for (int e = tid; e < kRC * li; e += 256) {
-            const int rr = e / li, cc = e % li;
-            Xs[rr * lis + cc] = rr < nr ? X[(rb + rr) * ldx + cc] : 0.0f;
+        for (int e = tid; e < rg * li; e += 256) {
+            const int rr = e / li, cc = e - rr * li;
+            Xs[e] = rr < nr ? X[(rb + rr) * ldx + cc] : 0.0f;
         }
         __syncthreads();
-        if (4 * tc < lop) {
-            double acc[4][4];
+        if (act && tr < nr) {
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            const float* xr = Xs + tr * li;
+            const double* mc = Ms + 4 * tc;
+            int i = 0;
+            for (; i + 4 <= li; i += 4) {
+                double xv[4];
+                double2 m01[4], m23[4];
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+                for (int u = 0; u < 4; ++u) {
+                    xv[u] = xr[i + u];
+                    m01[u] = *reinterpret_cast<const double2*>(mc + (i + u) * lop);
+                    m23[u] = *reinterpret_cast<const double2*>(mc + (i + u) * lop + 2);
+                }
 #pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-            for (int i = 0; i < li; ++i) {
-                double xv[4], mv[4];
-#pragma unroll
-                for (int a = 0; a < 4; ++a) xv[a] = Xs[(4 * tr + a) * lis + i];
-#pragma unroll
-                for (int b = 0; b < 4; ++b) mv[b] = Ms[i * lop + 4 * tc + b];
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) acc[a][b] = fma(xv[a], mv[b], acc[a][b]);
-            }
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                const int rr = 4 * tr + a;
-                if (rr >= nr) continue;
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const int o = 4 * tc + b;
-                    if (o < lo) out[(rb + rr) * ldo + o] = (float)acc[a][b];
+                for (int u = 0; u < 4; ++u) {
+                    acc[0] = fma(xv[u], m01[u].x, acc[0]);
+                    acc[1] = fma(xv[u], m01[u].y, acc[1]);
+                    acc[2] = fma(xv[u], m23[u].x, acc[2]);
+                    acc[3] = fma(xv[u], m23[u].y, acc[3]);
                 }
             }
+            for (; i < li; ++i) {
+                const double xv = xr[i];
+                const double2 m01 = *reinterpret_cast<const double2*>(mc + i * lop);
+                const double2 m23 = *reinterpret_cast<const double2*>(mc + i * lop + 2);
+                acc[0] = fma(xv, m01.x, acc[0]);
+                acc[1] = fma(xv, m01.y, acc[1]);
+                acc[2] = fma(xv, m23.x, acc[2]);
+                acc[3] = fma(xv, m23.y, acc[3]);
+            }
+            float* orow = out + (rb + tr) * ldo;
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if (4 * tc + b < lo) orow[4 * tc + b] = (float)acc[b];
         }
     }
 }
@@ -705,7 +719,9 @@ __global__ __launch_bounds__(64) void k_jacobi_vectors(const double2* __restrict
 }  // namespace
 
 int gram_wgs(int64_t rows) {
-    int64_t w = rows / 64;
+    // one 32-row chunk per workgroup up to 128 workgroups (latency-bound: a
+    // longer chunk loop costs more than the larger partial sum)
+    int64_t w = rows / 32;
     if (w > 128) w = 128;
     if (w < 1) w = 1;
     return (int)w;
@@ -759,10 +775,13 @@ hipError_t launch_chol_rinv_small(const double* T, int64_t l, double* Rinv, int*
 hipError_t launch_apply_small(const float* X, int64_t rows, int64_t li, int64_t ldx, const double* M, int64_t lo,
                               int64_t ldm, float* out, int64_t ldo, hipStream_t st, const int* gate) {
     if (li < 1 || li > kMaxL || lo < 1 || lo > kMaxL) return hipErrorInvalidValue;
-    int64_t blocks = (rows + kRC - 1) / kRC;
-    if (blocks > 1024) blocks = 1024;
+    const int64_t lop = (lo + 3) & ~3, rg = 256 / (lop / 4);
+    int64_t blocks = (rows + rg - 1) / rg;
+    if (blocks > 2048) blocks = 2048;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_apply_small, dim3((unsigned)blocks), dim3(256), 0, st, X, rows, (int)li, ldx, M, (int)lo,
+    // M (li x lop doubles), then the X chunk (rg x li floats)
+    const size_t lds = (size_t)li * lop * sizeof(double) + (size_t)rg * li * sizeof(float);
+    hipLaunchKernelGGL(k_apply_small, dim3((unsigned)blocks), dim3(256), lds, st, X, rows, (int)li, ldx, M, (int)lo,
                        ldm, out, ldo, gate);
     return hipGetLastError();
 }
