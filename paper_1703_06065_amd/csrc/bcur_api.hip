@@ -461,17 +461,16 @@ bcur_status fit_run(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t m, 
     {
         StageScope ts(ctx, BCUR_STAGE_FIT_INV);
         if (d_cols) {
-            HIPCHK(launch_gram_from_cols(H, np, d_cols, c, b.G, st));
+            HIPCHK(launch_gram_from_cols(H, np, d_cols, c, b.G, st, refine ? b.G32 : nullptr, cp));
         } else {
             if (!b.Gtmp || !d_ident) return fail(ctx, BCUR_E_ARG, "internal: no Gram buffer");
             const GemmPlan pg = plan_sgemm(c, c, m, true, true);
             HIPCHK(launch_sgemm(pg, c, c, m, true, C, ldc, C, ldc, b.Gtmp, cp, b.part, EPI_STORE, nullptr, 0, nullptr,
                                 0, nullptr, st));
-            HIPCHK(launch_gram_from_cols(b.Gtmp, cp, d_ident, c, b.G, st));
+            HIPCHK(launch_gram_from_cols(b.Gtmp, cp, d_ident, c, b.G, st, refine ? b.G32 : nullptr, cp));
         }
-        // G as factored, in FP32, for the refinement's F = H - G U (its entries are
-        // FP32 values: read off H or formed by an FP32 GEMM)
-        if (refine) HIPCHK(launch_f64_to_f32_2d(b.G, c, c, c, b.G32, cp, st));
+        // (with a refinement step, G32 holds G as factored, rounded to FP32, for
+        // its F = H - G U)
         double* Linv = nullptr;
         HIPCHK(launch_chol_linv(b.G, c, b.spdws, b.info, b.piv, ldexp(1.0, -24), &Linv, st));
         HIPCHK(launch_f64_to_f32_2d(Linv, c, c, c, b.X32, cp, st));

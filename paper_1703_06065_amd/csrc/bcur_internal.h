@@ -29,8 +29,9 @@ hipError_t launch_expand_blocks(const int64_t* idx, int64_t s, const int64_t* of
 hipError_t launch_gather_rows(const float* A, int64_t lda, int64_t n, const int64_t* d_rows, int64_t r,
                               float* R, int64_t ldr, hipStream_t st);
 hipError_t launch_sum_f64(const double* x, int64_t count, double* out, hipStream_t st);
+// G (c x c, FP64) = symmetrized H[:, cols]; G32 (ld ldg32), when not null, gets the same values in FP32
 hipError_t launch_gram_from_cols(const float* H, int64_t ldh, const int64_t* d_cols, int64_t c, double* G,
-                                 hipStream_t st);
+                                 hipStream_t st, float* G32 = nullptr, int64_t ldg32 = 0);
 hipError_t launch_f64_to_f32(const double* x, int64_t count, float* y, hipStream_t st);
 // y (rows x ldy) = x (rows x cols, ldx) rounded to FP32, zero in columns cols..ldy-1
 hipError_t launch_f64_to_f32_2d(const double* x, int64_t rows, int64_t cols, int64_t ldx, float* y, int64_t ldy,

@@ -365,12 +365,15 @@ __global__ __launch_bounds__(256) void k_gather_rows(const float* __restrict__ A
 // G = C^T C read from H = C^T A at the chosen columns, symmetrized, FP64.
 __global__ __launch_bounds__(256) void k_gram_from_cols(const float* __restrict__ H, int64_t ldh,
                                                         const int64_t* __restrict__ cols, int64_t c,
-                                                        double* __restrict__ G) {
+                                                        double* __restrict__ G, float* __restrict__ G32,
+                                                        int64_t ldg32) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= c * c) return;
     const int64_t i = e / c, j = e - i * c;
     const double a = H[i * ldh + cols[j]], b = H[j * ldh + cols[i]];
-    G[e] = 0.5 * (a + b);
+    const double g = 0.5 * (a + b);
+    G[e] = g;
+    if (G32) G32[i * ldg32 + j] = (float)g;
 }
 
 __global__ __launch_bounds__(256) void k_f64_to_f32(const double* __restrict__ x, int64_t count,
@@ -505,9 +508,10 @@ hipError_t launch_gather_rows(const float* A, int64_t lda, int64_t n, const int6
 }
 
 hipError_t launch_gram_from_cols(const float* H, int64_t ldh, const int64_t* d_cols, int64_t c, double* G,
-                                 hipStream_t st) {
+                                 hipStream_t st, float* G32, int64_t ldg32) {
     const int64_t blocks = (c * c + 255) / 256;
-    hipLaunchKernelGGL(k_gram_from_cols, dim3((unsigned)blocks), dim3(256), 0, st, H, ldh, d_cols, c, G);
+    hipLaunchKernelGGL(k_gram_from_cols, dim3((unsigned)blocks), dim3(256), 0, st, H, ldh, d_cols, c, G, G32,
+                       ldg32);
     return hipGetLastError();
 }
 
