@@ -26,7 +26,7 @@ PEAK_HBM_GBS = 8000.0
 def algorithmic_flops(m, n, k, l, q, c):
     """FLOPs the method needs per decomposition (sketch width l, no padding)."""
     rf = (2 * q + 3) * 2.0 * m * n * l              # (q+1) x (A Q, A^T Z) + the Rayleigh-Ritz A Q
-    fit = 2 * 2.0 * m * c * n + 5 * 2.0 * c * c * n  # C^T A, A - C U; X^T (X H), H - G U, X^T (X F)
+    fit = 2 * 2.0 * m * c * n + 3 * 2.0 * c * c * n + 2.0 * c ** 3  # C^T A, A - C U; G^-1 H, H - G U, G^-1 F; X^T X
     return rf, fit
 
 

@@ -224,11 +224,11 @@ enum {
     BCUR_STAGE_GATHER = 8,    /* C = A S */
     BCUR_STAGE_FIT_H = 9,     /* H = C^T A, main GEMM kernel */
     BCUR_STAGE_FIT_REDUCE = 10, /* split-K sums of the fit GEMMs */
-    BCUR_STAGE_FIT_INV = 11,  /* (C^T C)^-1: blocked FP64 Cholesky inverse */
-    BCUR_STAGE_FIT_U = 12,    /* U = X^T (X H), X = L^-1, G = L L^T */
+    BCUR_STAGE_FIT_INV = 11,  /* G = C^T C, its FP64 Cholesky with X = L^-1, G^-1 = X^T X */
+    BCUR_STAGE_FIT_U = 12,    /* U = G^-1 H, G^-1 = X^T X, X = L^-1, G = L L^T */
     BCUR_STAGE_FIT_E = 13,    /* ||A - C U||_F^2 (the residual is not stored) */
     BCUR_STAGE_FIT_F = 14,    /* F = C^T (A - C U), formed as H - (C^T C) U */
-    BCUR_STAGE_FIT_DU = 15,   /* U += X^T (X F) with <X^T X F, F> */
+    BCUR_STAGE_FIT_DU = 15,   /* U += G^-1 F with <G^-1 F, F> */
     BCUR_STAGE_RF_CAST = 16,  /* BF16 copies of A and of the sketch panels */
     BCUR_STAGE_A1_ROWS = 17,  /* Algorithm 1: uniform row draws, R = A[rows, :] and its transpose */
     BCUR_STAGE_A1_SVDR = 18,  /* Algorithm 1: R R^T, its eigensolver, V_kr = R^T U_kr Sigma^-1 */

@@ -515,8 +515,9 @@ struct FitOut {
 // U = C^+ A by Cholesky QR2 in FP64 (the scheme of the row-block variant):
 // L1 L1^T = C^T C from FP32 C with FP64 sums, Q1 = C L1^-T, L2 L2^T = Q1^T Q1,
 // U = L1^-T L2^-T L2^-1 Q1^T A, with pivots below 2^-50 of the largest dropped
-// (a basic least-squares solution on the kept columns).  Then E = A - C U for
-// the returned FP32 U with its fused norm: err2 is that U's exact residual.
+// (a basic least-squares solution on the kept columns).  Then ||A - C U||_F^2
+// for the returned FP32 U (norm-only residual epilogue): err2 is that U's exact
+// residual.
 bcur_status fit_fallback64(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t m, int64_t n, int64_t lda,
                            const float* C, int64_t c, int64_t ldc, float* U, int64_t ldu, double* err2) {
     hipStream_t st = ctx->stream;

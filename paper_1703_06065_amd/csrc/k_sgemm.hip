@@ -2,7 +2,7 @@
 // accumulation) for every contraction of the Block CUR path:
 //   Z = A Q, Y = A^T Z          (range finder passes, N = sketch width)
 //   H = C^T A                   (fit: projection onto the chosen columns)
-//   U = X^T (X H), ||A - C U||  (fit: solve and residual norm)
+//   G^-1 = X^T X, U = G^-1 H, ||A - C U||  (fit: solve and residual norm)
 //   F = H - G U                 (fit: the refinement's right-hand side)
 // D = op(A) B with op(A) = A (M x K) or A^T (A stored K x M), B is K x N; all
 // operands row-major.  Tiles are staged through LDS in k-major order so each
@@ -461,7 +461,7 @@ hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K,
         a.split_stride = 0;
     }
     // the fused epilogues exist for the square tile only (a 256 x 128 residual
-    // tile measured slower: 202 us against 192 us for E = A - C U at 8192 x 4096 x 256)
+    // tile measured slower: 202 us against 192 us for the residual A - C U at 8192 x 4096 x 256)
     const int cfg = store_like ? p.cfg : 2;
     const Cfg c = kCfg[cfg];
     dim3 grid((unsigned)((M + c.BM - 1) / c.BM), (unsigned)((N + c.BN - 1) / c.BN), (unsigned)p.splits);
