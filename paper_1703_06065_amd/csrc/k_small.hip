@@ -261,6 +261,62 @@ __global__ __launch_bounds__(256) void k_apply_small(const float* __restrict__ X
     }
 }
 
+// The same product for lo > 64: 32-row chunks, each thread a 4 x 4 block of
+// outputs (8 x 32 threads: 32 rows x 128 columns), M in a fixed LDS array.
+__global__ __launch_bounds__(256) void k_apply_wide(const float* __restrict__ X, int64_t rows, int li, int64_t ldx,
+                                                     const double* __restrict__ M, int lo, int64_t ldm,
+                                                     float* __restrict__ out, int64_t ldo,
+                                                     const int* __restrict__ gate) {
+    __shared__ double Ms[kMaxL * kMaxL];
+    __shared__ float Xs[kRC * (kMaxL + 1)];
+    if (gate && *gate == 0) return;
+    const int lop = (lo + 3) & ~3;
+    const int lis = li + 1;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < li * lop; e += 256) {
+        const int i = e / lop, o = e % lop;
+        Ms[e] = o < lo ? M[(int64_t)i * ldm + o] : 0.0;
+    }
+    const int tr = tid / 32, tc = tid % 32;   // 8 x 32 threads -> 32 rows x 128 columns
+    for (int64_t rb = (int64_t)blockIdx.x * kRC; rb < rows; rb += (int64_t)gridDim.x * kRC) {
+        const int nr = (int)(rows - rb < kRC ? rows - rb : kRC);
+        __syncthreads();
+        for (int e = tid; e < kRC * li; e += 256) {
+            const int rr = e / li, cc = e % li;
+            Xs[rr * lis + cc] = rr < nr ? X[(rb + rr) * ldx + cc] : 0.0f;
+        }
+        __syncthreads();
+        if (4 * tc < lop) {
+            double acc[4][4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+            for (int i = 0; i < li; ++i) {
+                double xv[4], mv[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) xv[a] = Xs[(4 * tr + a) * lis + i];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) mv[b] = Ms[i * lop + 4 * tc + b];
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) acc[a][b] = fma(xv[a], mv[b], acc[a][b]);
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const int rr = 4 * tr + a;
+                if (rr >= nr) continue;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int o = 4 * tc + b;
+                    if (o < lo) out[(rb + rr) * ldo + o] = (float)acc[a][b];
+                }
+            }
+        }
+    }
+}
+
 // Cyclic Jacobi eigensolver of the small symmetric Rayleigh-Ritz matrix T,
 // in two kernels.
 //
@@ -775,9 +831,20 @@ hipError_t launch_chol_rinv_small(const double* T, int64_t l, double* Rinv, int*
 hipError_t launch_apply_small(const float* X, int64_t rows, int64_t li, int64_t ldx, const double* M, int64_t lo,
                               int64_t ldm, float* out, int64_t ldo, hipStream_t st, const int* gate) {
     if (li < 1 || li > kMaxL || lo < 1 || lo > kMaxL) return hipErrorInvalidValue;
+    if (lo > 64) {
+        int64_t wblocks = (rows + kRC - 1) / kRC;
+        if (wblocks > 1024) wblocks = 1024;
+        if (wblocks < 1) wblocks = 1;
+        hipLaunchKernelGGL(k_apply_wide, dim3((unsigned)wblocks), dim3(256), 0, st, X, rows, (int)li, ldx, M,
+                           (int)lo, ldm, out, ldo, gate);
+        return hipGetLastError();
+    }
     const int64_t lop = (lo + 3) & ~3, rg = 256 / (lop / 4);
     int64_t blocks = (rows + rg - 1) / rg;
-    if (blocks > 2048) blocks = 2048;
+    // every workgroup loads all of M: at most 16 MB of such loads in all (at least
+    // 128 workgroups), so a large M is shared by several chunks of rows
+    const int64_t cap = std::max<int64_t>(128, ((int64_t)16 << 20) / (li * lop * (int64_t)sizeof(double)));
+    if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
     // M (li x lop doubles), then the X chunk (rg x li floats)
     const size_t lds = (size_t)li * lop * sizeof(double) + (size_t)rg * li * sizeof(float);
