@@ -1,0 +1,46 @@
+"""Host-side checks of bench.py (no GPU): the one-GPU refusal, the HBM
+traffic figure derived from the committed counter readings, and the FLOP
+model of a decomposition."""
+import importlib.util
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bench():
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
+
+
+def test_traffic_is_the_scaled_counter_readings():
+    b = _bench()
+    t = b.TRAFFIC
+    want = 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+    assert b.traffic_bytes(t["m"], t["n"], t["c"]) == round(want)
+    # the readings belong to one shape only
+    assert b.traffic_bytes(t["m"], t["n"], t["c"] + 16) is None
+    # HBM bytes per launch of the residual GEMM: at least the algorithmic 4 (mn + mc + cn)
+    m, n, c = t["m"], t["n"], t["c"]
+    assert b.traffic_bytes(m, n, c) >= 4 * (m * n + m * c + c * n)
+
+
+def test_flop_model():
+    b = _bench()
+    m, n, k, l, q, c = 8192, 4096, 50, 60, 2, 256
+    rf, fit = b.algorithmic_flops(m, n, k, l, q, c)
+    # 2q + 3 passes over A in the range finder (q + 1 times A Q and A^T Z, then the Rayleigh-Ritz A Q)
+    assert rf == (2 * q + 3) * 2.0 * m * n * l
+    # H = C^T A and the residual, then G^-1 H, H - G U, G^-1 F and G^-1 = X^T X
+    assert fit == 4.0 * m * c * n + 6.0 * c * c * n + 2.0 * c ** 3
