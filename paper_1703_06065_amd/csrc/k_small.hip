@@ -71,31 +71,33 @@ __global__ __launch_bounds__(1024) void k_gram64(const T* __restrict__ X, int64_
 }
 
 // T[e] = sum over the partial Gram matrices, fixed order: the `parts`
-// partials are split into 4 groups (g = w mod 4), each thread sums one group
-// for one entry with up to 16 loads in flight, and the 4 group sums are added
-// in group order.
+// partials are split into 8 groups (g = w mod 8), each thread sums one group
+// for one entry with 4 loads in flight, and the 8 group sums are added in a
+// fixed tree.  The order depends on w only, so T keeps the bitwise symmetry of
+// the partials.
 __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ partial, int parts, int64_t ll,
                                                      double* __restrict__ T, const int* __restrict__ gate) {
-    __shared__ double sg[4][64];
+    __shared__ double sg[8][32];
     if (gate && *gate == 0) return;
-    const int tid = threadIdx.x, g = tid >> 6, el = tid & 63;
-    const int64_t e = (int64_t)blockIdx.x * 64 + el;
+    const int tid = threadIdx.x, g = tid >> 5, el = tid & 31;
+    const int64_t e = (int64_t)blockIdx.x * 32 + el;
     double acc = 0.0;
     if (e < ll) {
         int w = g;
-        for (; w + 12 < parts; w += 16) {
-            const double v0 = partial[(int64_t)w * ll + e], v1 = partial[(int64_t)(w + 4) * ll + e];
-            const double v2 = partial[(int64_t)(w + 8) * ll + e], v3 = partial[(int64_t)(w + 12) * ll + e];
+        for (; w + 24 < parts; w += 32) {
+            const double v0 = partial[(int64_t)w * ll + e], v1 = partial[(int64_t)(w + 8) * ll + e];
+            const double v2 = partial[(int64_t)(w + 16) * ll + e], v3 = partial[(int64_t)(w + 24) * ll + e];
             acc += v0;
             acc += v1;
             acc += v2;
             acc += v3;
         }
-        for (; w < parts; w += 4) acc += partial[(int64_t)w * ll + e];
+        for (; w < parts; w += 8) acc += partial[(int64_t)w * ll + e];
     }
     sg[g][el] = acc;
     __syncthreads();
-    if (g == 0 && e < ll) T[e] = ((sg[0][el] + sg[1][el]) + sg[2][el]) + sg[3][el];
+    if (g == 0 && e < ll)
+        T[e] = ((sg[0][el] + sg[1][el]) + (sg[2][el] + sg[3][el])) + ((sg[4][el] + sg[5][el]) + (sg[6][el] + sg[7][el]));
 }
 
 // T + shift I = R^T R for the l x l Gram matrix T (FP64, row-major), with
@@ -808,7 +810,7 @@ hipError_t launch_gram64(const double* X, int64_t rows, int64_t l, int64_t ldx, 
 hipError_t launch_gram_reduce(const double* partial, int parts, int64_t l, double* T, hipStream_t st,
                               const int* gate) {
     const int64_t ll = l * l;
-    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((ll + 63) / 64)), dim3(256), 0, st, partial, parts, ll, T,
+    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((ll + 31) / 32)), dim3(256), 0, st, partial, parts, ll, T,
                        gate);
     return hipGetLastError();
 }
