@@ -90,12 +90,6 @@ def exact_left_subspace(A: np.ndarray, k: int) -> np.ndarray:
     return U[:, :k]
 
 
-def best_rank_k_error(A: np.ndarray, k: int) -> float:
-    """||A - A_k||_F = sqrt(sum_{i>k} sigma_i^2) (Eckart-Young, Sec. 2.1)."""
-    s = np.linalg.svd(np.asarray(A, dtype=np.float64), compute_uv=False)
-    return float(math.sqrt(float(np.sum(s[k:] ** 2))))
-
-
 # ---------------------------------------------------------------------------
 # Def. 1, Def. 2, Def. 3, Def. 4
 # ---------------------------------------------------------------------------
@@ -143,6 +137,58 @@ def incoherence(U: np.ndarray) -> float:
     U = np.asarray(U, dtype=np.float64)
     m, k = U.shape
     return float(m / k * np.max(np.sum(U * U, axis=1)))
+
+
+# ---------------------------------------------------------------------------
+# The test matrix of the range finder, drawn from a seed
+# ---------------------------------------------------------------------------
+#
+# The sketch needs random numbers of its own (the test matrix Omega).  They
+# come from a counter-based generator so that the host and the device draw
+# the same matrix from the same seed without exchanging it: Philox4x64-10 of
+# Salmon, Moraes, Dror and Shaw ("Parallel random numbers: as easy as 1, 2,
+# 3", SC 2011), written here from that definition.
+
+_PHILOX_M = (0xD2E7470EE14C6C93, 0xCA5A826395121157)   # round multipliers
+_PHILOX_W = (0x9E3779B97F4A7C15, 0xBB67AE8584CAA73B)   # key increments (Weyl)
+_MASK64 = (1 << 64) - 1
+
+
+def philox4x64_10(counter: Sequence[int], key: Sequence[int]) -> List[int]:
+    """Philox4x64 with 10 rounds: four 64-bit counter words, two key words.
+
+    A round multiplies words 0 and 2 by the two multipliers (full 128-bit
+    products), and forms the new words (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2),
+    hi(M0 c0) ^ c3 ^ k1, lo(M0 c0)); the key is bumped by the Weyl constants
+    after each round."""
+    c = [int(x) & _MASK64 for x in counter]
+    k0, k1 = int(key[0]) & _MASK64, int(key[1]) & _MASK64
+    for _ in range(10):
+        p0 = _PHILOX_M[0] * c[0]
+        p1 = _PHILOX_M[1] * c[2]
+        c = [((p1 >> 64) ^ c[1] ^ k0) & _MASK64, p1 & _MASK64,
+             ((p0 >> 64) ^ c[3] ^ k1) & _MASK64, p0 & _MASK64]
+        k0 = (k0 + _PHILOX_W[0]) & _MASK64
+        k1 = (k1 + _PHILOX_W[1]) & _MASK64
+    return c
+
+
+def rademacher_omega(n: int, l: int, seed: int) -> np.ndarray:
+    """The n x l Rademacher test matrix of seed ``seed`` (l <= 256).
+
+    Row i is one Philox4x64-10 block with counter (i, 0, 0, 0) and key
+    (seed, 0); its 256 output bits, word 0 first and the least significant
+    bit of a word first, give Omega[i, j] = +1 for a 0 bit j and -1 for a 1
+    bit.  A narrower sketch therefore uses the leading columns of a wider one."""
+    if not (0 <= l <= 256):
+        raise ValueError("the test matrix has at most 256 columns")
+    out = np.empty((n, l))
+    for i in range(n):
+        words = philox4x64_10((i, 0, 0, 0), (seed, 0))
+        for j in range(l):
+            bit = (words[j >> 6] >> (j & 63)) & 1
+            out[i, j] = -1.0 if bit else 1.0
+    return out
 
 
 # ---------------------------------------------------------------------------

@@ -134,6 +134,105 @@ def check_twin_converges(O):
     assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-8, errs
 
 
+def check_twin_left_vectors_on_low_rank(O):
+    """On an exactly rank-rho A (rho <= l, distinct singular values) the
+    twin's left vectors U_k = Z W_k / sigma_k are the exact top-k left
+    singular vectors up to column signs (A v_i = sigma_i u_i, Sec. 2.1):
+    orthonormal, |U_k^T U_exact| = I, and the row-block scores read off them
+    equal the exact row leverage of the blocks (Def. 2 on A^T, Corollary 1).
+    The exact vectors come from numpy's SVD, not from the oracle."""
+    for (m, n, rho, k, l, seed) in [(300, 200, 15, 10, 20, 7), (120, 260, 8, 6, 12, 8)]:
+        A = gen.gaussian_product(m, n, rho, seed)
+        rf = O.range_finder(A, gen.rademacher(n, l, seed), 1, k)
+        Uk = np.asarray(rf["Uk"])
+        assert Uk.shape == (m, k), Uk.shape
+        assert np.abs(Uk.T @ Uk - np.eye(k)).max() <= 1e-10, np.abs(Uk.T @ Uk - np.eye(k)).max()
+        Ue = np.linalg.svd(A, full_matrices=False)[0][:, :k]
+        assert np.abs(np.abs(Uk.T @ Ue) - np.eye(k)).max() <= 1e-9
+        roff = gen.contiguous_blocks(m, 12)
+        want = np.add.reduceat(np.sum(Ue * Ue, axis=1), roff[:-1])
+        assert np.allclose(O.block_scores(Uk, roff), want, atol=1e-10)
+
+
+def check_score_condition_first_order(O):
+    """kappa = lam_1 / (lam_k - lam_{k+1}) is the first-order sensitivity of
+    the top-k eigenspace of T to a perturbation of relative size eps: the
+    symmetric perturbation eps lam_1 (e_k e_{k+1}^T + e_{k+1} e_k^T) of
+    T = diag(lam) turns that eigenspace by the angle eps kappa + O(eps^2)
+    (the 2 x 2 rotation that diagonalizes rows k, k+1).  The angle is measured
+    with numpy's eigh on planted spectra whose gaps differ from position to
+    position, so a gap taken one place off changes the answer."""
+    spectra = [np.array([9.0, 7.5, 5.0, 4.2, 4.0, 1.0, 0.7, 0.2]),
+               np.array([1.0, 0.5, 0.3, 0.29, 0.1, 0.05]),
+               np.array([3.0, 2.0, 1.97, 1.0, 0.9, 0.89, 0.3])]
+    eps = 1e-8
+    for lam in spectra:
+        for k in range(1, len(lam) - 1):
+            T = np.diag(lam)
+            T[k - 1, k] = T[k, k - 1] = eps * lam[0]
+            ev, V = np.linalg.eigh(T)
+            Vk = V[:, np.argsort(ev)[::-1][:k]]
+            sin = float(np.linalg.norm(Vk[k:, :], 2))
+            got = O.score_condition(lam, k)
+            assert abs(got - sin / eps) <= 1e-4 * got, (k, got, sin / eps)
+    assert O.score_condition(np.array([2.0, 1.0, 1.0]), 1) < math.inf
+    assert O.score_condition(np.array([2.0, 1.0, 1.0]), 2) == math.inf
+
+
+def check_cond2_planted(O):
+    """cond(C) = sigma_max / sigma_min for a planted SVD C = U diag(sigma) V^T
+    (Haar U and V), and equals ||C||_2 ||C^+||_2 with numpy's pinv."""
+    rng = np.random.default_rng(33)
+    for (m, c, lo, hi) in [(50, 8, 1e-3, 2.0), (200, 40, 0.5, 7.0), (30, 30, 1e-6, 1.0)]:
+        sig = np.exp(rng.uniform(math.log(lo), math.log(hi), size=c))
+        sig[0], sig[-1] = hi, lo
+        C = gen.haar_orthonormal(rng, m, c) @ np.diag(sig) @ gen.haar_orthonormal(rng, c, c).T
+        got = O.cond2(C)
+        assert abs(got - hi / lo) <= 1e-6 * hi / lo, (got, hi / lo)
+        alt = np.linalg.norm(C, 2) * np.linalg.norm(np.linalg.pinv(C, rcond=1e-14), 2)
+        assert abs(got - alt) <= 1e-6 * alt
+
+
+# --------------------------------------------------------------------------
+# The seeded test matrix (Philox4x64-10)
+# --------------------------------------------------------------------------
+
+def check_omega_philox_library(O):
+    """The oracle's Philox4x64-10 against numpy's Philox bit generator, an
+    independent library implementation of the same published generator.
+    numpy advances its 256-bit counter before each block, so the state
+    counter c yields the block of counter c + 1 (all ones wraps to zero);
+    keys and counters go in as uint64 arrays (a Python list above 2^63
+    would pass through a float cast).
+    The test matrix rows are then read off numpy's stream: bit j of a row's
+    256 bits (word 0 first, least significant bit first) gives +1 for 0 and
+    -1 for 1; a narrower sketch takes the leading columns."""
+    rng = np.random.default_rng(31)
+    mask = (1 << 64) - 1
+    for _ in range(8):
+        key = [int(x) for x in rng.integers(0, 2 ** 63, size=2)]
+        ctr = [int(x) for x in rng.integers(0, 2 ** 62, size=4)]
+        want = [int(x) for x in np.random.Philox(counter=ctr, key=key).random_raw(4)]
+        assert O.philox4x64_10([ctr[0] + 1] + ctr[1:], key) == want
+    want0 = [int(x) for x in np.random.Philox(counter=np.full(4, mask, dtype=np.uint64),
+                                               key=np.array([5, 0], dtype=np.uint64)).random_raw(4)]
+    assert O.philox4x64_10([0, 0, 0, 0], [5, 0]) == want0
+    n, l = 37, 112
+    for seed in (0, 987654321, (1 << 64) - 3):
+        om = O.rademacher_omega(n, l, seed)
+        for i in range(n):
+            ctr = [mask] * 4 if i == 0 else [i - 1, 0, 0, 0]
+            words = np.random.Philox(counter=np.array(ctr, dtype=np.uint64),
+                                     key=np.array([seed, 0], dtype=np.uint64)).random_raw(4).astype("<u8")
+            bits = np.unpackbits(words.view(np.uint8), bitorder="little")
+            assert np.array_equal(om[i], 1.0 - 2.0 * bits[:l].astype(np.float64)), (seed, i)
+        assert np.array_equal(O.rademacher_omega(n, 60, seed), om[:, :60])
+    big = O.rademacher_omega(2000, 64, 11)
+    assert set(np.unique(big)) == {-1.0, 1.0}
+    assert abs(float(big.mean())) <= 5.0 / math.sqrt(big.size)
+    assert not np.array_equal(O.rademacher_omega(4, 64, 1), O.rademacher_omega(4, 64, 2))
+
+
 # --------------------------------------------------------------------------
 # Sampling (Alg. 1 step 2, the sampling matrix S of Sec. 3.1)
 # --------------------------------------------------------------------------
@@ -654,6 +753,10 @@ ALL_CHECKS = [
     check_scores_bounds_permutation,
     check_row_scores_transpose,
     check_twin_exact_on_low_rank,
+    check_twin_left_vectors_on_low_rank,
+    check_score_condition_first_order,
+    check_cond2_planted,
+    check_omega_philox_library,
     check_twin_converges,
     check_sampler_inverse_cdf,
     check_sampler_edges,

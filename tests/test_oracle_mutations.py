@@ -139,7 +139,76 @@ def _incoherence_without_m_over_k(U):
     return float(np.max(np.sum(U * U, axis=1)))
 
 
+def _uk_divides_by_lam(A, omega, q, k):
+    out = dict(O.range_finder(A, omega, q, k))
+    out["Uk"] = (np.asarray(A, dtype=np.float64) @ out["Q"] @ out["W"][:, :k]) / out["lam"][:k]
+    return out
+
+
+def _uk_from_q(A, omega, q, k):
+    out = dict(O.range_finder(A, omega, q, k))
+    out["Uk"] = (out["Q"] @ out["W"][:, :k]) / out["ritz"][:k]
+    return out
+
+
+def _kappa_gap_shifted(lam, k):
+    if k + 1 >= len(lam):
+        return 1.0
+    gap = lam[k] - lam[k + 1]
+    return float(lam[0] / gap) if gap > 0 else math.inf
+
+
+def _kappa_without_lam1(lam, k):
+    if k >= len(lam):
+        return 1.0
+    gap = lam[k - 1] - lam[k]
+    return float(1.0 / gap) if gap > 0 else math.inf
+
+
+def _cond_without_ratio(C):
+    return float(np.linalg.svd(np.asarray(C, dtype=np.float64), compute_uv=False)[0])
+
+
+def _philox_weyl_swapped(counter, key):
+    c = [int(x) & O._MASK64 for x in counter]
+    k0, k1 = int(key[0]), int(key[1])
+    for _ in range(10):
+        p0 = O._PHILOX_M[0] * c[0]
+        p1 = O._PHILOX_M[1] * c[2]
+        c = [((p1 >> 64) ^ c[1] ^ k0) & O._MASK64, p1 & O._MASK64,
+             ((p0 >> 64) ^ c[3] ^ k1) & O._MASK64, p0 & O._MASK64]
+        k0 = (k0 + O._PHILOX_W[1]) & O._MASK64
+        k1 = (k1 + O._PHILOX_W[0]) & O._MASK64
+    return c
+
+
+def _omega_msb_first(n, l, seed):
+    out = np.empty((n, l))
+    for i in range(n):
+        words = O.philox4x64_10((i, 0, 0, 0), (seed, 0))
+        for j in range(l):
+            out[i, j] = -1.0 if (words[j >> 6] >> (63 - (j & 63))) & 1 else 1.0
+    return out
+
+
+def _omega_counter_from_one(n, l, seed):
+    out = np.empty((n, l))
+    for i in range(n):
+        words = O.philox4x64_10((i + 1, 0, 0, 0), (seed, 0))
+        for j in range(l):
+            out[i, j] = -1.0 if (words[j >> 6] >> (j & 63)) & 1 else 1.0
+    return out
+
+
 MUTANTS = {
+    "uk-divides-by-lam": dict(range_finder=_uk_divides_by_lam),
+    "uk-from-q": dict(range_finder=_uk_from_q),
+    "kappa-gap-off-by-one": dict(score_condition=_kappa_gap_shifted),
+    "kappa-without-lam1": dict(score_condition=_kappa_without_lam1),
+    "cond-without-ratio": dict(cond2=_cond_without_ratio),
+    "philox-weyl-swapped": dict(philox4x64_10=_philox_weyl_swapped),
+    "omega-msb-first": dict(rademacher_omega=_omega_msb_first),
+    "omega-counter-from-one": dict(rademacher_omega=_omega_counter_from_one),
     "stable-rank-spectral-unsquared": dict(block_stable_rank=_stable_rank_spectral_unsquared),
     "incoherence-without-m-over-k": dict(incoherence=_incoherence_without_m_over_k),
     "boost-reuses-draws": dict(trial_draws=lambda draws, i, s: draws[:s]),
