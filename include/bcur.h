@@ -50,7 +50,8 @@ typedef enum bcur_status {
     BCUR_E_RANKDEF = 5,    /* a Cholesky factorization met a pivot below its threshold */
     BCUR_E_ADMIT = 6,      /* serving: the request can never fit the memory budget */
     BCUR_PENDING = 7,      /* serving: the request has not finished yet */
-    BCUR_E_STATE = 8       /* serving: unknown or already collected ticket */
+    BCUR_E_STATE = 8       /* serving: unknown or already collected ticket; context: a call was made
+                              while an asynchronous decomposition is in flight (see bcur_wait) */
 } bcur_status;
 
 /* Arithmetic used by the range finder's passes over A. */
@@ -79,8 +80,11 @@ typedef struct bcur_ctx bcur_ctx;
 /* Create a context on HIP device `device` that issues all work on `stream`
  * (a hipStream_t owned by the caller; NULL means the device's null stream).
  * The context owns a grow-only device workspace and a pinned host staging
- * buffer. */
-bcur_status bcur_create(bcur_ctx** out, int device, void* stream);
+ * buffer.  scratch_budget: the most device workspace, in bytes, the context
+ * may hold (0: no limit); a call whose workspace would exceed it fails with
+ * BCUR_E_NOMEM before allocating anything (bcur_footprint gives a
+ * decomposition's need from its shapes). */
+bcur_status bcur_create(bcur_ctx** out, int device, void* stream, size_t scratch_budget);
 
 /* Destroy a context, freeing only what the library allocated. */
 bcur_status bcur_destroy(bcur_ctx* ctx);
@@ -100,6 +104,16 @@ size_t bcur_workspace_bytes(const bcur_ctx* ctx);
 bcur_status bcur_release_workspace(bcur_ctx* ctx);
 
 /* ---- stage calls -------------------------------------------------------- */
+
+/* The Rademacher test matrix of the range finder (its random input; Sec. 3.1
+ * allows the score step to be sketched) drawn on the device from a seed:
+ * omega[i][j] = +1 or -1 from bit j of the Philox4x64-10 block (Salmon et
+ * al., SC 2011) with counter (i, 0, 0, 0) and key (seed, 0); bit j is bit
+ * j % 64 of output word j / 64, and a 0 bit gives +1.  The matrix of a
+ * narrower sketch is the leading columns of a wider one.
+ * omega: device n x l float32 (leading dimension ldo >= l); columns l ..
+ * ldo-1 are not written.  Requires 1 <= l <= 256.  Stream-ordered. */
+bcur_status bcur_test_matrix(bcur_ctx* ctx, int64_t n, int64_t l, uint64_t seed, float* omega, int64_t ldo);
 
 /* ||A||_F^2 = sum_ij A_ij^2 (Sec. 2.1, Frobenius norm), accumulated in float64
  * in a fixed order (bitwise reproducible on one device).
@@ -269,6 +283,9 @@ typedef struct bcur_params {
      * rows in selection order, each block's in map order. */
     const int64_t* col_map;
     const int64_t* row_map;
+    /* Seed of the test matrix (bcur_test_matrix) when the call's omega is
+     * NULL; ignored otherwise. */
+    uint64_t seed;
 } bcur_params;
 
 typedef struct bcur_result {
@@ -296,12 +313,32 @@ typedef struct bcur_result {
 /* One Block CUR decomposition: stages 1-6 above.
  * A: device m x n (lda).  col_off: host G+1 column-block offsets.
  * row_off: host Gr+1 row-block offsets, or NULL (columns only).
- * omega: device n x l Rademacher (or any) test matrix.  draws: host, s + s_r
- * 64-bit words (column draws first).  Synchronous. */
+ * omega: device n x l test matrix (dense, leading dimension l), or NULL: the
+ * Rademacher matrix of params->seed is drawn on the device (bcur_test_matrix).
+ * draws: host, s + s_r 64-bit words (column draws first).  Synchronous. */
 bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda,
                            const int64_t* col_off, int64_t G, const int64_t* row_off, int64_t Gr,
                            const bcur_params* params, const float* omega, const uint64_t* draws,
                            bcur_result* result);
+
+/* bcur_decompose without waiting for it: the call checks its pointers, copies
+ * the host inputs (offsets, draws, maps, parameters) and returns; the
+ * decomposition then runs on the context's own host thread, its device work
+ * issued after everything queued on the context's stream before this call
+ * (the call records an event there that the work waits for) and on an
+ * internal stream of the default priority.  A, omega and result (with the
+ * buffers it points to) are borrowed until bcur_wait returns: every output,
+ * host and device, is valid only then.  Until then any other call on the
+ * context returns BCUR_E_STATE.  Argument errors found after the return are
+ * reported by bcur_wait. */
+bcur_status bcur_decompose_async(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda,
+                                 const int64_t* col_off, int64_t G, const int64_t* row_off, int64_t Gr,
+                                 const bcur_params* params, const float* omega, const uint64_t* draws,
+                                 bcur_result* result);
+
+/* Wait for the context's asynchronous decomposition and return its status
+ * (BCUR_OK at once when none is in flight). */
+bcur_status bcur_wait(bcur_ctx* ctx);
 
 /* Device workspace one bcur_decompose call needs for these shapes and
  * parameters (bytes; library_holds_u != 0 when result->U will be NULL).
@@ -318,7 +355,7 @@ bcur_status bcur_footprint(int64_t m, int64_t n, const int64_t* col_off, int64_t
  * draws s blocks with draws[i*s .. i*s+s-1], gathers C_i and fits U_i = C_i^+ A
  * with its residual exactly as bcur_decompose does (columns only, params->s_r
  * = 0); the H_i = C_i^T A products of all trials run as one GEMM over their
- * concatenated columns.  result describes the kept trial (smallest err, the
+ * concatenated columns.  omega may be NULL (the test matrix of params->seed).  result describes the kept trial (smallest err, the
  * first on ties) and receives its U; errs (host, t) receives every trial's
  * err; *best (may be NULL) its index.  1 <= t <= 64.  Synchronous. */
 bcur_status bcur_decompose_boost(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda,
@@ -422,7 +459,7 @@ typedef struct bcur_request {
     const int64_t* row_off;  /* host or NULL, copied */
     int64_t Gr;
     bcur_params params;
-    const float* omega;      /* device, borrowed */
+    const float* omega;      /* device, borrowed; NULL: the test matrix of params.seed */
     const uint64_t* draws;   /* host, s + s_r words, copied */
     float* U;                /* device output or NULL, borrowed */
     int64_t ldu, u_rows_cap;

@@ -382,6 +382,30 @@ def fit_columns(A: np.ndarray, C: np.ndarray) -> Tuple[np.ndarray, float]:
     return U, float(math.sqrt(float(np.sum(E * E))))
 
 
+def fit_columns_qr(A: np.ndarray, C: np.ndarray, cols: Optional[Sequence[int]] = None,
+                   panel: int = 1024) -> Tuple[float, Optional[np.ndarray]]:
+    """err = ||A - C C^+ A||_F for a C of full column rank, by the thin
+    Householder QR C = Q R: C C^+ = Q Q^T (Sec. 2.1 projection), so the
+    residual of each column panel A_J is A_J - Q (Q^T A_J); panels of
+    ``panel`` columns keep the memory at a few m x panel arrays.  With
+    ``cols``, also U[:, cols] = R^-1 Q^T A[:, cols] (C^+ A on those columns).
+    For a rank-deficient C use ``fit_columns``."""
+    A = np.asarray(A)
+    C = np.asarray(C, dtype=np.float64)
+    Q, R = np.linalg.qr(C)
+    n = A.shape[1]
+    e2 = 0.0
+    for j0 in range(0, n, panel):
+        AJ = np.asarray(A[:, j0:j0 + panel], dtype=np.float64)
+        E = AJ - Q @ (Q.T @ AJ)
+        e2 += float(np.sum(E * E))
+    U = None
+    if cols is not None:
+        AJ = np.asarray(A[:, np.asarray(cols, dtype=np.int64)], dtype=np.float64)
+        U = np.linalg.solve(R, Q.T @ AJ)
+    return float(math.sqrt(e2)), U
+
+
 def fit_cur(A: np.ndarray, C: np.ndarray, R: np.ndarray) -> Tuple[np.ndarray, float]:
     """U = C^+ A R^+ and err = ||A - C U R||_F (the CUR fit with both
     projections, Sec. 2.1)."""

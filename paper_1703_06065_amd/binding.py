@@ -32,6 +32,7 @@ SYMBOLS = [
     "bcur_sketch_pass", "bcur_release_workspace", "bcur_footprint", "bcur_server_create", "bcur_server_destroy",
     "bcur_server_submit", "bcur_server_poll", "bcur_server_wait", "bcur_server_stats", "bcur_decompose_alg1",
     "bcur_decompose_boost", "bcur_block_stable_rank", "bcur_incoherence", "bcur_decompose_alg1_boost",
+    "bcur_test_matrix", "bcur_decompose_async", "bcur_wait",
 ]
 
 STAGES = ["frob", "rf_AQ", "rf_AtZ", "rf_reduce", "rf_orth", "rf_rr", "scores", "sample", "gather", "fit_H",
@@ -49,7 +50,7 @@ class Params(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int64), ("s", ctypes.c_int64), ("l", ctypes.c_int64), ("q", ctypes.c_int64),
                 ("replace", ctypes.c_int32), ("precision", ctypes.c_int32), ("refine", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("s_r", ctypes.c_int64), ("col_map", ctypes.POINTER(ctypes.c_int64)),
-                ("row_map", ctypes.POINTER(ctypes.c_int64))]
+                ("row_map", ctypes.POINTER(ctypes.c_int64)), ("seed", ctypes.c_uint64)]
 
 
 class Result(ctypes.Structure):
@@ -106,7 +107,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     i64, i32, u32, dbl, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_double, ctypes.c_void_p
     P = ctypes.POINTER
     sig = {
-        "bcur_create": (i32, [P(vp), i32, vp]),
+        "bcur_create": (i32, [P(vp), i32, vp, ctypes.c_size_t]),
+        "bcur_test_matrix": (i32, [vp, i64, i64, ctypes.c_uint64, vp, i64]),
+        "bcur_decompose_async": (i32, [vp, vp, i64, i64, i64, P(i64), i64, P(i64), i64, P(Params), vp,
+                                       P(ctypes.c_uint64), P(Result)]),
+        "bcur_wait": (i32, [vp]),
         "bcur_destroy": (i32, [vp]),
         "bcur_synchronize": (i32, [vp]),
         "bcur_status_str": (ctypes.c_char_p, [i32]),
@@ -183,18 +188,120 @@ def padded_empty(rows: int, cols: int, device="cuda"):
     return torch.empty((rows, ld), dtype=torch.float32, device=device)[:, :cols]
 
 
-class Context:
-    """One library context bound to a device and to torch's current stream."""
+def _omega_arg(omega, m: int, n: int, k: int, l: Optional[int]):
+    """(device pointer or None, l, seed) for a test-matrix argument that is a
+    dense n x l CUDA tensor or an integer seed (the library then draws the
+    Rademacher matrix of that seed; l defaults to min(k + 10, m, n, 128))."""
+    if isinstance(omega, (int, np.integer)):
+        if l is None:
+            l = min(k + 10, m, n, 128)
+        return None, int(l), int(omega) & ((1 << 64) - 1)
+    po, on, lo, ldo = _check_dev(omega, "omega")
+    if on != n or ldo != lo:
+        raise ValueError("omega must be a dense n x l tensor")
+    if l is not None and l != lo:
+        raise ValueError("l does not match omega")
+    return po, lo, 0
 
-    def __init__(self, device: int = 0, stream=None):
+
+def _check_map(a, count, name):
+    if a is None:
+        return None
+    a = _i64(a)
+    if a.size != count:
+        raise ValueError(f"{name} must have {count} entries")
+    return a
+
+
+class _DecomposeCall:
+    """Arguments and result buffers of one bcur_decompose call (kept alive
+    until its result is read)."""
+
+    def __init__(self, A, offsets, k, s, omega, draws, q, replace, refine, precision, want_u, row_offsets, s_r,
+                 U_out, col_map, row_map, l, seed):
+        p, m, n, lda = _check_dev(A, "A")
+        po, l, om_seed = _omega_arg(omega, m, n, k, l)
+        self.keep = [A, omega, U_out]
+        self.off = _i64(offsets)
+        G = len(self.off) - 1
+        rowv = row_offsets is not None and s_r > 0
+        self.dr = np.ascontiguousarray(draws, dtype=np.uint64)
+        if self.dr.size < s + (s_r if rowv else 0):
+            raise ValueError("need s draws (s + s_r for the row-block variant)")
+        prm = Params(k=k, s=s, l=l, q=q, replace=int(replace), precision=precision, refine=refine, reserved=0,
+                     s_r=s_r, seed=om_seed if seed is None else int(seed))
+        self.cmap = _check_map(col_map, n, "col_map")
+        self.rmap = _check_map(row_map, m, "row_map")
+        if self.cmap is not None:
+            prm.col_map = _ptr(self.cmap, ctypes.c_int64)
+        if self.rmap is not None:
+            prm.row_map = _ptr(self.rmap, ctypes.c_int64)
+        self.prm = prm
+        self.idx = np.empty(s, dtype=np.int64)
+        self.w = np.empty(s)
+        self.sc = np.empty(G)
+        self.ritz = np.empty(l)
+        res = Result()
+        res.idx = _ptr(self.idx, ctypes.c_int64)
+        res.weights = _ptr(self.w, ctypes.c_double)
+        res.scores = _ptr(self.sc, ctypes.c_double)
+        res.ritz = _ptr(self.ritz, ctypes.c_double)
+        self.U = None
+        if want_u:
+            cap = min(s * int(np.max(np.diff(self.off))), n)
+            ucols = n
+            if rowv:
+                ucols = min(s_r * int(np.max(np.diff(_i64(row_offsets)))), m)
+            self.U = U_out if U_out is not None else padded_empty(cap, ucols, A.device)
+            res.U = self.U.data_ptr()
+            res.ldu = self.U.stride(0)
+            res.u_rows_cap = self.U.shape[0]
+        roff_p, Gr = None, 0
+        self.idx_r = self.rsc = None
+        self.roff = None
+        if row_offsets is not None:
+            self.roff = _i64(row_offsets)
+            Gr = len(self.roff) - 1
+            roff_p = _ptr(self.roff, ctypes.c_int64)
+            self.idx_r = np.empty(max(s_r, 1), dtype=np.int64)
+            self.rsc = np.empty(Gr)
+            res.idx_r = _ptr(self.idx_r, ctypes.c_int64)
+            res.row_scores = _ptr(self.rsc, ctypes.c_double)
+        self.res = res
+        self.s_r = s_r
+        self.args = (p, m, n, lda, _ptr(self.off, ctypes.c_int64), G, roff_p, Gr, ctypes.byref(prm), po,
+                     _ptr(self.dr, ctypes.c_uint64), ctypes.byref(res))
+
+    def result(self):
+        res = self.res
+        out = {"idx": self.idx, "weights": self.w, "scores": self.sc, "ritz": self.ritz, "c": res.c, "r": res.r,
+               "frob2": res.frob2, "err": res.err, "rel_err": res.rel_err, "min_margin": res.min_margin,
+               "flags": res.flags, "rr_sweeps": res.rr_sweeps}
+        if self.U is not None:
+            out["U"] = self.U[:res.c, :res.r] if res.r else self.U[:res.c]
+        if self.idx_r is not None:
+            out["idx_r"] = self.idx_r[:self.s_r]
+            out["row_scores"] = self.rsc
+        return out
+
+
+class Context:
+    """One library context bound to a device and to torch's current stream.
+
+    scratch_budget: the most device workspace (bytes) the context may hold,
+    0 for no limit."""
+
+    def __init__(self, device: int = 0, stream=None, scratch_budget: int = 0):
         import torch
         self.lib = load_library()
         self.device = device
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self._stream = stream
+        self._pending = None
         h = ctypes.c_void_p()
-        st = self.lib.bcur_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream))
+        st = self.lib.bcur_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream),
+                                  ctypes.c_size_t(scratch_budget))
         if st != OK:
             raise BcurError(st, self.lib.bcur_status_str(st).decode())
         self.h = h
@@ -302,6 +409,8 @@ class Context:
     def sample_blocks(self, scores, draws, s: int, replace: bool = False):
         sc = np.ascontiguousarray(scores, dtype=np.float64)
         dr = np.ascontiguousarray(draws, dtype=np.uint64)
+        if dr.size < s:
+            raise ValueError("need s draws")
         idx = np.empty(s, dtype=np.int64)
         w = np.empty(s)
         mg = np.empty(s)
@@ -334,84 +443,78 @@ class Context:
         return U, err.value, fl.value
 
     # -- the whole path ----------------------------------------------------
+    def test_matrix(self, n: int, l: int, seed: int):
+        """The n x l Rademacher test matrix the library draws from `seed`."""
+        import torch
+        om = torch.empty((n, l), dtype=torch.float32, device=f"cuda:{self.device}")
+        self._chk(self.lib.bcur_test_matrix(self.h, n, l, int(seed) & ((1 << 64) - 1), om.data_ptr(), l))
+        return om
+
+    def footprint(self, m: int, n: int, offsets, k: int, s: int, l: int, q: int = 2,
+                  precision: int = PREC_FP32, row_offsets=None, s_r: int = 0, library_holds_u: bool = False,
+                  col_map=None, row_map=None) -> int:
+        """bcur_footprint: device workspace bytes of one decomposition of these shapes."""
+        off = _i64(offsets)
+        prm = Params(k=k, s=s, l=l, q=q, precision=precision, s_r=s_r)
+        cmap = _check_map(col_map, n, "col_map")
+        rmap = _check_map(row_map, m, "row_map")
+        if cmap is not None:
+            prm.col_map = _ptr(cmap, ctypes.c_int64)
+        if rmap is not None:
+            prm.row_map = _ptr(rmap, ctypes.c_int64)
+        roff = _i64(row_offsets) if row_offsets is not None else None
+        out = ctypes.c_size_t()
+        self._chk(self.lib.bcur_footprint(m, n, _ptr(off, ctypes.c_int64), len(off) - 1,
+                                          None if roff is None else _ptr(roff, ctypes.c_int64),
+                                          0 if roff is None else len(roff) - 1, ctypes.byref(prm),
+                                          int(library_holds_u), ctypes.byref(out)))
+        return int(out.value)
+
     def decompose(self, A, offsets, k: int, s: int, omega, draws, q: int = 2, replace: bool = False,
                   refine: int = 1, precision: int = PREC_FP32, want_u: bool = True, row_offsets=None,
-                  s_r: int = 0, U_out=None, col_map=None, row_map=None):
-        p, m, n, lda = _check_dev(A, "A")
-        po, on, l, ldo = _check_dev(omega, "omega")
-        if on != n or ldo != l:
-            raise ValueError("omega must be a dense n x l tensor")
-        off = _i64(offsets)
-        G = len(off) - 1
-        dr = np.ascontiguousarray(draws, dtype=np.uint64)
-        prm = Params(k=k, s=s, l=l, q=q, replace=int(replace), precision=precision, refine=refine, reserved=0,
-                     s_r=s_r)
-        cmap = rmap = None
-        if col_map is not None:
-            cmap = _i64(col_map)
-            prm.col_map = _ptr(cmap, ctypes.c_int64)
-        if row_map is not None:
-            rmap = _i64(row_map)
-            prm.row_map = _ptr(rmap, ctypes.c_int64)
-        idx = np.empty(s, dtype=np.int64)
-        w = np.empty(s)
-        sc = np.empty(G)
-        ritz = np.empty(l)
-        res = Result()
-        res.idx = _ptr(idx, ctypes.c_int64)
-        res.weights = _ptr(w, ctypes.c_double)
-        res.scores = _ptr(sc, ctypes.c_double)
-        res.ritz = _ptr(ritz, ctypes.c_double)
-        U = None
-        if want_u:
-            cap = min(s * int(np.max(np.diff(off))), n)
-            ucols = n
-            if row_offsets is not None and s_r > 0:
-                ucols = min(s_r * int(np.max(np.diff(_i64(row_offsets)))), m)
-            U = U_out if U_out is not None else padded_empty(cap, ucols, A.device)
-            res.U = U.data_ptr()
-            res.ldu = U.stride(0)
-            res.u_rows_cap = U.shape[0]
-        roff_p, Gr = None, 0
-        idx_r = rsc = None
-        if row_offsets is not None:
-            roff = _i64(row_offsets)
-            Gr = len(roff) - 1
-            roff_p = _ptr(roff, ctypes.c_int64)
-            idx_r = np.empty(max(s_r, 1), dtype=np.int64)
-            rsc = np.empty(Gr)
-            res.idx_r = _ptr(idx_r, ctypes.c_int64)
-            res.row_scores = _ptr(rsc, ctypes.c_double)
-        self._chk(self.lib.bcur_decompose(self.h, p, m, n, lda, _ptr(off, ctypes.c_int64), G, roff_p, Gr,
-                                          ctypes.byref(prm), po, _ptr(dr, ctypes.c_uint64), ctypes.byref(res)))
-        out = {"idx": idx, "weights": w, "scores": sc, "ritz": ritz, "c": res.c, "r": res.r, "frob2": res.frob2,
-               "err": res.err, "rel_err": res.rel_err, "min_margin": res.min_margin, "flags": res.flags,
-               "rr_sweeps": res.rr_sweeps}
-        if U is not None:
-            out["U"] = U[:res.c, :res.r] if res.r else U[:res.c]
-        if idx_r is not None:
-            out["idx_r"] = idx_r[:s_r]
-            out["row_scores"] = rsc
-        return out
+                  s_r: int = 0, U_out=None, col_map=None, row_map=None, l: Optional[int] = None):
+        """One decomposition.  omega: a dense n x l CUDA tensor, or an integer
+        seed of the test matrix drawn on the device (sketch width `l`, by
+        default min(k + 10, m, n, 128))."""
+        call = _DecomposeCall(A, offsets, k, s, omega, draws, q, replace, refine, precision, want_u, row_offsets,
+                              s_r, U_out, col_map, row_map, l, None)
+        self._chk(self.lib.bcur_decompose(self.h, *call.args))
+        return call.result()
 
+    def decompose_async(self, A, offsets, k: int, s: int, omega, draws, q: int = 2, replace: bool = False,
+                        refine: int = 1, precision: int = PREC_FP32, want_u: bool = True, row_offsets=None,
+                        s_r: int = 0, U_out=None, col_map=None, row_map=None, l: Optional[int] = None):
+        """bcur_decompose_async: returns at once; `wait()` returns the result."""
+        if self._pending is not None:
+            raise BcurError(E_STATE, "a decomposition is already in flight on this context")
+        call = _DecomposeCall(A, offsets, k, s, omega, draws, q, replace, refine, precision, want_u, row_offsets,
+                              s_r, U_out, col_map, row_map, l, None)
+        self._chk(self.lib.bcur_decompose_async(self.h, *call.args))
+        self._pending = call
+        return call
+
+    def wait(self):
+        """bcur_wait: the result of the decomposition in flight (None if none)."""
+        call, self._pending = self._pending, None
+        self._chk(self.lib.bcur_wait(self.h))
+        return call.result() if call is not None else None
 
     def decompose_boost(self, A, offsets, k: int, s: int, omega, draws, t: int, q: int = 2, replace: bool = False,
-                        refine: int = 1, precision: int = PREC_FP32, want_u: bool = True, U_out=None, col_map=None):
+                        refine: int = 1, precision: int = PREC_FP32, want_u: bool = True, U_out=None, col_map=None,
+                        l: Optional[int] = None):
         """Boosting: t samplings (draws[i*s:(i+1)*s] for trial i) from one set of
         scores; returns the kept trial's result with every trial's err."""
         p, m, n, lda = _check_dev(A, "A")
-        po, on, l, ldo = _check_dev(omega, "omega")
-        if on != n or ldo != l:
-            raise ValueError("omega must be a dense n x l tensor")
+        po, l, om_seed = _omega_arg(omega, m, n, k, l)
         off = _i64(offsets)
         G = len(off) - 1
         dr = np.ascontiguousarray(draws, dtype=np.uint64)
         if dr.size < t * s:
             raise ValueError("need t * s draws")
-        prm = Params(k=k, s=s, l=l, q=q, replace=int(replace), precision=precision, refine=refine, reserved=0, s_r=0)
-        cmap = None
-        if col_map is not None:
-            cmap = _i64(col_map)
+        prm = Params(k=k, s=s, l=l, q=q, replace=int(replace), precision=precision, refine=refine, reserved=0, s_r=0,
+                     seed=om_seed)
+        cmap = _check_map(col_map, n, "col_map")
+        if cmap is not None:
             prm.col_map = _ptr(cmap, ctypes.c_int64)
         idx = np.empty(s, dtype=np.int64)
         w = np.empty(s)
@@ -457,9 +560,8 @@ class Context:
             raise ValueError("need r + s draws")
         errs = best = None
         prm = Alg1Params(r=r, kr=kr, s=s, rank_k=rank_k, replace=int(replace), pinv_eig=int(pinv_eig))
-        cmap = None
-        if col_map is not None:
-            cmap = _i64(col_map)
+        cmap = _check_map(col_map, n, "col_map")
+        if cmap is not None:
             prm.col_map = _ptr(cmap, ctypes.c_int64)
         rows = np.empty(r, dtype=np.int64)
         idx = np.empty(s, dtype=np.int64)
@@ -526,14 +628,15 @@ class Server:
 
     def submit(self, A, offsets, k: int, s: int, omega, draws, q: int = 2, replace: bool = False,
                refine: int = 1, precision: int = PREC_FP32, row_offsets=None, s_r: int = 0, U_out=None,
-               col_map=None):
+               col_map=None, l: Optional[int] = None):
+        """omega: a dense n x l CUDA tensor or an integer seed (as in Context.decompose)."""
         import torch
         p, m, n, lda = _check_dev(A, "A")
-        po, on, l, ldo = _check_dev(omega, "omega")
-        if on != n or ldo != l:
-            raise ValueError("omega must be a dense n x l tensor")
+        po, l, om_seed = _omega_arg(omega, m, n, k, l)
         off = _i64(offsets)
         dr = np.ascontiguousarray(draws, dtype=np.uint64)
+        if dr.size < s + (s_r if row_offsets is not None and s_r > 0 else 0):
+            raise ValueError("need s draws (s + s_r for the row-block variant)")
         rq = Request()
         rq.A, rq.m, rq.n, rq.lda = p, m, n, lda
         rq.col_off, rq.G = _ptr(off, ctypes.c_int64), len(off) - 1
@@ -542,10 +645,9 @@ class Server:
             roff = _i64(row_offsets)
             rq.row_off, rq.Gr = _ptr(roff, ctypes.c_int64), len(roff) - 1
         rq.params = Params(k=k, s=s, l=l, q=q, replace=int(replace), precision=precision, refine=refine,
-                           reserved=0, s_r=s_r if roff is not None else 0)
-        cmap = None   # copied by the server at submission
-        if col_map is not None:
-            cmap = _i64(col_map)
+                           reserved=0, s_r=s_r if roff is not None else 0, seed=om_seed)
+        cmap = _check_map(col_map, n, "col_map")   # copied by the server at submission
+        if cmap is not None:
             rq.params.col_map = _ptr(cmap, ctypes.c_int64)
         rq.omega = po
         rq.draws = _ptr(dr, ctypes.c_uint64)

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/bcur.h"
@@ -26,10 +27,22 @@ struct StageTimer {
     int64_t count[BCUR_NUM_STAGES] = {};
 };
 
+// Host copies of an asynchronous decomposition's inputs (bcur_decompose_async).
+struct AsyncJob {
+    const float* A = nullptr;
+    int64_t m = 0, n = 0, lda = 0, G = 0, Gr = 0;
+    std::vector<int64_t> col_off, row_off, col_map, row_map;
+    std::vector<uint64_t> draws;
+    bcur_params p{};
+    const float* omega = nullptr;
+    bcur_result* res = nullptr;
+};
+
 struct bcur_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    size_t budget = 0;         // most device workspace the context may hold (0: no limit)
     char* ws = nullptr;
     size_t ws_bytes = 0;
     char* pinned = nullptr;
@@ -37,6 +50,14 @@ struct bcur_ctx {
     bool pinned_busy = false;  // a call left copies into `pinned` without synchronizing
     std::string err;
     StageTimer timer;
+    // asynchronous decomposition: its host thread, its stream (default
+    // priority) and the event that orders it after the caller's stream
+    std::thread worker;
+    bool inflight = false;
+    bcur_status job_status = BCUR_OK;
+    hipStream_t astream = nullptr;
+    hipEvent_t ev_in = nullptr;
+    AsyncJob job;
 };
 
 namespace {
@@ -70,6 +91,15 @@ bcur_status fail(bcur_ctx* ctx, bcur_status st, const char* fmt, ...) {
         if (s_ != BCUR_OK) return s_;         \
     } while (0)
 
+// Entry points other than bcur_wait refuse to run while an asynchronous
+// decomposition uses the context (its host thread owns the context's state,
+// the error message included, until bcur_wait).
+#define GUARD(ctx)                                  \
+    do {                                            \
+        if (!(ctx)) return BCUR_E_ARG;              \
+        if ((ctx)->inflight) return BCUR_E_STATE;   \
+    } while (0)
+
 // Bump allocator over the context workspace.  Layout functions run twice:
 // once with a null base to size the workspace, once to hand out pointers.
 struct Arena {
@@ -86,11 +116,15 @@ struct Arena {
 
 bcur_status reserve(bcur_ctx* ctx, size_t bytes) {
     if (bytes <= ctx->ws_bytes) return BCUR_OK;
+    if (ctx->budget && bytes > ctx->budget)
+        return fail(ctx, BCUR_E_NOMEM, "the call needs %zu bytes of device workspace, over the context's budget of %zu",
+                    bytes, ctx->budget);
     HIPCHK(hipStreamSynchronize(ctx->stream));
     if (ctx->ws) HIPCHK(hipFree(ctx->ws));
     ctx->ws = nullptr;
     ctx->ws_bytes = 0;
     size_t want = bytes + bytes / 8;
+    if (ctx->budget) want = std::min(want, ctx->budget);
     if (hipMalloc(&ctx->ws, want) != hipSuccess) {
         ctx->ws = nullptr;
         return fail(ctx, BCUR_E_NOMEM, "device workspace of %zu bytes", want);
@@ -342,14 +376,18 @@ bcur_status cast_a_bf16(bcur_ctx* ctx, const RFBufs& b, const float* A, int64_t 
 // caller computes it separately on the BF16 path (range_finder_fuses_frob).
 bool range_finder_fuses_frob(int64_t q, int precision) { return !(precision == BCUR_PREC_BF16 && q > 0); }
 
+// omega: device n x l (dense), or null: the test matrix of `seed` is drawn into Q.
 bcur_status range_finder_run(bcur_ctx* ctx, const RFBufs& b, const float* A, int64_t m, int64_t n, int64_t lda,
-                             const float* omega, int64_t l, int64_t k, int64_t q, float* Vk, float* Uk,
+                             const float* omega, uint64_t seed, int64_t l, int64_t k, int64_t q, float* Vk, float* Uk,
                              int precision = BCUR_PREC_FP32, double* frob2 = nullptr) {
     hipStream_t st = ctx->stream;
     const int64_t lp = round4(l);
     HIPCHK(hipMemsetAsync(b.info, 0, 4 * sizeof(int), st));
-    HIPCHK(hipMemcpy2DAsync(b.Q, lp * sizeof(float), omega, l * sizeof(float), l * sizeof(float), n,
-                            hipMemcpyDeviceToDevice, st));
+    if (omega)
+        HIPCHK(hipMemcpy2DAsync(b.Q, lp * sizeof(float), omega, l * sizeof(float), l * sizeof(float), n,
+                                hipMemcpyDeviceToDevice, st));
+    else
+        HIPCHK(launch_test_matrix(seed, n, l, lp, b.Q, lp, st));
     const GemmPlan pz = plan_sgemm(m, l, n, false, true);
     const GemmPlan py = plan_sgemm(n, l, m, true, true);
     const bool bf16 = precision == BCUR_PREC_BF16 && q > 0;
@@ -761,6 +799,7 @@ const char* bcur_last_error(const bcur_ctx* ctx) { return ctx ? ctx->err.c_str()
 size_t bcur_workspace_bytes(const bcur_ctx* ctx) { return ctx ? ctx->ws_bytes : 0; }
 
 bcur_status bcur_release_workspace(bcur_ctx* ctx) {
+    GUARD(ctx);
     if (!ctx) return BCUR_E_ARG;
     HIPCHK(hipStreamSynchronize(ctx->stream));
     if (ctx->ws) HIPCHK(hipFree(ctx->ws));
@@ -780,7 +819,7 @@ bcur_status bcur_footprint(int64_t m, int64_t n, const int64_t* col_off, int64_t
     return BCUR_OK;
 }
 
-bcur_status bcur_create(bcur_ctx** out, int device, void* stream) {
+bcur_status bcur_create(bcur_ctx** out, int device, void* stream, size_t scratch_budget) {
     if (!out) return BCUR_E_ARG;
     *out = nullptr;
     int count = 0;
@@ -793,12 +832,14 @@ bcur_status bcur_create(bcur_ctx** out, int device, void* stream) {
         return BCUR_E_HIP;
     }
     ctx->stream = (hipStream_t)stream;   // NULL: the device's null stream
+    ctx->budget = scratch_budget;
     *out = ctx;
     return BCUR_OK;
 }
 
 bcur_status bcur_destroy(bcur_ctx* ctx) {
     if (!ctx) return BCUR_E_ARG;
+    (void)bcur_wait(ctx);
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->ws) (void)hipFree(ctx->ws);
@@ -806,17 +847,21 @@ bcur_status bcur_destroy(bcur_ctx* ctx) {
     timer_resolve(ctx);
     for (hipEvent_t e : ctx->timer.pool) (void)hipEventDestroy(e);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    if (ctx->astream) (void)hipStreamDestroy(ctx->astream);
+    if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
     delete ctx;
     return BCUR_OK;
 }
 
 bcur_status bcur_synchronize(bcur_ctx* ctx) {
+    GUARD(ctx);
     if (!ctx) return BCUR_E_ARG;
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return BCUR_OK;
 }
 
 bcur_status bcur_timing_enable(bcur_ctx* ctx, int32_t on) {
+    GUARD(ctx);
     if (!ctx) return BCUR_E_ARG;
     HIPCHK(hipStreamSynchronize(ctx->stream));
     timer_resolve(ctx);
@@ -830,6 +875,7 @@ bcur_status bcur_timing_enable(bcur_ctx* ctx, int32_t on) {
 }
 
 bcur_status bcur_timing_read(bcur_ctx* ctx, double* ms, int64_t* count) {
+    GUARD(ctx);
     if (!ctx || !ms || !count) return BCUR_E_ARG;
     timer_resolve(ctx);
     for (int i = 0; i < BCUR_NUM_STAGES; ++i) {
@@ -839,8 +885,18 @@ bcur_status bcur_timing_read(bcur_ctx* ctx, double* ms, int64_t* count) {
     return BCUR_OK;
 }
 
+bcur_status bcur_test_matrix(bcur_ctx* ctx, int64_t n, int64_t l, uint64_t seed, float* omega, int64_t ldo) {
+    GUARD(ctx);
+    if (!omega) return fail(ctx, BCUR_E_ARG, "omega is required");
+    if (n < 1 || l < 1 || l > 256 || ldo < l) return fail(ctx, BCUR_E_ARG, "need n >= 1, 1 <= l <= 256, ldo >= l");
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(launch_test_matrix(seed, n, l, l, omega, ldo, ctx->stream));
+    return BCUR_OK;
+}
+
 bcur_status bcur_frob2(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda, double* out_frob2,
                        int32_t* out_finite) {
+    GUARD(ctx);
     if (!ctx || !out_frob2) return fail(ctx, BCUR_E_ARG, "null argument");
     STCHK(check_matrix(ctx, A, m, n, lda, "A"));
     HIPCHK(hipSetDevice(ctx->device));
@@ -864,6 +920,7 @@ bcur_status bcur_frob2(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int6
 
 bcur_status bcur_range_finder(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda, const float* omega,
                               int64_t l, int64_t k, int64_t q, int32_t precision, float* Vk, float* Uk, double* ritz) {
+    GUARD(ctx);
     if (!ctx) return BCUR_E_ARG;
     STCHK(check_matrix(ctx, A, m, n, lda, "A"));
     if (!omega || !Vk) return fail(ctx, BCUR_E_ARG, "omega and Vk are required");
@@ -880,7 +937,7 @@ bcur_status bcur_range_finder(bcur_ctx* ctx, const float* A, int64_t m, int64_t 
     STCHK(reserve(ctx, a.off));
     Arena r{ctx->ws, 0};
     rf_layout(r, b, m, n, l, k, bf16);
-    STCHK(range_finder_run(ctx, b, A, m, n, lda, omega, l, k, q, Vk, Uk, precision));
+    STCHK(range_finder_run(ctx, b, A, m, n, lda, omega, 0, l, k, q, Vk, Uk, precision));
     if (ritz) {
         STCHK(reserve_pinned(ctx, l * sizeof(double)));
         HIPCHK(hipMemcpyAsync(ctx->pinned, b.lam, l * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
@@ -893,6 +950,7 @@ bcur_status bcur_range_finder(bcur_ctx* ctx, const float* A, int64_t m, int64_t 
 
 bcur_status bcur_sketch_pass(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda, const float* Q,
                              int64_t l, int64_t ldq, int32_t precision, float* Y, int64_t ldy) {
+    GUARD(ctx);
     if (!ctx) return BCUR_E_ARG;
     STCHK(check_matrix(ctx, A, m, n, lda, "A"));
     STCHK(check_matrix(ctx, Q, n, l, ldq, "Q"));
@@ -930,6 +988,7 @@ bcur_status bcur_sketch_pass(bcur_ctx* ctx, const float* A, int64_t m, int64_t n
 
 bcur_status bcur_block_scores(bcur_ctx* ctx, const float* V, int64_t n, int64_t k, int64_t ldv, const int64_t* offsets,
                               int64_t G, double* scores) {
+    GUARD(ctx);
     if (!ctx || !V || !scores) return fail(ctx, BCUR_E_ARG, "null argument");
     if (n < 1 || k < 1 || ldv < k) return fail(ctx, BCUR_E_ARG, "bad V shape");
     STCHK(check_offsets(ctx, offsets, G, n, "offsets"));
@@ -951,6 +1010,7 @@ bcur_status bcur_block_scores(bcur_ctx* ctx, const float* V, int64_t n, int64_t 
 bcur_status bcur_block_stable_rank(bcur_ctx* ctx, const float* V, int64_t n, int64_t k, int64_t ldv,
                                    const int64_t* offsets, int64_t G, const int64_t* col_map, double* ratios,
                                    int32_t* steps, double* alpha) {
+    GUARD(ctx);
     if (!ctx || !V || !alpha) return fail(ctx, BCUR_E_ARG, "null argument");
     if (n < 1 || k < 1 || ldv < k) return fail(ctx, BCUR_E_ARG, "bad V shape");
     STCHK(check_offsets(ctx, offsets, G, n, "offsets"));
@@ -1001,6 +1061,7 @@ bcur_status bcur_block_stable_rank(bcur_ctx* ctx, const float* V, int64_t n, int
 }
 
 bcur_status bcur_incoherence(bcur_ctx* ctx, const float* U, int64_t m, int64_t k, int64_t ldu, double* mu) {
+    GUARD(ctx);
     if (!ctx || !U || !mu) return fail(ctx, BCUR_E_ARG, "null argument");
     if (m < 1 || k < 1 || ldu < k) return fail(ctx, BCUR_E_ARG, "bad U shape");
     HIPCHK(hipSetDevice(ctx->device));
@@ -1024,6 +1085,7 @@ bcur_status bcur_incoherence(bcur_ctx* ctx, const float* U, int64_t m, int64_t k
 
 bcur_status bcur_sample_blocks(bcur_ctx* ctx, const double* scores, int64_t G, const uint64_t* draws, int64_t s,
                                int32_t replace, int64_t* idx, double* weights, double* margins) {
+    GUARD(ctx);
     if (!ctx || !scores || !draws || !idx) return fail(ctx, BCUR_E_ARG, "null argument");
     if (G < 1 || s < 1 || (!replace && s > G)) return fail(ctx, BCUR_E_ARG, "need 1 <= s <= G (without replacement)");
     HIPCHK(hipSetDevice(ctx->device));
@@ -1068,6 +1130,7 @@ bcur_status bcur_sample_blocks(bcur_ctx* ctx, const double* scores, int64_t G, c
 
 bcur_status bcur_gather_columns(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda, const int64_t* offsets,
                                 int64_t G, const int64_t* idx, int64_t s, float* C, int64_t ldc, int64_t* c_out) {
+    GUARD(ctx);
     if (!ctx || !idx || !C || !c_out) return fail(ctx, BCUR_E_ARG, "null argument");
     STCHK(check_matrix(ctx, A, m, n, lda, "A"));
     STCHK(check_offsets(ctx, offsets, G, n, "offsets"));
@@ -1092,6 +1155,7 @@ bcur_status bcur_gather_columns(bcur_ctx* ctx, const float* A, int64_t m, int64_
 
 bcur_status bcur_fit_columns(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda, const float* C, int64_t c,
                              int64_t ldc, int32_t refine, float* U, int64_t ldu, double* err, uint32_t* flags) {
+    GUARD(ctx);
     if (!ctx || !U || !err) return fail(ctx, BCUR_E_ARG, "null argument");
     STCHK(check_matrix(ctx, A, m, n, lda, "A"));
     STCHK(check_matrix(ctx, C, m, c, ldc, "C"));
@@ -1122,11 +1186,14 @@ bcur_status bcur_fit_columns(bcur_ctx* ctx, const float* A, int64_t m, int64_t n
     return BCUR_OK;
 }
 
-bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda, const int64_t* col_off,
+}  // extern "C"
+
+namespace {
+
+bcur_status decompose_impl(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda, const int64_t* col_off,
                            int64_t G, const int64_t* row_off, int64_t Gr, const bcur_params* p, const float* omega,
                            const uint64_t* draws, bcur_result* res) {
-    if (!ctx) return BCUR_E_ARG;
-    if (!p || !res || !omega || !draws || !res->idx) return fail(ctx, BCUR_E_ARG, "null argument");
+    if (!p || !res || !draws || !res->idx) return fail(ctx, BCUR_E_ARG, "null argument");
     STCHK(check_matrix(ctx, A, m, n, lda, "A"));
     STCHK(check_offsets(ctx, col_off, G, n, "col_off"));
     const int64_t k = p->k, l = p->l, s = p->s, q = p->q;
@@ -1251,7 +1318,7 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
         HIPCHK(launch_frob2(A, m, n, lda, d_fpart, frob2_grid(m, n), d_frob, st));
     }
     // 2. sketched top-k right subspace (and left vectors for the row blocks)
-    STCHK(range_finder_run(ctx, rb, A, m, n, lda, omega, l, k, q, Vk, Uk, p->precision,
+    STCHK(range_finder_run(ctx, rb, A, m, n, lda, omega, p->seed, l, k, q, Vk, Uk, p->precision,
                            fused_frob ? d_frob : nullptr));
     // 3. block scores (with a map, over the rows of V_k (U_k) listed in map
     // order, so each block's rows are contiguous), 4. sampling
@@ -1400,11 +1467,84 @@ bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
     return BCUR_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda, const int64_t* col_off,
+                           int64_t G, const int64_t* row_off, int64_t Gr, const bcur_params* p, const float* omega,
+                           const uint64_t* draws, bcur_result* res) {
+    GUARD(ctx);
+    return decompose_impl(ctx, A, m, n, lda, col_off, G, row_off, Gr, p, omega, draws, res);
+}
+
+bcur_status bcur_decompose_async(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda,
+                                 const int64_t* col_off, int64_t G, const int64_t* row_off, int64_t Gr,
+                                 const bcur_params* p, const float* omega, const uint64_t* draws, bcur_result* res) {
+    GUARD(ctx);
+    if (!p || !res || !draws || !res->idx || !col_off) return fail(ctx, BCUR_E_ARG, "null argument");
+    STCHK(check_offsets(ctx, col_off, G, n, "col_off"));
+    const bool rowv = row_off != nullptr && p->s_r > 0;
+    if (rowv) STCHK(check_offsets(ctx, row_off, Gr, m, "row_off"));
+    if (p->s < 1 || p->s_r < 0) return fail(ctx, BCUR_E_ARG, "need s >= 1 and s_r >= 0");
+    AsyncJob& j = ctx->job;
+    j.A = A;
+    j.m = m;
+    j.n = n;
+    j.lda = lda;
+    j.G = G;
+    j.Gr = rowv ? Gr : 0;
+    j.col_off.assign(col_off, col_off + G + 1);
+    if (rowv) j.row_off.assign(row_off, row_off + Gr + 1);
+    else j.row_off.clear();
+    j.draws.assign(draws, draws + p->s + (rowv ? p->s_r : 0));
+    j.p = *p;
+    if (p->col_map) j.col_map.assign(p->col_map, p->col_map + n);
+    else j.col_map.clear();
+    if (rowv && p->row_map) j.row_map.assign(p->row_map, p->row_map + m);
+    else j.row_map.clear();
+    j.p.col_map = j.col_map.empty() ? nullptr : j.col_map.data();
+    j.p.row_map = j.row_map.empty() ? nullptr : j.row_map.data();
+    j.omega = omega;
+    j.res = res;
+    HIPCHK(hipSetDevice(ctx->device));
+    if (!ctx->astream) HIPCHK(hipStreamCreateWithFlags(&ctx->astream, hipStreamNonBlocking));
+    if (!ctx->ev_in) HIPCHK(hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(ctx->ev_in, ctx->stream));
+    HIPCHK(hipStreamWaitEvent(ctx->astream, ctx->ev_in, 0));
+    ctx->inflight = true;
+    ctx->worker = std::thread([ctx]() {
+        AsyncJob& jb = ctx->job;
+        if (hipSetDevice(ctx->device) != hipSuccess) {
+            ctx->job_status = fail(ctx, BCUR_E_HIP, "hipSetDevice failed on the context's host thread");
+            return;
+        }
+        hipStream_t caller = ctx->stream;
+        ctx->stream = ctx->astream;
+        ctx->job_status = decompose_impl(ctx, jb.A, jb.m, jb.n, jb.lda, jb.col_off.data(), jb.G,
+                                         jb.row_off.empty() ? nullptr : jb.row_off.data(), jb.Gr, &jb.p, jb.omega,
+                                         jb.draws.data(), jb.res);
+        // a failed call may have left work queued: finish it before the stream is handed back
+        (void)hipStreamSynchronize(ctx->astream);
+        ctx->stream = caller;
+    });
+    return BCUR_OK;
+}
+
+bcur_status bcur_wait(bcur_ctx* ctx) {
+    if (!ctx) return BCUR_E_ARG;
+    if (!ctx->inflight) return BCUR_OK;
+    ctx->worker.join();
+    ctx->inflight = false;
+    return ctx->job_status;
+}
+
 bcur_status bcur_decompose_boost(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda,
                                  const int64_t* col_off, int64_t G, const bcur_params* p, const float* omega,
                                  int64_t t, const uint64_t* draws, bcur_result* res, double* errs, int64_t* best_out) {
     if (!ctx) return BCUR_E_ARG;
-    if (!p || !res || !omega || !draws || !res->idx || !errs) return fail(ctx, BCUR_E_ARG, "null argument");
+    GUARD(ctx);
+    if (!p || !res || !draws || !res->idx || !errs) return fail(ctx, BCUR_E_ARG, "null argument");
     STCHK(check_matrix(ctx, A, m, n, lda, "A"));
     STCHK(check_offsets(ctx, col_off, G, n, "col_off"));
     const int64_t k = p->k, l = p->l, s = p->s, q = p->q;
@@ -1521,7 +1661,7 @@ bcur_status bcur_decompose_boost(bcur_ctx* ctx, const float* A, int64_t m, int64
         HIPCHK(launch_frob2(A, m, n, lda, d_fpart, frob2_grid(m, n), d_frob, st));
     }
     // one top-k subspace and one set of scores for every trial
-    STCHK(range_finder_run(ctx, rb, A, m, n, lda, omega, l, k, q, Vk, nullptr, p->precision,
+    STCHK(range_finder_run(ctx, rb, A, m, n, lda, omega, p->seed, l, k, q, Vk, nullptr, p->precision,
                            fused_frob ? d_frob : nullptr));
     {
         StageScope ts(ctx, BCUR_STAGE_SCORES);
@@ -1899,6 +2039,7 @@ static bcur_status alg1_impl(bcur_ctx* ctx, const float* A, int64_t m, int64_t n
 bcur_status bcur_decompose_alg1(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda,
                                 const int64_t* col_off, int64_t G, const bcur_alg1_params* p, const uint64_t* draws,
                                 bcur_alg1_result* res) {
+    GUARD(ctx);
     if (!ctx) return BCUR_E_ARG;
     if (!res) return fail(ctx, BCUR_E_ARG, "null argument");
     return alg1_impl(ctx, A, m, n, lda, col_off, G, p, draws, res, res->U ? 0 : 1, res->U ? -1 : 0, nullptr);
@@ -1908,6 +2049,7 @@ bcur_status bcur_decompose_alg1_boost(bcur_ctx* ctx, const float* A, int64_t m, 
                                       const int64_t* col_off, int64_t G, const bcur_alg1_params* p, int64_t t,
                                       const uint64_t* draws, bcur_alg1_result* res, double* errs,
                                       int64_t* best_out) {
+    GUARD(ctx);
     if (!ctx) return BCUR_E_ARG;
     if (!p || !res || !draws || !res->rows || !res->idx || !errs) return fail(ctx, BCUR_E_ARG, "null argument");
     if (t < 1 || t > kMaxTrials) return fail(ctx, BCUR_E_ARG, "need 1 <= t <= %lld", (long long)kMaxTrials);

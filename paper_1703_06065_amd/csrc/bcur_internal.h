@@ -26,6 +26,11 @@ hipError_t launch_gather_cols(const float* A, int64_t lda, int64_t m, const int6
 // outside [0, G) is read as 0
 hipError_t launch_expand_blocks(const int64_t* idx, int64_t s, const int64_t* off, int64_t G, const int64_t* map,
                                 int64_t b, int64_t* out, hipStream_t st);
+// Q (n x wcols, ldq) = the Rademacher test matrix of `seed` in columns 0 .. l-1 (l <= 256,
+// l <= wcols <= 256), zero in columns l .. wcols-1: row i from the Philox4x64-10 block of
+// counter (i, 0, 0, 0) and key (seed, 0), bit j giving +1 (0) or -1 (1)
+hipError_t launch_test_matrix(uint64_t seed, int64_t n, int64_t l, int64_t wcols, float* Q, int64_t ldq,
+                              hipStream_t st);
 hipError_t launch_gather_rows(const float* A, int64_t lda, int64_t n, const int64_t* d_rows, int64_t r,
                               float* R, int64_t ldr, hipStream_t st);
 hipError_t launch_sum_f64(const double* x, int64_t count, double* out, hipStream_t st);

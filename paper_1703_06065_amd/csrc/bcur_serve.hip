@@ -212,7 +212,7 @@ bcur_status bcur_server_create(bcur_server** out, int device, size_t hbm_budget,
     for (int i = 0; i < max_slots; ++i) {
         Slot& sl = srv->slots[i];
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
-            bcur_create(&sl.ctx, device, sl.stream) != BCUR_OK) {
+            bcur_create(&sl.ctx, device, sl.stream, 0) != BCUR_OK) {
             for (int j = 0; j <= i; ++j) {
                 if (srv->slots[j].ctx) bcur_destroy(srv->slots[j].ctx);
                 if (srv->slots[j].stream) (void)hipStreamDestroy(srv->slots[j].stream);

@@ -324,6 +324,57 @@ __global__ __launch_bounds__(1024) void k_sample(const double* __restrict__ scor
 // A block index outside [0, G) (the sampler did not run on valid scores) is
 // read as block 0, so every later access stays in bounds; the host rejects
 // such a result after its synchronization.
+// ---- the seeded test matrix ---------------------------------------------------
+//
+// Philox4x64-10 (Salmon, Moraes, Dror and Shaw, SC 2011): four 64-bit counter
+// words and two key words; each of the ten rounds takes the full 128-bit
+// products of words 0 and 2 with the two round multipliers and bumps the key
+// by the two Weyl constants.
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+    constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
+        const uint64_t lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
+        c[0] = hi1 ^ c[1] ^ k0;
+        c[1] = lo1;
+        c[2] = hi0 ^ c[3] ^ k1;
+        c[3] = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+}
+
+// Rademacher test matrix: row i is the Philox block of counter (i, 0, 0, 0)
+// and key (seed, 0); bit j of its 256 bits (word j / 64, bit j % 64) gives
+// +1 (bit 0) or -1 (bit 1) in column j < l; columns l .. wcols-1 get 0.  One
+// workgroup makes kOmRows rows: one thread per row draws the block into LDS,
+// then the workgroup writes the rows with consecutive threads on consecutive
+// columns.
+constexpr int kOmRows = 64;
+__global__ __launch_bounds__(256) void k_test_matrix(uint64_t seed, int64_t n, int l, int wcols,
+                                                     float* __restrict__ Q, int64_t ldq) {
+    __shared__ uint64_t words[kOmRows][4];
+    const int64_t r0 = (int64_t)blockIdx.x * kOmRows;
+    const int t = threadIdx.x;
+    if (t < kOmRows && r0 + t < n) {
+        uint64_t c[4] = {(uint64_t)(r0 + t), 0, 0, 0};
+        philox4x64_10(c, seed, 0);
+#pragma unroll
+        for (int w = 0; w < 4; ++w) words[t][w] = c[w];
+    }
+    __syncthreads();
+    const int rows = (int)min<int64_t>(kOmRows, n - r0);
+    const int total = rows * wcols;
+    for (int e = t; e < total; e += 256) {
+        const int i = e / wcols, j = e - i * wcols;
+        float v = 0.0f;
+        if (j < l) v = ((words[i][j >> 6] >> (j & 63)) & 1) ? -1.0f : 1.0f;
+        Q[(r0 + i) * ldq + j] = v;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_expand_blocks(const int64_t* __restrict__ idx, int64_t s,
                                                       const int64_t* __restrict__ off, int64_t G,
                                                       const int64_t* __restrict__ map, int64_t b,
@@ -489,6 +540,14 @@ hipError_t launch_sample(const double* scores, int64_t G, const uint64_t* draws,
 hipError_t launch_gather_cols(const float* A, int64_t lda, int64_t m, const int64_t* d_cols, int64_t c, float* C,
                               int64_t ldc, hipStream_t st) {
     hipLaunchKernelGGL(k_gather_cols, grid2d(c, m), dim3(256), 0, st, A, lda, m, d_cols, c, C, ldc);
+    return hipGetLastError();
+}
+
+hipError_t launch_test_matrix(uint64_t seed, int64_t n, int64_t l, int64_t wcols, float* Q, int64_t ldq,
+                              hipStream_t st) {
+    if (n <= 0 || wcols <= 0) return hipSuccess;
+    const int64_t grid = (n + kOmRows - 1) / kOmRows;
+    k_test_matrix<<<(unsigned)grid, 256, 0, st>>>(seed, n, (int)l, (int)wcols, Q, ldq);
     return hipGetLastError();
 }
 

@@ -435,6 +435,23 @@ def check_fit_projection(O):
         prev = e
 
 
+def check_fit_qr_route(O):
+    """For a C of full column rank the QR route gives the minimum-norm least
+    squares solution too: its err and U columns equal numpy's SVD-based
+    lstsq, panel by panel (several panel widths, a ragged last panel)."""
+    rng = np.random.default_rng(34)
+    for (m, n, c) in [(200, 90, 17), (100, 300, 64), (500, 33, 5)]:
+        A = rng.standard_normal((m, n))
+        C = rng.standard_normal((m, c)) @ np.diag(np.logspace(0, -3, c))
+        U_ref, res, _, _ = np.linalg.lstsq(C, A, rcond=None)
+        e_ref = math.sqrt(float(np.sum((A - C @ U_ref) ** 2)))
+        for panel in (7, 32, n):
+            cols = [0, n // 2, n - 1]
+            err, U = O.fit_columns_qr(A, C, cols=cols, panel=panel)
+            assert abs(err - e_ref) <= 1e-10 * e_ref, (err, e_ref)
+            assert np.allclose(U, U_ref[:, cols], rtol=1e-8, atol=1e-10 * np.abs(U_ref).max())
+
+
 def check_fit_bruteforce(O, max_subsets=None):
     """Brute force over every s-subset of blocks of the tiny workload: the
     sampled error lies between the best and worst subset, and equals that
@@ -767,6 +784,7 @@ ALL_CHECKS = [
     check_block_product_variance,
     check_sampling_matrix_example,
     check_fit_projection,
+    check_fit_qr_route,
     check_cur_reductions,
     check_paper_synthetic_generator,
     check_alg1_rows_uniform_distinct,

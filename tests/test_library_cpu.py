@@ -42,10 +42,12 @@ def test_status_strings(lib):
 
 
 def test_create_rejects_null_out(lib):
-    assert lib.bcur_create(None, 0, None) == binding.E_ARG
+    assert lib.bcur_create(None, 0, None, 0) == binding.E_ARG
 
 
 def test_calls_reject_null_context(lib):
     assert lib.bcur_destroy(None) == binding.E_ARG
     assert lib.bcur_synchronize(None) == binding.E_ARG
+    assert lib.bcur_wait(None) == binding.E_ARG
+    assert lib.bcur_test_matrix(None, 4, 4, 0, None, 4) == binding.E_ARG
     assert lib.bcur_last_error(None) == b""

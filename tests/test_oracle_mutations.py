@@ -200,8 +200,26 @@ def _omega_counter_from_one(n, l, seed):
     return out
 
 
+def _fit_qr_drops_last_panel(A, C, cols=None, panel=1024):
+    A = np.asarray(A, dtype=np.float64)
+    n = A.shape[1]
+    last = ((n - 1) // panel) * panel
+    return O.fit_columns_qr(A[:, :last] if last > 0 else A, C, cols=cols, panel=panel)[0], \
+        O.fit_columns_qr(A, C, cols=cols, panel=panel)[1]
+
+
+def _fit_qr_without_rinv(A, C, cols=None, panel=1024):
+    err, _ = O.fit_columns_qr(A, C, panel=panel)
+    if cols is None:
+        return err, None
+    Q, R = np.linalg.qr(np.asarray(C, dtype=np.float64))
+    return err, Q.T @ np.asarray(A, dtype=np.float64)[:, cols]
+
+
 MUTANTS = {
     "uk-divides-by-lam": dict(range_finder=_uk_divides_by_lam),
+    "fit-qr-drops-last-panel": dict(fit_columns_qr=_fit_qr_drops_last_panel),
+    "fit-qr-without-rinv": dict(fit_columns_qr=_fit_qr_without_rinv),
     "uk-from-q": dict(range_finder=_uk_from_q),
     "kappa-gap-off-by-one": dict(score_condition=_kappa_gap_shifted),
     "kappa-without-lam1": dict(score_condition=_kappa_without_lam1),
