@@ -26,14 +26,19 @@ def test_more_than_one_gpu_is_refused():
 
 def test_traffic_is_the_scaled_counter_readings():
     b = _bench()
-    t = b.TRAFFIC
-    want = 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
-    assert b.traffic_bytes(t["m"], t["n"], t["c"]) == round(want)
-    # the readings belong to one shape only
-    assert b.traffic_bytes(t["m"], t["n"], t["c"] + 16) is None
-    # HBM bytes per launch of the residual GEMM: at least the algorithmic 4 (mn + mc + cn)
-    m, n, c = t["m"], t["n"], t["c"]
-    assert b.traffic_bytes(m, n, c) >= 4 * (m * n + m * c + c * n)
+    src = b._source_hash()
+    fake = {"fit_E": {"src": src, "fetch_kib": 1000.0, "fetch_scale": 2.0, "write_kib": 10.0, "write_scale": 1.0}}
+    assert b.traffic_for(fake, "fit_E") == round(1024.0 * (1000.0 * 2.0 + 10.0 * 1.0))
+    assert b.traffic_for(fake, "fit_H") is None
+    # readings taken on another kernel source are not reported
+    stale = {"fit_E": dict(fake["fit_E"], src="0" * 16)}
+    assert b.traffic_for(stale, "fit_E") is None
+    # committed readings: at least the algorithmic bytes of one launch, 4 (mn + mc + cn)
+    for table, (m, n, c) in ((b.TRAFFIC_LARGE, (65536, 16384, 2048)), (b.TRAFFIC_PLAIN, (8192, 4096, 256))):
+        for st in table:
+            got = b.traffic_for(table, st)
+            if got is not None:
+                assert got >= 4 * (m * n + m * c + c * n), (st, got)
 
 
 def test_flop_model():

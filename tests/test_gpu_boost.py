@@ -3,7 +3,7 @@ oracle: t samplings from one set of scores, each fitted, the trial of
 smallest error kept.
 
 Tolerances are those of the single decomposition (tests/test_gpu_parity.py):
-scores within tau max(l_g, k/G), tau = max(1e-5, 64 u32 kappa); each trial's
+scores within the derived gate of tests/gates.py; each trial's
 blocks identical when its smallest margin exceeds 2 G max_g tol_g; each
 trial's err within 1e-5 relative plus 16 u32 ||A||_F.  The kept trial must be
 the oracle's whenever the oracle's best error is ahead of every other trial's
@@ -19,10 +19,11 @@ import torch
 from oracle import bcur_oracle as O
 from workloads import gen
 
+from .gates import index_margin_needed, score_gate
+
 pytestmark = pytest.mark.gpu
 
 U32 = 2.0 ** -24
-SCORE_C = 64.0
 
 
 @pytest.fixture(scope="module")
@@ -53,11 +54,10 @@ def check_boost(ctx, w, t, seed, replace=False, label=""):
     note(f"boost {label} {w.name} m={w.m} n={w.n} G={w.G} k={w.k} s={w.s} t={t} replace={replace}")
     res = ctx.decompose_boost(dev(w.A), w.offsets, w.k, w.s, dev_dense(w.omega), draws, t, q=w.q, replace=replace)
     ref = O.boost(w.A, w.offsets, w.k, w.s, w.omega, draws, t, q=w.q, replace=replace)
-    tau = max(1e-5, SCORE_C * U32 * min(ref["kappa"], 1e12))
-    tol = tau * np.maximum(ref["scores"], w.k / w.G)
+    tol = score_gate(w.A, w.offsets, w.k, w.q, w.omega, ref["scores"])["tol"]
     assert np.all(np.abs(res["scores"] - ref["scores"]) <= tol)
     assert abs(res["frob2"] - ref["frob2"]) <= 1e-12 * ref["frob2"]
-    need = 2 * w.G * tol.max()
+    need = index_margin_needed(tol)
     etol = err_tol(max(ref["errs"]), ref["frob2"])
     # every trial: the oracle's errors where the selections agree
     for i, tr in enumerate(ref["trials"]):

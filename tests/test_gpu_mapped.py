@@ -1,7 +1,7 @@
 """Blocks of arbitrary column (row) sets on the GPU: block g is the set
 col_map[off[g] .. off[g+1]-1] (Def. 2 with a scattered E_g).  Parity with the
 FP64 oracle's decompose_mapped under the tolerances of tests/test_gpu_parity.py
-(scores tau max(l_g, k/G), blocks identical when the margin allows, err 1e-5
+(scores within the derived gate of tests/gates.py, blocks identical when the margin allows, err 1e-5
 relative plus 16 u32 ||A||_F); the identity map reproduces the contiguous
 path bit for bit, and the server returns the same result as the direct call.
 """
@@ -14,10 +14,11 @@ import torch
 from oracle import bcur_oracle as O
 from workloads import gen
 
+from .gates import index_margin_needed, score_gate
+
 pytestmark = pytest.mark.gpu
 
 U32 = 2.0 ** -24
-SCORE_C = 64.0
 
 
 @pytest.fixture(scope="module")
@@ -51,10 +52,13 @@ def check_mapped(ctx, w, col_map=None, row_map=None, row_offsets=None, s_r=0, la
                         row_map=row_map, row_offsets=row_offsets, s_r=s_r)
     ref = O.decompose_mapped(w.A, w.offsets, w.k, w.s, w.omega, draws, col_map=col_map, row_map=row_map, q=w.q,
                              row_offsets=row_offsets, s_r=s_r)
-    tau = max(1e-5, SCORE_C * U32 * min(ref["kappa"], 1e12))
-    tol = tau * np.maximum(ref["scores"], w.k / w.G)
+    # the gate of the contiguous problem on A with its rows and columns in map order
+    cm = np.arange(w.n) if col_map is None else np.asarray(col_map)
+    rm = np.arange(w.m) if row_map is None else np.asarray(row_map)
+    gt = score_gate(w.A[np.ix_(rm, cm)], w.offsets, w.k, w.q, w.omega[cm], ref["scores"])
+    tol = gt["tol"]
     assert np.all(np.abs(res["scores"] - ref["scores"]) <= tol)
-    need = 2 * w.G * tol.max()
+    need = index_margin_needed(tol)
     note(f"  idx gpu={list(res['idx'])} oracle={list(ref['idx'])} margin={ref['margins'].min():.2e} need {need:.2e}")
     if ref["margins"].min() > need:
         assert np.array_equal(res["idx"], ref["idx"])
