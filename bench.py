@@ -2,11 +2,16 @@
 
 One step = one whole decomposition (||A||_F^2, the sketched top-k right
 subspace, block scores, sampling, gather, U = C^+ A with one refinement step,
-and the residual) of the 8192 x 4096 float32 workload (rank-50 signal, 1e-3
-noise, 256 column blocks of 16, k = 50, s = 16, two power iterations), with A
-already resident in HBM.  Prints one JSON line.
+and the residual) with A already resident in HBM.  The default workload is
+the large one-GPU share: 65536 x 16384 float32 (rank-100 signal sigma_i =
+exp(-i/20), 1e-4 noise), 256 column blocks of 64, k = 100, s = 32, two power
+iterations; the range finder's first two iterations run in BF16, its last
+pass, the fit and the residual in FP32, the small factorizations in FP64.
+`--workload plain-fp32` runs the 8192 x 4096 FP32 workload (256 blocks of
+16, k = 50, s = 16).  The test matrix is drawn on the device from the seed.
+Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--workload W] [--mode M]
 """
 from __future__ import annotations
 
@@ -30,30 +35,11 @@ def algorithmic_flops(m, n, k, l, q, c):
     return rf, fit
 
 
-# HBM bytes per launch of the dominant kernel (the residual GEMM) from
-# rocprofv3 counter runs of this command (FETCH_SIZE and WRITE_SIZE, KiB per
-# dispatch), each scaled by the same counter's reading for a plain copy of
-# known size; None when the kernel has changed since the counters were taken.
-TRAFFIC = {"m": 8192, "n": 4096, "c": 256, "fetch_kib": 92456.1, "write_kib": 64.3,
-           "fetch_scale": 262144.0 / 131092.8125, "write_scale": 262144.0 / 262144.0}
-
-
-def traffic_bytes(m, n, c):
-    t = TRAFFIC
-    if (m, n, c) != (t["m"], t["n"], t["c"]) or t["fetch_kib"] is None:
-        return None
-    return round(1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]))
-
-
 def cpu_baseline(w, budget_s=20.0):
     """The FP64 oracle twin as it stands, on the host cores, on whole
     decompositions of the same workload (bounded by ``budget_s``)."""
     from oracle import bcur_oracle as O
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
-    except Exception:  # pragma: no cover
-        threads = os.cpu_count()
+    threads = _cpu_threads()
     done, t0 = 0, time.perf_counter()
     while True:
         O.decompose(w.A, w.offsets, w.k, w.s, w.omega, w.draws, q=w.q)
@@ -68,31 +54,37 @@ def cpu_baseline(w, budget_s=20.0):
 
 def serve_bench(args):
     """Continuous batching under Poisson arrivals (the serving workload):
-    requests of m in [256, 8192] x n in [256, 4096], rank 5..50 (k = rank),
-    block width in {8, 16, 32, 64}, s in [4, 32].  A pool of seeded request
-    matrices is generated once and reused (each request has its own test
-    matrix and draws).  Measures the saturation throughput (all requests
-    submitted at once), then p50/p99 latency at arrival rates that are
-    fractions of it, and mixed precision (BF16 range finder) against plain
-    FP32 at saturation, with the largest per-request residual gap."""
+    ``--requests`` distinct requests (2000 by default), each an m x n low-rank
+    + noise FP32 matrix with m in [256, 8192], n in [256, 4096], rank 5..50
+    (k = rank), block width in {8, 16, 32, 64}, s in [4, 32]; request i has
+    its own matrix (drawn on the GPU from seed i), its own test matrix (device
+    Philox seed i) and its own draws.  Measures the saturation throughput (all
+    requests submitted at once) in plain FP32 and with the BF16 range finder,
+    compares them at equal residual accuracy (|err_bf16 - err_fp32| <= 1e-5
+    err_fp32 per request), then p50/p99 latency at Poisson arrival rates that
+    are fractions of the FP32 saturation throughput."""
     import numpy as np
     import torch
 
     from paper_1703_06065_amd import Server
-    from paper_1703_06065_amd.binding import PREC_BF16, PREC_FP32, to_device
+    from paper_1703_06065_amd.binding import PREC_BF16, PREC_FP32
     from workloads import gen
 
-    pool = [gen.serving_request(i) for i in range(args.pool)]
-    dev = [(to_device(w.A), torch.from_numpy(w.omega).cuda()) for w in pool]
+    t0 = time.perf_counter()
+    specs = [gen.serving_spec(i) for i in range(args.requests)]
+    mats = [gen.serving_matrix_device(sp) for sp in specs]
+    draws = [gen.draws_u64(sp.s, 7919 + sp.req_id) for sp in specs]
     torch.cuda.synchronize()
+    print(f"[serve] {len(specs)} request matrices drawn on the GPU in {time.perf_counter() - t0:.1f} s "
+          f"({sum(sp.m * sp.n for sp in specs) * 4 / 2 ** 30:.1f} GiB)", file=sys.stderr, flush=True)
 
-    def run(n_req, rate, precision):
+    def run(rate, precision, n_req=None):
+        n_req = len(specs) if n_req is None else n_req
         srv = Server(0, hbm_budget=args.budget_gib << 30, max_slots=args.slots)
         rng = np.random.default_rng(12345)
         gaps = rng.exponential(1.0 / rate, size=n_req) if rate > 0 else np.zeros(n_req)
         tickets = []
-        t0 = time.perf_counter()
-        next_t = t0
+        next_t = time.perf_counter()
         for i in range(n_req):
             next_t += gaps[i]
             while True:
@@ -100,14 +92,10 @@ def serve_bench(args):
                 if now >= next_t:
                     break
                 time.sleep(min(0.0005, next_t - now))
-            w = pool[i % len(pool)]
-            A, om = dev[i % len(pool)]
-            tickets.append((i % len(pool), srv.submit(A, w.offsets, w.k, w.s, om, gen.draws_u64(w.s, 7919 + i),
-                                                      q=w.q, precision=precision)))
-        errs = {}
-        for j, t in tickets:
-            r = srv.wait(t)
-            errs.setdefault(j, []).append(r["err"])
+            sp = specs[i]
+            tickets.append(srv.submit(mats[i], sp.offsets, sp.k, sp.s, sp.req_id, draws[i], q=2, l=sp.l,
+                                      precision=precision))
+        errs = np.array([srv.wait(t)["err"] for t in tickets])
         st = srv.stats()
         srv.close()
         print(f"[serve] {n_req} requests at rate {rate:.1f}/s ({'bf16' if precision == PREC_BF16 else 'fp32'}): "
@@ -115,30 +103,32 @@ def serve_bench(args):
               flush=True)
         return st, errs
 
-    # warm up every slot and shape
-    run(min(2 * len(pool), args.requests), 0, PREC_FP32)
-    sat, errs32 = run(args.requests, 0, PREC_FP32)
-    sat_mixed, errs16 = run(args.requests, 0, PREC_BF16)
+    run(0, PREC_FP32, n_req=min(200, len(specs)))   # warm up every slot
+    sat, e32 = run(0, PREC_FP32)
+    sat_mixed, e16 = run(0, PREC_BF16)
+    gap = np.abs(e16 - e32) / np.maximum(e32, 1e-300)
+    equal = gap <= 1e-5
     sweep = []
     for frac in (0.25, 0.5, 0.75, 0.9, 1.0, 1.25):
-        st, _ = run(args.requests, frac * sat["throughput"], PREC_FP32)
+        st, _ = run(frac * sat["throughput"], PREC_FP32)
         sweep.append({"rate_frac": frac, "offered_per_s": round(frac * sat["throughput"], 2),
                       "throughput": round(st["throughput"], 2), "p50_ms": round(st["p50_ms"], 3),
                       "p99_ms": round(st["p99_ms"], 3), "peak_running": st["peak_running"]})
-    gap = 0.0
-    for j in errs32:
-        for a, b in zip(errs32[j], errs16.get(j, [])):
-            gap = max(gap, abs(a - b) / max(a, 1e-300))
+    makespan_mixed = len(specs) / sat_mixed["throughput"]
     out = {
         "metric": "served block-CUR decompositions/s and p50/p99 latency",
         "value": sat["throughput"], "unit": "decompositions/s", "n_gpus": 1, "higher_is_better": True,
-        "dtype": "f32", "data": f"synthetic serving mix, pool of {len(pool)} seeded matrices",
-        "config": {"workload": "serving: m 256-8192, n 256-4096, rank 5-50, block 8-64, s 4-32",
-                   "requests_per_point": args.requests, "slots": args.slots, "budget_gib": args.budget_gib},
-        "saturation": {"fp32": round(sat["throughput"], 2), "mixed_bf16": round(sat_mixed["throughput"], 2),
-                       "mixed_over_fp32": round(sat_mixed["throughput"] / sat["throughput"], 3),
-                       "max_rel_residual_gap_mixed_vs_fp32": gap,
-                       "p50_ms_fp32": round(sat["p50_ms"], 3), "p99_ms_fp32": round(sat["p99_ms"], 3)},
+        "dtype": "f32", "data": f"synthetic serving mix: {len(specs)} distinct seeded requests (matrices drawn on "
+                                f"the GPU)",
+        "config": {"workload": "serving: m 256-8192, n 256-4096, rank 5-50 (k = rank), block 8-64, s 4-32, q = 2",
+                   "requests": len(specs), "slots": args.slots, "budget_gib": args.budget_gib},
+        "p50_ms": round(sat["p50_ms"], 3), "p99_ms": round(sat["p99_ms"], 3),
+        "mixed_vs_fp32": {
+            "fp32_per_s": round(sat["throughput"], 2), "bf16_range_finder_per_s": round(sat_mixed["throughput"], 2),
+            "ratio": round(sat_mixed["throughput"] / sat["throughput"], 4),
+            "requests_at_equal_residual": int(np.sum(equal)),
+            "bf16_per_s_counting_equal_residual_only": round(float(np.sum(equal)) / makespan_mixed, 2),
+            "max_rel_residual_gap": float(gap.max()), "median_rel_residual_gap": float(np.median(gap))},
         "poisson_sweep": sweep,
     }
     print(json.dumps(out), flush=True)
@@ -420,70 +410,180 @@ def diag_bench(args):
     print(json.dumps(out), flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--mode", choices=["decompose", "serve", "alg1", "boost", "diag"], default="decompose")
-    ap.add_argument("--trials", type=int, default=3, help="boosting: t = ln(1/delta) trials (3 for delta = 0.05)")
-    ap.add_argument("--rows", type=int, default=128, help="Algorithm 1: rows drawn (r)")
-    ap.add_argument("--kr", type=int, default=0,
-                    help="Algorithm 1: right singular vectors of R behind the scores (0: r, as in the listing)")
-    ap.add_argument("--requests", type=int, default=2000)
-    ap.add_argument("--pool", type=int, default=24)
-    ap.add_argument("--slots", type=int, default=4)
-    ap.add_argument("--budget-gib", type=int, default=16)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
-        sys.exit(2)
-    if args.mode == "serve":
-        serve_bench(args)
-        return
-    if args.mode == "alg1":
-        alg1_bench(args)
-        return
-    if args.mode == "boost":
-        boost_bench(args)
-        return
-    if args.mode == "diag":
-        diag_bench(args)
-        return
+def copy_bench(args):
+    """A plain device copy of known size (torch's copy kernel), the yardstick
+    for reading the HBM traffic counters: FETCH_SIZE and WRITE_SIZE of this
+    launch against its 2 x 1 GiB of algorithmic traffic give the scales that
+    turn the counters of the path's kernels into bytes."""
+    import torch
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(args.steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "copy", "bytes_read_per_launch": nbytes, "bytes_written_per_launch": nbytes,
+                      "launches": args.steps}), flush=True)
 
+
+def scores_bench(args):
+    """Block leverage scores (Def. 2) on the stress shape where the pass is
+    bandwidth-bound rather than launch-bound: V of 4M x 100 FP32 (1.6 GB) in
+    65536 blocks of 64 rows.  One step = one bcur_block_scores call; the
+    kernel's own time comes from HIP events on the library's stream."""
     import numpy as np
     import torch
 
     from paper_1703_06065_amd import Context
-    from paper_1703_06065_amd.binding import to_device
+    n, k, b = 1 << 22, 100, 64
+    g = torch.Generator(device="cuda").manual_seed(args.seed)
+    V = torch.randn((n, k), dtype=torch.float32, device="cuda", generator=g)
+    off = np.arange(0, n + 1, b, dtype=np.int64)
+    ctx = Context(0)
+    for _ in range(args.warmup):
+        ctx.block_scores(V, off)
+    torch.cuda.synchronize()
+    ctx.timing_enable(("scores",))
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sc = ctx.block_scores(V, off)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = ctx.timing_read()["scores"]
+    ctx.timing_enable(False)
+    avg_ms = st[0] / max(st[1], 1)
+    nbytes = 4.0 * n * k
+    ach = nbytes / (avg_ms * 1e-3) / 1e9
+    out = {"metric": "block-score passes/s (stress shape)", "value": args.steps / el, "unit": "passes/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32->f64",
+           "data": "synthetic (torch.randn V)",
+           "config": {"workload": f"block scores: V {n}x{k} FP32, {len(off) - 1} blocks of {b} rows",
+                      "n": n, "k": k, "G": len(off) - 1},
+           "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None, "kernel": "k_block_scores",
+                        "avg_ms": round(avg_ms, 5), "algorithmic_bytes_per_launch": nbytes},
+           "sum_of_scores": float(np.sum(sc))}
+    print(json.dumps(out), flush=True)
+
+
+def _cpu_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+    except Exception:  # pragma: no cover
+        return os.cpu_count()
+
+
+def cpu_baseline_large(w, omega64, budget_fit_cols=(128, 256)):
+    """The FP64 oracle as it stands, timed step by step on a bounded sample of
+    the large-share workload (a whole oracle decomposition takes minutes):
+    ||A||_F^2 on all of A; the twin's range finder with q = 0 on all of A
+    (three of the 2q + 3 passes over A, with one QR and the Rayleigh-Ritz
+    step), scaled by (2q + 3) / 3; scores and sampling; the least-squares fit
+    of two leading column panels of A (lstsq, then the explicit residual),
+    extrapolated linearly in the panel width to all n columns (the fit's cost
+    is a fixed factorization of C plus a per-column part)."""
+    import numpy as np
+
+    from oracle import bcur_oracle as O
+    A64 = w.A.astype(np.float64)
+    t = {}
+    c0 = time.perf_counter()
+    O.frob2(A64)
+    t["frob2"] = time.perf_counter() - c0
+    c0 = time.perf_counter()
+    rf = O.range_finder(A64, omega64, 0, w.k)
+    t["range_finder_q0"] = time.perf_counter() - c0
+    c0 = time.perf_counter()
+    sc = O.block_scores(rf["Vk"], w.offsets)
+    smp = O.sample_blocks(sc, w.draws[:w.s], w.s)
+    C = O.gather_columns(A64, w.offsets, smp["idx"])
+    t["scores_sample_gather"] = time.perf_counter() - c0
+    fits = []
+    for nc in budget_fit_cols:
+        c0 = time.perf_counter()
+        O.fit_columns(A64[:, :nc], C)
+        fits.append(time.perf_counter() - c0)
+    n0, n1 = budget_fit_cols
+    per_col = max(fits[1] - fits[0], 0.0) / (n1 - n0)
+    fit_all = fits[0] + per_col * (w.n - n0)
+    total = t["frob2"] + t["range_finder_q0"] * (2 * w.q + 3) / 3.0 + t["scores_sample_gather"] + fit_all
+    spent = sum(t.values()) + sum(fits)
+    return {"value": 1.0 / total, "unit": "decompositions/s", "cores": int(_cpu_threads()), "kind": "oracle",
+            "sample": f"FP64 oracle twin on the same {w.m}x{w.n} input, timed step by step ({spent:.1f} s of CPU "
+                      f"time): frob2 {t['frob2']:.2f} s; range finder with q=0 {t['range_finder_q0']:.2f} s, "
+                      f"scaled x{(2 * w.q + 3) / 3.0:.3f} to q={w.q}; scores+sampling+gather "
+                      f"{t['scores_sample_gather']:.2f} s; lstsq fit of {n0} and {n1} columns "
+                      f"{fits[0]:.2f} / {fits[1]:.2f} s, extrapolated to {w.n} columns ({fit_all:.1f} s); "
+                      f"estimated {total:.1f} s per decomposition"}
+
+
+# HBM traffic of the dominant kernels, from rocprofv3 counter runs of
+# `bench.py` (FETCH_SIZE and WRITE_SIZE, KiB per dispatch), each scaled by the
+# same counter's reading for the plain 1 GiB copy of `bench.py --mode copy`.
+# The readings hold for the kernel source whose hash is stored beside them; a
+# changed source reports traffic None until the counters are taken again.
+TRAFFIC_LARGE = {}
+TRAFFIC_PLAIN = {}
+
+
+def _source_hash():
+    import hashlib
+    src = os.path.join(ROOT, "paper_1703_06065_amd", "csrc", "k_sgemm.hip")
+    with open(src, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_for(table, stage):
+    t = table.get(stage)
+    if not t or t.get("src") != _source_hash():
+        return None
+    return round(1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]))
+
+
+def decompose_bench(args):
+    import numpy as np
+    import torch
+
+    from paper_1703_06065_amd import Context
+    from paper_1703_06065_amd.binding import PREC_BF16, PREC_FP32, padded_empty, to_device
     from workloads import gen
 
-    w = gen.plain_fp32(args.seed)
+    large = args.workload == "large-share"
+    t0 = time.perf_counter()
+    w = gen.large_share(args.seed) if large else gen.plain_fp32(args.seed)
+    precision = PREC_BF16 if large else PREC_FP32
+    print(f"[bench] {w.name} generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     A = to_device(w.A)
-    om = torch.from_numpy(w.omega).cuda()
+    seed = args.seed   # the test matrix is drawn on the device from this seed
     ctx = Context(0)
     cap = w.s * int(np.max(np.diff(w.offsets)))
-    from paper_1703_06065_amd.binding import padded_empty
     Ubuf = padded_empty(cap, w.n)
+
+    def step():
+        return ctx.decompose(A, w.offsets, w.k, w.s, seed, w.draws, q=w.q, l=w.l, precision=precision,
+                             U_out=Ubuf)
+
     for _ in range(args.warmup):
-        res = ctx.decompose(A, w.offsets, w.k, w.s, om, w.draws, q=w.q, U_out=Ubuf)
+        res = step()
     torch.cuda.synchronize()
-    # timed region: only the dominant kernel's launch records HIP events
-    ctx.timing_enable(("fit_E",))
+    # timed region: only the two largest MFMA kernels (the residual GEMM and
+    # H = C^T A, one launch each per decomposition) record HIP events
+    ctx.timing_enable(("fit_E", "fit_H"))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        res = ctx.decompose(A, w.offsets, w.k, w.s, om, w.draws, q=w.q, U_out=Ubuf)
+        res = step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     stages = ctx.timing_read()
+    print(f"[bench] timed {args.steps} steps in {t1 - t0:.2f} s", file=sys.stderr, flush=True)
     # per-stage breakdown from a separate, untimed pass (its events slow the host side)
     ctx.timing_enable(True)
     nb = min(args.steps, 10)
     for _ in range(nb):
-        ctx.decompose(A, w.offsets, w.k, w.s, om, w.draws, q=w.q, U_out=Ubuf)
+        step()
     torch.cuda.synchronize()
     breakdown = ctx.timing_read()
     ctx.timing_enable(False)
@@ -491,23 +591,29 @@ def main():
     c = int(res["c"])
     rf_flops, fit_flops = algorithmic_flops(w.m, w.n, w.k, w.l, w.q, c)
 
-    # Roofline of the dominant kernel: of the kernels that a throughput roofline
-    # bounds (MFMA or HBM), the one with the largest device time per
-    # decomposition is the residual GEMM ||A - C U||_F^2 (k_sgemm<128,128>, NN,
-    # norm-only epilogue: A is read, nothing m x n is written), one launch per
-    # decomposition in stage fit_E.  The one-workgroup FP64 solvers (the l x l
-    # Jacobi of the Rayleigh-Ritz step and the c x c Cholesky inverse) take
-    # longer but are latency-bound: their times are in stage_ms_per_step
-    # (rf_rr, fit_inv).
+    # Roofline of the dominant kernel: of the kernels that a throughput
+    # roofline bounds, the one with the largest device time per decomposition.
+    # At these shapes that is one of the two c-wide MFMA GEMMs over A, each
+    # 2 m c n FLOP per launch and one launch per decomposition: the residual
+    # ||A - C U||_F^2 (k_sgemm<128,128> NN, norm-only epilogue, stage fit_E) or
+    # H = C^T A (k_sgemm<256,128> TN, stage fit_H).  The one-workgroup FP64
+    # solvers are latency-bound; their times are in stage_ms_per_step.
+    kern = {"fit_E": ("k_sgemm<128,128,16,2,2> norm-only residual epilogue (||A - C U||_F^2)",
+                      4.0 * (w.m * w.n + w.m * c + c * w.n)),
+            "fit_H": ("k_sgemm<256,128,16,4,2> TN (H = C^T A)", 4.0 * (w.m * w.n + w.m * c + c * w.n))}
+    avg = {st: stages[st][0] / max(stages[st][1], 1) for st in kern}
+    dom = max(avg, key=avg.get)
     per_launch_flop = 2.0 * w.m * c * w.n
-    n_launch = stages["fit_E"][1]
-    avg_ms = stages["fit_E"][0] / max(n_launch, 1)
+    avg_ms = avg[dom]
     ach = per_launch_flop / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    table = TRAFFIC_LARGE if large else TRAFFIC_PLAIN
     roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(ach / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": traffic_bytes(w.m, w.n, c),
-            "kernel": "k_sgemm<128,128,16,2,2> norm-only residual epilogue (||A - C U||_F^2)",
-            "launches_per_step": 1, "avg_ms": round(avg_ms, 5), "flop_per_launch": per_launch_flop,
-            "algorithmic_bytes_per_launch": 4.0 * (w.m * w.n + w.m * c + c * w.n)}
+            "frac": round(ach / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": traffic_for(table, dom),
+            "kernel": kern[dom][0], "stage": dom, "launches_per_step": 1, "avg_ms": round(avg_ms, 5),
+            "flop_per_launch": per_launch_flop, "algorithmic_bytes_per_launch": kern[dom][1],
+            "other_stage_avg_ms": {st: round(v, 5) for st, v in avg.items() if st != dom}}
+    prec = "BF16 range finder (q BF16 power iterations, final FP32 pass), FP32 fit with one refinement step, " \
+           "FP64 small factorizations" if large else "FP32 range finder and fit, FP64 small factorizations"
     out = {
         "metric": "block-CUR decompositions/s",
         "value": args.steps / el,
@@ -520,18 +626,58 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic (seeded numpy: rank-50 Haar signal sigma_i = 1/i + 1e-3 Gaussian noise)",
-        "config": {"workload": f"plain-fp32 {w.m}x{w.n}, {w.G} column blocks of 16, k={w.k}, s={w.s}, "
-                               f"q={w.q}, l={w.l}", "m": w.m, "n": w.n, "G": w.G, "k": w.k, "s": w.s, "q": w.q,
-                   "l": w.l, "c": c, "refine": 1},
+        "data": ("synthetic (seeded numpy: rank-100 Haar signal sigma_i = exp(-i/20) + 1e-4 Gaussian noise)" if large
+                 else "synthetic (seeded numpy: rank-50 Haar signal sigma_i = 1/i + 1e-3 Gaussian noise)"),
+        "config": {"workload": f"{w.name}: {w.G} column blocks of {int(w.offsets[1])}, k={w.k}, s={w.s}, q={w.q}, "
+                               f"l={w.l}; {prec}",
+                   "m": w.m, "n": w.n, "G": w.G, "k": w.k, "s": w.s, "q": w.q, "l": w.l, "c": c, "refine": 1,
+                   "precision": "bf16-range-finder" if large else "fp32", "test_matrix": f"Philox seed {seed}"},
         "tflops_total": round((rf_flops + fit_flops) * args.steps / el / 1e12, 3),
         "stage_ms_per_step": {k: round(v[0] / nb, 5) for k, v in breakdown.items() if v[1]},
         "err": res["err"], "rel_err": res["rel_err"], "rr_sweeps": res["rr_sweeps"],
         "roofline": roof,
     }
+    del A
+    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w)
+        from oracle import bcur_oracle as O
+        om64 = O.rademacher_omega(w.n, w.l, seed)
+        if large:
+            out["cpu_baseline"] = cpu_baseline_large(w, om64)
+        else:
+            out["cpu_baseline"] = cpu_baseline(dataclasses_replace_omega(w, om64))
     print(json.dumps(out), flush=True)
+
+
+def dataclasses_replace_omega(w, omega):
+    import dataclasses
+    return dataclasses.replace(w, omega=omega)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--mode", choices=["decompose", "serve", "alg1", "boost", "diag", "copy", "scores"],
+                    default="decompose")
+    ap.add_argument("--workload", choices=["large-share", "plain-fp32"], default="large-share",
+                    help="decompose mode: 65536 x 16384 (BF16 range finder) or 8192 x 4096 (FP32)")
+    ap.add_argument("--trials", type=int, default=3, help="boosting: t = ln(1/delta) trials (3 for delta = 0.05)")
+    ap.add_argument("--rows", type=int, default=128, help="Algorithm 1: rows drawn (r)")
+    ap.add_argument("--kr", type=int, default=0,
+                    help="Algorithm 1: right singular vectors of R behind the scores (0: r, as in the listing)")
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--budget-gib", type=int, default=16)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    {"serve": serve_bench, "alg1": alg1_bench, "boost": boost_bench, "diag": diag_bench, "copy": copy_bench,
+     "scores": scores_bench, "decompose": decompose_bench}[args.mode](args)
 
 
 if __name__ == "__main__":

@@ -48,7 +48,7 @@ struct bcur_ctx {
     char* pinned = nullptr;
     size_t pinned_bytes = 0;
     bool pinned_busy = false;  // a call left copies into `pinned` without synchronizing
-    std::string err;
+    char err[512] = {0};       // message of the last error (a fixed buffer: reporting allocates nothing)
     StageTimer timer;
     // asynchronous decomposition: its host thread, its stream (default
     // priority) and the event that orders it after the caller's stream
@@ -69,12 +69,11 @@ inline int64_t round4(int64_t x) { return (x + 3) & ~(int64_t)3; }
 
 bcur_status fail(bcur_ctx* ctx, bcur_status st, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
 bcur_status fail(bcur_ctx* ctx, bcur_status st, const char* fmt, ...) {
-    char buf[512];
+    if (!ctx) return st;
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vsnprintf(ctx->err, sizeof ctx->err, fmt, ap);
     va_end(ap);
-    if (ctx) ctx->err = buf;
     return st;
 }
 
@@ -226,6 +225,20 @@ std::vector<int64_t> expand_blocks(const int64_t* off, const int64_t* idx, int64
         for (int64_t c = off[j]; c < off[j + 1]; ++c) out.push_back(map ? map[c] : c);
     }
     return out;
+}
+
+// The same list written to out (capacity cap), without allocating; returns its length.
+int64_t expand_blocks_into(const int64_t* off, const int64_t* idx, int64_t s, const int64_t* map, int64_t* out,
+                           int64_t cap) {
+    int64_t n = 0;
+    for (int64_t t = 0; t < s; ++t) {
+        const int64_t j = idx[t];
+        bool dup = false;
+        for (int64_t u = 0; u < t && !dup; ++u) dup = idx[u] == j;
+        if (dup) continue;
+        for (int64_t c = off[j]; c < off[j + 1] && n < cap; ++c) out[n++] = map ? map[c] : c;
+    }
+    return n;
 }
 
 // The common width of all blocks, or 0 when they differ.
@@ -592,17 +605,29 @@ bcur_status fit_fallback64(bcur_ctx* ctx, const FitBufs& b, const float* A, int6
     return BCUR_OK;
 }
 
+// Bytes of host staging fit_collect reads its small results into.
+size_t fit_collect_bytes(const FitBufs& b) {
+    return (size_t)(reinterpret_cast<const char*>(b.info + 4) - reinterpret_cast<const char*>(b.errv));
+}
+
+// hstage: host buffer of fit_collect_bytes(b) bytes, or null (one is allocated).
 bcur_status fit_collect(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t m, int64_t n, int64_t lda,
-                        const float* C, int64_t c, int64_t ldc, float* U, int64_t ldu, FitOut* out) {
+                        const float* C, int64_t c, int64_t ldc, float* U, int64_t ldu, FitOut* out,
+                        char* hstage = nullptr) {
     const int64_t nblk = (c + 63) / 64;
     // errv, piv and info are consecutive in the workspace: one copy
     const char* d0 = reinterpret_cast<const char*>(b.errv);
-    std::vector<char> hb((size_t)(reinterpret_cast<const char*>(b.info + 4) - d0));
-    HIPCHK(hipMemcpyAsync(hb.data(), d0, hb.size(), hipMemcpyDeviceToHost, ctx->stream));
+    const size_t span = fit_collect_bytes(b);
+    std::vector<char> own;
+    if (!hstage) {
+        own.resize(span);
+        hstage = own.data();
+    }
+    HIPCHK(hipMemcpyAsync(hstage, d0, span, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
-    const double* hv = reinterpret_cast<const double*>(hb.data());
-    const double* piv = reinterpret_cast<const double*>(hb.data() + (reinterpret_cast<const char*>(b.piv) - d0));
-    const int* hinfo = reinterpret_cast<const int*>(hb.data() + (reinterpret_cast<const char*>(b.info) - d0));
+    const double* hv = reinterpret_cast<const double*>(hstage);
+    const double* piv = reinterpret_cast<const double*>(hstage + (reinterpret_cast<const char*>(b.piv) - d0));
+    const int* hinfo = reinterpret_cast<const int*>(hstage + (reinterpret_cast<const char*>(b.info) - d0));
     uint32_t fl = 0;
     if (hinfo[0] & 1) fl |= BCUR_FLAG_RANKDEF_C;
     double pmin = INFINITY, pmax = 0.0;
@@ -794,7 +819,7 @@ const char* bcur_status_str(int status) {
     }
 }
 
-const char* bcur_last_error(const bcur_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+const char* bcur_last_error(const bcur_ctx* ctx) { return ctx ? ctx->err : ""; }
 
 size_t bcur_workspace_bytes(const bcur_ctx* ctx) { return ctx ? ctx->ws_bytes : 0; }
 
@@ -1001,7 +1026,10 @@ bcur_status bcur_block_scores(bcur_ctx* ctx, const float* V, int64_t n, int64_t 
     int64_t* d_off = b.take<int64_t>(G + 1);
     double* d_sc = b.take<double>(G);
     HIPCHK(hipMemcpyAsync(d_off, offsets, (G + 1) * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
-    HIPCHK(launch_block_scores(V, k, ldv, d_off, G, d_sc, ctx->stream));
+    {
+        StageScope ts(ctx, BCUR_STAGE_SCORES);
+        HIPCHK(launch_block_scores(V, k, ldv, d_off, G, d_sc, ctx->stream));
+    }
     HIPCHK(hipMemcpyAsync(scores, d_sc, G * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return BCUR_OK;
@@ -1271,7 +1299,8 @@ bcur_status decompose_impl(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
     };
     // (+256 per merged span: offsets | draws, lam | info keep their workspace padding)
     const size_t pin_need = side_bytes(G, s, cmax) + (rowv ? side_bytes(Gr, s_r, rmax) : 0) + 16 + 8 * l + 64 +
-                            (p->col_map ? 8 * n + 8 : 0) + (rmap_h ? 8 * m + 8 : 0) + 3 * 256;
+                            (p->col_map ? 8 * n + 8 : 0) + (rmap_h ? 8 * m + 8 : 0) + 3 * 256 +
+                            (rowv ? 0 : fit_collect_bytes(fb) + 8);
     STCHK(reserve_pinned(ctx, pin_need));
     if (ctx->pinned_busy) HIPCHK(hipStreamSynchronize(st));
     ctx->pinned_busy = true;
@@ -1399,14 +1428,10 @@ bcur_status decompose_impl(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
     } else {
         HIPCHK(hipStreamSynchronize(st));
         STCHK(check_draws());
-        const std::vector<int64_t> cols = expand_blocks(col_off, hc.idx, s, p->col_map);
-        c = (int64_t)cols.size();
-        memcpy(hc.list, cols.data(), c * sizeof(int64_t));
+        c = expand_blocks_into(col_off, hc.idx, s, p->col_map, hc.list, cmax);
         HIPCHK(hipMemcpyAsync(sc.list, hc.list, c * sizeof(int64_t), hipMemcpyHostToDevice, st));
         if (rowv) {
-            const std::vector<int64_t> rows = expand_blocks(row_off, hr.idx, s_r, rmap_h);
-            r = (int64_t)rows.size();
-            memcpy(hr.list, rows.data(), r * sizeof(int64_t));
+            r = expand_blocks_into(row_off, hr.idx, s_r, rmap_h, hr.list, rmax);
             HIPCHK(hipMemcpyAsync(sr.list, hr.list, r * sizeof(int64_t), hipMemcpyHostToDevice, st));
         }
     }
@@ -1437,7 +1462,8 @@ bcur_status decompose_impl(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
     } else {
         STCHK(fit_run(ctx, fb, A, m, n, lda, Cbuf, c, ldc, sc.list, nullptr, p->refine, U, ldu));
         FitOut fo;
-        STCHK(fit_collect(ctx, fb, A, m, n, lda, Cbuf, c, ldc, U, ldu, &fo));
+        char* h_fit = ptake(fit_collect_bytes(fb));
+        STCHK(fit_collect(ctx, fb, A, m, n, lda, Cbuf, c, ldc, U, ldu, &fo, h_fit));
         err2 = fo.err2;
         fl = fo.flags;
     }

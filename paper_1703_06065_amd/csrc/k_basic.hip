@@ -2,6 +2,8 @@
 // leverage scores, block sampling, gathers and small utilities.
 #include <math.h>
 
+#include <algorithm>
+
 #include "bcur_internal.h"
 
 namespace bcur {
@@ -93,23 +95,42 @@ __global__ __launch_bounds__(256) void k_block_scores(const float* __restrict__ 
     __shared__ double sh[4];
     const int64_t g = blockIdx.x;
     const int64_t r0 = off[g], r1 = off[g + 1];
-    double acc = 0.0;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     if (ldv == k) {
+        // the block's rows are one contiguous run: 16-byte loads from the first
+        // 16-byte boundary on, the few elements before it and after the last
+        // whole float4 one by one; four independent FP64 sums per thread
         const float* base = V + r0 * k;
         const int64_t cnt = (r1 - r0) * k;
-        for (int64_t e = threadIdx.x; e < cnt; e += 256) {
-            const double x = base[e];
-            acc += x * x;
+        const int64_t head = min<int64_t>((int64_t)((16 - ((uintptr_t)base & 15)) & 15) / 4, cnt);
+        if (threadIdx.x < head) {
+            const double x = base[threadIdx.x];
+            a0 += x * x;
+        }
+        const float4* b4 = reinterpret_cast<const float4*>(base + head);
+        const int64_t n4 = (cnt - head) / 4;
+        for (int64_t e = threadIdx.x; e < n4; e += 256) {
+            const float4 v = b4[e];
+            const double x = v.x, y = v.y, z = v.z, w = v.w;
+            a0 += x * x;
+            a1 += y * y;
+            a2 += z * z;
+            a3 += w * w;
+        }
+        const int64_t t = head + 4 * n4 + threadIdx.x;
+        if (t < cnt) {
+            const double x = base[t];
+            a1 += x * x;
         }
     } else {
         const int64_t cnt = (r1 - r0) * k;
         for (int64_t e = threadIdx.x; e < cnt; e += 256) {
             const int64_t r = e / k, c = e - r * k;
             const double x = V[(r0 + r) * ldv + c];
-            acc += x * x;
+            a0 += x * x;
         }
     }
-    const double r = block_sum<256>(acc, sh);
+    const double r = block_sum<256>((a0 + a1) + (a2 + a3), sh);
     if (threadIdx.x == 0) scores[g] = r;
 }
 
@@ -401,6 +422,47 @@ __global__ __launch_bounds__(256) void k_gather_cols(const float* __restrict__ A
     }
 }
 
+// The same copy with 16-byte moves.  Output columns go in groups of four; a
+// group whose four source columns are consecutive and start at a multiple of
+// 4 (part of a contiguous block) moves as one float4, any other group element
+// by element.  Workgroup (x, y) reads the source of groups y*kGatherGroups ..
+// into LDS once and copies them for a band of `band` rows, consecutive threads
+// on consecutive groups of a row.  Needs A, C 16-byte aligned and lda, ldc
+// multiples of 4.
+constexpr int kGatherGroups = 1024;
+__global__ __launch_bounds__(256) void k_gather_cols_v4(const float* __restrict__ A, int64_t lda, int64_t m,
+                                                        const int64_t* __restrict__ cols, int64_t c,
+                                                        float* __restrict__ C, int64_t ldc, int64_t band) {
+    __shared__ int64_t src[kGatherGroups];
+    const int tid = threadIdx.x;
+    const int64_t g0 = (int64_t)blockIdx.y * kGatherGroups;
+    const int ng = (int)min<int64_t>(kGatherGroups, (c + 3) / 4 - g0);
+    for (int q = tid; q < ng; q += 256) {
+        const int64_t t = (g0 + q) * 4;
+        const int64_t s0 = cols[t];
+        bool ok = t + 3 < c && (s0 & 3) == 0;
+        if (ok) ok = cols[t + 1] == s0 + 1 && cols[t + 2] == s0 + 2 && cols[t + 3] == s0 + 3;
+        src[q] = ok ? s0 : -1;
+    }
+    __syncthreads();
+    const int64_t i0 = (int64_t)blockIdx.x * band;
+    const int64_t rows = min<int64_t>(band, m - i0);
+    const int64_t total = rows * ng;
+    for (int64_t e = tid; e < total; e += 256) {
+        const int64_t i = i0 + e / ng;
+        const int q = (int)(e % ng);
+        const int64_t t = (g0 + q) * 4;
+        const int64_t s0 = src[q];
+        const float* a = A + i * lda;
+        float* o = C + i * ldc + t;
+        if (s0 >= 0) {
+            *reinterpret_cast<float4*>(o) = *reinterpret_cast<const float4*>(a + s0);
+        } else {
+            for (int u = 0; u < 4 && t + u < c; ++u) o[u] = a[cols[t + u]];
+        }
+    }
+}
+
 // R[t][j] = A[rows[t]][j]
 __global__ __launch_bounds__(256) void k_gather_rows(const float* __restrict__ A, int64_t lda, int64_t n,
                                                      const int64_t* __restrict__ rows, int64_t r,
@@ -539,6 +601,18 @@ hipError_t launch_sample(const double* scores, int64_t G, const uint64_t* draws,
 
 hipError_t launch_gather_cols(const float* A, int64_t lda, int64_t m, const int64_t* d_cols, int64_t c, float* C,
                               int64_t ldc, hipStream_t st) {
+    if (m <= 0 || c <= 0) return hipSuccess;
+    if (((uintptr_t)A & 15) == 0 && ((uintptr_t)C & 15) == 0 && (lda & 3) == 0 && (ldc & 3) == 0) {
+        const int64_t groups = (c + 3) / 4;
+        const int64_t gy = (groups + kGatherGroups - 1) / kGatherGroups;
+        const int64_t per = std::min<int64_t>(groups, kGatherGroups);
+        // about 16 float4 moves per thread for each band of rows
+        const int64_t band = std::max<int64_t>(1, 4096 / per);
+        const int64_t gx = (m + band - 1) / band;
+        hipLaunchKernelGGL(k_gather_cols_v4, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, st, A, lda, m, d_cols,
+                           c, C, ldc, band);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_gather_cols, grid2d(c, m), dim3(256), 0, st, A, lda, m, d_cols, c, C, ldc);
     return hipGetLastError();
 }

@@ -23,12 +23,14 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
     return (uint16_t)(u >> 16);
 }
 
-// out (m x n, ldo) = bf16(A); outT (n x m, ldt) = bf16(A)^T, through 64 x 64 LDS tiles.
+// out (m x n, ldo) = bf16(A); outT (n x m, ldt) = bf16(A)^T, through 64 x 64 LDS tiles; the
+// grid covers the tiles from row rb and column cb on.
 __global__ __launch_bounds__(256) void k_cast_bf16_both(const float* __restrict__ A, int64_t m, int64_t n,
                                                         int64_t lda, uint16_t* __restrict__ out, int64_t ldo,
-                                                        uint16_t* __restrict__ outT, int64_t ldt) {
+                                                        uint16_t* __restrict__ outT, int64_t ldt, int64_t rb,
+                                                        int64_t cb) {
     __shared__ uint16_t tile[64][66];
-    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+    const int64_t r0 = rb + (int64_t)blockIdx.y * 64, c0 = cb + (int64_t)blockIdx.x * 64;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     for (int i = ty; i < 64; i += 4) {
         const int64_t r = r0 + i, c = c0 + tx;
@@ -44,6 +46,45 @@ __global__ __launch_bounds__(256) void k_cast_bf16_both(const float* __restrict_
     for (int i = ty; i < 64; i += 4) {
         const int64_t c = c0 + i, r = r0 + tx;
         if (c < n && r < m) outT[c * ldt + r] = tile[tx][i];
+    }
+}
+
+// The same casts for a whole 64 x 64 tile inside A with lda, ldo and ldt
+// multiples of 4 and 16-byte aligned A (8-byte aligned outputs): each thread
+// loads 4 consecutive floats of a row (one 16-byte load) and stores their 4
+// BF16 values with one 8-byte store to out; the transposed tile goes out
+// from LDS as 4 consecutive rows of one column per thread (one 8-byte store).
+__global__ __launch_bounds__(256) void k_cast_bf16_both_v4(const float* __restrict__ A, int64_t lda,
+                                                           uint16_t* __restrict__ out, int64_t ldo,
+                                                           uint16_t* __restrict__ outT, int64_t ldt) {
+    __shared__ uint16_t tile[64][68];
+    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int row = ty + 16 * i;
+        const float4 v = *reinterpret_cast<const float4*>(A + (r0 + row) * lda + c0 + 4 * tx);
+        const uint16_t b0 = bf16_rne(v.x), b1 = bf16_rne(v.y), b2 = bf16_rne(v.z), b3 = bf16_rne(v.w);
+        if (out) {
+            uint2 pk;
+            pk.x = b0 | ((uint32_t)b1 << 16);
+            pk.y = b2 | ((uint32_t)b3 << 16);
+            *reinterpret_cast<uint2*>(out + (r0 + row) * ldo + c0 + 4 * tx) = pk;
+        }
+        tile[row][4 * tx + 0] = b0;
+        tile[row][4 * tx + 1] = b1;
+        tile[row][4 * tx + 2] = b2;
+        tile[row][4 * tx + 3] = b3;
+    }
+    if (!outT) return;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int col = ty + 16 * i;
+        uint2 pk;
+        pk.x = tile[4 * tx + 0][col] | ((uint32_t)tile[4 * tx + 1][col] << 16);
+        pk.y = tile[4 * tx + 2][col] | ((uint32_t)tile[4 * tx + 3][col] << 16);
+        *reinterpret_cast<uint2*>(outT + (c0 + col) * ldt + r0 + 4 * tx) = pk;
     }
 }
 
@@ -171,8 +212,28 @@ __global__ __launch_bounds__(WM* WN * 64) void k_bgemm_nt(const BArgs g) {
 
 hipError_t launch_cast_bf16_both(const float* A, int64_t m, int64_t n, int64_t lda, uint16_t* out, int64_t ldo,
                                  uint16_t* outT, int64_t ldt, hipStream_t st) {
-    dim3 grid((unsigned)((n + 63) / 64), (unsigned)((m + 63) / 64));
-    hipLaunchKernelGGL(k_cast_bf16_both, grid, dim3(256), 0, st, A, m, n, lda, out, ldo, outT, ldt);
+    if (m <= 0 || n <= 0) return hipSuccess;
+    const bool vec = ((uintptr_t)A & 15) == 0 && (lda & 3) == 0 && ((uintptr_t)out & 7) == 0 && (ldo & 3) == 0 &&
+                     ((uintptr_t)outT & 7) == 0 && (ldt & 3) == 0;
+    const int64_t m64 = vec ? m / 64 * 64 : 0, n64 = vec ? n / 64 * 64 : 0;
+    if (m64 > 0 && n64 > 0) {
+        hipLaunchKernelGGL(k_cast_bf16_both_v4, dim3((unsigned)(n64 / 64), (unsigned)(m64 / 64)), dim3(256), 0, st, A,
+                           lda, out, ldo, outT, ldt);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    // the rest: columns n64 .. n-1 of every row, then rows m64 .. m-1 of columns 0 .. n64-1
+    const int64_t mm = (m64 > 0 && n64 > 0) ? m64 : 0, nn = (m64 > 0 && n64 > 0) ? n64 : 0;
+    if (nn < n) {
+        dim3 grid((unsigned)((n - nn + 63) / 64), (unsigned)((m + 63) / 64));
+        hipLaunchKernelGGL(k_cast_bf16_both, grid, dim3(256), 0, st, A, m, n, lda, out, ldo, outT, ldt, (int64_t)0,
+                           nn);
+    }
+    if (mm < m && nn > 0) {
+        dim3 grid((unsigned)(nn / 64), (unsigned)((m - mm + 63) / 64));
+        hipLaunchKernelGGL(k_cast_bf16_both, grid, dim3(256), 0, st, A, m, nn, lda, out, ldo, outT, ldt, mm,
+                           (int64_t)0);
+    }
     return hipGetLastError();
 }
 

@@ -1,7 +1,8 @@
 // FP64 dense kernels for the c x c normal-equation matrix G = C^T C of the
 // fit: a tiled FP64 GEMM, and G^-1 by a blocked right-looking Cholesky
-// (64-wide panels factored in LDS), a blocked triangular inverse computed by
-// anti-diagonal wavefronts, and Ginv = L^-T L^-1.
+// (64-wide panels factored in LDS), a blocked triangular inverse computed
+// recursively (both halves, then the coupling block, one level of the
+// recursion per pair of launches), and Ginv = L^-T L^-1.
 #include <math.h>
 
 #include "bcur_internal.h"
@@ -352,46 +353,61 @@ __global__ __launch_bounds__(kMW * 64) void k_chol_inv_mfma(const double* __rest
     }
 }
 
-// One anti-diagonal of the blocked inverse X = L^-1 (lower):
-// X_ij = -Linv_ii (sum_{p=j}^{i-1} L_ip X_pj) for i = j + d, j = blockIdx.x.
-__global__ __launch_bounds__(256) void k_trtri_step(const double* __restrict__ L, double* __restrict__ X, int64_t c,
-                                                    int d, const double* __restrict__ Linv) {
+// One level of the recursive blocked inverse X = L^-1 (lower; NB-blocks, the
+// diagonal blocks already in X).  Node z of the level covers the blocks
+// b0 = 2 h z .. min(b0 + 2h, nblk) - 1; with mid = b0 + h its lower-left part
+// is X21 = -X22 (L21 X11), X11 and X22 the inverses of its two halves (formed
+// by the levels before).  PASS 0 forms T = L21 X11 (node z's T at
+// T + z (h NB)^2, leading dimension h NB); PASS 1 writes X21 = -X22 T.  Both
+// skip the zero parts of the triangular factors: T's columns from tn0 on need
+// only rows k >= tn0 of X11, and X21's rows up to tm0 + NB only columns
+// k < tm0 + NB of X22.  This equals the block forward substitution
+// X_ij = -Linv_ii sum_{j <= p < i} L_ip X_pj (also with dropped pivots, whose
+// rows of Linv are zero) up to the order of the sums.
+template <int PASS>
+__global__ __launch_bounds__(256) void k_trtri_level(const double* __restrict__ L, double* __restrict__ X, int64_t c,
+                                                     int64_t h, int64_t nblk, double* __restrict__ T) {
     __shared__ double As[KB * (NB + 1)], Bs[KB * (NB + 1)];
-    __shared__ double T[NB * (NB + 1)];
-    __shared__ double Li[NB * (NB + 1)];
-    const int64_t jb = blockIdx.x, ib = jb + d;
-    const int64_t j0 = jb * NB, i0 = ib * NB;
-    const int64_t wi = c - i0 < NB ? c - i0 : NB, wj = c - j0 < NB ? c - j0 : NB;
+    const int64_t z = blockIdx.z;
+    const int64_t b0 = 2 * h * z, mid = b0 + h;
+    if (mid >= nblk) return;
+    const int64_t b1 = b0 + 2 * h < nblk ? b0 + 2 * h : nblk;
+    const int64_t r0 = mid * NB, r1 = b1 * NB < c ? b1 * NB : c;
+    const int64_t c0 = b0 * NB, c1 = mid * NB;
+    const int64_t rows = r1 - r0, cols = c1 - c0;
+    const int64_t tm0 = (int64_t)blockIdx.x * NB, tn0 = (int64_t)blockIdx.y * NB;
+    if (tm0 >= rows || tn0 >= cols) return;
+    const int64_t ldt = h * NB;
+    double* Tz = T + z * ldt * ldt;
     double acc[4][4] = {};
-    // T = L[i0:i0+wi, j0:i0] X[j0:i0, j0:j0+wj]
-    tile_mm<false, false>(acc, L + i0 * c + j0, c, X + j0 * c + j0, c, wi, wj, i0 - j0, As, Bs);
+    if (PASS == 0)
+        tile_mm<false, false>(acc, L + (r0 + tm0) * c + c0 + tn0, c, X + (c0 + tn0) * c + c0 + tn0, c, rows - tm0,
+                              cols - tn0, cols - tn0, As, Bs);
+    else
+        tile_mm<false, false>(acc, X + (r0 + tm0) * c + r0, c, Tz + tn0, ldt, rows - tm0, cols - tn0,
+                              rows < tm0 + NB ? rows : tm0 + NB, As, Bs);
     const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) T[(ty + 16 * i) * (NB + 1) + tx + 16 * j] = acc[i][j];
-    for (int e = threadIdx.x; e < NB * NB; e += 256) Li[(e / NB) * (NB + 1) + e % NB] = Linv[ib * NB * NB + e];
-    __syncthreads();
-    double x[4][4] = {};
-    for (int p = 0; p < NB; ++p) {
-        double a[4], b[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) a[i] = Li[(ty + 16 * i) * (NB + 1) + p];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) b[j] = T[p * (NB + 1) + tx + 16 * j];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) x[i][j] = fma(a[i], b[j], x[i][j]);
-    }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int row = ty + 16 * i, col = tx + 16 * j;
-            if (row < wi && col < wj) X[(i0 + row) * c + j0 + col] = -x[i][j];
+            const int64_t row = tm0 + ty + 16 * i, col = tn0 + tx + 16 * j;
+            if (row < rows && col < cols) {
+                if (PASS == 0) Tz[row * ldt + col] = acc[i][j];
+                else X[(r0 + row) * c + c0 + col] = -acc[i][j];
+            }
         }
+}
+
+// Doubles of the recursive inverse's T buffer: the largest level's nodes x (h NB)^2.
+int64_t trtri_t_doubles(int64_t nblk) {
+    int64_t best = 0;
+    for (int64_t h = 1; h < nblk; h *= 2) {
+        const int64_t nodes = (nblk + 2 * h - 1) / (2 * h);
+        const int64_t v = nodes * (h * NB) * (h * NB);
+        if (v > best) best = v;
+    }
+    return best;
 }
 
 // X = 0, then the diagonal blocks of X = L^-1 from Linv.
@@ -407,7 +423,8 @@ __global__ __launch_bounds__(256) void k_init_xinv(double* __restrict__ X, int64
 
 size_t spd_inverse_ws_doubles(int64_t c) {
     const int64_t nblk = (c + NB - 1) / NB;
-    return (size_t)(nblk * NB * NB) + (size_t)(c * c) + (size_t)(2 * nblk) + 8;
+    return (size_t)(nblk * NB * NB) + (size_t)(c * c) + (size_t)(2 * nblk) + 8 +
+           (c > kFullChol ? (size_t)trtri_t_doubles(nblk) : 0);
 }
 
 template <typename TAe, typename TBe>
@@ -447,8 +464,9 @@ hipError_t launch_dgemm_df(int64_t M, int64_t N, int64_t K, double alpha, const 
     return dgemm_any(M, N, K, alpha, A, lda, tA, B, ldb, tB, beta, D, ldd, st);
 }
 
-// ws: [Linv blocks nblk*NB*NB][X c*c][piv 2*nblk][maxdiag].  Factor G (in
-// place, lower L) and form X = L^-1 (lower) in the workspace; returns X.
+// ws: [Linv blocks nblk*NB*NB][X c*c][piv 2*nblk][maxdiag, 8][T of the
+// recursive inverse].  Factor G (in place, lower L) and form X = L^-1 (lower)
+// in the workspace; returns X.
 static hipError_t chol_and_inverse_factor(double* G, int64_t c, double* ws, int* info, double* piv, double rel_tau,
                                           double** Xout, hipStream_t st) {
     const int64_t nblk = (c + NB - 1) / NB;
@@ -480,9 +498,12 @@ static hipError_t chol_and_inverse_factor(double* G, int64_t c, double* ws, int*
     int64_t blocks = (c * c + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_init_xinv, dim3((unsigned)blocks), dim3(256), 0, st, X, c, (const double*)Linv);
-    for (int d = 1; d < nblk; ++d)
-        hipLaunchKernelGGL(k_trtri_step, dim3((unsigned)(nblk - d)), dim3(256), 0, st, (const double*)G, X, c, d,
-                           (const double*)Linv);
+    double* T = maxd + 8;
+    for (int64_t h = 1; h < nblk; h *= 2) {
+        const dim3 grid((unsigned)h, (unsigned)h, (unsigned)((nblk + 2 * h - 1) / (2 * h)));
+        hipLaunchKernelGGL(k_trtri_level<0>, grid, dim3(256), 0, st, (const double*)G, X, c, h, nblk, T);
+        hipLaunchKernelGGL(k_trtri_level<1>, grid, dim3(256), 0, st, (const double*)G, X, c, h, nblk, T);
+    }
     if (piv) {
         const hipError_t e2 = hipMemcpyAsync(piv, pivb, sizeof(double) * 2 * nblk, hipMemcpyDeviceToDevice, st);
         if (e2 != hipSuccess) return e2;

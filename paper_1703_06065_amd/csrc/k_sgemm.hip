@@ -30,7 +30,39 @@ struct GemmArgs {
     const float* Y;
     int64_t ldy;
     double* wsum;
+    int swz;            // tile order (see tile_of); 0: blockIdx.x, blockIdx.y are the M and N tiles
+    int64_t tm, tn;     // M and N tiles
 };
+
+// Tile order.  Workgroups are handed to the eight XCDs (each with its own L2)
+// round-robin by their linear index L, XCD L % 8; the order below gives every
+// XCD a compact set of tiles, so the operand panels its workgroups stream are
+// shared in its L2 instead of being fetched by several XCDs.  The grid is then
+// one-dimensional in x (split-K in z).
+//   swz 1 (tm % 64 == 0, tn % 8 == 0): XCD x owns the M-tiles x tm/8 ..
+//          (x+1) tm/8 - 1 and every N-tile, walked as 8 x 8 squares of tiles
+//          (M fastest), so each panel of either operand serves 8 workgroups;
+//   swz 2 (tn % 8 == 0): XCD x owns the N-tiles x tn/8 .. (x+1) tn/8 - 1 and
+//          every M-tile, all M-tiles of one N-tile in a row, so the N-panel
+//          (the long operand of H = C^T A) is read once.
+__device__ __forceinline__ void tile_of(const GemmArgs& g, int64_t& mt, int64_t& nt) {
+    if (g.swz == 0) {
+        mt = blockIdx.x;
+        nt = blockIdx.y;
+        return;
+    }
+    const int64_t L = blockIdx.x, x = L & 7, t = L >> 3;
+    if (g.swz == 1) {
+        const int64_t band = g.tm >> 3, nbn = g.tn >> 3;
+        const int64_t b = t >> 6, q = t & 63;
+        mt = x * band + (b / nbn) * 8 + (q & 7);
+        nt = (b % nbn) * 8 + (q >> 3);
+    } else {
+        const int64_t band = g.tn >> 3;
+        mt = t % g.tm;
+        nt = x * band + t / g.tm;
+    }
+}
 
 // Load 4 consecutive floats p[0..3] (p 16-byte aligned), zero outside [c, cend).
 __device__ __forceinline__ float4 ld4(const float* p, bool rowok, int64_t c, int64_t cend) {
@@ -63,7 +95,9 @@ __global__ __launch_bounds__(WM* WN * 64) void k_sgemm(const GemmArgs g) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 31, h = lane >> 5;
     const int wm = wave % WM, wn = wave / WM;
-    const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
+    int64_t mtile, ntile;
+    tile_of(g, mtile, ntile);
+    const int64_t m0 = mtile * BM, n0 = ntile * BN;
     const int64_t kbeg = (int64_t)blockIdx.z * g.kchunk;
     const int64_t kend = g.K < kbeg + g.kchunk ? g.K : kbeg + g.kchunk;
 
@@ -127,7 +161,7 @@ __global__ __launch_bounds__(WM* WN * 64) void k_sgemm(const GemmArgs g) {
     // (each element of A is loaded by exactly one workgroup of the first column
     // of tiles; the others do not count)
     constexpr bool kSqa = EPI == EPI_STORE_SQA && !TA;
-    const bool count_sq = kSqa && blockIdx.y == 0;
+    const bool count_sq = kSqa && ntile == 0;
     double sqa = 0.0;
     auto store_tiles = [&]() {
 #pragma unroll
@@ -451,6 +485,7 @@ hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K,
     a.Y = Y;
     a.ldy = ldy;
     a.wsum = wsum;
+    a.swz = 0;
     if (p.splits > 1) {
         a.D = partial;
         a.ldd = N;
@@ -464,7 +499,14 @@ hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K,
     // tile measured slower: 202 us against 192 us for the residual A - C U at 8192 x 4096 x 256)
     const int cfg = store_like ? p.cfg : 2;
     const Cfg c = kCfg[cfg];
-    dim3 grid((unsigned)((M + c.BM - 1) / c.BM), (unsigned)((N + c.BN - 1) / c.BN), (unsigned)p.splits);
+    a.tm = (M + c.BM - 1) / c.BM;
+    a.tn = (N + c.BN - 1) / c.BN;
+    dim3 grid((unsigned)a.tm, (unsigned)a.tn, (unsigned)p.splits);
+    // XCD-compact tile orders for the big products (square tiles, or the wide
+    // transposed tile of H = C^T A)
+    if (cfg == 2 && a.tm % 64 == 0 && a.tn % 8 == 0) a.swz = 1;
+    else if (cfg == 3 && a.tn % 8 == 0) a.swz = 2;
+    if (a.swz) grid = dim3((unsigned)(a.tm * a.tn), 1, (unsigned)p.splits);
     hipError_t e;
     switch (cfg * 100 + (transA ? 10 : 0) + epi) {
         case 0: e = run<0, false, EPI_STORE>(a, grid, st); break;

@@ -217,6 +217,69 @@ def large_share(seed: int = 0, m: int = 65536, n: int = 16384) -> Workload:
                    seed=seed, precision="bf16")
 
 
+@dataclasses.dataclass
+class ServingSpec:
+    """Shape and parameters of one serving request (the matrix is drawn separately)."""
+    req_id: int
+    m: int
+    n: int
+    rank: int
+    b: int
+    s: int
+    offsets: np.ndarray
+
+    @property
+    def k(self) -> int:
+        return self.rank
+
+    @property
+    def l(self) -> int:
+        return min(self.rank + 10, self.m, self.n)
+
+
+def serving_spec(req_id: int, m_range=(256, 8192), n_range=(256, 4096)) -> ServingSpec:
+    """The request recipe of ``serving_request`` without its matrix: m in
+    [256, 8192], n in [256, 4096], rank uniform in [5, 50] (k = rank), block
+    width in {8, 16, 32, 64}, s in [4, 32] clamped to min(s, G, m // b)."""
+    rng = np.random.default_rng([req_id, 0x5E7E])
+    m = int(rng.integers(m_range[0], m_range[1] + 1))
+    n = int(rng.integers(n_range[0], n_range[1] + 1))
+    rank = int(rng.integers(5, 51))
+    b = int(rng.choice([8, 16, 32, 64]))
+    s = int(rng.integers(4, 33))
+    off = contiguous_blocks(n, b)
+    G = len(off) - 1
+    rank = min(rank, m, n)
+    s = max(1, min(s, G, m // b))
+    return ServingSpec(req_id, m, n, rank, b, s, off)
+
+
+def serving_matrix_device(spec: ServingSpec, device="cuda", noise: float = 1e-3):
+    """A = U diag(1/i) V^T + noise N(0, 1) for one serving request, drawn on the
+    GPU with a torch generator seeded by the request id (U, V: QR of Gaussian
+    matrices with R's diagonal signs folded in, the Haar recipe above), as a
+    float32 tensor whose leading dimension is a multiple of 4.  Used where
+    thousands of distinct request matrices are needed at once."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(1_000_003 * (spec.req_id + 1))
+    r = spec.rank
+
+    def haar(rows):
+        q, rr = torch.linalg.qr(torch.randn((rows, r), generator=g, device=device, dtype=torch.float64))
+        d = torch.sign(torch.diagonal(rr))
+        d[d == 0] = 1.0
+        return q * d
+
+    u, v = haar(spec.m), haar(spec.n)
+    sig = 1.0 / torch.arange(1, r + 1, device=device, dtype=torch.float64)
+    ld = (spec.n + 3) // 4 * 4
+    out = torch.empty((spec.m, ld), dtype=torch.float32, device=device)[:, :spec.n]
+    a = (u * sig) @ v.T + noise * torch.randn((spec.m, spec.n), generator=g, device=device, dtype=torch.float64)
+    out.copy_(a)
+    return out
+
+
 def serving_request(req_id: int, m_range=(256, 8192), n_range=(256, 4096)) -> Workload:
     """One request of the serving mix: m in [256, 8192], n in [256, 4096],
     rank uniform in [5, 50] (sigma_i = 1/i, 1e-3 noise), block width in
