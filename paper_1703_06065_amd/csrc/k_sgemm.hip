@@ -41,10 +41,10 @@ struct GemmArgs {
 // one-dimensional in x (split-K in z).
 //   swz 1 (tm % 64 == 0, tn % 8 == 0): XCD x owns the M-tiles x tm/8 ..
 //          (x+1) tm/8 - 1 and every N-tile, walked as 8 x 8 squares of tiles
-//          (M fastest), so each panel of either operand serves 8 workgroups;
-//   swz 2 (tn % 8 == 0): XCD x owns the N-tiles x tn/8 .. (x+1) tn/8 - 1 and
-//          every M-tile, all M-tiles of one N-tile in a row, so the N-panel
-//          (the long operand of H = C^T A) is read once.
+//          (M fastest), so each panel of either operand serves 8 workgroups.
+// (H = C^T A keeps the plain order: giving each XCD a band of N-tiles raised
+// its HBM fetch from 36 to 52 GiB at 65536 x 16384 x 2048 without changing
+// its time.)
 __device__ __forceinline__ void tile_of(const GemmArgs& g, int64_t& mt, int64_t& nt) {
     if (g.swz == 0) {
         mt = blockIdx.x;
@@ -52,16 +52,10 @@ __device__ __forceinline__ void tile_of(const GemmArgs& g, int64_t& mt, int64_t&
         return;
     }
     const int64_t L = blockIdx.x, x = L & 7, t = L >> 3;
-    if (g.swz == 1) {
-        const int64_t band = g.tm >> 3, nbn = g.tn >> 3;
-        const int64_t b = t >> 6, q = t & 63;
-        mt = x * band + (b / nbn) * 8 + (q & 7);
-        nt = (b % nbn) * 8 + (q >> 3);
-    } else {
-        const int64_t band = g.tn >> 3;
-        mt = t % g.tm;
-        nt = x * band + t / g.tm;
-    }
+    const int64_t band = g.tm >> 3, nbn = g.tn >> 3;
+    const int64_t b = t >> 6, q = t & 63;
+    mt = x * band + (b / nbn) * 8 + (q & 7);
+    nt = (b % nbn) * 8 + (q >> 3);
 }
 
 // Load 4 consecutive floats p[0..3] (p 16-byte aligned), zero outside [c, cend).
@@ -502,10 +496,8 @@ hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K,
     a.tm = (M + c.BM - 1) / c.BM;
     a.tn = (N + c.BN - 1) / c.BN;
     dim3 grid((unsigned)a.tm, (unsigned)a.tn, (unsigned)p.splits);
-    // XCD-compact tile orders for the big products (square tiles, or the wide
-    // transposed tile of H = C^T A)
+    // XCD-compact tile order for the big square-tile products
     if (cfg == 2 && a.tm % 64 == 0 && a.tn % 8 == 0) a.swz = 1;
-    else if (cfg == 3 && a.tn % 8 == 0) a.swz = 2;
     if (a.swz) grid = dim3((unsigned)(a.tm * a.tn), 1, (unsigned)p.splits);
     hipError_t e;
     switch (cfg * 100 + (transA ? 10 : 0) + epi) {
