@@ -340,6 +340,24 @@ bcur_status bcur_decompose_async(bcur_ctx* ctx, const float* A, int64_t m, int64
  * (BCUR_OK at once when none is in flight). */
 bcur_status bcur_wait(bcur_ctx* ctx);
 
+/* bcur_decompose for callers that cannot allocate during the call (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * it calls no hipMalloc, hipFree, hipHostMalloc or host allocator.  Its
+ * device workspace is a static array of the library, 128 MiB on each GPU the
+ * library runs on (held from the first bcur_create on that GPU until the
+ * process ends); its host staging is a static 1 MiB buffer per GPU.  A call
+ * whose workspace (bcur_footprint with library_holds_u = 0) exceeds 128 MiB,
+ * or whose staging exceeds 1 MiB, fails with BCUR_E_NOMEM before any work.
+ * result->U must be a caller buffer; block maps (params->col_map, row_map)
+ * are refused with BCUR_E_ARG; stage timing is not recorded.  Every call on a
+ * GPU shares that GPU's arrays and leaves its contents behind (each call
+ * clears what it needs): calls that overlap on one GPU, from any contexts,
+ * race.  Results are bitwise those of bcur_decompose.  Synchronous. */
+bcur_status bcur_decompose_noalloc(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda,
+                                   const int64_t* col_off, int64_t G, const int64_t* row_off, int64_t Gr,
+                                   const bcur_params* params, const float* omega, const uint64_t* draws,
+                                   bcur_result* result);
+
 /* Device workspace one bcur_decompose call needs for these shapes and
  * parameters (bytes; library_holds_u != 0 when result->U will be NULL).
  * Host only, no device access. */

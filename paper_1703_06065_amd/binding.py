@@ -32,7 +32,7 @@ SYMBOLS = [
     "bcur_sketch_pass", "bcur_release_workspace", "bcur_footprint", "bcur_server_create", "bcur_server_destroy",
     "bcur_server_submit", "bcur_server_poll", "bcur_server_wait", "bcur_server_stats", "bcur_decompose_alg1",
     "bcur_decompose_boost", "bcur_block_stable_rank", "bcur_incoherence", "bcur_decompose_alg1_boost",
-    "bcur_test_matrix", "bcur_decompose_async", "bcur_wait",
+    "bcur_test_matrix", "bcur_decompose_async", "bcur_wait", "bcur_decompose_noalloc",
 ]
 
 STAGES = ["frob", "rf_AQ", "rf_AtZ", "rf_reduce", "rf_orth", "rf_rr", "scores", "sample", "gather", "fit_H",
@@ -112,6 +112,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "bcur_decompose_async": (i32, [vp, vp, i64, i64, i64, P(i64), i64, P(i64), i64, P(Params), vp,
                                        P(ctypes.c_uint64), P(Result)]),
         "bcur_wait": (i32, [vp]),
+        "bcur_decompose_noalloc": (i32, [vp, vp, i64, i64, i64, P(i64), i64, P(i64), i64, P(Params), vp,
+                                         P(ctypes.c_uint64), P(Result)]),
         "bcur_destroy": (i32, [vp]),
         "bcur_synchronize": (i32, [vp]),
         "bcur_status_str": (ctypes.c_char_p, [i32]),
@@ -492,6 +494,18 @@ class Context:
         self._chk(self.lib.bcur_decompose_async(self.h, *call.args))
         self._pending = call
         return call
+
+    def decompose_noalloc(self, A, offsets, k: int, s: int, omega, draws, U_out, q: int = 2,
+                          replace: bool = False, refine: int = 1, precision: int = PREC_FP32, row_offsets=None,
+                          s_r: int = 0, l: Optional[int] = None):
+        """bcur_decompose_noalloc: the library allocates nothing (its static
+        scratch array and host staging serve); U_out is required."""
+        if U_out is None:
+            raise ValueError("U_out is required without allocation")
+        call = _DecomposeCall(A, offsets, k, s, omega, draws, q, replace, refine, precision, True, row_offsets,
+                              s_r, U_out, None, None, l, None)
+        self._chk(self.lib.bcur_decompose_noalloc(self.h, *call.args))
+        return call.result()
 
     def wait(self):
         """bcur_wait: the result of the decomposition in flight (None if none)."""

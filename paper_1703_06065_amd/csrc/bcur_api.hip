@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -15,6 +16,21 @@
 #include "bcur_internal.h"
 
 using namespace bcur;
+
+// Scratch of the entry point that allocates nothing (bcur_decompose_noalloc):
+// one array per GPU, held from the library's first use on that GPU until the
+// process ends.  In host code its name is only a stand-in: the device address
+// comes from hipGetSymbolAddress, taken once per device in bcur_create.
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+__device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 16;
+constexpr size_t kHostStageBytes = (size_t)1 << 20;
+void* g_scratch[kMaxDevices];                                   // device address of scratch, per device
+alignas(64) char g_host_stage[kMaxDevices][kHostStageBytes];    // host staging of those calls, per device
+std::mutex g_scratch_mu;
+}  // namespace
 
 // Per-stage device timing: event pairs are recorded on the context's stream
 // and resolved (elapsed time added to the stage total) on the next read.
@@ -48,6 +64,7 @@ struct bcur_ctx {
     char* pinned = nullptr;
     size_t pinned_bytes = 0;
     bool pinned_busy = false;  // a call left copies into `pinned` without synchronizing
+    bool noalloc = false;      // workspace and staging are handed in: nothing may be allocated
     char err[512] = {0};       // message of the last error (a fixed buffer: reporting allocates nothing)
     StageTimer timer;
     // asynchronous decomposition: its host thread, its stream (default
@@ -115,6 +132,9 @@ struct Arena {
 
 bcur_status reserve(bcur_ctx* ctx, size_t bytes) {
     if (bytes <= ctx->ws_bytes) return BCUR_OK;
+    if (ctx->noalloc)
+        return fail(ctx, BCUR_E_NOMEM, "the call needs %zu bytes of scratch, above the %zu available", bytes,
+                    ctx->ws_bytes);
     if (ctx->budget && bytes > ctx->budget)
         return fail(ctx, BCUR_E_NOMEM, "the call needs %zu bytes of device workspace, over the context's budget of %zu",
                     bytes, ctx->budget);
@@ -134,6 +154,9 @@ bcur_status reserve(bcur_ctx* ctx, size_t bytes) {
 
 bcur_status reserve_pinned(bcur_ctx* ctx, size_t bytes) {
     if (bytes <= ctx->pinned_bytes) return BCUR_OK;
+    if (ctx->noalloc)
+        return fail(ctx, BCUR_E_NOMEM, "the call needs %zu bytes of host staging, above the %zu available", bytes,
+                    ctx->pinned_bytes);
     if (ctx->pinned) HIPCHK(hipHostFree(ctx->pinned));
     ctx->pinned = nullptr;
     ctx->pinned_bytes = 0;
@@ -858,6 +881,18 @@ bcur_status bcur_create(bcur_ctx** out, int device, void* stream, size_t scratch
     }
     ctx->stream = (hipStream_t)stream;   // NULL: the device's null stream
     ctx->budget = scratch_budget;
+    if (device < kMaxDevices) {
+        // the scratch array's address on this device (the device is current here)
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch[device]) {
+            void* ptr = nullptr;
+            if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+                delete ctx;
+                return BCUR_E_HIP;
+            }
+            g_scratch[device] = ptr;
+        }
+    }
     *out = ctx;
     return BCUR_OK;
 }
@@ -1563,6 +1598,43 @@ bcur_status bcur_wait(bcur_ctx* ctx) {
     ctx->worker.join();
     ctx->inflight = false;
     return ctx->job_status;
+}
+
+bcur_status bcur_decompose_noalloc(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda,
+                                   const int64_t* col_off, int64_t G, const int64_t* row_off, int64_t Gr,
+                                   const bcur_params* p, const float* omega, const uint64_t* draws, bcur_result* res) {
+    GUARD(ctx);
+    if (!p || !res) return fail(ctx, BCUR_E_ARG, "null argument");
+    if (p->col_map || (row_off && p->s_r > 0 && p->row_map))
+        return fail(ctx, BCUR_E_ARG, "block maps are not taken without allocation: use bcur_decompose");
+    if (!res->U) return fail(ctx, BCUR_E_ARG, "U must be a caller buffer without allocation");
+    if (ctx->device >= kMaxDevices || !g_scratch[ctx->device])
+        return fail(ctx, BCUR_E_HIP, "no scratch array on device %d", ctx->device);
+    // the device's scratch array and host staging stand in for the context's
+    // workspace and pinned buffer for this call; nothing is allocated
+    char* const ws = ctx->ws;
+    const size_t ws_bytes = ctx->ws_bytes;
+    char* const pinned = ctx->pinned;
+    const size_t pinned_bytes = ctx->pinned_bytes;
+    const bool pinned_busy = ctx->pinned_busy, timing = ctx->timer.on;
+    ctx->ws = static_cast<char*>(g_scratch[ctx->device]);
+    ctx->ws_bytes = kScratchBytes;
+    ctx->pinned = g_host_stage[ctx->device];
+    ctx->pinned_bytes = kHostStageBytes;
+    ctx->pinned_busy = false;
+    ctx->timer.on = false;   // stage events are not recorded by this call
+    ctx->noalloc = true;
+    const bcur_status st = decompose_impl(ctx, A, m, n, lda, col_off, G, row_off, Gr, p, omega, draws, res);
+    // a failed call may leave copies through the shared staging in flight
+    if (st != BCUR_OK) (void)hipStreamSynchronize(ctx->stream);
+    ctx->noalloc = false;
+    ctx->ws = ws;
+    ctx->ws_bytes = ws_bytes;
+    ctx->pinned = pinned;
+    ctx->pinned_bytes = pinned_bytes;
+    ctx->pinned_busy = pinned_busy;
+    ctx->timer.on = timing;
+    return st;
 }
 
 bcur_status bcur_decompose_boost(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda,
