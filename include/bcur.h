@@ -308,6 +308,14 @@ typedef struct bcur_result {
     double min_margin;   /* smallest sampling margin over the column draws */
     uint32_t flags;      /* BCUR_FLAG_* */
     uint32_t rr_sweeps;  /* Jacobi sweeps of the Rayleigh-Ritz eigensolver */
+    /* precision report */
+    double kappa;        /* lam_1 / (lam_k - lam_{k+1}) of the Ritz values (lam = Ritz value^2; 1 when k = l,
+                            inf without a gap): how strongly rounding of the passes over A can move the top-k
+                            subspace and so the scores (their error is below about 4 sqrt(max(m, n)) u32 kappa
+                            max(l_g, k / G) in FP32, with u_bf16 in place of u32 on the BF16 passes) */
+    double cond_c;       /* columns only: sqrt(largest / smallest pivot) of the Cholesky factor of C^T C, a
+                            lower bound on cond(C) (U carries a relative error of about sqrt(m) u32 cond(C)^2
+                            err / ||A||_F); 0 for the row-block variant */
 } bcur_result;
 
 /* One Block CUR decomposition: stages 1-6 above.

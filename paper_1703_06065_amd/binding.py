@@ -60,7 +60,7 @@ class Result(ctypes.Structure):
                 ("idx_r", ctypes.POINTER(ctypes.c_int64)), ("row_scores", ctypes.POINTER(ctypes.c_double)),
                 ("c", ctypes.c_int64), ("r", ctypes.c_int64), ("frob2", ctypes.c_double), ("err", ctypes.c_double),
                 ("rel_err", ctypes.c_double), ("min_margin", ctypes.c_double), ("flags", ctypes.c_uint32),
-                ("rr_sweeps", ctypes.c_uint32)]
+                ("rr_sweeps", ctypes.c_uint32), ("kappa", ctypes.c_double), ("cond_c", ctypes.c_double)]
 
 
 class Alg1Params(ctypes.Structure):
@@ -278,7 +278,7 @@ class _DecomposeCall:
         res = self.res
         out = {"idx": self.idx, "weights": self.w, "scores": self.sc, "ritz": self.ritz, "c": res.c, "r": res.r,
                "frob2": res.frob2, "err": res.err, "rel_err": res.rel_err, "min_margin": res.min_margin,
-               "flags": res.flags, "rr_sweeps": res.rr_sweeps}
+               "flags": res.flags, "rr_sweeps": res.rr_sweeps, "kappa": res.kappa, "cond_c": res.cond_c}
         if self.U is not None:
             out["U"] = self.U[:res.c, :res.r] if res.r else self.U[:res.c]
         if self.idx_r is not None:
@@ -697,7 +697,7 @@ class Server:
             raise BcurError(st, self.lib.bcur_status_str(st).decode())
         out = {"idx": idx, "weights": w, "scores": sc, "ritz": rz, "c": res.c, "r": res.r, "frob2": res.frob2,
                "err": res.err, "rel_err": res.rel_err, "min_margin": res.min_margin, "flags": res.flags,
-               "rr_sweeps": res.rr_sweeps}
+               "rr_sweeps": res.rr_sweeps, "kappa": res.kappa, "cond_c": res.cond_c}
         if U is not None:
             out["U"] = U[:res.c, :res.r] if res.r else U[:res.c]
         if s_r:

@@ -409,8 +409,10 @@ bcur_status cast_a_bf16(bcur_ctx* ctx, const RFBufs& b, const float* A, int64_t 
 //
 // frob2 (device, or null): with an FP32 first pass, ||A||_F^2 is summed from
 // that pass's loads of A (each element is loaded once) into frob2[0]; the
-// caller computes it separately on the BF16 path (range_finder_fuses_frob).
-bool range_finder_fuses_frob(int64_t q, int precision) { return !(precision == BCUR_PREC_BF16 && q > 0); }
+// caller computes it separately where the range finder has no FP32 pass
+// (range_finder_fuses_frob).  On the BF16 path the first FP32 pass is that of
+// the last power iteration.
+bool range_finder_fuses_frob(int64_t q, int precision) { (void)q; (void)precision; return true; }
 
 // omega: device n x l (dense), or null: the test matrix of `seed` is drawn into Q.
 bcur_status range_finder_run(bcur_ctx* ctx, const RFBufs& b, const float* A, int64_t m, int64_t n, int64_t lda,
@@ -432,7 +434,7 @@ bcur_status range_finder_run(bcur_ctx* ctx, const RFBufs& b, const float* A, int
         if (bf16 && it < q) {
             STCHK(sketch_pass_bf16(ctx, b, m, n, b.Q, lp, l, b.Y));
         } else {
-            const bool sqa = frob2 && it == 0;
+            const bool sqa = frob2 && it == (bf16 ? q : 0);
             STCHK(gemm_timed(ctx, BCUR_STAGE_RF_AQ, BCUR_STAGE_RF_REDUCE, pz, m, l, n, false, A, lda, b.Q, lp, b.Z,
                              lp, b.part, sqa ? EPI_STORE_SQA : EPI_STORE, nullptr, 0, nullptr, 0,
                              sqa ? b.sqpart : nullptr));
@@ -584,6 +586,7 @@ bcur_status fit_run(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t m, 
 struct FitOut {
     double err2;
     uint32_t flags;
+    double cond_est;   // sqrt(largest / smallest Cholesky pivot of C^T C): a lower bound on cond(C)
 };
 
 // U = C^+ A by Cholesky QR2 in FP64 (the scheme of the row-block variant):
@@ -667,6 +670,7 @@ bcur_status fit_collect(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t
     }
     out->err2 = std::max(err2, 0.0);
     out->flags = fl;
+    out->cond_est = (pmin > 0.0 && pmax > 0.0) ? sqrt(pmax / pmin) : INFINITY;
     return BCUR_OK;
 }
 
@@ -1484,6 +1488,7 @@ bcur_status decompose_impl(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
     const int64_t ldu = res->U ? res->ldu : round4(ucols);
     double err2 = 0.0;
     uint32_t fl = 0;
+    double cond_est = 0.0;
     if (rowv) {
         STCHK(fit_cur_run(ctx, cb, A, m, n, lda, Cbuf, c, ldc, r, U, ldu));
         double hv[4];
@@ -1501,6 +1506,7 @@ bcur_status decompose_impl(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
         STCHK(fit_collect(ctx, fb, A, m, n, lda, Cbuf, c, ldc, U, ldu, &fo, h_fit));
         err2 = fo.err2;
         fl = fo.flags;
+        cond_est = fo.cond_est;
     }
     ctx->pinned_busy = false;  // the fit's synchronization completed every copy
     if (on_device) STCHK(check_draws());
@@ -1525,6 +1531,11 @@ bcur_status decompose_impl(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, 
     res->min_margin = mm;
     res->flags = fl;
     res->rr_sweeps = (uint32_t)rinfo[2];
+    // lam_1 / (lam_k - lam_{k+1}) of the Ritz values: the sensitivity of the
+    // top-k subspace, and so of the scores, to perturbations of A
+    const double gap = k < l ? h_lam[k - 1] - h_lam[k] : 0.0;
+    res->kappa = k >= l ? 1.0 : (gap > 0.0 ? h_lam[0] / gap : INFINITY);
+    res->cond_c = cond_est;
     return BCUR_OK;
 }
 
@@ -1816,6 +1827,7 @@ bcur_status bcur_decompose_boost(bcur_ctx* ctx, const float* A, int64_t m, int64
     int64_t best = -1;
     double best_err2 = INFINITY;
     uint32_t best_flags = 0;
+    double best_cond = 0.0;
     for (int64_t i = 0; i < t; ++i) {
         const float* Ci = Call + seg_off[i];
         STCHK(fit_run(ctx, fb, A, m, n, lda, Ci, seg_c[i], ctot, d_list + seg_off[i], nullptr, p->refine, Ucur, np,
@@ -1827,6 +1839,7 @@ bcur_status bcur_decompose_boost(bcur_ctx* ctx, const float* A, int64_t m, int64
             best_err2 = fo.err2;
             best = i;
             best_flags = fo.flags;
+            best_cond = fo.cond_est;
             HIPCHK(hipMemcpy2DAsync(Ubest, ldb * sizeof(float), Ucur, np * sizeof(float), n * sizeof(float),
                                     seg_c[i], hipMemcpyDeviceToDevice, st));
         }
@@ -1852,6 +1865,9 @@ bcur_status bcur_decompose_boost(bcur_ctx* ctx, const float* A, int64_t m, int64
     res->min_margin = mm;
     res->flags = fl;
     res->rr_sweeps = (uint32_t)rinfo[2];
+    const double gap = k < l ? h_lam[k - 1] - h_lam[k] : 0.0;
+    res->kappa = k >= l ? 1.0 : (gap > 0.0 ? h_lam[0] / gap : INFINITY);
+    res->cond_c = best_cond;
     if (best_out) *best_out = best;
     return BCUR_OK;
 }

@@ -184,6 +184,8 @@ void copy_out(const Ticket* t, bcur_result* out) {
     out->min_margin = t->res.min_margin;
     out->flags = t->res.flags;
     out->rr_sweeps = t->res.rr_sweeps;
+    out->kappa = t->res.kappa;
+    out->cond_c = t->res.cond_c;
 }
 
 double percentile(std::vector<double> v, double q) {

@@ -71,8 +71,18 @@ __device__ __forceinline__ float4 ld4(const float* p, bool rowok, int64_t c, int
     return v;
 }
 
+// The norm-only residual epilogue has two forms.  EPI_RESID_NORM reads the
+// residual input X for the thread's outputs before the main loop (its latency
+// hides behind the MFMA work; best for a short K, the loads occupy 64 more
+// registers: two waves per SIMD).  kResidLate reads X in the epilogue and
+// asks the compiler for four waves per SIMD (no spills at these tiles): for a
+// long K the occupancy hides the main loop's own latency better (65536 x
+// 16384 x 2048: 38.3 -> 36.4 ms; 8192 x 4096 x 256: 0.178 -> 0.187 ms, so the
+// early read stays for short K).
+constexpr int kResidLate = 5;
+
 template <int BM, int BN, int BK, int WM, int WN, bool TA, int EPI>
-__global__ __launch_bounds__(WM* WN * 64) void k_sgemm(const GemmArgs g) {
+__global__ __launch_bounds__(WM* WN * 64, EPI == kResidLate ? 4 : 1) void k_sgemm(const GemmArgs g) {
     constexpr int NT = WM * WN * 64;
     constexpr int WTM = BM / WM, WTN = BN / WN;
     constexpr int TM = WTM / 32, TN = WTN / 32;
@@ -108,10 +118,11 @@ __global__ __launch_bounds__(WM* WN * 64) void k_sgemm(const GemmArgs g) {
     // EPI_RESID: the residual input X of this thread's outputs is read before the
     // main loop (a wave-uniform base plus one lane offset per load), so its HBM
     // latency is hidden behind the MFMA work instead of following it.
-    constexpr bool kResid = EPI == EPI_RESID || EPI == EPI_RESID_NORM;
-    constexpr int XM = kResid ? TM : 1, XN = kResid ? TN : 1;
+    constexpr bool kResid = EPI == EPI_RESID || EPI == EPI_RESID_NORM || EPI == kResidLate;
+    constexpr bool kPre = EPI == EPI_RESID || EPI == EPI_RESID_NORM;
+    constexpr int XM = kPre ? TM : 1, XN = kPre ? TN : 1;
     float xv[XM][XN][16];
-    if constexpr (kResid) {
+    if constexpr (kPre) {
         const int wmu = __builtin_amdgcn_readfirstlane(wm), wnu = __builtin_amdgcn_readfirstlane(wn);
         const int64_t rb0 = m0 + wmu * WTM, cb0 = n0 + wnu * WTN;
         const float* xbase = g.X + rb0 * g.ldx + cb0;
@@ -226,7 +237,10 @@ __global__ __launch_bounds__(WM* WN * 64) void k_sgemm(const GemmArgs g) {
                     if (EPI == EPI_STORE || EPI == EPI_STORE_SQA) {
                         D[row * g.ldd + col] = x;
                     } else if (kResid) {
-                        const float e = xv[i][j][v] - x;
+                        float xe;
+                        if constexpr (kPre) xe = xv[i][j][v];
+                        else xe = g.X[row * g.ldx + col];
+                        const float e = xe - x;
                         if (EPI == EPI_RESID) D[row * g.ldd + col] = e;
                         wacc += (double)e * (double)e;
                     } else {
@@ -512,7 +526,9 @@ hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K,
         case 104: e = run<1, false, EPI_STORE_SQA>(a, grid, st); break;
         case 204: e = run<2, false, EPI_STORE_SQA>(a, grid, st); break;
         case 201: e = run<2, false, EPI_RESID>(a, grid, st); break;
-        case 203: e = run<2, false, EPI_RESID_NORM>(a, grid, st); break;
+        case 203:
+            e = K >= 1024 ? run<2, false, kResidLate>(a, grid, st) : run<2, false, EPI_RESID_NORM>(a, grid, st);
+            break;
         case 202: e = run<2, false, EPI_ADD_DOT>(a, grid, st); break;
         case 212: e = run<2, true, EPI_ADD_DOT>(a, grid, st); break;
         default: return hipErrorInvalidValue;

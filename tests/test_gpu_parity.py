@@ -275,8 +275,17 @@ def _check_decompose(ctx, w, replace=False, refine=1, label="", omega=None, prec
             cond = O.cond2(C)
             rel_u = np.linalg.norm(Ug - ref["U"]) / np.linalg.norm(ref["U"])
             gate = u_gate(cond, ref["err"], math.sqrt(ref["frob2"]), w.m)
-            note(f"  rel U gap {rel_u:.2e} gate {gate:.2e} cond(C)={cond:.3g}")
+            note(f"  rel U gap {rel_u:.2e} gate {gate:.2e} cond(C)={cond:.3g} reported estimate {res['cond_c']:.3g}")
             assert rel_u <= gate
+            # the reported estimate is a lower bound on cond(C): the diagonal of a triangular factor
+            assert 1.0 - 1e-6 <= res["cond_c"] <= cond * (1 + 1e-4)
+    # the precision report: kappa from the returned Ritz values, near the twin's
+    lam = np.asarray(res["ritz"], dtype=np.float64) ** 2
+    if w.k < w.l:
+        k_own = lam[0] / (lam[w.k - 1] - lam[w.k])
+        assert abs(res["kappa"] - k_own) <= 1e-6 * k_own
+        note(f"  kappa reported {res['kappa']:.4g} twin {ref['kappa']:.4g}")
+        assert abs(res["kappa"] - ref["kappa"]) <= 0.1 * ref["kappa"]
     else:
         # a different but valid selection: distinct blocks, in range, and a
         # residual that matches the oracle's fit of the GPU's own blocks
