@@ -25,7 +25,39 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
+# An FP32 product on the split-BF16 path costs six BF16 MFMA products.
+SPLIT_BF16_PRODUCTS = 6
+
+
+def split_bf16(M, N, K):
+    """Whether the library forms an M x N x K FP32 product from the three-term
+    BF16 splits of its operands (the rule stated with BCUR_PREC_FP32 in
+    include/bcur.h): at least 8e9 multiply-adds, M, K >= 256, and N >= 256 or
+    64 < N <= 128."""
+    wide = N >= 256 or 64 < N <= 128
+    return M >= 256 and K >= 256 and wide and float(M) * N * K >= 8.0e9
+
+
+def mfma_roofline(M, N, K, avg_ms, kernel_fp32, kernel_split, **extra):
+    """Roofline entry of one FP32 product of 2 M N K FLOP per launch: against
+    the FP32 MFMA peak, or on the split-BF16 path against the BF16 MFMA peak
+    divided by its six products per FP32 product."""
+    flop = 2.0 * M * N * K
+    ach = flop / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    if split_bf16(M, N, K):
+        peak = PEAK_BF16_MFMA_TFLOPS / SPLIT_BF16_PRODUCTS
+        roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": round(peak, 2), "unit": "TFLOP/s",
+                "frac": round(ach / peak, 4), "kernel": kernel_split, "mfma_dtype": "bf16",
+                "peak_basis": f"BF16 MFMA peak {PEAK_BF16_MFMA_TFLOPS:g} TFLOP/s / {SPLIT_BF16_PRODUCTS} products",
+                "bf16_tflops_executed": round(SPLIT_BF16_PRODUCTS * ach, 3)}
+    else:
+        roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(ach / PEAK_FP32_MFMA_TFLOPS, 4), "kernel": kernel_fp32, "mfma_dtype": "f32"}
+    roof.update({"traffic": None, "launches_per_step": 1, "avg_ms": round(avg_ms, 5), "flop_per_launch": flop})
+    roof.update(extra)
+    return roof
 
 
 def algorithmic_flops(m, n, k, l, q, c):
@@ -183,14 +215,10 @@ def alg1_bench(args):
     el = t1 - t0
     c = int(res["c"])
     # the residual GEMM A - (C U) R: 2 m r n FLOP per launch, one launch per step
-    per_launch_flop = 2.0 * w.m * r * w.n
     avg_ms = stages["fit_E"][0] / max(stages["fit_E"][1], 1)
-    ach = per_launch_flop / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
-    roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(ach / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
-            "kernel": "k_sgemm<128,128,16,2,2> residual epilogue (E = A - (C U) R)", "launches_per_step": 1,
-            "avg_ms": round(avg_ms, 5), "flop_per_launch": per_launch_flop,
-            "algorithmic_bytes_per_launch": 4.0 * (w.m * r + r * w.n + 2.0 * w.m * w.n)}
+    roof = mfma_roofline(w.m, w.n, r, avg_ms, "k_sgemm<128,128,16,2,2> residual epilogue (E = A - (C U) R)",
+                         "k_xgemm<256,256> split-BF16, norm-only residual epilogue (E = A - (C U) R)",
+                         algorithmic_bytes_per_launch=4.0 * (w.m * r + r * w.n + 2.0 * w.m * w.n))
     out = {
         "metric": "block-CUR decompositions/s (Algorithm 1: uniform rows, U = W^+)",
         "value": args.steps / el,
@@ -274,14 +302,11 @@ def boost_bench(args):
     # every trial here has c = 256 columns (16 distinct blocks of 16): ctot = t c
     c = int(res["c"])
     ctot = t * c
-    per_launch_flop = 2.0 * w.m * ctot * w.n
     avg_ms = stages["fit_H"][0] / max(stages["fit_H"][1], 1)
-    ach = per_launch_flop / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
-    roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(ach / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
-            "kernel": "k_sgemm<256,128,16,4,2,TA> (H = C^T A over the t trials' concatenated columns)",
-            "launches_per_step": 1, "avg_ms": round(avg_ms, 5), "flop_per_launch": per_launch_flop,
-            "algorithmic_bytes_per_launch": 4.0 * (w.m * ctot + w.m * w.n + ctot * w.n)}
+    roof = mfma_roofline(ctot, w.n, w.m, avg_ms,
+                         "k_sgemm<256,128,16,4,2,TA> (H = C^T A over the t trials' concatenated columns)",
+                         "k_xgemm<256,256,TA> split-BF16 (H = C^T A over the t trials' concatenated columns)",
+                         algorithmic_bytes_per_launch=4.0 * (w.m * ctot + w.m * w.n + ctot * w.n))
     rf_flops, fit_flops = algorithmic_flops(w.m, w.n, w.k, w.l, w.q, c)
     out = {
         "metric": f"block-CUR boosted decompositions/s (t = {t} trials)",
@@ -593,27 +618,26 @@ def decompose_bench(args):
 
     # Roofline of the dominant kernel: of the kernels that a throughput
     # roofline bounds, the one with the largest device time per decomposition.
-    # At these shapes that is one of the two c-wide MFMA GEMMs over A, each
+    # At these shapes that is one of the two c-wide products over A, each
     # 2 m c n FLOP per launch and one launch per decomposition: the residual
-    # ||A - C U||_F^2 (k_sgemm<128,128> NN, norm-only epilogue, stage fit_E) or
-    # H = C^T A (k_sgemm<256,128> TN, stage fit_H).  The one-workgroup FP64
-    # solvers are latency-bound; their times are in stage_ms_per_step.
-    kern = {"fit_E": ("k_sgemm<128,128,16,2,2> norm-only residual epilogue (||A - C U||_F^2)",
-                      4.0 * (w.m * w.n + w.m * c + c * w.n)),
-            "fit_H": ("k_sgemm<256,128,16,4,2> TN (H = C^T A)", 4.0 * (w.m * w.n + w.m * c + c * w.n))}
-    avg = {st: stages[st][0] / max(stages[st][1], 1) for st in kern}
+    # ||A - C U||_F^2 (NN, norm-only epilogue, stage fit_E) or H = C^T A (TN,
+    # stage fit_H), on the split-BF16 kernel at these sizes.  The
+    # one-workgroup FP64 solvers are latency-bound; their times are in
+    # stage_ms_per_step.
+    shapes = {"fit_E": (w.m, w.n, c), "fit_H": (c, w.n, w.m)}
+    names = {"fit_E": ("k_sgemm<128,128,16,2,2> norm-only residual epilogue (||A - C U||_F^2)",
+                       "k_xgemm<256,256> split-BF16, norm-only residual epilogue (||A - C U||_F^2)"),
+             "fit_H": ("k_sgemm<256,128,16,4,2> TN (H = C^T A)", "k_xgemm<256,256,TA> split-BF16 (H = C^T A)")}
+    avg = {st: stages[st][0] / max(stages[st][1], 1) for st in shapes}
     dom = max(avg, key=avg.get)
-    per_launch_flop = 2.0 * w.m * c * w.n
-    avg_ms = avg[dom]
-    ach = per_launch_flop / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
     table = TRAFFIC_LARGE if large else TRAFFIC_PLAIN
-    roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(ach / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": traffic_for(table, dom),
-            "kernel": kern[dom][0], "stage": dom, "launches_per_step": 1, "avg_ms": round(avg_ms, 5),
-            "flop_per_launch": per_launch_flop, "algorithmic_bytes_per_launch": kern[dom][1],
-            "other_stage_avg_ms": {st: round(v, 5) for st, v in avg.items() if st != dom}}
+    roof = mfma_roofline(*shapes[dom], avg[dom], *names[dom], stage=dom,
+                         algorithmic_bytes_per_launch=4.0 * (w.m * w.n + w.m * c + c * w.n),
+                         other_stage_avg_ms={st: round(v, 5) for st, v in avg.items() if st != dom})
+    roof["traffic"] = traffic_for(table, dom)
     prec = "BF16 range finder (q BF16 power iterations, final FP32 pass), FP32 fit with one refinement step, " \
            "FP64 small factorizations" if large else "FP32 range finder and fit, FP64 small factorizations"
+    prec += "; large FP32 products as six BF16 MFMA products of exact three-term BF16 splits, FP32 accumulation"
     out = {
         "metric": "block-CUR decompositions/s",
         "value": args.steps / el,

@@ -54,10 +54,23 @@ typedef enum bcur_status {
                               while an asynchronous decomposition is in flight (see bcur_wait) */
 } bcur_status;
 
-/* Arithmetic used by the range finder's passes over A. */
+/* Arithmetic used by the range finder's passes over A.
+ *
+ * FP32 products (every product of BCUR_PREC_FP32, the fit, and the last
+ * power pass of BCUR_PREC_BF16) accumulate in FP32.  Small products run on
+ * the FP32 matrix cores.  Products of at least 8e9 multiply-adds with
+ * N >= 256, or 64 < N <= 128 (a sketch width), split each FP32 operand
+ * exactly into three BF16 terms, a = a0 + a1 + a2, and form a b from the
+ * six largest of the nine term products on the BF16 matrix cores.  The
+ * three dropped terms are below 2^-23 |a b|, two FP32 unit roundoffs, which
+ * is less than the FP32 accumulation's own rounding; the results meet the
+ * same tolerances as FP32 MFMA products.  The split needs |a| < 3.38e38 (a
+ * larger finite value rounds to infinity in BF16); non-finite operands give
+ * NaN. */
 enum {
-    BCUR_PREC_FP32 = 0,    /* FP32 MFMA, FP32 accumulation */
-    BCUR_PREC_BF16 = 1     /* BF16 MFMA with FP32 accumulation, then one FP32 power pass */
+    BCUR_PREC_FP32 = 0,    /* FP32 products as above */
+    BCUR_PREC_BF16 = 1     /* first q power iterations: A and the basis rounded to BF16, BF16 MFMA with
+                              FP32 accumulation; then one FP32 power pass */
 };
 
 /* Bits of bcur_result.flags. */
@@ -142,7 +155,7 @@ bcur_status bcur_range_finder(bcur_ctx* ctx, const float* A, int64_t m, int64_t 
                               float* Vk, float* Uk, double* ritz);
 
 /* One sketch pass of the range finder: Y = A^T (A Q), the power step that
- * multiplies a basis by A^T A.  BCUR_PREC_FP32: FP32 MFMA, FP32 accumulation.
+ * multiplies a basis by A^T A.  BCUR_PREC_FP32: FP32 products (see BCUR_PREC_FP32).
  * BCUR_PREC_BF16: A and Q rounded to BF16 (nearest even), BF16 MFMA with
  * FP32 accumulation, A Q rounded to BF16 before the second product.
  * A: device m x n (lda).  Q: device n x l (ldq).  Y: device n x l (ldy,

@@ -496,10 +496,10 @@ void fit_layout(Arena& a, FitBufs& b, int64_t m, int64_t n, int64_t c, bool need
     b.G = a.take<double>(c * c);
     b.spdws = a.take<double>(spd_inverse_ws_doubles(c));
     b.nwsE = resid_parts(m, n, c);
-    b.nwsD = add_dot_parts(pu, c, n);
+    b.nwsD = add_dot_parts(pu, c, n, c);
     b.wsE = a.take<double>(b.nwsE);
     b.wsD = a.take<double>(b.nwsD);
-    b.wsF = a.take<double>(resid_parts(c, n, c));
+    b.wsF = a.take<double>(resid_store_parts(c, n));
     b.errv = a.take<double>(8);
     b.piv = a.take<double>(2 * ((c + 63) / 64));
     b.info = a.take<int>(4);
@@ -578,7 +578,7 @@ bcur_status fit_run(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t m, 
                                     st));
     }
     // one partial per workgroup of the residual GEMM, and of the dU sum
-    HIPCHK(launch_fit_err(b.wsE, resid_parts(m, n, c), b.wsD, refine ? add_dot_parts(pu, c, n) : 0, b.errv, st));
+    HIPCHK(launch_fit_err(b.wsE, resid_parts(m, n, c), b.wsD, refine ? add_dot_parts(pu, c, n, c) : 0, b.errv, st));
     return BCUR_OK;
 }
 

@@ -72,13 +72,15 @@ hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K,
                              hipStream_t st);
 hipError_t launch_splitk_reduce(const GemmPlan& p, int64_t M, int64_t N, const float* partial, float* D,
                                 int64_t ldd, hipStream_t st);
-// wsum partials written by a residual epilogue (EPI_RESID / EPI_RESID_NORM) of an M x N x K
+// wsum partials written by the norm-only residual epilogue (EPI_RESID_NORM) of an M x N x K
 // product planned with plan_sgemm(M, N, K, false, false): one per workgroup
 int64_t resid_parts(int64_t M, int64_t N, int64_t K);
+// wsum partials written by EPI_RESID (the FP32 square tile) of an M x N product
+int64_t resid_store_parts(int64_t M, int64_t N);
 // D = X + op(A) B and wsum[w] = partial sums of (op(A) B) * Y,
 // with split-K when the plan has it (the sum and the epilogue then run in a
 // second kernel).  add_dot_parts gives the number of wsum partials written.
-int64_t add_dot_parts(const GemmPlan& p, int64_t M, int64_t N);
+int64_t add_dot_parts(const GemmPlan& p, int64_t M, int64_t N, int64_t K);
 hipError_t launch_sgemm_add_dot(const GemmPlan& p, int64_t M, int64_t N, int64_t K, bool transA, const float* A,
                                 int64_t lda, const float* B, int64_t ldb, float* D, int64_t ldd, float* partial,
                                 const float* X, int64_t ldx, const float* Y, int64_t ldy, double* wsum, hipStream_t st);

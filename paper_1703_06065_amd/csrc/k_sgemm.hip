@@ -32,6 +32,7 @@ struct GemmArgs {
     double* wsum;
     int swz;            // tile order (see tile_of); 0: blockIdx.x, blockIdx.y are the M and N tiles
     int64_t tm, tn;     // M and N tiles
+    bool full;          // k_xgemm: every tile and k-step inside the matrices (no bounds checks)
 };
 
 // Tile order.  Workgroups are handed to the eight XCDs (each with its own L2)
@@ -274,6 +275,342 @@ __global__ __launch_bounds__(WM* WN * 64, EPI == kResidLate ? 4 : 1) void k_sgem
     }
 }
 
+// The same products with each FP32 operand split exactly into three BF16
+// terms, a = a0 + a1 + a2 (a0 = bf16(a), a1 = bf16(a - a0), a2 = the rest,
+// each rounded to nearest: a has 24 significant bits, a0 and a1 take 8 each
+// and the remainder has at most 8, so the split loses nothing), and the
+// product a b formed by six BF16 MFMAs (v_mfma_f32_32x32x16_bf16, FP32
+// accumulation) as a0 b0 + a0 b1 + a1 b0 + a0 b2 + a1 b1 + a2 b0.  The
+// dropped terms a1 b2 + a2 b1 + a2 b2 are below 2^-23 |a b| (|a1| <= 2^-8 |a|,
+// |a2| <= 2^-16 |a|), so each product is within two FP32 unit roundoffs of
+// the exact one, below the rounding of the FP32 accumulation that follows.
+// The BF16 matrix cores run sixteen times the FP32 MFMA rate, so the six
+// products take 6/16 of the FP32 MFMA time.  (Valid for |a| < 3.38e38: larger
+// finite FP32 values round to infinity in BF16; infinities and NaNs give NaN.)
+//
+// Tile 256 x 256 x 16 for eight waves (128 x 64 each), LDS double-buffered
+// (one barrier per step).  Each operand tile sits in LDS as three BF16
+// planes, one 48-byte row (16 k values and 16 bytes of padding) per output
+// row or column, so each MFMA operand read (8 consecutive k per lane) is one
+// 16-byte LDS read.  Each thread splits 8 consecutive k of one row or column
+// into the planes (three 16-byte LDS writes per 8 values):
+//   * A stored k-contiguous: four consecutive lanes read 64 contiguous bytes
+//     of each of two rows (16 rows per wave load instruction) and swap one
+//     16-byte half with the neighbouring lane, so each ends with one row's
+//     octet;
+//   * an operand stored with k as the row index (A when transposed, and B):
+//     a thread takes a pair of adjacent columns and one octet of k, eight
+//     8-byte loads contiguous across the wave (A on waves 0-3, B on waves
+//     4-7); the transposition into k-contiguous LDS rows comes with the split.
+// FULL (every tile and k-step inside the matrices): no bounds checks, and
+// the loads address a wave-uniform base in scalar registers plus a 32-bit
+// lane offset, so the step's vector ALU work is the split itself.
+typedef __bf16 xbf16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 xbf16x8 __attribute__((ext_vector_type(8)));
+typedef float xf32x2 __attribute__((ext_vector_type(2)));
+typedef float xf32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void split3(const float* v, uint4& p0, uint4& p1, uint4& p2) {
+    uint32_t w0[4], w1[4], w2[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const xf32x2 x = {v[2 * i], v[2 * i + 1]};
+        const xbf16x2 h0 = __builtin_convertvector(x, xbf16x2);
+        const xf32x2 r1 = x - __builtin_convertvector(h0, xf32x2);
+        const xbf16x2 h1 = __builtin_convertvector(r1, xbf16x2);
+        const xf32x2 r2 = r1 - __builtin_convertvector(h1, xf32x2);
+        const xbf16x2 h2 = __builtin_convertvector(r2, xbf16x2);
+        w0[i] = __builtin_bit_cast(uint32_t, h0);
+        w1[i] = __builtin_bit_cast(uint32_t, h1);
+        w2[i] = __builtin_bit_cast(uint32_t, h2);
+    }
+    p0 = make_uint4(w0[0], w0[1], w0[2], w0[3]);
+    p1 = make_uint4(w1[0], w1[1], w1[2], w1[3]);
+    p2 = make_uint4(w2[0], w2[1], w2[2], w2[3]);
+}
+
+// A wave-uniform global address, moved to scalar registers (kept in the
+// global address space, so its loads are global loads, not FLAT ones that
+// the LDS wait counter would also have to wait for).
+typedef const __attribute__((address_space(1))) char* gchar_ptr;
+__device__ __forceinline__ gchar_ptr uniform_ptr(const void* p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return reinterpret_cast<gchar_ptr>(((uint64_t)hi << 32) | lo);
+}
+
+// The largest leading dimension (floats) the FULL kernels address with
+// 32-bit lane offsets (8 rows of it, and 32 rows of A not transposed).
+constexpr int64_t kXFullMaxLd = (int64_t)1 << 25;
+
+template <bool TA, int EPI, bool FULL, int BN>
+__global__ __launch_bounds__(512) void k_xgemm(const GemmArgs g) {
+    static_assert(BN == 256 || BN == 128, "tile width");
+    constexpr int BM = 256, BK = 16, NT = 512, WM = BN == 256 ? 2 : 4, WN = 8 / WM;
+    constexpr int WTM = BM / WM, WTN = BN / WN;
+    constexpr int TM = WTM / 32, TN = WTN / 32;
+    constexpr int ROW = 24;                         // bf16 per LDS row: 16 k + 8 padding (48 bytes)
+    constexpr int PA = BM * ROW, PB = BN * ROW;     // one plane
+    constexpr int STAGE = 3 * PA + 3 * PB;          // one buffer: three A planes, three B planes
+    static_assert(EPI == EPI_STORE || EPI == EPI_STORE_SQA || EPI == kResidLate || EPI == EPI_RESID ||
+                      EPI == EPI_ADD_DOT, "epilogue");
+    __shared__ __attribute__((aligned(16))) uint16_t lds[2 * STAGE];
+    __shared__ double red[NT / 64];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 31, h = lane >> 5;
+    const int wm = wave % WM, wn = wave / WM;
+    int64_t mtile, ntile;
+    tile_of(g, mtile, ntile);
+    const int64_t m0 = mtile * BM, n0 = ntile * BN;
+    const int64_t kbeg = (int64_t)blockIdx.z * g.kchunk;
+    const int64_t kend = g.K < kbeg + g.kchunk ? g.K : kbeg + g.kchunk;
+
+    f32x16 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+
+    // A not transposed: lanes 4j .. 4j+3 of wave w read rows w*32 + 2j and
+    // w*32 + 2j + 1 at k-quad lane & 3; afterwards the lane holds row
+    // w*32 + 2j + (lane & 1), octet (lane >> 1) & 1.
+    const int xg = lane >> 2, xe = lane & 1, xo = (lane >> 1) & 1;
+    // k-row-major operands, W columns wide: unit u = 64 (wave - first wave)
+    // + lane is column pair u % (W/2), octet u / (W/2).  A when transposed on
+    // waves 0-3; B on the BN/64 waves from wave 4
+    const bool bwave = wave >= 4 && wave < 4 + BN / 64;
+    const int uu = 64 * (bwave ? wave - 4 : wave) + lane;
+    const int uw = bwave ? BN / 2 : BM / 2;
+    const int cp = uu % uw, ko = uu / uw;
+    const bool xwave = !TA && wave < 8;     // A not transposed: waves 0-7 hold its 256 rows
+    const bool awave = TA && wave < 4;      // A transposed: units on waves 0-3
+    float pa[8], ku[16];
+
+    // FULL with a 128-wide tile: B's columns past N (a sketch width that is
+    // not a multiple of 128) are masked per lane; N is even, so a column
+    // pair is wholly inside or outside
+    auto load_units = [&](const float* base, int64_t ld, int64_t c0, int64_t ncols, int64_t k0) {
+        const int64_t gk = k0 + 8 * ko;
+        if constexpr (FULL) {
+            const gchar_ptr sb = uniform_ptr(base + gk * ld + c0);
+            const uint32_t voff = 8u * (uint32_t)cp, rstep = 4u * (uint32_t)ld;
+            const bool colok = BN == 256 || c0 + 2 * cp < ncols;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                xf32x2 x = {0.f, 0.f};
+                if (colok)
+                    x = *reinterpret_cast<const __attribute__((address_space(1))) xf32x2*>(sb + (t * rstep + voff));
+                ku[t] = x[0];
+                ku[8 + t] = x[1];
+            }
+        } else {
+            const int64_t gc = c0 + 2 * cp;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const float* q = base + (gk + t) * ld + gc;
+                const bool kin = gk + t < kend;
+                if (kin && gc + 1 < ncols) {
+                    const float2 x = *reinterpret_cast<const float2*>(q);
+                    ku[t] = x.x;
+                    ku[8 + t] = x.y;
+                } else {
+                    ku[t] = (kin && gc < ncols) ? q[0] : 0.f;
+                    ku[8 + t] = (kin && gc + 1 < ncols) ? q[1] : 0.f;
+                }
+            }
+        }
+    };
+    auto load = [&](int64_t k0) {
+        if (xwave) {
+            float4 l1, l2;
+            if constexpr (FULL) {
+                typedef const __attribute__((address_space(1))) xf32x4* gf4_ptr;
+                const gchar_ptr sb = uniform_ptr(g.A + (m0 + wave * 32) * g.lda + k0);
+                const uint32_t voff = (uint32_t)(2 * xg * g.lda + 4 * (lane & 3)) * 4u;
+                const xf32x4 v1 = *reinterpret_cast<gf4_ptr>(sb + voff);
+                const xf32x4 v2 = *reinterpret_cast<gf4_ptr>(sb + (voff + 4u * (uint32_t)g.lda));
+                l1 = make_float4(v1[0], v1[1], v1[2], v1[3]);
+                l2 = make_float4(v2[0], v2[1], v2[2], v2[3]);
+            } else {
+                const int64_t ra = m0 + wave * 32 + 2 * xg, gk = k0 + 4 * (lane & 3);
+                l1 = ld4(g.A + ra * g.lda + gk, ra < g.M, gk, kend);
+                l2 = ld4(g.A + (ra + 1) * g.lda + gk, ra + 1 < g.M, gk, kend);
+            }
+            // raw loads; the swap happens in store(), a step later
+            pa[0] = l1.x; pa[1] = l1.y; pa[2] = l1.z; pa[3] = l1.w;
+            pa[4] = l2.x; pa[5] = l2.y; pa[6] = l2.z; pa[7] = l2.w;
+        } else if (awave) {
+            load_units(g.A, g.lda, m0, g.M, k0);
+        }
+        if (bwave) load_units(g.B, g.ldb, n0, g.N, k0);
+    };
+    // EPI_STORE_SQA: the sum of squares of the A operand as it passes through
+    // (the workgroups of the first column of tiles load each element once)
+    constexpr bool kSqa = EPI == EPI_STORE_SQA && !TA;
+    const bool count_sq = kSqa && ntile == 0;
+    double sqa = 0.0;
+    auto put = [&](uint16_t* q, int plane_stride, const float* v) {
+        uint4 p0, p1, p2;
+        split3(v, p0, p1, p2);
+        *reinterpret_cast<uint4*>(q) = p0;
+        *reinterpret_cast<uint4*>(q + plane_stride) = p1;
+        *reinterpret_cast<uint4*>(q + 2 * plane_stride) = p2;
+    };
+    auto put_units = [&](uint16_t* q, int plane_stride) {
+        float v0[8], v1[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            v0[t] = ku[t];
+            v1[t] = ku[8 + t];
+        }
+        put(q, plane_stride, v0);
+        put(q + ROW, plane_stride, v1);
+    };
+    // counted: the step is a real one (the loop's last store repeats a step)
+    auto store = [&](int buf, bool counted) {
+        uint16_t* base = lds + buf * STAGE;
+        if (xwave) {
+            // even lanes keep their first row's quad and take the odd neighbour's,
+            // odd lanes give their first and keep their second row's (DPP quad
+            // permute 1 0 3 2: plain VALU, no LDS round trip)
+            float v[8];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const float snd = xe ? pa[t] : pa[4 + t];
+                const float rcv = __int_as_float(
+                    __builtin_amdgcn_mov_dpp(__float_as_int(snd), 0xB1, 0xF, 0xF, false));
+                v[t] = xe ? rcv : pa[t];
+                v[4 + t] = xe ? pa[4 + t] : rcv;
+            }
+            if (kSqa && count_sq && counted)
+#pragma unroll
+                for (int t = 0; t < 8; ++t) sqa = fma((double)v[t], (double)v[t], sqa);
+            put(base + (wave * 32 + 2 * xg + xe) * ROW + 8 * xo, PA, v);
+        } else if (awave) {
+            put_units(base + 2 * cp * ROW + 8 * ko, PA);
+        }
+        if (bwave) put_units(base + 3 * PA + 2 * cp * ROW + 8 * ko, PB);
+    };
+
+    int64_t k0 = kbeg;
+    int buf = 0;
+    if (k0 < kend) {
+        load(k0);
+        store(0, true);
+    }
+    __syncthreads();
+    for (; k0 < kend; k0 += BK) {
+        // the next step's operands (the last step reloads its own, which the
+        // idle buffer then receives unused: the loop body has no branch)
+        const bool more = k0 + BK < kend;
+        load(more ? k0 + BK : k0);
+        // keep the loads here, a whole step ahead of their use (left alone, the
+        // compiler sinks them next to the split and waits on them at once)
+        __builtin_amdgcn_sched_barrier(0);
+        const uint16_t* As = lds + buf * STAGE;
+        const uint16_t* Bs = As + 3 * PA;
+        auto fa = [&](int p, int i) {
+            return *reinterpret_cast<const xbf16x8*>(&As[p * PA + (wm * WTM + 32 * i + r) * ROW + 8 * h]);
+        };
+        auto fb = [&](int p, int j) {
+            return *reinterpret_cast<const xbf16x8*>(&Bs[p * PB + (wn * WTN + 32 * j + r) * ROW + 8 * h]);
+        };
+        // one plane pair over all TM x TN accumulators (consecutive MFMAs independent)
+        auto mfma_all = [&](const xbf16x8 (&a)[TM], const xbf16x8 (&b)[TN]) {
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        };
+        // the small terms first: a2 b0, a1 b1, a1 b0, then a0 (b2, b1, b0)
+        xbf16x8 b0[TN], b1[TN];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) b0[j] = fb(0, j);
+        {
+            xbf16x8 a2[TM];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) a2[i] = fa(2, i);
+            mfma_all(a2, b0);
+        }
+#pragma unroll
+        for (int j = 0; j < TN; ++j) b1[j] = fb(1, j);
+        {
+            xbf16x8 a1[TM];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) a1[i] = fa(1, i);
+            mfma_all(a1, b1);
+            mfma_all(a1, b0);
+        }
+        {
+            xbf16x8 a0[TM], b2[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) a0[i] = fa(0, i);
+#pragma unroll
+            for (int j = 0; j < TN; ++j) b2[j] = fb(2, j);
+            mfma_all(a0, b2);
+            mfma_all(a0, b1);
+            mfma_all(a0, b0);
+        }
+        // the other buffer was last read in the previous step, before the barrier
+        store(buf ^ 1, more);
+        __syncthreads();
+        buf ^= 1;
+    }
+
+    float* D = g.D + (int64_t)blockIdx.z * g.split_stride;
+    double wacc = 0.0;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int64_t row = m0 + wm * WTM + 32 * i + 8 * (v >> 2) + 4 * h + (v & 3);
+                const int64_t col = n0 + wn * WTN + 32 * j + r;
+                if (row < g.M && col < g.N) {
+                    const float x = acc[i][j][v];
+                    if (EPI == EPI_STORE || EPI == EPI_STORE_SQA) {
+                        D[row * g.ldd + col] = x;
+                    } else if (EPI == kResidLate || EPI == EPI_RESID) {
+                        const float e = g.X[row * g.ldx + col] - x;
+                        if (EPI == EPI_RESID) D[row * g.ldd + col] = e;
+                        wacc += (double)e * (double)e;
+                    } else {
+                        D[row * g.ldd + col] = g.X[row * g.ldx + col] + x;
+                        wacc += (double)x * (double)g.Y[row * g.ldy + col];
+                    }
+                }
+            }
+    if constexpr (EPI == EPI_STORE_SQA) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) sqa += __shfl_xor(sqa, o, 64);
+        if (lane == 0) red[wave] = sqa;
+        __syncthreads();
+        if (tid == 0) {
+            double s2 = 0.0;
+#pragma unroll
+            for (int w = 0; w < NT / 64; ++w) s2 += red[w];
+            g.wsum[blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z)] = s2;
+        }
+    } else if constexpr (EPI != EPI_STORE) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) wacc += __shfl_xor(wacc, o, 64);
+        if (lane == 0) red[wave] = wacc;
+        __syncthreads();
+        if (tid == 0) {
+            double s = 0.0;
+#pragma unroll
+            for (int w = 0; w < NT / 64; ++w) s += red[w];
+            g.wsum[blockIdx.x + (int64_t)gridDim.x * blockIdx.y] = s;
+        }
+    }
+}
+
 // D[row][col] = sum_s P[s][row][col] in the order s = 0, 1, ...
 __global__ __launch_bounds__(256) void k_splitk_reduce(const float* __restrict__ P, int splits, int64_t stride,
                                                        int64_t M, int64_t N, float* __restrict__ D, int64_t ldd) {
@@ -409,19 +746,44 @@ int64_t add_dot_blocks(int64_t M, int64_t N) {
 struct Cfg {
     int BM, BN;
 };
-constexpr Cfg kCfg[4] = {{128, 64}, {128, 128}, {128, 128}, {256, 128}};
+// Products large enough for the three-term BF16 split kernel (k_xgemm): the
+// 256 x 256 tile for N >= 256, the 256 x 128 tile for the sketch widths
+// 64 < N <= 128.
+bool split_bf16_pays(int64_t M, int64_t N, int64_t K) {
+    return M >= 256 && N >= 256 && K >= 256 && (double)M * (double)N * (double)K >= 8.0e9;
+}
+bool split_bf16_narrow_pays(int64_t M, int64_t N, int64_t K) {
+    return M >= 256 && N > 64 && N <= 128 && K >= 256 && (double)M * (double)N * (double)K >= 8.0e9;
+}
+// tile configuration of a product with a fused epilogue (the norm-only
+// residual, D = X - AB and D = X + AB; A not transposed)
+int resid_cfg(int epi, int64_t M, int64_t N, int64_t K) {
+    return (epi == EPI_RESID_NORM || epi == EPI_RESID || epi == EPI_ADD_DOT) && split_bf16_pays(M, N, K) ? 4 : 2;
+}
+constexpr Cfg kCfg[6] = {{128, 64}, {128, 128}, {128, 128}, {256, 128}, {256, 256}, {256, 128}};
 constexpr int kBK = 16;
 
 template <int CFG, bool TA, int EPI>
 hipError_t run(const GemmArgs& a, dim3 grid, hipStream_t st) {
-    if (CFG == 0)
+    if constexpr (CFG == 0)
         hipLaunchKernelGGL((k_sgemm<128, 64, kBK, 4, 1, TA, EPI>), grid, dim3(256), 0, st, a);
-    else if (CFG == 1)
+    else if constexpr (CFG == 1)
         hipLaunchKernelGGL((k_sgemm<128, 128, kBK, 4, 1, TA, EPI>), grid, dim3(256), 0, st, a);
-    else if (CFG == 2)
+    else if constexpr (CFG == 2)
         hipLaunchKernelGGL((k_sgemm<128, 128, kBK, 2, 2, TA, EPI>), grid, dim3(256), 0, st, a);
-    else
+    else if constexpr (CFG == 3)
         hipLaunchKernelGGL((k_sgemm<256, 128, kBK, 4, 2, TA, EPI>), grid, dim3(512), 0, st, a);
+    else if constexpr (CFG == 4) {
+        if (a.full)
+            hipLaunchKernelGGL((k_xgemm<TA, EPI, true, 256>), grid, dim3(512), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_xgemm<TA, EPI, false, 256>), grid, dim3(512), 0, st, a);
+    } else {
+        if (a.full)
+            hipLaunchKernelGGL((k_xgemm<TA, EPI, true, 128>), grid, dim3(512), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_xgemm<TA, EPI, false, 128>), grid, dim3(512), 0, st, a);
+    }
     return hipGetLastError();
 }
 
@@ -434,10 +796,12 @@ GemmPlan plan_sgemm(int64_t M, int64_t N, int64_t K, bool transA, bool allow_spl
     // (H = C^T A): 256 x 128 tiles of eight waves, so the long operand is streamed
     // half as often; the split-K target counts workgroups of eight waves
     if (transA && M > 128 && N > 128 && K >= 2048) p.cfg = 3;
+    if (split_bf16_pays(M, N, K)) p.cfg = 4;
+    if (split_bf16_narrow_pays(M, N, K)) p.cfg = 5;
     const int64_t tiles = ((M + kCfg[p.cfg].BM - 1) / kCfg[p.cfg].BM) * ((N + kCfg[p.cfg].BN - 1) / kCfg[p.cfg].BN);
-    const int64_t target = p.cfg == 3 ? 256 : 512;
+    const int64_t target = p.cfg >= 3 ? 256 : 512;
     int64_t splits = 1;
-    if (p.cfg == 3 && allow_split) {
+    if (p.cfg >= 3 && allow_split) {
         // one workgroup of eight waves fills a compute unit: pick the split
         // count that minimises (rounds of 256 workgroups) x (K per workgroup +
         // a fixed cost of about 64 K steps), so no round runs mostly empty
@@ -494,6 +858,7 @@ hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K,
     a.ldy = ldy;
     a.wsum = wsum;
     a.swz = 0;
+    a.full = false;
     if (p.splits > 1) {
         a.D = partial;
         a.ldd = N;
@@ -503,16 +868,21 @@ hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K,
         a.ldd = ldd;
         a.split_stride = 0;
     }
-    // the fused epilogues exist for the square tile only (a 256 x 128 residual
-    // tile measured slower: 202 us against 192 us for the residual A - C U at 8192 x 4096 x 256)
-    const int cfg = store_like ? p.cfg : 2;
+    // the fused epilogues run on the square FP32 tile (a 256 x 128 residual tile
+    // measured slower: 202 us against 192 us for the residual A - C U at 8192 x
+    // 4096 x 256), the norm-only residual of a large product on the split-BF16 tile
+    const int cfg = store_like ? p.cfg : resid_cfg(epi, M, N, K);
     const Cfg c = kCfg[cfg];
     a.tm = (M + c.BM - 1) / c.BM;
     a.tn = (N + c.BN - 1) / c.BN;
     dim3 grid((unsigned)a.tm, (unsigned)a.tn, (unsigned)p.splits);
     // XCD-compact tile order for the big square-tile products
-    if (cfg == 2 && a.tm % 64 == 0 && a.tn % 8 == 0) a.swz = 1;
+    if ((cfg == 2 || cfg == 4) && a.tm % 64 == 0 && a.tn % 8 == 0) a.swz = 1;
     if (a.swz) grid = dim3((unsigned)(a.tm * a.tn), 1, (unsigned)p.splits);
+    a.full = (cfg == 4 ? N % 256 == 0 : cfg == 5 && N % 2 == 0) && M % 256 == 0 && K % kBK == 0 &&
+             p.kchunk % kBK == 0 &&
+             lda <= kXFullMaxLd && ldb <= kXFullMaxLd && ((uintptr_t)A & 15) == 0 && ((uintptr_t)B & 15) == 0 &&
+             lda % 4 == 0 && ldb % 4 == 0;
     hipError_t e;
     switch (cfg * 100 + (transA ? 10 : 0) + epi) {
         case 0: e = run<0, false, EPI_STORE>(a, grid, st); break;
@@ -522,6 +892,15 @@ hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K,
         case 200: e = run<2, false, EPI_STORE>(a, grid, st); break;
         case 210: e = run<2, true, EPI_STORE>(a, grid, st); break;
         case 310: e = run<3, true, EPI_STORE>(a, grid, st); break;
+        case 400: e = run<4, false, EPI_STORE>(a, grid, st); break;
+        case 410: e = run<4, true, EPI_STORE>(a, grid, st); break;
+        case 404: e = run<4, false, EPI_STORE_SQA>(a, grid, st); break;
+        case 403: e = run<4, false, kResidLate>(a, grid, st); break;
+        case 401: e = run<4, false, EPI_RESID>(a, grid, st); break;
+        case 402: e = run<4, false, EPI_ADD_DOT>(a, grid, st); break;
+        case 500: e = run<5, false, EPI_STORE>(a, grid, st); break;
+        case 510: e = run<5, true, EPI_STORE>(a, grid, st); break;
+        case 504: e = run<5, false, EPI_STORE_SQA>(a, grid, st); break;
         case 4: e = run<0, false, EPI_STORE_SQA>(a, grid, st); break;
         case 104: e = run<1, false, EPI_STORE_SQA>(a, grid, st); break;
         case 204: e = run<2, false, EPI_STORE_SQA>(a, grid, st); break;
@@ -556,13 +935,18 @@ hipError_t launch_splitk_reduce(const GemmPlan& p, int64_t M, int64_t N, const f
 }
 
 int64_t resid_parts(int64_t M, int64_t N, int64_t K) {
-    (void)K;   // the residual epilogues always run on the square tile
+    const Cfg c = kCfg[resid_cfg(EPI_RESID_NORM, M, N, K)];
+    return ((M + c.BM - 1) / c.BM) * ((N + c.BN - 1) / c.BN);
+}
+
+int64_t resid_store_parts(int64_t M, int64_t N) {
     return ((M + kCfg[2].BM - 1) / kCfg[2].BM) * ((N + kCfg[2].BN - 1) / kCfg[2].BN);
 }
 
-int64_t add_dot_parts(const GemmPlan& p, int64_t M, int64_t N) {
+int64_t add_dot_parts(const GemmPlan& p, int64_t M, int64_t N, int64_t K) {
     if (p.splits > 1) return add_dot_blocks(M, N);
-    return ((M + kCfg[2].BM - 1) / kCfg[2].BM) * ((N + kCfg[2].BN - 1) / kCfg[2].BN);
+    const Cfg c = kCfg[resid_cfg(EPI_ADD_DOT, M, N, K)];
+    return ((M + c.BM - 1) / c.BM) * ((N + c.BN - 1) / c.BN);
 }
 
 hipError_t launch_sgemm_add_dot(const GemmPlan& p, int64_t M, int64_t N, int64_t K, bool transA, const float* A,

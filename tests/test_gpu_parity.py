@@ -313,6 +313,26 @@ def test_decompose_shapes(ctx, m, n, b, k, s, ragged, seed):
     _check_decompose(ctx, w, label="shape")
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_frob2_fused_in_split_bf16_sketch(ctx, precision):
+    # ||A||_F^2 is summed by the first FP32 pass over A (A Q), which at
+    # m l n >= 8e9 runs on the 256 x 128 split-BF16 tile: every element of A
+    # counted exactly once (the kernel's last step repeats a load that must
+    # not count twice)
+    from paper_1703_06065_amd import binding
+    m, n, l, k, s = 8192, 8192, 120, 100, 8
+    note(f"fused ||A||^2 through the split-BF16 sketch tile m={m} n={n} l={l} precision={precision}")
+    rng = np.random.default_rng(4242)
+    A = rng.standard_normal((m, n), dtype=np.float32)
+    offsets = np.arange(0, n + 1, 64, dtype=np.int64)
+    draws = rng.integers(0, 2 ** 63, size=s, dtype=np.int64).astype(np.uint64)
+    prec = binding.PREC_BF16 if precision == "bf16" else binding.PREC_FP32
+    res = ctx.decompose(dev(A), offsets, k, s, 5, draws, q=1, l=l, precision=prec)
+    want = float(np.sum(A.astype(np.float64) ** 2))
+    note(f"  frob2 gpu={res['frob2']:.17g} exact={want:.17g} rel={abs(res['frob2'] - want) / want:.2e}")
+    assert abs(res["frob2"] - want) <= 1e-12 * want
+
+
 def test_decompose_with_replacement(ctx):
     w = gen.small_case(400, 300, 10, 8, 12, seed=11, noise=1e-2)
     _check_decompose(ctx, w, replace=True, label="replace")
@@ -401,6 +421,29 @@ def test_fit_columns_widths(ctx, c):
     rng = np.random.default_rng(3000 + c)
     C = rng.standard_normal((m, c))
     A = C[:, : min(c, 40)] @ rng.standard_normal((min(c, 40), n)) + 0.1 * rng.standard_normal((m, n))
+    A = A.astype(np.float32)
+    C = C.astype(np.float32)
+    U, err, flags = ctx.fit_columns(dev(A), dev(C), refine=1)
+    Uo, erro = O.fit_columns(A, C)
+    U = U.cpu().numpy().astype(np.float64)
+    cond = O.cond2(C)
+    rel_u = np.linalg.norm(U - Uo) / np.linalg.norm(Uo)
+    gate = u_gate(cond, erro, math.sqrt(O.frob2(A)), m)
+    note(f"  err={err:.9g} oracle={erro:.9g} rel_u={rel_u:.2e} gate={gate:.2e} cond={cond:.3g} flags={flags}")
+    assert abs(err - erro) <= err_tol(erro, O.frob2(A))
+    assert rel_u <= gate
+
+
+@pytest.mark.parametrize("m,n,c", [(4096, 4096, 512), (4100, 3900, 520)])
+def test_fit_columns_split_bf16_products(ctx, m, n, c):
+    # products of at least 8e9 multiply-adds (H = C^T A, ||A - C U||) run as
+    # six BF16 products of the exact three-term splits of their operands;
+    # whole 256 x 256 tiles take the path without bounds checks, a ragged
+    # shape the checked one.  Same gates as the FP32 products.
+    note(f"fit through the split-BF16 products m={m} n={n} c={c}")
+    rng = np.random.default_rng(m + n + c)
+    C = rng.standard_normal((m, c))
+    A = C[:, :60] @ rng.standard_normal((60, n)) + 0.05 * rng.standard_normal((m, n))
     A = A.astype(np.float32)
     C = C.astype(np.float32)
     U, err, flags = ctx.fit_columns(dev(A), dev(C), refine=1)
