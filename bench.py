@@ -549,8 +549,23 @@ def cpu_baseline_large(w, omega64, budget_fit_cols=(128, 256)):
 # same counter's reading for the plain 1 GiB copy of `bench.py --mode copy`.
 # The readings hold for the kernel source whose hash is stored beside them; a
 # changed source reports traffic None until the counters are taken again.
-TRAFFIC_LARGE = {}
-TRAFFIC_PLAIN = {}
+# 65536 x 16384 x 2048, rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) on
+# `bench.py --steps 1 --warmup 1 --no-cpu-baseline`; the 1 GiB copy reads
+# 524300 KiB of FETCH_SIZE (scale 2.0) and 1048576 KiB of WRITE_SIZE (1.0).
+TRAFFIC_LARGE = {
+    "fit_E": {"src": "c516bd288302aafb", "fetch_kib": 9071844.5, "fetch_scale": 1.9999, "write_kib": 515.5,
+              "write_scale": 1.0},
+    "fit_H": {"src": "c516bd288302aafb", "fetch_kib": 17318965.9, "fetch_scale": 1.9999, "write_kib": 131072.0,
+              "write_scale": 1.0},
+}
+# 8192 x 4096 x 256, the same counters on `bench.py --workload plain-fp32
+# --steps 3 --warmup 1 --no-cpu-baseline` (scales from the same copy runs).
+TRAFFIC_PLAIN = {
+    "fit_E": {"src": "c516bd288302aafb", "fetch_kib": 90264.5, "fetch_scale": 1.9999, "write_kib": 16.0,
+              "write_scale": 1.0},
+    "fit_H": {"src": "c516bd288302aafb", "fetch_kib": 98433.7, "fetch_scale": 1.9999, "write_kib": 65536.0,
+              "write_scale": 1.0},
+}
 
 
 def _source_hash():
