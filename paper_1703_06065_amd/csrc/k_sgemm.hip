@@ -344,10 +344,12 @@ __device__ __forceinline__ gchar_ptr uniform_ptr(const void* p) {
 // 32-bit lane offsets (8 rows of it, and 32 rows of A not transposed).
 constexpr int64_t kXFullMaxLd = (int64_t)1 << 25;
 
-template <bool TA, int EPI, bool FULL, int BN>
-__global__ __launch_bounds__(512) void k_xgemm(const GemmArgs g) {
-    static_assert(BN == 256 || BN == 128, "tile width");
-    constexpr int BM = 256, BK = 16, NT = 512, WM = BN == 256 ? 2 : 4, WN = 8 / WM;
+template <bool TA, int EPI, bool FULL, int BM, int BN>
+__global__ __launch_bounds__(BM * 2) void k_xgemm(const GemmArgs g) {
+    static_assert((BM == 256 && (BN == 256 || BN == 128)) || (BM == 128 && BN == 128), "tile shape");
+    // eight waves for 256 rows (128 x 64 or 64 x 64 per wave), four for 128 (64 x 64)
+    constexpr int NW = BM / 32, BK = 16, NT = 64 * NW;
+    constexpr int WM = BM == 256 && BN == 256 ? 2 : (BM == 256 ? 4 : 2), WN = NW / WM;
     constexpr int WTM = BM / WM, WTN = BN / WN;
     constexpr int TM = WTM / 32, TN = WTN / 32;
     constexpr int ROW = 24;                         // bf16 per LDS row: 16 k + 8 padding (48 bytes)
@@ -381,13 +383,14 @@ __global__ __launch_bounds__(512) void k_xgemm(const GemmArgs g) {
     const int xg = lane >> 2, xe = lane & 1, xo = (lane >> 1) & 1;
     // k-row-major operands, W columns wide: unit u = 64 (wave - first wave)
     // + lane is column pair u % (W/2), octet u / (W/2).  A when transposed on
-    // waves 0-3; B on the BN/64 waves from wave 4
-    const bool bwave = wave >= 4 && wave < 4 + BN / 64;
-    const int uu = 64 * (bwave ? wave - 4 : wave) + lane;
+    // the first BM/64 waves; B on the last BN/64
+    constexpr int WB0 = NW - BN / 64;
+    const bool bwave = wave >= WB0;
+    const int uu = 64 * (bwave ? wave - WB0 : wave) + lane;
     const int uw = bwave ? BN / 2 : BM / 2;
     const int cp = uu % uw, ko = uu / uw;
-    const bool xwave = !TA && wave < 8;     // A not transposed: waves 0-7 hold its 256 rows
-    const bool awave = TA && wave < 4;      // A transposed: units on waves 0-3
+    const bool xwave = !TA;                   // A not transposed: every wave holds 32 of its rows
+    const bool awave = TA && wave < BM / 64;  // A transposed: units on the first BM/64 waves
     float pa[8], ku[16];
 
     // FULL with a 128-wide tile: B's columns past N (a sketch width that is
@@ -760,7 +763,10 @@ bool split_bf16_narrow_pays(int64_t M, int64_t N, int64_t K) {
 int resid_cfg(int epi, int64_t M, int64_t N, int64_t K) {
     return (epi == EPI_RESID_NORM || epi == EPI_RESID || epi == EPI_ADD_DOT) && split_bf16_pays(M, N, K) ? 4 : 2;
 }
-constexpr Cfg kCfg[6] = {{128, 64}, {128, 128}, {128, 128}, {256, 128}, {256, 256}, {256, 128}};
+constexpr Cfg kCfg[7] = {{128, 64}, {128, 128}, {128, 128}, {256, 128}, {256, 256}, {256, 128}, {128, 128}};
+// The narrow split-BF16 tile: 5 (256 x 128, one workgroup per CU) or 6
+// (128 x 128, two per CU).
+constexpr int kXNarrow = 6;
 constexpr int kBK = 16;
 
 template <int CFG, bool TA, int EPI>
@@ -775,14 +781,19 @@ hipError_t run(const GemmArgs& a, dim3 grid, hipStream_t st) {
         hipLaunchKernelGGL((k_sgemm<256, 128, kBK, 4, 2, TA, EPI>), grid, dim3(512), 0, st, a);
     else if constexpr (CFG == 4) {
         if (a.full)
-            hipLaunchKernelGGL((k_xgemm<TA, EPI, true, 256>), grid, dim3(512), 0, st, a);
+            hipLaunchKernelGGL((k_xgemm<TA, EPI, true, 256, 256>), grid, dim3(512), 0, st, a);
         else
-            hipLaunchKernelGGL((k_xgemm<TA, EPI, false, 256>), grid, dim3(512), 0, st, a);
+            hipLaunchKernelGGL((k_xgemm<TA, EPI, false, 256, 256>), grid, dim3(512), 0, st, a);
+    } else if constexpr (CFG == 5) {
+        if (a.full)
+            hipLaunchKernelGGL((k_xgemm<TA, EPI, true, 256, 128>), grid, dim3(512), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_xgemm<TA, EPI, false, 256, 128>), grid, dim3(512), 0, st, a);
     } else {
         if (a.full)
-            hipLaunchKernelGGL((k_xgemm<TA, EPI, true, 128>), grid, dim3(512), 0, st, a);
+            hipLaunchKernelGGL((k_xgemm<TA, EPI, true, 128, 128>), grid, dim3(256), 0, st, a);
         else
-            hipLaunchKernelGGL((k_xgemm<TA, EPI, false, 128>), grid, dim3(512), 0, st, a);
+            hipLaunchKernelGGL((k_xgemm<TA, EPI, false, 128, 128>), grid, dim3(256), 0, st, a);
     }
     return hipGetLastError();
 }
@@ -797,19 +808,21 @@ GemmPlan plan_sgemm(int64_t M, int64_t N, int64_t K, bool transA, bool allow_spl
     // half as often; the split-K target counts workgroups of eight waves
     if (transA && M > 128 && N > 128 && K >= 2048) p.cfg = 3;
     if (split_bf16_pays(M, N, K)) p.cfg = 4;
-    if (split_bf16_narrow_pays(M, N, K)) p.cfg = 5;
+    if (split_bf16_narrow_pays(M, N, K)) p.cfg = kXNarrow;
     const int64_t tiles = ((M + kCfg[p.cfg].BM - 1) / kCfg[p.cfg].BM) * ((N + kCfg[p.cfg].BN - 1) / kCfg[p.cfg].BN);
     const int64_t target = p.cfg >= 3 ? 256 : 512;
     int64_t splits = 1;
     if (p.cfg >= 3 && allow_split) {
-        // one workgroup of eight waves fills a compute unit: pick the split
-        // count that minimises (rounds of 256 workgroups) x (K per workgroup +
-        // a fixed cost of about 64 K steps), so no round runs mostly empty
+        // a workgroup of eight waves fills a compute unit (two of the 128 x 128
+        // split tile's four): pick the split count that minimises (rounds of
+        // resident workgroups) x (K per workgroup + a fixed cost of about 64 K
+        // steps), so no round runs mostly empty
+        const int64_t round = p.cfg == 6 ? 512 : 256;
         const int64_t maxs = std::max<int64_t>(1, K / (4 * kBK));
         int64_t best = -1;
         for (int64_t s = 1; s <= maxs; ++s) {
             const int64_t kc = ((K + s - 1) / s + kBK - 1) / kBK * kBK;
-            const int64_t cost = ((tiles * s + 255) / 256) * (kc + 64);
+            const int64_t cost = ((tiles * s + round - 1) / round) * (kc + 64);
             if (best < 0 || cost < best) {
                 best = cost;
                 splits = s;
@@ -879,7 +892,8 @@ hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K,
     // XCD-compact tile order for the big square-tile products
     if ((cfg == 2 || cfg == 4) && a.tm % 64 == 0 && a.tn % 8 == 0) a.swz = 1;
     if (a.swz) grid = dim3((unsigned)(a.tm * a.tn), 1, (unsigned)p.splits);
-    a.full = (cfg == 4 ? N % 256 == 0 : cfg == 5 && N % 2 == 0) && M % 256 == 0 && K % kBK == 0 &&
+    a.full = (cfg == 4 ? N % 256 == 0 : (cfg == 5 || cfg == 6) && N % 2 == 0) && M % kCfg[cfg].BM == 0 &&
+             K % kBK == 0 &&
              p.kchunk % kBK == 0 &&
              lda <= kXFullMaxLd && ldb <= kXFullMaxLd && ((uintptr_t)A & 15) == 0 && ((uintptr_t)B & 15) == 0 &&
              lda % 4 == 0 && ldb % 4 == 0;
@@ -901,6 +915,9 @@ hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K,
         case 500: e = run<5, false, EPI_STORE>(a, grid, st); break;
         case 510: e = run<5, true, EPI_STORE>(a, grid, st); break;
         case 504: e = run<5, false, EPI_STORE_SQA>(a, grid, st); break;
+        case 600: e = run<6, false, EPI_STORE>(a, grid, st); break;
+        case 610: e = run<6, true, EPI_STORE>(a, grid, st); break;
+        case 604: e = run<6, false, EPI_STORE_SQA>(a, grid, st); break;
         case 4: e = run<0, false, EPI_STORE_SQA>(a, grid, st); break;
         case 104: e = run<1, false, EPI_STORE_SQA>(a, grid, st); break;
         case 204: e = run<2, false, EPI_STORE_SQA>(a, grid, st); break;
