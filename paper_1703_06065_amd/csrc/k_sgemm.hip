@@ -343,6 +343,7 @@ __device__ __forceinline__ gchar_ptr uniform_ptr(const void* p) {
 // The largest leading dimension (floats) the FULL kernels address with
 // 32-bit lane offsets (8 rows of it, and 32 rows of A not transposed).
 constexpr int64_t kXFullMaxLd = (int64_t)1 << 25;
+constexpr bool kXBCol = true;
 
 template <bool TA, int EPI, bool FULL, int BM, int BN>
 __global__ __launch_bounds__(BM * 2) void k_xgemm(const GemmArgs g) {
@@ -385,13 +386,21 @@ __global__ __launch_bounds__(BM * 2) void k_xgemm(const GemmArgs g) {
     // + lane is column pair u % (W/2), octet u / (W/2).  A when transposed on
     // the first BM/64 waves; B on the last BN/64
     constexpr int WB0 = NW - BN / 64;
-    const bool bwave = wave >= WB0;
+    // With A not transposed every wave already stages A, so B is staged one
+    // column per thread (column u % BN, octet u / BN for u = tid < 2 BN, eight
+    // 4-byte loads contiguous across the wave) and spread over all the waves;
+    // column pairs on the last waves only would give those waves three times
+    // the staging work of the others, and the rest would wait at each barrier.
+    constexpr bool BCOL = !TA && kXBCol;
+    const bool bwave = !BCOL && wave >= WB0;
+    const bool bcol = BCOL && tid < 2 * BN;
+    const int bcc = tid % BN, bco = tid / BN;
     const int uu = 64 * (bwave ? wave - WB0 : wave) + lane;
     const int uw = bwave ? BN / 2 : BM / 2;
     const int cp = uu % uw, ko = uu / uw;
     const bool xwave = !TA;                   // A not transposed: every wave holds 32 of its rows
     const bool awave = TA && wave < BM / 64;  // A transposed: units on the first BM/64 waves
-    float pa[8], ku[16];
+    float pa[8], ku[16], pb[8];
 
     // FULL with a 128-wide tile: B's columns past N (a sketch width that is
     // not a multiple of 128) are masked per lane; N is even, so a column
@@ -450,6 +459,23 @@ __global__ __launch_bounds__(BM * 2) void k_xgemm(const GemmArgs g) {
             load_units(g.A, g.lda, m0, g.M, k0);
         }
         if (bwave) load_units(g.B, g.ldb, n0, g.N, k0);
+        if (bcol) {
+            const int64_t gk = k0 + 8 * bco, gn = n0 + bcc;
+            if constexpr (FULL) {
+                const gchar_ptr sb = uniform_ptr(g.B + gk * g.ldb + n0);
+                const uint32_t voff = 4u * (uint32_t)bcc, rstep = 4u * (uint32_t)g.ldb;
+                const bool colok = BN == 256 || gn < g.N;
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    float x = 0.f;
+                    if (colok) x = *reinterpret_cast<const __attribute__((address_space(1))) float*>(sb + (t * rstep + voff));
+                    pb[t] = x;
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < 8; ++t) pb[t] = (gn < g.N && gk + t < kend) ? g.B[(gk + t) * g.ldb + gn] : 0.f;
+            }
+        }
     };
     // EPI_STORE_SQA: the sum of squares of the A operand as it passes through
     // (the workgroups of the first column of tiles load each element once)
@@ -497,6 +523,7 @@ __global__ __launch_bounds__(BM * 2) void k_xgemm(const GemmArgs g) {
             put_units(base + 2 * cp * ROW + 8 * ko, PA);
         }
         if (bwave) put_units(base + 3 * PA + 2 * cp * ROW + 8 * ko, PB);
+        if (bcol) put(base + 3 * PA + bcc * ROW + 8 * bco, PB, pb);
     };
 
     int64_t k0 = kbeg;
