@@ -1,5 +1,5 @@
 // FP64 dense kernels for the c x c normal-equation matrix G = C^T C of the
-// fit: a tiled FP64 GEMM, and G^-1 by a blocked right-looking Cholesky
+// fit: a tiled FP64 GEMM on the FP64 matrix cores, and G^-1 by a blocked right-looking Cholesky
 // (64-wide panels factored in LDS), a blocked triangular inverse computed
 // recursively (both halves, then the coupling block, one level of the
 // recursion per pair of launches), and Ginv = L^-T L^-1.
@@ -15,13 +15,32 @@ constexpr int NB = 64;   // panel width and GEMM tile
 constexpr int KB = 16;   // GEMM k step
 constexpr int kFullChol = 256;   // largest c factored by one workgroup
 
-// acc (thread's 4x4 at rows ty + 16 i, cols tx + 16 j of a 64x64 tile) +=
-// op(A)[0:M, 0:K] op(B)[0:K, 0:N]; A, B point at the tile's origin.
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+// One 64 x 64 FP64 tile product per workgroup of 256 threads: acc += op(A)[0:M,
+// 0:K] op(B)[0:K, 0:N] (A, B point at the tile's origin), staged through LDS
+// 16 k at a time.  On the FP64 matrix cores (v_mfma_f64_16x16x4f64: lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16]; register v of the result
+// is D[4 v + l / 16][l % 16]), each wave a 32 x 32 quarter as 2 x 2 MFMA tiles.
+// Element e = 4 (2 i + j) + v of a thread's 16 is at tile_row(e), tile_col(e).
+struct FTile {
+    d4v t[2][2];
+};
+__device__ __forceinline__ int tile_row(int e) {
+    const int lane = threadIdx.x & 63, wy = (threadIdx.x >> 6) >> 1;
+    return 32 * wy + 16 * (e >> 3) + 4 * (e & 3) + (lane >> 4);
+}
+__device__ __forceinline__ int tile_col(int e) {
+    const int lane = threadIdx.x & 63, wx = (threadIdx.x >> 6) & 1;
+    return 32 * wx + 16 * ((e >> 2) & 1) + (lane & 15);
+}
+__device__ __forceinline__ double tile_get(const FTile& a, int e) { return a.t[e >> 3][(e >> 2) & 1][e & 3]; }
+
 template <bool TA, bool TB, typename TAe = double, typename TBe = double>
-__device__ __forceinline__ void tile_mm(double (&acc)[4][4], const TAe* __restrict__ A, int64_t lda,
+__device__ __forceinline__ void tile_mm(FTile& acc, const TAe* __restrict__ A, int64_t lda,
                                         const TBe* __restrict__ B, int64_t ldb, int64_t M, int64_t N, int64_t K,
                                         double* As, double* Bs) {
-    const int tid = threadIdx.x, ty = tid / 16, tx = tid % 16;
+    const int tid = threadIdx.x, lane = tid & 63, wy = (tid >> 6) >> 1, wx = (tid >> 6) & 1;
     for (int64_t k0 = 0; k0 < K; k0 += KB) {
         __syncthreads();
         for (int e = tid; e < NB * KB; e += 256) {
@@ -53,17 +72,19 @@ __device__ __forceinline__ void tile_mm(double (&acc)[4][4], const TAe* __restri
             Bs[kk * (NB + 1) + col] = v;
         }
         __syncthreads();
-#pragma unroll 4
-        for (int kk = 0; kk < KB; ++kk) {
-            double a[4], b[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = As[kk * (NB + 1) + ty + 16 * i];
+        for (int kk = 0; kk < KB; kk += 4) {
+            const int kr = (kk + (lane >> 4)) * (NB + 1);
+            double a[2], b[2];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = Bs[kk * (NB + 1) + tx + 16 * j];
+            for (int i = 0; i < 2; ++i) a[i] = As[kr + 32 * wy + 16 * i + (lane & 15)];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 2; ++j) b[j] = Bs[kr + 32 * wx + 16 * j + (lane & 15)];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc.t[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc.t[i][j], 0, 0, 0);
         }
     }
 }
@@ -77,21 +98,18 @@ __global__ __launch_bounds__(256) void k_dgemm(int64_t M, int64_t N, int64_t K, 
                                                double* D, int64_t ldd) {
     __shared__ double As[KB * (NB + 1)], Bs[KB * (NB + 1)];
     const int64_t m0 = (int64_t)blockIdx.x * NB, n0 = (int64_t)blockIdx.y * NB;
-    double acc[4][4] = {};
+    FTile acc = {};
     const TAe* Ab = TA ? A + m0 : A + m0 * lda;
     const TBe* Bb = TB ? B + n0 * ldb : B + n0;
     tile_mm<TA, TB, TAe, TBe>(acc, Ab, lda, Bb, ldb, M - m0, N - n0, K, As, Bs);
-    const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t row = m0 + ty + 16 * i, col = n0 + tx + 16 * j;
-            if (row < M && col < N) {
-                const double v = alpha * acc[i][j];
-                D[row * ldd + col] = beta == 0.0 ? v : v + beta * D[row * ldd + col];
-            }
+    for (int e = 0; e < 16; ++e) {
+        const int64_t row = m0 + tile_row(e), col = n0 + tile_col(e);
+        if (row < M && col < N) {
+            const double v = alpha * tile_get(acc, e);
+            D[row * ldd + col] = beta == 0.0 ? v : v + beta * D[row * ldd + col];
         }
+    }
 }
 
 __global__ __launch_bounds__(256) void k_maxdiag(const double* __restrict__ G, int64_t c, double* __restrict__ out) {
@@ -167,7 +185,6 @@ __global__ __launch_bounds__(64) void k_potrf_diag(const double* __restrict__ G,
 //   C  every other tile below row J takes the rank-16 update
 //      -= L21_I [X_J | L21^T]_C.
 // Padding beyond c is the identity, so it never couples to the matrix.
-typedef double d4v __attribute__((ext_vector_type(4)));
 constexpr int kMT = 16;      // tiles per side
 constexpr int kMW = 8;       // waves
 constexpr int kMSlots = 17;  // lower tiles per wave: ceil(136 / 8)
@@ -379,24 +396,21 @@ __global__ __launch_bounds__(256) void k_trtri_level(const double* __restrict__ 
     if (tm0 >= rows || tn0 >= cols) return;
     const int64_t ldt = h * NB;
     double* Tz = T + z * ldt * ldt;
-    double acc[4][4] = {};
+    FTile acc = {};
     if (PASS == 0)
         tile_mm<false, false>(acc, L + (r0 + tm0) * c + c0 + tn0, c, X + (c0 + tn0) * c + c0 + tn0, c, rows - tm0,
                               cols - tn0, cols - tn0, As, Bs);
     else
         tile_mm<false, false>(acc, X + (r0 + tm0) * c + r0, c, Tz + tn0, ldt, rows - tm0, cols - tn0,
                               rows < tm0 + NB ? rows : tm0 + NB, As, Bs);
-    const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t row = tm0 + ty + 16 * i, col = tn0 + tx + 16 * j;
-            if (row < rows && col < cols) {
-                if (PASS == 0) Tz[row * ldt + col] = acc[i][j];
-                else X[(r0 + row) * c + c0 + col] = -acc[i][j];
-            }
+    for (int e = 0; e < 16; ++e) {
+        const int64_t row = tm0 + tile_row(e), col = tn0 + tile_col(e);
+        if (row < rows && col < cols) {
+            if (PASS == 0) Tz[row * ldt + col] = tile_get(acc, e);
+            else X[(r0 + row) * c + c0 + col] = -tile_get(acc, e);
         }
+    }
 }
 
 // Doubles of the recursive inverse's T buffer: the largest level's nodes x (h NB)^2.
