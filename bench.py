@@ -34,10 +34,12 @@ SPLIT_BF16_PRODUCTS = 6
 def split_bf16(M, N, K):
     """Whether the library forms an M x N x K FP32 product from the three-term
     BF16 splits of its operands (the rule stated with BCUR_PREC_FP32 in
-    include/bcur.h): at least 8e9 multiply-adds, M, K >= 256, and N >= 256 or
-    64 < N <= 128."""
-    wide = N >= 256 or 64 < N <= 128
-    return M >= 256 and K >= 256 and wide and float(M) * N * K >= 8.0e9
+    include/bcur.h): M, K >= 256, and N >= 256 with at least 8e9
+    multiply-adds, or 32 < N <= 128 with at least 1e9."""
+    if M < 256 or K < 256:
+        return False
+    mnk = float(M) * N * K
+    return (N >= 256 and mnk >= 8.0e9) or (32 < N <= 128 and mnk >= 1.0e9)
 
 
 def mfma_roofline(M, N, K, avg_ms, kernel_fp32, kernel_split, **extra):

@@ -58,8 +58,9 @@ typedef enum bcur_status {
  *
  * FP32 products (every product of BCUR_PREC_FP32, the fit, and the last
  * power pass of BCUR_PREC_BF16) accumulate in FP32.  Small products run on
- * the FP32 matrix cores.  Products of at least 8e9 multiply-adds with
- * N >= 256, or 64 < N <= 128 (a sketch width), split each FP32 operand
+ * the FP32 matrix cores.  Products with M, K >= 256 and either N >= 256 and
+ * at least 8e9 multiply-adds, or a sketch width 32 < N <= 128 and at least
+ * 1e9, split each FP32 operand
  * exactly into three BF16 terms, a = a0 + a1 + a2, and form a b from the
  * six largest of the nine term products on the BF16 matrix cores.  The
  * three dropped terms are below 2^-23 |a b|, two FP32 unit roundoffs, which

@@ -347,10 +347,10 @@ constexpr bool kXBCol = true;
 
 template <bool TA, int EPI, bool FULL, int BM, int BN>
 __global__ __launch_bounds__(BM * 2) void k_xgemm(const GemmArgs g) {
-    static_assert((BM == 256 && (BN == 256 || BN == 128)) || (BM == 128 && BN == 128), "tile shape");
-    // eight waves for 256 rows (128 x 64 or 64 x 64 per wave), four for 128 (64 x 64)
+    static_assert((BM == 256 && BN == 256) || (BM == 128 && (BN == 128 || BN == 64)), "tile shape");
+    // eight waves for 256 rows (128 x 64 per wave), four for 128 (64 x 64 or 64 x 32)
     constexpr int NW = BM / 32, BK = 16, NT = 64 * NW;
-    constexpr int WM = BM == 256 && BN == 256 ? 2 : (BM == 256 ? 4 : 2), WN = NW / WM;
+    constexpr int WM = 2, WN = NW / WM;
     constexpr int WTM = BM / WM, WTN = BN / WN;
     constexpr int TM = WTM / 32, TN = WTN / 32;
     constexpr int ROW = 24;                         // bf16 per LDS row: 16 k + 8 padding (48 bytes)
@@ -391,10 +391,14 @@ __global__ __launch_bounds__(BM * 2) void k_xgemm(const GemmArgs g) {
     // 4-byte loads contiguous across the wave) and spread over all the waves;
     // column pairs on the last waves only would give those waves three times
     // the staging work of the others, and the rest would wait at each barrier.
-    constexpr bool BCOL = !TA && kXBCol;
+    // (A 64-wide B is always staged by columns: as column pairs it would not
+    // fill a wave per octet.  With A transposed its columns go on the last
+    // 2 BN / 64 waves, after A's units.)
+    constexpr bool BCOL = (!TA && kXBCol) || BN == 64;
+    constexpr int BC0 = TA ? NT - 2 * BN : 0;
     const bool bwave = !BCOL && wave >= WB0;
-    const bool bcol = BCOL && tid < 2 * BN;
-    const int bcc = tid % BN, bco = tid / BN;
+    const bool bcol = BCOL && tid >= BC0 && tid < BC0 + 2 * BN;
+    const int bcc = (tid - BC0) % BN, bco = (tid - BC0) / BN;
     const int uu = 64 * (bwave ? wave - WB0 : wave) + lane;
     const int uw = bwave ? BN / 2 : BM / 2;
     const int cp = uu % uw, ko = uu / uw;
@@ -777,23 +781,28 @@ struct Cfg {
     int BM, BN;
 };
 // Products large enough for the three-term BF16 split kernel (k_xgemm): the
-// 256 x 256 tile for N >= 256, the 256 x 128 tile for the sketch widths
-// 64 < N <= 128.
+// 256 x 256 tile for N >= 256 (at least 8e9 multiply-adds), the 128 x 128
+// tile for the sketch widths 64 < N <= 128 and the 128 x 64 tile for
+// 32 < N <= 64 (at least 1e9).
 bool split_bf16_pays(int64_t M, int64_t N, int64_t K) {
     return M >= 256 && N >= 256 && K >= 256 && (double)M * (double)N * (double)K >= 8.0e9;
 }
+constexpr double kXNarrowMin = 1.0e9;   // multiply-adds of the smallest narrow product on the split tiles
 bool split_bf16_narrow_pays(int64_t M, int64_t N, int64_t K) {
-    return M >= 256 && N > 64 && N <= 128 && K >= 256 && (double)M * (double)N * (double)K >= 8.0e9;
+    return M >= 256 && N > 64 && N <= 128 && K >= 256 && (double)M * (double)N * (double)K >= kXNarrowMin;
+}
+bool split_bf16_narrow64_pays(int64_t M, int64_t N, int64_t K) {
+    return M >= 256 && N > 32 && N <= 64 && K >= 256 && (double)M * (double)N * (double)K >= kXNarrowMin;
 }
 // tile configuration of a product with a fused epilogue (the norm-only
 // residual, D = X - AB and D = X + AB; A not transposed)
 int resid_cfg(int epi, int64_t M, int64_t N, int64_t K) {
     return (epi == EPI_RESID_NORM || epi == EPI_RESID || epi == EPI_ADD_DOT) && split_bf16_pays(M, N, K) ? 4 : 2;
 }
-constexpr Cfg kCfg[7] = {{128, 64}, {128, 128}, {128, 128}, {256, 128}, {256, 256}, {256, 128}, {128, 128}};
-// The narrow split-BF16 tile: 5 (256 x 128, one workgroup per CU) or 6
-// (128 x 128, two per CU).
-constexpr int kXNarrow = 6;
+// 0-3: FP32 MFMA tiles; 4, 6, 7: split-BF16 tiles (5, a 256 x 128 split tile of
+// eight waves, measured slower than 6 for the sketch widths, is not used)
+constexpr Cfg kCfg[8] = {{128, 64}, {128, 128}, {128, 128}, {256, 128}, {256, 256}, {256, 128}, {128, 128},
+                         {128, 64}};
 constexpr int kBK = 16;
 
 template <int CFG, bool TA, int EPI>
@@ -811,16 +820,16 @@ hipError_t run(const GemmArgs& a, dim3 grid, hipStream_t st) {
             hipLaunchKernelGGL((k_xgemm<TA, EPI, true, 256, 256>), grid, dim3(512), 0, st, a);
         else
             hipLaunchKernelGGL((k_xgemm<TA, EPI, false, 256, 256>), grid, dim3(512), 0, st, a);
-    } else if constexpr (CFG == 5) {
-        if (a.full)
-            hipLaunchKernelGGL((k_xgemm<TA, EPI, true, 256, 128>), grid, dim3(512), 0, st, a);
-        else
-            hipLaunchKernelGGL((k_xgemm<TA, EPI, false, 256, 128>), grid, dim3(512), 0, st, a);
-    } else {
+    } else if constexpr (CFG == 6) {
         if (a.full)
             hipLaunchKernelGGL((k_xgemm<TA, EPI, true, 128, 128>), grid, dim3(256), 0, st, a);
         else
             hipLaunchKernelGGL((k_xgemm<TA, EPI, false, 128, 128>), grid, dim3(256), 0, st, a);
+    } else {
+        if (a.full)
+            hipLaunchKernelGGL((k_xgemm<TA, EPI, true, 128, 64>), grid, dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_xgemm<TA, EPI, false, 128, 64>), grid, dim3(256), 0, st, a);
     }
     return hipGetLastError();
 }
@@ -835,7 +844,8 @@ GemmPlan plan_sgemm(int64_t M, int64_t N, int64_t K, bool transA, bool allow_spl
     // half as often; the split-K target counts workgroups of eight waves
     if (transA && M > 128 && N > 128 && K >= 2048) p.cfg = 3;
     if (split_bf16_pays(M, N, K)) p.cfg = 4;
-    if (split_bf16_narrow_pays(M, N, K)) p.cfg = kXNarrow;
+    if (split_bf16_narrow_pays(M, N, K)) p.cfg = 6;
+    if (split_bf16_narrow64_pays(M, N, K)) p.cfg = 7;
     const int64_t tiles = ((M + kCfg[p.cfg].BM - 1) / kCfg[p.cfg].BM) * ((N + kCfg[p.cfg].BN - 1) / kCfg[p.cfg].BN);
     const int64_t target = p.cfg >= 3 ? 256 : 512;
     int64_t splits = 1;
@@ -844,7 +854,7 @@ GemmPlan plan_sgemm(int64_t M, int64_t N, int64_t K, bool transA, bool allow_spl
         // split tile's four): pick the split count that minimises (rounds of
         // resident workgroups) x (K per workgroup + a fixed cost of about 64 K
         // steps), so no round runs mostly empty
-        const int64_t round = p.cfg == 6 ? 512 : 256;
+        const int64_t round = p.cfg >= 6 ? 512 : 256;
         const int64_t maxs = std::max<int64_t>(1, K / (4 * kBK));
         int64_t best = -1;
         for (int64_t s = 1; s <= maxs; ++s) {
@@ -919,7 +929,7 @@ hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K,
     // XCD-compact tile order for the big square-tile products
     if ((cfg == 2 || cfg == 4) && a.tm % 64 == 0 && a.tn % 8 == 0) a.swz = 1;
     if (a.swz) grid = dim3((unsigned)(a.tm * a.tn), 1, (unsigned)p.splits);
-    a.full = (cfg == 4 ? N % 256 == 0 : (cfg == 5 || cfg == 6) && N % 2 == 0) && M % kCfg[cfg].BM == 0 &&
+    a.full = (cfg == 4 ? N % 256 == 0 : cfg >= 5 && N % 2 == 0) && M % kCfg[cfg].BM == 0 &&
              K % kBK == 0 &&
              p.kchunk % kBK == 0 &&
              lda <= kXFullMaxLd && ldb <= kXFullMaxLd && ((uintptr_t)A & 15) == 0 && ((uintptr_t)B & 15) == 0 &&
@@ -939,12 +949,12 @@ hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K,
         case 403: e = run<4, false, kResidLate>(a, grid, st); break;
         case 401: e = run<4, false, EPI_RESID>(a, grid, st); break;
         case 402: e = run<4, false, EPI_ADD_DOT>(a, grid, st); break;
-        case 500: e = run<5, false, EPI_STORE>(a, grid, st); break;
-        case 510: e = run<5, true, EPI_STORE>(a, grid, st); break;
-        case 504: e = run<5, false, EPI_STORE_SQA>(a, grid, st); break;
         case 600: e = run<6, false, EPI_STORE>(a, grid, st); break;
         case 610: e = run<6, true, EPI_STORE>(a, grid, st); break;
         case 604: e = run<6, false, EPI_STORE_SQA>(a, grid, st); break;
+        case 700: e = run<7, false, EPI_STORE>(a, grid, st); break;
+        case 710: e = run<7, true, EPI_STORE>(a, grid, st); break;
+        case 704: e = run<7, false, EPI_STORE_SQA>(a, grid, st); break;
         case 4: e = run<0, false, EPI_STORE_SQA>(a, grid, st); break;
         case 104: e = run<1, false, EPI_STORE_SQA>(a, grid, st); break;
         case 204: e = run<2, false, EPI_STORE_SQA>(a, grid, st); break;

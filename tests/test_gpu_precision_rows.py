@@ -58,7 +58,10 @@ def bf16_round(x):
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-@pytest.mark.parametrize("m,n,l", [(300, 200, 20), (517, 1030, 60), (2048, 1024, 110)])
+# the last three take the split-BF16 sketch tiles (m l n >= 1e9): 128 x 64
+# on whole tiles, then 128 x 64 and 128 x 128 on ragged ones
+@pytest.mark.parametrize("m,n,l", [(300, 200, 20), (517, 1030, 60), (2048, 1024, 110), (8192, 4096, 60),
+                                   (8200, 4100, 60), (8200, 4100, 100)])
 def test_sketch_pass_fp32(ctx, m, n, l):
     from paper_1703_06065_amd.binding import PREC_FP32
     note(f"sketch fp32 m={m} n={n} l={l}")
