@@ -208,8 +208,8 @@ bcur_status bcur_gather_columns(bcur_ctx* ctx, const float* A, int64_t m, int64_
  * the FP32 normal equations are inaccurate (BCUR_FLAG_ILLCOND_C), the fit is
  * redone by Cholesky QR2 in FP64 (a basic least-squares solution on the
  * columns kept at 2^-50) and err is the exact residual of the returned U.
- * A: device m x n (lda).  C: device m x c (ldc).  U: device c x n (ldu),
- * written.  err: host double.  flags: host uint32 (BCUR_FLAG_*), or NULL.
+ * A: device m x n (lda).  C: device m x c (ldc).  U: device c x n (ldu);
+ * only those c x n elements are written.  err: host double.  flags: host uint32 (BCUR_FLAG_*), or NULL.
  * Synchronous. */
 bcur_status bcur_fit_columns(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda,
                              const float* C, int64_t c, int64_t ldc, int32_t refine,

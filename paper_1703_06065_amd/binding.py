@@ -434,10 +434,16 @@ class Context:
                                                ctypes.byref(c)))
         return C[:, :c.value]
 
-    def fit_columns(self, A, C, refine: int = 1):
+    def fit_columns(self, A, C, refine: int = 1, U_out=None):
+        """U = C^+ A (c x n) and err = ||A - C U||_F.  U_out: a c x n float32
+        view to write (any row stride); only its c x n elements are written."""
         p, m, n, lda = _check_dev(A, "A")
         pc, mc, c, ldc = _check_dev(C, "C")
-        U = padded_empty(c, n, A.device)
+        if U_out is not None:
+            _check_dev(U_out, "U_out")
+            if tuple(U_out.shape) != (c, n):
+                raise ValueError(f"U_out must be {c} x {n}")
+        U = U_out if U_out is not None else padded_empty(c, n, A.device)
         err = ctypes.c_double()
         fl = ctypes.c_uint32()
         self._chk(self.lib.bcur_fit_columns(self.h, p, m, n, lda, pc, c, ldc, refine, U.data_ptr(), U.stride(0),

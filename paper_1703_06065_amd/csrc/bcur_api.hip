@@ -549,7 +549,7 @@ bcur_status fit_run(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t m, 
         // its F = H - G U)
         double* Linv = nullptr;
         HIPCHK(launch_chol_linv(b.G, c, b.spdws, b.info, b.piv, ldexp(1.0, -24), &Linv, st));
-        HIPCHK(launch_f64_to_f32_2d(Linv, c, c, c, b.X32, cp, st));
+        HIPCHK(launch_f64_to_f32_2d(Linv, c, c, c, b.X32, cp, true, st));
         // G^-1 = X^T X (X is zero above its diagonal)
         const GemmPlan pi = plan_sgemm(c, c, c, true, true);
         HIPCHK(launch_sgemm(pi, c, c, c, true, b.X32, cp, b.X32, cp, b.Gi32, cp, b.part, EPI_STORE, nullptr, 0,
@@ -617,7 +617,7 @@ bcur_status fit_fallback64(bcur_ctx* ctx, const FitBufs& b, const float* A, int6
             HIPCHK(launch_dgemm(c, w, c, 1.0, L2inv, c, false, b.T1, w, false, 0.0, b.T2, w, st));       // L2^-1 .
             HIPCHK(launch_dgemm(c, w, c, 1.0, L2inv, c, true, b.T2, w, false, 0.0, b.T1, w, st));        // L2^-T .
             HIPCHK(launch_dgemm(c, w, c, 1.0, b.L1, c, true, b.T1, w, false, 0.0, b.T2, w, st));         // L1^-T .
-            HIPCHK(launch_f64_to_f32_2d(b.T2, c, w, w, U + j0, ldu, st));
+            HIPCHK(launch_f64_to_f32_2d(b.T2, c, w, w, U + j0, ldu, false, st));
         }
     }
     const GemmPlan pe = plan_sgemm(m, n, c, false, false);
@@ -753,8 +753,8 @@ bcur_status fit_cur_run(bcur_ctx* ctx, const CurBufs& b, const float* A, int64_t
         HIPCHK(launch_dgemm(c, r, c, 1.0, L1inv, c, true, b.T1, r, false, 0.0, b.U0, r, st));
         // W = C U = Q1 (L2^-T H2) = Q1 T1
         HIPCHK(launch_dgemm(m, r, c, 1.0, b.Q1, c, false, b.T1, r, false, 0.0, b.Wd, r, st));
-        HIPCHK(launch_f64_to_f32_2d(b.Wd, m, r, r, b.W32, rp, st));
-        if (U) HIPCHK(launch_f64_to_f32_2d(b.U0, c, r, r, U, ldu, st));
+        HIPCHK(launch_f64_to_f32_2d(b.Wd, m, r, r, b.W32, rp, true, st));
+        if (U) HIPCHK(launch_f64_to_f32_2d(b.U0, c, r, r, U, ldu, false, st));
     }
     const GemmPlan pe = plan_sgemm(m, n, r, false, false);
     STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_E, BCUR_STAGE_FIT_REDUCE, pe, m, n, r, false, b.W32, rp, b.R, ldr, nullptr,
@@ -2110,7 +2110,7 @@ static bcur_status alg1_impl(bcur_ctx* ctx, const float* A, int64_t m, int64_t n
     {
         StageScope ts(ctx, BCUR_STAGE_A1_CU);
         HIPCHK(launch_dgemm_ff(m, r, c, 1.0, Cbuf, ldc, false, U, ldu, false, 0.0, P64, r, st));
-        HIPCHK(launch_f64_to_f32_2d(P64, m, r, r, P32, rp, st));
+        HIPCHK(launch_f64_to_f32_2d(P64, m, r, r, P32, rp, true, st));
     }
     const GemmPlan pe = plan_sgemm(m, n, r, false, false);
     STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_E, BCUR_STAGE_FIT_REDUCE, pe, m, n, r, false, P32, rp, R0, np, nullptr, 0,

@@ -38,9 +38,11 @@ hipError_t launch_sum_f64(const double* x, int64_t count, double* out, hipStream
 hipError_t launch_gram_from_cols(const float* H, int64_t ldh, const int64_t* d_cols, int64_t c, double* G,
                                  hipStream_t st, float* G32 = nullptr, int64_t ldg32 = 0);
 hipError_t launch_f64_to_f32(const double* x, int64_t count, float* y, hipStream_t st);
-// y (rows x ldy) = x (rows x cols, ldx) rounded to FP32, zero in columns cols..ldy-1
+// y[:, 0:cols] (row stride ldy) = x (rows x cols, ldx) rounded to FP32; with
+// zero_pad, also zero in columns cols..ldy-1 (y then owns whole rows of ldy:
+// never for a block of columns inside a wider matrix)
 hipError_t launch_f64_to_f32_2d(const double* x, int64_t rows, int64_t cols, int64_t ldx, float* y, int64_t ldy,
-                                hipStream_t st);
+                                bool zero_pad, hipStream_t st);
 hipError_t launch_cast_bf16(const float* A, int64_t m, int64_t n, int64_t lda, uint16_t* out, int64_t ldo,
                             hipStream_t st);
 hipError_t launch_zero_f32(float* x, int64_t rows, int64_t cols, int64_t ld, hipStream_t st);

@@ -495,10 +495,11 @@ __global__ __launch_bounds__(256) void k_f64_to_f32(const double* __restrict__ x
         y[e] = (float)x[e];
 }
 
+// wy: the columns of each row of y written (cols, or ldy to zero the padding)
 __global__ __launch_bounds__(256) void k_f64_to_f32_2d(const double* __restrict__ x, int64_t rows, int64_t cols,
-                                                       int64_t ldx, float* __restrict__ y, int64_t ldy) {
+                                                       int64_t ldx, float* __restrict__ y, int64_t ldy, int64_t wy) {
     for (int64_t i = blockIdx.y; i < rows; i += gridDim.y)
-        for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < ldy; j += (int64_t)gridDim.x * 256)
+        for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < wy; j += (int64_t)gridDim.x * 256)
             y[i * ldy + j] = j < cols ? (float)x[i * ldx + j] : 0.0f;
 }
 
@@ -657,8 +658,9 @@ hipError_t launch_f64_to_f32(const double* x, int64_t count, float* y, hipStream
 }
 
 hipError_t launch_f64_to_f32_2d(const double* x, int64_t rows, int64_t cols, int64_t ldx, float* y, int64_t ldy,
-                                hipStream_t st) {
-    hipLaunchKernelGGL(k_f64_to_f32_2d, grid2d(ldy, rows), dim3(256), 0, st, x, rows, cols, ldx, y, ldy);
+                                bool zero_pad, hipStream_t st) {
+    const int64_t wy = zero_pad ? ldy : cols;
+    hipLaunchKernelGGL(k_f64_to_f32_2d, grid2d(wy, rows), dim3(256), 0, st, x, rows, cols, ldx, y, ldy, wy);
     return hipGetLastError();
 }
 

@@ -482,6 +482,35 @@ def test_fit_columns_rank_deficient_wide(ctx):
     assert abs(err - own) <= tol
 
 
+def test_fit_columns_rank_deficient_many_panels(ctx):
+    # The FP64 fallback solves n > 1024 columns of A in panels of 1024; each
+    # panel of U is written where it belongs and nothing else of the output
+    # buffer is touched (U is a c x n view inside a wider, taller buffer whose
+    # other elements hold a sentinel).
+    import torch
+    from paper_1703_06065_amd import binding
+    m, n, c = 400, 2600, 120
+    rng = np.random.default_rng(32)
+    C = rng.standard_normal((m, c)).astype(np.float32)
+    C[:, 7] = C[:, 3]
+    A = rng.standard_normal((m, n)).astype(np.float32)
+    sentinel = 7.25
+    big = torch.full((c + 3, n + 12), sentinel, dtype=torch.float32, device="cuda")
+    note("fit rank-deficient, three fallback panels, guarded output")
+    U, err, flags = ctx.fit_columns(dev(A), dev(C), refine=1, U_out=big[:c, :n])
+    torch.cuda.synchronize()
+    hb = big.cpu().numpy()
+    assert flags & binding.FLAG_RANKDEF_C
+    assert np.all(hb[:c, n:] == sentinel) and np.all(hb[c:] == sentinel)
+    Uh = hb[:c, :n].astype(np.float64)
+    own = math.sqrt(O.frob2(A.astype(np.float64) - C.astype(np.float64) @ Uh))
+    _, erro = O.fit_columns(A, C)
+    tol = err_tol(erro, O.frob2(A)) + out_quant_tol(C.astype(np.float64), Uh)
+    note(f"  err={err:.9g} own residual={own:.9g} oracle={erro:.9g} tol={tol:.3e} flags={flags}")
+    assert np.all(np.isfinite(Uh))
+    assert abs(err - erro) <= tol and abs(own - erro) <= tol
+
+
 # ---------------------------------------------------------------------------
 # full size, in the configuration the benchmark times
 # ---------------------------------------------------------------------------
