@@ -225,31 +225,42 @@ __global__ __launch_bounds__(WM* WN * 64, EPI == kResidLate ? 4 : 1) void k_sgem
     // row 8 (v / 4) + 4 h + (v % 4), column r.
     float* D = g.D + (int64_t)blockIdx.z * g.split_stride;
     double wacc = 0.0;
+    // a tile wholly inside D takes the form without per-element tests, so the
+    // compiler issues its reads of X together instead of one at a time (not
+    // with the X + D and Y reads of EPI_ADD_DOT and the early X of EPI_RESID:
+    // there it would raise the registers past two waves per SIMD)
+    auto epilogue = [&](auto checked) {
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+        for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
+            for (int j = 0; j < TN; ++j)
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int64_t row = m0 + wm * WTM + 32 * i + 8 * (v >> 2) + 4 * h + (v & 3);
-                const int64_t col = n0 + wn * WTN + 32 * j + r;
-                if (row < g.M && col < g.N) {
-                    const float x = acc[i][j][v];
-                    if (EPI == EPI_STORE || EPI == EPI_STORE_SQA) {
-                        D[row * g.ldd + col] = x;
-                    } else if (kResid) {
-                        float xe;
-                        if constexpr (kPre) xe = xv[i][j][v];
-                        else xe = g.X[row * g.ldx + col];
-                        const float e = xe - x;
-                        if (EPI == EPI_RESID) D[row * g.ldd + col] = e;
-                        wacc += (double)e * (double)e;
-                    } else {
-                        D[row * g.ldd + col] = g.X[row * g.ldx + col] + x;
-                        wacc += (double)x * (double)g.Y[row * g.ldy + col];
+                for (int v = 0; v < 16; ++v) {
+                    const int64_t row = m0 + wm * WTM + 32 * i + 8 * (v >> 2) + 4 * h + (v & 3);
+                    const int64_t col = n0 + wn * WTN + 32 * j + r;
+                    if (!decltype(checked)::value || (row < g.M && col < g.N)) {
+                        const float x = acc[i][j][v];
+                        if (EPI == EPI_STORE || EPI == EPI_STORE_SQA) {
+                            D[row * g.ldd + col] = x;
+                        } else if (kResid) {
+                            float xe;
+                            if constexpr (kPre) xe = xv[i][j][v];
+                            else xe = g.X[row * g.ldx + col];
+                            const float e = xe - x;
+                            if (EPI == EPI_RESID) D[row * g.ldd + col] = e;
+                            wacc += (double)e * (double)e;
+                        } else {
+                            D[row * g.ldd + col] = g.X[row * g.ldx + col] + x;
+                            wacc += (double)x * (double)g.Y[row * g.ldy + col];
+                        }
                     }
                 }
-            }
+    };
+    constexpr bool kWhole = EPI == EPI_STORE || EPI == EPI_STORE_SQA || EPI == kResidLate;
+    if (kWhole && m0 + BM <= g.M && n0 + BN <= g.N)
+        epilogue(std::false_type{});
+    else
+        epilogue(std::true_type{});
     if constexpr (EPI == EPI_STORE_SQA) {
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) sqa += __shfl_xor(sqa, o, 64);
@@ -397,7 +408,9 @@ __global__ __launch_bounds__(BM * 2) void k_xgemm(const GemmArgs g) {
     constexpr bool BCOL = (!TA && kXBCol) || BN == 64;
     constexpr int BC0 = TA ? NT - 2 * BN : 0;
     const bool bwave = !BCOL && wave >= WB0;
-    const bool bcol = BCOL && tid >= BC0 && tid < BC0 + 2 * BN;
+    // (on the 256 x 256 tile with A not transposed every thread stages a
+    // column, known at compile time: its stores need no branch)
+    const bool bcol = BCOL && ((BM == 256 && BC0 == 0 && 2 * BN == NT) || (tid >= BC0 && tid < BC0 + 2 * BN));
     const int bcc = (tid - BC0) % BN, bco = (tid - BC0) / BN;
     const int uu = 64 * (bwave ? wave - WB0 : wave) + lane;
     const int uw = bwave ? BN / 2 : BM / 2;
@@ -598,28 +611,37 @@ __global__ __launch_bounds__(BM * 2) void k_xgemm(const GemmArgs g) {
 
     float* D = g.D + (int64_t)blockIdx.z * g.split_stride;
     double wacc = 0.0;
+    // a tile wholly inside D (always, in the full 256 x 256 form: M and N are
+    // multiples of 256) takes the form without per-element tests, so the
+    // compiler issues its reads of X and Y together instead of one at a time
+    auto epilogue = [&](auto checked) {
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+        for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
+            for (int j = 0; j < TN; ++j)
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int64_t row = m0 + wm * WTM + 32 * i + 8 * (v >> 2) + 4 * h + (v & 3);
-                const int64_t col = n0 + wn * WTN + 32 * j + r;
-                if (row < g.M && col < g.N) {
-                    const float x = acc[i][j][v];
-                    if (EPI == EPI_STORE || EPI == EPI_STORE_SQA) {
-                        D[row * g.ldd + col] = x;
-                    } else if (EPI == kResidLate || EPI == EPI_RESID) {
-                        const float e = g.X[row * g.ldx + col] - x;
-                        if (EPI == EPI_RESID) D[row * g.ldd + col] = e;
-                        wacc += (double)e * (double)e;
-                    } else {
-                        D[row * g.ldd + col] = g.X[row * g.ldx + col] + x;
-                        wacc += (double)x * (double)g.Y[row * g.ldy + col];
+                for (int v = 0; v < 16; ++v) {
+                    const int64_t row = m0 + wm * WTM + 32 * i + 8 * (v >> 2) + 4 * h + (v & 3);
+                    const int64_t col = n0 + wn * WTN + 32 * j + r;
+                    if (!decltype(checked)::value || (row < g.M && col < g.N)) {
+                        const float x = acc[i][j][v];
+                        if (EPI == EPI_STORE || EPI == EPI_STORE_SQA) {
+                            D[row * g.ldd + col] = x;
+                        } else if (EPI == kResidLate || EPI == EPI_RESID) {
+                            const float e = g.X[row * g.ldx + col] - x;
+                            if (EPI == EPI_RESID) D[row * g.ldd + col] = e;
+                            wacc += (double)e * (double)e;
+                        } else {
+                            D[row * g.ldd + col] = g.X[row * g.ldx + col] + x;
+                            wacc += (double)x * (double)g.Y[row * g.ldy + col];
+                        }
                     }
                 }
-            }
+    };
+    if ((FULL && BM == 256 && BN == 256) || (m0 + BM <= g.M && n0 + BN <= g.N))
+        epilogue(std::false_type{});
+    else
+        epilogue(std::true_type{});
     if constexpr (EPI == EPI_STORE_SQA) {
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) sqa += __shfl_xor(sqa, o, 64);
