@@ -555,17 +555,17 @@ def cpu_baseline_large(w, omega64, budget_fit_cols=(128, 256)):
 # `bench.py --steps 1 --warmup 1 --no-cpu-baseline`; the 1 GiB copy reads
 # 524300 KiB of FETCH_SIZE (scale 2.0) and 1048576 KiB of WRITE_SIZE (1.0).
 TRAFFIC_LARGE = {
-    "fit_E": {"src": "732818558f3e0c40", "fetch_kib": 8389755.7, "fetch_scale": 1.9999, "write_kib": 541.2,
+    "fit_E": {"src": "315f5074313214dc", "fetch_kib": 8389502.6, "fetch_scale": 1.9999, "write_kib": 540.7,
               "write_scale": 1.0},
-    "fit_H": {"src": "732818558f3e0c40", "fetch_kib": 17301575.0, "fetch_scale": 1.9999, "write_kib": 131072.0,
+    "fit_H": {"src": "315f5074313214dc", "fetch_kib": 17301575.1, "fetch_scale": 1.9999, "write_kib": 131072.0,
               "write_scale": 1.0},
 }
 # 8192 x 4096 x 256, the same counters on `bench.py --workload plain-fp32
 # --steps 3 --warmup 1 --no-cpu-baseline` (scales from the same copy runs).
 TRAFFIC_PLAIN = {
-    "fit_E": {"src": "732818558f3e0c40", "fetch_kib": 90194.0, "fetch_scale": 1.9999, "write_kib": 16.0,
+    "fit_E": {"src": "315f5074313214dc", "fetch_kib": 90194.0, "fetch_scale": 1.9999, "write_kib": 16.0,
               "write_scale": 1.0},
-    "fit_H": {"src": "732818558f3e0c40", "fetch_kib": 98374.8, "fetch_scale": 1.9999, "write_kib": 65536.0,
+    "fit_H": {"src": "315f5074313214dc", "fetch_kib": 98374.8, "fetch_scale": 1.9999, "write_kib": 65536.0,
               "write_scale": 1.0},
 }
 

@@ -41,9 +41,13 @@ __device__ __forceinline__ void tile_mm(FTile& acc, const TAe* __restrict__ A, i
                                         const TBe* __restrict__ B, int64_t ldb, int64_t M, int64_t N, int64_t K,
                                         double* As, double* Bs) {
     const int tid = threadIdx.x, lane = tid & 63, wy = (tid >> 6) >> 1, wx = (tid >> 6) & 1;
+    constexpr int EPT = NB * KB / 256;  // elements of each operand a thread stages per step
     for (int64_t k0 = 0; k0 < K; k0 += KB) {
-        __syncthreads();
-        for (int e = tid; e < NB * KB; e += 256) {
+        // all of a step's global reads first (issued together), then the LDS stores
+        double va[EPT], vb[EPT];
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            const int e = tid + 256 * u;
             int row, kk;
             if (!TA) {
                 row = e / KB;
@@ -53,11 +57,11 @@ __device__ __forceinline__ void tile_mm(FTile& acc, const TAe* __restrict__ A, i
                 row = e % NB;
             }
             const int64_t gk = k0 + kk;
-            double v = 0.0;
-            if (row < M && gk < K) v = (double)(TA ? A[gk * lda + row] : A[row * lda + gk]);
-            As[kk * (NB + 1) + row] = v;
+            va[u] = (row < M && gk < K) ? (double)(TA ? A[gk * lda + row] : A[row * lda + gk]) : 0.0;
         }
-        for (int e = tid; e < NB * KB; e += 256) {
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            const int e = tid + 256 * u;
             int col, kk;
             if (!TB) {
                 kk = e / NB;
@@ -67,9 +71,20 @@ __device__ __forceinline__ void tile_mm(FTile& acc, const TAe* __restrict__ A, i
                 kk = e % KB;
             }
             const int64_t gk = k0 + kk;
-            double v = 0.0;
-            if (col < N && gk < K) v = (double)(TB ? B[col * ldb + gk] : B[gk * ldb + col]);
-            Bs[kk * (NB + 1) + col] = v;
+            vb[u] = (col < N && gk < K) ? (double)(TB ? B[col * ldb + gk] : B[gk * ldb + col]) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            const int e = tid + 256 * u;
+            const int row = !TA ? e / KB : e % NB, kk = !TA ? e % KB : e / NB;
+            As[kk * (NB + 1) + row] = va[u];
+        }
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            const int e = tid + 256 * u;
+            const int col = !TB ? e % NB : e / KB, kk = !TB ? e / NB : e % KB;
+            Bs[kk * (NB + 1) + col] = vb[u];
         }
         __syncthreads();
 #pragma unroll
@@ -102,6 +117,24 @@ __global__ __launch_bounds__(256) void k_dgemm(int64_t M, int64_t N, int64_t K, 
     const TAe* Ab = TA ? A + m0 : A + m0 * lda;
     const TBe* Bb = TB ? B + n0 * ldb : B + n0;
     tile_mm<TA, TB, TAe, TBe>(acc, Ab, lda, Bb, ldb, M - m0, N - n0, K, As, Bs);
+    // a tile wholly inside D: the old values read together, then the stores,
+    // with no per-element test (each would make the compiler issue and wait
+    // for one read at a time)
+    if (m0 + NB <= M && n0 + NB <= N) {
+        double dv[16];
+        if (beta != 0.0) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) dv[e] = D[(m0 + tile_row(e)) * ldd + n0 + tile_col(e)];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) dv[e] = alpha * tile_get(acc, e) + beta * dv[e];
+        } else {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) dv[e] = alpha * tile_get(acc, e);
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) D[(m0 + tile_row(e)) * ldd + n0 + tile_col(e)] = dv[e];
+        return;
+    }
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
         const int64_t row = m0 + tile_row(e), col = n0 + tile_col(e);

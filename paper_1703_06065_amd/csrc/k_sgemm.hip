@@ -618,7 +618,21 @@ __global__ __launch_bounds__(BM * 2) void k_xgemm(const GemmArgs g) {
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
-            for (int j = 0; j < TN; ++j)
+            for (int j = 0; j < TN; ++j) {
+                // whole tiles: the sixteen reads of X (and Y) of a 32 x 32 block
+                // before its stores, so they are issued together even where D
+                // is X (U += dU in place: each element is read before it is
+                // written, and blocks do not overlap)
+                float xr[16], yr[16];
+                if constexpr (!decltype(checked)::value && EPI != EPI_STORE && EPI != EPI_STORE_SQA) {
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) {
+                        const int64_t row = m0 + wm * WTM + 32 * i + 8 * (v >> 2) + 4 * h + (v & 3);
+                        const int64_t col = n0 + wn * WTN + 32 * j + r;
+                        xr[v] = g.X[row * g.ldx + col];
+                        if constexpr (EPI == EPI_ADD_DOT) yr[v] = g.Y[row * g.ldy + col];
+                    }
+                }
 #pragma unroll
                 for (int v = 0; v < 16; ++v) {
                     const int64_t row = m0 + wm * WTM + 32 * i + 8 * (v >> 2) + 4 * h + (v & 3);
@@ -628,15 +642,19 @@ __global__ __launch_bounds__(BM * 2) void k_xgemm(const GemmArgs g) {
                         if (EPI == EPI_STORE || EPI == EPI_STORE_SQA) {
                             D[row * g.ldd + col] = x;
                         } else if (EPI == kResidLate || EPI == EPI_RESID) {
-                            const float e = g.X[row * g.ldx + col] - x;
+                            const float xe = decltype(checked)::value ? g.X[row * g.ldx + col] : xr[v];
+                            const float e = xe - x;
                             if (EPI == EPI_RESID) D[row * g.ldd + col] = e;
                             wacc += (double)e * (double)e;
                         } else {
-                            D[row * g.ldd + col] = g.X[row * g.ldx + col] + x;
-                            wacc += (double)x * (double)g.Y[row * g.ldy + col];
+                            const float xe = decltype(checked)::value ? g.X[row * g.ldx + col] : xr[v];
+                            const float ye = decltype(checked)::value ? g.Y[row * g.ldy + col] : yr[v];
+                            D[row * g.ldd + col] = xe + x;
+                            wacc += (double)x * (double)ye;
                         }
                     }
                 }
+            }
     };
     if ((FULL && BM == 256 && BN == 256) || (m0 + BM <= g.M && n0 + BN <= g.N))
         epilogue(std::false_type{});
