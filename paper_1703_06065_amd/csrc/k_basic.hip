@@ -437,18 +437,41 @@ __global__ __launch_bounds__(256) void k_gather_cols_v4(const float* __restrict_
     const int tid = threadIdx.x;
     const int64_t g0 = (int64_t)blockIdx.y * kGatherGroups;
     const int ng = (int)min<int64_t>(kGatherGroups, (c + 3) / 4 - g0);
+    int mine = 1;
     for (int q = tid; q < ng; q += 256) {
         const int64_t t = (g0 + q) * 4;
         const int64_t s0 = cols[t];
         bool ok = t + 3 < c && (s0 & 3) == 0;
         if (ok) ok = cols[t + 1] == s0 + 1 && cols[t + 2] == s0 + 2 && cols[t + 3] == s0 + 3;
         src[q] = ok ? s0 : -1;
+        mine &= ok ? 1 : 0;
     }
-    __syncthreads();
+    // every group of this workgroup a contiguous aligned run
+    const bool all = __syncthreads_and(mine) != 0;
     const int64_t i0 = (int64_t)blockIdx.x * band;
     const int64_t rows = min<int64_t>(band, m - i0);
     const int64_t total = rows * ng;
-    for (int64_t e = tid; e < total; e += 256) {
+    // every group a contiguous aligned run (the usual case: blocks of whole
+    // float4s): eight moves per thread at a time, the eight reads issued
+    // together and the stores with no test between them
+    constexpr int U = 8;
+    int64_t e0 = tid;
+    if (all) {
+        for (; e0 + (U - 1) * 256 < total; e0 += U * 256) {
+            float4 v[U];
+            float* o[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t e = e0 + u * 256, i = i0 + e / ng;
+                const int q = (int)(e % ng);
+                v[u] = *reinterpret_cast<const float4*>(A + i * lda + src[q]);
+                o[u] = C + i * ldc + (g0 + q) * 4;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) *reinterpret_cast<float4*>(o[u]) = v[u];
+        }
+    }
+    for (int64_t e = e0; e < total; e += 256) {
         const int64_t i = i0 + e / ng;
         const int q = (int)(e % ng);
         const int64_t t = (g0 + q) * 4;

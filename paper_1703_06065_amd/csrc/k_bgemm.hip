@@ -60,10 +60,14 @@ __global__ __launch_bounds__(256) void k_cast_bf16_both_v4(const float* __restri
     __shared__ uint16_t tile[64][68];
     const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    // the four 16-byte reads first (issued together), then the casts and stores
+    float4 va[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) va[i] = *reinterpret_cast<const float4*>(A + (r0 + ty + 16 * i) * lda + c0 + 4 * tx);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int row = ty + 16 * i;
-        const float4 v = *reinterpret_cast<const float4*>(A + (r0 + row) * lda + c0 + 4 * tx);
+        const float4 v = va[i];
         const uint16_t b0 = bf16_rne(v.x), b1 = bf16_rne(v.y), b2 = bf16_rne(v.z), b3 = bf16_rne(v.w);
         if (out) {
             uint2 pk;
