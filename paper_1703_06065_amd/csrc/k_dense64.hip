@@ -165,12 +165,15 @@ __global__ __launch_bounds__(256) void k_maxdiag(const double* __restrict__ G, i
 // the inverse built from L^-1 is that of the kept columns, with zero rows and
 // columns for the dropped ones.  Writes L^-1 (NB x NB, lower, zero padded) into
 // Linv; G is only read (the diagonal block of L is not needed later).
-// piv[0..1] receive the smallest and largest pivot.
-__global__ __launch_bounds__(64) void k_potrf_diag(const double* __restrict__ G, int64_t c, int64_t j0, int w,
-                                                     const double* __restrict__ maxdiag, double rel_tau,
-                                                     double* __restrict__ Linv, double* __restrict__ piv,
-                                                     int* __restrict__ info) {
-    constexpr int TG = 8, NR = 8;
+// piv[0..1] receive the smallest and largest pivot.  Four waves (16 x 16
+// threads, ten entries each): a pivot step's work is spread four times wider
+// than on one wave of 8 x 8 threads (36 entries each), whose instruction
+// stream bounded every step.
+__global__ __launch_bounds__(256) void k_potrf_diag(const double* __restrict__ G, int64_t c, int64_t j0, int w,
+                                                      const double* __restrict__ maxdiag, double rel_tau,
+                                                      double* __restrict__ Linv, double* __restrict__ piv,
+                                                      int* __restrict__ info) {
+    constexpr int TG = 16, NR = 4;
     __shared__ double P[2 * TG * NR + 1];
     __shared__ double pv[TG * NR];
     const int tid = threadIdx.x, tr = tid / TG, tc = tid % TG;
@@ -531,7 +534,7 @@ static hipError_t chol_and_inverse_factor(double* G, int64_t c, double* ws, int*
     for (int64_t jb = 0; jb < nblk; ++jb) {
         const int64_t j0 = jb * NB;
         const int w = (int)(c - j0 < NB ? c - j0 : NB);
-        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(64), 0, st, (const double*)G, c, j0, w,
+        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, st, (const double*)G, c, j0, w,
                            (const double*)maxd, rel_tau, Linv + jb * NB * NB, pivb + 2 * jb, info);
         const int64_t rows = c - j0 - w;
         if (rows > 0) {
