@@ -715,7 +715,7 @@ def main():
     ap.add_argument("--budget-gib", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     {"serve": serve_bench, "alg1": alg1_bench, "boost": boost_bench, "diag": diag_bench, "copy": copy_bench,
      "scores": scores_bench, "decompose": decompose_bench}[args.mode](args)
