@@ -62,10 +62,26 @@ def mfma_roofline(M, N, K, avg_ms, kernel_fp32, kernel_split, **extra):
     return roof
 
 
+def resid_columns(m, n, c):
+    """Columns of A the residual pass covers.  U on C's own columns is the
+    identity (C e_k is that column of A: a residual of exactly zero there),
+    so where the pass runs on the split-BF16 tile and the shorter pass takes
+    fewer rounds of workgroups it covers only the n - c others (the rule
+    stated with bcur_decompose in include/bcur.h)."""
+    ne = n - c
+    ok = ne >= 256 and m >= 256 and c >= 256 and n <= 262144 and float(m) * ne * c >= 8.0e9
+
+    def rounds(cols):   # of 256 workgroups, on 256 x 256 tiles
+        return -(-(-(-m // 256) * -(-cols // 256)) // 256)
+
+    return ne if ok and rounds(ne) < rounds(n) else n
+
+
 def algorithmic_flops(m, n, k, l, q, c):
     """FLOPs the method needs per decomposition (sketch width l, no padding)."""
     rf = (2 * q + 3) * 2.0 * m * n * l              # (q+1) x (A Q, A^T Z) + the Rayleigh-Ritz A Q
-    fit = 2 * 2.0 * m * c * n + 3 * 2.0 * c * c * n + 2.0 * c ** 3  # C^T A, A - C U; G^-1 H, H - G U, G^-1 F; X^T X
+    # C^T A, A - C U over the columns outside C; G^-1 H, H - G U, G^-1 F; X^T X
+    fit = 2.0 * m * c * n + 2.0 * m * c * resid_columns(m, n, c) + 3 * 2.0 * c * c * n + 2.0 * c ** 3
     return rf, fit
 
 
@@ -555,17 +571,17 @@ def cpu_baseline_large(w, omega64, budget_fit_cols=(128, 256)):
 # `bench.py --steps 1 --warmup 1 --no-cpu-baseline`; the 1 GiB copy reads
 # 524300 KiB of FETCH_SIZE (scale 2.0) and 1048576 KiB of WRITE_SIZE (1.0).
 TRAFFIC_LARGE = {
-    "fit_E": {"src": "315f5074313214dc", "fetch_kib": 8389502.6, "fetch_scale": 1.9999, "write_kib": 540.7,
+    "fit_E": {"src": "3e8df830f82cb630", "fetch_kib": 7348632.0, "fetch_scale": 1.9999, "write_kib": 477.0,
               "write_scale": 1.0},
-    "fit_H": {"src": "315f5074313214dc", "fetch_kib": 17301575.1, "fetch_scale": 1.9999, "write_kib": 131072.0,
+    "fit_H": {"src": "3e8df830f82cb630", "fetch_kib": 17301575.1, "fetch_scale": 1.9999, "write_kib": 131072.0,
               "write_scale": 1.0},
 }
 # 8192 x 4096 x 256, the same counters on `bench.py --workload plain-fp32
 # --steps 3 --warmup 1 --no-cpu-baseline` (scales from the same copy runs).
 TRAFFIC_PLAIN = {
-    "fit_E": {"src": "315f5074313214dc", "fetch_kib": 90194.0, "fetch_scale": 1.9999, "write_kib": 16.0,
+    "fit_E": {"src": "3e8df830f82cb630", "fetch_kib": 90197.5, "fetch_scale": 1.9999, "write_kib": 16.0,
               "write_scale": 1.0},
-    "fit_H": {"src": "315f5074313214dc", "fetch_kib": 98374.8, "fetch_scale": 1.9999, "write_kib": 65536.0,
+    "fit_H": {"src": "3e8df830f82cb630", "fetch_kib": 98374.8, "fetch_scale": 1.9999, "write_kib": 65536.0,
               "write_scale": 1.0},
 }
 
@@ -636,12 +652,15 @@ def decompose_bench(args):
     # Roofline of the dominant kernel: of the kernels that a throughput
     # roofline bounds, the one with the largest device time per decomposition.
     # At these shapes that is one of the two c-wide products over A, each
-    # 2 m c n FLOP per launch and one launch per decomposition: the residual
-    # ||A - C U||_F^2 (NN, norm-only epilogue, stage fit_E) or H = C^T A (TN,
-    # stage fit_H), on the split-BF16 kernel at these sizes.  The
+    # one launch each per decomposition: the residual ||A - C U||_F^2 (NN,
+    # norm-only epilogue, stage fit_E; 2 m c (n - c) FLOP over the columns
+    # outside C) or H = C^T A (TN, stage fit_H; 2 m c n), on the split-BF16
+    # kernel at these sizes.  The
     # one-workgroup FP64 solvers are latency-bound; their times are in
     # stage_ms_per_step.
-    shapes = {"fit_E": (w.m, w.n, c), "fit_H": (c, w.n, w.m)}
+    ne = resid_columns(w.m, w.n, c)
+    shapes = {"fit_E": (w.m, ne, c), "fit_H": (c, w.n, w.m)}
+    abytes = {"fit_E": 4.0 * (w.m * ne + w.m * c + c * ne), "fit_H": 4.0 * (w.m * w.n + w.m * c + c * w.n)}
     names = {"fit_E": ("k_sgemm<128,128,16,2,2> norm-only residual epilogue (||A - C U||_F^2)",
                        "k_xgemm<256,256> split-BF16, norm-only residual epilogue (||A - C U||_F^2)"),
              "fit_H": ("k_sgemm<256,128,16,4,2> TN (H = C^T A)", "k_xgemm<256,256,TA> split-BF16 (H = C^T A)")}
@@ -649,7 +668,7 @@ def decompose_bench(args):
     dom = max(avg, key=avg.get)
     table = TRAFFIC_LARGE if large else TRAFFIC_PLAIN
     roof = mfma_roofline(*shapes[dom], avg[dom], *names[dom], stage=dom,
-                         algorithmic_bytes_per_launch=4.0 * (w.m * w.n + w.m * c + c * w.n),
+                         algorithmic_bytes_per_launch=abytes[dom],
                          other_stage_avg_ms={st: round(v, 5) for st, v in avg.items() if st != dom})
     roof["traffic"] = traffic_for(table, dom)
     prec = "BF16 range finder (q BF16 power iterations, final FP32 pass), FP32 fit with one refinement step, " \

@@ -337,7 +337,15 @@ typedef struct bcur_result {
  * row_off: host Gr+1 row-block offsets, or NULL (columns only).
  * omega: device n x l test matrix (dense, leading dimension l), or NULL: the
  * Rademacher matrix of params->seed is drawn on the device (bcur_test_matrix).
- * draws: host, s + s_r 64-bit words (column draws first).  Synchronous. */
+ * draws: host, s + s_r 64-bit words (column draws first).
+ * Columns only: U on C's own columns is the identity (C e_k is that column of
+ * A exactly, so the residual there is zero; it is the least-squares solution
+ * there when C has full column rank, the case the FP32 fit keeps, and the
+ * FP64 fallback recomputes U whole otherwise).  Where the residual product is
+ * large enough for the split-BF16 tile (m, c, n - c >= 256 and
+ * m c (n - c) >= 8e9, n <= 262144) and its 256 x 256 tiles over n - c columns
+ * take fewer rounds of 256 workgroups than over n, the residual pass covers
+ * only the other n - c columns.  Synchronous. */
 bcur_status bcur_decompose(bcur_ctx* ctx, const float* A, int64_t m, int64_t n, int64_t lda,
                            const int64_t* col_off, int64_t G, const int64_t* row_off, int64_t Gr,
                            const bcur_params* params, const float* omega, const uint64_t* draws,

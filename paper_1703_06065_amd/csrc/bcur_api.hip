@@ -335,10 +335,11 @@ void rf_layout(Arena& a, RFBufs& b, int64_t m, int64_t n, int64_t l, int64_t k, 
 bcur_status gemm_timed(bcur_ctx* ctx, int stage, int rstage, const GemmPlan& p, int64_t M, int64_t N, int64_t K,
                        bool tA, const float* A, int64_t lda, const float* B, int64_t ldb, float* D, int64_t ldd,
                        float* part, int epi = EPI_STORE, const float* X = nullptr, int64_t ldx = 0,
-                       const float* Y = nullptr, int64_t ldy = 0, double* wsum = nullptr) {
+                       const float* Y = nullptr, int64_t ldy = 0, double* wsum = nullptr, const int* ncol = nullptr) {
     {
         StageScope ts(ctx, stage);
-        HIPCHK(launch_sgemm_main(p, M, N, K, tA, A, lda, B, ldb, D, ldd, part, epi, X, ldx, Y, ldy, wsum, ctx->stream));
+        HIPCHK(launch_sgemm_main(p, M, N, K, tA, A, lda, B, ldb, D, ldd, part, epi, X, ldx, Y, ldy, wsum, ctx->stream,
+                                 ncol));
     }
     if (p.splits > 1) {
         StageScope ts(ctx, rstage);
@@ -475,7 +476,9 @@ struct FitBufs {
     // ill-conditioned C: its Gram matrix, L1^-1, Q1 = C L1^-T, two c x kFbPanel panels
     double *Gc64, *L1, *Q1, *T1, *T2;
     int64_t nwsE, nwsD;
+    size_t npart;   // floats of split-K partials in part
     int* info;
+    int* ncol;   // the columns of A outside C, for the residual pass
 };
 
 void fit_layout(Arena& a, FitBufs& b, int64_t m, int64_t n, int64_t c, bool need_gtmp) {
@@ -491,18 +494,23 @@ void fit_layout(Arena& a, FitBufs& b, int64_t m, int64_t n, int64_t c, bool need
     const GemmPlan pu = plan_sgemm(c, n, c, false, true);
     size_t part = std::max(std::max(sgemm_partial_floats(ph, c, n), sgemm_partial_floats(pg, c, c)),
                            std::max(sgemm_partial_floats(pu, c, n), sgemm_partial_floats(pi, c, c)));
-    b.part = a.take<float>(std::max<size_t>(part, 4));
+    b.npart = std::max<size_t>(part, 4);
+    b.part = a.take<float>(b.npart);
     b.Gtmp = need_gtmp ? a.take<float>(c * cp) : nullptr;
     b.G = a.take<double>(c * c);
     b.spdws = a.take<double>(spd_inverse_ws_doubles(c));
-    b.nwsE = resid_parts(m, n, c);
-    b.nwsD = add_dot_parts(pu, c, n, c);
+    // c is the most columns a call may fit; the partial counts of a call with
+    // fewer (repeated or narrower blocks) can be larger: a smaller product can
+    // take the smaller tile
+    b.nwsE = resid_parts_max(m, n);
+    b.nwsD = add_dot_parts_max(c, n);
     b.wsE = a.take<double>(b.nwsE);
     b.wsD = a.take<double>(b.nwsD);
     b.wsF = a.take<double>(resid_store_parts(c, n));
     b.errv = a.take<double>(8);
     b.piv = a.take<double>(2 * ((c + 63) / 64));
     b.info = a.take<int>(4);
+    b.ncol = a.take<int>(n <= kComplementMaxN ? n : 1);
     b.Gc64 = a.take<double>(c * c);
     b.L1 = a.take<double>(c * c);
     b.Q1 = a.take<double>(m * c);
@@ -522,13 +530,29 @@ void fit_layout(Arena& a, FitBufs& b, int64_t m, int64_t n, int64_t c, bool need
 // ||E||^2 (before it), b.info[0] bit 0 = pivots dropped, b.piv = pivot ranges.
 // Hpre: H = C^T A already computed by the caller (c x n, ld round4(n)); b.H is
 // then unused.
+// With d_cols (distinct columns, as every caller that passes them guarantees),
+// C e_k is column cols[k] of A exactly, so U[:, cols] = I leaves those columns
+// a residual of exactly zero; it is their least-squares solution when C has
+// full column rank, the case this path keeps (otherwise fit_collect redoes U
+// whole in FP64).  The residual pass then covers the other n - c columns
+// only, through their list, and with a refinement step F[:, cols] = 0, so
+// dU leaves those columns at I and adds nothing for them to <F, dU>.  Taken
+// where the shorter pass runs fewer rounds of workgroups than the whole one
+// (otherwise the two small launches it needs would cost more than it saves).
+// b.info[3] = 1 if the list of columns repeats one.
 bcur_status fit_run(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t m, int64_t n, int64_t lda, const float* C,
                     int64_t c, int64_t ldc, const int64_t* d_cols, const int64_t* d_ident, int refine, float* U,
                     int64_t ldu, const float* Hpre = nullptr) {
     hipStream_t st = ctx->stream;
     const int64_t np = round4(n), cp = round4(c);
     HIPCHK(hipMemsetAsync(b.info, 0, 4 * sizeof(int), st));
-    const GemmPlan ph = plan_sgemm(c, n, m, true, true);
+    const int64_t nr = n - c;
+    const bool skip = d_cols && nr > 0 && n <= kComplementMaxN && resid_cols_ok(m, nr, c) &&
+                      resid_rounds(m, nr, c) < resid_rounds(m, n, c);
+    if (skip) HIPCHK(launch_complement_cols(d_cols, c, n, b.ncol, b.info + 3, st));
+    // (the buffers are laid out for the most columns a call may fit; a call
+    // with fewer can split its products into more parts than part holds)
+    const GemmPlan ph = plan_sgemm_within(c, n, m, true, b.npart);
     // H = C^T A, or the caller's precomputed rows of it (ld np)
     const float* H = Hpre ? Hpre : b.H;
     if (!Hpre)
@@ -540,7 +564,7 @@ bcur_status fit_run(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t m, 
             HIPCHK(launch_gram_from_cols(H, np, d_cols, c, b.G, st, refine ? b.G32 : nullptr, cp));
         } else {
             if (!b.Gtmp || !d_ident) return fail(ctx, BCUR_E_ARG, "internal: no Gram buffer");
-            const GemmPlan pg = plan_sgemm(c, c, m, true, true);
+            const GemmPlan pg = plan_sgemm_within(c, c, m, true, b.npart);
             HIPCHK(launch_sgemm(pg, c, c, m, true, C, ldc, C, ldc, b.Gtmp, cp, b.part, EPI_STORE, nullptr, 0, nullptr,
                                 0, nullptr, st));
             HIPCHK(launch_gram_from_cols(b.Gtmp, cp, d_ident, c, b.G, st, refine ? b.G32 : nullptr, cp));
@@ -551,26 +575,29 @@ bcur_status fit_run(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t m, 
         HIPCHK(launch_chol_linv(b.G, c, b.spdws, b.info, b.piv, ldexp(1.0, -24), &Linv, st));
         HIPCHK(launch_f64_to_f32_2d(Linv, c, c, c, b.X32, cp, true, st));
         // G^-1 = X^T X (X is zero above its diagonal)
-        const GemmPlan pi = plan_sgemm(c, c, c, true, true);
+        const GemmPlan pi = plan_sgemm_within(c, c, c, true, b.npart);
         HIPCHK(launch_sgemm(pi, c, c, c, true, b.X32, cp, b.X32, cp, b.Gi32, cp, b.part, EPI_STORE, nullptr, 0,
                             nullptr, 0, nullptr, st));
     }
     // U = G^-1 H
-    const GemmPlan pu = plan_sgemm(c, n, c, false, true);
+    const GemmPlan pu = plan_sgemm_within(c, n, c, false, b.npart);
     STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_U, BCUR_STAGE_FIT_REDUCE, pu, c, n, c, false, b.Gi32, cp, H, np, U, ldu,
                      b.part));
+    if (skip && !refine) HIPCHK(launch_pin_selected(d_cols, c, U, ldu, nullptr, 0, st));
     // ||A - C U||_F^2 (the residual itself is never stored)
-    const GemmPlan pe = plan_sgemm(m, n, c, false, false);
-    STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_E, BCUR_STAGE_FIT_REDUCE, pe, m, n, c, false, C, ldc, U, ldu, nullptr, 0,
-                     nullptr, EPI_RESID_NORM, A, lda, nullptr, 0, b.wsE));
+    const int64_t ne = skip ? nr : n;
+    const GemmPlan pe = plan_sgemm(m, ne, c, false, false);
+    STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_E, BCUR_STAGE_FIT_REDUCE, pe, m, ne, c, false, C, ldc, U, ldu, nullptr, 0,
+                     nullptr, EPI_RESID_NORM, A, lda, nullptr, 0, b.wsE, skip ? b.ncol : nullptr));
     if (refine) {
         // F = C^T (A - C U) = H - G U from the products already formed: a c x n x c
         // GEMM in place of a second 2 m c n pass over the m x n residual
         {
             StageScope ts(ctx, BCUR_STAGE_FIT_F);
-            const GemmPlan pf = plan_sgemm(c, n, c, false, true);
+            const GemmPlan pf = plan_sgemm_within(c, n, c, false, b.npart);
             HIPCHK(launch_sgemm(pf, c, n, c, false, b.G32, cp, U, ldu, b.F, np, b.part, EPI_RESID, H, np, nullptr, 0,
                                 b.wsF, st));
+            if (skip) HIPCHK(launch_pin_selected(d_cols, c, U, ldu, b.F, np, st));
         }
         // U += G^-1 F with <G^-1 F, F>
         StageScope ts(ctx, BCUR_STAGE_FIT_DU);
@@ -578,7 +605,7 @@ bcur_status fit_run(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t m, 
                                     st));
     }
     // one partial per workgroup of the residual GEMM, and of the dU sum
-    HIPCHK(launch_fit_err(b.wsE, resid_parts(m, n, c), b.wsD, refine ? add_dot_parts(pu, c, n, c) : 0, b.errv, st));
+    HIPCHK(launch_fit_err(b.wsE, resid_parts(m, ne, c), b.wsD, refine ? add_dot_parts(pu, c, n, c) : 0, b.errv, st));
     return BCUR_OK;
 }
 
@@ -623,7 +650,7 @@ bcur_status fit_fallback64(bcur_ctx* ctx, const FitBufs& b, const float* A, int6
     const GemmPlan pe = plan_sgemm(m, n, c, false, false);
     STCHK(gemm_timed(ctx, BCUR_STAGE_FIT_E, BCUR_STAGE_FIT_REDUCE, pe, m, n, c, false, C, ldc, U, ldu, nullptr, 0,
                      nullptr, EPI_RESID_NORM, A, lda, nullptr, 0, b.wsE));
-    HIPCHK(launch_fit_err(b.wsE, b.nwsE, b.wsD, 0, b.errv, st));
+    HIPCHK(launch_fit_err(b.wsE, resid_parts(m, n, c), b.wsD, 0, b.errv, st));
     double hv[3];
     HIPCHK(hipMemcpyAsync(hv, b.errv, sizeof hv, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -654,6 +681,7 @@ bcur_status fit_collect(bcur_ctx* ctx, const FitBufs& b, const float* A, int64_t
     const double* hv = reinterpret_cast<const double*>(hstage);
     const double* piv = reinterpret_cast<const double*>(hstage + (reinterpret_cast<const char*>(b.piv) - d0));
     const int* hinfo = reinterpret_cast<const int*>(hstage + (reinterpret_cast<const char*>(b.info) - d0));
+    if (hinfo[3]) return fail(ctx, BCUR_E_HIP, "internal: the chosen columns repeat or fall outside A");
     uint32_t fl = 0;
     if (hinfo[0] & 1) fl |= BCUR_FLAG_RANKDEF_C;
     double pmin = INFINITY, pmax = 0.0;
@@ -699,7 +727,7 @@ void cur_layout(Arena& a, CurBufs& b, int64_t m, int64_t n, int64_t c, int64_t r
     b.Wd = a.take<double>(m * r);
     b.spc = a.take<double>(spd_inverse_ws_doubles(c));
     b.spr = a.take<double>(spd_inverse_ws_doubles(r));
-    b.wsE = a.take<double>(resid_parts(m, n, r));
+    b.wsE = a.take<double>(resid_parts_max(m, n));
     b.errv = a.take<double>(4);
     b.pivc = a.take<double>(2 * ((c + 63) / 64));
     b.pivr = a.take<double>(2 * ((r + 63) / 64));

@@ -46,6 +46,15 @@ hipError_t launch_f64_to_f32_2d(const double* x, int64_t rows, int64_t cols, int
 hipError_t launch_cast_bf16(const float* A, int64_t m, int64_t n, int64_t lda, uint16_t* out, int64_t ldo,
                             hipStream_t st);
 hipError_t launch_zero_f32(float* x, int64_t rows, int64_t cols, int64_t ld, hipStream_t st);
+// ncol[0 .. n - c) = the columns of 0 .. n-1 that are not in cols (c distinct
+// columns in [0, n), n <= kComplementMaxN), ascending.  A list that repeats a
+// column or names one outside [0, n) sets *bad = 1 (the first n - c of the
+// columns left are still written, nothing past them).
+constexpr int64_t kComplementMaxN = 262144;
+hipError_t launch_complement_cols(const int64_t* cols, int64_t c, int64_t n, int* ncol, int* bad, hipStream_t st);
+// U[i][cols[k]] = (i == k) for i, k < c and, when F is not null, F[i][cols[k]] = 0
+hipError_t launch_pin_selected(const int64_t* cols, int64_t c, float* U, int64_t ldu, float* F, int64_t ldf,
+                               hipStream_t st);
 hipError_t launch_fit_err(const double* parts, int64_t nparts_e, const double* dot_parts, int64_t nparts_d,
                           double* out, hipStream_t st);
 
@@ -60,6 +69,10 @@ struct GemmPlan {
 // D = op(A) B, op(A) = A (M x K, lda) or A^T (A stored K x M, lda); B is K x N (ldb).
 GemmPlan plan_sgemm(int64_t M, int64_t N, int64_t K, bool transA, bool allow_split);
 size_t sgemm_partial_floats(const GemmPlan& p, int64_t M, int64_t N);
+// plan_sgemm (split-K allowed) with at most cap_floats of split partials: the
+// split count is lowered when the plan's would need more (a workspace laid out
+// for a larger product than the one run can hold fewer splits of it)
+GemmPlan plan_sgemm_within(int64_t M, int64_t N, int64_t K, bool transA, size_t cap_floats);
 // EPI_STORE: D = acc.  EPI_RESID: D = X - acc, wsum[wg] = sum (X - acc)^2.
 // EPI_RESID_NORM: wsum only, D is not written (may be null).
 // EPI_STORE_SQA (A not transposed): as EPI_STORE, and wsum[wg] (one per workgroup of the grid,
@@ -71,18 +84,31 @@ size_t sgemm_partial_floats(const GemmPlan& p, int64_t M, int64_t N);
 hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K, bool transA, const float* A,
                              int64_t lda, const float* B, int64_t ldb, float* D, int64_t ldd, float* partial,
                              int epi, const float* X, int64_t ldx, const float* Y, int64_t ldy, double* wsum,
-                             hipStream_t st);
+                             hipStream_t st, const int* ncol = nullptr);
 hipError_t launch_splitk_reduce(const GemmPlan& p, int64_t M, int64_t N, const float* partial, float* D,
                                 int64_t ldd, hipStream_t st);
 // wsum partials written by the norm-only residual epilogue (EPI_RESID_NORM) of an M x N x K
 // product planned with plan_sgemm(M, N, K, false, false): one per workgroup
 int64_t resid_parts(int64_t M, int64_t N, int64_t K);
+// The most partials any norm-only residual of M x N writes, whatever K (its
+// tile depends on M N K: a buffer laid out for the largest K a call may see
+// must hold the smaller tile's count)
+int64_t resid_parts_max(int64_t M, int64_t N);
+// Whether EPI_RESID_NORM of an M x N x K product runs on the split-BF16 tile,
+// the one that takes a column list (ncol: output column j is column ncol[j]
+// of B and X, j < N; launch_sgemm_main rejects a list anywhere else)
+bool resid_cols_ok(int64_t M, int64_t N, int64_t K);
+// Rounds of 256 workgroups (one a compute unit on the split-BF16 tile) the
+// norm-only residual of M x N x K launches
+int64_t resid_rounds(int64_t M, int64_t N, int64_t K);
 // wsum partials written by EPI_RESID (the FP32 square tile) of an M x N product
 int64_t resid_store_parts(int64_t M, int64_t N);
 // D = X + op(A) B and wsum[w] = partial sums of (op(A) B) * Y,
 // with split-K when the plan has it (the sum and the epilogue then run in a
 // second kernel).  add_dot_parts gives the number of wsum partials written.
 int64_t add_dot_parts(const GemmPlan& p, int64_t M, int64_t N, int64_t K);
+// the most add_dot_parts gives for M x N, whatever K and plan
+int64_t add_dot_parts_max(int64_t M, int64_t N);
 hipError_t launch_sgemm_add_dot(const GemmPlan& p, int64_t M, int64_t N, int64_t K, bool transA, const float* A,
                                 int64_t lda, const float* B, int64_t ldb, float* D, int64_t ldd, float* partial,
                                 const float* X, int64_t ldx, const float* Y, int64_t ldy, double* wsum, hipStream_t st);

@@ -579,6 +579,74 @@ __global__ __launch_bounds__(256) void k_fit_err(const double* __restrict__ a, i
     }
 }
 
+// The columns not chosen, ascending, in one workgroup: the chosen columns as
+// a bit set in LDS, each thread a run of its words, and a scan of the runs'
+// counts giving each thread where it writes.
+__global__ __launch_bounds__(1024) void k_complement_cols(const int64_t* __restrict__ cols, int64_t c, int64_t n,
+                                                          int* __restrict__ ncol, int* __restrict__ bad) {
+    __shared__ uint32_t bits[kComplementMaxN / 32];
+    __shared__ int wtot[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t words = (n + 31) / 32;
+    for (int64_t w = tid; w < words; w += 1024) bits[w] = 0u;
+    __syncthreads();
+    int outside = 0;
+    for (int64_t k = tid; k < c; k += 1024) {
+        const int64_t j = cols[k];
+        if (j >= 0 && j < n)
+            atomicOr(&bits[j >> 5], 1u << (j & 31));
+        else
+            outside = 1;
+    }
+    outside = __syncthreads_or(outside);
+    const int64_t per = (words + 1023) / 1024;
+    const int64_t w0 = min<int64_t>(words, (int64_t)tid * per), w1 = min<int64_t>(words, w0 + per);
+    auto avail = [&](int64_t w) {
+        uint32_t f = ~bits[w];
+        if (w == words - 1 && (n & 31)) f &= (1u << (n & 31)) - 1u;
+        return f;
+    };
+    int cnt = 0;
+    for (int64_t w = w0; w < w1; ++w) cnt += __popc(avail(w));
+    int inc = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) wtot[wave] = inc;
+    __syncthreads();
+    int base = 0, total = 0;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        if (v < wave) base += wtot[v];
+        total += wtot[v];
+    }
+    const int64_t lim = n - c;
+    int64_t pos = base + inc - cnt;
+    for (int64_t w = w0; w < w1; ++w) {
+        uint32_t f = avail(w);
+        while (f) {
+            const int b = __ffs(f) - 1;
+            f &= f - 1u;
+            if (pos < lim) ncol[pos] = (int)(w * 32 + b);
+            ++pos;
+        }
+    }
+    if (tid == 0 && (outside || total != lim)) *bad = 1;
+}
+
+__global__ __launch_bounds__(256) void k_pin_selected(const int64_t* __restrict__ cols, int64_t c,
+                                                      float* __restrict__ U, int64_t ldu, float* __restrict__ F,
+                                                      int64_t ldf) {
+    const int64_t total = c * c;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const int64_t i = e / c, k = e - i * c, j = cols[k];
+        U[i * ldu + j] = i == k ? 1.0f : 0.0f;
+        if (F) F[i * ldf + j] = 0.0f;
+    }
+}
+
 inline dim3 grid2d(int64_t cols, int64_t rows) {
     int64_t gx = (cols + 255) / 256;
     if (gx > 64) gx = 64;
@@ -695,6 +763,21 @@ hipError_t launch_cast_bf16(const float* A, int64_t m, int64_t n, int64_t lda, u
 
 hipError_t launch_zero_f32(float* x, int64_t rows, int64_t cols, int64_t ld, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_f32, grid2d(cols, rows), dim3(256), 0, st, x, rows, cols, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_complement_cols(const int64_t* cols, int64_t c, int64_t n, int* ncol, int* bad, hipStream_t st) {
+    if (c < 1 || n <= c || n > kComplementMaxN) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_complement_cols, dim3(1), dim3(1024), 0, st, cols, c, n, ncol, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_pin_selected(const int64_t* cols, int64_t c, float* U, int64_t ldu, float* F, int64_t ldf,
+                               hipStream_t st) {
+    if (c < 1) return hipSuccess;
+    int64_t blocks = (c * c + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_pin_selected, dim3((unsigned)blocks), dim3(256), 0, st, cols, c, U, ldu, F, ldf);
     return hipGetLastError();
 }
 

@@ -33,6 +33,9 @@ struct GemmArgs {
     int swz;            // tile order (see tile_of); 0: blockIdx.x, blockIdx.y are the M and N tiles
     int64_t tm, tn;     // M and N tiles
     bool full;          // k_xgemm: every tile and k-step inside the matrices (no bounds checks)
+    // k_xgemm's norm-only residual (A not transposed): when not null, output
+    // column j (< N) is column ncol[j] of B and X (null: column j)
+    const int* ncol;
 };
 
 // Tile order.  Workgroups are handed to the eight XCDs (each with its own L2)
@@ -412,6 +415,14 @@ __global__ __launch_bounds__(BM * 2) void k_xgemm(const GemmArgs g) {
     // column, known at compile time: its stores need no branch)
     const bool bcol = BCOL && ((BM == 256 && BC0 == 0 && 2 * BN == NT) || (tid >= BC0 && tid < BC0 + 2 * BN));
     const int bcc = (tid - BC0) % BN, bco = (tid - BC0) / BN;
+    // the column of B this thread stages: through the residual's column list
+    // when it has one (read once per tile)
+    constexpr bool kCols = EPI == kResidLate && !TA;
+    int64_t bsrc = 0;
+    if constexpr (kCols) {
+        bsrc = n0 + bcc;
+        if (g.ncol && bcol && bsrc < g.N) bsrc = g.ncol[bsrc];
+    }
     const int uu = 64 * (bwave ? wave - WB0 : wave) + lane;
     const int uw = bwave ? BN / 2 : BM / 2;
     const int cp = uu % uw, ko = uu / uw;
@@ -479,8 +490,10 @@ __global__ __launch_bounds__(BM * 2) void k_xgemm(const GemmArgs g) {
         if (bcol) {
             const int64_t gk = k0 + 8 * bco, gn = n0 + bcc;
             if constexpr (FULL) {
-                const gchar_ptr sb = uniform_ptr(g.B + gk * g.ldb + n0);
-                const uint32_t voff = 4u * (uint32_t)bcc, rstep = 4u * (uint32_t)g.ldb;
+                // (with a column list the lane offset carries the whole column:
+                // below N <= ldb <= kXFullMaxLd, so 4 (7 ldb + column) fits 32 bits)
+                const gchar_ptr sb = uniform_ptr(g.B + gk * g.ldb + (kCols ? 0 : n0));
+                const uint32_t voff = 4u * (uint32_t)(kCols ? bsrc : bcc), rstep = 4u * (uint32_t)g.ldb;
                 const bool colok = BN == 256 || gn < g.N;
 #pragma unroll
                 for (int t = 0; t < 8; ++t) {
@@ -490,7 +503,8 @@ __global__ __launch_bounds__(BM * 2) void k_xgemm(const GemmArgs g) {
                 }
             } else {
 #pragma unroll
-                for (int t = 0; t < 8; ++t) pb[t] = (gn < g.N && gk + t < kend) ? g.B[(gk + t) * g.ldb + gn] : 0.f;
+                for (int t = 0; t < 8; ++t)
+                    pb[t] = (gn < g.N && gk + t < kend) ? g.B[(gk + t) * g.ldb + (kCols ? bsrc : gn)] : 0.f;
             }
         }
     };
@@ -614,6 +628,14 @@ __global__ __launch_bounds__(BM * 2) void k_xgemm(const GemmArgs g) {
     // a tile wholly inside D (always, in the full 256 x 256 form: M and N are
     // multiples of 256) takes the form without per-element tests, so the
     // compiler issues its reads of X and Y together instead of one at a time
+    // with a column list, the column of X each lane reads in block column j
+    int64_t xcol[TN] = {};
+    if constexpr (kCols)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            xcol[j] = n0 + wn * WTN + 32 * j + r;
+            if (g.ncol && xcol[j] < g.N) xcol[j] = g.ncol[xcol[j]];
+        }
     auto epilogue = [&](auto checked) {
 #pragma unroll
         for (int i = 0; i < TM; ++i)
@@ -629,7 +651,7 @@ __global__ __launch_bounds__(BM * 2) void k_xgemm(const GemmArgs g) {
                     for (int v = 0; v < 16; ++v) {
                         const int64_t row = m0 + wm * WTM + 32 * i + 8 * (v >> 2) + 4 * h + (v & 3);
                         const int64_t col = n0 + wn * WTN + 32 * j + r;
-                        xr[v] = g.X[row * g.ldx + col];
+                        xr[v] = g.X[row * g.ldx + (kCols ? xcol[j] : col)];
                         if constexpr (EPI == EPI_ADD_DOT) yr[v] = g.Y[row * g.ldy + col];
                     }
                 }
@@ -642,7 +664,8 @@ __global__ __launch_bounds__(BM * 2) void k_xgemm(const GemmArgs g) {
                         if (EPI == EPI_STORE || EPI == EPI_STORE_SQA) {
                             D[row * g.ldd + col] = x;
                         } else if (EPI == kResidLate || EPI == EPI_RESID) {
-                            const float xe = decltype(checked)::value ? g.X[row * g.ldx + col] : xr[v];
+                            const float xe =
+                                decltype(checked)::value ? g.X[row * g.ldx + (kCols ? xcol[j] : col)] : xr[v];
                             const float e = xe - x;
                             if (EPI == EPI_RESID) D[row * g.ldd + col] = e;
                             wacc += (double)e * (double)e;
@@ -926,11 +949,27 @@ size_t sgemm_partial_floats(const GemmPlan& p, int64_t M, int64_t N) {
     return p.splits > 1 ? (size_t)p.splits * (size_t)M * (size_t)N : 0;
 }
 
+GemmPlan plan_sgemm_within(int64_t M, int64_t N, int64_t K, bool transA, size_t cap_floats) {
+    GemmPlan p = plan_sgemm(M, N, K, transA, true);
+    if (sgemm_partial_floats(p, M, N) <= cap_floats) return p;
+    const int64_t most = std::max<int64_t>(1, (int64_t)(cap_floats / ((size_t)M * (size_t)N)));
+    int64_t kchunk = (K + most - 1) / most;
+    kchunk = std::max<int64_t>(kBK, (kchunk + kBK - 1) / kBK * kBK);
+    const int64_t splits = std::max<int64_t>(1, (K + kchunk - 1) / kchunk);
+    p.splits = (int)splits;
+    p.kchunk = kchunk;
+    const Cfg c = kCfg[p.cfg];
+    p.wgs = ((M + c.BM - 1) / c.BM) * ((N + c.BN - 1) / c.BN) * splits;
+    return p;
+}
+
 hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K, bool transA, const float* A,
                              int64_t lda, const float* B, int64_t ldb, float* D, int64_t ldd, float* partial, int epi,
-                             const float* X, int64_t ldx, const float* Y, int64_t ldy, double* wsum, hipStream_t st) {
+                             const float* X, int64_t ldx, const float* Y, int64_t ldy, double* wsum, hipStream_t st,
+                             const int* ncol) {
     if (M <= 0 || N <= 0) return hipSuccess;
     const bool store_like = epi == EPI_STORE || epi == EPI_STORE_SQA;
+    if (ncol && (epi != EPI_RESID_NORM || transA || !resid_cols_ok(M, N, K))) return hipErrorInvalidValue;
     if (!store_like && p.splits != 1) return hipErrorInvalidValue;
     if (epi == EPI_STORE_SQA && transA) return hipErrorInvalidValue;
     GemmArgs a;
@@ -949,6 +988,7 @@ hipError_t launch_sgemm_main(const GemmPlan& p, int64_t M, int64_t N, int64_t K,
     a.wsum = wsum;
     a.swz = 0;
     a.full = false;
+    a.ncol = ncol;
     if (p.splits > 1) {
         a.D = partial;
         a.ldd = N;
@@ -1028,8 +1068,21 @@ hipError_t launch_splitk_reduce(const GemmPlan& p, int64_t M, int64_t N, const f
     return hipGetLastError();
 }
 
+bool resid_cols_ok(int64_t M, int64_t N, int64_t K) {
+    return resid_cfg(EPI_RESID_NORM, M, N, K) == 4;
+}
+
+int64_t resid_rounds(int64_t M, int64_t N, int64_t K) {
+    return (resid_parts(M, N, K) + 255) / 256;
+}
+
 int64_t resid_parts(int64_t M, int64_t N, int64_t K) {
     const Cfg c = kCfg[resid_cfg(EPI_RESID_NORM, M, N, K)];
+    return ((M + c.BM - 1) / c.BM) * ((N + c.BN - 1) / c.BN);
+}
+
+int64_t resid_parts_max(int64_t M, int64_t N) {
+    const Cfg c = kCfg[2];   // the smaller of the two residual tiles
     return ((M + c.BM - 1) / c.BM) * ((N + c.BN - 1) / c.BN);
 }
 
@@ -1041,6 +1094,10 @@ int64_t add_dot_parts(const GemmPlan& p, int64_t M, int64_t N, int64_t K) {
     if (p.splits > 1) return add_dot_blocks(M, N);
     const Cfg c = kCfg[resid_cfg(EPI_ADD_DOT, M, N, K)];
     return ((M + c.BM - 1) / c.BM) * ((N + c.BN - 1) / c.BN);
+}
+
+int64_t add_dot_parts_max(int64_t M, int64_t N) {
+    return std::max<int64_t>(kAddDotBlocks, ((M + kCfg[2].BM - 1) / kCfg[2].BM) * ((N + kCfg[2].BN - 1) / kCfg[2].BN));
 }
 
 hipError_t launch_sgemm_add_dot(const GemmPlan& p, int64_t M, int64_t N, int64_t K, bool transA, const float* A,

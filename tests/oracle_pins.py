@@ -452,6 +452,32 @@ def check_fit_qr_route(O):
             assert np.allclose(U, U_ref[:, cols], rtol=1e-8, atol=1e-10 * np.abs(U_ref).max())
 
 
+def check_fit_selected_columns(O):
+    """C C^+ C = C (a Penrose condition, Sec. 2.1), so the residual of the
+    fit is zero on the chosen columns and err^2 is the sum over the others;
+    with C of full column rank C^+ C = I, so U on the chosen columns is the
+    identity (the columns of C in their order).  A repeated block leaves C
+    rank-deficient: the residual there is still zero, U there is not I."""
+    w = gen.tiny()
+    A = w.A.astype(np.float64)
+    off = w.offsets
+    for idx in ([5, 1, 30, 17], [0], [31, 2, 9, 8, 14, 22]):
+        cols = O.selected_columns(off, idx)
+        C = A[:, cols]
+        U, err = O.fit_columns(A, C)
+        assert np.abs(U[:, cols] - np.eye(len(cols))).max() <= 1e-9
+        E = A - C @ U
+        assert np.abs(E[:, cols]).max() <= 1e-12 * np.abs(A).max()
+        rest = np.setdiff1d(np.arange(A.shape[1]), cols)
+        assert abs(math.sqrt(float(np.sum(E[:, rest] ** 2))) - err) <= 1e-12 * err
+    cols = O.selected_columns(off, [4, 4, 6], dedupe=False)
+    C = A[:, cols]
+    U, err = O.fit_columns(A, C)
+    E = A - C @ U
+    assert np.abs(E[:, cols]).max() <= 1e-12 * np.abs(A).max()
+    assert np.abs(U[:, cols] - np.eye(len(cols))).max() > 0.1
+
+
 def check_fit_bruteforce(O, max_subsets=None):
     """Brute force over every s-subset of blocks of the tiny workload: the
     sampled error lies between the best and worst subset, and equals that
@@ -785,6 +811,7 @@ ALL_CHECKS = [
     check_sampling_matrix_example,
     check_fit_projection,
     check_fit_qr_route,
+    check_fit_selected_columns,
     check_cur_reductions,
     check_paper_synthetic_generator,
     check_alg1_rows_uniform_distinct,

@@ -338,6 +338,35 @@ def test_decompose_with_replacement(ctx):
     _check_decompose(ctx, w, replace=True, label="replace")
 
 
+@pytest.mark.parametrize("word", [0x9E3779B97F4A7C15, 2 ** 64 - 1])
+def test_decompose_fewer_columns_than_laid_out(ctx, word):
+    """Draws with replacement that all pick one block: the workspace is laid
+    out for s blocks (432 columns, for which the residual product is large
+    enough for the 256 x 256 tile) but the fit runs with one block's columns,
+    whose residual takes the 128 x 128 tile and writes more partial sums
+    than the larger product would.  err and U against the oracle's fit of
+    the same columns."""
+    from paper_1703_06065_amd import binding
+    m, n, b, s = 5181, 3590, 16, 27
+    w = gen.small_case(m, n, b, k=22, s=s, seed=1531)
+    draws = np.full(s, word, dtype=np.uint64)
+    res = ctx.decompose(dev(w.A), w.offsets, w.k, w.s, dev_dense(w.omega), draws, q=w.q, replace=True, l=w.l)
+    idx = res["idx"]
+    assert len(set(idx.tolist())) == 1
+    cols = O.selected_columns(w.offsets, idx)
+    c = len(cols)
+    assert res["c"] == c and c in (6, 16)
+    assert not res["flags"] & (binding.FLAG_RANKDEF_C | binding.FLAG_ILLCOND_C)
+    A64 = w.A.astype(np.float64)
+    U_ref, e_ref = O.fit_columns(A64, A64[:, cols])
+    frob2 = O.frob2(A64)
+    note(f"one block of {c} columns: err={res['err']:.9g} oracle={e_ref:.9g}")
+    assert abs(res["err"] - e_ref) <= err_tol(e_ref, frob2)
+    Ug = res["U"][:c].cpu().numpy().astype(np.float64)
+    rel_u = np.linalg.norm(Ug - U_ref) / np.linalg.norm(U_ref)
+    assert rel_u <= u_gate(O.cond2(A64[:, cols]), e_ref, math.sqrt(frob2), m)
+
+
 def test_decompose_all_blocks_zero_error(ctx):
     w = gen.small_case(300, 96, 8, 6, 12, seed=12, noise=1e-2)
     note("decompose all blocks")
@@ -519,3 +548,63 @@ def test_decompose_plain_fp32_full_size(ctx):
     w = gen.plain_fp32(0)
     res, ref = _check_decompose(ctx, w, label="full-size")
     assert np.array_equal(res["idx"], ref["idx"])
+
+
+def _residual_skips_chosen(m, n, c):
+    """The documented rule: the residual pass covers only the n - c columns
+    outside C when that product runs on the split-BF16 tile and its 256 x 256
+    tiles take fewer rounds of 256 workgroups than over all n columns."""
+    ne = n - c
+    if not (ne >= 256 and m >= 256 and c >= 256 and n <= 262144 and m * ne * c >= 8e9):
+        return False
+    rounds = lambda cols: -(-(-(-m // 256) * -(-cols // 256)) // 256)
+    return rounds(ne) < rounds(n)
+
+
+@pytest.mark.parametrize("s,replace,refine,ragged", [
+    (48, False, 1, False),   # n - c = 2040 columns: the tile-checked form of the column list
+    (48, False, 0, False),   # no refinement: U[:, cols] = I set before the residual pass
+    (70, True, 1, False),    # draws with replacement: repeated blocks dropped on the host
+    (70, False, 1, True),    # ragged blocks: the columns expanded on the host
+])
+def test_decompose_residual_over_unchosen_columns(ctx, s, replace, refine, ragged):
+    """A residual product that runs fewer rounds of workgroups over the
+    n - c columns outside C: U on C's own columns is set to the identity (C
+    e_k is that column of A, so their residual is exactly zero) and the pass
+    covers the other columns through their list.  err against the oracle's
+    fit of the GPU's own blocks, U on C's columns bit-exactly I, and U on 16
+    other columns against R^-1 Q^T a_j within the U gate."""
+    from paper_1703_06065_amd import binding
+    m, n, b = 16384, 3000, 20
+    w = gen.small_case(m, n, b, k=20, s=s, seed=11, ragged=ragged)
+    note(f"residual over unchosen columns: {m}x{n} s={s} replace={replace} refine={refine} ragged={ragged}")
+    res = ctx.decompose(dev(w.A), w.offsets, w.k, w.s, dev_dense(w.omega), w.draws, q=w.q, replace=replace,
+                        refine=refine, l=w.l)
+    assert not res["flags"] & (binding.FLAG_RANKDEF_C | binding.FLAG_ILLCOND_C)
+    cols = O.selected_columns(w.offsets, res["idx"])
+    c = len(cols)
+    assert res["c"] == c and _residual_skips_chosen(m, n, c), c
+    Ug = res["U"][:c].cpu().numpy()
+    assert np.array_equal(Ug[:, cols], np.eye(c, dtype=np.float32))
+    A64 = w.A.astype(np.float64)
+    C = A64[:, cols]
+    rest = np.setdiff1d(np.arange(n), cols)
+    J = np.sort(np.random.default_rng(5).choice(rest, 16, replace=False))
+    e_ref, U_J = O.fit_columns_qr(A64, C, cols=J)
+    frob2 = O.frob2(A64)
+    tol = err_tol(e_ref, frob2)
+    note(f"  c={c} err={res['err']:.9g} oracle={e_ref:.9g} rel={abs(res['err'] - e_ref) / e_ref:.2e}")
+    assert abs(res["err"] - e_ref) <= tol
+    cond = O.cond2(C)
+    rel_u = np.linalg.norm(Ug[:, J].astype(np.float64) - U_J) / np.linalg.norm(U_J)
+    gate = u_gate(cond, e_ref, math.sqrt(frob2), m)
+    note(f"  rel U gap on 16 other columns {rel_u:.2e} gate {gate:.2e} cond(C)={cond:.3g}")
+    assert rel_u <= gate
+
+
+def test_residual_rule_at_the_benchmarked_sizes():
+    """The column list is taken at 65536 x 16384 with c = 2048 (64 rounds of
+    workgroups over all columns, 56 over the others), not at 8192 x 4096 with
+    c = 256 (two rounds either way)."""
+    assert _residual_skips_chosen(65536, 16384, 2048)
+    assert not _residual_skips_chosen(8192, 4096, 256)
