@@ -1,8 +1,12 @@
 // BF16 sketch passes on the CDNA4 matrix cores (v_mfma_f32_32x32x16_bf16,
 // FP32 accumulation).  Both operands are stored with k contiguous ("NT"):
 // D (M x N, FP32) = A (M x K, bf16) * B^T, B stored N x K (bf16).  A tile
-// row of 32 k values is 64 bytes; each lane's MFMA operand is 8 consecutive
-// k values, one 16-byte LDS read.  Split-K partial tiles are summed in a
+// row of 64 k values is 128 bytes; each lane's MFMA operand is 8 consecutive
+// k values, one 16-byte LDS read.  The passes are bound by HBM latency (a
+// sketch product has few tiles), so each step stages 64 k: four 16-byte
+// loads of A and four of B per thread in flight behind the step's MFMAs
+// (542 -> 452 us a pass at 65536 x 16384, l = 110, against 32 k a step; 128 k
+// measured no better).  Split-K partial tiles are summed in a
 // fixed order by the FP32 GEMM's reduction kernel.
 //
 // Also here: the casts that produce the k-contiguous operands:
@@ -122,11 +126,11 @@ __device__ __forceinline__ uint4 ld8(const uint16_t* p, bool rowok, int64_t c, i
 
 template <int BM, int BN, int WM, int WN>
 __global__ __launch_bounds__(WM* WN * 64) void k_bgemm_nt(const BArgs g) {
-    constexpr int BK = 32;                 // k per LDS stage
+    constexpr int BK = 64;                 // k per LDS stage
     constexpr int NT = WM * WN * 64;
     constexpr int WTM = BM / WM, WTN = BN / WN;
     constexpr int TM = WTM / 32, TN = WTN / 32;
-    constexpr int LDS_ROW = BK + 8;        // bf16 per LDS row (80 bytes: spreads banks)
+    constexpr int LDS_ROW = BK + 8;        // bf16 per LDS row (144 bytes: spreads banks)
     constexpr int A_V = BM * BK / 8 / NT;  // 16-byte vectors per thread
     constexpr int B_V = BN * BK / 8 / NT;
     static_assert(TM >= 1 && TN >= 1 && A_V >= 1 && B_V >= 1, "tile shape");
@@ -259,7 +263,7 @@ GemmPlan plan_bgemm(int64_t M, int64_t N, int64_t K) {
         if (splits < 1) splits = 1;
     }
     int64_t kchunk = (K + splits - 1) / splits;
-    kchunk = ((kchunk + 31) / 32) * 32;
+    kchunk = ((kchunk + 63) / 64) * 64;
     splits = (K + kchunk - 1) / kchunk;
     if (splits < 1) splits = 1;
     p.splits = (int)splits;
